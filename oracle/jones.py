@@ -1,0 +1,71 @@
+"""Jones matrices and chains (paper Section 2.2).
+
+parity pinned: identities checked in tests/test_oracle_pins.py (vec trick,
+permutation, conjugate-transpose of a chain, identity for an empty side).
+"""
+import numpy as np
+
+# eq. permutation: vec(G^H) = P conj(vec(G)), P involutory
+PERM = np.array([[1, 0, 0, 0],
+                 [0, 0, 1, 0],
+                 [0, 1, 0, 0],
+                 [0, 0, 0, 1]], dtype=np.float64)
+PERM_IDX = np.array([0, 2, 1, 3])
+
+
+def vec(A):
+    """Row-major vectorisation of [...,2,2] -> [...,4] (eq. jones)."""
+    A = np.asarray(A)
+    return A.reshape(A.shape[:-2] + (4,))
+
+
+def unvec(v):
+    """Inverse row-major vectorisation [...,4] -> [...,2,2]."""
+    v = np.asarray(v)
+    return v.reshape(v.shape[:-1] + (2, 2))
+
+
+def dagger(A):
+    return np.conj(np.swapaxes(A, -1, -2))
+
+
+def eye2(S):
+    out = np.zeros((S, 2, 2), dtype=np.complex128)
+    out[:, 0, 0] = 1.0
+    out[:, 1, 1] = 1.0
+    return out
+
+
+def term_jones(term, vis, rows, chans, ants, d):
+    """Jones matrix of one chain term for antenna `ants` at samples (rows, chans),
+    direction d.  The gain is looked up through the term's time/frequency/direction
+    maps.  Diagonal terms use only entries XX and YY; a delay term is
+    diag(exp(2 pi i nu tau_X), exp(2 pi i nu tau_Y)) at the channel frequency nu."""
+    t = np.asarray(vis.row_time)[rows]
+    gt = np.asarray(term.t_map)[t]
+    gf = np.asarray(term.f_map)[chans]
+    gd = int(np.asarray(term.d_map)[d])
+    S = rows.size
+    J = np.zeros((S, 2, 2), dtype=np.complex128)
+    if term.kind == "delay":
+        tau = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]      # [S][2]
+        nu = np.asarray(vis.chan_freq, dtype=np.float64)[chans]
+        J[:, 0, 0] = np.exp(2j * np.pi * nu * tau[:, 0])
+        J[:, 1, 1] = np.exp(2j * np.pi * nu * tau[:, 1])
+    else:
+        g = np.asarray(term.gains, dtype=np.complex128)[gt, gf, ants, gd]      # [S][4]
+        if term.kind == "diag":
+            J[:, 0, 0] = g[:, 0]
+            J[:, 1, 1] = g[:, 3]
+        else:
+            J[:] = unvec(g)
+    return J
+
+
+def chain_product(chain, vis, rows, chans, ants, d, j0, j1):
+    """Product G_j0 G_j0+1 ... G_j1-1 (eq. joneschain); the empty product is I
+    (eq. jonesfactor)."""
+    C = eye2(rows.size)
+    for j in range(j0, j1):
+        C = C @ term_jones(chain[j], vis, rows, chans, ants, d)
+    return C

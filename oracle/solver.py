@@ -1,0 +1,312 @@
+"""AllJones Gauss-Newton solver for one chain term, interval by interval.
+
+Follows the paper's Section 2.3-2.4 and Algorithm 1.  Readings taken where the
+paper is silent or inconsistent (see the design notes of the repository):
+
+* Sign of the update.  The Jacobian of the residual is minus the model
+  derivative (eq. jacobian_A); eq. update subtracts, Algorithm 1 adds.  Both
+  amount to  x <- x + [sum K^H W K]^-1 sum K^H W r  with K = dv/dg, which is
+  what is computed here.
+* Blocks.  The kept diagonal blocks are per (interval, antenna, gain
+  direction): 4x4 for a complex 2x2 term, 2x2 over (XX, YY) for a diagonal
+  term, real 2x2 over (tau_X, tau_Y) for a delay term.
+* Conjugate baselines are folded in (eq. jhj_entry_simplified): a row (p,q)
+  also serves antenna q as the virtual row (q,p) with D^H, M^H and the weights
+  permuted by P.
+* Damping (the paper leaves the step length open, noting that the extension to
+  Levenberg-Marquardt is trivial): x <- x + alpha_k Delta with alpha = 1
+  (full), 1/2 (half), or 1 on odd / 1/2 on even updates (alternate).  The
+  default picks alternate for direction-independent complex/diagonal terms,
+  half for direction-dependent terms and full for delay terms.
+* Convergence (Algorithm 1's "||Delta g|| > eps"): per interval, the 2-norm
+  of the applied step over the unknown entries of unflagged blocks divided by
+  the 2-norm of the updated gains; for delays, the largest band-edge phase
+  change 2 pi nu_max |alpha Delta tau|.  The iteration count is the number of
+  applied updates.
+* A block whose Cholesky pivot falls to 1e-12 of its largest diagonal entry
+  (or that has no data) gets Delta = 0 and gain flag 1; flagged blocks are
+  left out of the convergence norm.  The flag reflects the last update.
+
+parity pinned: see tests/test_oracle_pins.py (finite-difference and dense
+augmented-Jacobian checks, one-step exactness, StefCal closed form, damping
+2-cycle, noise-free recovery, invariances).
+"""
+from __future__ import annotations
+
+import copy
+import numpy as np
+
+from .jones import PERM_IDX, vec, unvec, dagger, term_jones, chain_product
+
+UNKNOWNS = {"diag": (0, 3), "c2x2": (0, 1, 2, 3), "delay": (0, 3)}
+PIVOT_REL = 1e-12
+
+
+# ----------------------------------------------------------------------------
+# samples of one solution interval
+# ----------------------------------------------------------------------------
+
+class Samples:
+    """Unflagged cross-correlation samples (row, chan) in one orientation."""
+
+    def __init__(self, rows, chans, p, q, D, M, w):
+        self.rows, self.chans, self.p, self.q = rows, chans, p, q
+        self.D, self.M, self.w = D, M, w
+
+    @property
+    def size(self):
+        return self.rows.size
+
+
+def weights4(vis, rows, chans):
+    w = np.asarray(vis.weight)[rows, chans].astype(np.float64)
+    if w.shape[-1] == 1:
+        w = np.repeat(w, 4, axis=-1)
+    return w
+
+
+def samples_of(vis, rows, chans):
+    """All (row, chan) pairs of the given rows x chans that are used by the solver:
+    flag == 0 and p != q (no autocorrelations, paper Section 2.2)."""
+    rr, cc = np.meshgrid(rows, chans, indexing="ij")
+    rr, cc = rr.ravel(), cc.ravel()
+    flag = np.asarray(vis.flag)
+    a1, a2 = np.asarray(vis.ant1), np.asarray(vis.ant2)
+    keep = (flag[rr, cc] == 0) & (a1[rr] != a2[rr])
+    rr, cc = rr[keep], cc[keep]
+    D = np.asarray(vis.data)[rr, cc].astype(np.complex128)
+    M = np.asarray(vis.model)[rr, cc].astype(np.complex128)
+    return Samples(rr, cc, a1[rr].astype(np.int64), a2[rr].astype(np.int64), D, M,
+                   weights4(vis, rr, cc))
+
+
+def conjugate_samples(s: Samples) -> Samples:
+    """The conjugate baseline (q,p): V_qp = V_pq^H, so D -> D^H, M -> M^H and
+    the per-correlation weights are permuted by P (eq. jonesconj)."""
+    D = vec(dagger(unvec(s.D)))
+    M = vec(dagger(unvec(s.M)))
+    return Samples(s.rows, s.chans, s.q, s.p, D, M, s.w[:, PERM_IDX])
+
+
+def interval_rows_chans(vis, term, gt, gf):
+    t_of_row = np.asarray(term.t_map)[np.asarray(vis.row_time)]
+    rows = np.nonzero(t_of_row == gt)[0]
+    chans = np.nonzero(np.asarray(term.f_map) == gf)[0]
+    return rows, chans
+
+
+# ----------------------------------------------------------------------------
+# model, residual and Jacobian blocks
+# ----------------------------------------------------------------------------
+
+def model_and_blocks(vis, chain, n, s: Samples):
+    """Model V (eq. baselinemodel) and, per gain direction delta of term n, the
+    block K = sum_{d: d_map(d)=delta} C<_{p,d} (x) (C>_{p,d} M_d C_{q,d}^H)^T
+    (eq. chain_trick, eq. g_derivative_di / _dd), rows (a,b), columns (i,k),
+    i.e. K[(a,b),(i,k)] = A[a,i] B[k,b].  Also returns the active term's Jones
+    matrix per direction (needed by the delay parameterisation)."""
+    term = chain[n]
+    n_dir = s.M.shape[1]
+    n_gdir = int(term.n_gdir)
+    d_map = np.asarray(term.d_map)
+    S = s.size
+    V = np.zeros((S, 2, 2), dtype=np.complex128)
+    K = np.zeros((S, n_gdir, 4, 4), dtype=np.complex128)
+    Gn = np.zeros((S, n_gdir, 2, 2), dtype=np.complex128)
+    N = len(chain)
+    for d in range(n_dir):
+        A = chain_product(chain, vis, s.rows, s.chans, s.p, d, 0, n)
+        G = term_jones(term, vis, s.rows, s.chans, s.p, d)
+        Cr = chain_product(chain, vis, s.rows, s.chans, s.p, d, n + 1, N)
+        Cq = chain_product(chain, vis, s.rows, s.chans, s.q, d, 0, N)
+        Md = unvec(s.M[:, d])
+        B = Cr @ Md @ dagger(Cq)
+        V += A @ G @ B
+        Kd = np.einsum("sai,skb->sabik", A, B).reshape(S, 4, 4)
+        K[:, d_map[d]] += Kd
+        Gn[:, d_map[d]] = G
+    return vec(V), K, Gn
+
+
+def accumulate(vis, chain, n, s_fwd: Samples):
+    """JHJ and JHr blocks per (antenna, gain direction) over one interval
+    (eq. jhj_entry_simplified, eq. jhr_entry_simplified; delay: eq. jhj_case2,
+    eq. jhwr_case2 without their common factor 2, which cancels in the update).
+    Also returns chi^2 = sum w |r|^2 over the interval (eq. min)."""
+    term = chain[n]
+    U = list(UNKNOWNS[term.kind])
+    n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
+    nu_ = len(U)
+    if term.kind == "delay":
+        JHJ = np.zeros((n_ant, n_gdir, 2, 2), dtype=np.float64)
+        JHr = np.zeros((n_ant, n_gdir, 2), dtype=np.float64)
+    else:
+        JHJ = np.zeros((n_ant, n_gdir, nu_, nu_), dtype=np.complex128)
+        JHr = np.zeros((n_ant, n_gdir, nu_), dtype=np.complex128)
+    chisq = 0.0
+    for k, s in enumerate((s_fwd, conjugate_samples(s_fwd))):
+        if s.size == 0:
+            continue
+        V, K, Gn = model_and_blocks(vis, chain, n, s)
+        R = s.D - V
+        if k == 0:
+            chisq = float(np.sum(s.w * np.abs(R) ** 2))
+        Ku = K[..., U]                                               # [S][gd][4][nu]
+        if term.kind == "delay":
+            nu = np.asarray(vis.chan_freq, dtype=np.float64)[s.chans]
+            gdiag = np.stack([Gn[..., 0, 0], Gn[..., 1, 1]], axis=-1)   # [S][gd][2]
+            dg = 2j * np.pi * nu[:, None, None] * gdiag                 # d g_c / d tau_c
+            E = Ku * dg[:, :, None, :]
+            H = np.real(np.einsum("sdxu,sx,sdxv->sduv", np.conj(E), s.w, E))
+            b = np.real(np.einsum("sdxu,sx->sdu", np.conj(E), s.w * R))
+        else:
+            H = np.einsum("sdxu,sx,sdxv->sduv", np.conj(Ku), s.w, Ku)
+            b = np.einsum("sdxu,sx->sdu", np.conj(Ku), s.w * R)
+        np.add.at(JHJ, s.p, H)
+        np.add.at(JHr, s.p, b)
+    return JHJ, JHr, chisq
+
+
+# ----------------------------------------------------------------------------
+# per-block solve (Cholesky, FP64) and damping
+# ----------------------------------------------------------------------------
+
+def block_solve(H, b, rel=PIVOT_REL):
+    """Solve H x = b for a small Hermitian positive-definite block by Cholesky
+    H = L L^H.  Returns (x, singular): singular when the block is empty or a
+    pivot is <= rel * max diagonal (then x = 0)."""
+    n = b.shape[0]
+    diag = np.real(np.diag(H))
+    dmax = float(np.max(diag)) if n else 0.0
+    if not (np.isfinite(dmax) and dmax > 0.0):
+        return np.zeros_like(b), True
+    L = np.zeros((n, n), dtype=H.dtype)
+    for j in range(n):
+        s = np.real(H[j, j]) - np.sum(np.abs(L[j, :j]) ** 2)
+        if not (s > rel * dmax):
+            return np.zeros_like(b), True
+        L[j, j] = np.sqrt(s)
+        for i in range(j + 1, n):
+            L[i, j] = (H[i, j] - np.sum(L[i, :j] * np.conj(L[j, :j]))) / L[j, j]
+    y = np.zeros_like(b)
+    for i in range(n):
+        y[i] = (b[i] - np.sum(L[i, :i] * y[:i])) / L[i, i]
+    x = np.zeros_like(b)
+    for i in reversed(range(n)):
+        x[i] = (y[i] - np.sum(np.conj(L[i + 1:, i]) * x[i + 1:])) / np.conj(L[i, i])
+    return x, False
+
+
+def resolve_damping(mode, term):
+    if mode == "auto":
+        if term.kind == "delay":
+            return "full"
+        return "half" if term.direction_dependent else "alternate"
+    if mode not in ("full", "half", "alternate"):
+        raise ValueError(f"unknown damping {mode!r}")
+    return mode
+
+
+def step_length(mode, k):
+    """alpha for the k-th applied update (k = 1, 2, ...)."""
+    if mode == "full":
+        return 1.0
+    if mode == "half":
+        return 0.5
+    return 1.0 if (k % 2 == 1) else 0.5
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 over every interval of one term
+# ----------------------------------------------------------------------------
+
+def copy_chain(chain):
+    out = []
+    for t in chain:
+        c = copy.copy(t)
+        for name in ("gains", "params", "gain_flags"):
+            v = getattr(t, name)
+            if v is not None:
+                setattr(c, name, np.array(v, copy=True))
+        for name in ("t_map", "f_map", "d_map"):
+            setattr(c, name, np.asarray(getattr(t, name)))
+        out.append(c)
+    return out
+
+
+def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
+    """Algorithm 1 for one interval of term n (in place on chain[n]).
+    Returns (iters, converged, chisq_first, chisq_last)."""
+    term = chain[n]
+    mode = resolve_damping(damping, term)
+    U = list(UNKNOWNS[term.kind])
+    rows, chans = interval_rows_chans(vis, term, gt, gf)
+    s = samples_of(vis, rows, chans)
+    nu_max = float(np.max(np.asarray(vis.chan_freq)[chans])) if chans.size else 0.0
+    iters, converged = 0, 0
+    chisq_first = chisq_last = 0.0
+    n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
+    n_pass = max_iter if max_iter > 0 else 1      # max_iter = 0: evaluate chi^2 only
+    for k in range(1, n_pass + 1):
+        JHJ, JHr, chi2 = accumulate(vis, chain, n, s)
+        if k == 1:
+            chisq_first = chi2
+        chisq_last = chi2
+        if max_iter <= 0:
+            break
+        delta = np.zeros_like(JHr)
+        flags = np.zeros((n_ant, n_gdir), dtype=np.int8)
+        for a in range(n_ant):
+            for dd in range(n_gdir):
+                x, sing = block_solve(JHJ[a, dd], JHr[a, dd])
+                delta[a, dd] = x
+                flags[a, dd] = 1 if sing else 0
+        alpha = step_length(mode, k)
+        step = alpha * delta
+        ok = flags == 0
+        if term.kind == "delay":
+            term.params[gt, gf] = term.params[gt, gf] + step
+            ratio = float(np.max(2.0 * np.pi * nu_max * np.abs(step[ok]))) if np.any(ok) else 0.0
+        else:
+            x_new = term.gains[gt, gf].copy()
+            x_new[..., U] = x_new[..., U] + step
+            num = float(np.sum(np.abs(step[ok]) ** 2))
+            den = float(np.sum(np.abs(x_new[..., U][ok]) ** 2))
+            term.gains[gt, gf] = x_new
+            ratio = 0.0 if num == 0.0 else (np.sqrt(num / den) if den > 0.0 else np.inf)
+        term.gain_flags[gt, gf] = flags
+        iters = k
+        if ratio <= tol:
+            converged = 1
+            break
+    return iters, converged, chisq_first, chisq_last
+
+
+def solve_term(vis, chain, n, tol=1e-6, max_iter=100, damping="auto", intervals=None):
+    """Solve term n of the chain over all of its solution intervals, each
+    independently (paper Section 2.3, last paragraph), other terms fixed.
+    Returns (new_chain, stats) with stats arrays [n_gt][n_gf]."""
+    chain = copy_chain(chain)
+    term = chain[n]
+    shape = (int(term.n_gt), int(term.n_gf))
+    st = dict(iters=np.zeros(shape, np.int32), converged=np.zeros(shape, np.uint8),
+              chisq_first=np.zeros(shape), chisq_last=np.zeros(shape))
+    todo = intervals if intervals is not None else [(a, b) for a in range(shape[0]) for b in range(shape[1])]
+    for gt, gf in todo:
+        it, cv, c0, c1 = solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping)
+        st["iters"][gt, gf] = it
+        st["converged"][gt, gf] = cv
+        st["chisq_first"][gt, gf] = c0
+        st["chisq_last"][gt, gf] = c1
+    return chain, st
+
+
+def solve_chain(vis, chain, n_epoch=1, tol=1e-6, max_iter=100, damping="auto"):
+    """Each term solved to convergence in turn with the others fixed, repeated
+    for n_epoch passes over the chain (paper Section 4.3)."""
+    stats = []
+    for _ in range(n_epoch):
+        for n in range(len(chain)):
+            chain, st = solve_term(vis, chain, n, tol, max_iter, damping)
+            stats.append(st)
+    return chain, stats

@@ -1,0 +1,106 @@
+"""Small random problems for tests (numpy, host).  No solver arithmetic here:
+data are produced with an independent einsum forward model."""
+import numpy as np
+
+from synth.problem import Term, Vis
+
+
+def rand_c(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def jones_of(term, t, c, a, d, freq):
+    """Generator-side Jones lookup for one sample (independent of the oracle)."""
+    gt, gf, gd = term.t_map[t], term.f_map[c], term.d_map[d]
+    if term.kind == "delay":
+        tau = term.params[gt, gf, a, gd]
+        return np.diag(np.exp(2j * np.pi * freq[c] * tau))
+    g = term.gains[gt, gf, a, gd]
+    if term.kind == "diag":
+        return np.diag([g[0], g[3]])
+    return g.reshape(2, 2)
+
+
+def forward_data(vis, chain):
+    """D = sum_d C_p M_d C_q^H with C = product of chain terms, sample by sample."""
+    out = np.zeros(vis.data.shape, dtype=np.complex128)
+    for r in range(vis.data.shape[0]):
+        p, q, t = vis.ant1[r], vis.ant2[r], vis.row_time[r]
+        for c in range(vis.data.shape[1]):
+            V = np.zeros((2, 2), dtype=np.complex128)
+            for d in range(vis.model.shape[2]):
+                Cp = np.eye(2, dtype=np.complex128)
+                Cq = np.eye(2, dtype=np.complex128)
+                for term in chain:
+                    Cp = Cp @ jones_of(term, t, c, p, d, vis.chan_freq)
+                    Cq = Cq @ jones_of(term, t, c, q, d, vis.chan_freq)
+                V += Cp @ vis.model[r, c, d].reshape(2, 2) @ Cq.conj().T
+            out[r, c] = V.reshape(4)
+    return out
+
+
+def make_vis(rng, n_ant=5, n_time=3, n_chan=2, n_dir=1, n_wcorr=4, polarised=True,
+             freq0=1.0e9, dfreq=1.0e6, all_pairs=False):
+    p, q = np.triu_indices(n_ant, k=1)
+    if all_pairs:
+        pass
+    nbl = p.size
+    ant1 = np.tile(p, n_time).astype(np.int32)
+    ant2 = np.tile(q, n_time).astype(np.int32)
+    row_time = np.repeat(np.arange(n_time), nbl).astype(np.int32)
+    n_row = ant1.size
+    model = rand_c(rng, n_row, n_chan, n_dir, 4)
+    if not polarised:
+        model[..., 1] = 0
+        model[..., 2] = 0
+        model[..., 3] = model[..., 0]
+    weight = rng.uniform(0.5, 2.0, (n_row, n_chan, n_wcorr))
+    return Vis(data=np.zeros((n_row, n_chan, 4), np.complex128), model=model, weight=weight,
+               flag=np.zeros((n_row, n_chan), np.uint8), ant1=ant1, ant2=ant2, row_time=row_time,
+               chan_freq=freq0 + dfreq * np.arange(n_chan), n_ant=n_ant, n_time=n_time)
+
+
+def make_term(rng, kind, n_time, n_chan, n_ant, t_int=None, f_int=None, n_dir=1, dd=False,
+              scale=0.3, name=""):
+    t_int = t_int or n_time
+    f_int = f_int or n_chan
+    t_map = (np.arange(n_time) // t_int).astype(np.int32)
+    f_map = (np.arange(n_chan) // f_int).astype(np.int32)
+    d_map = np.arange(n_dir, dtype=np.int32) if dd else np.zeros(n_dir, np.int32)
+    n_gt, n_gf, n_gdir = int(t_map.max()) + 1, int(f_map.max()) + 1, int(d_map.max()) + 1
+    shape = (n_gt, n_gf, n_ant, n_gdir)
+    gains = np.zeros(shape + (4,), np.complex128)
+    gains[..., 0] = 1
+    gains[..., 3] = 1
+    params = None
+    if kind == "delay":
+        params = rng.uniform(-1e-9, 1e-9, shape + (2,))
+    else:
+        gains = gains + scale * rand_c(rng, *shape, 4)
+        if kind == "diag":
+            gains[..., 1] = 0
+            gains[..., 2] = 0
+    return Term(kind=kind, t_map=t_map, f_map=f_map, d_map=d_map, n_gt=n_gt, n_gf=n_gf,
+                n_gdir=n_gdir, gains=gains, params=params,
+                gain_flags=np.zeros(shape, np.int8), direction_dependent=dd, name=name)
+
+
+def unit_like(term):
+    t = term.copy()
+    g = np.zeros_like(term.gains)
+    g[..., 0] = 1
+    g[..., 3] = 1
+    t.gains = g
+    if term.params is not None:
+        t.params = np.zeros_like(term.params)
+    t.gain_flags = np.zeros_like(term.gain_flags)
+    return t
+
+
+def reference_diag(g, ref=0):
+    """Remove the per-correlation phase gauge: antenna `ref` XX/YY phases -> 0."""
+    out = g.copy()
+    for c in (0, 3):
+        ph = g[:, :, ref:ref + 1, :, c] / np.abs(g[:, :, ref:ref + 1, :, c])
+        out[..., c] = g[..., c] / ph
+    return out

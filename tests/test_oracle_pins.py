@@ -1,0 +1,494 @@
+"""Pins for the CPU oracle against what the paper and the mathematics fix
+(identities, brute force, closed forms, exact recovery, invariances).
+None of these compare the oracle with itself."""
+import numpy as np
+import pytest
+
+from oracle import dense, jones, outputs, solver, warmstart, delay_init
+from oracle.jones import PERM, dagger, unvec, vec
+from synth.generate import config_tiny, to_numpy_vis
+from helpers import (forward_data, make_term, make_vis, rand_c, reference_diag, unit_like)
+
+RNG = np.random.default_rng(20241213)
+
+
+# --------------------------------------------------------------------------
+# identities (eq. vectrick, eq. jonesconj, eq. permutation, eq. joneschainct)
+# --------------------------------------------------------------------------
+
+def test_vec_trick_row_major():
+    for _ in range(20):
+        A, X, B = (rand_c(RNG, 2, 2) for _ in range(3))
+        lhs = (A @ X @ B).reshape(4)
+        rhs = np.kron(A, B.T) @ X.reshape(4)
+        assert np.max(np.abs(lhs - rhs)) < 1e-14
+
+
+def test_permutation_conjugate_transpose():
+    assert np.array_equal(PERM @ PERM, np.eye(4))
+    for _ in range(20):
+        G = rand_c(RNG, 2, 2)
+        assert np.max(np.abs(vec(dagger(G)) - PERM @ np.conj(vec(G)))) < 1e-15
+
+
+def test_chain_dagger_reverse_and_empty_identity():
+    rng = np.random.default_rng(1)
+    vis = make_vis(rng, n_ant=3, n_time=1, n_chan=1)
+    chain = [make_term(rng, k, 1, 1, 3) for k in ("c2x2", "diag", "c2x2")]
+    rows = np.array([0]); chans = np.array([0]); ants = np.array([1])
+    C = jones.chain_product(chain, vis, rows, chans, ants, 0, 0, 3)[0]
+    Gs = [jones.term_jones(t, vis, rows, chans, ants, 0)[0] for t in chain]
+    rev = dagger(Gs[2]) @ dagger(Gs[1]) @ dagger(Gs[0])
+    assert np.max(np.abs(dagger(C) - rev)) < 1e-14
+    E = jones.chain_product(chain, vis, rows, chans, ants, 0, 1, 1)[0]
+    assert np.array_equal(E, np.eye(2))
+
+
+# --------------------------------------------------------------------------
+# Jacobian blocks against finite-difference Wirtinger derivatives
+# --------------------------------------------------------------------------
+
+def _model_of_sample(vis, chain, r, c, p, q):
+    N = len(chain)
+    V = np.zeros((2, 2), complex)
+    for d in range(vis.model.shape[2]):
+        Cp = jones.chain_product(chain, vis, np.array([r]), np.array([c]), np.array([p]), d, 0, N)[0]
+        Cq = jones.chain_product(chain, vis, np.array([r]), np.array([c]), np.array([q]), d, 0, N)[0]
+        V += Cp @ unvec(np.asarray(vis.model)[r, c, d]) @ dagger(Cq)
+    return V.reshape(4)
+
+
+@pytest.mark.parametrize("dd", [False, True])
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_jacobian_block_matches_fd(dd, n):
+    rng = np.random.default_rng(7 + n + 10 * dd)
+    vis = make_vis(rng, n_ant=4, n_time=1, n_chan=1, n_dir=2)
+    kinds = ["c2x2", "c2x2", "diag"]
+    chain = [make_term(rng, k, 1, 1, 4, n_dir=2, dd=(dd if j == n else False))
+             for j, k in enumerate(kinds)]
+    chain[n] = make_term(rng, "c2x2", 1, 1, 4, n_dir=2, dd=dd)
+    r = 2
+    p, q = vis.ant1[r], vis.ant2[r]
+    for orient in ("fwd", "conj"):
+        s = solver.samples_of(vis, np.array([r]), np.array([0]))
+        if orient == "conj":
+            s = solver.conjugate_samples(s)
+        _, K, _ = solver.model_and_blocks(vis, chain, n, s)
+        a = s.p[0]
+        h = 1e-6
+        for gd in range(int(chain[n].n_gdir)):
+            for u in range(4):
+                cols = []
+                for dz in (h, 1j * h):
+                    vals = []
+                    for sgn in (1, -1):
+                        ch = solver.copy_chain(chain)
+                        ch[n].gains[0, 0, a, gd, u] += sgn * dz
+                        V = _model_of_sample(vis, ch, r, 0, p, q)
+                        if orient == "conj":
+                            V = vec(dagger(unvec(V)))
+                        vals.append(V)
+                    cols.append((vals[0] - vals[1]) / (2 * h))
+                dv_dg = 0.5 * (cols[0] - 1j * cols[1])
+                assert np.max(np.abs(K[0, gd, :, u] - dv_dg)) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# AllJones blocks = diagonal blocks of the dense augmented J^H W J
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["c2x2", "diag"])
+@pytest.mark.parametrize("dd", [False, True])
+def test_alljones_blocks_equal_dense_diagonal(kind, dd):
+    rng = np.random.default_rng(11 + dd)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=1, n_chan=3, n_dir=2)
+    chain = [make_term(rng, "c2x2", 1, 3, n_ant, n_dir=2),
+             make_term(rng, kind, 1, 3, n_ant, n_dir=2, dd=dd),
+             make_term(rng, "diag", 1, 3, n_ant, n_dir=2)]
+    n = 1
+    vis.data = forward_data(vis, chain) + 0.3 * rand_c(rng, *vis.data.shape)
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(3))
+    JHJ, JHr, _ = solver.accumulate(vis, chain, n, s)
+    D_JHJ, D_JHr, idx = dense.dense_complex(vis, chain, n, 0, 0)
+    nunk = len(idx)
+    U = solver.UNKNOWNS[kind]
+    scale = np.max(np.abs(D_JHJ))
+    for a in range(n_ant):
+        for g in range(int(chain[n].n_gdir)):
+            sel = [j for j, (aa, gg, _) in enumerate(idx) if aa == a and gg == g]
+            blk = D_JHJ[np.ix_(sel, sel)]
+            assert np.max(np.abs(blk - JHJ[a, g])) < 1e-7 * scale
+            # J = -dv/dg, so the dense J^H W r_aug is minus the oracle's JHr
+            assert np.max(np.abs(-D_JHr[sel] - JHr[a, g])) < 1e-7 * scale
+    assert D_JHJ.shape == (2 * nunk, 2 * nunk)
+    assert len(U) * n_ant * int(chain[n].n_gdir) == nunk
+
+
+def test_delay_blocks_equal_dense_2re_form():
+    rng = np.random.default_rng(5)
+    n_ant = 4
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=4, n_dir=1, freq0=1.0e9, dfreq=50e6)
+    chain = [make_term(rng, "delay", 2, 4, n_ant), make_term(rng, "diag", 2, 4, n_ant)]
+    vis.data = forward_data(vis, chain) + 0.2 * rand_c(rng, *vis.data.shape)
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(4))
+    JHJ, JHr, _ = solver.accumulate(vis, chain, 0, s)
+    D_JHJ, D_JHr, idx = dense.dense_delay(vis, chain, 0, 0, 0, h=1e-14)
+    scale = np.max(np.abs(D_JHJ))
+    for a in range(n_ant):
+        sel = [j for j, (aa, _, _) in enumerate(idx) if aa == a]
+        # eq. jhj_entry_param: J_o^H W J_o = 2 Re(...); J_o = -dv/dtau
+        assert np.max(np.abs(D_JHJ[np.ix_(sel, sel)] - 2 * JHJ[a, 0])) < 1e-6 * scale
+        assert np.max(np.abs(D_JHr[sel] + 2 * JHr[a, 0])) < 1e-6 * scale
+
+
+def test_jhj_hermitian_psd():
+    rng = np.random.default_rng(3)
+    vis = make_vis(rng, n_ant=6, n_time=2, n_chan=3, n_dir=2)
+    chain = [make_term(rng, "c2x2", 2, 3, 6, n_dir=2), make_term(rng, "c2x2", 2, 3, 6, n_dir=2, dd=True)]
+    vis.data = rand_c(rng, *vis.data.shape)
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(3))
+    for n in (0, 1):
+        JHJ, _, _ = solver.accumulate(vis, chain, n, s)
+        for blk in JHJ.reshape(-1, 4, 4):
+            nrm = np.max(np.abs(blk))
+            assert np.max(np.abs(blk - dagger(blk))) <= 1e-14 * nrm
+            assert np.min(np.linalg.eigvalsh(blk)) >= -1e-12 * nrm
+
+
+# --------------------------------------------------------------------------
+# closed forms: one-step exactness, StefCal, damping 2-cycle
+# --------------------------------------------------------------------------
+
+def test_one_full_step_exact_for_single_perturbed_antenna():
+    rng = np.random.default_rng(9)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=1, n_chan=4, n_dir=1)
+    truth = [make_term(rng, "c2x2", 1, 4, n_ant)]
+    vis.data = forward_data(vis, truth)
+    start = solver.copy_chain(truth)
+    a = 2
+    start[0].gains[0, 0, a, 0] += 0.2 * rand_c(rng, 4)
+    out, _ = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=1, damping="full")
+    assert np.max(np.abs(out[0].gains[0, 0, a] - truth[0].gains[0, 0, a])) < 1e-13
+
+
+def test_single_diagonal_step_is_stefcal_closed_form():
+    rng = np.random.default_rng(21)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=3, n_dir=1)
+    vis.data = rand_c(rng, *vis.data.shape)
+    start = [make_term(rng, "diag", 2, 3, n_ant)]
+    out, _ = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=1, damping="full")
+    g = start[0].gains[0, 0]
+    # weighted alternating least squares, written sample by sample:
+    # g_a^i = sum w conj(y) d / sum w |y|^2 over every correlation (i, b) of
+    # every baseline touching a, with y = m[i,b] conj(g_q^b) (a first) or the
+    # conjugate-transposed sample (a second).
+    for a in range(n_ant):
+        for i, c in enumerate((0, 3)):
+            num = 0j
+            den = 0.0
+            for r in range(vis.data.shape[0]):
+                p, q = vis.ant1[r], vis.ant2[r]
+                for ch in range(3):
+                    D = vis.data[r, ch].reshape(2, 2)
+                    M = vis.model[r, ch, 0].reshape(2, 2)
+                    W = vis.weight[r, ch].reshape(2, 2)
+                    if p == a:
+                        Dm, Mm, Wm, other = D, M, W, q
+                    elif q == a:
+                        Dm, Mm, Wm, other = D.conj().T, M.conj().T, W.T, p
+                    else:
+                        continue
+                    go = np.array([g[other, 0, 0], g[other, 0, 3]])
+                    for b in range(2):
+                        y = Mm[i, b] * np.conj(go[b])
+                        num += Wm[i, b] * np.conj(y) * Dm[i, b]
+                        den += Wm[i, b] * abs(y) ** 2
+            assert abs(out[0].gains[0, 0, a, 0, c] - num / den) < 1e-13
+
+
+def test_full_step_two_cycle_closed_form():
+    rng = np.random.default_rng(4)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=1, n_chan=3, n_dir=1, polarised=False)
+    truth = [make_term(rng, "diag", 1, 3, n_ant)]
+    vis.data = forward_data(vis, truth)
+    c = 1.3
+    start = solver.copy_chain(truth)
+    start[0].gains = truth[0].gains * c
+    out, _ = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=1, damping="full")
+    expect = truth[0].gains / np.conj(c)
+    assert np.max(np.abs(out[0].gains[..., [0, 3]] - expect[..., [0, 3]])) < 1e-13
+    out2, _ = solver.solve_term(vis, out, 0, tol=-1.0, max_iter=1, damping="full")
+    assert np.max(np.abs(out2[0].gains[..., [0, 3]] - start[0].gains[..., [0, 3]])) < 1e-13
+
+
+def test_block_solve_cholesky_textbook():
+    rng = np.random.default_rng(2)
+    A = rand_c(rng, 4, 4)
+    H = A @ dagger(A) + 0.1 * np.eye(4)
+    b = rand_c(rng, 4)
+    x, sing = solver.block_solve(H, b)
+    assert not sing
+    assert np.max(np.abs(x - np.linalg.solve(H, b))) < 1e-12
+    Hs = np.zeros((2, 2), complex); Hs[0, 0] = 1.0
+    _, sing = solver.block_solve(Hs, np.ones(2, complex))
+    assert sing
+
+
+# --------------------------------------------------------------------------
+# exact recovery of the truth up to gauge (noise-free)
+# --------------------------------------------------------------------------
+
+def test_recovery_tiny_diagonal():
+    p = config_tiny(sigma=0.0)
+    vis = to_numpy_vis(p.vis)
+    out, st = solver.solve_term(vis, p.chain, 0, tol=1e-12, max_iter=200)
+    assert st["converged"].all()
+    err = np.abs(reference_diag(out[0].gains)[..., [0, 3]] - reference_diag(p.truth[0].gains)[..., [0, 3]])
+    assert err.max() < 1e-10
+    V = outputs.corrupt(vis, out)
+    assert np.max(np.abs(V - vis.data)) < 1e-10
+
+
+def test_recovery_full_jones_polarised_model():
+    rng = np.random.default_rng(17)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=4, n_chan=4, n_dir=1)
+    truth = [make_term(rng, "c2x2", 4, 4, n_ant, t_int=2, f_int=2, scale=0.2)]
+    vis.data = forward_data(vis, truth)
+    out, st = solver.solve_term(vis, [unit_like(truth[0])], 0, tol=1e-12, max_iter=400)
+    assert st["converged"].all()
+    R = outputs.residual(vis, out)
+    assert np.max(np.abs(R)) < 1e-9
+
+
+def test_recovery_delay_in_basin():
+    rng = np.random.default_rng(23)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=16, n_dir=1, polarised=False,
+                   freq0=1.0e9, dfreq=10e6)
+    truth = [make_term(rng, "delay", 2, 16, n_ant)]
+    truth[0].params = rng.uniform(-0.4e-9, 0.4e-9, truth[0].params.shape)
+    truth[0].params[:, :, 0] = 0.0
+    vis.data = forward_data(vis, truth)
+    start = unit_like(truth[0])
+    out, st = solver.solve_term(vis, [start], 0, tol=1e-12, max_iter=200)
+    assert st["converged"].all()
+    # delays carry a gauge: only tau_p - tau_q enters the data, per hand
+    got = out[0].params - out[0].params[:, :, :1]
+    assert np.max(np.abs(got - truth[0].params)) < 1e-15
+
+
+def test_recovery_direction_dependent_four_directions():
+    rng = np.random.default_rng(29)
+    n_ant = 7
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=6, n_dir=4, polarised=False)
+    truth = [make_term(rng, "diag", 2, 6, n_ant, n_dir=4, dd=True, scale=0.15)]
+    vis.data = forward_data(vis, truth)
+    out, st = solver.solve_term(vis, [unit_like(truth[0])], 0, tol=1e-12, max_iter=2000)
+    R = outputs.residual(vis, out)
+    assert np.max(np.abs(R)) < 1e-8
+
+
+def test_recovery_chain_of_two_terms():
+    rng = np.random.default_rng(31)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=4, n_chan=4, n_dir=1, polarised=False)
+    truth = [make_term(rng, "diag", 4, 4, n_ant, t_int=4, f_int=1, scale=0.2),
+             make_term(rng, "diag", 4, 4, n_ant, t_int=1, f_int=4, scale=0.2)]
+    vis.data = forward_data(vis, truth)
+    chain = [unit_like(t) for t in truth]
+    chain, _ = solver.solve_chain(vis, chain, n_epoch=30, tol=1e-13, max_iter=200)
+    R = outputs.residual(vis, chain)
+    assert np.max(np.abs(R)) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# identities of the model and invariances
+# --------------------------------------------------------------------------
+
+def test_di_equals_dd_with_equal_gains():
+    rng = np.random.default_rng(37)
+    vis = make_vis(rng, n_ant=4, n_time=1, n_chan=2, n_dir=3)
+    di = make_term(rng, "c2x2", 1, 2, 4, n_dir=3, dd=False)
+    dd = make_term(rng, "c2x2", 1, 2, 4, n_dir=3, dd=True)
+    dd.gains = np.repeat(di.gains, 3, axis=3)
+    vis.data = rand_c(rng, *vis.data.shape)
+    V1 = outputs.corrupt(vis, [di])
+    V2 = outputs.corrupt(vis, [dd])
+    assert np.max(np.abs(V1 - V2)) < 1e-14
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(2))
+    _, K1, _ = solver.model_and_blocks(vis, [di], 0, s)
+    _, K2, _ = solver.model_and_blocks(vis, [dd], 0, s)
+    assert np.max(np.abs(K1[:, 0] - K2.sum(axis=1))) < 1e-14
+
+
+def _noisy_problem(seed):
+    rng = np.random.default_rng(seed)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=4, n_chan=4, n_dir=1)
+    truth = [make_term(rng, "c2x2", 4, 4, n_ant, t_int=2, f_int=2, scale=0.2)]
+    vis.data = forward_data(vis, truth) + 0.05 * rand_c(rng, *vis.data.shape)
+    return vis, [unit_like(truth[0])]
+
+
+def test_interval_independence():
+    vis, chain = _noisy_problem(41)
+    a, _ = solver.solve_term(vis, chain, 0, tol=1e-8, max_iter=50)
+    vis2 = vis.copy(data=vis.data.copy())
+    rows = np.nonzero(vis.row_time >= 2)[0]          # second time interval only
+    vis2.data[rows] += 10.0
+    b, _ = solver.solve_term(vis2, chain, 0, tol=1e-8, max_iter=50)
+    assert np.array_equal(a[0].gains[0], b[0].gains[0])
+    assert not np.allclose(a[0].gains[1], b[0].gains[1])
+
+
+def test_row_permutation_invariance():
+    vis, chain = _noisy_problem(43)
+    a, _ = solver.solve_term(vis, chain, 0, tol=1e-10, max_iter=60)
+    perm = np.random.default_rng(1).permutation(vis.data.shape[0])
+    vp = vis.copy(data=vis.data[perm], model=vis.model[perm], weight=vis.weight[perm],
+                  flag=vis.flag[perm], ant1=vis.ant1[perm], ant2=vis.ant2[perm],
+                  row_time=vis.row_time[perm])
+    b, _ = solver.solve_term(vp, chain, 0, tol=1e-10, max_iter=60)
+    assert np.max(np.abs(a[0].gains - b[0].gains)) < 1e-12
+
+
+def test_conjugate_baseline_swap_invariance():
+    vis, chain = _noisy_problem(47)
+    a, _ = solver.solve_term(vis, chain, 0, tol=1e-10, max_iter=60)
+    sw = np.arange(vis.data.shape[0]) % 3 == 0
+    D, M, W = vis.data.copy(), vis.model.copy(), vis.weight.copy()
+    D[sw] = vec(dagger(unvec(D[sw])))
+    M[sw] = vec(dagger(unvec(M[sw])))
+    W[sw] = W[sw][..., [0, 2, 1, 3]]
+    a1, a2 = vis.ant1.copy(), vis.ant2.copy()
+    a1[sw], a2[sw] = vis.ant2[sw], vis.ant1[sw]
+    vs = vis.copy(data=D, model=M, weight=W, ant1=a1, ant2=a2)
+    b, _ = solver.solve_term(vs, chain, 0, tol=1e-10, max_iter=60)
+    assert np.max(np.abs(a[0].gains - b[0].gains)) < 1e-12
+
+
+def test_garbage_under_flags_is_ignored():
+    vis, chain = _noisy_problem(53)
+    rng = np.random.default_rng(2)
+    flag = (rng.random(vis.flag.shape) < 0.2).astype(np.uint8)
+    v1 = vis.copy(flag=flag)
+    a, _ = solver.solve_term(v1, chain, 0, tol=1e-10, max_iter=60)
+    D = vis.data.copy(); M = vis.model.copy(); W = vis.weight.copy()
+    D[flag == 1] = np.nan
+    M[flag == 1] = 1e30
+    W[flag == 1] = np.inf
+    v2 = vis.copy(data=D, model=M, weight=W, flag=flag)
+    b, _ = solver.solve_term(v2, chain, 0, tol=1e-10, max_iter=60)
+    assert np.array_equal(a[0].gains, b[0].gains)
+
+
+def test_fully_flagged_antenna_gets_gain_flag():
+    vis, chain = _noisy_problem(59)
+    flag = np.zeros_like(vis.flag)
+    flag[(vis.ant1 == 3) | (vis.ant2 == 3)] = 1
+    out, _ = solver.solve_term(vis.copy(flag=flag), chain, 0, tol=1e-8, max_iter=20)
+    assert (out[0].gain_flags[:, :, 3] == 1).all()
+    assert (out[0].gain_flags[:, :, [0, 1, 2, 4, 5]] == 0).all()
+    assert np.array_equal(out[0].gains[:, :, 3], chain[0].gains[:, :, 3])
+
+
+def test_noisy_tiny_statistics():
+    p = config_tiny(sigma=0.01)
+    vis = to_numpy_vis(p.vis)
+    out, st = solver.solve_term(vis, p.chain, 0, tol=1e-10, max_iter=200)
+    err = np.abs(reference_diag(out[0].gains)[..., [0, 3]] - reference_diag(p.truth[0].gains)[..., [0, 3]])
+    # per gain: sigma / sqrt(sum |y|^2) with ~ 6 baselines x 40 samples x 2 corr, |y| ~ 1
+    assert 1e-4 < np.sqrt(np.mean(err ** 2)) < 1e-2
+    n_samp = vis.data.shape[0] * vis.data.shape[1]
+    dof = 2 * 4 * n_samp
+    R = outputs.residual(vis, out)
+    chi2 = np.sum(np.abs(R) ** 2) / 0.01 ** 2
+    assert 0.8 < chi2 / dof < 1.2
+
+
+# --------------------------------------------------------------------------
+# outputs
+# --------------------------------------------------------------------------
+
+def test_outputs_corrupt_correct_residual():
+    rng = np.random.default_rng(61)
+    vis = make_vis(rng, n_ant=5, n_time=2, n_chan=3, n_dir=2)
+    chain = [make_term(rng, "c2x2", 2, 3, 5, n_dir=2), make_term(rng, "diag", 2, 3, 5, n_dir=2)]
+    vis.data = forward_data(vis, chain)
+    assert np.max(np.abs(outputs.corrupt(vis, chain) - vis.data)) < 1e-13
+    assert np.max(np.abs(outputs.residual(vis, chain))) < 1e-13
+    mask = np.array([1, 0], np.uint8)
+    only0 = vis.copy(model=vis.model[:, :, :1])
+    assert np.max(np.abs(outputs.corrupt(vis, chain, mask) - forward_data(only0, chain))) < 1e-13
+    v1 = vis.copy(model=vis.model[:, :, :1])
+    v1.data = forward_data(v1, chain)
+    C = outputs.correct(v1, chain)
+    assert np.max(np.abs(C - v1.model[:, :, 0])) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# delay initial estimate
+# --------------------------------------------------------------------------
+
+def test_delay_init_recovers_delays_within_grid():
+    rng = np.random.default_rng(67)
+    n_ant = 5
+    n_chan = 64
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=n_chan, n_dir=1, polarised=False,
+                   freq0=856e6, dfreq=856e6 / n_chan)
+    truth = [make_term(rng, "delay", 2, n_chan, n_ant)]
+    truth[0].params = rng.uniform(-5e-9, 5e-9, truth[0].params.shape)
+    truth[0].params[:, :, 0] = 0.0
+    vis.data = forward_data(vis, truth)
+    out = delay_init.delay_init(vis, [unit_like(truth[0])], 0, ref_ant=0)
+    step = delay_init.delay_grid(vis.chan_freq)[1] - delay_init.delay_grid(vis.chan_freq)[0]
+    assert np.max(np.abs(out[0].params - truth[0].params)) <= 0.5 * step + 1e-15
+
+
+# --------------------------------------------------------------------------
+# warm-start MLP and features
+# --------------------------------------------------------------------------
+
+def test_mlp_backward_matches_finite_differences():
+    rng = np.random.default_rng(71)
+    I, H, O, B = 6, 5, 4, 3
+    n = sum(warmstart.param_sizes(I, H, O))
+    params = rng.standard_normal(n) * 0.5
+    x = rng.standard_normal((B, I))
+    t = rng.standard_normal((B, O))
+    y, pre = warmstart.forward(params, x, I, H, O)
+    L, dy = warmstart.mse(y, t)
+    g = warmstart.backward(params, x, pre, dy, I, H, O)
+    h = 1e-6
+    for j in range(n):
+        e = np.zeros(n); e[j] = h
+        Lp, _ = warmstart.mse(warmstart.forward(params + e, x, I, H, O)[0], t)
+        Lm, _ = warmstart.mse(warmstart.forward(params - e, x, I, H, O)[0], t)
+        assert abs((Lp - Lm) / (2 * h) - g[j]) < 1e-7
+
+
+def test_adam_first_step_is_sign_step():
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = warmstart.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 0.01, 0.9, 0.999, 1e-12, 1)
+    assert np.max(np.abs(p + 0.01 * np.sign(g))) < 1e-9
+
+
+def test_features_equal_gain_product_noise_free():
+    rng = np.random.default_rng(73)
+    vis = make_vis(rng, n_ant=2, n_time=2, n_chan=3, n_dir=1, polarised=False)
+    truth = [make_term(rng, "diag", 2, 3, 2)]
+    truth[0].gains = truth[0].gains[:1, :1].repeat(1, 0)
+    truth[0].t_map = np.zeros(2, np.int32); truth[0].f_map = np.zeros(3, np.int32)
+    truth[0].n_gt = truth[0].n_gf = 1
+    vis.data = forward_data(vis, truth)
+    f = warmstart.features(vis, truth[0], 0, 0).reshape(2, 4, 2)
+    g = truth[0].gains[0, 0, :, 0]
+    rho = f[..., 0] + 1j * f[..., 1]
+    # one baseline (0,1): D_XX = g0X M conj(g1X) -> rho_0,XX = g0X conj(g1X)
+    assert abs(rho[0, 0] - g[0, 0] * np.conj(g[1, 0])) < 1e-12
+    assert abs(rho[1, 3] - g[1, 3] * np.conj(g[0, 3])) < 1e-12
