@@ -1,0 +1,192 @@
+/*
+ * qc.h - C-ABI of libqc, an MI355X (gfx950) implementation of the
+ * per-solution-interval Jones-chain gain solver of Kenyon et al.,
+ * "Africanus II. QuartiCal: calibrating radio interferometer data at scale
+ * using Numba and Dask" (arXiv 2412.10072).
+ *
+ * The method (Section 2 and Algorithm 1 of the paper): for every solution
+ * interval of one chain term, form the corrupted model
+ *     V_pq = sum_d C_{p,d} M_{pq,d} C_{q,d}^H            (eq. baselinemodel)
+ * with C a product of 2x2 Jones terms (eq. joneschain), the residual
+ * r = d - v (eq. baselineresidual), reduce the per-antenna "AllJones" blocks
+ * J^H W J and J^H W r over every row and channel of the interval
+ * (eq. jhj_entry_simplified, eq. jhr_entry_simplified; eq. jhj_case2 /
+ * eq. jhwr_case2 for delay terms), solve the small per-antenna systems and
+ * update the gains (eq. update), and iterate to convergence.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array pointer is a DEVICE pointer owned by the caller.  The library
+ *   never frees or retains it beyond the enqueued work.
+ * - 2x2 matrices are stored row-major as 4 correlations XX, XY, YX, YY
+ *   (eq. gvec, eq. jones).  complex64 = 2 x float (re, im), complex128 =
+ *   2 x double.
+ * - Rows are ordered by time (row_time non-decreasing); every term's t_map
+ *   and f_map are non-decreasing, so each solution interval is a contiguous
+ *   block of rows x a contiguous block of channels.  Violations are reported
+ *   as QC_E_ARG / QC_E_RANGE before any solve work is enqueued.
+ * - Errors: no exception crosses the ABI.  A non-OK status leaves a message
+ *   in qc_last_error(ctx).  Non-convergence is not an error (stats.converged
+ *   = 0); a singular or empty per-antenna block is not an error (its
+ *   gain_flags entry is set to 1 and its update is zero).  A non-finite value
+ *   in an unflagged sample is latched on the device and returned by
+ *   qc_ctx_sync as QC_E_NONFINITE.
+ * - Work is enqueued on `stream` (NULL = the null stream).  The argument
+ *   checks that need device data (row_time order, antenna and map ranges)
+ *   run first on the same stream and are waited for, so a call that returns
+ *   QC_OK has passed them.  The solve itself is asynchronous.
+ */
+#ifndef QC_H
+#define QC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qc_status;
+#define QC_OK           0
+#define QC_E_ARG       -1   /* bad argument (null pointer, bad enum, bad size, unsorted rows) */
+#define QC_E_RANGE     -2   /* antenna / time / map index out of range                        */
+#define QC_E_NONFINITE -3   /* non-finite value in an unflagged sample (latched)              */
+#define QC_E_DEVICE    -4   /* HIP runtime error                                              */
+#define QC_E_NOMEM     -5   /* device allocation failed                                       */
+#define QC_E_UNSUPPORTED -6 /* valid input outside what the library implements (message says) */
+
+#define QC_MAX_TERMS 8      /* chain length limit                                   */
+#define QC_MAX_DIR   8      /* model directions limit                               */
+#define QC_MAX_GDIR  4      /* gain directions of one term                          */
+#define QC_MAX_ANT   256    /* antennas                                             */
+
+typedef enum { QC_C64 = 0, QC_C128 = 1 } qc_dtype;          /* storage of data/model */
+typedef enum { QC_PREC_FP64 = 0, QC_PREC_MIXED = 1 } qc_prec;
+/* QC_PREC_FP64 : every product, sum and solve in FP64 (complex64 inputs are
+ *                upcast exactly).
+ * QC_PREC_MIXED: complex64 products and residuals, FP32 accumulation with
+ *                compensated (Kahan) sums of the per-antenna blocks, FP64
+ *                block solve, update and convergence test.  Needs QC_C64.   */
+
+typedef enum { QC_TERM_DIAGONAL = 0, QC_TERM_COMPLEX2X2 = 1, QC_TERM_DELAY = 2 } qc_term_type;
+/* DIAGONAL  : unknowns XX, YY of the gain (XY = YX = 0).
+ * COMPLEX2X2: all four entries.
+ * DELAY     : real parameters tau_X, tau_Y (seconds); the Jones matrix is
+ *             diag(exp(2 pi i nu tau_X), exp(2 pi i nu tau_Y)) at channel
+ *             frequency nu (the paper's second parameterisation scenario,
+ *             eq. jhj_case2, with a delay as the coarse parameter).       */
+
+typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3 } qc_damping;
+/* Step length alpha_k of x <- x + alpha_k * Delta (the paper leaves the step
+ * open, noting that Levenberg-Marquardt is a trivial extension):
+ * FULL alpha = 1; HALF alpha = 1/2; ALTERNATE alpha = 1 on odd, 1/2 on even
+ * updates; AUTO = FULL for delay terms, HALF for direction-dependent terms,
+ * ALTERNATE otherwise.                                                       */
+
+typedef enum { QC_CORRUPT = 0, QC_CORRECT = 1 } qc_apply_mode;
+
+typedef struct qc_ctx qc_ctx;   /* opaque: device, scratch, latched device error */
+
+/* Create a context on HIP device `device`.  One context per host thread. */
+qc_status   qc_ctx_create(int32_t device, qc_ctx** out);
+/* Destroy a context and free its scratch memory. */
+qc_status   qc_ctx_destroy(qc_ctx* ctx);
+/* Wait for the last stream used by ctx; returns a latched device error
+ * (QC_E_NONFINITE / QC_E_RANGE) and clears it. */
+qc_status   qc_ctx_sync(qc_ctx* ctx);
+/* Message for the last non-OK status of ctx; valid until the next call. */
+const char* qc_last_error(const qc_ctx* ctx);
+/* Duration in milliseconds of the last solve kernel launched through ctx,
+ * measured with HIP events on the launch stream around that kernel alone
+ * (waits for it).  Negative if none. */
+double      qc_last_kernel_ms(qc_ctx* ctx);
+
+/* One visibility set (paper Section 2.2; data model of Section 4.1). */
+typedef struct {
+  int64_t n_row;
+  int32_t n_chan, n_dir, n_ant, n_time, n_wcorr;  /* n_wcorr in {1, 4}        */
+  qc_dtype dtype;
+  const void*    data;      /* [n_row][n_chan][4]          complex            */
+  const void*    model;     /* [n_row][n_chan][n_dir][4]   complex            */
+  const void*    weight;    /* [n_row][n_chan][n_wcorr]    float (C64) / double (C128) */
+  const uint8_t* flag;      /* [n_row][n_chan]             nonzero = flagged  */
+  const int32_t* ant1;      /* [n_row] p                                      */
+  const int32_t* ant2;      /* [n_row] q (rows with p == q are ignored)       */
+  const int32_t* row_time;  /* [n_row] time index in [0, n_time), non-decreasing */
+  const double*  chan_freq; /* [n_chan] Hz                                    */
+} qc_vis;
+
+/* One term of the Jones chain with its own solution intervals (paper
+ * Section 4.3: data-to-gain mappings; gain layout of Section 4.4). */
+typedef struct {
+  qc_term_type type;
+  int32_t direction_dependent;  /* informs QC_DAMP_AUTO only; d_map decides the sharing */
+  int32_t n_gt, n_gf, n_gdir;
+  const int32_t* t_map;     /* [n_time] -> [0, n_gt), non-decreasing          */
+  const int32_t* f_map;     /* [n_chan] -> [0, n_gf), non-decreasing          */
+  const int32_t* d_map;     /* [n_dir]  -> [0, n_gdir)                        */
+  void*   gains;            /* [n_gt][n_gf][n_ant][n_gdir][4] complex128, in/out (DIAGONAL, COMPLEX2X2) */
+  double* params;           /* [n_gt][n_gf][n_ant][n_gdir][2] tau_X, tau_Y in s, in/out (DELAY) */
+  int8_t* gain_flags;       /* [n_gt][n_gf][n_ant][n_gdir] out (may be NULL for fixed terms) */
+} qc_term;
+
+typedef struct {
+  double     tol;           /* stop when the step ratio <= tol (negative: never) */
+  int32_t    max_iter;      /* updates per interval; 0 = evaluate chi^2 only     */
+  qc_prec    prec;
+  qc_damping damping;
+  void*      stream;        /* hipStream_t or NULL                               */
+} qc_solve_opts;
+
+/* Per interval of the active term, [n_gt][n_gf]; any pointer may be NULL. */
+typedef struct {
+  int32_t* iters;           /* number of applied updates                         */
+  uint8_t* converged;       /* 1 if the step ratio reached tol                    */
+  double*  chisq_first;     /* sum w |r|^2 at the initial gains                   */
+  double*  chisq_last;      /* sum w |r|^2 at the gains before the last update    */
+} qc_solve_stats;
+
+/*
+ * Solve term `active` of `chain` (chain order = array order, C = G_0 G_1 ...,
+ * eq. joneschain) over all of its solution intervals, each independently
+ * (Section 2.3, last paragraph), with the other terms fixed (Section 4.3).
+ * Algorithm 1 per interval:
+ *   repeat: accumulate JHJ and JHr per (antenna, gain direction) over the
+ *   interval's unflagged cross-correlation samples, conjugate baselines
+ *   folded in (eq. jhj_entry_simplified, eq. jhr_entry_simplified);
+ *   Delta = JHJ^-1 JHr by FP64 Cholesky; x <- x + alpha_k Delta;
+ *   stop when ||alpha_k Delta||_2 / ||x||_2 <= tol over the unflagged blocks
+ *   (delay: max over blocks of 2 pi nu_max |alpha_k Delta tau| <= tol) or
+ *   after max_iter updates.
+ * A block whose Cholesky pivot is <= 1e-12 of its largest diagonal entry (or
+ * that has no data) gets Delta = 0 and gain_flags = 1.
+ * The active term's gains/params are overwritten in place.
+ * Limitation: every term left of the active one must be DIAGONAL or DELAY
+ * with all its directions mapped to one gain direction (QC_E_UNSUPPORTED
+ * otherwise).
+ */
+qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
+                            int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats);
+
+/*
+ * Visibility outputs (Section 4.4).  For every (row, channel), flagged
+ * samples and autocorrelations included:
+ *   CORRUPT: out = sum_{d in mask} C_{p,d} M_d C_{q,d}^H
+ *   CORRECT: out = C_p^-1 D C_q^-H  (direction 0 of a chain whose every term
+ *            maps all directions to one gain; 0 where C_p or C_q is singular)
+ * dir_mask: [n_dir] uint8 host array, NULL = all directions.
+ * out: [n_row][n_chan][4] device array of the data dtype.  Arithmetic is in
+ * the data precision (complex64 -> FP32, complex128 -> FP64).
+ */
+qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
+                         qc_apply_mode mode, const uint8_t* dir_mask, void* out, void* stream);
+
+/* Residual r = D - sum_{d in mask} C_{p,d} M_d C_{q,d}^H (eq. baselineresidual);
+ * a mask that drops directions peels them.  Same layout and precision rules as
+ * qc_apply_gains. */
+qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
+                      const uint8_t* dir_mask, void* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QC_H */

@@ -1,0 +1,458 @@
+// Host side of the libqc C-ABI: context, argument checks, the device-side
+// validation pre-pass (row order, antenna and time ranges, per-interval row
+// ranges) and the public entry points declared in include/qc.h.
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qc_internal.h"
+
+using namespace qc;
+
+struct qc_ctx {
+  int device = 0;
+  std::string msg;
+  hipStream_t last_stream = nullptr;
+  int* d_err = nullptr;
+  long long* d_rowpos = nullptr;
+  size_t rowpos_cap = 0;
+  long long* d_rowlo = nullptr;
+  size_t rowlo_cap = 0;
+  long long* d_rowhi = nullptr;
+  size_t rowhi_cap = 0;
+  int* d_tt = nullptr;        // [2][n_gt] time range per gain time
+  size_t tt_cap = 0;
+  int* d_chlo = nullptr;
+  size_t chlo_cap = 0;
+  int* d_chhi = nullptr;
+  size_t chhi_cap = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  int waves = 4;
+};
+
+namespace {
+
+qc_status fail(qc_ctx* ctx, qc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->msg = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? QC_E_NOMEM : QC_E_DEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                    \
+  } while (0)
+
+template <typename P>
+hipError_t grow(P*& ptr, size_t& cap, size_t n) {
+  if (n <= cap && ptr) return hipSuccess;
+  if (ptr) {
+    hipError_t e = hipFree(ptr);
+    if (e != hipSuccess) return e;
+    ptr = nullptr;
+  }
+  size_t want = std::max<size_t>(n, 64);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), want * sizeof(P));
+  if (e != hipSuccess) {
+    cap = 0;
+    ptr = nullptr;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// validation kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_clear(int* err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) err[0] = 0;
+}
+
+// For rows sorted by time, rowpos[t] = first row with row_time >= t
+// (t = 0 .. n_time).  Each entry is written by exactly one row when the
+// order is valid; bad input raises a flag and every write stays in bounds.
+__global__ void k_rows(VisArgs v, long long* rowpos, int* err) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= v.n_row) return;
+  const int nt = v.n_time;
+  int t = v.row_time[r];
+  const int p = v.ant1[r], q = v.ant2[r];
+  int bad = 0;
+  if ((unsigned)p >= (unsigned)v.n_ant || (unsigned)q >= (unsigned)v.n_ant) bad |= ERR_RANGE;
+  if ((unsigned)t >= (unsigned)nt) bad |= ERR_RANGE;
+  int tp = (r > 0) ? v.row_time[r - 1] : -1;
+  if (r > 0 && tp > t) bad |= ERR_ORDER;
+  if (bad) atomicOr(err, bad);
+  t = min(max(t, -1), nt - 1);
+  tp = min(max(tp, -1), nt - 1);
+  for (int tt = tp + 1; tt <= t; ++tt) rowpos[tt] = r;
+  if (r == v.n_row - 1)
+    for (int tt = max(t, -1) + 1; tt <= nt; ++tt) rowpos[tt] = v.n_row;
+}
+
+__global__ void k_rowpos_empty(long long* rowpos, int nt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= nt) rowpos[t] = 0;
+}
+
+__global__ void k_ranges(const long long* rowpos, const int* tt, int n_gt, long long* lo, long long* hi) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_gt) return;
+  lo[g] = rowpos[tt[g]];
+  hi[g] = rowpos[tt[n_gt + g]];
+}
+
+// ---------------------------------------------------------------------------
+// host checks
+// ---------------------------------------------------------------------------
+
+struct HostMaps {
+  std::vector<int> t_map, f_map, d_map;
+};
+
+qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
+  if (!v) return fail(ctx, QC_E_ARG, "vis is NULL");
+  if (v->n_row < 0 || v->n_chan <= 0 || v->n_dir <= 0 || v->n_ant <= 0 || v->n_time <= 0)
+    return fail(ctx, QC_E_ARG, "bad sizes: n_row=%lld n_chan=%d n_dir=%d n_ant=%d n_time=%d",
+                (long long)v->n_row, v->n_chan, v->n_dir, v->n_ant, v->n_time);
+  if (v->n_dir > QC_MAX_DIR) return fail(ctx, QC_E_UNSUPPORTED, "n_dir=%d exceeds %d", v->n_dir, QC_MAX_DIR);
+  if (v->n_ant > QC_MAX_ANT) return fail(ctx, QC_E_UNSUPPORTED, "n_ant=%d exceeds %d", v->n_ant, QC_MAX_ANT);
+  if (v->n_wcorr != 1 && v->n_wcorr != 4) return fail(ctx, QC_E_ARG, "n_wcorr must be 1 or 4, got %d", v->n_wcorr);
+  if (v->dtype != QC_C64 && v->dtype != QC_C128) return fail(ctx, QC_E_ARG, "bad dtype %d", (int)v->dtype);
+  if (v->n_row > 0 && (!v->data || !v->model || !v->weight || !v->flag || !v->ant1 || !v->ant2 || !v->row_time))
+    return fail(ctx, QC_E_ARG, "a visibility array pointer is NULL");
+  if (!v->chan_freq) return fail(ctx, QC_E_ARG, "chan_freq is NULL");
+  return QC_OK;
+}
+
+qc_status check_term(qc_ctx* ctx, const qc_vis* v, const qc_term* t, int j, HostMaps& hm, hipStream_t s) {
+  if (t->type != QC_TERM_DIAGONAL && t->type != QC_TERM_COMPLEX2X2 && t->type != QC_TERM_DELAY)
+    return fail(ctx, QC_E_ARG, "term %d: bad type %d", j, (int)t->type);
+  if (t->n_gt <= 0 || t->n_gf <= 0 || t->n_gdir <= 0)
+    return fail(ctx, QC_E_ARG, "term %d: bad gain shape (%d, %d, %d)", j, t->n_gt, t->n_gf, t->n_gdir);
+  if (t->n_gdir > QC_MAX_GDIR)
+    return fail(ctx, QC_E_UNSUPPORTED, "term %d: n_gdir=%d exceeds %d", j, t->n_gdir, QC_MAX_GDIR);
+  if (!t->t_map || !t->f_map || !t->d_map) return fail(ctx, QC_E_ARG, "term %d: a map pointer is NULL", j);
+  if (t->type == QC_TERM_DELAY ? !t->params : !t->gains)
+    return fail(ctx, QC_E_ARG, "term %d: %s is NULL", j, t->type == QC_TERM_DELAY ? "params" : "gains");
+  hm.t_map.resize(v->n_time);
+  hm.f_map.resize(v->n_chan);
+  hm.d_map.resize(v->n_dir);
+  HIP_TRY(ctx, hipMemcpyAsync(hm.t_map.data(), t->t_map, sizeof(int) * v->n_time, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hm.f_map.data(), t->f_map, sizeof(int) * v->n_chan, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hm.d_map.data(), t->d_map, sizeof(int) * v->n_dir, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < v->n_time; ++i) {
+    if (hm.t_map[i] < 0 || hm.t_map[i] >= t->n_gt)
+      return fail(ctx, QC_E_RANGE, "term %d: t_map[%d]=%d outside [0,%d)", j, i, hm.t_map[i], t->n_gt);
+    if (i > 0 && hm.t_map[i] < hm.t_map[i - 1])
+      return fail(ctx, QC_E_ARG, "term %d: t_map is not non-decreasing at %d", j, i);
+  }
+  for (int i = 0; i < v->n_chan; ++i) {
+    if (hm.f_map[i] < 0 || hm.f_map[i] >= t->n_gf)
+      return fail(ctx, QC_E_RANGE, "term %d: f_map[%d]=%d outside [0,%d)", j, i, hm.f_map[i], t->n_gf);
+    if (i > 0 && hm.f_map[i] < hm.f_map[i - 1])
+      return fail(ctx, QC_E_ARG, "term %d: f_map is not non-decreasing at %d", j, i);
+  }
+  for (int i = 0; i < v->n_dir; ++i)
+    if (hm.d_map[i] < 0 || hm.d_map[i] >= t->n_gdir)
+      return fail(ctx, QC_E_RANGE, "term %d: d_map[%d]=%d outside [0,%d)", j, i, hm.d_map[i], t->n_gdir);
+  return QC_OK;
+}
+
+bool dmap_constant(const HostMaps& hm) {
+  for (size_t i = 1; i < hm.d_map.size(); ++i)
+    if (hm.d_map[i] != hm.d_map[0]) return false;
+  return true;
+}
+
+void fill_args(const qc_vis* v, const qc_term* chain, int n_term, int active, VisArgs& va, ChainArgs& ca) {
+  va.data = v->data;
+  va.model = v->model;
+  va.weight = v->weight;
+  va.flag = v->flag;
+  va.ant1 = v->ant1;
+  va.ant2 = v->ant2;
+  va.row_time = v->row_time;
+  va.freq = v->chan_freq;
+  va.n_row = v->n_row;
+  va.n_chan = v->n_chan;
+  va.n_dir = v->n_dir;
+  va.n_ant = v->n_ant;
+  va.n_time = v->n_time;
+  va.n_wcorr = v->n_wcorr;
+  memset(&ca, 0, sizeof ca);
+  ca.n_term = n_term;
+  ca.active = active;
+  for (int j = 0; j < n_term; ++j) {
+    const qc_term& t = chain[j];
+    TermArgs& ta = ca.t[j];
+    ta.kind = (int)t.type;
+    ta.n_gt = t.n_gt;
+    ta.n_gf = t.n_gf;
+    ta.n_gdir = t.n_gdir;
+    ta.t_map = t.t_map;
+    ta.f_map = t.f_map;
+    ta.d_map = t.d_map;
+    ta.gains = reinterpret_cast<const double2*>(t.gains);
+    ta.params = t.params;
+  }
+}
+
+qc_status read_err(qc_ctx* ctx, hipStream_t s) {
+  int h = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (h & ERR_ORDER) return fail(ctx, QC_E_ARG, "row_time is not non-decreasing");
+  if (h & ERR_RANGE) return fail(ctx, QC_E_RANGE, "antenna or time index out of range");
+  if (h & ERR_NONFINITE) return fail(ctx, QC_E_NONFINITE, "non-finite value in an unflagged sample");
+  return QC_OK;
+}
+
+// Validates the rows on the device and (when active >= 0) computes the row
+// and channel ranges of every solution interval of the active term.
+qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
+                  std::vector<HostMaps>& maps, hipStream_t s) {
+  qc_status st = check_vis(ctx, v);
+  if (st != QC_OK) return st;
+  if (!chain || n_term <= 0) return fail(ctx, QC_E_ARG, "empty chain");
+  if (n_term > QC_MAX_TERMS) return fail(ctx, QC_E_UNSUPPORTED, "n_term=%d exceeds %d", n_term, QC_MAX_TERMS);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  maps.assign(n_term, HostMaps());
+  for (int j = 0; j < n_term; ++j) {
+    st = check_term(ctx, v, &chain[j], j, maps[j], s);
+    if (st != QC_OK) return st;
+  }
+  VisArgs va;
+  ChainArgs ca;
+  fill_args(v, chain, n_term, active, va, ca);
+  HIP_TRY(ctx, grow(ctx->d_rowpos, ctx->rowpos_cap, (size_t)v->n_time + 1));
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, ctx->d_err);
+  if (v->n_row > 0) {
+    const long long nb = (v->n_row + 255) / 256;
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(256), 0, s, va, ctx->d_rowpos, ctx->d_err);
+  } else {
+    hipLaunchKernelGGL(k_rowpos_empty, dim3((v->n_time + 256) / 256), dim3(256), 0, s, ctx->d_rowpos, v->n_time);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  if (active >= 0) {
+    const qc_term& ta = chain[active];
+    const HostMaps& hm = maps[active];
+    std::vector<int> tt(2 * (size_t)ta.n_gt, 0), clo(ta.n_gf, 0), chi(ta.n_gf, 0);
+    for (int g = 0; g < ta.n_gt; ++g) {
+      auto lo = std::lower_bound(hm.t_map.begin(), hm.t_map.end(), g);
+      auto hi = std::upper_bound(hm.t_map.begin(), hm.t_map.end(), g);
+      tt[g] = (int)(lo - hm.t_map.begin());
+      tt[ta.n_gt + g] = (int)(hi - hm.t_map.begin());
+    }
+    for (int g = 0; g < ta.n_gf; ++g) {
+      auto lo = std::lower_bound(hm.f_map.begin(), hm.f_map.end(), g);
+      auto hi = std::upper_bound(hm.f_map.begin(), hm.f_map.end(), g);
+      clo[g] = (int)(lo - hm.f_map.begin());
+      chi[g] = (int)(hi - hm.f_map.begin());
+    }
+    HIP_TRY(ctx, grow(ctx->d_rowlo, ctx->rowlo_cap, (size_t)ta.n_gt));
+    HIP_TRY(ctx, grow(ctx->d_rowhi, ctx->rowhi_cap, (size_t)ta.n_gt));
+    HIP_TRY(ctx, grow(ctx->d_tt, ctx->tt_cap, 2 * (size_t)ta.n_gt));
+    HIP_TRY(ctx, grow(ctx->d_chlo, ctx->chlo_cap, (size_t)ta.n_gf));
+    HIP_TRY(ctx, grow(ctx->d_chhi, ctx->chhi_cap, (size_t)ta.n_gf));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tt, tt.data(), sizeof(int) * tt.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_chlo, clo.data(), sizeof(int) * clo.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_chhi, chi.data(), sizeof(int) * chi.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ranges, dim3((ta.n_gt + 255) / 256), dim3(256), 0, s, ctx->d_rowpos, ctx->d_tt,
+                       ta.n_gt, ctx->d_rowlo, ctx->d_rowhi);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  return read_err(ctx, s);
+}
+
+int resolve_damping(qc_damping d, const qc_term& t) {
+  if (d == QC_DAMP_AUTO) {
+    if (t.type == QC_TERM_DELAY) return 0;
+    return t.direction_dependent ? 1 : 2;
+  }
+  return (int)d;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public API
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+qc_status qc_ctx_create(int32_t device, qc_ctx** out) {
+  if (!out) return QC_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return QC_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return QC_E_DEVICE;
+  qc_ctx* c = new qc_ctx();
+  c->device = device;
+  if (hipMalloc(reinterpret_cast<void**>(&c->d_err), sizeof(int) * 4) != hipSuccess) {
+    delete c;
+    return QC_E_NOMEM;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    hipFree(c->d_err);
+    delete c;
+    return QC_E_DEVICE;
+  }
+  *out = c;
+  return QC_OK;
+}
+
+qc_status qc_ctx_destroy(qc_ctx* ctx) {
+  if (!ctx) return QC_E_ARG;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  hipFree(ctx->d_err);
+  hipFree(ctx->d_rowpos);
+  hipFree(ctx->d_rowlo);
+  hipFree(ctx->d_rowhi);
+  hipFree(ctx->d_tt);
+  hipFree(ctx->d_chlo);
+  hipFree(ctx->d_chhi);
+  hipEventDestroy(ctx->ev0);
+  hipEventDestroy(ctx->ev1);
+  delete ctx;
+  return QC_OK;
+}
+
+qc_status qc_ctx_sync(qc_ctx* ctx) {
+  if (!ctx) return QC_E_ARG;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  qc_status st = read_err(ctx, ctx->last_stream);
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, ctx->last_stream, ctx->d_err);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  return st;
+}
+
+const char* qc_last_error(const qc_ctx* ctx) { return ctx ? ctx->msg.c_str() : "null context"; }
+
+double qc_last_kernel_ms(qc_ctx* ctx) {
+  if (!ctx || !ctx->timed) return -1.0;
+  if (hipEventSynchronize(ctx->ev1) != hipSuccess) return -1.0;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return -1.0;
+  return (double)ms;
+}
+
+qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t active,
+                            const qc_solve_opts* opts, qc_solve_stats* stats) {
+  if (!ctx) return QC_E_ARG;
+  if (!opts) return fail(ctx, QC_E_ARG, "opts is NULL");
+  if (!chain || n_term <= 0 || active < 0 || active >= n_term)
+    return fail(ctx, QC_E_ARG, "active=%d outside the chain of %d terms", active, n_term);
+  if (opts->prec != QC_PREC_FP64 && opts->prec != QC_PREC_MIXED)
+    return fail(ctx, QC_E_ARG, "bad precision %d", (int)opts->prec);
+  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_AUTO)
+    return fail(ctx, QC_E_ARG, "bad damping %d", (int)opts->damping);
+  if (opts->max_iter < 0) return fail(ctx, QC_E_ARG, "max_iter < 0");
+  if (vis && opts->prec == QC_PREC_MIXED && vis->dtype != QC_C64)
+    return fail(ctx, QC_E_ARG, "MIXED precision needs complex64 data");
+  hipStream_t s = reinterpret_cast<hipStream_t>(opts->stream);
+  ctx->last_stream = s;
+  std::vector<HostMaps> maps;
+  qc_status st = prepare(ctx, vis, chain, n_term, active, maps, s);
+  if (st != QC_OK) return st;
+  for (int j = 0; j < active; ++j) {
+    if (chain[j].type == QC_TERM_COMPLEX2X2)
+      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must be diagonal or delay", j);
+    if (!dmap_constant(maps[j]))
+      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must map all directions to one gain", j);
+  }
+  SolveLaunch L;
+  memset(&L, 0, sizeof L);
+  fill_args(vis, chain, n_term, active, L.vis, L.chain);
+  L.vis_is_c128 = vis->dtype == QC_C128;
+  L.prec_mixed = opts->prec == QC_PREC_MIXED;
+  qc_term& ta = chain[active];
+  L.gains = reinterpret_cast<double2*>(ta.gains);
+  L.params = ta.params;
+  L.gflags = ta.gain_flags;
+  L.row_lo = ctx->d_rowlo;
+  L.row_hi = ctx->d_rowhi;
+  L.chan_lo = ctx->d_chlo;
+  L.chan_hi = ctx->d_chhi;
+  if (stats) {
+    L.iters = stats->iters;
+    L.converged = stats->converged;
+    L.chisq_first = stats->chisq_first;
+    L.chisq_last = stats->chisq_last;
+  }
+  L.tol = opts->tol;
+  L.max_iter = opts->max_iter;
+  L.damping = resolve_damping(opts->damping, ta);
+  L.err = ctx->d_err;
+  L.waves = ctx->waves;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  size_t lds = 0;
+  hipError_t e = launch_solve(L, s, &lds);
+  if (e != hipSuccess) {
+    ctx->timed = false;
+    if (lds > 160 * 1024)
+      return fail(ctx, QC_E_UNSUPPORTED, "per-interval state needs %zu B of LDS (n_ant=%d)", lds, vis->n_ant);
+    return fail(ctx, QC_E_DEVICE, "solve launch: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+  ctx->timed = true;
+  return QC_OK;
+}
+
+static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term, int mode,
+                                const uint8_t* dir_mask, void* out, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!out) return fail(ctx, QC_E_ARG, "out is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  std::vector<HostMaps> maps;
+  qc_status st = prepare(ctx, vis, chain, n_term, -1, maps, s);
+  if (st != QC_OK) return st;
+  if (mode == 1) {
+    for (int j = 0; j < n_term; ++j)
+      if (!dmap_constant(maps[j]))
+        return fail(ctx, QC_E_ARG, "CORRECT needs a direction-independent chain (term %d)", j);
+  }
+  OutputLaunch L;
+  memset(&L, 0, sizeof L);
+  fill_args(vis, chain, n_term, 0, L.vis, L.chain);
+  L.vis_is_c128 = vis->dtype == QC_C128;
+  L.mode = mode;
+  unsigned mask = 0;
+  for (int d = 0; d < vis->n_dir; ++d)
+    if (!dir_mask || dir_mask[d]) mask |= 1u << d;
+  L.dir_mask = mask;
+  L.out = out;
+  HIP_TRY(ctx, launch_outputs(L, s));
+  return QC_OK;
+}
+
+qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
+                         qc_apply_mode mode, const uint8_t* dir_mask, void* out, void* stream) {
+  if (mode != QC_CORRUPT && mode != QC_CORRECT) return fail(ctx, QC_E_ARG, "bad apply mode %d", (int)mode);
+  return outputs_common(ctx, vis, chain, n_term, mode == QC_CORRECT ? 1 : 0, dir_mask, out, stream);
+}
+
+qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
+                      const uint8_t* dir_mask, void* out, void* stream) {
+  return outputs_common(ctx, vis, chain, n_term, 2, dir_mask, out, stream);
+}
+
+}  // extern "C"

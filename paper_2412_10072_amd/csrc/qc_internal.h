@@ -1,0 +1,215 @@
+// Internal definitions shared by the libqc translation units: kernel
+// argument blocks, complex / 2x2 Jones arithmetic, Jones-term evaluation.
+//
+// 2x2 matrices are row-major (XX, XY, YX, YY), the vectorisation of the
+// paper's eq. gvec / eq. jones.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qc.h"
+
+namespace qc {
+
+// ---------------------------------------------------------------------------
+// argument blocks (passed to kernels by value)
+// ---------------------------------------------------------------------------
+
+enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2 };
+
+struct TermArgs {
+  int kind, n_gt, n_gf, n_gdir;
+  const int* t_map;
+  const int* f_map;
+  const int* d_map;
+  const double2* gains;   // [n_gt][n_gf][n_ant][n_gdir][4]
+  const double* params;   // [n_gt][n_gf][n_ant][n_gdir][2]
+};
+
+struct VisArgs {
+  const void* data;
+  const void* model;
+  const void* weight;
+  const uint8_t* flag;
+  const int* ant1;
+  const int* ant2;
+  const int* row_time;
+  const double* freq;
+  long long n_row;
+  int n_chan, n_dir, n_ant, n_time, n_wcorr;
+};
+
+struct ChainArgs {
+  int n_term, active;
+  TermArgs t[QC_MAX_TERMS];
+};
+
+// Error word values latched by kernels (first writer wins is not needed:
+// any nonzero value marks the call as failed; the host maps it to a status).
+enum { ERR_NONE = 0, ERR_RANGE = 1, ERR_ORDER = 2, ERR_NONFINITE = 4 };
+
+// ---------------------------------------------------------------------------
+// complex and 2x2 arithmetic
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> cmake(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> czero() { return cx<T>{T(0), T(0)}; }
+template <typename T> __device__ __forceinline__ cx<T> cone() { return cx<T>{T(1), T(0)}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T> __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+// conj(a) * b
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cx<T> mulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+template <typename T>
+struct m22 {
+  cx<T> a, b, c, d;   // [[a, b], [c, d]]
+};
+
+template <typename T> __device__ __forceinline__ m22<T> mident() {
+  return {cone<T>(), czero<T>(), czero<T>(), cone<T>()};
+}
+template <typename T> __device__ __forceinline__ m22<T> mzero() {
+  return {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
+}
+template <typename T> __device__ __forceinline__ m22<T> operator+(const m22<T>& x, const m22<T>& y) {
+  return {x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d};
+}
+template <typename T> __device__ __forceinline__ m22<T> operator-(const m22<T>& x, const m22<T>& y) {
+  return {x.a - y.a, x.b - y.b, x.c - y.c, x.d - y.d};
+}
+// X Y
+template <typename T> __device__ __forceinline__ m22<T> mmul(const m22<T>& x, const m22<T>& y) {
+  return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+}
+// X Y^H
+template <typename T> __device__ __forceinline__ m22<T> mmul_h(const m22<T>& x, const m22<T>& y) {
+  return {mulc(x.a, y.a) + mulc(x.b, y.b), mulc(x.a, y.c) + mulc(x.b, y.d),
+          mulc(x.c, y.a) + mulc(x.d, y.b), mulc(x.c, y.c) + mulc(x.d, y.d)};
+}
+// X^H
+template <typename T> __device__ __forceinline__ m22<T> herm(const m22<T>& x) {
+  return {conj(x.a), conj(x.c), conj(x.b), conj(x.d)};
+}
+// diag(al0, al1) X  (rows scaled)
+template <typename T> __device__ __forceinline__ m22<T> rowscale(cx<T> a0, cx<T> a1, const m22<T>& x) {
+  return {a0 * x.a, a0 * x.b, a1 * x.c, a1 * x.d};
+}
+
+// ---------------------------------------------------------------------------
+// Jones of one chain term at (time t, channel c, antenna x, direction d)
+// ---------------------------------------------------------------------------
+
+// exp(2 pi i nu tau) with the turn count removed in FP64 so that an FP32
+// sine/cosine sees an argument in [-pi, pi] (nu * tau reaches ~10 turns).
+template <typename T>
+__device__ __forceinline__ cx<T> phasor_turns(double turns) {
+  double fr = turns - rint(turns);
+  if constexpr (sizeof(T) == 4) {
+    float s, c;
+    sincospif(2.0f * (float)fr, &s, &c);
+    return cx<T>{c, s};
+  } else {
+    double s, c;
+    sincospi(2.0 * fr, &s, &c);
+    return cx<T>{c, s};
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int t, int c, int x, int d,
+                                             double nu) {
+  const int gt = tm.t_map[t];
+  const int gf = tm.f_map[c];
+  const int gd = tm.d_map[d];
+  const size_t blk = (((size_t)gt * tm.n_gf + gf) * n_ant + x) * tm.n_gdir + gd;
+  m22<T> J = mzero<T>();
+  if (tm.kind == KIND_DELAY) {
+    const double tx = tm.params[2 * blk + 0];
+    const double ty = tm.params[2 * blk + 1];
+    J.a = phasor_turns<T>(nu * tx);
+    J.d = phasor_turns<T>(nu * ty);
+  } else {
+    const double2* g = tm.gains + 4 * blk;
+    double2 g0 = g[0], g3 = g[3];
+    J.a = cmake<T>((T)g0.x, (T)g0.y);
+    J.d = cmake<T>((T)g3.x, (T)g3.y);
+    if (tm.kind == KIND_C2X2) {
+      double2 g1 = g[1], g2 = g[2];
+      J.b = cmake<T>((T)g1.x, (T)g1.y);
+      J.c = cmake<T>((T)g2.x, (T)g2.y);
+    }
+  }
+  return J;
+}
+
+// Product of terms [j0, j1) for antenna x; identity if empty.
+template <typename T>
+__device__ __forceinline__ m22<T> chain_range(const ChainArgs& ch, int n_ant, int j0, int j1, int t, int c,
+                                              int x, int d, double nu) {
+  m22<T> C = mident<T>();
+  for (int j = j0; j < j1; ++j) C = mmul(C, term_jones<T>(ch.t[j], n_ant, t, c, x, d, nu));
+  return C;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers implemented in the kernel translation units
+// ---------------------------------------------------------------------------
+
+struct SolveLaunch {
+  VisArgs vis;
+  ChainArgs chain;
+  int vis_is_c128;            // storage precision of data/model/weight
+  int prec_mixed;             // compute precision
+  // active term, in/out
+  double2* gains;
+  double* params;
+  int8_t* gflags;
+  // interval geometry of the active term (device)
+  const long long* row_lo;    // [n_gt]
+  const long long* row_hi;    // [n_gt]
+  const int* chan_lo;         // [n_gf]
+  const int* chan_hi;         // [n_gf]
+  // stats (device, may be null)
+  int* iters;
+  uint8_t* converged;
+  double* chisq_first;
+  double* chisq_last;
+  double tol;
+  int max_iter;
+  int damping;                // resolved: 0 full, 1 half, 2 alternate
+  int* err;
+  int waves;                  // waves per workgroup
+};
+
+hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_bytes_out);
+
+struct OutputLaunch {
+  VisArgs vis;
+  ChainArgs chain;
+  int vis_is_c128;
+  int mode;                   // 0 corrupt, 1 correct, 2 residual
+  unsigned dir_mask;          // bit d set = direction d included
+  void* out;
+};
+
+hipError_t launch_outputs(const OutputLaunch& L, hipStream_t stream);
+
+}  // namespace qc

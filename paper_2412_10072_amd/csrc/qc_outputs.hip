@@ -1,0 +1,112 @@
+// Visibility outputs after a solve (paper Section 4.4): corrupted model,
+// residual and corrected data, one streaming pass over every (row, channel).
+//
+//   CORRUPT : out = sum_{d in mask} C_{p,d} M_d C_{q,d}^H   (eq. baselinemodel)
+//   RESIDUAL: out = D - CORRUPT                               (eq. baselineresidual)
+//   CORRECT : out = C_p^-1 D C_q^-H  for a direction-independent chain; 0 where
+//             C_p or C_q is singular.
+//
+// Consecutive threads take consecutive channels of a row, so every load and
+// store of a wavefront is contiguous.  Arithmetic is in the data precision.
+
+#include "qc_internal.h"
+
+namespace qc {
+namespace {
+
+template <typename S, typename T>
+__device__ __forceinline__ m22<T> ld(const S* base, size_t elem) {
+  if constexpr (sizeof(S) == 4) {
+    const float4* p = reinterpret_cast<const float4*>(base) + 2 * elem;
+    const float4 u = p[0], v = p[1];
+    return {cmake<T>(u.x, u.y), cmake<T>(u.z, u.w), cmake<T>(v.x, v.y), cmake<T>(v.z, v.w)};
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(base) + 4 * elem;
+    const double2 a = p[0], b = p[1], c = p[2], d = p[3];
+    return {cmake<T>(a.x, a.y), cmake<T>(b.x, b.y), cmake<T>(c.x, c.y), cmake<T>(d.x, d.y)};
+  }
+}
+
+template <typename S, typename T>
+__device__ __forceinline__ void st(S* base, size_t elem, const m22<T>& x) {
+  if constexpr (sizeof(S) == 4) {
+    float4* p = reinterpret_cast<float4*>(base) + 2 * elem;
+    p[0] = make_float4(x.a.re, x.a.im, x.b.re, x.b.im);
+    p[1] = make_float4(x.c.re, x.c.im, x.d.re, x.d.im);
+  } else {
+    double2* p = reinterpret_cast<double2*>(base) + 4 * elem;
+    p[0] = make_double2(x.a.re, x.a.im);
+    p[1] = make_double2(x.b.re, x.b.im);
+    p[2] = make_double2(x.c.re, x.c.im);
+    p[3] = make_double2(x.d.re, x.d.im);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ bool inv2(const m22<T>& x, m22<T>& out) {
+  const cx<T> det = x.a * x.d - x.b * x.c;
+  if (det.re == T(0) && det.im == T(0)) return false;
+  const T n = norm2(det);
+  const cx<T> id = cmake<T>(det.re / n, -det.im / n);
+  out = {x.d * id, cmake<T>(-x.b.re, -x.b.im) * id, cmake<T>(-x.c.re, -x.c.im) * id, x.a * id};
+  return true;
+}
+
+template <typename S, int MODE>
+__global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
+  using T = S;
+  const VisArgs& V = L.vis;
+  const ChainArgs& CH = L.chain;
+  const size_t n = (size_t)V.n_row * V.n_chan;
+  const S* Dp = reinterpret_cast<const S*>(V.data);
+  const S* Mp = reinterpret_cast<const S*>(V.model);
+  S* Op = reinterpret_cast<S*>(L.out);
+  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = s / V.n_chan;
+    const int c = (int)(s - r * V.n_chan);
+    const int p = V.ant1[r], q = V.ant2[r], t = V.row_time[r];
+    if ((unsigned)p >= (unsigned)V.n_ant || (unsigned)q >= (unsigned)V.n_ant) continue;
+    const double nu = V.freq[c];
+    if constexpr (MODE == 1) {
+      const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, 0, nu);
+      const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, 0, nu);
+      m22<T> ip, iq;
+      const bool okp = inv2(Cp, ip), okq = inv2(Cq, iq);
+      m22<T> o = mzero<T>();
+      if (okp && okq) o = mmul_h(mmul(ip, ld<S, T>(Dp, s)), iq);
+      st<S, T>(Op, s, o);
+    } else {
+      m22<T> Vm = mzero<T>();
+      for (int d = 0; d < V.n_dir; ++d) {
+        if (!((L.dir_mask >> d) & 1u)) continue;
+        const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, d, nu);
+        const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, d, nu);
+        Vm = Vm + mmul_h(mmul(Cp, ld<S, T>(Mp, s * V.n_dir + d)), Cq);
+      }
+      if constexpr (MODE == 2) Vm = ld<S, T>(Dp, s) - Vm;
+      st<S, T>(Op, s, Vm);
+    }
+  }
+}
+
+template <typename S>
+hipError_t launch_s(const OutputLaunch& L, hipStream_t stream) {
+  const size_t n = (size_t)L.vis.n_row * L.vis.n_chan;
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  switch (L.mode) {
+    case 0: hipLaunchKernelGGL((k_outputs<S, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, L); break;
+    case 1: hipLaunchKernelGGL((k_outputs<S, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, L); break;
+    default: hipLaunchKernelGGL((k_outputs<S, 2>), dim3((unsigned)blocks), dim3(256), 0, stream, L); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_outputs(const OutputLaunch& L, hipStream_t stream) {
+  return L.vis_is_c128 ? launch_s<double>(L, stream) : launch_s<float>(L, stream);
+}
+
+}  // namespace qc

@@ -1,0 +1,717 @@
+// Fused per-interval AllJones Gauss-Newton solver for gfx950.
+//
+// One workgroup owns one solution interval of the active chain term and runs
+// the paper's Algorithm 1 on it to convergence without returning to the host:
+//
+//   repeat
+//     stream every (row, channel) sample of the interval from HBM once,
+//     form the corrupted model and residual in registers (eq. baselinemodel,
+//     eq. baselineresidual), form the per-antenna JHJ / JHr contributions of
+//     the sample for antenna p and, through the conjugate baseline
+//     v_qp = P conj(v_pq), for antenna q (eq. jhj_entry_simplified,
+//     eq. jhr_entry_simplified; delay terms: eq. jhj_case2, eq. jhwr_case2),
+//     and reduce them into per-wave LDS slots;
+//     combine the wave slots in a fixed order, solve every per-antenna block
+//     in FP64 (eq. update), apply the damped step, test convergence
+//   until converged or max_iter updates.
+//
+// Lanes map to 64 consecutive channels of one row (the innermost, contiguous
+// dimension), so every load of a wavefront is a contiguous 2 KB (complex64
+// 2x2) segment.  Rows are time-major and p-major within a time, so the
+// antenna-p contributions stay in registers for the length of a p-run; the
+// antenna-q contributions are reduced across the wavefront every row with a
+// reduce-scatter (each lane ends holding one summed value) and added to the
+// wave's private LDS slot with a compensated (Kahan) sum.  No atomics are
+// used, so the result is bitwise reproducible.
+//
+// Precision: T = float (MIXED: complex64 products and residuals, FP32 sums
+// with compensation) or double (FP64 everywhere).  The block solve, the
+// update and the convergence test are FP64 in both.
+
+#include <type_traits>
+
+#include "qc_internal.h"
+
+namespace qc {
+namespace {
+
+template <int KIND> struct KindInfo;
+template <> struct KindInfo<KIND_DIAG>  { static constexpr int NV = 6;  };
+template <> struct KindInfo<KIND_C2X2>  { static constexpr int NV = 16; };
+template <> struct KindInfo<KIND_DELAY> { static constexpr int NV = 4;  };
+
+constexpr int pow2ceil(int n) { return n <= 1 ? 1 : 2 * pow2ceil((n + 1) / 2); }
+constexpr double PIVOT_REL = 1e-12;
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// wavefront reduce-scatter: v[0..CNT) summed over the 64 lanes; afterwards
+// lane L holds the total of value `idx` in v[0], identical in every lane of
+// its group of 64/CNT consecutive lanes.
+// ---------------------------------------------------------------------------
+template <int CNT, int OFF, typename A>
+struct ReduceScatter {
+  static __device__ __forceinline__ void run(A* v, int lane, int& idx) {
+    if constexpr (OFF >= 1) {
+      if constexpr (CNT > 1) {
+        constexpr int H = CNT / 2;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          const A send = up ? v[j] : v[j + H];
+          const A keep = up ? v[j + H] : v[j];
+          v[j] = keep + __shfl_xor(send, OFF);
+        }
+        idx = 2 * idx + (up ? 1 : 0);
+        ReduceScatter<H, OFF / 2, A>::run(v, lane, idx);
+      } else {
+        v[0] += __shfl_xor(v[0], OFF);
+        ReduceScatter<1, OFF / 2, A>::run(v, lane, idx);
+      }
+    }
+  }
+};
+
+// Reduce NVP values across the wave and add value k (< NVAL) into
+// slot_s[k] (and its compensation slot_c[k] when KAHAN).  v is clobbered.
+template <int NVP, int NVAL, bool KAHAN, typename A>
+__device__ __forceinline__ void wave_flush(A* v, int lane, A* slot_s, A* slot_c) {
+  int idx = 0;
+  ReduceScatter<NVP, 32, A>::run(v, lane, idx);
+  constexpr int GROUP = 64 / NVP;
+  if ((lane & (GROUP - 1)) == 0 && idx < NVAL) {
+    const A x = v[0];
+    if constexpr (KAHAN) {
+      const A s = slot_s[idx];
+      const A c = slot_c[idx];
+      const A y = x - c;
+      const A t = s + y;
+      slot_c[idx] = (t - s) - y;
+      slot_s[idx] = t;
+    } else {
+      slot_s[idx] += x;
+    }
+  }
+}
+
+template <typename A>
+__device__ __forceinline__ A wave_sum(A x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// per-sample block contributions for one antenna orientation
+//
+// alpha = (a0, a1): diagonal of the chain left of the active term (identity
+// when ALPHA1).  B: the right factor C>_p M C_q^H summed over the directions
+// that share one gain (eq. chain_trick with eq. g_derivative_di / _dd), so
+// that the derivative block is K[(a,b),(i,k)] = alpha_a delta_ai B[k,b].
+// R: residual, w: weights of the orientation (row-major 2x2).
+//   COMPLEX2X2: JHJ splits into two 2x2 Hermitian blocks (one per row i of
+//     the gain): |alpha_i|^2 sum_b w_ib conj(B_kb) B_k'b;
+//     JHr[i,k] = conj(alpha_i) sum_b w_ib R_ib conj(B_kb).
+//   DIAGONAL: h_i = |alpha_i|^2 sum_b w_ib |B_ib|^2, j_i = conj(alpha_i) sum_b w_ib R_ib conj(B_ib).
+//   DELAY (g_i = exp(2 pi i nu tau_i)): h_i = (2 pi nu)^2 |alpha_i g_i|^2 sum_b w_ib |B_ib|^2,
+//     b_i = 2 pi nu Im(conj(g_i) j_i)   (the real parameterised blocks
+//     without their common factor 2, which cancels in the update).
+// ---------------------------------------------------------------------------
+template <int KIND, bool ALPHA1, typename T>
+__device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, const m22<T>& R, T w0, T w1,
+                                        T w2, T w3, cx<T> g0, cx<T> g1, T tpn, T* out) {
+  const cx<T> WR00 = scale(R.a, w0), WR01 = scale(R.b, w1);
+  const cx<T> WR10 = scale(R.c, w2), WR11 = scale(R.d, w3);
+  T s0 = T(1), s1 = T(1);
+  if constexpr (!ALPHA1) {
+    s0 = norm2(a0);
+    s1 = norm2(a1);
+  }
+  if constexpr (KIND == KIND_C2X2) {
+    const T n00 = norm2(B.a), n01 = norm2(B.b), n10 = norm2(B.c), n11 = norm2(B.d);
+    const cx<T> x0 = cmulc(B.a, B.c);   // conj(B_00) B_10
+    const cx<T> x1 = cmulc(B.b, B.d);   // conj(B_01) B_11
+    out[0] = s0 * (w0 * n00 + w1 * n01);
+    out[1] = s0 * (w0 * n10 + w1 * n11);
+    out[2] = s0 * (w0 * x0.re + w1 * x1.re);
+    out[3] = s0 * (w0 * x0.im + w1 * x1.im);
+    out[4] = s1 * (w2 * n00 + w3 * n01);
+    out[5] = s1 * (w2 * n10 + w3 * n11);
+    out[6] = s1 * (w2 * x0.re + w3 * x1.re);
+    out[7] = s1 * (w2 * x0.im + w3 * x1.im);
+    cx<T> J00 = mulc(WR00, B.a) + mulc(WR01, B.b);
+    cx<T> J01 = mulc(WR00, B.c) + mulc(WR01, B.d);
+    cx<T> J10 = mulc(WR10, B.a) + mulc(WR11, B.b);
+    cx<T> J11 = mulc(WR10, B.c) + mulc(WR11, B.d);
+    if constexpr (!ALPHA1) {
+      J00 = cmulc(a0, J00);
+      J01 = cmulc(a0, J01);
+      J10 = cmulc(a1, J10);
+      J11 = cmulc(a1, J11);
+    }
+    out[8] = J00.re;  out[9] = J00.im;
+    out[10] = J01.re; out[11] = J01.im;
+    out[12] = J10.re; out[13] = J10.im;
+    out[14] = J11.re; out[15] = J11.im;
+  } else {
+    T h0 = s0 * (w0 * norm2(B.a) + w1 * norm2(B.b));
+    T h1 = s1 * (w2 * norm2(B.c) + w3 * norm2(B.d));
+    cx<T> j0 = mulc(WR00, B.a) + mulc(WR01, B.b);
+    cx<T> j1 = mulc(WR10, B.c) + mulc(WR11, B.d);
+    if constexpr (!ALPHA1) {
+      j0 = cmulc(a0, j0);
+      j1 = cmulc(a1, j1);
+    }
+    if constexpr (KIND == KIND_DIAG) {
+      out[0] = h0;
+      out[1] = h1;
+      out[2] = j0.re; out[3] = j0.im;
+      out[4] = j1.re; out[5] = j1.im;
+    } else {
+      const T t2 = tpn * tpn;
+      out[0] = t2 * norm2(g0) * h0;
+      out[1] = t2 * norm2(g1) * h1;
+      out[2] = tpn * cmulc(g0, j0).im;
+      out[3] = tpn * cmulc(g1, j1).im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// sample loads
+// ---------------------------------------------------------------------------
+template <typename S, typename T>
+__device__ __forceinline__ m22<T> load_m22(const S* base, size_t elem) {
+  if constexpr (sizeof(S) == 4) {
+    const float4* p = reinterpret_cast<const float4*>(base) + 2 * elem;
+    const float4 u = p[0], v = p[1];
+    return {cmake<T>((T)u.x, (T)u.y), cmake<T>((T)u.z, (T)u.w), cmake<T>((T)v.x, (T)v.y),
+            cmake<T>((T)v.z, (T)v.w)};
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(base) + 4 * elem;
+    const double2 a = p[0], b = p[1], c = p[2], d = p[3];
+    return {cmake<T>((T)a.x, (T)a.y), cmake<T>((T)b.x, (T)b.y), cmake<T>((T)c.x, (T)c.y),
+            cmake<T>((T)d.x, (T)d.y)};
+  }
+}
+
+template <typename S, typename T>
+__device__ __forceinline__ void load_w(const S* base, size_t s, int n_wcorr, T& w0, T& w1, T& w2, T& w3) {
+  if (n_wcorr == 4) {
+    if constexpr (sizeof(S) == 4) {
+      const float4 u = reinterpret_cast<const float4*>(base)[s];
+      w0 = (T)u.x; w1 = (T)u.y; w2 = (T)u.z; w3 = (T)u.w;
+    } else {
+      const double2* p = reinterpret_cast<const double2*>(base) + 2 * s;
+      const double2 a = p[0], b = p[1];
+      w0 = (T)a.x; w1 = (T)a.y; w2 = (T)b.x; w3 = (T)b.y;
+    }
+  } else {
+    const T x = (T)base[s];
+    w0 = w1 = w2 = w3 = x;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ m22<T> select_m(bool use, const m22<T>& x) {
+  const T z = T(0);
+  return {cmake<T>(use ? x.a.re : z, use ? x.a.im : z), cmake<T>(use ? x.b.re : z, use ? x.b.im : z),
+          cmake<T>(use ? x.c.re : z, use ? x.c.im : z), cmake<T>(use ? x.d.re : z, use ? x.d.im : z)};
+}
+
+// ---------------------------------------------------------------------------
+// FP64 per-block solve by Cholesky (the pivot rule flags a block singular
+// when a pivot is <= PIVOT_REL times its largest diagonal entry).
+// ---------------------------------------------------------------------------
+struct c64d {
+  double re, im;
+};
+
+__device__ __forceinline__ bool chol2(double h00, double h11, double hre, double him, c64d b0, c64d b1,
+                                      double dmax, c64d& x0, c64d& x1) {
+  // H = [[h00, h01], [conj(h01), h11]], h01 = hre + i him
+  if (!(h00 > PIVOT_REL * dmax)) return false;
+  const double L00 = sqrt(h00);
+  const c64d L10 = {hre / L00, -him / L00};   // conj(h01) / L00
+  const double piv = h11 - (L10.re * L10.re + L10.im * L10.im);
+  if (!(piv > PIVOT_REL * dmax)) return false;
+  const double L11 = sqrt(piv);
+  const c64d y0 = {b0.re / L00, b0.im / L00};
+  // y1 = (b1 - L10 y0) / L11
+  const c64d ly = {L10.re * y0.re - L10.im * y0.im, L10.re * y0.im + L10.im * y0.re};
+  const c64d y1 = {(b1.re - ly.re) / L11, (b1.im - ly.im) / L11};
+  x1 = {y1.re / L11, y1.im / L11};
+  // x0 = (y0 - conj(L10) x1) / L00
+  const c64d cx1 = {L10.re * x1.re + L10.im * x1.im, L10.re * x1.im - L10.im * x1.re};
+  x0 = {(y0.re - cx1.re) / L00, (y0.im - cx1.im) / L00};
+  return true;
+}
+
+__device__ __forceinline__ bool chol_diag(double h, c64d b, double dmax, c64d& x) {
+  if (!(h > PIVOT_REL * dmax)) return false;
+  const double L = sqrt(h);
+  x = {(b.re / L) / L, (b.im / L) / L};
+  return true;
+}
+
+__device__ __forceinline__ double step_length(int damping, int k) {
+  if (damping == 0) return 1.0;
+  if (damping == 1) return 0.5;
+  return (k & 1) ? 1.0 : 0.5;
+}
+
+// ---------------------------------------------------------------------------
+// the fused kernel
+//
+// SINGLE: the chain is the active term alone, one direction, one gain
+//         direction (the plain full-Jones / diagonal solve).
+// NG:     gain directions of the active term held per antenna (1 or 4).
+// ---------------------------------------------------------------------------
+template <int KIND, typename S, typename T, bool SINGLE, int NG>
+__global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
+  using A = T;
+  constexpr bool KAHAN = (sizeof(T) == 4);
+  constexpr int NV = KindInfo<KIND>::NV;
+  constexpr int NVG = NV * NG;
+  constexpr int NVP = pow2ceil(NVG);
+  constexpr bool PACC = (NG == 1);   // keep antenna-p sums in registers over a p-run
+  static_assert(NVP <= 64, "too many values per antenna");
+
+  const VisArgs& V = L.vis;
+  const ChainArgs& CH = L.chain;
+  const TermArgs& TA = CH.t[CH.active];
+  const int n_ant = V.n_ant;
+  const int n_gdir = SINGLE ? 1 : TA.n_gdir;
+  const int n_gf = TA.n_gf;
+  const int interval = blockIdx.x;
+  const int gt = interval / n_gf;
+  const int gf = interval - gt * n_gf;
+  const long long r_lo = L.row_lo[gt], r_hi = L.row_hi[gt];
+  const int c_lo = L.chan_lo[gf], c_hi = L.chan_hi[gf];
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n_slots = n_ant * NG;
+  const int slot_vals = n_slots * NV;
+
+  // ---- LDS carve-up ----
+  extern __shared__ __align__(16) unsigned char lds[];
+  unsigned char* lp = lds;
+  double* tot = reinterpret_cast<double*>(lp);            lp += sizeof(double) * slot_vals;
+  double2* gm = reinterpret_cast<double2*>(lp);           lp += sizeof(double2) * n_slots * 4;
+  double* red = reinterpret_cast<double*>(lp);            lp += sizeof(double) * 2 * 16;
+  double* chiw = reinterpret_cast<double*>(lp);           lp += sizeof(double) * 16;
+  cx<T>* gc = reinterpret_cast<cx<T>*>(lp);               lp += sizeof(cx<T>) * n_slots * 4;
+  int* gfl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * n_slots;
+  int* ctl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * 4;
+  lp = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(lp) + 15) & ~uintptr_t(15));
+  A* acc_s = reinterpret_cast<A*>(lp);                    lp += sizeof(A) * slot_vals * nw;
+  A* acc_c = reinterpret_cast<A*>(lp);
+  A* my_s = acc_s + (size_t)wave * slot_vals;
+  A* my_c = KAHAN ? acc_c + (size_t)wave * slot_vals : nullptr;
+
+  // ---- initial gains of this interval into LDS ----
+  const size_t gbase = ((size_t)gt * n_gf + gf) * n_ant;
+  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+    const int ant = i / n_gdir, gd = i - ant * n_gdir;
+    const int slot = ant * NG + gd;
+    const size_t src = (gbase + ant) * n_gdir + gd;
+    if constexpr (KIND == KIND_DELAY) {
+      gm[slot * 4 + 0] = make_double2(L.params[2 * src + 0], L.params[2 * src + 1]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double2 g = L.gains[4 * src + k];
+        gm[slot * 4 + k] = g;
+        gc[slot * 4 + k] = cmake<T>((T)g.x, (T)g.y);
+      }
+    }
+    gfl[slot] = 0;
+  }
+  double nu_max = 0.0;
+  if constexpr (KIND == KIND_DELAY) {
+    if (threadIdx.x == 0) {
+      double m = 0.0;
+      for (int c = c_lo; c < c_hi; ++c) m = fmax(m, V.freq[c]);
+      red[0] = m;
+    }
+  }
+  __syncthreads();
+  if constexpr (KIND == KIND_DELAY) nu_max = red[0];
+
+  // ---- rows of this wave ----
+  const long long n_rows = r_hi - r_lo;
+  const long long rw_lo = r_lo + (n_rows * wave) / nw;
+  const long long rw_hi = r_lo + (n_rows * (wave + 1)) / nw;
+  const S* Dp = reinterpret_cast<const S*>(V.data);
+  const S* Mp = reinterpret_cast<const S*>(V.model);
+  const S* Wp = reinterpret_cast<const S*>(V.weight);
+  const int n_chan = V.n_chan;
+  const int n_dir = SINGLE ? 1 : V.n_dir;
+  const int n_term = CH.n_term;
+  const int act = CH.active;
+
+  double chisq_first = 0.0, chisq_last = 0.0;
+  int iters = 0, converged = 0;
+
+  for (int it = 0;; ++it) {
+    for (int i = lane; i < slot_vals; i += 64) {
+      my_s[i] = A(0);
+      if constexpr (KAHAN) my_c[i] = A(0);
+    }
+    A chi = A(0);
+    A pacc[NVP];
+#pragma unroll
+    for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
+    int p_cur = -1;
+
+    for (long long r = rw_lo; r < rw_hi; ++r) {
+      const int p = V.ant1[r];
+      const int q = V.ant2[r];
+      const int t = V.row_time[r];
+      if (p == q || (unsigned)p >= (unsigned)n_ant || (unsigned)q >= (unsigned)n_ant) continue;
+      if constexpr (PACC) {
+        if (p != p_cur) {
+          if (p_cur >= 0) {
+            wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s + (size_t)p_cur * NG * NV,
+                                        KAHAN ? my_c + (size_t)p_cur * NG * NV : nullptr);
+#pragma unroll
+            for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
+          }
+          p_cur = p;
+        }
+      }
+      A qacc[NVP];
+      A prow[NVP];
+#pragma unroll
+      for (int k = 0; k < NVP; ++k) { qacc[k] = A(0); prow[k] = A(0); }
+
+      // left factor of the active term (diagonal, direction independent)
+      cx<T> ap0 = cone<T>(), ap1 = cone<T>(), aq0 = cone<T>(), aq1 = cone<T>();
+
+      for (int c0 = c_lo; c0 < c_hi; c0 += 64) {
+        const int c = c0 + lane;
+        const bool inb = c < c_hi;
+        const int cc = inb ? c : c_lo;
+        const size_t s = (size_t)r * n_chan + cc;
+        const bool use = inb && (V.flag[s] == 0);
+        const double nu = V.freq[cc];
+        const T tpn = (T)(TWO_PI * nu);
+        T w0, w1, w2, w3;
+        load_w<S, T>(Wp, s, V.n_wcorr, w0, w1, w2, w3);
+        w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
+        const m22<T> D = select_m(use, load_m22<S, T>(Dp, s));
+
+        T vp[NVG], vq[NVG];
+        if constexpr (SINGLE) {
+          // chain = the active term alone: C_p = G_p, C_q = G_q
+          m22<T> Gp, Gq;
+          if constexpr (KIND == KIND_DELAY) {
+            const double2 tp = gm[p * 4], tq = gm[q * 4];
+            Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
+            Gq = {phasor_turns<T>(nu * tq.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tq.y)};
+          } else {
+            Gp = {gc[p * 4 + 0], gc[p * 4 + 1], gc[p * 4 + 2], gc[p * 4 + 3]};
+            Gq = {gc[q * 4 + 0], gc[q * 4 + 1], gc[q * 4 + 2], gc[q * 4 + 3]};
+            if constexpr (KIND == KIND_DIAG) {
+              Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
+            }
+          }
+          const m22<T> M = select_m(use, load_m22<S, T>(Mp, s));
+          const m22<T> B = mmul_h(M, Gq);        // M G_q^H
+          const m22<T> GM = mmul(Gp, M);         // G_p M
+          const m22<T> R = D - mmul(Gp, B);      // D - G_p M G_q^H
+          const m22<T> Bc = herm(GM);            // conjugate baseline: M^H G_p^H
+          const m22<T> Rc = herm(R);
+          contrib<KIND, true, T>(ap0, ap1, B, R, w0, w1, w2, w3, Gp.a, Gp.d, tpn, vp);
+          contrib<KIND, true, T>(aq0, aq1, Bc, Rc, w0, w2, w1, w3, Gq.a, Gq.d, tpn, vq);
+          chi += w0 * norm2(R.a) + w1 * norm2(R.b) + w2 * norm2(R.c) + w3 * norm2(R.d);
+        } else {
+          // left factor: product of the (diagonal, direction-independent)
+          // terms before the active one
+          {
+            m22<T> Ap = chain_range<T>(CH, n_ant, 0, act, t, cc, p, 0, nu);
+            m22<T> Aq = chain_range<T>(CH, n_ant, 0, act, t, cc, q, 0, nu);
+            ap0 = Ap.a; ap1 = Ap.d; aq0 = Aq.a; aq1 = Aq.d;
+          }
+          m22<T> Bs[NG], Bsc[NG];
+          cx<T> gp0[NG], gp1[NG], gq0[NG], gq1[NG];
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            Bs[g] = mzero<T>();
+            Bsc[g] = mzero<T>();
+            gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
+          }
+          m22<T> Vm = mzero<T>();
+          for (int d = 0; d < n_dir; ++d) {
+            const int gd = TA.d_map[d];
+            m22<T> Gp, Gq;
+            if constexpr (KIND == KIND_DELAY) {
+              const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
+              Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
+              Gq = {phasor_turns<T>(nu * tq.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tq.y)};
+            } else {
+              const cx<T>* gpp = gc + (p * NG + gd) * 4;
+              const cx<T>* gqq = gc + (q * NG + gd) * 4;
+              Gp = {gpp[0], gpp[1], gpp[2], gpp[3]};
+              Gq = {gqq[0], gqq[1], gqq[2], gqq[3]};
+              if constexpr (KIND == KIND_DIAG) {
+                Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
+              }
+            }
+            const m22<T> Rp = chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, p, d, nu);
+            const m22<T> Rq = chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, q, d, nu);
+            const m22<T> Cp = rowscale(ap0, ap1, mmul(Gp, Rp));
+            const m22<T> Cq = rowscale(aq0, aq1, mmul(Gq, Rq));
+            const m22<T> M = select_m(use, load_m22<S, T>(Mp, s * n_dir + d));
+            const m22<T> B = mmul_h(mmul(Rp, M), Cq);             // C>_p M C_q^H
+            const m22<T> Bc = mmul_h(mmul(Rq, herm(M)), Cp);      // C>_q M^H C_p^H
+            Vm = Vm + rowscale(ap0, ap1, mmul(Gp, B));
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+              const bool hit = (g == gd);
+              Bs[g] = hit ? Bs[g] + B : Bs[g];
+              Bsc[g] = hit ? Bsc[g] + Bc : Bsc[g];
+              gp0[g] = hit ? Gp.a : gp0[g];
+              gp1[g] = hit ? Gp.d : gp1[g];
+              gq0[g] = hit ? Gq.a : gq0[g];
+              gq1[g] = hit ? Gq.d : gq1[g];
+            }
+          }
+          const m22<T> R = D - Vm;
+          const m22<T> Rc = herm(R);
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            contrib<KIND, false, T>(ap0, ap1, Bs[g], R, w0, w1, w2, w3, gp0[g], gp1[g], tpn, vp + g * NV);
+            contrib<KIND, false, T>(aq0, aq1, Bsc[g], Rc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, vq + g * NV);
+          }
+          chi += w0 * norm2(R.a) + w1 * norm2(R.b) + w2 * norm2(R.c) + w3 * norm2(R.d);
+        }
+#pragma unroll
+        for (int k = 0; k < NVG; ++k) {
+          if constexpr (PACC) pacc[k] += vp[k];
+          else prow[k] += vp[k];
+          qacc[k] += vq[k];
+        }
+      }
+      wave_flush<NVP, NVG, KAHAN>(qacc, lane, my_s + (size_t)q * NG * NV,
+                                  KAHAN ? my_c + (size_t)q * NG * NV : nullptr);
+      if constexpr (!PACC) {
+        wave_flush<NVP, NVG, KAHAN>(prow, lane, my_s + (size_t)p * NG * NV,
+                                    KAHAN ? my_c + (size_t)p * NG * NV : nullptr);
+      }
+    }
+    if constexpr (PACC) {
+      if (p_cur >= 0)
+        wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s + (size_t)p_cur * NG * NV,
+                                    KAHAN ? my_c + (size_t)p_cur * NG * NV : nullptr);
+    }
+    {
+      const double cw = wave_sum<double>((double)chi);
+      if (lane == 0) chiw[wave] = cw;
+    }
+    __syncthreads();
+
+    // ---- combine the wave slots in a fixed order (FP64) ----
+    for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) {
+      double sum = 0.0;
+      for (int w = 0; w < nw; ++w) {
+        sum += (double)acc_s[(size_t)w * slot_vals + i];
+        if constexpr (KAHAN) sum -= (double)acc_c[(size_t)w * slot_vals + i];
+      }
+      tot[i] = sum;
+    }
+    double chi_now = 0.0;
+    for (int w = 0; w < nw; ++w) chi_now += chiw[w];
+    if (it == 0) chisq_first = chi_now;
+    chisq_last = chi_now;
+    __syncthreads();
+    if (it >= L.max_iter) break;
+
+    // ---- per-block FP64 solve and damped update ----
+    const int k_upd = it + 1;
+    const double alpha = step_length(L.damping, k_upd);
+    double num = 0.0, den = 0.0;
+    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+      const int ant = i / n_gdir, gd = i - ant * n_gdir;
+      const int slot = ant * NG + gd;
+      const double* h = tot + (size_t)slot * NV;
+      bool finite = true;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) finite = finite && isfinite(h[k]);
+      bool ok = finite;
+      if (!finite) atomicOr(L.err, ERR_NONFINITE);
+      if constexpr (KIND == KIND_C2X2) {
+        const double dmax = fmax(fmax(h[0], h[1]), fmax(h[4], h[5]));
+        c64d x00 = {0, 0}, x01 = {0, 0}, x10 = {0, 0}, x11 = {0, 0};
+        ok = ok && isfinite(dmax) && dmax > 0.0;
+        ok = ok && chol2(h[0], h[1], h[2], h[3], {h[8], h[9]}, {h[10], h[11]}, dmax, x00, x01);
+        ok = ok && chol2(h[4], h[5], h[6], h[7], {h[12], h[13]}, {h[14], h[15]}, dmax, x10, x11);
+        if (ok) {
+          const c64d dx[4] = {x00, x01, x10, x11};
+          double2* g = gm + slot * 4;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
+            const double2 xn = make_double2(g[k].x + sr, g[k].y + si);
+            g[k] = xn;
+            gc[slot * 4 + k] = cmake<T>((T)xn.x, (T)xn.y);
+            num += sr * sr + si * si;
+            den += xn.x * xn.x + xn.y * xn.y;
+          }
+        }
+      } else if constexpr (KIND == KIND_DIAG) {
+        const double dmax = fmax(h[0], h[1]);
+        c64d x0 = {0, 0}, x1 = {0, 0};
+        ok = ok && isfinite(dmax) && dmax > 0.0;
+        ok = ok && chol_diag(h[0], {h[2], h[3]}, dmax, x0);
+        ok = ok && chol_diag(h[1], {h[4], h[5]}, dmax, x1);
+        if (ok) {
+          const c64d dx[2] = {x0, x1};
+          double2* g = gm + slot * 4;
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int e = k ? 3 : 0;
+            const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
+            const double2 xn = make_double2(g[e].x + sr, g[e].y + si);
+            g[e] = xn;
+            gc[slot * 4 + e] = cmake<T>((T)xn.x, (T)xn.y);
+            num += sr * sr + si * si;
+            den += xn.x * xn.x + xn.y * xn.y;
+          }
+        }
+      } else {
+        const double dmax = fmax(h[0], h[1]);
+        ok = ok && isfinite(dmax) && dmax > 0.0;
+        ok = ok && (h[0] > PIVOT_REL * dmax) && (h[1] > PIVOT_REL * dmax);
+        if (ok) {
+          const double l0 = sqrt(h[0]), l1 = sqrt(h[1]);
+          const double d0 = alpha * ((h[2] / l0) / l0);
+          const double d1 = alpha * ((h[3] / l1) / l1);
+          double2* g = gm + slot * 4;
+          g[0] = make_double2(g[0].x + d0, g[0].y + d1);
+          num = fmax(num, TWO_PI * nu_max * fmax(fabs(d0), fabs(d1)));
+        }
+      }
+      gfl[slot] = ok ? 0 : 1;
+    }
+    // ---- convergence over the interval ----
+    {
+      double a = num, b = den;
+      if constexpr (KIND == KIND_DELAY) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+      } else {
+        a = wave_sum<double>(a);
+        b = wave_sum<double>(b);
+      }
+      if (lane == 0) {
+        red[2 * wave + 0] = a;
+        red[2 * wave + 1] = b;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < nw; ++w) {
+        if constexpr (KIND == KIND_DELAY) a = fmax(a, red[2 * w]);
+        else a += red[2 * w];
+        b += red[2 * w + 1];
+      }
+      double ratio;
+      if constexpr (KIND == KIND_DELAY) ratio = a;
+      else ratio = (a == 0.0) ? 0.0 : (b > 0.0 ? sqrt(a / b) : INFINITY);
+      ctl[0] = (ratio <= L.tol) ? 1 : 0;
+    }
+    __syncthreads();
+    iters = k_upd;
+    if (ctl[0]) {
+      converged = 1;
+      break;
+    }
+    if (k_upd >= L.max_iter) break;
+  }
+
+  // ---- write back ----
+  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+    const int ant = i / n_gdir, gd = i - ant * n_gdir;
+    const int slot = ant * NG + gd;
+    const size_t dst = (gbase + ant) * n_gdir + gd;
+    if constexpr (KIND == KIND_DELAY) {
+      L.params[2 * dst + 0] = gm[slot * 4].x;
+      L.params[2 * dst + 1] = gm[slot * 4].y;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) L.gains[4 * dst + k] = gm[slot * 4 + k];
+    }
+    if (L.gflags && L.max_iter > 0) L.gflags[dst] = (int8_t)gfl[slot];
+  }
+  if (threadIdx.x == 0) {
+    if (L.iters) L.iters[interval] = iters;
+    if (L.converged) L.converged[interval] = (uint8_t)converged;
+    if (L.chisq_first) L.chisq_first[interval] = chisq_first;
+    if (L.chisq_last) L.chisq_last[interval] = chisq_last;
+  }
+}
+
+template <int KIND, typename S, typename T, bool SINGLE, int NG>
+hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
+  const int n_slots = L.vis.n_ant * NG;
+  const int nv = KindInfo<KIND>::NV;
+  const int nw = L.waves;
+  size_t lds = sizeof(double) * n_slots * nv + sizeof(double2) * n_slots * 4 + sizeof(double) * 48 +
+               sizeof(cx<T>) * n_slots * 4 + sizeof(int) * (n_slots + 4);
+  lds = (lds + 15) & ~size_t(15);
+  lds += sizeof(T) * (size_t)n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1);
+  if (lds_out) *lds_out = lds;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto kern = k_solve_fused<KIND, S, T, SINGLE, NG>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const TermArgs& ta = L.chain.t[L.chain.active];
+  const unsigned grid = (unsigned)(ta.n_gt * ta.n_gf);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * nw), lds, stream, L);
+  return hipGetLastError();
+}
+
+template <int KIND, typename S, typename T>
+hipError_t launch_kind(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
+  const ChainArgs& ch = L.chain;
+  const TermArgs& ta = ch.t[ch.active];
+  const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
+  if (single) return launch_one<KIND, S, T, true, 1>(L, stream, lds_out);
+  if (ta.n_gdir == 1) return launch_one<KIND, S, T, false, 1>(L, stream, lds_out);
+  return launch_one<KIND, S, T, false, 4>(L, stream, lds_out);
+}
+
+}  // namespace
+
+hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
+  const int kind = L.chain.t[L.chain.active].kind;
+  if (L.prec_mixed) {
+    if (L.vis_is_c128) return hipErrorInvalidValue;
+    switch (kind) {
+      case KIND_DIAG: return launch_kind<KIND_DIAG, float, float>(L, stream, lds_out);
+      case KIND_C2X2: return launch_kind<KIND_C2X2, float, float>(L, stream, lds_out);
+      default: return launch_kind<KIND_DELAY, float, float>(L, stream, lds_out);
+    }
+  }
+  if (L.vis_is_c128) {
+    switch (kind) {
+      case KIND_DIAG: return launch_kind<KIND_DIAG, double, double>(L, stream, lds_out);
+      case KIND_C2X2: return launch_kind<KIND_C2X2, double, double>(L, stream, lds_out);
+      default: return launch_kind<KIND_DELAY, double, double>(L, stream, lds_out);
+    }
+  }
+  switch (kind) {
+    case KIND_DIAG: return launch_kind<KIND_DIAG, float, double>(L, stream, lds_out);
+    case KIND_C2X2: return launch_kind<KIND_C2X2, float, double>(L, stream, lds_out);
+    default: return launch_kind<KIND_DELAY, float, double>(L, stream, lds_out);
+  }
+}
+
+}  // namespace qc

@@ -1,0 +1,306 @@
+"""ctypes binding of libqc (include/qc.h): argument marshalling only.
+
+Every step of the solve runs in the HIP kernels of libqc.so; this module
+only checks tensor dtypes/devices/contiguity, fills the C structs with
+device pointers and calls the library.  It raises if the library is not
+built: there is no other code path.
+
+Arrays are torch tensors on the HIP device (the layouts are those of
+include/qc.h).  Visibility sets and chain terms are the plain containers
+of ``synth.problem`` (Vis, Term) holding such tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqc.so")
+
+QC_OK, QC_E_ARG, QC_E_RANGE, QC_E_NONFINITE, QC_E_DEVICE, QC_E_NOMEM, QC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "QC_OK", -1: "QC_E_ARG", -2: "QC_E_RANGE", -3: "QC_E_NONFINITE", -4: "QC_E_DEVICE",
+                -5: "QC_E_NOMEM", -6: "QC_E_UNSUPPORTED"}
+TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
+
+EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms",
+           "qc_solve_interval", "qc_apply_gains", "qc_residual")
+
+
+class QcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class QcVis(C.Structure):
+    _fields_ = [("n_row", C.c_int64), ("n_chan", C.c_int32), ("n_dir", C.c_int32), ("n_ant", C.c_int32),
+                ("n_time", C.c_int32), ("n_wcorr", C.c_int32), ("dtype", C.c_int32),
+                ("data", C.c_void_p), ("model", C.c_void_p), ("weight", C.c_void_p), ("flag", C.c_void_p),
+                ("ant1", C.c_void_p), ("ant2", C.c_void_p), ("row_time", C.c_void_p), ("chan_freq", C.c_void_p)]
+
+
+class QcTerm(C.Structure):
+    _fields_ = [("type", C.c_int32), ("direction_dependent", C.c_int32), ("n_gt", C.c_int32),
+                ("n_gf", C.c_int32), ("n_gdir", C.c_int32),
+                ("t_map", C.c_void_p), ("f_map", C.c_void_p), ("d_map", C.c_void_p),
+                ("gains", C.c_void_p), ("params", C.c_void_p), ("gain_flags", C.c_void_p)]
+
+
+class QcSolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32), ("damping", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class QcSolveStats(C.Structure):
+    _fields_ = [("iters", C.c_void_p), ("converged", C.c_void_p), ("chisq_first", C.c_void_p),
+                ("chisq_last", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libqc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libqc.so not built at {path}; run python -m paper_2412_10072_amd.build")
+    lib = C.CDLL(path)
+    lib.qc_ctx_create.argtypes = [C.c_int32, C.POINTER(C.c_void_p)]
+    lib.qc_ctx_destroy.argtypes = [C.c_void_p]
+    lib.qc_ctx_sync.argtypes = [C.c_void_p]
+    lib.qc_last_error.argtypes = [C.c_void_p]
+    lib.qc_last_error.restype = C.c_char_p
+    lib.qc_last_kernel_ms.argtypes = [C.c_void_p]
+    lib.qc_last_kernel_ms.restype = C.c_double
+    lib.qc_solve_interval.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
+                                      C.POINTER(QcSolveOpts), C.POINTER(QcSolveStats)]
+    lib.qc_apply_gains.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.qc_residual.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32,
+                                C.c_void_p, C.c_void_p, C.c_void_p]
+    for name in EXPORTS:
+        if name not in ("qc_last_error", "qc_last_kernel_ms"):
+            getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, name="array") -> Optional[int]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, got {type(t)}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the HIP device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def to_device(x, device, dtype=None) -> torch.Tensor:
+    t = torch.as_tensor(np.ascontiguousarray(x) if isinstance(x, np.ndarray) else x)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device).contiguous()
+
+
+def device_vis(vis, device="cuda"):
+    """Copy of a visibility container with every array on `device`."""
+    from synth.problem import Vis
+    return Vis(data=to_device(vis.data, device), model=to_device(vis.model, device),
+               weight=to_device(vis.weight, device), flag=to_device(vis.flag, device, torch.uint8),
+               ant1=to_device(vis.ant1, device, torch.int32), ant2=to_device(vis.ant2, device, torch.int32),
+               row_time=to_device(vis.row_time, device, torch.int32),
+               chan_freq=to_device(vis.chan_freq, device, torch.float64), n_ant=int(vis.n_ant),
+               n_time=int(vis.n_time))
+
+
+def device_term(term, device="cuda"):
+    """Copy of a chain term with every array on `device` (gains complex128)."""
+    t = term.copy()
+    t.t_map = to_device(term.t_map, device, torch.int32)
+    t.f_map = to_device(term.f_map, device, torch.int32)
+    t.d_map = to_device(term.d_map, device, torch.int32)
+    t.gains = to_device(term.gains, device, torch.complex128) if term.gains is not None else None
+    t.params = to_device(term.params, device, torch.float64) if term.params is not None else None
+    if term.gain_flags is not None:
+        gf = term.gain_flags
+    else:
+        g = term.gains if term.gains is not None else term.params
+        gf = np.zeros(tuple(g.shape[:4]), np.int8)
+    t.gain_flags = to_device(gf, device, torch.int8)
+    return t
+
+
+def host_term(term):
+    """Copy of a chain term with every array as numpy (for comparisons)."""
+    t = term.copy()
+    for name in ("t_map", "f_map", "d_map", "gains", "params", "gain_flags"):
+        v = getattr(term, name)
+        if isinstance(v, torch.Tensor):
+            setattr(t, name, v.detach().cpu().numpy())
+    return t
+
+
+def _c_vis(vis) -> QcVis:
+    data = vis.data
+    if data.dtype == torch.complex64:
+        dtype, wdt = 0, torch.float32
+    elif data.dtype == torch.complex128:
+        dtype, wdt = 1, torch.float64
+    else:
+        raise TypeError(f"data must be complex64 or complex128, got {data.dtype}")
+    n_row, n_chan = int(data.shape[0]), int(data.shape[1])
+    if tuple(data.shape) != (n_row, n_chan, 4):
+        raise ValueError(f"data must be [n_row][n_chan][4], got {tuple(data.shape)}")
+    if vis.model.dim() != 4 or tuple(vis.model.shape[:2]) != (n_row, n_chan) or vis.model.shape[3] != 4:
+        raise ValueError(f"model must be [n_row][n_chan][n_dir][4], got {tuple(vis.model.shape)}")
+    if vis.weight.dim() != 3 or tuple(vis.weight.shape[:2]) != (n_row, n_chan):
+        raise ValueError(f"weight must be [n_row][n_chan][n_wcorr], got {tuple(vis.weight.shape)}")
+    if tuple(vis.flag.shape) != (n_row, n_chan):
+        raise ValueError("flag must be [n_row][n_chan]")
+    for name in ("ant1", "ant2", "row_time"):
+        if tuple(getattr(vis, name).shape) != (n_row,):
+            raise ValueError(f"{name} must be [n_row]")
+    if tuple(vis.chan_freq.shape) != (n_chan,):
+        raise ValueError("chan_freq must be [n_chan]")
+    return QcVis(n_row=n_row, n_chan=n_chan, n_dir=int(vis.model.shape[2]), n_ant=int(vis.n_ant),
+                 n_time=int(vis.n_time), n_wcorr=int(vis.weight.shape[2]), dtype=dtype,
+                 data=_ptr(data, name="data"), model=_ptr(vis.model, data.dtype, "model"),
+                 weight=_ptr(vis.weight, wdt, "weight"), flag=_ptr(vis.flag, torch.uint8, "flag"),
+                 ant1=_ptr(vis.ant1, torch.int32, "ant1"), ant2=_ptr(vis.ant2, torch.int32, "ant2"),
+                 row_time=_ptr(vis.row_time, torch.int32, "row_time"),
+                 chan_freq=_ptr(vis.chan_freq, torch.float64, "chan_freq"))
+
+
+def _c_chain(chain: Sequence) -> C.Array:
+    arr = (QcTerm * len(chain))()
+    for j, t in enumerate(chain):
+        if t.kind not in TERM_TYPES:
+            raise ValueError(f"term {j}: unknown kind {t.kind!r}")
+        c = arr[j]
+        c.type = TERM_TYPES[t.kind]
+        c.direction_dependent = 1 if t.direction_dependent else 0
+        c.n_gt, c.n_gf, c.n_gdir = int(t.n_gt), int(t.n_gf), int(t.n_gdir)
+        c.t_map = _ptr(t.t_map, torch.int32, "t_map")
+        c.f_map = _ptr(t.f_map, torch.int32, "f_map")
+        c.d_map = _ptr(t.d_map, torch.int32, "d_map")
+        c.gains = _ptr(t.gains, torch.complex128, "gains") if t.gains is not None else None
+        c.params = _ptr(t.params, torch.float64, "params") if t.params is not None else None
+        c.gain_flags = _ptr(t.gain_flags, torch.int8, "gain_flags") if t.gain_flags is not None else None
+    return arr
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Context:
+    """A libqc context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.qc_ctx_create(device, C.byref(h))
+        if st != QC_OK:
+            raise QcError(st, f"qc_ctx_create({device}) failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.qc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != QC_OK:
+            raise QcError(st, self.lib.qc_last_error(self.h).decode())
+
+    def sync(self):
+        self._check(self.lib.qc_ctx_sync(self.h))
+
+    def last_kernel_ms(self) -> float:
+        return float(self.lib.qc_last_kernel_ms(self.h))
+
+    def solve(self, vis, chain, active: int = 0, tol: float = 1e-6, max_iter: int = 100,
+              prec: str = "mixed", damping: str = "auto", stream=None, stats: Optional[dict] = None):
+        """qc_solve_interval: solve chain[active] in place; returns the per-interval stats tensors."""
+        term = chain[active]
+        dev = vis.data.device
+        shape = (int(term.n_gt), int(term.n_gf))
+        if stats is None:
+            stats = dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
+                         converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
+                         chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
+                         chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev))
+        cv = _c_vis(vis)
+        cc = _c_chain(chain)
+        opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
+                           damping=DAMPINGS[damping], stream=_stream_ptr(stream))
+        cs = QcSolveStats(iters=_ptr(stats["iters"], torch.int32, "iters"),
+                          converged=_ptr(stats["converged"], torch.uint8, "converged"),
+                          chisq_first=_ptr(stats["chisq_first"], torch.float64, "chisq_first"),
+                          chisq_last=_ptr(stats["chisq_last"], torch.float64, "chisq_last"))
+        self._check(self.lib.qc_solve_interval(self.h, C.byref(cv), cc, len(chain), int(active),
+                                               C.byref(opts), C.byref(cs)))
+        return stats
+
+    def _out_like(self, vis, out):
+        if out is None:
+            out = torch.empty_like(vis.data)
+        _ptr(out, vis.data.dtype, "out")
+        if out.shape != vis.data.shape:
+            raise ValueError("out must have the shape of data")
+        return out
+
+    @staticmethod
+    def _mask(vis, dir_mask):
+        if dir_mask is None:
+            return None, None
+        m = np.ascontiguousarray(np.asarray(dir_mask, dtype=np.uint8))
+        if m.shape != (int(vis.model.shape[2]),):
+            raise ValueError("dir_mask must have n_dir entries")
+        return m, m.ctypes.data_as(C.c_void_p)
+
+    def residual(self, vis, chain, dir_mask=None, out=None, stream=None) -> torch.Tensor:
+        """qc_residual: D - sum_{d in mask} C_p M_d C_q^H."""
+        out = self._out_like(vis, out)
+        keep, mp = self._mask(vis, dir_mask)
+        cv = _c_vis(vis)
+        cc = _c_chain(chain)
+        self._check(self.lib.qc_residual(self.h, C.byref(cv), cc, len(chain), mp, C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(_stream_ptr(stream))))
+        return out
+
+    def apply(self, vis, chain, mode: str = "corrupt", dir_mask=None, out=None, stream=None) -> torch.Tensor:
+        """qc_apply_gains: CORRUPT (model through the chain) or CORRECT (C_p^-1 D C_q^-H)."""
+        out = self._out_like(vis, out)
+        keep, mp = self._mask(vis, dir_mask)
+        cv = _c_vis(vis)
+        cc = _c_chain(chain)
+        m = {"corrupt": 0, "correct": 1}[mode]
+        self._check(self.lib.qc_apply_gains(self.h, C.byref(cv), cc, len(chain), m, mp,
+                                            C.c_void_p(out.data_ptr()), C.c_void_p(_stream_ptr(stream))))
+        return out
