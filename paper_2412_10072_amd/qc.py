@@ -247,9 +247,10 @@ class Context:
     def solve(self, vis, chain, active: int = 0, tol: float = 1e-6, max_iter: int = 100,
               prec: str = "mixed", damping: str = "auto", stream=None, stats: Optional[dict] = None):
         """qc_solve_interval: solve chain[active] in place; returns the per-interval stats tensors."""
-        term = chain[active]
         dev = vis.data.device
-        shape = (int(term.n_gt), int(term.n_gf))
+        # an out-of-range `active` is passed on: the library rejects it with QC_E_ARG
+        term = chain[active] if 0 <= active < len(chain) else None
+        shape = (int(term.n_gt), int(term.n_gf)) if term is not None else (1, 1)
         if stats is None:
             stats = dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
                          converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
