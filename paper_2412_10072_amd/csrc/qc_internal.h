@@ -78,6 +78,23 @@ template <typename T> __device__ __forceinline__ cx<T> mulc(cx<T> a, cx<T> b) {
   return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
 }
 
+// Fused complex multiply-accumulate forms (4 FMAs each; the negations
+// become source modifiers):
+//   cfma(a, b, c)   = c + a b          cfma_cj(a, b, c) = c + a conj(b)
+//   cfms(a, b, c)   = c - a b          cfma_jc(a, b, c) = c + conj(a) b
+template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
+  return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+template <typename T> __device__ __forceinline__ cx<T> cfms(cx<T> a, cx<T> b, cx<T> c) {
+  return {fma(-a.re, b.re, fma(a.im, b.im, c.re)), fma(-a.re, b.im, fma(-a.im, b.re, c.im))};
+}
+template <typename T> __device__ __forceinline__ cx<T> cfma_cj(cx<T> a, cx<T> b, cx<T> c) {
+  return {fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.im, b.re, fma(-a.re, b.im, c.im))};
+}
+template <typename T> __device__ __forceinline__ cx<T> cfma_jc(cx<T> a, cx<T> b, cx<T> c) {
+  return {fma(a.re, b.re, fma(a.im, b.im, c.re)), fma(a.re, b.im, fma(-a.im, b.re, c.im))};
+}
+
 template <typename T>
 struct m22 {
   cx<T> a, b, c, d;   // [[a, b], [c, d]]
@@ -97,12 +114,23 @@ template <typename T> __device__ __forceinline__ m22<T> operator-(const m22<T>& 
 }
 // X Y
 template <typename T> __device__ __forceinline__ m22<T> mmul(const m22<T>& x, const m22<T>& y) {
-  return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d, x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+  return {cfma(x.b, y.c, x.a * y.a), cfma(x.b, y.d, x.a * y.b), cfma(x.d, y.c, x.c * y.a),
+          cfma(x.d, y.d, x.c * y.b)};
 }
 // X Y^H
 template <typename T> __device__ __forceinline__ m22<T> mmul_h(const m22<T>& x, const m22<T>& y) {
-  return {mulc(x.a, y.a) + mulc(x.b, y.b), mulc(x.a, y.c) + mulc(x.b, y.d),
-          mulc(x.c, y.a) + mulc(x.d, y.b), mulc(x.c, y.c) + mulc(x.d, y.d)};
+  return {cfma_cj(x.b, y.b, mulc(x.a, y.a)), cfma_cj(x.b, y.d, mulc(x.a, y.c)),
+          cfma_cj(x.d, y.b, mulc(x.c, y.a)), cfma_cj(x.d, y.d, mulc(x.c, y.c))};
+}
+// D - X Y
+template <typename T> __device__ __forceinline__ m22<T> msub_mul(const m22<T>& D, const m22<T>& x, const m22<T>& y) {
+  return {cfms(x.b, y.c, cfms(x.a, y.a, D.a)), cfms(x.b, y.d, cfms(x.a, y.b, D.b)),
+          cfms(x.d, y.c, cfms(x.c, y.a, D.c)), cfms(x.d, y.d, cfms(x.c, y.b, D.d))};
+}
+// A + X Y
+template <typename T> __device__ __forceinline__ m22<T> madd_mul(const m22<T>& A, const m22<T>& x, const m22<T>& y) {
+  return {cfma(x.b, y.c, cfma(x.a, y.a, A.a)), cfma(x.b, y.d, cfma(x.a, y.b, A.b)),
+          cfma(x.d, y.c, cfma(x.c, y.a, A.c)), cfma(x.d, y.d, cfma(x.c, y.b, A.d))};
 }
 // X^H
 template <typename T> __device__ __forceinline__ m22<T> herm(const m22<T>& x) {

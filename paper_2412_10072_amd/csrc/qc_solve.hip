@@ -41,6 +41,15 @@ template <> struct KindInfo<KIND_C2X2>  { static constexpr int NV = 16; };
 template <> struct KindInfo<KIND_DELAY> { static constexpr int NV = 4;  };
 
 constexpr int pow2ceil(int n) { return n <= 1 ? 1 : 2 * pow2ceil((n + 1) / 2); }
+
+// Dynamic LDS of the solve kernel.  Accumulator slots are addressed as
+// offsets from this symbol so that every access compiles to a ds_* op.
+extern __shared__ __align__(16) unsigned char qc_lds[];
+
+template <typename A>
+__device__ __forceinline__ A* lds_at(unsigned byte_off) {
+  return reinterpret_cast<A*>(qc_lds + byte_off);
+}
 constexpr double PIVOT_REL = 1e-12;
 constexpr double TWO_PI = 6.283185307179586476925286766559;
 
@@ -72,24 +81,102 @@ struct ReduceScatter {
   }
 };
 
-// Reduce NVP values across the wave and add value k (< NVAL) into
-// slot_s[k] (and its compensation slot_c[k] when KAHAN).  v is clobbered.
+// FP32 variant of the reduce-scatter built from cross-lane VALU operations
+// (no LDS traffic): the offset-32 and offset-16 steps use gfx950's
+// v_permlane32_swap / v_permlane16_swap, which exchange the upper half of
+// one register with the lower half of another, so a pair (x, y) becomes
+// (x_lo + x_hi | y_lo + y_hi) with one swap and one add; the steps inside a
+// 16-lane row use DPP (row mirror pairs lane i with 15 - i, half-row mirror
+// i with 7 - i, quad permutes i with i ^ 2 and i ^ 1).
+__device__ __forceinline__ unsigned fbits(float x) { return __builtin_bit_cast(unsigned, x); }
+__device__ __forceinline__ float ffrom(unsigned x) { return __builtin_bit_cast(float, x); }
+
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+
+template <int OFF> struct DppCtrl;
+template <> struct DppCtrl<8> { static constexpr int v = DPP_ROW_MIRROR; };
+template <> struct DppCtrl<4> { static constexpr int v = DPP_ROW_HALF_MIRROR; };
+template <> struct DppCtrl<2> { static constexpr int v = DPP_QUAD_XOR2; };
+template <> struct DppCtrl<1> { static constexpr int v = DPP_QUAD_XOR1; };
+
+template <int OFF>
+__device__ __forceinline__ float partner(float x) {
+  return ffrom((unsigned)__builtin_amdgcn_mov_dpp((int)fbits(x), DppCtrl<OFF>::v, 0xF, 0xF, true));
+}
+
+// lanes with bit OFF clear end with x summed over the pair, the others with y
+template <int OFF>
+__device__ __forceinline__ float pair_step(float x, float y, bool up) {
+  if constexpr (OFF == 32) {
+    auto r = __builtin_amdgcn_permlane32_swap(fbits(x), fbits(y), false, false);
+    return ffrom(r[0]) + ffrom(r[1]);
+  } else if constexpr (OFF == 16) {
+    auto r = __builtin_amdgcn_permlane16_swap(fbits(x), fbits(y), false, false);
+    return ffrom(r[0]) + ffrom(r[1]);
+  } else {
+    const float send = up ? x : y;
+    const float keep = up ? y : x;
+    return keep + partner<OFF>(send);
+  }
+}
+
+template <int OFF>
+__device__ __forceinline__ float full_step(float x) {
+  if constexpr (OFF == 32) {
+    auto r = __builtin_amdgcn_permlane32_swap(fbits(x), fbits(x), false, false);
+    return ffrom(r[0]) + ffrom(r[1]);
+  } else if constexpr (OFF == 16) {
+    auto r = __builtin_amdgcn_permlane16_swap(fbits(x), fbits(x), false, false);
+    return ffrom(r[0]) + ffrom(r[1]);
+  } else {
+    return x + partner<OFF>(x);
+  }
+}
+
+template <int CNT, int OFF>
+struct ReduceScatterF32 {
+  static __device__ __forceinline__ void run(float* v, int lane, int& idx) {
+    if constexpr (OFF >= 1) {
+      if constexpr (CNT > 1) {
+        constexpr int H = CNT / 2;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) v[j] = pair_step<OFF>(v[j], v[j + H], up);
+        idx = 2 * idx + (up ? 1 : 0);
+        ReduceScatterF32<H, OFF / 2>::run(v, lane, idx);
+      } else {
+        v[0] = full_step<OFF>(v[0]);
+        ReduceScatterF32<1, OFF / 2>::run(v, lane, idx);
+      }
+    }
+  }
+};
+
+// Reduce NVP values across the wave and add value k (< NVAL) into the LDS
+// slot at byte offset s_off (and its compensation slot at c_off when
+// KAHAN).  v is clobbered.
 template <int NVP, int NVAL, bool KAHAN, typename A>
-__device__ __forceinline__ void wave_flush(A* v, int lane, A* slot_s, A* slot_c) {
+__device__ __forceinline__ void wave_flush(A* v, int lane, unsigned s_off, unsigned c_off) {
   int idx = 0;
-  ReduceScatter<NVP, 32, A>::run(v, lane, idx);
+  if constexpr (sizeof(A) == 4) ReduceScatterF32<NVP, 32>::run(v, lane, idx);
+  else ReduceScatter<NVP, 32, A>::run(v, lane, idx);
   constexpr int GROUP = 64 / NVP;
   if ((lane & (GROUP - 1)) == 0 && idx < NVAL) {
     const A x = v[0];
+    A* ps = lds_at<A>(s_off) + idx;
     if constexpr (KAHAN) {
-      const A s = slot_s[idx];
-      const A c = slot_c[idx];
+      A* pc = lds_at<A>(c_off) + idx;
+      const A s = *ps;
+      const A c = *pc;
       const A y = x - c;
       const A t = s + y;
-      slot_c[idx] = (t - s) - y;
-      slot_s[idx] = t;
+      *pc = (t - s) - y;
+      *ps = t;
     } else {
-      slot_s[idx] += x;
+      *ps += x;
     }
   }
 }
@@ -108,7 +195,7 @@ __device__ __forceinline__ A wave_sum(A x) {
 // when ALPHA1).  B: the right factor C>_p M C_q^H summed over the directions
 // that share one gain (eq. chain_trick with eq. g_derivative_di / _dd), so
 // that the derivative block is K[(a,b),(i,k)] = alpha_a delta_ai B[k,b].
-// R: residual, w: weights of the orientation (row-major 2x2).
+// WR: weights times residual of the orientation, w: its weights (row-major 2x2).
 //   COMPLEX2X2: JHJ splits into two 2x2 Hermitian blocks (one per row i of
 //     the gain): |alpha_i|^2 sum_b w_ib conj(B_kb) B_k'b;
 //     JHr[i,k] = conj(alpha_i) sum_b w_ib R_ib conj(B_kb).
@@ -118,63 +205,83 @@ __device__ __forceinline__ A wave_sum(A x) {
 //     without their common factor 2, which cancels in the update).
 // ---------------------------------------------------------------------------
 template <int KIND, bool ALPHA1, typename T>
-__device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, const m22<T>& R, T w0, T w1,
-                                        T w2, T w3, cx<T> g0, cx<T> g1, T tpn, T* out) {
-  const cx<T> WR00 = scale(R.a, w0), WR01 = scale(R.b, w1);
-  const cx<T> WR10 = scale(R.c, w2), WR11 = scale(R.d, w3);
-  T s0 = T(1), s1 = T(1);
-  if constexpr (!ALPHA1) {
-    s0 = norm2(a0);
-    s1 = norm2(a1);
-  }
+__device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, const m22<T>& WR, T w0, T w1,
+                                        T w2, T w3, cx<T> g0, cx<T> g1, T tpn, T* acc) {
+  // acc += the contribution; WR = W o R (elementwise).  Every sum is an FMA
+  // chain into the accumulator.
   if constexpr (KIND == KIND_C2X2) {
     const T n00 = norm2(B.a), n01 = norm2(B.b), n10 = norm2(B.c), n11 = norm2(B.d);
     const cx<T> x0 = cmulc(B.a, B.c);   // conj(B_00) B_10
     const cx<T> x1 = cmulc(B.b, B.d);   // conj(B_01) B_11
-    out[0] = s0 * (w0 * n00 + w1 * n01);
-    out[1] = s0 * (w0 * n10 + w1 * n11);
-    out[2] = s0 * (w0 * x0.re + w1 * x1.re);
-    out[3] = s0 * (w0 * x0.im + w1 * x1.im);
-    out[4] = s1 * (w2 * n00 + w3 * n01);
-    out[5] = s1 * (w2 * n10 + w3 * n11);
-    out[6] = s1 * (w2 * x0.re + w3 * x1.re);
-    out[7] = s1 * (w2 * x0.im + w3 * x1.im);
-    cx<T> J00 = mulc(WR00, B.a) + mulc(WR01, B.b);
-    cx<T> J01 = mulc(WR00, B.c) + mulc(WR01, B.d);
-    cx<T> J10 = mulc(WR10, B.a) + mulc(WR11, B.b);
-    cx<T> J11 = mulc(WR10, B.c) + mulc(WR11, B.d);
-    if constexpr (!ALPHA1) {
-      J00 = cmulc(a0, J00);
-      J01 = cmulc(a0, J01);
-      J10 = cmulc(a1, J10);
-      J11 = cmulc(a1, J11);
+    if constexpr (ALPHA1) {
+      acc[0] = fma(w0, n00, fma(w1, n01, acc[0]));
+      acc[1] = fma(w0, n10, fma(w1, n11, acc[1]));
+      acc[2] = fma(w0, x0.re, fma(w1, x1.re, acc[2]));
+      acc[3] = fma(w0, x0.im, fma(w1, x1.im, acc[3]));
+      acc[4] = fma(w2, n00, fma(w3, n01, acc[4]));
+      acc[5] = fma(w2, n10, fma(w3, n11, acc[5]));
+      acc[6] = fma(w2, x0.re, fma(w3, x1.re, acc[6]));
+      acc[7] = fma(w2, x0.im, fma(w3, x1.im, acc[7]));
+      cx<T> j;
+      j = cfma_cj(WR.b, B.b, cfma_cj(WR.a, B.a, cmake(acc[8], acc[9])));   acc[8] = j.re;  acc[9] = j.im;
+      j = cfma_cj(WR.b, B.d, cfma_cj(WR.a, B.c, cmake(acc[10], acc[11]))); acc[10] = j.re; acc[11] = j.im;
+      j = cfma_cj(WR.d, B.b, cfma_cj(WR.c, B.a, cmake(acc[12], acc[13]))); acc[12] = j.re; acc[13] = j.im;
+      j = cfma_cj(WR.d, B.d, cfma_cj(WR.c, B.c, cmake(acc[14], acc[15]))); acc[14] = j.re; acc[15] = j.im;
+    } else {
+      const T s0 = norm2(a0), s1 = norm2(a1);
+      acc[0] = fma(s0, fma(w0, n00, w1 * n01), acc[0]);
+      acc[1] = fma(s0, fma(w0, n10, w1 * n11), acc[1]);
+      acc[2] = fma(s0, fma(w0, x0.re, w1 * x1.re), acc[2]);
+      acc[3] = fma(s0, fma(w0, x0.im, w1 * x1.im), acc[3]);
+      acc[4] = fma(s1, fma(w2, n00, w3 * n01), acc[4]);
+      acc[5] = fma(s1, fma(w2, n10, w3 * n11), acc[5]);
+      acc[6] = fma(s1, fma(w2, x0.re, w3 * x1.re), acc[6]);
+      acc[7] = fma(s1, fma(w2, x0.im, w3 * x1.im), acc[7]);
+      cx<T> j;
+      j = cfma_jc(a0, cfma_cj(WR.b, B.b, mulc(WR.a, B.a)), cmake(acc[8], acc[9]));    acc[8] = j.re;  acc[9] = j.im;
+      j = cfma_jc(a0, cfma_cj(WR.b, B.d, mulc(WR.a, B.c)), cmake(acc[10], acc[11]));  acc[10] = j.re; acc[11] = j.im;
+      j = cfma_jc(a1, cfma_cj(WR.d, B.b, mulc(WR.c, B.a)), cmake(acc[12], acc[13]));  acc[12] = j.re; acc[13] = j.im;
+      j = cfma_jc(a1, cfma_cj(WR.d, B.d, mulc(WR.c, B.c)), cmake(acc[14], acc[15]));  acc[14] = j.re; acc[15] = j.im;
     }
-    out[8] = J00.re;  out[9] = J00.im;
-    out[10] = J01.re; out[11] = J01.im;
-    out[12] = J10.re; out[13] = J10.im;
-    out[14] = J11.re; out[15] = J11.im;
   } else {
-    T h0 = s0 * (w0 * norm2(B.a) + w1 * norm2(B.b));
-    T h1 = s1 * (w2 * norm2(B.c) + w3 * norm2(B.d));
-    cx<T> j0 = mulc(WR00, B.a) + mulc(WR01, B.b);
-    cx<T> j1 = mulc(WR10, B.c) + mulc(WR11, B.d);
+    const T h0 = fma(w0, norm2(B.a), w1 * norm2(B.b));
+    const T h1 = fma(w2, norm2(B.c), w3 * norm2(B.d));
+    cx<T> j0 = cfma_cj(WR.b, B.b, mulc(WR.a, B.a));
+    cx<T> j1 = cfma_cj(WR.d, B.d, mulc(WR.c, B.c));
+    T s0 = T(1), s1 = T(1);
     if constexpr (!ALPHA1) {
+      s0 = norm2(a0);
+      s1 = norm2(a1);
       j0 = cmulc(a0, j0);
       j1 = cmulc(a1, j1);
     }
     if constexpr (KIND == KIND_DIAG) {
-      out[0] = h0;
-      out[1] = h1;
-      out[2] = j0.re; out[3] = j0.im;
-      out[4] = j1.re; out[5] = j1.im;
+      acc[0] = fma(s0, h0, acc[0]);
+      acc[1] = fma(s1, h1, acc[1]);
+      acc[2] += j0.re; acc[3] += j0.im;
+      acc[4] += j1.re; acc[5] += j1.im;
     } else {
       const T t2 = tpn * tpn;
-      out[0] = t2 * norm2(g0) * h0;
-      out[1] = t2 * norm2(g1) * h1;
-      out[2] = tpn * cmulc(g0, j0).im;
-      out[3] = tpn * cmulc(g1, j1).im;
+      acc[0] = fma(t2 * norm2(g0), s0 * h0, acc[0]);
+      acc[1] = fma(t2 * norm2(g1), s1 * h1, acc[1]);
+      acc[2] = fma(tpn, cmulc(g0, j0).im, acc[2]);
+      acc[3] = fma(tpn, cmulc(g1, j1).im, acc[3]);
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ m22<T> wmul(const m22<T>& R, T w0, T w1, T w2, T w3) {
+  return {scale(R.a, w0), scale(R.b, w1), scale(R.c, w2), scale(R.d, w3)};
+}
+
+// sum_ab w_ab |R_ab|^2 from WR = W o R
+template <typename T>
+__device__ __forceinline__ T chisq_acc(const m22<T>& WR, const m22<T>& R, T acc) {
+  acc = fma(WR.a.re, R.a.re, fma(WR.a.im, R.a.im, acc));
+  acc = fma(WR.b.re, R.b.re, fma(WR.b.im, R.b.im, acc));
+  acc = fma(WR.c.re, R.c.re, fma(WR.c.im, R.c.im, acc));
+  return fma(WR.d.re, R.d.re, fma(WR.d.im, R.d.im, acc));
 }
 
 // ---------------------------------------------------------------------------
@@ -295,8 +402,7 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   const int slot_vals = n_slots * NV;
 
   // ---- LDS carve-up ----
-  extern __shared__ __align__(16) unsigned char lds[];
-  unsigned char* lp = lds;
+  unsigned char* lp = qc_lds;
   double* tot = reinterpret_cast<double*>(lp);            lp += sizeof(double) * slot_vals;
   double2* gm = reinterpret_cast<double2*>(lp);           lp += sizeof(double2) * n_slots * 4;
   double* red = reinterpret_cast<double*>(lp);            lp += sizeof(double) * 2 * 16;
@@ -305,10 +411,17 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   int* gfl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * n_slots;
   int* ctl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * 4;
   lp = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(lp) + 15) & ~uintptr_t(15));
-  A* acc_s = reinterpret_cast<A*>(lp);                    lp += sizeof(A) * slot_vals * nw;
+  A* acc_s = reinterpret_cast<A*>(lp);
+  const unsigned acc_s_off = (unsigned)(lp - qc_lds);
+  lp += sizeof(A) * slot_vals * nw;
   A* acc_c = reinterpret_cast<A*>(lp);
+  const unsigned acc_c_off = (unsigned)(lp - qc_lds);
   A* my_s = acc_s + (size_t)wave * slot_vals;
-  A* my_c = KAHAN ? acc_c + (size_t)wave * slot_vals : nullptr;
+  A* my_c = acc_c + (size_t)wave * slot_vals;
+  // byte offsets of this wave's slots; antenna a's values start at a * NG * NV
+  const unsigned my_s_off = acc_s_off + (unsigned)(sizeof(A) * wave * slot_vals);
+  const unsigned my_c_off = acc_c_off + (unsigned)(sizeof(A) * wave * slot_vals);
+  constexpr unsigned ANT_BYTES = sizeof(A) * NG * NV;
 
   // ---- initial gains of this interval into LDS ----
   const size_t gbase = ((size_t)gt * n_gf + gf) * n_ant;
@@ -373,8 +486,7 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
       if constexpr (PACC) {
         if (p != p_cur) {
           if (p_cur >= 0) {
-            wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s + (size_t)p_cur * NG * NV,
-                                        KAHAN ? my_c + (size_t)p_cur * NG * NV : nullptr);
+            wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s_off + p_cur * ANT_BYTES, my_c_off + p_cur * ANT_BYTES);
 #pragma unroll
             for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
           }
@@ -402,7 +514,6 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
         w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
         const m22<T> D = select_m(use, load_m22<S, T>(Dp, s));
 
-        T vp[NVG], vq[NVG];
         if constexpr (SINGLE) {
           // chain = the active term alone: C_p = G_p, C_q = G_q
           m22<T> Gp, Gq;
@@ -420,12 +531,12 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
           const m22<T> M = select_m(use, load_m22<S, T>(Mp, s));
           const m22<T> B = mmul_h(M, Gq);        // M G_q^H
           const m22<T> GM = mmul(Gp, M);         // G_p M
-          const m22<T> R = D - mmul(Gp, B);      // D - G_p M G_q^H
-          const m22<T> Bc = herm(GM);            // conjugate baseline: M^H G_p^H
-          const m22<T> Rc = herm(R);
-          contrib<KIND, true, T>(ap0, ap1, B, R, w0, w1, w2, w3, Gp.a, Gp.d, tpn, vp);
-          contrib<KIND, true, T>(aq0, aq1, Bc, Rc, w0, w2, w1, w3, Gq.a, Gq.d, tpn, vq);
-          chi += w0 * norm2(R.a) + w1 * norm2(R.b) + w2 * norm2(R.c) + w3 * norm2(R.d);
+          const m22<T> R = msub_mul(D, Gp, B);   // D - G_p M G_q^H
+          const m22<T> WR = wmul(R, w0, w1, w2, w3);
+          // conjugate baseline: B' = M^H G_p^H, W' o R' = (W o R)^H
+          contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, Gp.a, Gp.d, tpn, PACC ? pacc : prow);
+          contrib<KIND, true, T>(aq0, aq1, herm(GM), herm(WR), w0, w2, w1, w3, Gq.a, Gq.d, tpn, qacc);
+          chi = chisq_acc(WR, R, chi);
         } else {
           // left factor: product of the (diagonal, direction-independent)
           // terms before the active one
@@ -479,32 +590,25 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
             }
           }
           const m22<T> R = D - Vm;
-          const m22<T> Rc = herm(R);
+          const m22<T> WR = wmul(R, w0, w1, w2, w3);
+          const m22<T> WRc = herm(WR);
 #pragma unroll
           for (int g = 0; g < NG; ++g) {
-            contrib<KIND, false, T>(ap0, ap1, Bs[g], R, w0, w1, w2, w3, gp0[g], gp1[g], tpn, vp + g * NV);
-            contrib<KIND, false, T>(aq0, aq1, Bsc[g], Rc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, vq + g * NV);
+            contrib<KIND, false, T>(ap0, ap1, Bs[g], WR, w0, w1, w2, w3, gp0[g], gp1[g], tpn,
+                                    (PACC ? pacc : prow) + g * NV);
+            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV);
           }
-          chi += w0 * norm2(R.a) + w1 * norm2(R.b) + w2 * norm2(R.c) + w3 * norm2(R.d);
-        }
-#pragma unroll
-        for (int k = 0; k < NVG; ++k) {
-          if constexpr (PACC) pacc[k] += vp[k];
-          else prow[k] += vp[k];
-          qacc[k] += vq[k];
+          chi = chisq_acc(WR, R, chi);
         }
       }
-      wave_flush<NVP, NVG, KAHAN>(qacc, lane, my_s + (size_t)q * NG * NV,
-                                  KAHAN ? my_c + (size_t)q * NG * NV : nullptr);
+      wave_flush<NVP, NVG, KAHAN>(qacc, lane, my_s_off + q * ANT_BYTES, my_c_off + q * ANT_BYTES);
       if constexpr (!PACC) {
-        wave_flush<NVP, NVG, KAHAN>(prow, lane, my_s + (size_t)p * NG * NV,
-                                    KAHAN ? my_c + (size_t)p * NG * NV : nullptr);
+        wave_flush<NVP, NVG, KAHAN>(prow, lane, my_s_off + p * ANT_BYTES, my_c_off + p * ANT_BYTES);
       }
     }
     if constexpr (PACC) {
       if (p_cur >= 0)
-        wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s + (size_t)p_cur * NG * NV,
-                                    KAHAN ? my_c + (size_t)p_cur * NG * NV : nullptr);
+        wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s_off + p_cur * ANT_BYTES, my_c_off + p_cur * ANT_BYTES);
     }
     {
       const double cw = wave_sum<double>((double)chi);
