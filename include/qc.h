@@ -168,6 +168,28 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
                             int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats);
 
 /*
+ * Chain / epoch driver (Section 4.3): for n_epoch passes over the chain, solve
+ * every term in array order with qc_solve_interval, the others fixed.
+ * stats: NULL or an array of n_epoch * n_term entries ([epoch][term]).
+ */
+qc_status qc_solve_chain(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t n_epoch,
+                         const qc_solve_opts* opts, qc_solve_stats* stats);
+
+/*
+ * Initial delay estimate (Section 4.3, "Initial estimates"): for every
+ * interval of the DELAY term k_term and every antenna a != ref_ant, per hand
+ * (X: XX, Y: YY), y(nu) = sum over the interval's unflagged samples of the
+ * baselines (ref, a) and (a, ref) of w D conj(M) (oriented so y ~
+ * exp(2 pi i nu (tau_a - tau_ref)), M summed over directions); tau_a is the
+ * first maximum of |sum_nu y(nu) exp(-2 pi i nu tau)|^2 on the grid
+ * tau_k = k / (N dnu), k = -N/2..N/2-1, dnu the mean channel spacing of the
+ * interval, N the smallest power of two >= 8 x its channels.  FP64.
+ * Writes k_term->params for every gain direction; ref_ant gets 0.
+ * QC_E_UNSUPPORTED if an interval has more than ~1900 channels.
+ */
+qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t ref_ant, void* stream);
+
+/*
  * Visibility outputs (Section 4.4).  For every (row, channel), flagged
  * samples and autocorrelations included:
  *   CORRUPT: out = sum_{d in mask} C_{p,d} M_d C_{q,d}^H

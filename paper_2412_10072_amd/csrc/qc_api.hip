@@ -30,6 +30,7 @@ struct qc_ctx {
   size_t chlo_cap = 0;
   int* d_chhi = nullptr;
   size_t chhi_cap = 0;
+  int max_int_chan = 0;       // channels of the widest interval of the last prepared term
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
   int waves = 4;
@@ -253,6 +254,7 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
     const qc_term& ta = chain[active];
     const HostMaps& hm = maps[active];
     std::vector<int> tt(2 * (size_t)ta.n_gt, 0), clo(ta.n_gf, 0), chi(ta.n_gf, 0);
+    ctx->max_int_chan = 0;
     for (int g = 0; g < ta.n_gt; ++g) {
       auto lo = std::lower_bound(hm.t_map.begin(), hm.t_map.end(), g);
       auto hi = std::upper_bound(hm.t_map.begin(), hm.t_map.end(), g);
@@ -264,6 +266,7 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
       auto hi = std::upper_bound(hm.f_map.begin(), hm.f_map.end(), g);
       clo[g] = (int)(lo - hm.f_map.begin());
       chi[g] = (int)(hi - hm.f_map.begin());
+      ctx->max_int_chan = std::max(ctx->max_int_chan, chi[g] - clo[g]);
     }
     HIP_TRY(ctx, grow(ctx->d_rowlo, ctx->rowlo_cap, (size_t)ta.n_gt));
     HIP_TRY(ctx, grow(ctx->d_rowhi, ctx->rowhi_cap, (size_t)ta.n_gt));
@@ -413,6 +416,51 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   }
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
   ctx->timed = true;
+  return QC_OK;
+}
+
+qc_status qc_solve_chain(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t n_epoch,
+                         const qc_solve_opts* opts, qc_solve_stats* stats) {
+  if (!ctx) return QC_E_ARG;
+  if (n_epoch < 0) return fail(ctx, QC_E_ARG, "n_epoch < 0");
+  for (int e = 0; e < n_epoch; ++e) {
+    for (int n = 0; n < n_term; ++n) {
+      qc_solve_stats* st = stats ? &stats[(size_t)e * n_term + n] : nullptr;
+      qc_status s = qc_solve_interval(ctx, vis, chain, n_term, n, opts, st);
+      if (s != QC_OK) return s;
+    }
+  }
+  return QC_OK;
+}
+
+qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t ref_ant, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!k_term) return fail(ctx, QC_E_ARG, "term is NULL");
+  if (k_term->type != QC_TERM_DELAY) return fail(ctx, QC_E_ARG, "qc_delay_init needs a DELAY term");
+  if (!vis) return fail(ctx, QC_E_ARG, "vis is NULL");
+  if (ref_ant < 0 || ref_ant >= vis->n_ant) return fail(ctx, QC_E_ARG, "ref_ant=%d outside [0,%d)", ref_ant, vis->n_ant);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  std::vector<HostMaps> maps;
+  qc_status st = prepare(ctx, vis, k_term, 1, 0, maps, s);
+  if (st != QC_OK) return st;
+  DelayInitLaunch L;
+  memset(&L, 0, sizeof L);
+  ChainArgs ca;
+  fill_args(vis, k_term, 1, 0, L.vis, ca);
+  L.vis_is_c128 = vis->dtype == QC_C128;
+  L.n_gt = k_term->n_gt;
+  L.n_gf = k_term->n_gf;
+  L.n_gdir = k_term->n_gdir;
+  L.ref_ant = ref_ant;
+  L.row_lo = ctx->d_rowlo;
+  L.row_hi = ctx->d_rowhi;
+  L.chan_lo = ctx->d_chlo;
+  L.chan_hi = ctx->d_chhi;
+  L.params = k_term->params;
+  if (delay_init_lds(ctx->max_int_chan) > 64 * 1024)
+    return fail(ctx, QC_E_UNSUPPORTED, "delay interval of %d channels exceeds the LDS budget", ctx->max_int_chan);
+  HIP_TRY(ctx, launch_delay_init(L, ctx->max_int_chan, s));
   return QC_OK;
 }
 

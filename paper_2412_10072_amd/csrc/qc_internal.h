@@ -229,6 +229,20 @@ struct SolveLaunch {
 
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_bytes_out);
 
+struct DelayInitLaunch {
+  VisArgs vis;
+  int vis_is_c128;
+  int n_gt, n_gf, n_gdir, ref_ant;
+  const long long* row_lo;    // [n_gt]
+  const long long* row_hi;
+  const int* chan_lo;         // [n_gf]
+  const int* chan_hi;
+  double* params;             // [n_gt][n_gf][n_ant][n_gdir][2]
+};
+
+size_t delay_init_lds(int max_chan);
+hipError_t launch_delay_init(const DelayInitLaunch& L, int max_chan, hipStream_t stream);
+
 struct OutputLaunch {
   VisArgs vis;
   ChainArgs chain;

@@ -29,7 +29,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
 
 EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms",
-           "qc_solve_interval", "qc_apply_gains", "qc_residual")
+           "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual")
 
 
 class QcError(RuntimeError):
@@ -82,6 +82,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_last_kernel_ms.restype = C.c_double
     lib.qc_solve_interval.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                       C.POINTER(QcSolveOpts), C.POINTER(QcSolveStats)]
+    lib.qc_solve_chain.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
+                                   C.POINTER(QcSolveOpts), C.c_void_p]
+    lib.qc_delay_init.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_void_p]
     lib.qc_apply_gains.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                    C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_residual.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32,
@@ -267,6 +270,39 @@ class Context:
         self._check(self.lib.qc_solve_interval(self.h, C.byref(cv), cc, len(chain), int(active),
                                                C.byref(opts), C.byref(cs)))
         return stats
+
+    def solve_chain(self, vis, chain, n_epoch: int = 1, tol: float = 1e-6, max_iter: int = 100,
+                    prec: str = "mixed", damping: str = "auto", stream=None):
+        """qc_solve_chain: every term solved in turn, n_epoch passes; returns [epoch][term] stats."""
+        dev = vis.data.device
+        stats, cstats = [], (QcSolveStats * max(1, n_epoch * len(chain)))()
+        for e in range(n_epoch):
+            row = []
+            for n, term in enumerate(chain):
+                shape = (int(term.n_gt), int(term.n_gf))
+                st = dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
+                          converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
+                          chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
+                          chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev))
+                c = cstats[e * len(chain) + n]
+                c.iters, c.converged = st["iters"].data_ptr(), st["converged"].data_ptr()
+                c.chisq_first, c.chisq_last = st["chisq_first"].data_ptr(), st["chisq_last"].data_ptr()
+                row.append(st)
+            stats.append(row)
+        cv = _c_vis(vis)
+        cc = _c_chain(chain)
+        opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
+                           damping=DAMPINGS[damping], stream=_stream_ptr(stream))
+        self._check(self.lib.qc_solve_chain(self.h, C.byref(cv), cc, len(chain), int(n_epoch), C.byref(opts),
+                                            C.cast(cstats, C.c_void_p)))
+        return stats
+
+    def delay_init(self, vis, term, ref_ant: int = 0, stream=None):
+        """qc_delay_init: Fourier-peak delay estimate written into term.params."""
+        cv = _c_vis(vis)
+        cc = _c_chain([term])
+        self._check(self.lib.qc_delay_init(self.h, C.byref(cv), cc, int(ref_ant), C.c_void_p(_stream_ptr(stream))))
+        return term
 
     def _out_like(self, vis, out):
         if out is None:

@@ -369,3 +369,89 @@ def to_device_vis(vis: Vis, device) -> Vis:
     return Vis(data=cv(vis.data), model=cv(vis.model), weight=cv(vis.weight), flag=cv(vis.flag),
                ant1=cv(vis.ant1), ant2=cv(vis.ant2), row_time=cv(vis.row_time),
                chan_freq=cv(vis.chan_freq), n_ant=vis.n_ant, n_time=vis.n_time)
+
+
+def clustered_sources(g, n_clusters: int, per_cluster: int, radius_deg: float, member_deg: float, device):
+    """Cluster centres uniform in a disk of radius_deg, members uniform within member_deg of
+    their centre; flux log-uniform in [0.01, 1] Jy.  Returns lists of (l, m, flux) per cluster."""
+    lc, mc, _ = random_sources(g, n_clusters, radius_deg, device)
+    out = []
+    for k in range(n_clusters):
+        dl, dm, flux = random_sources(g, per_cluster, member_deg, device)
+        out.append((lc[k] + dl, mc[k] + dm, flux))
+    return out
+
+
+def config_chain(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int = 512, n_clusters: int = 4,
+                 per_cluster: int = 5, sigma: float = 0.05, flag_frac: float = 0.10, k_tint: int = 60,
+                 de_tint: int = 16, de_fint: int = 128, delay_ns: float = 5.0, time_block: int = 4,
+                 dtype="c64", cfg_id: int = 3, de_amp: float = 0.2, de_phase: float = math.pi) -> Problem:
+    """Jones chain + directions: the MeerKAT-like array, n_time x n_chan over 856-1712 MHz,
+    n_clusters clusters of per_cluster point sources (one model direction per cluster).
+    Truth chain C_{p,d} = K B G dE_d:
+      K  delay, tau ~ U(-delay_ns, delay_ns) ns per antenna and hand, per k_tint times x full band
+         (antenna 0 has tau = 0);
+      B  diagonal bandpass per channel, smooth in frequency, constant in time;
+      G  diagonal gain per time, smooth in time, constant over the band;
+      dE direction-dependent diagonal, amp U(1 - de_amp, 1 + de_amp), phase U(-de_phase, de_phase)
+         (default U(0.8, 1.2), U(-pi, pi)), per de_tint x de_fint.
+    The chain returned for solving has unit gains, zero delays and the same intervals."""
+    g0 = rng(device, 2412, cfg_id, 0)
+    ant1, ant2, row_time = row_layout(n_time, n_ant)
+    nbl = n_ant * (n_ant - 1) // 2
+    n_row = ant1.size
+    freq = torch.linspace(856e6, 1712e6, n_chan, dtype=torch.float64, device=device)
+    enu = antenna_positions(g0, n_ant, 4000.0, device)
+    clusters = clustered_sources(g0, n_clusters, per_cluster, 1.0, 0.1, device)
+    n_dir = n_clusters
+    K = make_term("delay", n_time, n_chan, n_ant, k_tint, n_chan, n_dir=n_dir, name="K")
+    B = make_term("diag", n_time, n_chan, n_ant, n_time, 1, n_dir=n_dir, name="B")
+    G = make_term("diag", n_time, n_chan, n_ant, 1, n_chan, n_dir=n_dir, name="G")
+    dE = make_term("diag", n_time, n_chan, n_ant, de_tint, de_fint, n_dir=n_dir, direction_dependent=True,
+                   name="dE")
+    # truth values
+    tK = K.copy(params=(uniform(g0, K.params.shape, -delay_ns, delay_ns, device) * 1e-9).cpu().numpy())
+    tK.params[:, :, 0] = 0.0
+    xf = _norm_coord(n_chan, device)
+    xt = _norm_coord(n_time, device)
+    cB = smooth_poly(g0, n_ant * 4, 3, device)                          # [ant*4][4][4], use the nu part
+    PB = torch.einsum("pj,jy->py", cB[:, 0, :], torch.stack([xf ** j for j in range(4)], 0))
+    PB = PB.reshape(n_ant, 4, n_chan)
+    bg = np.zeros_like(B.gains)
+    for h, c in enumerate((0, 3)):
+        z = (1.0 + 0.1 * PB[:, 2 * h]) * torch.polar(torch.ones_like(PB[:, 0]), 0.5 * PB[:, 2 * h + 1])
+        bg[0, :, :, 0, c] = z.T.cpu().numpy()
+    tB = B.copy(gains=bg)
+    cG = smooth_poly(g0, n_ant * 4, 3, device)
+    PG = torch.einsum("pj,jy->py", cG[:, 0, :], torch.stack([xt ** j for j in range(4)], 0))
+    PG = PG.reshape(n_ant, 4, n_time)
+    gg = np.zeros_like(G.gains)
+    for h, c in enumerate((0, 3)):
+        z = (1.0 + 0.05 * PG[:, 2 * h]) * torch.polar(torch.ones_like(PG[:, 0]), 0.3 * PG[:, 2 * h + 1])
+        gg[:, 0, :, 0, c] = z.T.cpu().numpy()
+    tG = G.copy(gains=gg)
+    shp = dE.gains.shape[:4] + (2,)
+    amp = uniform(g0, shp, 1.0 - de_amp, 1.0 + de_amp, device).cpu().numpy()
+    ph = uniform(g0, shp, -de_phase, de_phase, device).cpu().numpy()
+    eg = np.zeros_like(dE.gains)
+    eg[..., 0] = amp[..., 0] * np.exp(1j * ph[..., 0])
+    eg[..., 3] = amp[..., 1] * np.exp(1j * ph[..., 1])
+    tdE = dE.copy(gains=eg)
+    truth = [tK, tB, tG, tdE]
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    model = torch.empty(n_row, n_chan, n_dir, 4, dtype=cdt, device=device)
+    for t0 in range(0, n_time, time_block):
+        t1 = min(n_time, t0 + time_block)
+        r0, r1 = t0 * nbl, t1 * nbl
+        uvw = uvw_tracks(enu, ant1[r0:r1], ant2[r0:r1], row_time[r0:r1], n_time)
+        for d, (l, m, flux) in enumerate(clusters):
+            M = point_source_vis(uvw, freq, l, m, flux)
+            model[r0:r1, :, d, 0] = M.to(cdt)
+            model[r0:r1, :, d, 1] = 0
+            model[r0:r1, :, d, 2] = 0
+            model[r0:r1, :, d, 3] = M.to(cdt)
+    g1 = rng(device, 2412, cfg_id, 1)
+    vis = _finish_vis(model, truth, ant1, ant2, row_time, freq, n_ant, n_time, sigma, g1,
+                      flag_frac, dtype, device, block_rows=time_block * nbl)
+    return Problem(vis=vis, chain=[K, B, G, dE], truth=truth,
+                   meta=dict(name="chain", sigma=sigma, n_samples=n_row * n_chan, n_dir=n_dir))

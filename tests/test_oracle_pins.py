@@ -492,3 +492,17 @@ def test_features_equal_gain_product_noise_free():
     # one baseline (0,1): D_XX = g0X M conj(g1X) -> rho_0,XX = g0X conj(g1X)
     assert abs(rho[0, 0] - g[0, 0] * np.conj(g[1, 0])) < 1e-12
     assert abs(rho[1, 3] - g[1, 3] * np.conj(g[0, 3])) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# the chain + directions generator against the oracle's model (two
+# independent implementations of eq. baselinemodel / eq. joneschain)
+# --------------------------------------------------------------------------
+
+def test_chain_generator_agrees_with_oracle_model():
+    from synth.generate import config_chain
+    p = config_chain(n_ant=6, n_time=8, n_chan=16, k_tint=4, de_tint=4, de_fint=8, sigma=0.0,
+                     flag_frac=0.0, dtype="c128")
+    vis = to_numpy_vis(p.vis)
+    R = outputs.residual(vis, p.truth)
+    assert np.abs(R).max() < 1e-12 * np.abs(vis.data).max()
