@@ -32,7 +32,7 @@ def test_delay_init_matches_oracle(qc_lib):
     vis_h = to_numpy_vis(p.vis)
     ref = o_delay.delay_init(vis_h, p.chain, 0, ref_ant=0)
     K = qc.device_term(p.chain[0], DEV)
-    qc_lib.delay_init(p.vis, K, ref_ant=0)
+    qc_lib.delay_init(qc.device_vis(vis_h, DEV), K, ref_ant=0)
     qc_lib.sync()
     got = K.params.cpu().numpy()
     assert np.array_equal(got, ref[0].params)
@@ -61,7 +61,7 @@ def test_chain_two_epochs_fp64(qc_lib):
     start = [t.copy() for t in p.chain]
     ref, _ = o_solver.solve_chain(vis_h, start, n_epoch=2, tol=-1.0, max_iter=3)
     chain_d = [qc.device_term(t, DEV) for t in start]
-    qc_lib.solve_chain(p.vis, chain_d, n_epoch=2, tol=-1.0, max_iter=3, prec="fp64")
+    qc_lib.solve_chain(qc.device_vis(vis_h, DEV), chain_d, n_epoch=2, tol=-1.0, max_iter=3, prec="fp64")
     qc_lib.sync()
     got = [qc.host_term(t) for t in chain_d]
     for g, r in zip(got, ref):
@@ -81,10 +81,11 @@ def test_chain_pipeline_mixed_reduces_residual(qc_lib):
     p = config_chain(n_ant=7, n_time=8, n_chan=32, k_tint=4, de_tint=4, de_fint=16, sigma=0.02,
                      dtype="c64", de_amp=0.1, de_phase=0.3)
     vis_h = to_numpy_vis(p.vis)
+    vis_d = qc.device_vis(vis_h, DEV)
     chain_d = [qc.device_term(t, DEV) for t in p.chain]
-    qc_lib.delay_init(p.vis, chain_d[0], ref_ant=0)
-    qc_lib.solve_chain(p.vis, chain_d, n_epoch=2, tol=1e-6, max_iter=60, prec="mixed")
-    R = qc_lib.residual(p.vis, chain_d)
+    qc_lib.delay_init(vis_d, chain_d[0], ref_ant=0)
+    qc_lib.solve_chain(vis_d, chain_d, n_epoch=2, tol=1e-6, max_iter=60, prec="mixed")
+    R = qc_lib.residual(vis_d, chain_d)
     qc_lib.sync()
     got = [qc.host_term(t) for t in chain_d]
     ref = o_delay.delay_init(vis_h, p.chain, 0, ref_ant=0)
