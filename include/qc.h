@@ -208,6 +208,48 @@ qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, i
 qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                       const uint8_t* dir_mask, void* out, void* stream);
 
+/*
+ * Batched solve of many independent problems of uneven size (row counts,
+ * antennas, channels, term types) in one graph launch.  Solution intervals
+ * are independent (Section 2.3), so the intervals of all problems form one
+ * pool of work: a persistent kernel per size bucket pulls intervals from a
+ * device queue (largest first) and runs the same per-interval solve as
+ * qc_solve_interval.  Each problem is a single-term chain: DIAGONAL or
+ * COMPLEX2X2, one model direction, one gain direction (QC_E_UNSUPPORTED
+ * otherwise).  Every problem must share the data dtype; opts apply to all.
+ * The plan holds the problems' device pointers: they must stay valid until
+ * qc_batch_destroy.  Gains are overwritten in place on every run.
+ */
+typedef struct {
+  qc_vis vis;
+  qc_term term;             /* the solved term (its gains/gain_flags are in/out) */
+  qc_solve_stats stats;     /* per interval of the term; pointers may be NULL */
+} qc_problem;
+
+#define QC_BATCH_BUCKETS 6  /* channel width (<=16, <=32, wider) x size (< 65536 samples, larger) */
+
+typedef struct qc_batch qc_batch;
+/* Validate every problem, build the work items and capture the graph. */
+qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_problem,
+                          const qc_solve_opts* opts, qc_batch** out);
+/* Autotuner: for every bucket, time each (waves per workgroup in {1,2,4,8},
+ * rows per step in {1,2,4}) on the batch itself (best of `reps` runs from
+ * the same initial gains, which are restored afterwards), keep the fastest
+ * and re-capture the graph. */
+qc_status qc_batch_tune(qc_batch* batch, int32_t reps);
+/* Launch the graph, ordered after earlier work on `stream`; later work on
+ * `stream` waits for it. */
+qc_status qc_batch_run(qc_batch* batch, void* stream);
+/* Milliseconds of the last qc_batch_run (waits for it); negative on error. */
+double    qc_batch_last_ms(qc_batch* batch);
+/* Schedule per bucket (arrays of QC_BATCH_BUCKETS; any may be NULL):
+ * work items, waves per workgroup, rows per step, tuned time (ms, < 0 if untuned). */
+qc_status qc_batch_schedule(const qc_batch* batch, int32_t* items, int32_t* waves, int32_t* rows_per_step,
+                            float* tuned_ms, int32_t n);
+qc_status qc_batch_destroy(qc_batch* batch);
+/* create + run + wait + destroy */
+qc_status qc_solve_batch(qc_ctx* ctx, const qc_problem* problems, int32_t n_problem, const qc_solve_opts* opts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,71 +9,11 @@
 #include <string>
 #include <vector>
 
-#include "qc_internal.h"
+#include "qc_host.h"
 
 using namespace qc;
 
-struct qc_ctx {
-  int device = 0;
-  std::string msg;
-  hipStream_t last_stream = nullptr;
-  int* d_err = nullptr;
-  long long* d_rowpos = nullptr;
-  size_t rowpos_cap = 0;
-  long long* d_rowlo = nullptr;
-  size_t rowlo_cap = 0;
-  long long* d_rowhi = nullptr;
-  size_t rowhi_cap = 0;
-  int* d_tt = nullptr;        // [2][n_gt] time range per gain time
-  size_t tt_cap = 0;
-  int* d_chlo = nullptr;
-  size_t chlo_cap = 0;
-  int* d_chhi = nullptr;
-  size_t chhi_cap = 0;
-  int max_int_chan = 0;       // channels of the widest interval of the last prepared term
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool timed = false;
-  int waves = 4;
-};
-
-namespace {
-
-qc_status fail(qc_ctx* ctx, qc_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  if (ctx) ctx->msg = buf;
-  return st;
-}
-
-#define HIP_TRY(ctx, expr)                                                                   \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess)                                                                    \
-      return fail(ctx, e_ == hipErrorOutOfMemory ? QC_E_NOMEM : QC_E_DEVICE, "%s: %s", #expr, \
-                  hipGetErrorString(e_));                                                    \
-  } while (0)
-
-template <typename P>
-hipError_t grow(P*& ptr, size_t& cap, size_t n) {
-  if (n <= cap && ptr) return hipSuccess;
-  if (ptr) {
-    hipError_t e = hipFree(ptr);
-    if (e != hipSuccess) return e;
-    ptr = nullptr;
-  }
-  size_t want = std::max<size_t>(n, 64);
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), want * sizeof(P));
-  if (e != hipSuccess) {
-    cap = 0;
-    ptr = nullptr;
-    return e;
-  }
-  cap = want;
-  return hipSuccess;
-}
+namespace qc {
 
 // ---------------------------------------------------------------------------
 // validation kernels
@@ -120,10 +60,6 @@ __global__ void k_ranges(const long long* rowpos, const int* tt, int n_gt, long 
 // ---------------------------------------------------------------------------
 // host checks
 // ---------------------------------------------------------------------------
-
-struct HostMaps {
-  std::vector<int> t_map, f_map, d_map;
-};
 
 qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
   if (!v) return fail(ctx, QC_E_ARG, "vis is NULL");
@@ -273,6 +209,8 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
     HIP_TRY(ctx, grow(ctx->d_tt, ctx->tt_cap, 2 * (size_t)ta.n_gt));
     HIP_TRY(ctx, grow(ctx->d_chlo, ctx->chlo_cap, (size_t)ta.n_gf));
     HIP_TRY(ctx, grow(ctx->d_chhi, ctx->chhi_cap, (size_t)ta.n_gf));
+    ctx->h_clo = clo;
+    ctx->h_chi = chi;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tt, tt.data(), sizeof(int) * tt.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_chlo, clo.data(), sizeof(int) * clo.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_chhi, chi.data(), sizeof(int) * chi.size(), hipMemcpyHostToDevice, s));
@@ -291,7 +229,7 @@ int resolve_damping(qc_damping d, const qc_term& t) {
   return (int)d;
 }
 
-}  // namespace
+}  // namespace qc
 
 // ---------------------------------------------------------------------------
 // public API
@@ -405,6 +343,8 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   L.damping = resolve_damping(opts->damping, ta);
   L.err = ctx->d_err;
   L.waves = ctx->waves;
+  L.max_int_chan = ctx->max_int_chan;
+  L.rows_per_step = 0;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   size_t lds = 0;
   hipError_t e = launch_solve(L, s, &lds);

@@ -1,0 +1,44 @@
+// Batch descriptors shared by the persistent batch kernel and its host plan.
+#pragma once
+
+#include "qc_internal.h"
+
+namespace qc {
+
+// One problem of a batch: a visibility set and its single solved term.
+struct BatchProb {
+  VisArgs vis;
+  TermArgs term;
+  double2* gains;
+  int8_t* gflags;
+  int* iters;
+  uint8_t* converged;
+  double* chisq_first;
+  double* chisq_last;
+  int damping;
+  int pad;
+};
+
+// One work item: one solution interval of one problem.
+struct BatchItem {
+  long long r_lo, r_hi;
+  int c_lo, c_hi;
+  int prob, gt, gf, pad;
+};
+
+struct BatchArgs {
+  const BatchProb* probs;
+  const BatchItem* items;
+  int item_begin, n_items;     // this bucket's items
+  int* queue;                  // this bucket's counter (zeroed before the launch)
+  double tol;
+  int max_iter;
+  int* err;
+};
+
+void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps);
+size_t batch_lds_bytes(int prec_mixed, int max_ant, int waves);
+hipError_t launch_batch_bucket(const BatchArgs& B, void* kern, int waves, size_t lds, int grid, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+
+}  // namespace qc

@@ -1,0 +1,103 @@
+// Batched solve of many independent calibration problems of uneven size in
+// one persistent launch per size bucket, captured in a hipGraph.
+//
+// Work unit: one solution interval of one problem (intervals are independent,
+// paper Section 2.3, so problems and intervals mix freely).  The host sorts
+// the intervals into buckets by channel width (which fixes the rows-per-step
+// tile) and by size, largest first inside a bucket (longest-processing-time
+// order).  For each bucket a persistent kernel with one workgroup per
+// resident slot pulls interval indices from a device counter and runs the
+// per-interval Gauss-Newton loop (solve_interval) on each until the bucket's
+// queue is empty, so every workgroup reaches the exit.  The bucket kernels
+// run on parallel branches of one graph.
+//
+// Schedule: each bucket has (waves per workgroup, rows per step).  Defaults
+// come from the channel width; qc_batch_tune times every candidate on the
+// batch itself and keeps the fastest per bucket.
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "qc_batch.h"
+#include "qc_interval.h"
+
+namespace qc {
+namespace {
+
+template <typename S, typename T, int RPS>
+__global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
+  __shared__ int s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(B.queue, 1);
+    __syncthreads();
+    const int k = s_next;
+    __syncthreads();
+    if (k >= B.n_items) break;
+    const BatchItem I = B.items[B.item_begin + k];
+    const BatchProb& P = B.probs[I.prob];
+    Job J;
+    J.V = &P.vis;
+    J.CH = nullptr;
+    J.TA = &P.term;
+    J.gains = P.gains;
+    J.params = nullptr;
+    J.gflags = P.gflags;
+    J.iters = P.iters;
+    J.converged = P.converged;
+    J.chisq_first = P.chisq_first;
+    J.chisq_last = P.chisq_last;
+    J.gt = I.gt;
+    J.gf = I.gf;
+    J.n_gf = P.term.n_gf;
+    J.r_lo = I.r_lo;
+    J.r_hi = I.r_hi;
+    J.c_lo = I.c_lo;
+    J.c_hi = I.c_hi;
+    J.tol = B.tol;
+    J.max_iter = B.max_iter;
+    J.damping = P.damping;
+    J.err = B.err;
+    if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, true, 1, RPS>(J);
+    else solve_interval<KIND_C2X2, S, T, true, 1, RPS>(J);
+  }
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+template <typename S, typename T>
+void* batch_kernel(int rps) {
+  if (rps == 4) return reinterpret_cast<void*>(k_solve_batch<S, T, 4>);
+  if (rps == 2) return reinterpret_cast<void*>(k_solve_batch<S, T, 2>);
+  return reinterpret_cast<void*>(k_solve_batch<S, T, 1>);
+}
+
+}  // namespace
+
+void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps) {
+  if (prec_mixed) return batch_kernel<float, float>(rps);
+  if (vis_c128) return batch_kernel<double, double>(rps);
+  return batch_kernel<float, double>(rps);
+}
+
+size_t batch_lds_bytes(int prec_mixed, int max_ant, int waves) {
+  // the full-Jones term needs the most LDS per antenna
+  if (prec_mixed) return interval_lds_bytes<KIND_C2X2, float, 1>(max_ant, waves);
+  return interval_lds_bytes<KIND_C2X2, double, 1>(max_ant, waves);
+}
+
+hipError_t launch_batch_bucket(const BatchArgs& B, void* kern, int waves, size_t lds, int grid, hipStream_t s) {
+  if (B.n_items <= 0) return hipSuccess;
+  void* args[] = {const_cast<BatchArgs*>(&B)};
+  return hipLaunchKernel(kern, dim3(grid), dim3(64 * waves), args, lds, s);
+}
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ints, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace qc

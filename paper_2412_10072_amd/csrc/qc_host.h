@@ -1,0 +1,89 @@
+// Host-side internals of libqc shared by the API translation units: the
+// context, error reporting and the argument / device-side validation helpers.
+#pragma once
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qc_internal.h"
+
+struct qc_ctx {
+  int device = 0;
+  std::string msg;
+  hipStream_t last_stream = nullptr;
+  int* d_err = nullptr;
+  long long* d_rowpos = nullptr;
+  size_t rowpos_cap = 0;
+  long long* d_rowlo = nullptr;
+  size_t rowlo_cap = 0;
+  long long* d_rowhi = nullptr;
+  size_t rowhi_cap = 0;
+  int* d_tt = nullptr;        // [2][n_gt] time range per gain time
+  size_t tt_cap = 0;
+  int* d_chlo = nullptr;
+  size_t chlo_cap = 0;
+  int* d_chhi = nullptr;
+  size_t chhi_cap = 0;
+  int max_int_chan = 0;       // channels of the widest interval of the last prepared term
+  std::vector<int> h_clo, h_chi;   // channel range of every interval of the last prepared term
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  int waves = 4;
+};
+
+namespace qc {
+
+inline qc_status fail(qc_ctx* ctx, qc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->msg = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? QC_E_NOMEM : QC_E_DEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                    \
+  } while (0)
+
+template <typename P>
+hipError_t grow(P*& ptr, size_t& cap, size_t n) {
+  if (n <= cap && ptr) return hipSuccess;
+  if (ptr) {
+    hipError_t e = hipFree(ptr);
+    if (e != hipSuccess) return e;
+    ptr = nullptr;
+  }
+  size_t want = std::max<size_t>(n, 64);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), want * sizeof(P));
+  if (e != hipSuccess) {
+    cap = 0;
+    ptr = nullptr;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+
+struct HostMaps {
+  std::vector<int> t_map, f_map, d_map;
+};
+
+qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
+                  std::vector<HostMaps>& maps, hipStream_t s);
+void fill_args(const qc_vis* v, const qc_term* chain, int n_term, int active, VisArgs& va, ChainArgs& ca);
+qc_status read_err(qc_ctx* ctx, hipStream_t s);
+int resolve_damping(qc_damping d, const qc_term& t);
+bool dmap_constant(const HostMaps& hm);
+
+}  // namespace qc

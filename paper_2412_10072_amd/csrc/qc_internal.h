@@ -225,6 +225,8 @@ struct SolveLaunch {
   int damping;                // resolved: 0 full, 1 half, 2 alternate
   int* err;
   int waves;                  // waves per workgroup
+  int max_int_chan;           // channels of the widest interval
+  int rows_per_step;          // 0: chosen from max_int_chan
 };
 
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_bytes_out);

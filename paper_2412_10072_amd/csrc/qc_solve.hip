@@ -1,7 +1,9 @@
-// Fused per-interval AllJones Gauss-Newton solver for gfx950.
+// Fused per-interval AllJones Gauss-Newton solver for gfx950: one workgroup
+// per solution interval of the active chain term (grid = intervals).
 //
-// One workgroup owns one solution interval of the active chain term and runs
-// the paper's Algorithm 1 on it to convergence without returning to the host:
+// Each workgroup runs the paper's Algorithm 1 on its interval to convergence
+// without returning to the host (the loop itself is solve_interval in
+// qc_interval.h):
 //
 //   repeat
 //     stream every (row, channel) sample of the interval from HBM once,
@@ -15,761 +17,62 @@
 //     in FP64 (eq. update), apply the damped step, test convergence
 //   until converged or max_iter updates.
 //
-// Lanes map to 64 consecutive channels of one row (the innermost, contiguous
-// dimension), so every load of a wavefront is a contiguous 2 KB (complex64
-// 2x2) segment.  Rows are time-major and p-major within a time, so the
-// antenna-p contributions stay in registers for the length of a p-run; the
-// antenna-q contributions are reduced across the wavefront every row with a
-// reduce-scatter (each lane ends holding one summed value) and added to the
-// wave's private LDS slot with a compensated (Kahan) sum.  No atomics are
-// used, so the result is bitwise reproducible.
+// Lanes map to consecutive channels of a row (the innermost, contiguous
+// dimension), so every load of a wavefront is a contiguous segment.  Rows are
+// time-major and p-major within a time, so the antenna-p contributions stay
+// in registers for the length of a p-run; the antenna-q contributions are
+// reduced across the wavefront every row with a reduce-scatter (each lane
+// ends holding one summed value) and added to the wave's private LDS slot
+// with a compensated (Kahan) sum.  No atomics are used, so the result is
+// bitwise reproducible.
 //
 // Precision: T = float (MIXED: complex64 products and residuals, FP32 sums
 // with compensation) or double (FP64 everywhere).  The block solve, the
 // update and the convergence test are FP64 in both.
 
-#include <type_traits>
-
-#include "qc_internal.h"
+#include "qc_interval.h"
 
 namespace qc {
 namespace {
 
-template <int KIND> struct KindInfo;
-template <> struct KindInfo<KIND_DIAG>  { static constexpr int NV = 6;  };
-template <> struct KindInfo<KIND_C2X2>  { static constexpr int NV = 16; };
-template <> struct KindInfo<KIND_DELAY> { static constexpr int NV = 4;  };
-
-constexpr int pow2ceil(int n) { return n <= 1 ? 1 : 2 * pow2ceil((n + 1) / 2); }
-
-// Dynamic LDS of the solve kernel.  Accumulator slots are addressed as
-// offsets from this symbol so that every access compiles to a ds_* op.
-extern __shared__ __align__(16) unsigned char qc_lds[];
-
-template <typename A>
-__device__ __forceinline__ A* lds_at(unsigned byte_off) {
-  return reinterpret_cast<A*>(qc_lds + byte_off);
-}
-constexpr double PIVOT_REL = 1e-12;
-constexpr double TWO_PI = 6.283185307179586476925286766559;
-
-// ---------------------------------------------------------------------------
-// wavefront reduce-scatter: v[0..CNT) summed over the 64 lanes; afterwards
-// lane L holds the total of value `idx` in v[0], identical in every lane of
-// its group of 64/CNT consecutive lanes.
-// ---------------------------------------------------------------------------
-template <int CNT, int OFF, typename A>
-struct ReduceScatter {
-  static __device__ __forceinline__ void run(A* v, int lane, int& idx) {
-    if constexpr (OFF >= 1) {
-      if constexpr (CNT > 1) {
-        constexpr int H = CNT / 2;
-        const bool up = (lane & OFF) != 0;
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-          const A send = up ? v[j] : v[j + H];
-          const A keep = up ? v[j + H] : v[j];
-          v[j] = keep + __shfl_xor(send, OFF);
-        }
-        idx = 2 * idx + (up ? 1 : 0);
-        ReduceScatter<H, OFF / 2, A>::run(v, lane, idx);
-      } else {
-        v[0] += __shfl_xor(v[0], OFF);
-        ReduceScatter<1, OFF / 2, A>::run(v, lane, idx);
-      }
-    }
-  }
-};
-
-// FP32 variant of the reduce-scatter built from cross-lane VALU operations
-// (no LDS traffic): the offset-32 and offset-16 steps use gfx950's
-// v_permlane32_swap / v_permlane16_swap, which exchange the upper half of
-// one register with the lower half of another, so a pair (x, y) becomes
-// (x_lo + x_hi | y_lo + y_hi) with one swap and one add; the steps inside a
-// 16-lane row use DPP (row mirror pairs lane i with 15 - i, half-row mirror
-// i with 7 - i, quad permutes i with i ^ 2 and i ^ 1).
-__device__ __forceinline__ unsigned fbits(float x) { return __builtin_bit_cast(unsigned, x); }
-__device__ __forceinline__ float ffrom(unsigned x) { return __builtin_bit_cast(float, x); }
-
-constexpr int DPP_ROW_MIRROR = 0x140;
-constexpr int DPP_ROW_HALF_MIRROR = 0x141;
-constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
-constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
-
-template <int OFF> struct DppCtrl;
-template <> struct DppCtrl<8> { static constexpr int v = DPP_ROW_MIRROR; };
-template <> struct DppCtrl<4> { static constexpr int v = DPP_ROW_HALF_MIRROR; };
-template <> struct DppCtrl<2> { static constexpr int v = DPP_QUAD_XOR2; };
-template <> struct DppCtrl<1> { static constexpr int v = DPP_QUAD_XOR1; };
-
-template <int OFF>
-__device__ __forceinline__ float partner(float x) {
-  return ffrom((unsigned)__builtin_amdgcn_mov_dpp((int)fbits(x), DppCtrl<OFF>::v, 0xF, 0xF, true));
-}
-
-// lanes with bit OFF clear end with x summed over the pair, the others with y
-template <int OFF>
-__device__ __forceinline__ float pair_step(float x, float y, bool up) {
-  if constexpr (OFF == 32) {
-    auto r = __builtin_amdgcn_permlane32_swap(fbits(x), fbits(y), false, false);
-    return ffrom(r[0]) + ffrom(r[1]);
-  } else if constexpr (OFF == 16) {
-    auto r = __builtin_amdgcn_permlane16_swap(fbits(x), fbits(y), false, false);
-    return ffrom(r[0]) + ffrom(r[1]);
-  } else {
-    const float send = up ? x : y;
-    const float keep = up ? y : x;
-    return keep + partner<OFF>(send);
-  }
-}
-
-template <int OFF>
-__device__ __forceinline__ float full_step(float x) {
-  if constexpr (OFF == 32) {
-    auto r = __builtin_amdgcn_permlane32_swap(fbits(x), fbits(x), false, false);
-    return ffrom(r[0]) + ffrom(r[1]);
-  } else if constexpr (OFF == 16) {
-    auto r = __builtin_amdgcn_permlane16_swap(fbits(x), fbits(x), false, false);
-    return ffrom(r[0]) + ffrom(r[1]);
-  } else {
-    return x + partner<OFF>(x);
-  }
-}
-
-template <int CNT, int OFF>
-struct ReduceScatterF32 {
-  static __device__ __forceinline__ void run(float* v, int lane, int& idx) {
-    if constexpr (OFF >= 1) {
-      if constexpr (CNT > 1) {
-        constexpr int H = CNT / 2;
-        const bool up = (lane & OFF) != 0;
-#pragma unroll
-        for (int j = 0; j < H; ++j) v[j] = pair_step<OFF>(v[j], v[j + H], up);
-        idx = 2 * idx + (up ? 1 : 0);
-        ReduceScatterF32<H, OFF / 2>::run(v, lane, idx);
-      } else {
-        v[0] = full_step<OFF>(v[0]);
-        ReduceScatterF32<1, OFF / 2>::run(v, lane, idx);
-      }
-    }
-  }
-};
-
-// Reduce NVP values across the wave and add value k (< NVAL) into the LDS
-// slot at byte offset s_off (and its compensation slot at c_off when
-// KAHAN).  v is clobbered.
-template <int NVP, int NVAL, bool KAHAN, typename A>
-__device__ __forceinline__ void wave_flush(A* v, int lane, unsigned s_off, unsigned c_off) {
-  int idx = 0;
-  if constexpr (sizeof(A) == 4) ReduceScatterF32<NVP, 32>::run(v, lane, idx);
-  else ReduceScatter<NVP, 32, A>::run(v, lane, idx);
-  constexpr int GROUP = 64 / NVP;
-  if ((lane & (GROUP - 1)) == 0 && idx < NVAL) {
-    const A x = v[0];
-    A* ps = lds_at<A>(s_off) + idx;
-    if constexpr (KAHAN) {
-      A* pc = lds_at<A>(c_off) + idx;
-      const A s = *ps;
-      const A c = *pc;
-      const A y = x - c;
-      const A t = s + y;
-      *pc = (t - s) - y;
-      *ps = t;
-    } else {
-      *ps += x;
-    }
-  }
-}
-
-template <typename A>
-__device__ __forceinline__ A wave_sum(A x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-// ---------------------------------------------------------------------------
-// per-sample block contributions for one antenna orientation
-//
-// alpha = (a0, a1): diagonal of the chain left of the active term (identity
-// when ALPHA1).  B: the right factor C>_p M C_q^H summed over the directions
-// that share one gain (eq. chain_trick with eq. g_derivative_di / _dd), so
-// that the derivative block is K[(a,b),(i,k)] = alpha_a delta_ai B[k,b].
-// WR: weights times residual of the orientation, w: its weights (row-major 2x2).
-//   COMPLEX2X2: JHJ splits into two 2x2 Hermitian blocks (one per row i of
-//     the gain): |alpha_i|^2 sum_b w_ib conj(B_kb) B_k'b;
-//     JHr[i,k] = conj(alpha_i) sum_b w_ib R_ib conj(B_kb).
-//   DIAGONAL: h_i = |alpha_i|^2 sum_b w_ib |B_ib|^2, j_i = conj(alpha_i) sum_b w_ib R_ib conj(B_ib).
-//   DELAY (g_i = exp(2 pi i nu tau_i)): h_i = (2 pi nu)^2 |alpha_i g_i|^2 sum_b w_ib |B_ib|^2,
-//     b_i = 2 pi nu Im(conj(g_i) j_i)   (the real parameterised blocks
-//     without their common factor 2, which cancels in the update).
-// ---------------------------------------------------------------------------
-template <int KIND, bool ALPHA1, typename T>
-__device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, const m22<T>& WR, T w0, T w1,
-                                        T w2, T w3, cx<T> g0, cx<T> g1, T tpn, T* acc) {
-  // acc += the contribution; WR = W o R (elementwise).  Every sum is an FMA
-  // chain into the accumulator.
-  if constexpr (KIND == KIND_C2X2) {
-    const T n00 = norm2(B.a), n01 = norm2(B.b), n10 = norm2(B.c), n11 = norm2(B.d);
-    const cx<T> x0 = cmulc(B.a, B.c);   // conj(B_00) B_10
-    const cx<T> x1 = cmulc(B.b, B.d);   // conj(B_01) B_11
-    if constexpr (ALPHA1) {
-      acc[0] = fma(w0, n00, fma(w1, n01, acc[0]));
-      acc[1] = fma(w0, n10, fma(w1, n11, acc[1]));
-      acc[2] = fma(w0, x0.re, fma(w1, x1.re, acc[2]));
-      acc[3] = fma(w0, x0.im, fma(w1, x1.im, acc[3]));
-      acc[4] = fma(w2, n00, fma(w3, n01, acc[4]));
-      acc[5] = fma(w2, n10, fma(w3, n11, acc[5]));
-      acc[6] = fma(w2, x0.re, fma(w3, x1.re, acc[6]));
-      acc[7] = fma(w2, x0.im, fma(w3, x1.im, acc[7]));
-      cx<T> j;
-      j = cfma_cj(WR.b, B.b, cfma_cj(WR.a, B.a, cmake(acc[8], acc[9])));   acc[8] = j.re;  acc[9] = j.im;
-      j = cfma_cj(WR.b, B.d, cfma_cj(WR.a, B.c, cmake(acc[10], acc[11]))); acc[10] = j.re; acc[11] = j.im;
-      j = cfma_cj(WR.d, B.b, cfma_cj(WR.c, B.a, cmake(acc[12], acc[13]))); acc[12] = j.re; acc[13] = j.im;
-      j = cfma_cj(WR.d, B.d, cfma_cj(WR.c, B.c, cmake(acc[14], acc[15]))); acc[14] = j.re; acc[15] = j.im;
-    } else {
-      const T s0 = norm2(a0), s1 = norm2(a1);
-      acc[0] = fma(s0, fma(w0, n00, w1 * n01), acc[0]);
-      acc[1] = fma(s0, fma(w0, n10, w1 * n11), acc[1]);
-      acc[2] = fma(s0, fma(w0, x0.re, w1 * x1.re), acc[2]);
-      acc[3] = fma(s0, fma(w0, x0.im, w1 * x1.im), acc[3]);
-      acc[4] = fma(s1, fma(w2, n00, w3 * n01), acc[4]);
-      acc[5] = fma(s1, fma(w2, n10, w3 * n11), acc[5]);
-      acc[6] = fma(s1, fma(w2, x0.re, w3 * x1.re), acc[6]);
-      acc[7] = fma(s1, fma(w2, x0.im, w3 * x1.im), acc[7]);
-      cx<T> j;
-      j = cfma_jc(a0, cfma_cj(WR.b, B.b, mulc(WR.a, B.a)), cmake(acc[8], acc[9]));    acc[8] = j.re;  acc[9] = j.im;
-      j = cfma_jc(a0, cfma_cj(WR.b, B.d, mulc(WR.a, B.c)), cmake(acc[10], acc[11]));  acc[10] = j.re; acc[11] = j.im;
-      j = cfma_jc(a1, cfma_cj(WR.d, B.b, mulc(WR.c, B.a)), cmake(acc[12], acc[13]));  acc[12] = j.re; acc[13] = j.im;
-      j = cfma_jc(a1, cfma_cj(WR.d, B.d, mulc(WR.c, B.c)), cmake(acc[14], acc[15]));  acc[14] = j.re; acc[15] = j.im;
-    }
-  } else {
-    const T h0 = fma(w0, norm2(B.a), w1 * norm2(B.b));
-    const T h1 = fma(w2, norm2(B.c), w3 * norm2(B.d));
-    cx<T> j0 = cfma_cj(WR.b, B.b, mulc(WR.a, B.a));
-    cx<T> j1 = cfma_cj(WR.d, B.d, mulc(WR.c, B.c));
-    T s0 = T(1), s1 = T(1);
-    if constexpr (!ALPHA1) {
-      s0 = norm2(a0);
-      s1 = norm2(a1);
-      j0 = cmulc(a0, j0);
-      j1 = cmulc(a1, j1);
-    }
-    if constexpr (KIND == KIND_DIAG) {
-      acc[0] = fma(s0, h0, acc[0]);
-      acc[1] = fma(s1, h1, acc[1]);
-      acc[2] += j0.re; acc[3] += j0.im;
-      acc[4] += j1.re; acc[5] += j1.im;
-    } else {
-      const T t2 = tpn * tpn;
-      acc[0] = fma(t2 * norm2(g0), s0 * h0, acc[0]);
-      acc[1] = fma(t2 * norm2(g1), s1 * h1, acc[1]);
-      acc[2] = fma(tpn, cmulc(g0, j0).im, acc[2]);
-      acc[3] = fma(tpn, cmulc(g1, j1).im, acc[3]);
-    }
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ m22<T> wmul(const m22<T>& R, T w0, T w1, T w2, T w3) {
-  return {scale(R.a, w0), scale(R.b, w1), scale(R.c, w2), scale(R.d, w3)};
-}
-
-// sum_ab w_ab |R_ab|^2 from WR = W o R
-template <typename T>
-__device__ __forceinline__ T chisq_acc(const m22<T>& WR, const m22<T>& R, T acc) {
-  acc = fma(WR.a.re, R.a.re, fma(WR.a.im, R.a.im, acc));
-  acc = fma(WR.b.re, R.b.re, fma(WR.b.im, R.b.im, acc));
-  acc = fma(WR.c.re, R.c.re, fma(WR.c.im, R.c.im, acc));
-  return fma(WR.d.re, R.d.re, fma(WR.d.im, R.d.im, acc));
-}
-
-// ---------------------------------------------------------------------------
-// sample loads
-// ---------------------------------------------------------------------------
-template <typename S, typename T>
-__device__ __forceinline__ m22<T> load_m22(const S* base, size_t elem) {
-  if constexpr (sizeof(S) == 4) {
-    const float4* p = reinterpret_cast<const float4*>(base) + 2 * elem;
-    const float4 u = p[0], v = p[1];
-    return {cmake<T>((T)u.x, (T)u.y), cmake<T>((T)u.z, (T)u.w), cmake<T>((T)v.x, (T)v.y),
-            cmake<T>((T)v.z, (T)v.w)};
-  } else {
-    const double2* p = reinterpret_cast<const double2*>(base) + 4 * elem;
-    const double2 a = p[0], b = p[1], c = p[2], d = p[3];
-    return {cmake<T>((T)a.x, (T)a.y), cmake<T>((T)b.x, (T)b.y), cmake<T>((T)c.x, (T)c.y),
-            cmake<T>((T)d.x, (T)d.y)};
-  }
-}
-
-template <typename S, typename T>
-__device__ __forceinline__ void load_w(const S* base, size_t s, int n_wcorr, T& w0, T& w1, T& w2, T& w3) {
-  if (n_wcorr == 4) {
-    if constexpr (sizeof(S) == 4) {
-      const float4 u = reinterpret_cast<const float4*>(base)[s];
-      w0 = (T)u.x; w1 = (T)u.y; w2 = (T)u.z; w3 = (T)u.w;
-    } else {
-      const double2* p = reinterpret_cast<const double2*>(base) + 2 * s;
-      const double2 a = p[0], b = p[1];
-      w0 = (T)a.x; w1 = (T)a.y; w2 = (T)b.x; w3 = (T)b.y;
-    }
-  } else {
-    const T x = (T)base[s];
-    w0 = w1 = w2 = w3 = x;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ m22<T> select_m(bool use, const m22<T>& x) {
-  const T z = T(0);
-  return {cmake<T>(use ? x.a.re : z, use ? x.a.im : z), cmake<T>(use ? x.b.re : z, use ? x.b.im : z),
-          cmake<T>(use ? x.c.re : z, use ? x.c.im : z), cmake<T>(use ? x.d.re : z, use ? x.d.im : z)};
-}
-
-// ---------------------------------------------------------------------------
-// FP64 per-block solve by Cholesky (the pivot rule flags a block singular
-// when a pivot is <= PIVOT_REL times its largest diagonal entry).
-// ---------------------------------------------------------------------------
-struct c64d {
-  double re, im;
-};
-
-__device__ __forceinline__ bool chol2(double h00, double h11, double hre, double him, c64d b0, c64d b1,
-                                      double dmax, c64d& x0, c64d& x1) {
-  // H = [[h00, h01], [conj(h01), h11]], h01 = hre + i him
-  if (!(h00 > PIVOT_REL * dmax)) return false;
-  const double L00 = sqrt(h00);
-  const c64d L10 = {hre / L00, -him / L00};   // conj(h01) / L00
-  const double piv = h11 - (L10.re * L10.re + L10.im * L10.im);
-  if (!(piv > PIVOT_REL * dmax)) return false;
-  const double L11 = sqrt(piv);
-  const c64d y0 = {b0.re / L00, b0.im / L00};
-  // y1 = (b1 - L10 y0) / L11
-  const c64d ly = {L10.re * y0.re - L10.im * y0.im, L10.re * y0.im + L10.im * y0.re};
-  const c64d y1 = {(b1.re - ly.re) / L11, (b1.im - ly.im) / L11};
-  x1 = {y1.re / L11, y1.im / L11};
-  // x0 = (y0 - conj(L10) x1) / L00
-  const c64d cx1 = {L10.re * x1.re + L10.im * x1.im, L10.re * x1.im - L10.im * x1.re};
-  x0 = {(y0.re - cx1.re) / L00, (y0.im - cx1.im) / L00};
-  return true;
-}
-
-__device__ __forceinline__ bool chol_diag(double h, c64d b, double dmax, c64d& x) {
-  if (!(h > PIVOT_REL * dmax)) return false;
-  const double L = sqrt(h);
-  x = {(b.re / L) / L, (b.im / L) / L};
-  return true;
-}
-
-__device__ __forceinline__ double step_length(int damping, int k) {
-  if (damping == 0) return 1.0;
-  if (damping == 1) return 0.5;
-  return (k & 1) ? 1.0 : 0.5;
-}
-
-// ---------------------------------------------------------------------------
-// the fused kernel
-//
-// SINGLE: the chain is the active term alone, one direction, one gain
-//         direction (the plain full-Jones / diagonal solve).
-// NG:     gain directions of the active term held per antenna (1 or 4).
-// ---------------------------------------------------------------------------
-template <int KIND, typename S, typename T, bool SINGLE, int NG>
+template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
 __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
-  using A = T;
-  constexpr bool KAHAN = (sizeof(T) == 4);
-  constexpr int NV = KindInfo<KIND>::NV;
-  constexpr int NVG = NV * NG;
-  constexpr int NVP = pow2ceil(NVG);
-  constexpr bool PACC = (NG == 1);   // keep antenna-p sums in registers over a p-run
-  static_assert(NVP <= 64, "too many values per antenna");
-
-  const VisArgs& V = L.vis;
-  const ChainArgs& CH = L.chain;
-  const TermArgs& TA = CH.t[CH.active];
-  const int n_ant = V.n_ant;
-  const int n_gdir = SINGLE ? 1 : TA.n_gdir;
+  const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
-  const int interval = blockIdx.x;
-  const int gt = interval / n_gf;
-  const int gf = interval - gt * n_gf;
-  const long long r_lo = L.row_lo[gt], r_hi = L.row_hi[gt];
-  const int c_lo = L.chan_lo[gf], c_hi = L.chan_hi[gf];
-  const int nw = blockDim.x >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int n_slots = n_ant * NG;
-  const int slot_vals = n_slots * NV;
-
-  // ---- LDS carve-up ----
-  unsigned char* lp = qc_lds;
-  double* tot = reinterpret_cast<double*>(lp);            lp += sizeof(double) * slot_vals;
-  double2* gm = reinterpret_cast<double2*>(lp);           lp += sizeof(double2) * n_slots * 4;
-  double* red = reinterpret_cast<double*>(lp);            lp += sizeof(double) * 2 * 16;
-  double* chiw = reinterpret_cast<double*>(lp);           lp += sizeof(double) * 16;
-  cx<T>* gc = reinterpret_cast<cx<T>*>(lp);               lp += sizeof(cx<T>) * n_slots * 4;
-  int* gfl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * n_slots;
-  int* ctl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * 4;
-  lp = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(lp) + 15) & ~uintptr_t(15));
-  A* acc_s = reinterpret_cast<A*>(lp);
-  const unsigned acc_s_off = (unsigned)(lp - qc_lds);
-  lp += sizeof(A) * slot_vals * nw;
-  A* acc_c = reinterpret_cast<A*>(lp);
-  const unsigned acc_c_off = (unsigned)(lp - qc_lds);
-  A* my_s = acc_s + (size_t)wave * slot_vals;
-  A* my_c = acc_c + (size_t)wave * slot_vals;
-  // byte offsets of this wave's slots; antenna a's values start at a * NG * NV
-  const unsigned my_s_off = acc_s_off + (unsigned)(sizeof(A) * wave * slot_vals);
-  const unsigned my_c_off = acc_c_off + (unsigned)(sizeof(A) * wave * slot_vals);
-  constexpr unsigned ANT_BYTES = sizeof(A) * NG * NV;
-
-  // ---- initial gains of this interval into LDS ----
-  const size_t gbase = ((size_t)gt * n_gf + gf) * n_ant;
-  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
-    const int ant = i / n_gdir, gd = i - ant * n_gdir;
-    const int slot = ant * NG + gd;
-    const size_t src = (gbase + ant) * n_gdir + gd;
-    if constexpr (KIND == KIND_DELAY) {
-      gm[slot * 4 + 0] = make_double2(L.params[2 * src + 0], L.params[2 * src + 1]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double2 g = L.gains[4 * src + k];
-        gm[slot * 4 + k] = g;
-        gc[slot * 4 + k] = cmake<T>((T)g.x, (T)g.y);
-      }
-    }
-    gfl[slot] = 0;
-  }
-  double nu_max = 0.0;
-  if constexpr (KIND == KIND_DELAY) {
-    if (threadIdx.x == 0) {
-      double m = 0.0;
-      for (int c = c_lo; c < c_hi; ++c) m = fmax(m, V.freq[c]);
-      red[0] = m;
-    }
-  }
-  __syncthreads();
-  if constexpr (KIND == KIND_DELAY) nu_max = red[0];
-
-  // ---- rows of this wave ----
-  const long long n_rows = r_hi - r_lo;
-  const long long rw_lo = r_lo + (n_rows * wave) / nw;
-  const long long rw_hi = r_lo + (n_rows * (wave + 1)) / nw;
-  const S* Dp = reinterpret_cast<const S*>(V.data);
-  const S* Mp = reinterpret_cast<const S*>(V.model);
-  const S* Wp = reinterpret_cast<const S*>(V.weight);
-  const int n_chan = V.n_chan;
-  const int n_dir = SINGLE ? 1 : V.n_dir;
-  const int n_term = CH.n_term;
-  const int act = CH.active;
-
-  double chisq_first = 0.0, chisq_last = 0.0;
-  int iters = 0, converged = 0;
-
-  for (int it = 0;; ++it) {
-    for (int i = lane; i < slot_vals; i += 64) {
-      my_s[i] = A(0);
-      if constexpr (KAHAN) my_c[i] = A(0);
-    }
-    A chi = A(0);
-    A pacc[NVP];
-#pragma unroll
-    for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
-    int p_cur = -1;
-
-    for (long long r = rw_lo; r < rw_hi; ++r) {
-      const int p = V.ant1[r];
-      const int q = V.ant2[r];
-      const int t = V.row_time[r];
-      if (p == q || (unsigned)p >= (unsigned)n_ant || (unsigned)q >= (unsigned)n_ant) continue;
-      if constexpr (PACC) {
-        if (p != p_cur) {
-          if (p_cur >= 0) {
-            wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s_off + p_cur * ANT_BYTES, my_c_off + p_cur * ANT_BYTES);
-#pragma unroll
-            for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
-          }
-          p_cur = p;
-        }
-      }
-      A qacc[NVP];
-      A prow[NVP];
-#pragma unroll
-      for (int k = 0; k < NVP; ++k) { qacc[k] = A(0); prow[k] = A(0); }
-
-      // left factor of the active term (diagonal, direction independent)
-      cx<T> ap0 = cone<T>(), ap1 = cone<T>(), aq0 = cone<T>(), aq1 = cone<T>();
-
-      for (int c0 = c_lo; c0 < c_hi; c0 += 64) {
-        const int c = c0 + lane;
-        const bool inb = c < c_hi;
-        const int cc = inb ? c : c_lo;
-        const size_t s = (size_t)r * n_chan + cc;
-        const bool use = inb && (V.flag[s] == 0);
-        const double nu = V.freq[cc];
-        const T tpn = (T)(TWO_PI * nu);
-        T w0, w1, w2, w3;
-        load_w<S, T>(Wp, s, V.n_wcorr, w0, w1, w2, w3);
-        w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
-        const m22<T> D = select_m(use, load_m22<S, T>(Dp, s));
-
-        if constexpr (SINGLE) {
-          // chain = the active term alone: C_p = G_p, C_q = G_q
-          m22<T> Gp, Gq;
-          if constexpr (KIND == KIND_DELAY) {
-            const double2 tp = gm[p * 4], tq = gm[q * 4];
-            Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
-            Gq = {phasor_turns<T>(nu * tq.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tq.y)};
-          } else {
-            Gp = {gc[p * 4 + 0], gc[p * 4 + 1], gc[p * 4 + 2], gc[p * 4 + 3]};
-            Gq = {gc[q * 4 + 0], gc[q * 4 + 1], gc[q * 4 + 2], gc[q * 4 + 3]};
-            if constexpr (KIND == KIND_DIAG) {
-              Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
-            }
-          }
-          const m22<T> M = select_m(use, load_m22<S, T>(Mp, s));
-          const m22<T> B = mmul_h(M, Gq);        // M G_q^H
-          const m22<T> GM = mmul(Gp, M);         // G_p M
-          const m22<T> R = msub_mul(D, Gp, B);   // D - G_p M G_q^H
-          const m22<T> WR = wmul(R, w0, w1, w2, w3);
-          // conjugate baseline: B' = M^H G_p^H, W' o R' = (W o R)^H
-          contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, Gp.a, Gp.d, tpn, PACC ? pacc : prow);
-          contrib<KIND, true, T>(aq0, aq1, herm(GM), herm(WR), w0, w2, w1, w3, Gq.a, Gq.d, tpn, qacc);
-          chi = chisq_acc(WR, R, chi);
-        } else {
-          // left factor: product of the (diagonal, direction-independent)
-          // terms before the active one
-          {
-            m22<T> Ap = chain_range<T>(CH, n_ant, 0, act, t, cc, p, 0, nu);
-            m22<T> Aq = chain_range<T>(CH, n_ant, 0, act, t, cc, q, 0, nu);
-            ap0 = Ap.a; ap1 = Ap.d; aq0 = Aq.a; aq1 = Aq.d;
-          }
-          m22<T> Bs[NG], Bsc[NG];
-          cx<T> gp0[NG], gp1[NG], gq0[NG], gq1[NG];
-#pragma unroll
-          for (int g = 0; g < NG; ++g) {
-            Bs[g] = mzero<T>();
-            Bsc[g] = mzero<T>();
-            gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
-          }
-          m22<T> Vm = mzero<T>();
-          for (int d = 0; d < n_dir; ++d) {
-            const int gd = TA.d_map[d];
-            m22<T> Gp, Gq;
-            if constexpr (KIND == KIND_DELAY) {
-              const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
-              Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
-              Gq = {phasor_turns<T>(nu * tq.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tq.y)};
-            } else {
-              const cx<T>* gpp = gc + (p * NG + gd) * 4;
-              const cx<T>* gqq = gc + (q * NG + gd) * 4;
-              Gp = {gpp[0], gpp[1], gpp[2], gpp[3]};
-              Gq = {gqq[0], gqq[1], gqq[2], gqq[3]};
-              if constexpr (KIND == KIND_DIAG) {
-                Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
-              }
-            }
-            const m22<T> Rp = chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, p, d, nu);
-            const m22<T> Rq = chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, q, d, nu);
-            const m22<T> Cp = rowscale(ap0, ap1, mmul(Gp, Rp));
-            const m22<T> Cq = rowscale(aq0, aq1, mmul(Gq, Rq));
-            const m22<T> M = select_m(use, load_m22<S, T>(Mp, s * n_dir + d));
-            const m22<T> B = mmul_h(mmul(Rp, M), Cq);             // C>_p M C_q^H
-            const m22<T> Bc = mmul_h(mmul(Rq, herm(M)), Cp);      // C>_q M^H C_p^H
-            Vm = Vm + rowscale(ap0, ap1, mmul(Gp, B));
-#pragma unroll
-            for (int g = 0; g < NG; ++g) {
-              const bool hit = (g == gd);
-              Bs[g] = hit ? Bs[g] + B : Bs[g];
-              Bsc[g] = hit ? Bsc[g] + Bc : Bsc[g];
-              gp0[g] = hit ? Gp.a : gp0[g];
-              gp1[g] = hit ? Gp.d : gp1[g];
-              gq0[g] = hit ? Gq.a : gq0[g];
-              gq1[g] = hit ? Gq.d : gq1[g];
-            }
-          }
-          const m22<T> R = D - Vm;
-          const m22<T> WR = wmul(R, w0, w1, w2, w3);
-          const m22<T> WRc = herm(WR);
-#pragma unroll
-          for (int g = 0; g < NG; ++g) {
-            contrib<KIND, false, T>(ap0, ap1, Bs[g], WR, w0, w1, w2, w3, gp0[g], gp1[g], tpn,
-                                    (PACC ? pacc : prow) + g * NV);
-            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV);
-          }
-          chi = chisq_acc(WR, R, chi);
-        }
-      }
-      wave_flush<NVP, NVG, KAHAN>(qacc, lane, my_s_off + q * ANT_BYTES, my_c_off + q * ANT_BYTES);
-      if constexpr (!PACC) {
-        wave_flush<NVP, NVG, KAHAN>(prow, lane, my_s_off + p * ANT_BYTES, my_c_off + p * ANT_BYTES);
-      }
-    }
-    if constexpr (PACC) {
-      if (p_cur >= 0)
-        wave_flush<NVP, NVG, KAHAN>(pacc, lane, my_s_off + p_cur * ANT_BYTES, my_c_off + p_cur * ANT_BYTES);
-    }
-    {
-      const double cw = wave_sum<double>((double)chi);
-      if (lane == 0) chiw[wave] = cw;
-    }
-    __syncthreads();
-
-    // ---- combine the wave slots in a fixed order (FP64) ----
-    for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) {
-      double sum = 0.0;
-      for (int w = 0; w < nw; ++w) {
-        sum += (double)acc_s[(size_t)w * slot_vals + i];
-        if constexpr (KAHAN) sum -= (double)acc_c[(size_t)w * slot_vals + i];
-      }
-      tot[i] = sum;
-    }
-    double chi_now = 0.0;
-    for (int w = 0; w < nw; ++w) chi_now += chiw[w];
-    if (it == 0) chisq_first = chi_now;
-    chisq_last = chi_now;
-    __syncthreads();
-    if (it >= L.max_iter) break;
-
-    // ---- per-block FP64 solve and damped update ----
-    const int k_upd = it + 1;
-    const double alpha = step_length(L.damping, k_upd);
-    double num = 0.0, den = 0.0;
-    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
-      const int ant = i / n_gdir, gd = i - ant * n_gdir;
-      const int slot = ant * NG + gd;
-      const double* h = tot + (size_t)slot * NV;
-      bool finite = true;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) finite = finite && isfinite(h[k]);
-      bool ok = finite;
-      if (!finite) atomicOr(L.err, ERR_NONFINITE);
-      if constexpr (KIND == KIND_C2X2) {
-        const double dmax = fmax(fmax(h[0], h[1]), fmax(h[4], h[5]));
-        c64d x00 = {0, 0}, x01 = {0, 0}, x10 = {0, 0}, x11 = {0, 0};
-        ok = ok && isfinite(dmax) && dmax > 0.0;
-        ok = ok && chol2(h[0], h[1], h[2], h[3], {h[8], h[9]}, {h[10], h[11]}, dmax, x00, x01);
-        ok = ok && chol2(h[4], h[5], h[6], h[7], {h[12], h[13]}, {h[14], h[15]}, dmax, x10, x11);
-        if (ok) {
-          const c64d dx[4] = {x00, x01, x10, x11};
-          double2* g = gm + slot * 4;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
-            const double2 xn = make_double2(g[k].x + sr, g[k].y + si);
-            g[k] = xn;
-            gc[slot * 4 + k] = cmake<T>((T)xn.x, (T)xn.y);
-            num += sr * sr + si * si;
-            den += xn.x * xn.x + xn.y * xn.y;
-          }
-        }
-      } else if constexpr (KIND == KIND_DIAG) {
-        const double dmax = fmax(h[0], h[1]);
-        c64d x0 = {0, 0}, x1 = {0, 0};
-        ok = ok && isfinite(dmax) && dmax > 0.0;
-        ok = ok && chol_diag(h[0], {h[2], h[3]}, dmax, x0);
-        ok = ok && chol_diag(h[1], {h[4], h[5]}, dmax, x1);
-        if (ok) {
-          const c64d dx[2] = {x0, x1};
-          double2* g = gm + slot * 4;
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const int e = k ? 3 : 0;
-            const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
-            const double2 xn = make_double2(g[e].x + sr, g[e].y + si);
-            g[e] = xn;
-            gc[slot * 4 + e] = cmake<T>((T)xn.x, (T)xn.y);
-            num += sr * sr + si * si;
-            den += xn.x * xn.x + xn.y * xn.y;
-          }
-        }
-      } else {
-        const double dmax = fmax(h[0], h[1]);
-        ok = ok && isfinite(dmax) && dmax > 0.0;
-        ok = ok && (h[0] > PIVOT_REL * dmax) && (h[1] > PIVOT_REL * dmax);
-        if (ok) {
-          const double l0 = sqrt(h[0]), l1 = sqrt(h[1]);
-          const double d0 = alpha * ((h[2] / l0) / l0);
-          const double d1 = alpha * ((h[3] / l1) / l1);
-          double2* g = gm + slot * 4;
-          g[0] = make_double2(g[0].x + d0, g[0].y + d1);
-          num = fmax(num, TWO_PI * nu_max * fmax(fabs(d0), fabs(d1)));
-        }
-      }
-      gfl[slot] = ok ? 0 : 1;
-    }
-    // ---- convergence over the interval ----
-    {
-      double a = num, b = den;
-      if constexpr (KIND == KIND_DELAY) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
-      } else {
-        a = wave_sum<double>(a);
-        b = wave_sum<double>(b);
-      }
-      if (lane == 0) {
-        red[2 * wave + 0] = a;
-        red[2 * wave + 1] = b;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < nw; ++w) {
-        if constexpr (KIND == KIND_DELAY) a = fmax(a, red[2 * w]);
-        else a += red[2 * w];
-        b += red[2 * w + 1];
-      }
-      double ratio;
-      if constexpr (KIND == KIND_DELAY) ratio = a;
-      else ratio = (a == 0.0) ? 0.0 : (b > 0.0 ? sqrt(a / b) : INFINITY);
-      ctl[0] = (ratio <= L.tol) ? 1 : 0;
-    }
-    __syncthreads();
-    iters = k_upd;
-    if (ctl[0]) {
-      converged = 1;
-      break;
-    }
-    if (k_upd >= L.max_iter) break;
-  }
-
-  // ---- write back ----
-  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
-    const int ant = i / n_gdir, gd = i - ant * n_gdir;
-    const int slot = ant * NG + gd;
-    const size_t dst = (gbase + ant) * n_gdir + gd;
-    if constexpr (KIND == KIND_DELAY) {
-      L.params[2 * dst + 0] = gm[slot * 4].x;
-      L.params[2 * dst + 1] = gm[slot * 4].y;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) L.gains[4 * dst + k] = gm[slot * 4 + k];
-    }
-    if (L.gflags && L.max_iter > 0) L.gflags[dst] = (int8_t)gfl[slot];
-  }
-  if (threadIdx.x == 0) {
-    if (L.iters) L.iters[interval] = iters;
-    if (L.converged) L.converged[interval] = (uint8_t)converged;
-    if (L.chisq_first) L.chisq_first[interval] = chisq_first;
-    if (L.chisq_last) L.chisq_last[interval] = chisq_last;
-  }
+  const int gt = blockIdx.x / n_gf;
+  const int gf = blockIdx.x - gt * n_gf;
+  Job J;
+  J.V = &L.vis;
+  J.CH = &L.chain;
+  J.TA = &TA;
+  J.gains = L.gains;
+  J.params = L.params;
+  J.gflags = L.gflags;
+  J.iters = L.iters;
+  J.converged = L.converged;
+  J.chisq_first = L.chisq_first;
+  J.chisq_last = L.chisq_last;
+  J.gt = gt;
+  J.gf = gf;
+  J.n_gf = n_gf;
+  J.r_lo = L.row_lo[gt];
+  J.r_hi = L.row_hi[gt];
+  J.c_lo = L.chan_lo[gf];
+  J.c_hi = L.chan_hi[gf];
+  J.tol = L.tol;
+  J.max_iter = L.max_iter;
+  J.damping = L.damping;
+  J.err = L.err;
+  solve_interval<KIND, S, T, SINGLE, NG, RPS>(J);
 }
 
-template <int KIND, typename S, typename T, bool SINGLE, int NG>
+template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
-  const int n_slots = L.vis.n_ant * NG;
-  const int nv = KindInfo<KIND>::NV;
   const int nw = L.waves;
-  size_t lds = sizeof(double) * n_slots * nv + sizeof(double2) * n_slots * 4 + sizeof(double) * 48 +
-               sizeof(cx<T>) * n_slots * 4 + sizeof(int) * (n_slots + 4);
-  lds = (lds + 15) & ~size_t(15);
-  lds += sizeof(T) * (size_t)n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1);
+  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = k_solve_fused<KIND, S, T, SINGLE, NG>;
+  auto kern = k_solve_fused<KIND, S, T, SINGLE, NG, RPS>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -782,14 +85,28 @@ hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out)
   return hipGetLastError();
 }
 
+// Rows per wavefront step for the widest interval: keep lanes busy when an
+// interval has few channels (single-term chains only).
+inline int rows_per_step(int max_chan, int nvp) {
+  if (max_chan <= 16 && nvp <= 16) return 4;
+  if (max_chan <= 32 && nvp <= 32) return 2;
+  return 1;
+}
+
 template <int KIND, typename S, typename T>
 hipError_t launch_kind(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
   const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
-  if (single) return launch_one<KIND, S, T, true, 1>(L, stream, lds_out);
-  if (ta.n_gdir == 1) return launch_one<KIND, S, T, false, 1>(L, stream, lds_out);
-  return launch_one<KIND, S, T, false, 4>(L, stream, lds_out);
+  if (single) {
+    constexpr int NVP = pow2ceil(KindInfo<KIND>::NV);
+    const int rps = L.rows_per_step > 0 ? L.rows_per_step : rows_per_step(L.max_int_chan, NVP);
+    if (rps == 4) return launch_one<KIND, S, T, true, 1, 4>(L, stream, lds_out);
+    if (rps == 2) return launch_one<KIND, S, T, true, 1, 2>(L, stream, lds_out);
+    return launch_one<KIND, S, T, true, 1, 1>(L, stream, lds_out);
+  }
+  if (ta.n_gdir == 1) return launch_one<KIND, S, T, false, 1, 1>(L, stream, lds_out);
+  return launch_one<KIND, S, T, false, 4, 1>(L, stream, lds_out);
 }
 
 }  // namespace

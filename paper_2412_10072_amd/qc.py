@@ -29,7 +29,10 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
 
 EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms",
-           "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual")
+           "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
+           "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
+           "qc_batch_destroy", "qc_solve_batch")
+BATCH_BUCKETS = 6
 
 
 class QcError(RuntimeError):
@@ -62,6 +65,10 @@ class QcSolveStats(C.Structure):
                 ("chisq_last", C.c_void_p)]
 
 
+class QcProblem(C.Structure):
+    _fields_ = [("vis", QcVis), ("term", QcTerm), ("stats", QcSolveStats)]
+
+
 _lib = None
 
 
@@ -89,8 +96,16 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                    C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_residual.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32,
                                 C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.qc_batch_create.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(QcSolveOpts), C.POINTER(C.c_void_p)]
+    lib.qc_batch_tune.argtypes = [C.c_void_p, C.c_int32]
+    lib.qc_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+    lib.qc_batch_last_ms.argtypes = [C.c_void_p]
+    lib.qc_batch_last_ms.restype = C.c_double
+    lib.qc_batch_schedule.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
+    lib.qc_batch_destroy.argtypes = [C.c_void_p]
+    lib.qc_solve_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(QcSolveOpts)]
     for name in EXPORTS:
-        if name not in ("qc_last_error", "qc_last_kernel_ms"):
+        if name not in ("qc_last_error", "qc_last_kernel_ms", "qc_batch_last_ms"):
             getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -341,3 +356,71 @@ class Context:
         self._check(self.lib.qc_apply_gains(self.h, C.byref(cv), cc, len(chain), m, mp,
                                             C.c_void_p(out.data_ptr()), C.c_void_p(_stream_ptr(stream))))
         return out
+
+
+def _stats_for(term, dev):
+    shape = (int(term.n_gt), int(term.n_gf))
+    return dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
+                converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
+                chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
+                chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev))
+
+
+class Batch:
+    """A qc_batch plan: many independent single-term problems solved by one
+    graph launch (qc_batch_create / qc_batch_tune / qc_batch_run).
+
+    problems: list of (vis, term) pairs with device tensors; each term's
+    gains are solved in place on every run.  The plan keeps references to
+    every tensor it was given."""
+
+    def __init__(self, ctx: "Context", problems, tol: float = 1e-6, max_iter: int = 100,
+                 prec: str = "mixed", damping: str = "auto", stream=None):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.problems = list(problems)
+        self.stats = []
+        arr = (QcProblem * len(self.problems))()
+        for i, (vis, term) in enumerate(self.problems):
+            st = _stats_for(term, vis.data.device)
+            self.stats.append(st)
+            arr[i].vis = _c_vis(vis)
+            arr[i].term = _c_chain([term])[0]
+            arr[i].stats = QcSolveStats(iters=st["iters"].data_ptr(), converged=st["converged"].data_ptr(),
+                                        chisq_first=st["chisq_first"].data_ptr(),
+                                        chisq_last=st["chisq_last"].data_ptr())
+        self._arr = arr
+        opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
+                           damping=DAMPINGS[damping], stream=_stream_ptr(stream))
+        h = C.c_void_p()
+        ctx._check(self.lib.qc_batch_create(ctx.h, C.cast(arr, C.c_void_p), len(self.problems), C.byref(opts),
+                                            C.byref(h)))
+        self.h = h
+
+    def tune(self, reps: int = 1):
+        self.ctx._check(self.lib.qc_batch_tune(self.h, int(reps)))
+
+    def run(self, stream=None):
+        self.ctx._check(self.lib.qc_batch_run(self.h, C.c_void_p(_stream_ptr(stream))))
+
+    def last_ms(self) -> float:
+        return float(self.lib.qc_batch_last_ms(self.h))
+
+    def schedule(self):
+        n = BATCH_BUCKETS
+        items, waves, rps = (C.c_int32 * n)(), (C.c_int32 * n)(), (C.c_int32 * n)()
+        ms = (C.c_float * n)()
+        self.ctx._check(self.lib.qc_batch_schedule(self.h, items, waves, rps, ms, n))
+        return [dict(items=items[i], waves=waves[i], rows_per_step=rps[i], tuned_ms=float(ms[i]))
+                for i in range(n)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.qc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -293,13 +293,16 @@ def config_tiny(device="cpu", sigma: float = 0.01, n_ant: int = 7, n_time: int =
 def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int = 1024,
                    t_int: int = 1, f_int: int = 64, n_src: int = 20, sigma: float = 0.05,
                    flag_frac: float = 0.10, leakage_var: float = 0.05, time_block: int = 4,
-                   kind: str = "c2x2", dtype="c64", cfg_id: int = 2) -> Problem:
+                   kind: str = "c2x2", dtype="c64", cfg_id: int = 2, seed_block: int = 0,
+                   n_wcorr: int = 4, row_drop: float = 0.0) -> Problem:
     """MeerKAT-shaped full-Jones solve: 64 antennas in an 8 km array, 600 x 8 s times,
     1024 channels over 856-1712 MHz, 20 point sources (log-uniform 0.01-1 Jy within 1 deg),
     complex-2x2 truth gains smooth in time and frequency (diagonal (1 + 0.1 P) e^{i pi P},
     leakage CN(0, 0.05) (1 + 0.1 P)), 10% random flags, noise sigma 0.05, weights 1/sigma^2,
-    solution interval 1 time x 64 channels.  Generated block by block in device memory."""
-    g0 = rng(device, 2412, cfg_id, 0)
+    solution interval 1 time x 64 channels.  Generated block by block in device memory.
+    row_drop > 0 removes that fraction of rows at random (whole-row flags compacted out,
+    rows stay time-ordered)."""
+    g0 = rng(device, 2412, cfg_id, 2 * seed_block)
     ant1, ant2, row_time = row_layout(n_time, n_ant)
     nbl = n_ant * (n_ant - 1) // 2
     n_row = ant1.size
@@ -335,12 +338,52 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
         model[r0:r1, :, 0, 1] = 0
         model[r0:r1, :, 0, 2] = 0
         model[r0:r1, :, 0, 3] = M.to(cdt)
-    g1 = rng(device, 2412, cfg_id, 1)
+    g1 = rng(device, 2412, cfg_id, 2 * seed_block + 1)
     vis = _finish_vis(model, [truth], ant1, ant2, row_time, freq, n_ant, n_time, sigma, g1,
-                      flag_frac, dtype, device, block_rows=time_block * nbl)
+                      flag_frac, dtype, device, block_rows=time_block * nbl, n_wcorr=n_wcorr)
+    if row_drop > 0:
+        keep = torch.rand(n_row, generator=g1, device=device) >= row_drop
+        idx = torch.nonzero(keep).squeeze(1)
+        vis = Vis(data=vis.data[idx].contiguous(), model=vis.model[idx].contiguous(),
+                  weight=vis.weight[idx].contiguous(), flag=vis.flag[idx].contiguous(),
+                  ant1=vis.ant1[idx].contiguous(), ant2=vis.ant2[idx].contiguous(),
+                  row_time=vis.row_time[idx].contiguous(), chan_freq=vis.chan_freq,
+                  n_ant=n_ant, n_time=n_time)
+    n_row = int(vis.data.shape[0])
     return Problem(vis=vis, chain=[term], truth=[truth],
                    meta=dict(name="meerkat", sigma=sigma, n_samples=n_row * n_chan,
-                             n_time=n_time, n_chan=n_chan, n_ant=n_ant))
+                             n_time=n_time, n_chan=n_chan, n_ant=n_ant, kind=kind, t_int=t_int,
+                             f_int=f_int))
+
+
+def batch_shapes(n_problems: int = 256, cfg_id: int = 4, ant_range=(16, 64), time_range=(20, 200),
+                 chan_range=(16, 256), flag_max: float = 0.3):
+    """Shapes of the uneven batch: per problem antennas ~U{16..64}, times ~U{20..200},
+    channels ~U{16..256}, flag fraction f ~U(0, 0.3), term diag / c2x2 50/50, solution
+    interval t_int in {1, 4, 10} x f_int in {16, 32, n_chan} (uniform)."""
+    r = np.random.default_rng(np.random.SeedSequence([2412, cfg_id, 999]))
+    out = []
+    for i in range(n_problems):
+        n_ant = int(r.integers(ant_range[0], ant_range[1] + 1))
+        n_time = int(r.integers(time_range[0], time_range[1] + 1))
+        n_chan = int(r.integers(chan_range[0], chan_range[1] + 1))
+        f = float(r.uniform(0.0, flag_max))
+        kind = "diag" if r.random() < 0.5 else "c2x2"
+        t_int = int(r.choice([1, 4, 10]))
+        f_int = int(r.choice([16, 32, n_chan]))
+        out.append(dict(n_ant=n_ant, n_time=n_time, n_chan=n_chan, flag=f, kind=kind, t_int=t_int,
+                        f_int=f_int))
+    return out
+
+
+def config_batch_problem(shape: dict, index: int, device="cpu", dtype="c64", cfg_id: int = 4) -> Problem:
+    """One problem of the uneven batch: MeerKAT-like sky and gains at the given shape, whole
+    rows flagged with probability f and compacted out, per-sample flags Bernoulli(f / 3),
+    one weight per sample (n_wcorr = 1)."""
+    return config_meerkat(device=device, n_ant=shape["n_ant"], n_time=shape["n_time"],
+                          n_chan=shape["n_chan"], t_int=shape["t_int"], f_int=shape["f_int"],
+                          flag_frac=shape["flag"] / 3.0, kind=shape["kind"], dtype=dtype, cfg_id=cfg_id,
+                          seed_block=index, n_wcorr=1, row_drop=shape["flag"])
 
 
 def slice_times(vis: Vis, t0: int, t1: int) -> Vis:
