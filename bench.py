@@ -37,6 +37,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the solve kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (calibrated on a copy of known size), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_solve_fused_meerkat_fulljones_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return rec
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(prob, budget_s: float = 20.0):
     """The oracle as it stands, timed on host cores on a bounded sample of the
     same workload: whole intervals solved to tol 1e-6 until ~budget_s."""
@@ -61,6 +79,117 @@ def cpu_baseline(prob, budget_s: float = 20.0):
                        f"baselines solved to tol 1e-6 by the FP64 NumPy oracle in {dt:.1f} s")
 
 
+def leg_batch(ctx, dev, n_problems: int = 256, steps: int = 3):
+    """Uneven batch: n_problems independent problems (antennas U{16..64}, times U{20..200},
+    channels U{16..256}, dropped rows, diag / c2x2 50/50) solved to tol 1e-6 (MIXED) by
+    (a) the plain loop of one qc_solve_interval per problem, (b) one graph launch of the
+    batch with the default schedule, (c) the same after the autotuner.  Also FP64 vs MIXED
+    on the GPU and both against the oracle on sampled problems."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+    from oracle import solver as o_solver
+    from synth.generate import batch_shapes, config_batch_problem, to_numpy_vis
+
+    t0 = time.perf_counter()
+    shapes = batch_shapes(n_problems)
+    probs = []
+    for i, sh in enumerate(shapes):
+        p = config_batch_problem(sh, i, device=dev)
+        probs.append((p.vis, qc.device_term(p.chain[0], dev), p.chain[0]))
+    torch.cuda.synchronize()
+    n_samples = int(sum(int(v.data.shape[0]) * int(v.data.shape[1]) for v, _, _ in probs))
+    log(f"batch: generated {n_problems} problems, {n_samples / 1e9:.3f}e9 samples in "
+        f"{time.perf_counter() - t0:.1f} s; HBM in use {torch.cuda.memory_allocated() / 1e9:.1f} GB")
+    init = [t.gains.clone() for _, t, _ in probs]
+    stream = torch.cuda.current_stream()
+
+    def reset():
+        for (_, t, _), g0 in zip(probs, init):
+            t.gains.copy_(g0)
+
+    # (a) plain: one qc_solve_interval per problem, back to back
+    reset()
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    kern = 0.0
+    for vis, t, _ in probs:
+        ctx.solve(vis, [t], 0, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
+        kern += ctx.last_kernel_ms()
+    torch.cuda.synchronize()
+    plain_ms = 1e3 * (time.perf_counter() - tp)
+    plain_gains = [t.gains.clone() for _, t, _ in probs]
+    # (b) one graph launch, default schedule; (c) after tuning
+    pairs = [(v, t) for v, t, _ in probs]
+    b = qc.Batch(ctx, pairs, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
+
+    def timed_runs(k):
+        ms = []
+        for _ in range(k):
+            reset()
+            b.run(stream)
+            ms.append(b.last_ms())
+        return ms
+
+    default_ms = timed_runs(steps)
+    tt = time.perf_counter()
+    b.tune(reps=1)
+    tune_s = time.perf_counter() - tt
+    tuned_ms = timed_runs(steps)
+    sched = b.schedule()
+    iters = np.concatenate([st["iters"].cpu().numpy().ravel() for st in b.stats])
+    mixed = [t.gains.clone() for _, t, _ in probs]
+    d_plain = max(float((m - g).abs().max()) for m, g in zip(mixed, plain_gains))
+    b.close()
+    # FP64 on the GPU, same inputs
+    bf = qc.Batch(ctx, pairs, tol=1e-6, max_iter=100, prec="fp64", stream=stream)
+    reset()
+    bf.run(stream)
+    fp64_ms = bf.last_ms()
+    fp64 = [t.gains.clone() for _, t, _ in probs]
+    bf.close()
+
+    def rel(a, w, kind):
+        a, w = a.cpu().numpy(), np.asarray(w)
+        if kind == "diag":
+            a, w = a[..., [0, 3]], w[..., [0, 3]]
+        nt, nf = w.shape[:2]
+        d = np.linalg.norm((a - w).reshape(nt, nf, -1), axis=-1)
+        n = np.linalg.norm(w.reshape(nt, nf, -1), axis=-1)
+        return float(np.max(d / np.maximum(n, 1e-300)))
+
+    e_mf = max(rel(m, f.cpu().numpy(), t0_.kind) for m, f, (_, _, t0_) in zip(mixed, fp64, probs))
+    # oracle on the smallest problems of each term type (bounded CPU time)
+    order = np.argsort([int(v.data.shape[0]) * int(v.data.shape[1]) for v, _, _ in probs])
+    picked, seen = [], {"diag": 0, "c2x2": 0}
+    for i in order:
+        k = probs[i][2].kind
+        if seen[k] < 2:
+            picked.append(int(i))
+            seen[k] += 1
+    e_mo, e_fo = 0.0, 0.0
+    for i in picked:
+        vis, _, term_h = probs[i]
+        ref, _ = o_solver.solve_term(to_numpy_vis(vis), [term_h], 0, tol=1e-6, max_iter=100)
+        e_mo = max(e_mo, rel(mixed[i], ref[0].gains, term_h.kind))
+        e_fo = max(e_fo, rel(fp64[i], ref[0].gains, term_h.kind))
+    out = dict(problems=n_problems, samples=n_samples,
+               plain_wall_ms=plain_ms, plain_kernel_ms=kern,
+               batch_default_ms=float(np.mean(default_ms)), batch_tuned_ms=float(np.mean(tuned_ms)),
+               tune_s=tune_s, batch_fp64_ms=fp64_ms,
+               vis_per_s_plain=n_samples / (plain_ms * 1e-3),
+               vis_per_s_batched=n_samples / (np.mean(tuned_ms) * 1e-3),
+               speedup_vs_plain=plain_ms / float(np.mean(tuned_ms)),
+               mean_iterations=float(iters.mean()), schedule=sched,
+               max_abs_diff_batched_vs_plain=d_plain,
+               rel_err_mixed_vs_fp64_gpu=e_mf, rel_err_mixed_vs_oracle=e_mo, rel_err_fp64_vs_oracle=e_fo,
+               oracle_problems=picked)
+    log(f"batch: plain {plain_ms:.1f} ms (kernels {kern:.1f}), graph default {np.mean(default_ms):.1f} ms, "
+        f"tuned {np.mean(tuned_ms):.1f} ms (tuning {tune_s:.1f} s), fp64 {fp64_ms:.1f} ms; "
+        f"mixed vs fp64 {e_mf:.2e}, vs oracle {e_mo:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +197,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup override (tuning)")
+    ap.add_argument("--legs", default="batch", help="comma list of extra legs: batch (or none)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver shards by solution intervals with no communication, "
@@ -82,6 +213,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(1 << 32, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 4294967296 B read + 4294967296 B written")
+        del src, dst
+        torch.cuda.empty_cache()
     t0 = time.perf_counter()
     prob = config_meerkat(device=dev, n_time=args.n_time)
     torch.cuda.synchronize()
@@ -92,8 +231,6 @@ def main():
         f"{time.perf_counter() - t0:.1f} s; HBM in use {torch.cuda.memory_allocated() / 1e9:.1f} GB")
 
     ctx = qc.Context(0)
-    if args.waves:
-        ctx.lib.qc_set_waves(ctx.h, args.waves) if hasattr(ctx.lib, "qc_set_waves") else None
     term0 = qc.device_term(prob.chain[0], dev)
     init_gains = term0.gains.clone()
     chain = [term0]
@@ -160,10 +297,28 @@ def main():
                    "converged_fraction": conv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_solve_fused",
-                     "kernel_ms": k_ms},
+                     "kernel_ms": k_ms, "algorithmic_gb_per_launch": float(np.mean(alg_bytes)) / 1e9},
     }
+    tr = measured_traffic()
+    if tr is not None and args.n_time == 600:
+        out["roofline"]["traffic"] = tr["traffic_bytes"] / 1e9
+        out["roofline"]["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    if legs:
+        out["legs"] = {}
+        del prob, vis, resid, chain, term0, init_gains
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if "batch" in legs:
+        try:
+            out["legs"]["batch"] = leg_batch(ctx, dev)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["batch"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"batch leg failed: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -100,6 +100,12 @@ const char* qc_last_error(const qc_ctx* ctx);
  * (waits for it).  Negative if none. */
 double      qc_last_kernel_ms(qc_ctx* ctx);
 
+/* Launch shape of the per-interval solve used by qc_solve_interval,
+ * qc_solve_chain: waves per workgroup (1, 2, 4, 8; 0 = 4) and rows per
+ * wavefront step (1, 2, 4; 0 = 4 rows of 16 lanes).
+ * Multi-row steps apply to single-term, single-direction chains only. */
+qc_status   qc_ctx_set_tile(qc_ctx* ctx, int32_t waves, int32_t rows_per_step);
+
 /* One visibility set (paper Section 2.2; data model of Section 4.1). */
 typedef struct {
   int64_t n_row;

@@ -344,7 +344,7 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   L.err = ctx->d_err;
   L.waves = ctx->waves;
   L.max_int_chan = ctx->max_int_chan;
-  L.rows_per_step = 0;
+  L.rows_per_step = ctx->rows_per_step;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   size_t lds = 0;
   hipError_t e = launch_solve(L, s, &lds);
@@ -356,6 +356,17 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   }
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
   ctx->timed = true;
+  return QC_OK;
+}
+
+qc_status qc_ctx_set_tile(qc_ctx* ctx, int32_t waves, int32_t rows_per_step) {
+  if (!ctx) return QC_E_ARG;
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(ctx, QC_E_ARG, "waves must be 1, 2, 4 or 8 (0 = default)");
+  if (rows_per_step != 0 && rows_per_step != 1 && rows_per_step != 2 && rows_per_step != 4)
+    return fail(ctx, QC_E_ARG, "rows_per_step must be 1, 2 or 4 (0 = from the interval width)");
+  ctx->waves = waves ? waves : 4;
+  ctx->rows_per_step = rows_per_step;
   return QC_OK;
 }
 

@@ -32,7 +32,8 @@ struct qc_ctx {
   std::vector<int> h_clo, h_chi;   // channel range of every interval of the last prepared term
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
-  int waves = 4;
+  int waves = 4;              // waves per workgroup of the per-interval solve
+  int rows_per_step = 0;      // 0: the kernel default
 };
 
 namespace qc {

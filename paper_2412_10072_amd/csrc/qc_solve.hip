@@ -85,12 +85,13 @@ hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out)
   return hipGetLastError();
 }
 
-// Rows per wavefront step for the widest interval: keep lanes busy when an
-// interval has few channels (single-term chains only).
+// Rows per wavefront step of the single-term kernel: 4 rows of 16 lanes.
+// Narrow intervals keep every lane busy, and on wide intervals one segmented
+// flush serves 4 rows instead of one (measured on the MeerKAT-shaped
+// full-Jones solve: 155.9 ms against 175.1 ms for 1 row of 64 lanes).
 inline int rows_per_step(int max_chan, int nvp) {
-  if (max_chan <= 16 && nvp <= 16) return 4;
-  if (max_chan <= 32 && nvp <= 32) return 2;
-  return 1;
+  (void)max_chan;
+  return nvp <= 16 ? 4 : (nvp <= 32 ? 2 : 1);
 }
 
 template <int KIND, typename S, typename T>

@@ -28,7 +28,7 @@ TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
 
-EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms",
+EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms", "qc_ctx_set_tile",
            "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch")
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_last_kernel_ms.restype = C.c_double
     lib.qc_solve_interval.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                       C.POINTER(QcSolveOpts), C.POINTER(QcSolveStats)]
+    lib.qc_ctx_set_tile.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.qc_solve_chain.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                    C.POINTER(QcSolveOpts), C.c_void_p]
     lib.qc_delay_init.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_void_p]
@@ -258,6 +259,10 @@ class Context:
 
     def sync(self):
         self._check(self.lib.qc_ctx_sync(self.h))
+
+    def set_tile(self, waves: int = 0, rows_per_step: int = 0):
+        """qc_ctx_set_tile: launch shape of the per-interval solve (0 = default)."""
+        self._check(self.lib.qc_ctx_set_tile(self.h, int(waves), int(rows_per_step)))
 
     def last_kernel_ms(self) -> float:
         return float(self.lib.qc_last_kernel_ms(self.h))
