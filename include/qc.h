@@ -141,6 +141,10 @@ typedef struct {
   qc_prec    prec;
   qc_damping damping;
   void*      stream;        /* hipStream_t or NULL                               */
+  const double* chisq_ref;  /* NULL, or per interval of the active term [n_gt][n_gf]:
+                               an interval whose chi^2 at the starting gains exceeds
+                               its entry restarts once from unit gains (warm-start
+                               fallback; the reference is chi^2 at unit gains) */
 } qc_solve_opts;
 
 /* Per interval of the active term, [n_gt][n_gf]; any pointer may be NULL. */
@@ -149,6 +153,7 @@ typedef struct {
   uint8_t* converged;       /* 1 if the step ratio reached tol                    */
   double*  chisq_first;     /* sum w |r|^2 at the initial gains                   */
   double*  chisq_last;      /* sum w |r|^2 at the gains before the last update    */
+  uint8_t* restarted;       /* 1 if the chisq_ref fallback restarted the interval */
 } qc_solve_stats;
 
 /*
@@ -213,6 +218,43 @@ qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, i
  * qc_apply_gains. */
 qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                       const uint8_t* dir_mask, void* out, void* stream);
+
+/*
+ * Learned warm start (a two-layer MLP from interval features to initial
+ * diagonal gains), all FP32 unless stated.  Parameters are one flat array
+ * [W1 (n_hid x n_in) | b1 (n_hid) | W2 (n_out x n_hid) | b2 (n_out)],
+ * row-major; y = W2 relu(W1 x + b1) + b2.
+ */
+/* Interval features of `layout`'s solution intervals: per antenna a and
+ * correlation k, rho_{a,k} = sum w_k D_k conj(M_k) / (sum w_k |M_k|^2 + 1e-12)
+ * over the interval's unflagged samples, conjugate baselines folded in (D^H,
+ * M^H, weights permuted by P), M summed over directions.
+ * feat: [n_gt*n_gf][n_ant*8] float, layout [antenna][corr][re, im].
+ * chisq_unit: NULL or [n_gt*n_gf] double, sum w |D - M|^2 (chi^2 at unit gains).
+ * ref_ant >= 0: every ratio is rotated, per correlation, by the phase of that
+ * antenna's, rho_a conj(rho_ref) / |rho_ref| (the gauge of the targets);
+ * ref_ant < 0: raw ratios. */
+qc_status qc_ws_features(qc_ctx* ctx, const qc_vis* vis, const qc_term* layout, float* feat,
+                         double* chisq_unit, int32_t ref_ant, void* stream);
+/* Forward pass of a batch: pre [batch][n_hid] = W1 x + b1, y [batch][n_out]. */
+qc_status qc_mlp_forward(qc_ctx* ctx, const float* params, const float* x, int32_t batch, int32_t n_in,
+                         int32_t n_hid, int32_t n_out, float* y, float* pre, void* stream);
+/* Gradient of sum(dy * y) with respect to the parameters (grad has the
+ * parameters' layout); needs the forward pass's pre-activations. */
+qc_status qc_mlp_backward(qc_ctx* ctx, const float* params, const float* x, const float* pre, const float* dy,
+                          int32_t batch, int32_t n_in, int32_t n_hid, int32_t n_out, float* grad, void* stream);
+/* Adam (Kingma & Ba) with bias correction; step counts from 1. */
+qc_status qc_adam_step(qc_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t n, float lr,
+                       float b1, float b2, float eps, int32_t step, void* stream);
+/* Mean squared error over n values: dy = 2 (y - t) / n; loss (device, 1 float, may be NULL). */
+qc_status qc_mse_grad(qc_ctx* ctx, const float* y, const float* t, int32_t n, float* dy, float* loss, void* stream);
+/* Diagonal gains [n_int][n_ant][1][4] complex128 from y [n_int][n_ant][hand][re, im]. */
+qc_status qc_ws_gains(qc_ctx* ctx, const float* y, int32_t n_int, int32_t n_ant, void* gains, void* stream);
+/* Regression targets from solved diagonal gains [n_int][n_ant][1][4] complex128:
+ * per interval and hand, g_a conj(g_ref) / |g_ref| (the free phase gauge fixed at
+ * ref_ant), written as y [n_int][n_ant][hand][re, im] float. */
+qc_status qc_ws_labels(qc_ctx* ctx, const void* gains, int32_t n_int, int32_t n_ant, int32_t ref_ant, float* y,
+                       void* stream);
 
 /*
  * Batched solve of many independent problems of uneven size (row counts,

@@ -7,6 +7,11 @@ Features of one solution interval, per antenna a and correlation k
 
 laid out [antenna][corr][re, im] (64 antennas -> 512 inputs).
 
+The network sees the features referenced to one antenna, per correlation:
+rho_{a,k} conj(rho_{ref,k}) / |rho_{ref,k}| (unchanged where rho_{ref,k} = 0),
+the same gauge as its targets (gains with the reference antenna's phase
+removed).
+
 MLP: y = W2 relu(W1 x + b1) + b2 with flat parameters [W1 (H x I) | b1 (H) |
 W2 (O x H) | b2 (O)], all row-major.  Loss: mean squared error over the batch
 and outputs.  Adam (Kingma & Ba 2015) with bias correction.
@@ -33,6 +38,18 @@ def features(vis, term, gt, gf):
         np.add.at(den, o.p, o.w * np.abs(Mt) ** 2)
     rho = num / (den + FEAT_EPS)
     return np.stack([rho.real, rho.imag], axis=-1).reshape(-1)
+
+
+def reference_features(f, n_ant, ref=0):
+    """Rotate every antenna's ratio, per correlation, by the phase of the
+    reference antenna's: rho_a conj(rho_ref) / |rho_ref|."""
+    rho = np.asarray(f, np.float64).reshape(n_ant, 4, 2)
+    z = rho[..., 0] + 1j * rho[..., 1]
+    r = z[ref]
+    mag = np.abs(r)
+    rot = np.where(mag > 0, np.conj(r) / np.where(mag > 0, mag, 1.0), 1.0)
+    out = z * rot[None, :]
+    return np.stack([out.real, out.imag], axis=-1).reshape(-1)
 
 
 def param_sizes(n_in, n_hid, n_out):

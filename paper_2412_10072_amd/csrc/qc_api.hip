@@ -269,6 +269,7 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_tt);
   hipFree(ctx->d_chlo);
   hipFree(ctx->d_chhi);
+  hipFree(ctx->d_dh);
   hipEventDestroy(ctx->ev0);
   hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -337,7 +338,9 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
     L.converged = stats->converged;
     L.chisq_first = stats->chisq_first;
     L.chisq_last = stats->chisq_last;
+    L.restarted = stats->restarted;
   }
+  L.chisq_ref = opts->chisq_ref;
   L.tol = opts->tol;
   L.max_iter = opts->max_iter;
   L.damping = resolve_damping(opts->damping, ta);
@@ -412,6 +415,119 @@ qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t
   if (delay_init_lds(ctx->max_int_chan) > 64 * 1024)
     return fail(ctx, QC_E_UNSUPPORTED, "delay interval of %d channels exceeds the LDS budget", ctx->max_int_chan);
   HIP_TRY(ctx, launch_delay_init(L, ctx->max_int_chan, s));
+  return QC_OK;
+}
+
+qc_status qc_ws_features(qc_ctx* ctx, const qc_vis* vis, const qc_term* layout, float* feat, double* chisq_unit,
+                         int32_t ref_ant, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!layout || !feat) return fail(ctx, QC_E_ARG, "layout or feat is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  std::vector<HostMaps> maps;
+  qc_status st = prepare(ctx, vis, layout, 1, 0, maps, s);
+  if (st != QC_OK) return st;
+  FeatLaunch L;
+  memset(&L, 0, sizeof L);
+  ChainArgs ca;
+  fill_args(vis, layout, 1, 0, L.vis, ca);
+  L.vis_is_c128 = vis->dtype == QC_C128;
+  L.n_gt = layout->n_gt;
+  L.n_gf = layout->n_gf;
+  L.row_lo = ctx->d_rowlo;
+  L.row_hi = ctx->d_rowhi;
+  L.chan_lo = ctx->d_chlo;
+  L.chan_hi = ctx->d_chhi;
+  L.feat = feat;
+  L.feat_stride = vis->n_ant * 8;
+  L.chisq_unit = chisq_unit;
+  if (ref_ant >= vis->n_ant) return fail(ctx, QC_E_ARG, "ref_ant=%d outside [0,%d)", ref_ant, vis->n_ant);
+  L.ref_ant = ref_ant;
+  hipError_t e = launch_ws_features(L, 4, s);
+  if (e == hipErrorInvalidValue) return fail(ctx, QC_E_UNSUPPORTED, "too many antennas for the feature pass");
+  HIP_TRY(ctx, e);
+  return QC_OK;
+}
+
+static qc_status check_mlp(qc_ctx* ctx, int batch, int n_in, int n_hid, int n_out) {
+  if (batch <= 0 || n_in <= 0 || n_hid <= 0 || n_out <= 0)
+    return fail(ctx, QC_E_ARG, "bad MLP shape batch=%d in=%d hid=%d out=%d", batch, n_in, n_hid, n_out);
+  return QC_OK;
+}
+
+qc_status qc_mlp_forward(qc_ctx* ctx, const float* params, const float* x, int32_t batch, int32_t n_in,
+                         int32_t n_hid, int32_t n_out, float* y, float* pre, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!params || !x || !y || !pre) return fail(ctx, QC_E_ARG, "a pointer is NULL");
+  qc_status st = check_mlp(ctx, batch, n_in, n_hid, n_out);
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  const float* W1 = params;
+  const float* b1 = W1 + (size_t)n_hid * n_in;
+  const float* W2 = b1 + n_hid;
+  const float* b2 = W2 + (size_t)n_out * n_hid;
+  HIP_TRY(ctx, launch_linear_fwd(x, W1, b1, pre, batch, n_in, n_hid, 0, s));
+  HIP_TRY(ctx, launch_linear_fwd(pre, W2, b2, y, batch, n_hid, n_out, 1, s));
+  return QC_OK;
+}
+
+qc_status qc_mlp_backward(qc_ctx* ctx, const float* params, const float* x, const float* pre, const float* dy,
+                          int32_t batch, int32_t n_in, int32_t n_hid, int32_t n_out, float* grad, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!params || !x || !pre || !dy || !grad) return fail(ctx, QC_E_ARG, "a pointer is NULL");
+  qc_status st = check_mlp(ctx, batch, n_in, n_hid, n_out);
+  if (st != QC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, grow(ctx->d_dh, ctx->dh_cap, (size_t)batch * n_hid));
+  const float* W2 = params + (size_t)n_hid * n_in + n_hid;
+  float* gW1 = grad;
+  float* gb1 = gW1 + (size_t)n_hid * n_in;
+  float* gW2 = gb1 + n_hid;
+  float* gb2 = gW2 + (size_t)n_out * n_hid;
+  HIP_TRY(ctx, launch_linear_bwd_w(pre, dy, gW2, gb2, batch, n_hid, n_out, 1, s));
+  HIP_TRY(ctx, launch_linear_bwd_x(dy, W2, pre, ctx->d_dh, batch, n_hid, n_out, 1, s));
+  HIP_TRY(ctx, launch_linear_bwd_w(x, ctx->d_dh, gW1, gb1, batch, n_in, n_hid, 0, s));
+  return QC_OK;
+}
+
+qc_status qc_adam_step(qc_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t n, float lr,
+                       float b1, float b2, float eps, int32_t step, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!params || !grad || !m || !v || n <= 0 || step <= 0) return fail(ctx, QC_E_ARG, "bad Adam arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, launch_adam(params, grad, m, v, n, lr, b1, b2, eps, step, s));
+  return QC_OK;
+}
+
+qc_status qc_mse_grad(qc_ctx* ctx, const float* y, const float* t, int32_t n, float* dy, float* loss, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!y || !t || !dy || n <= 0) return fail(ctx, QC_E_ARG, "bad MSE arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, launch_mse(y, t, dy, loss, n, s));
+  return QC_OK;
+}
+
+qc_status qc_ws_gains(qc_ctx* ctx, const float* y, int32_t n_int, int32_t n_ant, void* gains, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!y || !gains || n_int < 0 || n_ant <= 0) return fail(ctx, QC_E_ARG, "bad warm-start gain arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, launch_ws_gains(y, n_ant * 4, n_int, n_ant, reinterpret_cast<double2*>(gains), s));
+  return QC_OK;
+}
+
+qc_status qc_ws_labels(qc_ctx* ctx, const void* gains, int32_t n_int, int32_t n_ant, int32_t ref_ant, float* y,
+                       void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!gains || !y || n_int < 0 || n_ant <= 0 || ref_ant < 0 || ref_ant >= n_ant)
+    return fail(ctx, QC_E_ARG, "bad warm-start label arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, launch_ws_labels(reinterpret_cast<const double2*>(gains), n_int, n_ant, ref_ant, y, s));
   return QC_OK;
 }
 

@@ -58,6 +58,8 @@ __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
     J.max_iter = B.max_iter;
     J.damping = P.damping;
     J.err = B.err;
+    J.chisq_ref = nullptr;
+    J.restarted = nullptr;
     if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, true, 1, RPS>(J);
     else solve_interval<KIND_C2X2, S, T, true, 1, RPS>(J);
   }

@@ -30,6 +30,8 @@ struct qc_ctx {
   size_t chhi_cap = 0;
   int max_int_chan = 0;       // channels of the widest interval of the last prepared term
   std::vector<int> h_clo, h_chi;   // channel range of every interval of the last prepared term
+  float* d_dh = nullptr;      // MLP backward scratch [batch][n_hid]
+  size_t dh_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
   int waves = 4;              // waves per workgroup of the per-interval solve

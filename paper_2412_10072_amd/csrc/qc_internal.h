@@ -226,7 +226,9 @@ struct SolveLaunch {
   int* err;
   int waves;                  // waves per workgroup
   int max_int_chan;           // channels of the widest interval
-  int rows_per_step;          // 0: chosen from max_int_chan
+  int rows_per_step;          // 0: the kernel default
+  const double* chisq_ref;    // may be null
+  uint8_t* restarted;         // may be null
 };
 
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_bytes_out);
@@ -244,6 +246,33 @@ struct DelayInitLaunch {
 
 size_t delay_init_lds(int max_chan);
 hipError_t launch_delay_init(const DelayInitLaunch& L, int max_chan, hipStream_t stream);
+
+struct FeatLaunch {
+  VisArgs vis;
+  int vis_is_c128;
+  int n_gt, n_gf;
+  const long long* row_lo;
+  const long long* row_hi;
+  const int* chan_lo;
+  const int* chan_hi;
+  float* feat;                // [n_gt * n_gf][feat_stride]
+  int feat_stride;
+  double* chisq_unit;         // [n_gt * n_gf] or null
+  int ref_ant;                // < 0: raw ratios
+};
+
+hipError_t launch_ws_features(const FeatLaunch& L, int waves, hipStream_t stream);
+hipError_t launch_linear_fwd(const float* x, const float* W, const float* b, float* y, int B, int I, int O,
+                             int relu_in, hipStream_t s);
+hipError_t launch_linear_bwd_w(const float* x, const float* dy, float* gW, float* gb, int B, int I, int O,
+                               int relu_in, hipStream_t s);
+hipError_t launch_linear_bwd_x(const float* dy, const float* W, const float* pre, float* dx, int B, int I, int O,
+                               int relu_mask, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_mse(const float* y, const float* t, float* dy, float* loss, int n, hipStream_t s);
+hipError_t launch_ws_gains(const float* y, int y_stride, int n_int, int n_ant, double2* gains, hipStream_t s);
+hipError_t launch_ws_labels(const double2* gains, int n_int, int n_ant, int ref, float* y, hipStream_t s);
 
 struct OutputLaunch {
   VisArgs vis;

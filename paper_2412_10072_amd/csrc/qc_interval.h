@@ -375,6 +375,8 @@ struct Job {
   double tol;
   int max_iter, damping;
   int* err;
+  const double* chisq_ref;   // per interval: restart from unit gains if chi^2 at the start exceeds it
+  uint8_t* restarted;        // per interval: 1 if that restart happened
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
@@ -485,7 +487,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   const int n_dir = SINGLE ? 1 : V.n_dir;
 
   double chisq_first = 0.0, chisq_last = 0.0;
-  int iters = 0, converged = 0;
+  int iters = 0, converged = 0, restarted = 0;
 
   for (int it = 0;; ++it) {
     for (int i = lane; i < slot_vals; i += 64) {
@@ -665,6 +667,21 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     }
     double chi_now = 0.0;
     for (int w = 0; w < nw; ++w) chi_now += chiw[w];
+    if (it == 0 && J.chisq_ref && !restarted && chi_now > J.chisq_ref[interval]) {
+      // the starting gains fit worse than unit gains: start again from those
+      restarted = 1;
+      for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double v = (KIND != KIND_DELAY && (k == 0 || k == 3)) ? 1.0 : 0.0;
+          gm[i * 4 + k] = make_double2(v, 0.0);
+          gc[i * 4 + k] = cmake<T>((T)v, T(0));
+        }
+      }
+      __syncthreads();
+      it = -1;
+      continue;
+    }
     if (it == 0) chisq_first = chi_now;
     chisq_last = chi_now;
     __syncthreads();
@@ -792,6 +809,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     if (J.converged) J.converged[interval] = (uint8_t)converged;
     if (J.chisq_first) J.chisq_first[interval] = chisq_first;
     if (J.chisq_last) J.chisq_last[interval] = chisq_last;
+    if (J.restarted) J.restarted[interval] = (uint8_t)restarted;
   }
   __syncthreads();   // the LDS may be reused by the workgroup's next interval
 }

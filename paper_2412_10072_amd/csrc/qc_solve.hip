@@ -63,6 +63,8 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   J.max_iter = L.max_iter;
   J.damping = L.damping;
   J.err = L.err;
+  J.chisq_ref = L.chisq_ref;
+  J.restarted = L.restarted;
   solve_interval<KIND, S, T, SINGLE, NG, RPS>(J);
 }
 

@@ -31,7 +31,8 @@ DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
 EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms", "qc_ctx_set_tile",
            "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
-           "qc_batch_destroy", "qc_solve_batch")
+           "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
+           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels")
 BATCH_BUCKETS = 6
 
 
@@ -57,12 +58,12 @@ class QcTerm(C.Structure):
 
 class QcSolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32), ("damping", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("chisq_ref", C.c_void_p)]
 
 
 class QcSolveStats(C.Structure):
     _fields_ = [("iters", C.c_void_p), ("converged", C.c_void_p), ("chisq_first", C.c_void_p),
-                ("chisq_last", C.c_void_p)]
+                ("chisq_last", C.c_void_p), ("restarted", C.c_void_p)]
 
 
 class QcProblem(C.Structure):
@@ -105,6 +106,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_batch_schedule.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
     lib.qc_batch_destroy.argtypes = [C.c_void_p]
     lib.qc_solve_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(QcSolveOpts)]
+    vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
+    lib.qc_ws_features.argtypes = [vp, C.POINTER(QcVis), C.POINTER(QcTerm), vp, vp, i32, vp]
+    lib.qc_mlp_forward.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
+    lib.qc_mlp_backward.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp]
+    lib.qc_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, i32, vp]
+    lib.qc_mse_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.qc_ws_gains.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.qc_ws_labels.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     for name in EXPORTS:
         if name not in ("qc_last_error", "qc_last_kernel_ms", "qc_batch_last_ms"):
             getattr(lib, name).restype = C.c_int32
@@ -230,6 +239,31 @@ def _stream_ptr(stream) -> Optional[int]:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+class _Shape1:
+    n_gt = n_gf = 1
+
+
+def _stats_for(term, dev):
+    shape = (int(term.n_gt), int(term.n_gf))
+    return dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
+                converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
+                chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
+                chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev),
+                restarted=torch.zeros(shape, dtype=torch.uint8, device=dev))
+
+
+def _c_stats(st) -> QcSolveStats:
+    return QcSolveStats(iters=_ptr(st["iters"], torch.int32, "iters"),
+                        converged=_ptr(st["converged"], torch.uint8, "converged"),
+                        chisq_first=_ptr(st["chisq_first"], torch.float64, "chisq_first"),
+                        chisq_last=_ptr(st["chisq_last"], torch.float64, "chisq_last"),
+                        restarted=_ptr(st.get("restarted"), torch.uint8, "restarted"))
+
+
+def _f32(t, name):
+    return _ptr(t, torch.float32, name)
+
+
 class Context:
     """A libqc context on one HIP device."""
 
@@ -268,25 +302,22 @@ class Context:
         return float(self.lib.qc_last_kernel_ms(self.h))
 
     def solve(self, vis, chain, active: int = 0, tol: float = 1e-6, max_iter: int = 100,
-              prec: str = "mixed", damping: str = "auto", stream=None, stats: Optional[dict] = None):
-        """qc_solve_interval: solve chain[active] in place; returns the per-interval stats tensors."""
+              prec: str = "mixed", damping: str = "auto", stream=None, stats: Optional[dict] = None,
+              chisq_ref: Optional[torch.Tensor] = None):
+        """qc_solve_interval: solve chain[active] in place; returns the per-interval stats tensors.
+        chisq_ref (per interval, float64): restart an interval from unit gains when chi^2 at its
+        starting gains exceeds the entry (warm-start fallback)."""
         dev = vis.data.device
         # an out-of-range `active` is passed on: the library rejects it with QC_E_ARG
         term = chain[active] if 0 <= active < len(chain) else None
-        shape = (int(term.n_gt), int(term.n_gf)) if term is not None else (1, 1)
         if stats is None:
-            stats = dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
-                         converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
-                         chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
-                         chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev))
+            stats = _stats_for(term, dev) if term is not None else _stats_for(_Shape1(), dev)
         cv = _c_vis(vis)
         cc = _c_chain(chain)
         opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
-                           damping=DAMPINGS[damping], stream=_stream_ptr(stream))
-        cs = QcSolveStats(iters=_ptr(stats["iters"], torch.int32, "iters"),
-                          converged=_ptr(stats["converged"], torch.uint8, "converged"),
-                          chisq_first=_ptr(stats["chisq_first"], torch.float64, "chisq_first"),
-                          chisq_last=_ptr(stats["chisq_last"], torch.float64, "chisq_last"))
+                           damping=DAMPINGS[damping], stream=_stream_ptr(stream),
+                           chisq_ref=_ptr(chisq_ref, torch.float64, "chisq_ref"))
+        cs = _c_stats(stats)
         self._check(self.lib.qc_solve_interval(self.h, C.byref(cv), cc, len(chain), int(active),
                                                C.byref(opts), C.byref(cs)))
         return stats
@@ -299,14 +330,8 @@ class Context:
         for e in range(n_epoch):
             row = []
             for n, term in enumerate(chain):
-                shape = (int(term.n_gt), int(term.n_gf))
-                st = dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
-                          converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
-                          chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
-                          chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev))
-                c = cstats[e * len(chain) + n]
-                c.iters, c.converged = st["iters"].data_ptr(), st["converged"].data_ptr()
-                c.chisq_first, c.chisq_last = st["chisq_first"].data_ptr(), st["chisq_last"].data_ptr()
+                st = _stats_for(term, dev)
+                cstats[e * len(chain) + n] = _c_stats(st)
                 row.append(st)
             stats.append(row)
         cv = _c_vis(vis)
@@ -323,6 +348,72 @@ class Context:
         cc = _c_chain([term])
         self._check(self.lib.qc_delay_init(self.h, C.byref(cv), cc, int(ref_ant), C.c_void_p(_stream_ptr(stream))))
         return term
+
+    # ---- learned warm start ----------------------------------------------
+
+    def ws_features(self, vis, layout, feat: Optional[torch.Tensor] = None,
+                    chisq_unit: Optional[torch.Tensor] = None, ref_ant: int = -1, stream=None):
+        """qc_ws_features: per-interval features [n_int][n_ant*8] (float32), referenced to
+        ref_ant when >= 0, and, if given, chi^2 at unit gains per interval (float64)."""
+        n_int = int(layout.n_gt) * int(layout.n_gf)
+        if feat is None:
+            feat = torch.empty(n_int, int(vis.n_ant) * 8, dtype=torch.float32, device=vis.data.device)
+        if tuple(feat.shape) != (n_int, int(vis.n_ant) * 8):
+            raise ValueError("feat must be [n_int][n_ant*8]")
+        cv = _c_vis(vis)
+        cc = _c_chain([layout])
+        self._check(self.lib.qc_ws_features(self.h, C.byref(cv), cc, C.c_void_p(_f32(feat, "feat")),
+                                            C.c_void_p(_ptr(chisq_unit, torch.float64, "chisq_unit")),
+                                            int(ref_ant), C.c_void_p(_stream_ptr(stream))))
+        return feat
+
+    def mlp_forward(self, params, x, n_hid: int, n_out: int, y=None, pre=None, stream=None):
+        B, n_in = int(x.shape[0]), int(x.shape[1])
+        dev = x.device
+        y = torch.empty(B, n_out, dtype=torch.float32, device=dev) if y is None else y
+        pre = torch.empty(B, n_hid, dtype=torch.float32, device=dev) if pre is None else pre
+        self._check(self.lib.qc_mlp_forward(self.h, _f32(params, "params"), _f32(x, "x"), B, n_in, n_hid, n_out,
+                                            _f32(y, "y"), _f32(pre, "pre"), C.c_void_p(_stream_ptr(stream))))
+        return y, pre
+
+    def mlp_backward(self, params, x, pre, dy, n_hid: int, n_out: int, grad=None, stream=None):
+        B, n_in = int(x.shape[0]), int(x.shape[1])
+        grad = torch.empty_like(params) if grad is None else grad
+        self._check(self.lib.qc_mlp_backward(self.h, _f32(params, "params"), _f32(x, "x"), _f32(pre, "pre"),
+                                             _f32(dy, "dy"), B, n_in, n_hid, n_out, _f32(grad, "grad"),
+                                             C.c_void_p(_stream_ptr(stream))))
+        return grad
+
+    def adam_step(self, params, grad, m, v, lr: float, b1: float, b2: float, eps: float, step: int, stream=None):
+        self._check(self.lib.qc_adam_step(self.h, _f32(params, "params"), _f32(grad, "grad"), _f32(m, "m"),
+                                          _f32(v, "v"), int(params.numel()), float(lr), float(b1), float(b2),
+                                          float(eps), int(step), C.c_void_p(_stream_ptr(stream))))
+
+    def mse_grad(self, y, t, dy=None, loss=None, stream=None):
+        dy = torch.empty_like(y) if dy is None else dy
+        self._check(self.lib.qc_mse_grad(self.h, _f32(y, "y"), _f32(t, "t"), int(y.numel()), _f32(dy, "dy"),
+                                         C.c_void_p(_ptr(loss, torch.float32, "loss")),
+                                         C.c_void_p(_stream_ptr(stream))))
+        return dy
+
+    def ws_gains(self, y, n_ant: int, gains, stream=None):
+        """qc_ws_gains: network output [n_int][n_ant*4] -> diagonal gains (complex128, in place)."""
+        n_int = int(y.shape[0])
+        if tuple(y.shape) != (n_int, n_ant * 4) or gains.numel() != n_int * n_ant * 4:
+            raise ValueError("y must be [n_int][n_ant*4] and gains [.. n_int ..][n_ant][1][4]")
+        self._check(self.lib.qc_ws_gains(self.h, _f32(y, "y"), n_int, int(n_ant),
+                                         C.c_void_p(_ptr(gains, torch.complex128, "gains")),
+                                         C.c_void_p(_stream_ptr(stream))))
+        return gains
+
+    def ws_labels(self, gains, n_ant: int, ref_ant: int = 0, y=None, stream=None):
+        """qc_ws_labels: solved diagonal gains -> referenced targets [n_int][n_ant*4] (float32)."""
+        n_int = gains.numel() // (n_ant * 4)
+        y = torch.empty(n_int, n_ant * 4, dtype=torch.float32, device=gains.device) if y is None else y
+        self._check(self.lib.qc_ws_labels(self.h, C.c_void_p(_ptr(gains, torch.complex128, "gains")), n_int,
+                                          int(n_ant), int(ref_ant), C.c_void_p(_f32(y, "y")),
+                                          C.c_void_p(_stream_ptr(stream))))
+        return y
 
     def _out_like(self, vis, out):
         if out is None:
@@ -363,14 +454,6 @@ class Context:
         return out
 
 
-def _stats_for(term, dev):
-    shape = (int(term.n_gt), int(term.n_gf))
-    return dict(iters=torch.zeros(shape, dtype=torch.int32, device=dev),
-                converged=torch.zeros(shape, dtype=torch.uint8, device=dev),
-                chisq_first=torch.zeros(shape, dtype=torch.float64, device=dev),
-                chisq_last=torch.zeros(shape, dtype=torch.float64, device=dev))
-
-
 class Batch:
     """A qc_batch plan: many independent single-term problems solved by one
     graph launch (qc_batch_create / qc_batch_tune / qc_batch_run).
@@ -391,9 +474,7 @@ class Batch:
             self.stats.append(st)
             arr[i].vis = _c_vis(vis)
             arr[i].term = _c_chain([term])[0]
-            arr[i].stats = QcSolveStats(iters=st["iters"].data_ptr(), converged=st["converged"].data_ptr(),
-                                        chisq_first=st["chisq_first"].data_ptr(),
-                                        chisq_last=st["chisq_last"].data_ptr())
+            arr[i].stats = _c_stats(st)
         self._arr = arr
         opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
                            damping=DAMPINGS[damping], stream=_stream_ptr(stream))

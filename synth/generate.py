@@ -294,14 +294,16 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
                    t_int: int = 1, f_int: int = 64, n_src: int = 20, sigma: float = 0.05,
                    flag_frac: float = 0.10, leakage_var: float = 0.05, time_block: int = 4,
                    kind: str = "c2x2", dtype="c64", cfg_id: int = 2, seed_block: int = 0,
-                   n_wcorr: int = 4, row_drop: float = 0.0) -> Problem:
+                   n_wcorr: int = 4, row_drop: float = 0.0, gain_mode: str = "smooth") -> Problem:
     """MeerKAT-shaped full-Jones solve: 64 antennas in an 8 km array, 600 x 8 s times,
     1024 channels over 856-1712 MHz, 20 point sources (log-uniform 0.01-1 Jy within 1 deg),
     complex-2x2 truth gains smooth in time and frequency (diagonal (1 + 0.1 P) e^{i pi P},
     leakage CN(0, 0.05) (1 + 0.1 P)), 10% random flags, noise sigma 0.05, weights 1/sigma^2,
     solution interval 1 time x 64 channels.  Generated block by block in device memory.
     row_drop > 0 removes that fraction of rows at random (whole-row flags compacted out,
-    rows stay time-ordered)."""
+    rows stay time-ordered).
+    gain_mode="random": independent diagonal truth gains per interval, amp U(0.8, 1.2),
+    phase U(-pi, pi), antenna 0 phase 0 (the warm-start training and evaluation data)."""
     g0 = rng(device, 2412, cfg_id, 2 * seed_block)
     ant1, ant2, row_time = row_layout(n_time, n_ant)
     nbl = n_ant * (n_ant - 1) // 2
@@ -319,8 +321,13 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
     P = P.permute(2, 3, 0, 1)                                    # [gt][gf][ant][8]
     tg = torch.zeros(term.n_gt, term.n_gf, n_ant, 1, 4, dtype=torch.complex128, device=device)
     for k, c in enumerate((0, 3)):
-        amp = 1.0 + 0.1 * P[..., 2 * k]
-        ph = math.pi * P[..., 2 * k + 1]
+        if gain_mode == "random":
+            amp = uniform(g0, (term.n_gt, term.n_gf, n_ant), 0.8, 1.2, device)
+            ph = uniform(g0, (term.n_gt, term.n_gf, n_ant), -math.pi, math.pi, device)
+            ph[:, :, 0] = 0.0
+        else:
+            amp = 1.0 + 0.1 * P[..., 2 * k]
+            ph = math.pi * P[..., 2 * k + 1]
         tg[:, :, :, 0, c] = amp * torch.polar(torch.ones_like(ph), ph)
     if kind == "c2x2":
         z = cnormal(g0, (n_ant, 2), math.sqrt(leakage_var / 2.0), device)

@@ -41,8 +41,9 @@ def test_binding_struct_layout_matches_header():
     assert qc.QcVis.data.offset == 32
     assert C.sizeof(qc.QcTerm) == 24 + 6 * 8
     assert qc.QcTerm.t_map.offset == 24
-    assert C.sizeof(qc.QcSolveOpts) == 8 + 3 * 4 + 4 + 8
-    assert C.sizeof(qc.QcSolveStats) == 4 * 8
+    assert C.sizeof(qc.QcSolveOpts) == 8 + 3 * 4 + 4 + 8 + 8
+    assert C.sizeof(qc.QcSolveStats) == 5 * 8
+    assert C.sizeof(qc.QcProblem) == C.sizeof(qc.QcVis) + C.sizeof(qc.QcTerm) + C.sizeof(qc.QcSolveStats)
 
 
 def test_context_without_device_fails_cleanly():

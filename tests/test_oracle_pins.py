@@ -506,3 +506,25 @@ def test_chain_generator_agrees_with_oracle_model():
     vis = to_numpy_vis(p.vis)
     R = outputs.residual(vis, p.truth)
     assert np.abs(R).max() < 1e-12 * np.abs(vis.data).max()
+
+
+def test_reference_features_gauge():
+    """Referenced features do not change when every gain takes a common phase
+    per hand (the gauge): with data from gains g and from g e^{i phi} the
+    referenced ratios agree."""
+    rng = np.random.default_rng(79)
+    n_ant = 4
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=3, n_dir=1, polarised=False)
+    truth = [make_term(rng, "diag", 2, 3, n_ant)]
+    truth[0].t_map = np.zeros(2, np.int32); truth[0].f_map = np.zeros(3, np.int32)
+    truth[0].gains = truth[0].gains[:1, :1]
+    truth[0].n_gt = truth[0].n_gf = 1
+    vis.data = forward_data(vis, truth)
+    f1 = warmstart.reference_features(warmstart.features(vis, truth[0], 0, 0), n_ant)
+    rot = truth[0].copy(gains=truth[0].gains * np.exp(1j * np.array([0.7, 0, 0, -1.9])))
+    v2 = vis.copy(data=forward_data(vis, [rot]))
+    f2 = warmstart.reference_features(warmstart.features(v2, rot, 0, 0), n_ant)
+    assert np.abs(f1 - f2).max() < 1e-12
+    # the reference antenna's own XX / YY ratios become real and non-negative
+    z = f1.reshape(n_ant, 4, 2)
+    assert abs(z[0, 0, 1]) < 1e-15 and z[0, 0, 0] >= 0 and abs(z[0, 3, 1]) < 1e-15
