@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -249,6 +250,63 @@ def leg_warm(ctx, dev, n_sets: int = 5, n_time_train: int = 625, epochs: int = 3
     return out
 
 
+def leg_chain(ctx, dev, n_epoch: int = 2):
+    """Jones chain + directions: 64 antennas, 300 times x 512 channels, 4 clusters of 5
+    sources (one model direction each); chain K (delay, 60 times x band) . B (bandpass,
+    all times x 1 channel) . G (gain, 1 time x band) . dE (direction-dependent, 16 times x
+    128 channels); Fourier-peak delay start, then n_epoch epochs over the chain to tol 1e-6
+    (MIXED), then the residual."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+    from synth.generate import config_chain
+
+    t0 = time.perf_counter()
+    p = config_chain(device=dev)
+    torch.cuda.synchronize()
+    vis = p.vis
+    n_samples = int(vis.data.shape[0]) * int(vis.data.shape[1])
+    log(f"chain: generated {n_samples / 1e9:.3f}e9 samples x {vis.model.shape[2]} directions in "
+        f"{time.perf_counter() - t0:.1f} s")
+    chain = [qc.device_term(t, dev) for t in p.chain]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ctx.delay_init(vis, chain[0], ref_ant=0, stream=stream)
+    torch.cuda.synchronize()
+    t_delay = time.perf_counter() - ts
+    log(f"chain: delay initial estimate {1e3 * t_delay:.1f} ms")
+    terms = []
+    for e in range(n_epoch):
+        for n, t in enumerate(chain):
+            t1 = time.perf_counter()
+            st = ctx.solve(vis, chain, n, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
+            torch.cuda.synchronize()
+            terms.append(dict(epoch=e, term=t.name, intervals=int(t.n_gt * t.n_gf),
+                              split_parts=int(ctx.last_split_parts()),
+                              ms=1e3 * (time.perf_counter() - t1),
+                              mean_iterations=float(st["iters"].float().mean().item()),
+                              converged=float(st["converged"].float().mean().item())))
+            d = terms[-1]
+            log(f"chain: epoch {e} term {d['term']}: {d['ms']:.0f} ms, {d['intervals']} intervals, "
+                f"parts {d['split_parts']}, mean iterations {d['mean_iterations']:.2f}, "
+                f"converged {100 * d['converged']:.1f}%")
+    t2 = time.perf_counter()
+    resid = ctx.residual(vis, chain, stream=stream)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - ts
+    use = (vis.flag == 0)
+    rms = float(torch.sqrt((resid.abs() ** 2).sum(-1)[use].mean() / 4).item())
+    sigma = float(p.meta["sigma"])
+    out = dict(samples=n_samples, directions=int(vis.model.shape[2]), delay_init_ms=1e3 * t_delay,
+               terms=terms, residual_ms=1e3 * (time.perf_counter() - t2), total_s=t_total,
+               vis_per_s=n_samples / t_total, residual_rms=rms, noise_rms=sigma * math.sqrt(2))
+    log(f"chain: delay init {1e3 * t_delay:.1f} ms; " + "; ".join(
+        f"{d['term']}{d['epoch']} {d['ms']:.0f} ms it {d['mean_iterations']:.1f} parts {d['split_parts']}"
+        for d in terms) + f"; total {t_total:.2f} s; residual rms {rms:.4f} (noise {sigma * math.sqrt(2):.4f})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,7 +314,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="batch,warm", help="comma list of extra legs: batch, warm (or none)")
+    ap.add_argument("--legs", default="batch,warm,chain",
+                    help="comma list of extra legs: batch, warm, chain (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -384,6 +443,14 @@ def main():
         except Exception as e:   # report, keep the main measurement
             out["legs"]["warm"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"warm leg failed: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if "chain" in legs:
+        try:
+            out["legs"]["chain"] = leg_chain(ctx, dev)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["chain"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"chain leg failed: {e}")
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)

@@ -105,6 +105,15 @@ double      qc_last_kernel_ms(qc_ctx* ctx);
  * wavefront step (1, 2, 4; 0 = 4 rows of 16 lanes).
  * Multi-row steps apply to single-term, single-direction chains only. */
 qc_status   qc_ctx_set_tile(qc_ctx* ctx, int32_t waves, int32_t rows_per_step);
+/* Schedule of qc_solve_interval: parts = 0 chooses automatically (a term with
+ * fewer intervals than twice the compute units, of >= 2^20 samples each, is
+ * split), 1 never splits (one workgroup runs each interval to the end),
+ * > 1 cuts every interval's rows into that many parts streamed by separate
+ * workgroups whose FP64 blocks are summed in a fixed order before each update
+ * (the host then waits on the device once per iteration). */
+qc_status   qc_ctx_set_split(qc_ctx* ctx, int32_t parts);
+/* Parts per interval of the last qc_solve_interval (1 = not split). */
+int32_t     qc_ctx_last_split(const qc_ctx* ctx);
 
 /* One visibility set (paper Section 2.2; data model of Section 4.1). */
 typedef struct {

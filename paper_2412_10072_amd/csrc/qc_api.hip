@@ -3,6 +3,7 @@
 // ranges) and the public entry points declared in include/qc.h.
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -249,6 +250,8 @@ qc_status qc_ctx_create(int32_t device, qc_ctx** out) {
     delete c;
     return QC_E_NOMEM;
   }
+  hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device);
+  if (c->n_cu <= 0) c->n_cu = 256;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     hipFree(c->d_err);
     delete c;
@@ -270,6 +273,10 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_chlo);
   hipFree(ctx->d_chhi);
   hipFree(ctx->d_dh);
+  hipFree(ctx->d_partials);
+  hipFree(ctx->d_passes);
+  hipFree(ctx->d_done);
+  hipFree(ctx->d_active);
   hipEventDestroy(ctx->ev0);
   hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -348,9 +355,54 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   L.waves = ctx->waves;
   L.max_int_chan = ctx->max_int_chan;
   L.rows_per_step = ctx->rows_per_step;
-  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  // schedule: fused (one workgroup per interval) unless the term has few, large
+  // intervals, which are then cut into parts streamed by separate workgroups
+  const int n_int = ta.n_gt * ta.n_gf;
+  const double avg_samples = n_int > 0 ? (double)vis->n_row * vis->n_chan / n_int : 0.0;
+  int parts = 1;
+  if (ctx->split_parts > 1) {
+    parts = ctx->split_parts;
+  } else if (ctx->split_parts == 0 && !opts->chisq_ref && n_int > 0 && n_int < 2 * ctx->n_cu &&
+             avg_samples >= (double)(1 << 20)) {
+    const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
+    parts = (int)std::ceil(4.0 * ctx->n_cu / n_int);
+    parts = std::max(2, std::min(parts, (int)std::max(1.0, rows_per_int / 64.0)));
+  }
+  if (parts > 1 && opts->chisq_ref)
+    return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take chisq_ref");
+  ctx->last_split_parts = parts;
   size_t lds = 0;
-  hipError_t e = launch_solve(L, s, &lds);
+  hipError_t e = hipSuccess;
+  if (parts <= 1) {
+    HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+    e = launch_solve(L, nullptr, s, &lds);
+  } else {
+    const int nv = ta.type == QC_TERM_DIAGONAL ? 6 : (ta.type == QC_TERM_COMPLEX2X2 ? 16 : 4);
+    const int ng = ta.n_gdir == 1 ? 1 : 4;
+    const size_t stride = (size_t)vis->n_ant * ng * nv + 1;
+    HIP_TRY(ctx, grow(ctx->d_partials, ctx->partials_cap, stride * (size_t)n_int * parts));
+    HIP_TRY(ctx, grow(ctx->d_passes, ctx->passes_cap, (size_t)n_int));
+    HIP_TRY(ctx, grow(ctx->d_done, ctx->done_cap, (size_t)n_int));
+    HIP_TRY(ctx, grow(ctx->d_active, ctx->active_cap, 1));
+    SplitLaunch P;
+    P.n_part = parts;
+    P.partials = ctx->d_partials;
+    P.state.passes = ctx->d_passes;
+    P.state.done = ctx->d_done;
+    P.state.n_active = ctx->d_active;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+    P.phase = 0;
+    e = launch_solve(L, &P, s, &lds);
+    P.phase = 1;
+    for (int k = 0; k <= opts->max_iter && e == hipSuccess; ++k) {
+      e = launch_solve(L, &P, s, &lds);
+      if (e != hipSuccess) break;
+      int active = 0;
+      HIP_TRY(ctx, hipMemcpyAsync(&active, ctx->d_active, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      if (active <= 0) break;
+    }
+  }
   if (e != hipSuccess) {
     ctx->timed = false;
     if (lds > 160 * 1024)
@@ -359,6 +411,15 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   }
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
   ctx->timed = true;
+  return QC_OK;
+}
+
+int32_t qc_ctx_last_split(const qc_ctx* ctx) { return ctx ? ctx->last_split_parts : -1; }
+
+qc_status qc_ctx_set_split(qc_ctx* ctx, int32_t parts) {
+  if (!ctx) return QC_E_ARG;
+  if (parts < 0) return fail(ctx, QC_E_ARG, "parts must be >= 0");
+  ctx->split_parts = parts;
   return QC_OK;
 }
 

@@ -36,6 +36,17 @@ struct qc_ctx {
   bool timed = false;
   int waves = 4;              // waves per workgroup of the per-interval solve
   int rows_per_step = 0;      // 0: the kernel default
+  int split_parts = 0;        // 0: automatic, 1: never split, > 1: parts per interval
+  int n_cu = 0;               // compute units of the device
+  double* d_partials = nullptr;
+  size_t partials_cap = 0;
+  int* d_passes = nullptr;
+  size_t passes_cap = 0;
+  uint8_t* d_done = nullptr;
+  size_t done_cap = 0;
+  int* d_active = nullptr;
+  size_t active_cap = 0;
+  int last_split_parts = 1;   // parts per interval of the last solve (1 = fused)
 };
 
 namespace qc {

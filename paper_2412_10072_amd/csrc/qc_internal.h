@@ -231,7 +231,24 @@ struct SolveLaunch {
   uint8_t* restarted;         // may be null
 };
 
-hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_bytes_out);
+// Split schedule (see qc_solve.hip): per-interval iteration state in device
+// memory; phase 0 resets it, phase 1 runs one pass + update over every
+// active interval.
+struct SplitState {
+  int* passes;                // [n_int] passes accumulated so far
+  uint8_t* done;              // [n_int]
+  int* n_active;              // intervals not done
+};
+
+struct SplitLaunch {
+  int phase;
+  int n_part;                 // parts per interval
+  double* partials;           // [n_int][n_part][slot values + 1]
+  SplitState state;
+};
+
+// P == nullptr: the fused schedule (one workgroup runs an interval to the end).
+hipError_t launch_solve(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_bytes_out);
 
 struct DelayInitLaunch {
   VisArgs vis;

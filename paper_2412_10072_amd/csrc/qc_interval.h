@@ -134,33 +134,42 @@ struct ReduceScatterF32 {
 
 // Reduce NVP values across each segment of LPR lanes (one row of the step)
 // and add value k (< NVAL) into that segment's LDS slot at byte offset s_off
-// (and its compensation slot at c_off when KAHAN).  s_off, c_off and valid
-// are uniform within a segment.  Segments may target the same antenna, so
-// their read-modify-writes run one segment after the other.  v is clobbered.
+// (and its compensation slot at c_off when KAHAN).  When NVP > LPR every lane
+// ends holding NVP / LPR consecutive values.  s_off, c_off and valid are
+// uniform within a segment.  Segments may target the same antenna, so their
+// read-modify-writes run one segment after the other.  v is clobbered.
 template <int NVP, int NVAL, bool KAHAN, int LPR, typename A>
 __device__ __forceinline__ void wave_flush(A* v, int lane, unsigned s_off, unsigned c_off, bool valid) {
-  static_assert(NVP <= LPR, "more values than lanes in a segment");
   int idx = 0;
-  if constexpr (sizeof(A) == 4) ReduceScatterF32<NVP, LPR / 2>::run(v, lane, idx);
-  else ReduceScatter<NVP, LPR / 2, A>::run(v, lane, idx);
-  constexpr int GROUP = LPR / NVP;
+  if constexpr (LPR > 1) {
+    if constexpr (sizeof(A) == 4) ReduceScatterF32<NVP, LPR / 2>::run(v, lane, idx);
+    else ReduceScatter<NVP, LPR / 2, A>::run(v, lane, idx);
+  }
+  constexpr int PER = NVP > LPR ? NVP / LPR : 1;       // values held per lane
+  constexpr int GROUP = NVP < LPR ? LPR / NVP : 1;     // lanes holding the same values
   constexpr int SEGS = 64 / LPR;
-  const bool owner = valid && (lane & (GROUP - 1)) == 0 && idx < NVAL;
-  const A x = v[0];
+  const bool owner = valid && (lane & (GROUP - 1)) == 0;
 #pragma unroll
   for (int g = 0; g < SEGS; ++g) {
     if (owner && (SEGS == 1 || lane / LPR == g)) {
-      A* ps = lds_at<A>(s_off) + idx;
-      if constexpr (KAHAN) {
-        A* pc = lds_at<A>(c_off) + idx;
-        const A s = *ps;
-        const A c = *pc;
-        const A y = x - c;
-        const A t = s + y;
-        *pc = (t - s) - y;
-        *ps = t;
-      } else {
-        *ps += x;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int k = idx * PER + j;
+        if (k < NVAL) {
+          const A x = v[j];
+          A* ps = lds_at<A>(s_off) + k;
+          if constexpr (KAHAN) {
+            A* pc = lds_at<A>(c_off) + k;
+            const A s = *ps;
+            const A c = *pc;
+            const A y = x - c;
+            const A t = s + y;
+            *pc = (t - s) - y;
+            *ps = t;
+          } else {
+            *ps += x;
+          }
+        }
       }
     }
   }
@@ -377,6 +386,7 @@ struct Job {
   int* err;
   const double* chisq_ref;   // per interval: restart from unit gains if chi^2 at the start exceeds it
   uint8_t* restarted;        // per interval: 1 if that restart happened
+  double* partial;           // pass-only mode: [slot values + 1] FP64 blocks and chi^2 of these rows
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
@@ -390,13 +400,123 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw) {
   return b + sizeof(T) * n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1);
 }
 
+// One FP64 block solve per (antenna, gain direction) of an interval from its
+// accumulated blocks `tot`, the damped update of the LDS gains, and the
+// convergence test over the interval (uniform over the workgroup).
+template <int KIND, typename T, int NG>
+__device__ __forceinline__ bool update_and_test(const double* tot, double2* gm, cx<T>* gc, int* gfl, double* red,
+                                                int* ctl, int n_ant, int n_gdir, int k_upd, int damping,
+                                                double nu_max, double tol, int* err) {
+  constexpr int NV = KindInfo<KIND>::NV;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+const double alpha = step_length(damping, k_upd);
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+    const int ant = i / n_gdir, gd = i - ant * n_gdir;
+    const int slot = ant * NG + gd;
+    const double* h = tot + (size_t)slot * NV;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) finite = finite && isfinite(h[k]);
+    bool ok = finite;
+    if (!finite) atomicOr(err, ERR_NONFINITE);
+    if constexpr (KIND == KIND_C2X2) {
+      const double dmax = fmax(fmax(h[0], h[1]), fmax(h[4], h[5]));
+      c64d x00 = {0, 0}, x01 = {0, 0}, x10 = {0, 0}, x11 = {0, 0};
+      ok = ok && isfinite(dmax) && dmax > 0.0;
+      ok = ok && chol2(h[0], h[1], h[2], h[3], {h[8], h[9]}, {h[10], h[11]}, dmax, x00, x01);
+      ok = ok && chol2(h[4], h[5], h[6], h[7], {h[12], h[13]}, {h[14], h[15]}, dmax, x10, x11);
+      if (ok) {
+        const c64d dx[4] = {x00, x01, x10, x11};
+        double2* g = gm + slot * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
+          const double2 xn = make_double2(g[k].x + sr, g[k].y + si);
+          g[k] = xn;
+          gc[slot * 4 + k] = cmake<T>((T)xn.x, (T)xn.y);
+          num += sr * sr + si * si;
+          den += xn.x * xn.x + xn.y * xn.y;
+        }
+      }
+    } else if constexpr (KIND == KIND_DIAG) {
+      const double dmax = fmax(h[0], h[1]);
+      c64d x0 = {0, 0}, x1 = {0, 0};
+      ok = ok && isfinite(dmax) && dmax > 0.0;
+      ok = ok && chol_diag(h[0], {h[2], h[3]}, dmax, x0);
+      ok = ok && chol_diag(h[1], {h[4], h[5]}, dmax, x1);
+      if (ok) {
+        const c64d dx[2] = {x0, x1};
+        double2* g = gm + slot * 4;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int e = k ? 3 : 0;
+          const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
+          const double2 xn = make_double2(g[e].x + sr, g[e].y + si);
+          g[e] = xn;
+          gc[slot * 4 + e] = cmake<T>((T)xn.x, (T)xn.y);
+          num += sr * sr + si * si;
+          den += xn.x * xn.x + xn.y * xn.y;
+        }
+      }
+    } else {
+      const double dmax = fmax(h[0], h[1]);
+      ok = ok && isfinite(dmax) && dmax > 0.0;
+      ok = ok && (h[0] > PIVOT_REL * dmax) && (h[1] > PIVOT_REL * dmax);
+      if (ok) {
+        const double l0 = sqrt(h[0]), l1 = sqrt(h[1]);
+        const double d0 = alpha * ((h[2] / l0) / l0);
+        const double d1 = alpha * ((h[3] / l1) / l1);
+        double2* g = gm + slot * 4;
+        g[0] = make_double2(g[0].x + d0, g[0].y + d1);
+        num = fmax(num, TWO_PI * nu_max * fmax(fabs(d0), fabs(d1)));
+      }
+    }
+    gfl[slot] = ok ? 0 : 1;
+  }
+  // ---- convergence over the interval ----
+  {
+    double a = num, b = den;
+    if constexpr (KIND == KIND_DELAY) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+    } else {
+      a = wave_sum<double>(a);
+      b = wave_sum<double>(b);
+    }
+    if (lane == 0) {
+      red[2 * wave + 0] = a;
+      red[2 * wave + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      if constexpr (KIND == KIND_DELAY) a = fmax(a, red[2 * w]);
+      else a += red[2 * w];
+      b += red[2 * w + 1];
+    }
+    double ratio;
+    if constexpr (KIND == KIND_DELAY) ratio = a;
+    else ratio = (a == 0.0) ? 0.0 : (b > 0.0 ? sqrt(a / b) : INFINITY);
+    ctl[0] = (ratio <= tol) ? 1 : 0;
+  }
+  __syncthreads();
+  return ctl[0] != 0;
+}
+
 // SINGLE: the chain is the active term alone, one direction, one gain
 //         direction (the plain full-Jones / diagonal solve).
 // NG:     gain directions of the active term held per antenna (1 or 4).
 // RPS:    rows per wavefront step: lanes are RPS segments of 64/RPS
 //         consecutive channels of consecutive rows (narrow intervals keep
 //         every lane busy).
-template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+// PASS_ONLY: one streaming pass over rows [r_lo, r_hi) at the gains in
+//         J.gains; the FP64 blocks and chi^2 go to J.partial (split schedule).
+template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS, bool PASS_ONLY = false>
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool KAHAN = (sizeof(T) == 4);
@@ -406,8 +526,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   constexpr int LPR = 64 / RPS;              // lanes per row
   constexpr bool PACC = (NG == 1);           // keep antenna-p sums in registers over a p-run
   static_assert(NVP <= 64, "too many values per antenna");
-  static_assert(SINGLE || RPS == 1, "multi-row steps need the single-term kernel");
-  static_assert(NVP <= LPR, "too many values for a row segment");
+  static_assert(SINGLE || RPS == 1 || NG == 1, "multi-row steps of the general kernel take one gain direction");
 
   const VisArgs& V = *J.V;
   const TermArgs& TA = *J.TA;
@@ -667,6 +786,12 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     }
     double chi_now = 0.0;
     for (int w = 0; w < nw; ++w) chi_now += chiw[w];
+    if constexpr (PASS_ONLY) {
+      for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) J.partial[i] = tot[i];
+      if (threadIdx.x == 0) J.partial[slot_vals] = chi_now;
+      __syncthreads();
+      return;
+    }
     if (it == 0 && J.chisq_ref && !restarted && chi_now > J.chisq_ref[interval]) {
       // the starting gains fit worse than unit gains: start again from those
       restarted = 1;
@@ -686,104 +811,11 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     chisq_last = chi_now;
     __syncthreads();
     if (it >= J.max_iter) break;
-    // ---- per-block FP64 solve and damped update ----
     const int k_upd = it + 1;
-    const double alpha = step_length(J.damping, k_upd);
-    double num = 0.0, den = 0.0;
-    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
-      const int ant = i / n_gdir, gd = i - ant * n_gdir;
-      const int slot = ant * NG + gd;
-      const double* h = tot + (size_t)slot * NV;
-      bool finite = true;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) finite = finite && isfinite(h[k]);
-      bool ok = finite;
-      if (!finite) atomicOr(J.err, ERR_NONFINITE);
-      if constexpr (KIND == KIND_C2X2) {
-        const double dmax = fmax(fmax(h[0], h[1]), fmax(h[4], h[5]));
-        c64d x00 = {0, 0}, x01 = {0, 0}, x10 = {0, 0}, x11 = {0, 0};
-        ok = ok && isfinite(dmax) && dmax > 0.0;
-        ok = ok && chol2(h[0], h[1], h[2], h[3], {h[8], h[9]}, {h[10], h[11]}, dmax, x00, x01);
-        ok = ok && chol2(h[4], h[5], h[6], h[7], {h[12], h[13]}, {h[14], h[15]}, dmax, x10, x11);
-        if (ok) {
-          const c64d dx[4] = {x00, x01, x10, x11};
-          double2* g = gm + slot * 4;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
-            const double2 xn = make_double2(g[k].x + sr, g[k].y + si);
-            g[k] = xn;
-            gc[slot * 4 + k] = cmake<T>((T)xn.x, (T)xn.y);
-            num += sr * sr + si * si;
-            den += xn.x * xn.x + xn.y * xn.y;
-          }
-        }
-      } else if constexpr (KIND == KIND_DIAG) {
-        const double dmax = fmax(h[0], h[1]);
-        c64d x0 = {0, 0}, x1 = {0, 0};
-        ok = ok && isfinite(dmax) && dmax > 0.0;
-        ok = ok && chol_diag(h[0], {h[2], h[3]}, dmax, x0);
-        ok = ok && chol_diag(h[1], {h[4], h[5]}, dmax, x1);
-        if (ok) {
-          const c64d dx[2] = {x0, x1};
-          double2* g = gm + slot * 4;
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const int e = k ? 3 : 0;
-            const double sr = alpha * dx[k].re, si = alpha * dx[k].im;
-            const double2 xn = make_double2(g[e].x + sr, g[e].y + si);
-            g[e] = xn;
-            gc[slot * 4 + e] = cmake<T>((T)xn.x, (T)xn.y);
-            num += sr * sr + si * si;
-            den += xn.x * xn.x + xn.y * xn.y;
-          }
-        }
-      } else {
-        const double dmax = fmax(h[0], h[1]);
-        ok = ok && isfinite(dmax) && dmax > 0.0;
-        ok = ok && (h[0] > PIVOT_REL * dmax) && (h[1] > PIVOT_REL * dmax);
-        if (ok) {
-          const double l0 = sqrt(h[0]), l1 = sqrt(h[1]);
-          const double d0 = alpha * ((h[2] / l0) / l0);
-          const double d1 = alpha * ((h[3] / l1) / l1);
-          double2* g = gm + slot * 4;
-          g[0] = make_double2(g[0].x + d0, g[0].y + d1);
-          num = fmax(num, TWO_PI * nu_max * fmax(fabs(d0), fabs(d1)));
-        }
-      }
-      gfl[slot] = ok ? 0 : 1;
-    }
-    // ---- convergence over the interval ----
-    {
-      double a = num, b = den;
-      if constexpr (KIND == KIND_DELAY) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
-      } else {
-        a = wave_sum<double>(a);
-        b = wave_sum<double>(b);
-      }
-      if (lane == 0) {
-        red[2 * wave + 0] = a;
-        red[2 * wave + 1] = b;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < nw; ++w) {
-        if constexpr (KIND == KIND_DELAY) a = fmax(a, red[2 * w]);
-        else a += red[2 * w];
-        b += red[2 * w + 1];
-      }
-      double ratio;
-      if constexpr (KIND == KIND_DELAY) ratio = a;
-      else ratio = (a == 0.0) ? 0.0 : (b > 0.0 ? sqrt(a / b) : INFINITY);
-      ctl[0] = (ratio <= J.tol) ? 1 : 0;
-    }
-    __syncthreads();
+    const bool conv = update_and_test<KIND, T, NG>(tot, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd, J.damping,
+                                                   nu_max, J.tol, J.err);
     iters = k_upd;
-    if (ctl[0]) {
+    if (conv) {
       converged = 1;
       break;
     }
@@ -812,6 +844,107 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     if (J.restarted) J.restarted[interval] = (uint8_t)restarted;
   }
   __syncthreads();   // the LDS may be reused by the workgroup's next interval
+}
+
+// ---------------------------------------------------------------------------
+// split schedule: the update half of one iteration of one interval
+// ---------------------------------------------------------------------------
+
+// Sums the interval's n_part partial blocks in a fixed order, then does what
+// the fused loop does after a pass: chi^2 bookkeeping, the FP64 block solves,
+// the damped update of the gains in device memory, the convergence test.
+template <int KIND, typename T, int NG>
+__device__ __forceinline__ void split_update(const Job& J, const double* partials, int n_part, const SplitState& St) {
+  constexpr int NV = KindInfo<KIND>::NV;
+  const VisArgs& V = *J.V;
+  const TermArgs& TA = *J.TA;
+  const int n_ant = V.n_ant;
+  const int n_gdir = TA.n_gdir;
+  const int interval = J.gt * J.n_gf + J.gf;
+  if (St.done[interval]) return;
+  const int n_slots = n_ant * NG;
+  const int slot_vals = n_slots * NV;
+  unsigned char* lp = qc_lds;
+  double* tot = reinterpret_cast<double*>(lp);            lp += sizeof(double) * slot_vals;
+  double2* gm = reinterpret_cast<double2*>(lp);           lp += sizeof(double2) * n_slots * 4;
+  double* red = reinterpret_cast<double*>(lp);            lp += sizeof(double) * 2 * 16;
+  double* chiw = reinterpret_cast<double*>(lp);           lp += sizeof(double) * 16;
+  cx<T>* gc = reinterpret_cast<cx<T>*>(lp);               lp += sizeof(cx<T>) * n_slots * 4;
+  int* gfl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * n_slots;
+  int* ctl = reinterpret_cast<int*>(lp);
+  const size_t gbase = ((size_t)J.gt * J.n_gf + J.gf) * n_ant;
+  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+    const int ant = i / n_gdir, gd = i - ant * n_gdir;
+    const int slot = ant * NG + gd;
+    const size_t src = (gbase + ant) * n_gdir + gd;
+    if constexpr (KIND == KIND_DELAY) {
+      gm[slot * 4 + 0] = make_double2(J.params[2 * src + 0], J.params[2 * src + 1]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double2 g = J.gains[4 * src + k];
+        gm[slot * 4 + k] = g;
+        gc[slot * 4 + k] = cmake<T>((T)g.x, (T)g.y);
+      }
+    }
+    gfl[slot] = 0;
+  }
+  const size_t stride = (size_t)slot_vals + 1;
+  for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) {
+    double sum = 0.0;
+    for (int k = 0; k < n_part; ++k) sum += partials[k * stride + i];
+    tot[i] = sum;
+  }
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int k = 0; k < n_part; ++k) c += partials[k * stride + slot_vals];
+    chiw[0] = c;
+    double m = 0.0;
+    if (KIND == KIND_DELAY)
+      for (int c2 = J.c_lo; c2 < J.c_hi; ++c2) m = fmax(m, V.freq[c2]);
+    red[0] = m;
+  }
+  __syncthreads();
+  const double chi_now = chiw[0];
+  const double nu_max = red[0];
+  const int pass = St.passes[interval];
+  if (threadIdx.x == 0) {
+    if (pass == 0 && J.chisq_first) J.chisq_first[interval] = chi_now;
+    if (J.chisq_last) J.chisq_last[interval] = chi_now;
+  }
+  __syncthreads();
+  bool finish = false, conv = false;
+  if (pass >= J.max_iter) {
+    finish = true;
+  } else {
+    const int k_upd = pass + 1;
+    conv = update_and_test<KIND, T, NG>(tot, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd, J.damping, nu_max, J.tol,
+                                        J.err);
+    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+      const int ant = i / n_gdir, gd = i - ant * n_gdir;
+      const int slot = ant * NG + gd;
+      const size_t dst = (gbase + ant) * n_gdir + gd;
+      if constexpr (KIND == KIND_DELAY) {
+        J.params[2 * dst + 0] = gm[slot * 4].x;
+        J.params[2 * dst + 1] = gm[slot * 4].y;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
+      }
+      if (J.gflags) J.gflags[dst] = (int8_t)gfl[slot];
+    }
+    finish = conv || k_upd >= J.max_iter;
+  }
+  if (threadIdx.x == 0) {
+    const int iters = pass >= J.max_iter ? pass : pass + 1;
+    St.passes[interval] = pass + 1;
+    if (J.iters) J.iters[interval] = iters;
+    if (J.converged) J.converged[interval] = conv ? 1 : 0;
+    if (finish) {
+      St.done[interval] = 1;
+      atomicSub(St.n_active, 1);
+    }
+  }
 }
 
 }  // namespace qc

@@ -68,6 +68,130 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   solve_interval<KIND, S, T, SINGLE, NG, RPS>(J);
 }
 
+// Split schedule for intervals too large for one workgroup: every interval's
+// rows are cut into n_part parts; one workgroup per part streams its rows at
+// the current gains and writes FP64 blocks; one workgroup per interval then
+// sums the parts in a fixed order and updates (split_update).  The host
+// repeats pass + update until no interval is active.
+template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+__global__ void __launch_bounds__(512) k_split_pass(SolveLaunch L, int n_part, double* partials,
+                                                    const uint8_t* done) {
+  const TermArgs& TA = L.chain.t[L.chain.active];
+  const int n_gf = TA.n_gf;
+  const int interval = blockIdx.x / n_part;
+  const int part = blockIdx.x - interval * n_part;
+  if (done[interval]) return;
+  const int gt = interval / n_gf;
+  const int gf = interval - gt * n_gf;
+  const long long lo = L.row_lo[gt], n = L.row_hi[gt] - lo;
+  const size_t stride = (size_t)L.vis.n_ant * NG * KindInfo<KIND>::NV + 1;
+  Job J;
+  J.V = &L.vis;
+  J.CH = &L.chain;
+  J.TA = &TA;
+  J.gains = L.gains;
+  J.params = L.params;
+  J.gflags = nullptr;
+  J.iters = nullptr;
+  J.converged = nullptr;
+  J.chisq_first = nullptr;
+  J.chisq_last = nullptr;
+  J.gt = gt;
+  J.gf = gf;
+  J.n_gf = n_gf;
+  J.r_lo = lo + (n * part) / n_part;
+  J.r_hi = lo + (n * (part + 1)) / n_part;
+  J.c_lo = L.chan_lo[gf];
+  J.c_hi = L.chan_hi[gf];
+  J.tol = L.tol;
+  J.max_iter = 1;
+  J.damping = L.damping;
+  J.err = L.err;
+  J.chisq_ref = nullptr;
+  J.restarted = nullptr;
+  J.partial = partials + (size_t)blockIdx.x * stride;
+  solve_interval<KIND, S, T, SINGLE, NG, RPS, true>(J);
+}
+
+template <int KIND, typename T, int NG>
+__global__ void __launch_bounds__(256) k_split_update(SolveLaunch L, int n_part, const double* partials,
+                                                      SplitState St) {
+  const TermArgs& TA = L.chain.t[L.chain.active];
+  const int n_gf = TA.n_gf;
+  const int interval = blockIdx.x;
+  const int gt = interval / n_gf;
+  const int gf = interval - gt * n_gf;
+  const size_t stride = (size_t)L.vis.n_ant * NG * KindInfo<KIND>::NV + 1;
+  Job J;
+  J.V = &L.vis;
+  J.CH = &L.chain;
+  J.TA = &TA;
+  J.gains = L.gains;
+  J.params = L.params;
+  J.gflags = L.gflags;
+  J.iters = L.iters;
+  J.converged = L.converged;
+  J.chisq_first = L.chisq_first;
+  J.chisq_last = L.chisq_last;
+  J.gt = gt;
+  J.gf = gf;
+  J.n_gf = n_gf;
+  J.r_lo = L.row_lo[gt];
+  J.r_hi = L.row_hi[gt];
+  J.c_lo = L.chan_lo[gf];
+  J.c_hi = L.chan_hi[gf];
+  J.tol = L.tol;
+  J.max_iter = L.max_iter;
+  J.damping = L.damping;
+  J.err = L.err;
+  J.chisq_ref = nullptr;
+  J.restarted = nullptr;
+  J.partial = nullptr;
+  split_update<KIND, T, NG>(J, partials + (size_t)interval * n_part * stride, n_part, St);
+}
+
+__global__ void k_split_reset(SplitState St, int n_int) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_int) {
+    St.passes[i] = 0;
+    St.done[i] = 0;
+  }
+  if (i == 0) St.n_active[0] = n_int;
+}
+
+template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
+  const int nw = L.waves;
+  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw);
+  const size_t lds_u = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, 0);
+  if (lds_out) *lds_out = lds;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto kp = k_split_pass<KIND, S, T, SINGLE, NG, RPS>;
+  auto ku = k_split_update<KIND, T, NG>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kp),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (lds_u > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ku),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_u);
+    if (e != hipSuccess) return e;
+  }
+  const TermArgs& ta = L.chain.t[L.chain.active];
+  const int n_int = ta.n_gt * ta.n_gf;
+  if (n_int == 0) return hipSuccess;
+  if (P.phase == 0) {
+    hipLaunchKernelGGL(k_split_reset, dim3((n_int + 255) / 256), dim3(256), 0, stream, P.state, n_int);
+  } else {
+    hipLaunchKernelGGL(kp, dim3((unsigned)(n_int * P.n_part)), dim3(64 * nw), lds, stream, L, P.n_part, P.partials,
+                       (const uint8_t*)P.state.done);
+    hipLaunchKernelGGL(ku, dim3((unsigned)n_int), dim3(256), lds_u, stream, L, P.n_part,
+                       (const double*)P.partials, P.state);
+  }
+  return hipGetLastError();
+}
+
 template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   const int nw = L.waves;
@@ -97,44 +221,53 @@ inline int rows_per_step(int max_chan, int nvp) {
 }
 
 template <int KIND, typename S, typename T>
-hipError_t launch_kind(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
+hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
   const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
+#define QC_LAUNCH(SINGLE_, NG_, RPS_)                                                       \
+  return P ? launch_split_one<KIND, S, T, SINGLE_, NG_, RPS_>(L, *P, stream, lds_out)     \
+           : launch_one<KIND, S, T, SINGLE_, NG_, RPS_>(L, stream, lds_out)
   if (single) {
     constexpr int NVP = pow2ceil(KindInfo<KIND>::NV);
     const int rps = L.rows_per_step > 0 ? L.rows_per_step : rows_per_step(L.max_int_chan, NVP);
-    if (rps == 4) return launch_one<KIND, S, T, true, 1, 4>(L, stream, lds_out);
-    if (rps == 2) return launch_one<KIND, S, T, true, 1, 2>(L, stream, lds_out);
-    return launch_one<KIND, S, T, true, 1, 1>(L, stream, lds_out);
+    if (rps == 4) { QC_LAUNCH(true, 1, 4); }
+    if (rps == 2) { QC_LAUNCH(true, 1, 2); }
+    QC_LAUNCH(true, 1, 1);
   }
-  if (ta.n_gdir == 1) return launch_one<KIND, S, T, false, 1, 1>(L, stream, lds_out);
-  return launch_one<KIND, S, T, false, 4, 1>(L, stream, lds_out);
+  // general chains: intervals of a few channels (a bandpass per channel) take
+  // one row per lane so that every lane works
+  if (ta.n_gdir == 1) {
+    if (L.max_int_chan <= 4) { QC_LAUNCH(false, 1, 64); }
+    QC_LAUNCH(false, 1, 1);
+  }
+  QC_LAUNCH(false, 4, 1);
+#undef QC_LAUNCH
 }
 
 }  // namespace
 
-hipError_t launch_solve(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
+hipError_t launch_solve(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
   const int kind = L.chain.t[L.chain.active].kind;
   if (L.prec_mixed) {
     if (L.vis_is_c128) return hipErrorInvalidValue;
     switch (kind) {
-      case KIND_DIAG: return launch_kind<KIND_DIAG, float, float>(L, stream, lds_out);
-      case KIND_C2X2: return launch_kind<KIND_C2X2, float, float>(L, stream, lds_out);
-      default: return launch_kind<KIND_DELAY, float, float>(L, stream, lds_out);
+      case KIND_DIAG: return launch_kind<KIND_DIAG, float, float>(L, P, stream, lds_out);
+      case KIND_C2X2: return launch_kind<KIND_C2X2, float, float>(L, P, stream, lds_out);
+      default: return launch_kind<KIND_DELAY, float, float>(L, P, stream, lds_out);
     }
   }
   if (L.vis_is_c128) {
     switch (kind) {
-      case KIND_DIAG: return launch_kind<KIND_DIAG, double, double>(L, stream, lds_out);
-      case KIND_C2X2: return launch_kind<KIND_C2X2, double, double>(L, stream, lds_out);
-      default: return launch_kind<KIND_DELAY, double, double>(L, stream, lds_out);
+      case KIND_DIAG: return launch_kind<KIND_DIAG, double, double>(L, P, stream, lds_out);
+      case KIND_C2X2: return launch_kind<KIND_C2X2, double, double>(L, P, stream, lds_out);
+      default: return launch_kind<KIND_DELAY, double, double>(L, P, stream, lds_out);
     }
   }
   switch (kind) {
-    case KIND_DIAG: return launch_kind<KIND_DIAG, float, double>(L, stream, lds_out);
-    case KIND_C2X2: return launch_kind<KIND_C2X2, float, double>(L, stream, lds_out);
-    default: return launch_kind<KIND_DELAY, float, double>(L, stream, lds_out);
+    case KIND_DIAG: return launch_kind<KIND_DIAG, float, double>(L, P, stream, lds_out);
+    case KIND_C2X2: return launch_kind<KIND_C2X2, float, double>(L, P, stream, lds_out);
+    default: return launch_kind<KIND_DELAY, float, double>(L, P, stream, lds_out);
   }
 }
 

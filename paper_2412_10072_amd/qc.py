@@ -29,6 +29,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
 
 EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms", "qc_ctx_set_tile",
+           "qc_ctx_set_split", "qc_ctx_last_split",
            "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
@@ -91,6 +92,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_solve_interval.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                       C.POINTER(QcSolveOpts), C.POINTER(QcSolveStats)]
     lib.qc_ctx_set_tile.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.qc_ctx_set_split.argtypes = [C.c_void_p, C.c_int32]
+    lib.qc_ctx_last_split.argtypes = [C.c_void_p]
+    lib.qc_ctx_last_split.restype = C.c_int32
     lib.qc_solve_chain.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                    C.POINTER(QcSolveOpts), C.c_void_p]
     lib.qc_delay_init.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_void_p]
@@ -115,7 +119,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_ws_gains.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.qc_ws_labels.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     for name in EXPORTS:
-        if name not in ("qc_last_error", "qc_last_kernel_ms", "qc_batch_last_ms"):
+        if name not in ("qc_last_error", "qc_last_kernel_ms", "qc_batch_last_ms", "qc_ctx_last_split"):
             getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -297,6 +301,13 @@ class Context:
     def set_tile(self, waves: int = 0, rows_per_step: int = 0):
         """qc_ctx_set_tile: launch shape of the per-interval solve (0 = default)."""
         self._check(self.lib.qc_ctx_set_tile(self.h, int(waves), int(rows_per_step)))
+
+    def set_split(self, parts: int = 0):
+        """qc_ctx_set_split: 0 automatic, 1 never split, > 1 parts per interval."""
+        self._check(self.lib.qc_ctx_set_split(self.h, int(parts)))
+
+    def last_split_parts(self) -> int:
+        return int(self.lib.qc_ctx_last_split(self.h))
 
     def last_kernel_ms(self) -> float:
         return float(self.lib.qc_last_kernel_ms(self.h))
