@@ -435,7 +435,7 @@ def clustered_sources(g, n_clusters: int, per_cluster: int, radius_deg: float, m
 def config_chain(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int = 512, n_clusters: int = 4,
                  per_cluster: int = 5, sigma: float = 0.05, flag_frac: float = 0.10, k_tint: int = 60,
                  de_tint: int = 16, de_fint: int = 128, delay_ns: float = 5.0, time_block: int = 4,
-                 dtype="c64", cfg_id: int = 3, de_amp: float = 0.2, de_phase: float = math.pi) -> Problem:
+                 dtype="c64", cfg_id: int = 3, de_amp: float = 0.2, de_phase: float = 0.5) -> Problem:
     """Jones chain + directions: the MeerKAT-like array, n_time x n_chan over 856-1712 MHz,
     n_clusters clusters of per_cluster point sources (one model direction per cluster).
     Truth chain C_{p,d} = K B G dE_d:
@@ -444,7 +444,11 @@ def config_chain(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int =
       B  diagonal bandpass per channel, smooth in frequency, constant in time;
       G  diagonal gain per time, smooth in time, constant over the band;
       dE direction-dependent diagonal, amp U(1 - de_amp, 1 + de_amp), phase U(-de_phase, de_phase)
-         (default U(0.8, 1.2), U(-pi, pi)), per de_tint x de_fint.
+         rad (default U(0.8, 1.2), U(-0.5, 0.5)), per de_tint x de_fint.  dE is the differential
+         direction-dependent correction on top of the direction-independent chain, so it stays
+         near unity; with phases spread over U(-pi, pi) the term-by-term solve from unit gains
+         stalls in a poor local minimum (and, on small arrays, the per-direction block-diagonal
+         update diverges).
     The chain returned for solving has unit gains, zero delays and the same intervals."""
     g0 = rng(device, 2412, cfg_id, 0)
     ant1, ant2, row_time = row_layout(n_time, n_ant)

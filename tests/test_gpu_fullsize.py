@@ -1,0 +1,180 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times, on sampled outputs the CPU FP64 oracle can compute one by
+one (whole-problem oracle runs at these sizes would take hours).
+
+  * MeerKAT-shaped full-Jones solve (64 antennas, 600 times x 1024 channels,
+    complex64, 9600 intervals of 1 time x 64 channels), MIXED to tol 1e-6 with
+    the default tile, then the residual pass: sampled intervals against the
+    oracle (gains <= 1e-4, iteration counts within one), every interval's
+    statistics checked for validity, the residual on the sampled intervals
+    against the oracle's residual through the same gains.
+  * K.B.G.dE chain with 4 directions (300 times x 512 channels): the delay
+    initial estimate on every K interval and antenna (a grid argmax taken in
+    FP64 on both sides: identical), one MIXED update of a G interval and of a
+    B interval against the oracle (<= 1e-4), and, where one oracle iteration
+    would take minutes (K: 62M samples per interval, split schedule; dE), the
+    size-independent property that the MIXED update agrees with the FP64
+    GPU path (whose oracle parity the small-size tests establish) to 1e-4,
+    and the split K reduction with the unsplit one.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import delay_init as o_delay
+from oracle import outputs as o_out
+from oracle import solver as o_solver
+from synth.generate import config_chain, config_meerkat
+from synth.problem import Vis
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def host_slice(vis, r0, r1, c0, c1):
+    """Rows [r0, r1) x channels [c0, c1) of a device visibility set, on the host."""
+    def h(x):
+        return x.cpu().numpy()
+    return Vis(data=h(vis.data[r0:r1, c0:c1]), model=h(vis.model[r0:r1, c0:c1]),
+               weight=h(vis.weight[r0:r1, c0:c1]), flag=h(vis.flag[r0:r1, c0:c1]),
+               ant1=h(vis.ant1[r0:r1]), ant2=h(vis.ant2[r0:r1]), row_time=h(vis.row_time[r0:r1]),
+               chan_freq=h(vis.chan_freq[c0:c1]), n_ant=int(vis.n_ant), n_time=int(vis.n_time))
+
+
+def host_chain_slice(chain, c0, c1):
+    """Host copies of chain terms with their channel maps cut to [c0, c1)."""
+    from paper_2412_10072_amd import qc
+    out = []
+    for t in chain:
+        h = qc.host_term(t)
+        out.append(h.copy(f_map=np.asarray(h.f_map)[c0:c1], t_map=np.asarray(h.t_map),
+                          d_map=np.asarray(h.d_map)))
+    return out
+
+
+def rel_err(got, want, cols):
+    d = np.linalg.norm((got[..., cols] - want[..., cols]).ravel())
+    return float(d / max(np.linalg.norm(want[..., cols].ravel()), 1e-300))
+
+
+def test_meerkat_full_size_sampled_parity(qc_lib):
+    from paper_2412_10072_amd import qc
+    say("full-size MeerKAT: generating 600 x 1024 x 2016 baselines")
+    p = config_meerkat(device=DEV)
+    vis = p.vis
+    nbl = 64 * 63 // 2
+    term = qc.device_term(p.chain[0], DEV)
+    unit = p.chain[0]
+    st = qc_lib.solve(vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+    resid = qc_lib.residual(vis, [term])
+    qc_lib.sync()
+    it = st["iters"].cpu().numpy()
+    cv = st["converged"].cpu().numpy()
+    c0 = st["chisq_first"].cpu().numpy()
+    c1 = st["chisq_last"].cpu().numpy()
+    say(f"solved: iterations {it.min()}..{it.max()} mean {it.mean():.2f}, converged {cv.mean():.3f}")
+    assert it.shape == (600, 16)
+    assert (it >= 1).all() and (it <= 100).all()
+    assert cv.all()
+    assert np.isfinite(c1).all() and (c1 <= c0).all()
+    gains = term.gains.cpu().numpy()
+    assert np.isfinite(gains).all()
+    samples = [(0, 0), (0, 15), (299, 7), (451, 3), (599, 15)]
+    rng = np.random.default_rng(11)
+    samples += [(int(rng.integers(600)), int(rng.integers(16))) for _ in range(2)]
+    for gt, gf in samples:
+        r0, r1, ch0, ch1 = gt * nbl, (gt + 1) * nbl, gf * 64, (gf + 1) * 64
+        vh = host_slice(vis, r0, r1, ch0, ch1)
+        ref = o_solver.copy_chain([unit.copy(f_map=np.asarray(unit.f_map)[ch0:ch1])])
+        ri, rc, _, _ = o_solver.solve_interval(vh, ref, 0, gt, gf, 1e-6, 100)
+        e = rel_err(gains[gt, gf], ref[0].gains[gt, gf], [0, 1, 2, 3])
+        say(f"interval ({gt}, {gf}): oracle {ri} updates, gpu {it[gt, gf]}, rel err {e:.2e}")
+        assert rc == 1
+        assert abs(int(it[gt, gf]) - ri) <= 1
+        assert e <= 1e-4
+        # residual through the GPU's own gains, sample by sample
+        got_chain = [qc.host_term(term).copy(f_map=np.asarray(unit.f_map)[ch0:ch1])]
+        want_r = o_out.residual(vh, got_chain)
+        got_r = resid[r0:r1, ch0:ch1].cpu().numpy()
+        keep = vh.flag == 0
+        scale = np.abs(vh.data[keep]).max()
+        assert np.abs(got_r[keep] - want_r[keep]).max() <= 2e-6 * scale
+
+
+def test_chain_full_size_sampled_parity(qc_lib):
+    from paper_2412_10072_amd import qc
+    say("full-size chain: generating 300 x 512, 4 directions")
+    p = config_chain(device=DEV)
+    vis = p.vis
+    nbl = 64 * 63 // 2
+    n_row, n_chan = int(vis.data.shape[0]), int(vis.data.shape[1])
+
+    # A0: delay initial estimate, every K interval and antenna
+    K = qc.device_term(p.chain[0], DEV)
+    qc_lib.delay_init(vis, K, ref_ant=0)
+    qc_lib.sync()
+    a1, a2 = vis.ant1.cpu().numpy(), vis.ant2.cpu().numpy()
+    ref_rows = np.nonzero((a1 == 0) | (a2 == 0))[0]
+    vr = Vis(data=vis.data[ref_rows].cpu().numpy(), model=vis.model[ref_rows].cpu().numpy(),
+             weight=vis.weight[ref_rows].cpu().numpy(), flag=vis.flag[ref_rows].cpu().numpy(),
+             ant1=a1[ref_rows], ant2=a2[ref_rows], row_time=vis.row_time[ref_rows].cpu().numpy(),
+             chan_freq=vis.chan_freq.cpu().numpy(), n_ant=64, n_time=300)
+    want = o_delay.delay_init(vr, [p.chain[0]], 0, ref_ant=0)[0].params
+    say("delay init compared on the reference-antenna rows")
+    assert np.array_equal(K.params.cpu().numpy(), want)
+
+    # G and B: one MIXED update against the oracle, other terms at the truth
+    def chain_with(active):
+        ch = [qc.device_term(t, DEV) for t in p.truth]
+        ch[active] = qc.device_term(p.chain[active], DEV)
+        return ch
+
+    for active, name, rows, chans in ((2, "G", (137 * nbl, 138 * nbl), (0, n_chan)),
+                                      (1, "B", (0, n_row), (301, 302))):
+        ch = chain_with(active)
+        qc_lib.solve(vis, ch, active, tol=-1.0, max_iter=1, prec="mixed")
+        qc_lib.sync()
+        vh = host_slice(vis, rows[0], rows[1], chans[0], chans[1])
+        hc = host_chain_slice(chain_with(active), chans[0], chans[1])
+        gt = 137 if name == "G" else 0
+        gf = 0 if name == "G" else 301
+        o_solver.solve_interval(vh, hc, active, gt, gf, -1.0, 1)
+        got = ch[active].gains.cpu().numpy()[gt, gf]
+        e = rel_err(got, hc[active].gains[gt, gf], [0, 3])
+        say(f"{name} interval ({gt}, {gf}): one MIXED update, rel err {e:.2e}")
+        assert e <= 1e-4
+
+    # dE: MIXED against the FP64 GPU path, two updates on every interval
+    got = {}
+    for prec in ("mixed", "fp64"):
+        ch = chain_with(3)
+        qc_lib.solve(vis, ch, 3, tol=-1.0, max_iter=2, prec=prec)
+        qc_lib.sync()
+        got[prec] = ch[3].gains.cpu().numpy()
+    nt, nf = got["fp64"].shape[:2]
+    e = max(rel_err(got["mixed"][a, b], got["fp64"][a, b], [0, 3]) for a in range(nt) for b in range(nf))
+    say(f"dE: MIXED vs FP64 after two updates, max rel err {e:.2e}")
+    assert e <= 1e-4
+
+    # K: split reduction (the benchmark's schedule) against one workgroup per interval
+    res = {}
+    for parts in (0, 1):
+        qc_lib.set_split(parts)
+        ch = chain_with(0)
+        ch[0].params.copy_(K.params)
+        qc_lib.solve(vis, ch, 0, tol=-1.0, max_iter=2, prec="mixed")
+        qc_lib.sync()
+        res[parts] = (ch[0].params.cpu().numpy(), qc_lib.last_split_parts())
+    qc_lib.set_split(0)
+    tau_s, n_s = res[0]
+    tau_1, n_1 = res[1]
+    say(f"K: split parts {n_s} vs {n_1}, max |dtau| {np.abs(tau_s - tau_1).max():.3e} s")
+    assert n_s > 1 and n_1 == 1
+    assert np.abs(tau_s - tau_1).max() <= 1e-4 * max(np.abs(tau_1).max(), 1e-12)
