@@ -332,6 +332,9 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   fill_args(vis, chain, n_term, active, L.vis, L.chain);
   L.vis_is_c128 = vis->dtype == QC_C128;
   L.prec_mixed = opts->prec == QC_PREC_MIXED;
+  L.diag_chain = 1;
+  for (int j = 0; j < n_term; ++j)
+    if (chain[j].type == QC_TERM_COMPLEX2X2) L.diag_chain = 0;
   qc_term& ta = chain[active];
   L.gains = reinterpret_cast<double2*>(ta.gains);
   L.params = ta.params;
@@ -355,15 +358,17 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   L.waves = ctx->waves;
   L.max_int_chan = ctx->max_int_chan;
   L.rows_per_step = ctx->rows_per_step;
-  // schedule: fused (one workgroup per interval) unless the term has few, large
-  // intervals, which are then cut into parts streamed by separate workgroups
+  // schedule: fused (one workgroup per interval) unless the term has too few
+  // intervals to give every CU several workgroups and they are large enough
+  // (>= 2^18 samples on average) to amortise a host wait per iteration; those
+  // are cut into parts streamed by separate workgroups (about 4 per CU)
   const int n_int = ta.n_gt * ta.n_gf;
   const double avg_samples = n_int > 0 ? (double)vis->n_row * vis->n_chan / n_int : 0.0;
   int parts = 1;
   if (ctx->split_parts > 1) {
     parts = ctx->split_parts;
-  } else if (ctx->split_parts == 0 && !opts->chisq_ref && n_int > 0 && n_int < 2 * ctx->n_cu &&
-             avg_samples >= (double)(1 << 20)) {
+  } else if (ctx->split_parts == 0 && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
+             avg_samples >= (double)(1 << 18)) {
     const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
     parts = (int)std::ceil(4.0 * ctx->n_cu / n_int);
     parts = std::max(2, std::min(parts, (int)std::max(1.0, rows_per_int / 64.0)));

@@ -17,6 +17,8 @@ namespace qc {
 // ---------------------------------------------------------------------------
 
 enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2 };
+// per-sample chain evaluation of the solver kernels
+enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2 };
 
 struct TermArgs {
   int kind, n_gt, n_gf, n_gdir;
@@ -206,6 +208,7 @@ struct SolveLaunch {
   ChainArgs chain;
   int vis_is_c128;            // storage precision of data/model/weight
   int prec_mixed;             // compute precision
+  int diag_chain;             // every chain term is diagonal or a delay
   // active term, in/out
   double2* gains;
   double* params;

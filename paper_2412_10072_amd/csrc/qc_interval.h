@@ -313,6 +313,17 @@ __device__ __forceinline__ void load_w(const S* base, size_t s, int n_wcorr, T& 
   }
 }
 
+// Component-wise selects: a conditional between whole structs becomes a
+// select of their addresses, which forces them into scratch memory.
+template <typename T>
+__device__ __forceinline__ cx<T> csel(bool c, cx<T> x, cx<T> y) {
+  return cmake<T>(c ? x.re : y.re, c ? x.im : y.im);
+}
+template <typename T>
+__device__ __forceinline__ m22<T> msel(bool c, const m22<T>& x, const m22<T>& y) {
+  return {csel(c, x.a, y.a), csel(c, x.b, y.b), csel(c, x.c, y.c), csel(c, x.d, y.d)};
+}
+
 template <typename T>
 __device__ __forceinline__ m22<T> select_m(bool use, const m22<T>& x) {
   const T z = T(0);
@@ -508,17 +519,24 @@ const double alpha = step_length(damping, k_upd);
   return ctl[0] != 0;
 }
 
-// SINGLE: the chain is the active term alone, one direction, one gain
-//         direction (the plain full-Jones / diagonal solve).
+// CHM:    how the chain is evaluated per sample.
+//         CHAIN_SINGLE: the chain is the active term alone, one direction,
+//         one gain direction (the plain full-Jones / diagonal solve).
+//         CHAIN_DIAG: every term is diagonal or a delay, so the Jones
+//         matrices commute and each is a pair of complex numbers.
+//         CHAIN_GENERAL: any chain (2x2 products).
 // NG:     gain directions of the active term held per antenna (1 or 4).
 // RPS:    rows per wavefront step: lanes are RPS segments of 64/RPS
 //         consecutive channels of consecutive rows (narrow intervals keep
 //         every lane busy).
 // PASS_ONLY: one streaming pass over rows [r_lo, r_hi) at the gains in
 //         J.gains; the FP64 blocks and chi^2 go to J.partial (split schedule).
-template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS, bool PASS_ONLY = false>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false>
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
+  constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
+  constexpr bool DIAGC = (CHM == CHAIN_DIAG);
+  static_assert(!DIAGC || KIND != KIND_C2X2, "a diagonal chain has no full-Jones term");
   constexpr bool KAHAN = (sizeof(T) == 4);
   constexpr int NV = KindInfo<KIND>::NV;
   constexpr int NVG = NV * NG;
@@ -690,6 +708,97 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, Gp.a, Gp.d, tpn, PACC ? pacc : prow);
           contrib<KIND, true, T>(aq0, aq1, herm(GM), herm(WR), w0, w2, w1, w3, Gq.a, Gq.d, tpn, qacc);
           chi = chisq_acc(WR, R, chi);
+        } else if constexpr (DIAGC) {
+          // Diagonal chain: C_{a,d} = g_{a,d} o_{a,d} per hand, o the product
+          // of every other term (all diagonal, so the order is immaterial).
+          // Then with the active gain g:
+          //   model        V_ij  = sum_d g_{p,i} B_ij
+          //   forward      B_ij  = o_{p,i} M_ij conj(C_{q,j})      (dV_ij / dg_{p,i})
+          //   conjugate    Bc_ij = o_{q,i} conj(M_ji C_{p,j})     (d(V^H)_ij / dg_{q,i})
+          // and the left factor handed to contrib is the identity.
+          const ChainArgs& CH = *J.CH;
+          const int act = CH.active;
+          const int n_term = CH.n_term;
+          // direction-independent part of o (terms with one gain direction)
+          cx<T> op0 = cone<T>(), op1 = cone<T>(), oq0 = cone<T>(), oq1 = cone<T>();
+          for (int j = 0; j < n_term; ++j) {
+            if (j == act || CH.t[j].n_gdir > 1) continue;
+            const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, 0, nu);
+            const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, 0, nu);
+            op0 = op0 * Jp.a; op1 = op1 * Jp.d;
+            oq0 = oq0 * Jq.a; oq1 = oq1 * Jq.d;
+          }
+          m22<T> Bs[NG], Bsc[NG];
+          cx<T> gp0[NG], gp1[NG], gq0[NG], gq1[NG];
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            Bs[g] = mzero<T>();
+            Bsc[g] = mzero<T>();
+            gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
+          }
+          m22<T> Vm = mzero<T>();
+          for (int d = 0; d < n_dir; ++d) {
+            const int gd = TA.d_map[d];
+            cx<T> hp0, hp1, hq0, hq1;            // active gains of p and q
+            if constexpr (KIND == KIND_DELAY) {
+              const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
+              hp0 = phasor_turns<T>(nu * tp.x);
+              hp1 = phasor_turns<T>(nu * tp.y);
+              hq0 = phasor_turns<T>(nu * tq.x);
+              hq1 = phasor_turns<T>(nu * tq.y);
+            } else {
+              const cx<T>* gpp = gc + (p * NG + gd) * 4;
+              const cx<T>* gqq = gc + (q * NG + gd) * 4;
+              hp0 = gpp[0]; hp1 = gpp[3];
+              hq0 = gqq[0]; hq1 = gqq[3];
+            }
+            // direction-dependent part of o
+            cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
+            for (int j = 0; j < n_term; ++j) {
+              if (j == act || CH.t[j].n_gdir <= 1) continue;
+              const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, d, nu);
+              const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, d, nu);
+              rp0 = rp0 * Jp.a; rp1 = rp1 * Jp.d;
+              rq0 = rq0 * Jq.a; rq1 = rq1 * Jq.d;
+            }
+            const cx<T> cp0 = hp0 * rp0, cp1 = hp1 * rp1;
+            const cx<T> cq0 = hq0 * rq0, cq1 = hq1 * rq1;
+            const m22<T> M = select_m(use, load_m22<S, T>(Mp, s * n_dir + d));
+            m22<T> B, Bc;
+            B.a = mulc(rp0 * M.a, cq0);
+            B.b = mulc(rp0 * M.b, cq1);
+            B.c = mulc(rp1 * M.c, cq0);
+            B.d = mulc(rp1 * M.d, cq1);
+            Bc.a = mulc(rq0, M.a * cp0);
+            Bc.b = mulc(rq0, M.c * cp1);
+            Bc.c = mulc(rq1, M.b * cp0);
+            Bc.d = mulc(rq1, M.d * cp1);
+            Vm.a = cfma(hp0, B.a, Vm.a);
+            Vm.b = cfma(hp0, B.b, Vm.b);
+            Vm.c = cfma(hp1, B.c, Vm.c);
+            Vm.d = cfma(hp1, B.d, Vm.d);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+              const bool hit = (g == gd);
+              const bool h = (NG == 1) || hit;    // one gain direction: every d maps to 0
+              Bs[g] = msel(h, Bs[g] + B, Bs[g]);
+              Bsc[g] = msel(h, Bsc[g] + Bc, Bsc[g]);
+              gp0[g] = csel(h, hp0, gp0[g]);
+              gp1[g] = csel(h, hp1, gp1[g]);
+              gq0[g] = csel(h, hq0, gq0[g]);
+              gq1[g] = csel(h, hq1, gq1[g]);
+            }
+          }
+          const m22<T> R = D - Vm;
+          const m22<T> WR = wmul(R, w0, w1, w2, w3);
+          const m22<T> WRc = herm(WR);
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            contrib<KIND, false, T>(ap0, ap1, Bs[g], WR, w0, w1, w2, w3, gp0[g], gp1[g], tpn,
+                                    (PACC ? pacc : prow) + g * NV);
+            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV);
+          }
+          chi = chisq_acc(WR, R, chi);
         } else {
           const ChainArgs& CH = *J.CH;
           const int act = CH.active;
@@ -737,12 +846,13 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
               const bool hit = (g == gd);
-              Bs[g] = hit ? Bs[g] + B : Bs[g];
-              Bsc[g] = hit ? Bsc[g] + Bc : Bsc[g];
-              gp0[g] = hit ? Gp.a : gp0[g];
-              gp1[g] = hit ? Gp.d : gp1[g];
-              gq0[g] = hit ? Gq.a : gq0[g];
-              gq1[g] = hit ? Gq.d : gq1[g];
+              const bool h = (NG == 1) || hit;    // one gain direction: every d maps to 0
+              Bs[g] = msel(h, Bs[g] + B, Bs[g]);
+              Bsc[g] = msel(h, Bsc[g] + Bc, Bsc[g]);
+              gp0[g] = csel(h, Gp.a, gp0[g]);
+              gp1[g] = csel(h, Gp.d, gp1[g]);
+              gq0[g] = csel(h, Gq.a, gq0[g]);
+              gq1[g] = csel(h, Gq.d, gq1[g]);
             }
           }
           const m22<T> R = D - Vm;

@@ -35,7 +35,7 @@
 namespace qc {
 namespace {
 
-template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
 __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   J.err = L.err;
   J.chisq_ref = L.chisq_ref;
   J.restarted = L.restarted;
-  solve_interval<KIND, S, T, SINGLE, NG, RPS>(J);
+  solve_interval<KIND, S, T, CHM, NG, RPS>(J);
 }
 
 // Split schedule for intervals too large for one workgroup: every interval's
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
 // the current gains and writes FP64 blocks; one workgroup per interval then
 // sums the parts in a fixed order and updates (split_update).  The host
 // repeats pass + update until no interval is active.
-template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
 __global__ void __launch_bounds__(512) k_split_pass(SolveLaunch L, int n_part, double* partials,
                                                     const uint8_t* done) {
   const TermArgs& TA = L.chain.t[L.chain.active];
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(512) k_split_pass(SolveLaunch L, int n_part, d
   J.chisq_ref = nullptr;
   J.restarted = nullptr;
   J.partial = partials + (size_t)blockIdx.x * stride;
-  solve_interval<KIND, S, T, SINGLE, NG, RPS, true>(J);
+  solve_interval<KIND, S, T, CHM, NG, RPS, true>(J);
 }
 
 template <int KIND, typename T, int NG>
@@ -159,14 +159,14 @@ __global__ void k_split_reset(SplitState St, int n_int) {
   if (i == 0) St.n_active[0] = n_int;
 }
 
-template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
 hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
   const int nw = L.waves;
   const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw);
   const size_t lds_u = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, 0);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kp = k_split_pass<KIND, S, T, SINGLE, NG, RPS>;
+  auto kp = k_split_pass<KIND, S, T, CHM, NG, RPS>;
   auto ku = k_split_update<KIND, T, NG>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kp),
@@ -192,13 +192,13 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
   return hipGetLastError();
 }
 
-template <int KIND, typename S, typename T, bool SINGLE, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   const int nw = L.waves;
   const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = k_solve_fused<KIND, S, T, SINGLE, NG, RPS>;
+  auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -225,23 +225,32 @@ hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t s
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
   const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
-#define QC_LAUNCH(SINGLE_, NG_, RPS_)                                                       \
-  return P ? launch_split_one<KIND, S, T, SINGLE_, NG_, RPS_>(L, *P, stream, lds_out)     \
-           : launch_one<KIND, S, T, SINGLE_, NG_, RPS_>(L, stream, lds_out)
+#define QC_LAUNCH(CHM_, NG_, RPS_)                                                          \
+  return P ? launch_split_one<KIND, S, T, CHM_, NG_, RPS_>(L, *P, stream, lds_out)        \
+           : launch_one<KIND, S, T, CHM_, NG_, RPS_>(L, stream, lds_out)
   if (single) {
     constexpr int NVP = pow2ceil(KindInfo<KIND>::NV);
     const int rps = L.rows_per_step > 0 ? L.rows_per_step : rows_per_step(L.max_int_chan, NVP);
-    if (rps == 4) { QC_LAUNCH(true, 1, 4); }
-    if (rps == 2) { QC_LAUNCH(true, 1, 2); }
-    QC_LAUNCH(true, 1, 1);
+    if (rps == 4) { QC_LAUNCH(CHAIN_SINGLE, 1, 4); }
+    if (rps == 2) { QC_LAUNCH(CHAIN_SINGLE, 1, 2); }
+    QC_LAUNCH(CHAIN_SINGLE, 1, 1);
   }
-  // general chains: intervals of a few channels (a bandpass per channel) take
-  // one row per lane so that every lane works
+  // chains: intervals of a few channels (a bandpass per channel) take one row
+  // per lane so that every lane works
+  if constexpr (KIND != KIND_C2X2) {
+    if (L.diag_chain) {
+      if (ta.n_gdir == 1) {
+        if (L.max_int_chan <= 4) { QC_LAUNCH(CHAIN_DIAG, 1, 64); }
+        QC_LAUNCH(CHAIN_DIAG, 1, 1);
+      }
+      QC_LAUNCH(CHAIN_DIAG, 4, 1);
+    }
+  }
   if (ta.n_gdir == 1) {
-    if (L.max_int_chan <= 4) { QC_LAUNCH(false, 1, 64); }
-    QC_LAUNCH(false, 1, 1);
+    if (L.max_int_chan <= 4) { QC_LAUNCH(CHAIN_GENERAL, 1, 64); }
+    QC_LAUNCH(CHAIN_GENERAL, 1, 1);
   }
-  QC_LAUNCH(false, 4, 1);
+  QC_LAUNCH(CHAIN_GENERAL, 4, 1);
 #undef QC_LAUNCH
 }
 
