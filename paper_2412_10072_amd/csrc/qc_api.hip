@@ -616,6 +616,9 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
   fill_args(vis, chain, n_term, 0, L.vis, L.chain);
   L.vis_is_c128 = vis->dtype == QC_C128;
   L.mode = mode;
+  L.diag_chain = 1;
+  for (int j = 0; j < n_term; ++j)
+    if (chain[j].type == QC_TERM_COMPLEX2X2) L.diag_chain = 0;
   unsigned mask = 0;
   for (int d = 0; d < vis->n_dir; ++d)
     if (!dir_mask || dir_mask[d]) mask |= 1u << d;

@@ -300,6 +300,7 @@ struct OutputLaunch {
   int vis_is_c128;
   int mode;                   // 0 corrupt, 1 correct, 2 residual
   unsigned dir_mask;          // bit d set = direction d included
+  int diag_chain;             // every chain term is diagonal or a delay
   void* out;
 };
 

@@ -175,6 +175,65 @@ __device__ __forceinline__ void wave_flush(A* v, int lane, unsigned s_off, unsig
   }
 }
 
+// Flush for steps whose lanes hold different rows (one row per lane): each
+// valid lane adds its NVAL values into the LDS slot of its own antenna `key`
+// (bytes s_base + key * ant_bytes, compensation at c_base + ...).  With RUNS
+// the lanes first sum over contiguous runs of equal key (a segmented scan),
+// so only the last lane of each run writes.  Writers that share a key take
+// turns: in each round the lowest pending lane of every key (an LDS atomic
+// min on the wave's claim word for that antenna) adds its values, so the
+// order of the additions does not depend on timing.  v is clobbered.
+template <int NVAL, bool KAHAN, bool RUNS, typename A>
+__device__ __forceinline__ void lane_flush(A* v, int lane, int key, unsigned s_base, unsigned c_base,
+                                           unsigned ant_bytes, unsigned* claim, bool valid) {
+  if constexpr (RUNS) {
+    const int kprev = __shfl_up(key, 1);
+    const int vprev = __shfl_up((int)valid, 1);
+    const bool head = lane == 0 || !valid || !vprev || kprev != key;
+    int start = head ? lane : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(start, o);
+      if (lane >= o) start = max(start, u);
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+      for (int k = 0; k < NVAL; ++k) {
+        const A u = __shfl_up(v[k], o);
+        if (lane - o >= start) v[k] += u;
+      }
+    }
+    const int knext = __shfl_down(key, 1);
+    const int vnext = __shfl_down((int)valid, 1);
+    const bool tail = lane == 63 || !vnext || knext != key;
+    valid = valid && tail;
+  }
+  while (__ballot(valid) != 0) {
+    if (valid) claim[key] = 0xffffffffu;
+    if (valid) atomicMin(&claim[key], (unsigned)lane);
+    const bool win = valid && claim[key] == (unsigned)lane;
+    if (win) {
+#pragma unroll
+      for (int k = 0; k < NVAL; ++k) {
+        A* ps = lds_at<A>(s_base + (unsigned)key * ant_bytes) + k;
+        if constexpr (KAHAN) {
+          A* pc = lds_at<A>(c_base + (unsigned)key * ant_bytes) + k;
+          const A s = *ps;
+          const A c = *pc;
+          const A y = v[k] - c;
+          const A t = s + y;
+          *pc = (t - s) - y;
+          *ps = t;
+        } else {
+          *ps += v[k];
+        }
+      }
+    }
+    valid = valid && !win;
+  }
+}
+
 template <typename A>
 __device__ __forceinline__ A wave_sum(A x) {
 #pragma unroll
@@ -401,14 +460,17 @@ struct Job {
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
+// lane_rows: steps of one row per lane, which add a claim word per antenna
+// and wave.
 template <int KIND, typename T, int NG>
-__host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw) {
+__host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool lane_rows = false) {
   const size_t n_slots = (size_t)n_ant * NG;
   const size_t nv = KindInfo<KIND>::NV;
   size_t b = sizeof(double) * n_slots * nv + sizeof(double2) * n_slots * 4 + sizeof(double) * 48 +
              sizeof(cx<T>) * n_slots * 4 + sizeof(int) * (n_slots + 4);
   b = (b + 15) & ~size_t(15);
-  return b + sizeof(T) * n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1);
+  return b + sizeof(T) * n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1) +
+         (lane_rows ? sizeof(unsigned) * (size_t)n_ant * nw : 0);
 }
 
 // One FP64 block solve per (antenna, gain direction) of an interval from its
@@ -542,7 +604,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   constexpr int NVG = NV * NG;
   constexpr int NVP = pow2ceil(NVG);
   constexpr int LPR = 64 / RPS;              // lanes per row
-  constexpr bool PACC = (NG == 1);           // keep antenna-p sums in registers over a p-run
+  constexpr bool LANE_ROWS = (LPR == 1);     // one row per lane: flush by lane_flush
+  constexpr bool PACC = (NG == 1) && !LANE_ROWS;  // keep antenna-p sums in registers over a p-run
   static_assert(NVP <= 64, "too many values per antenna");
   static_assert(SINGLE || RPS == 1 || NG == 1, "multi-row steps of the general kernel take one gain direction");
 
@@ -577,6 +640,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   lp += sizeof(A) * slot_vals * nw;
   A* acc_c = reinterpret_cast<A*>(lp);
   const unsigned acc_c_off = (unsigned)(lp - qc_lds);
+  if constexpr (KAHAN) lp += sizeof(A) * slot_vals * nw;
+  // one claim word per antenna and wave (lane-per-row steps only)
+  unsigned* claim = reinterpret_cast<unsigned*>(lp) + (size_t)wave * n_ant;
   A* my_s = acc_s + (size_t)wave * slot_vals;
   A* my_c = acc_c + (size_t)wave * slot_vals;
   // byte offsets of this wave's slots; antenna a's values start at a * NG * NV
@@ -867,9 +933,14 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           chi = chisq_acc(WR, R, chi);
         }
       }
-      wave_flush<NVP, NVG, KAHAN, LPR>(qacc, lane, my_s_off + q * ANT_BYTES, my_c_off + q * ANT_BYTES, row_ok);
-      if constexpr (!PACC) {
-        wave_flush<NVP, NVG, KAHAN, LPR>(prow, lane, my_s_off + p * ANT_BYTES, my_c_off + p * ANT_BYTES, row_ok);
+      if constexpr (LANE_ROWS) {
+        lane_flush<NVG, KAHAN, false>(qacc, lane, q, my_s_off, my_c_off, ANT_BYTES, claim, row_ok);
+        lane_flush<NVG, KAHAN, true>(prow, lane, p, my_s_off, my_c_off, ANT_BYTES, claim, row_ok);
+      } else {
+        wave_flush<NVP, NVG, KAHAN, LPR>(qacc, lane, my_s_off + q * ANT_BYTES, my_c_off + q * ANT_BYTES, row_ok);
+        if constexpr (!PACC) {
+          wave_flush<NVP, NVG, KAHAN, LPR>(prow, lane, my_s_off + p * ANT_BYTES, my_c_off + p * ANT_BYTES, row_ok);
+        }
       }
     }
     if constexpr (PACC) {

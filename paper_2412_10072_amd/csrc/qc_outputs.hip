@@ -43,6 +43,12 @@ __device__ __forceinline__ void st(S* base, size_t elem, const m22<T>& x) {
 }
 
 template <typename T>
+__device__ __forceinline__ cx<T> cinv(cx<T> a) {
+  const T n = norm2(a);
+  return cmake<T>(a.re / n, -a.im / n);
+}
+
+template <typename T>
 __device__ __forceinline__ bool inv2(const m22<T>& x, m22<T>& out) {
   const cx<T> det = x.a * x.d - x.b * x.c;
   if (det.re == T(0) && det.im == T(0)) return false;
@@ -52,7 +58,24 @@ __device__ __forceinline__ bool inv2(const m22<T>& x, m22<T>& out) {
   return true;
 }
 
-template <typename S, int MODE>
+// Diagonal of the chain product for antenna x: the direction-independent
+// terms (one gain direction) when DD is false, the direction-dependent ones
+// at direction d when DD is true.  Diagonal Jones matrices commute.
+template <typename T, bool DD>
+__device__ __forceinline__ void diag_part(const ChainArgs& CH, int n_ant, int t, int c, int x, int d, double nu,
+                                          cx<T>& h0, cx<T>& h1) {
+  for (int j = 0; j < CH.n_term; ++j) {
+    if ((CH.t[j].n_gdir > 1) != DD) continue;
+    const m22<T> J = term_jones<T>(CH.t[j], n_ant, t, c, x, d, nu);
+    h0 = h0 * J.a;
+    h1 = h1 * J.d;
+  }
+}
+
+// DIAG: every term is diagonal or a delay, so each chain product is a pair
+// of complex numbers and the direction-independent part is formed once per
+// sample.
+template <typename S, int MODE, bool DIAG>
 __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
   using T = S;
   const VisArgs& V = L.vis;
@@ -67,7 +90,38 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
     const int p = V.ant1[r], q = V.ant2[r], t = V.row_time[r];
     if ((unsigned)p >= (unsigned)V.n_ant || (unsigned)q >= (unsigned)V.n_ant) continue;
     const double nu = V.freq[c];
-    if constexpr (MODE == 1) {
+    if constexpr (DIAG) {
+      cx<T> p0 = cone<T>(), p1 = cone<T>(), q0 = cone<T>(), q1 = cone<T>();
+      diag_part<T, false>(CH, V.n_ant, t, c, p, 0, nu, p0, p1);
+      diag_part<T, false>(CH, V.n_ant, t, c, q, 0, nu, q0, q1);
+      if constexpr (MODE == 1) {
+        // C_p^-1 D C_q^-H, zero where C_p or C_q is singular
+        const bool ok = !(p0.re == T(0) && p0.im == T(0)) && !(p1.re == T(0) && p1.im == T(0)) &&
+                        !(q0.re == T(0) && q0.im == T(0)) && !(q1.re == T(0) && q1.im == T(0));
+        m22<T> o = mzero<T>();
+        if (ok) {
+          const m22<T> D = ld<S, T>(Dp, s);
+          const cx<T> ip0 = cinv(p0), ip1 = cinv(p1), iq0 = cinv(q0), iq1 = cinv(q1);
+          o = {mulc(ip0 * D.a, iq0), mulc(ip0 * D.b, iq1), mulc(ip1 * D.c, iq0), mulc(ip1 * D.d, iq1)};
+        }
+        st<S, T>(Op, s, o);
+      } else {
+        m22<T> Vm = mzero<T>();
+        for (int d = 0; d < V.n_dir; ++d) {
+          if (!((L.dir_mask >> d) & 1u)) continue;
+          cx<T> cp0 = p0, cp1 = p1, cq0 = q0, cq1 = q1;
+          diag_part<T, true>(CH, V.n_ant, t, c, p, d, nu, cp0, cp1);
+          diag_part<T, true>(CH, V.n_ant, t, c, q, d, nu, cq0, cq1);
+          const m22<T> M = ld<S, T>(Mp, s * V.n_dir + d);
+          Vm.a = Vm.a + mulc(cp0 * M.a, cq0);
+          Vm.b = Vm.b + mulc(cp0 * M.b, cq1);
+          Vm.c = Vm.c + mulc(cp1 * M.c, cq0);
+          Vm.d = Vm.d + mulc(cp1 * M.d, cq1);
+        }
+        if constexpr (MODE == 2) Vm = ld<S, T>(Dp, s) - Vm;
+        st<S, T>(Op, s, Vm);
+      }
+    } else if constexpr (MODE == 1) {
       const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, 0, nu);
       const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, 0, nu);
       m22<T> ip, iq;
@@ -95,10 +149,19 @@ hipError_t launch_s(const OutputLaunch& L, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   size_t blocks = (n + 255) / 256;
   if (blocks > 256 * 64) blocks = 256 * 64;
-  switch (L.mode) {
-    case 0: hipLaunchKernelGGL((k_outputs<S, 0>), dim3((unsigned)blocks), dim3(256), 0, stream, L); break;
-    case 1: hipLaunchKernelGGL((k_outputs<S, 1>), dim3((unsigned)blocks), dim3(256), 0, stream, L); break;
-    default: hipLaunchKernelGGL((k_outputs<S, 2>), dim3((unsigned)blocks), dim3(256), 0, stream, L); break;
+  const dim3 g((unsigned)blocks), b(256);
+  if (L.diag_chain) {
+    switch (L.mode) {
+      case 0: hipLaunchKernelGGL((k_outputs<S, 0, true>), g, b, 0, stream, L); break;
+      case 1: hipLaunchKernelGGL((k_outputs<S, 1, true>), g, b, 0, stream, L); break;
+      default: hipLaunchKernelGGL((k_outputs<S, 2, true>), g, b, 0, stream, L); break;
+    }
+  } else {
+    switch (L.mode) {
+      case 0: hipLaunchKernelGGL((k_outputs<S, 0, false>), g, b, 0, stream, L); break;
+      case 1: hipLaunchKernelGGL((k_outputs<S, 1, false>), g, b, 0, stream, L); break;
+      default: hipLaunchKernelGGL((k_outputs<S, 2, false>), g, b, 0, stream, L); break;
+    }
   }
   return hipGetLastError();
 }

@@ -162,7 +162,7 @@ __global__ void k_split_reset(SplitState St, int n_int) {
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
 hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
   const int nw = L.waves;
-  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw);
+  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw, RPS == 64);
   const size_t lds_u = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, 0);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
@@ -195,7 +195,7 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   const int nw = L.waves;
-  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw);
+  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw, RPS == 64);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS>;
