@@ -34,6 +34,20 @@ BYTES_PER_SAMPLE = 32 + 32 + 16 + 1        # data c64 2x2, model c64 2x2, 4 fp32
 BYTES_PER_ROW = 12                          # ant1, ant2, row_time int32
 
 
+def pass_bytes(vis, term_h):
+    """Algorithmic HBM bytes of one solver pass over each solution interval of a
+    term, [n_gt][n_gf]: samples x (data + model over every direction + weights +
+    flag) + rows x row metadata (read once per 64-channel chunk)."""
+    import numpy as np
+    elt = vis.data.element_size()                           # one complex correlation
+    per_sample = 4 * elt * (1 + int(vis.model.shape[2])) + int(vis.weight.shape[2]) * vis.weight.element_size() + 1
+    t_map = np.asarray(term_h.t_map.cpu() if hasattr(term_h.t_map, "cpu") else term_h.t_map)
+    f_map = np.asarray(term_h.f_map.cpu() if hasattr(term_h.f_map, "cpu") else term_h.f_map)
+    rows = np.bincount(t_map[vis.row_time.cpu().numpy()], minlength=int(term_h.n_gt)).astype(np.float64)
+    chans = np.bincount(f_map, minlength=int(term_h.n_gf)).astype(np.float64)
+    return rows[:, None] * chans[None, :] * per_sample + rows[:, None] * BYTES_PER_ROW * np.ceil(chans[None, :] / 64.0)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -133,12 +147,15 @@ def leg_batch(ctx, dev, n_problems: int = 256, steps: int = 3):
         return ms
 
     default_ms = timed_runs(steps)
+    reset()                      # tune on the starting gains, as the timed runs solve
     tt = time.perf_counter()
     b.tune(reps=1)
     tune_s = time.perf_counter() - tt
     tuned_ms = timed_runs(steps)
     sched = b.schedule()
     iters = np.concatenate([st["iters"].cpu().numpy().ravel() for st in b.stats])
+    alg_bytes = float(sum(np.sum(np.maximum(st["iters"].cpu().numpy().reshape(pass_bytes(v, th).shape), 1)
+                                 * pass_bytes(v, th)) for st, (v, _, th) in zip(b.stats, probs)))
     mixed = [t.gains.clone() for _, t, _ in probs]
     d_plain = max(float((m - g).abs().max()) for m, g in zip(mixed, plain_gains))
     b.close()
@@ -182,6 +199,9 @@ def leg_batch(ctx, dev, n_problems: int = 256, steps: int = 3):
                vis_per_s_batched=n_samples / (np.mean(tuned_ms) * 1e-3),
                speedup_vs_plain=plain_ms / float(np.mean(tuned_ms)),
                mean_iterations=float(iters.mean()), schedule=sched,
+               algorithmic_gb=alg_bytes / 1e9,
+               achieved_gbs_batched=alg_bytes / (np.mean(tuned_ms) * 1e-3) / 1e9,
+               hbm_frac_batched=alg_bytes / (np.mean(tuned_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS,
                max_abs_diff_batched_vs_plain=d_plain,
                rel_err_mixed_vs_fp64_gpu=e_mf, rel_err_mixed_vs_oracle=e_mo, rel_err_fp64_vs_oracle=e_fo,
                oracle_problems=picked)
@@ -282,24 +302,29 @@ def leg_chain(ctx, dev, n_epoch: int = 2):
             t1 = time.perf_counter()
             st = ctx.solve(vis, chain, n, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
             torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t1)
+            it = st["iters"].cpu().numpy()
+            gb = float(np.sum(np.maximum(it, 1) * pass_bytes(vis, p.chain[n]))) / 1e9
             terms.append(dict(epoch=e, term=t.name, intervals=int(t.n_gt * t.n_gf),
-                              split_parts=int(ctx.last_split_parts()),
-                              ms=1e3 * (time.perf_counter() - t1),
-                              mean_iterations=float(st["iters"].float().mean().item()),
-                              converged=float(st["converged"].float().mean().item())))
+                              split_parts=int(ctx.last_split_parts()), ms=ms,
+                              mean_iterations=float(it.mean()), max_iterations=int(it.max()),
+                              converged=float(st["converged"].float().mean().item()),
+                              algorithmic_gb=gb, achieved_gbs=gb / (ms * 1e-3)))
             d = terms[-1]
             log(f"chain: epoch {e} term {d['term']}: {d['ms']:.0f} ms, {d['intervals']} intervals, "
-                f"parts {d['split_parts']}, mean iterations {d['mean_iterations']:.2f}, "
-                f"converged {100 * d['converged']:.1f}%")
+                f"parts {d['split_parts']}, mean iterations {d['mean_iterations']:.2f} (max "
+                f"{d['max_iterations']}), converged {100 * d['converged']:.1f}%, {gb:.1f} GB -> "
+                f"{d['achieved_gbs']:.0f} GB/s")
     t2 = time.perf_counter()
     resid = ctx.residual(vis, chain, stream=stream)
     torch.cuda.synchronize()
-    t_total = time.perf_counter() - ts
+    t_end = time.perf_counter()
+    t_total = t_end - ts
     use = (vis.flag == 0)
     rms = float(torch.sqrt((resid.abs() ** 2).sum(-1)[use].mean() / 4).item())
     sigma = float(p.meta["sigma"])
     out = dict(samples=n_samples, directions=int(vis.model.shape[2]), delay_init_ms=1e3 * t_delay,
-               terms=terms, residual_ms=1e3 * (time.perf_counter() - t2), total_s=t_total,
+               terms=terms, residual_ms=1e3 * (t_end - t2), total_s=t_total,
                vis_per_s=n_samples / t_total, residual_rms=rms, noise_rms=sigma * math.sqrt(2))
     log(f"chain: delay init {1e3 * t_delay:.1f} ms; " + "; ".join(
         f"{d['term']}{d['epoch']} {d['ms']:.0f} ms it {d['mean_iterations']:.1f} parts {d['split_parts']}"
@@ -355,11 +380,7 @@ def main():
     resid = torch.empty_like(vis.data)
     stream = torch.cuda.current_stream()
     n_int = int(term0.n_gt * term0.n_gf)
-    rows_per_int = np.bincount(np.asarray(prob.chain[0].t_map)[vis.row_time.cpu().numpy()],
-                               minlength=term0.n_gt)
-    chans_per_int = np.bincount(np.asarray(prob.chain[0].f_map), minlength=term0.n_gf)
-    int_bytes = (rows_per_int[:, None] * chans_per_int[None, :] * BYTES_PER_SAMPLE
-                 + rows_per_int[:, None] * BYTES_PER_ROW * np.ceil(chans_per_int[None, :] / 64.0))
+    int_bytes = pass_bytes(vis, prob.chain[0])
 
     def step():
         term0.gains.copy_(init_gains)

@@ -291,9 +291,10 @@ typedef struct qc_batch qc_batch;
 qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_problem,
                           const qc_solve_opts* opts, qc_batch** out);
 /* Autotuner: for every bucket, time each (waves per workgroup in {1,2,4,8},
- * rows per step in {1,2,4}) on the batch itself (best of `reps` runs from
- * the same initial gains, which are restored afterwards), keep the fastest
- * and re-capture the graph. */
+ * rows per step in {1,2,4}) on the batch itself (best of `reps` runs, each
+ * from the gains present at the call, which are restored afterwards), keep
+ * the fastest and re-capture the graph.  Call it with the starting gains in
+ * place: from converged gains every trial times only one or two updates. */
 qc_status qc_batch_tune(qc_batch* batch, int32_t reps);
 /* Launch the graph, ordered after earlier work on `stream`; later work on
  * `stream` waits for it. */

@@ -274,6 +274,7 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_chhi);
   hipFree(ctx->d_dh);
   hipFree(ctx->d_partials);
+  hipFree(ctx->d_otab);
   hipFree(ctx->d_passes);
   hipFree(ctx->d_done);
   hipFree(ctx->d_active);
@@ -376,12 +377,17 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   if (parts > 1 && opts->chisq_ref)
     return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take chisq_ref");
   ctx->last_split_parts = parts;
-  size_t lds = 0;
-  hipError_t e = hipSuccess;
-  if (parts <= 1) {
-    HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
-    e = launch_solve(L, nullptr, s, &lds);
-  } else {
+  // diagonal chains: the direction-independent terms other than the active
+  // one are fixed during the solve; tabulate their product once
+  const bool single_chain = (n_term == 1 && vis->n_dir == 1 && ta.n_gdir == 1);
+  bool other_di = false;
+  for (int j = 0; j < n_term; ++j)
+    if (j != active && chain[j].n_gdir == 1) other_di = true;
+  const bool want_tab = L.diag_chain && !single_chain && other_di;
+  L.otab = nullptr;
+  if (want_tab) HIP_TRY(ctx, grow(ctx->d_otab, ctx->otab_cap, chain_table_bytes(L)));
+  SplitLaunch P;
+  if (parts > 1) {
     const int nv = ta.type == QC_TERM_DIAGONAL ? 6 : (ta.type == QC_TERM_COMPLEX2X2 ? 16 : 4);
     const int ng = ta.n_gdir == 1 ? 1 : 4;
     const size_t stride = (size_t)vis->n_ant * ng * nv + 1;
@@ -389,23 +395,34 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
     HIP_TRY(ctx, grow(ctx->d_passes, ctx->passes_cap, (size_t)n_int));
     HIP_TRY(ctx, grow(ctx->d_done, ctx->done_cap, (size_t)n_int));
     HIP_TRY(ctx, grow(ctx->d_active, ctx->active_cap, 1));
-    SplitLaunch P;
     P.n_part = parts;
     P.partials = ctx->d_partials;
     P.state.passes = ctx->d_passes;
     P.state.done = ctx->d_done;
     P.state.n_active = ctx->d_active;
-    HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  }
+  size_t lds = 0;
+  hipError_t e = hipSuccess;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  if (want_tab) {
+    e = launch_chain_table(L, ctx->d_otab, s);
+    L.otab = ctx->d_otab;
+  }
+  if (e != hipSuccess) {
+    // reported below
+  } else if (parts <= 1) {
+    e = launch_solve(L, nullptr, s, &lds);
+  } else {
     P.phase = 0;
     e = launch_solve(L, &P, s, &lds);
     P.phase = 1;
     for (int k = 0; k <= opts->max_iter && e == hipSuccess; ++k) {
       e = launch_solve(L, &P, s, &lds);
       if (e != hipSuccess) break;
-      int active = 0;
-      HIP_TRY(ctx, hipMemcpyAsync(&active, ctx->d_active, sizeof(int), hipMemcpyDeviceToHost, s));
+      int n_active = 0;
+      HIP_TRY(ctx, hipMemcpyAsync(&n_active, ctx->d_active, sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_TRY(ctx, hipStreamSynchronize(s));
-      if (active <= 0) break;
+      if (n_active <= 0) break;
     }
   }
   if (e != hipSuccess) {

@@ -60,6 +60,8 @@ __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
     J.err = B.err;
     J.chisq_ref = nullptr;
     J.restarted = nullptr;
+    J.partial = nullptr;
+    J.otab = nullptr;
     if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, true, 1, RPS>(J);
     else solve_interval<KIND_C2X2, S, T, true, 1, RPS>(J);
   }

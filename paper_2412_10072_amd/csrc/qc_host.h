@@ -40,6 +40,8 @@ struct qc_ctx {
   int n_cu = 0;               // compute units of the device
   double* d_partials = nullptr;
   size_t partials_cap = 0;
+  unsigned char* d_otab = nullptr;    // fixed chain factors of diagonal chains
+  size_t otab_cap = 0;
   int* d_passes = nullptr;
   size_t passes_cap = 0;
   uint8_t* d_done = nullptr;

@@ -232,7 +232,15 @@ struct SolveLaunch {
   int rows_per_step;          // 0: the kernel default
   const double* chisq_ref;    // may be null
   uint8_t* restarted;         // may be null
+  // diagonal chains: product of the direction-independent terms other than
+  // the active one, [n_time][n_ant][n_chan][2 hands] complex of the compute
+  // precision, or null (then formed per sample)
+  const void* otab;
 };
+
+// Fills L.otab (see above) on `stream`; `bytes` of table memory are needed.
+size_t chain_table_bytes(const SolveLaunch& L);
+hipError_t launch_chain_table(const SolveLaunch& L, void* table, hipStream_t stream);
 
 // Split schedule (see qc_solve.hip): per-interval iteration state in device
 // memory; phase 0 resets it, phase 1 runs one pass + update over every

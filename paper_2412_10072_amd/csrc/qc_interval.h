@@ -457,6 +457,7 @@ struct Job {
   const double* chisq_ref;   // per interval: restart from unit gains if chi^2 at the start exceeds it
   uint8_t* restarted;        // per interval: 1 if that restart happened
   double* partial;           // pass-only mode: [slot values + 1] FP64 blocks and chi^2 of these rows
+  const void* otab;          // diagonal chains: fixed direction-independent factors, or null
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
@@ -785,14 +786,23 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           const ChainArgs& CH = *J.CH;
           const int act = CH.active;
           const int n_term = CH.n_term;
-          // direction-independent part of o (terms with one gain direction)
+          // direction-independent part of o (terms with one gain direction):
+          // from the precomputed table when there is one
           cx<T> op0 = cone<T>(), op1 = cone<T>(), oq0 = cone<T>(), oq1 = cone<T>();
-          for (int j = 0; j < n_term; ++j) {
-            if (j == act || CH.t[j].n_gdir > 1) continue;
-            const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, 0, nu);
-            const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, 0, nu);
-            op0 = op0 * Jp.a; op1 = op1 * Jp.d;
-            oq0 = oq0 * Jq.a; oq1 = oq1 * Jq.d;
+          if (J.otab) {
+            const cx<T>* ot = reinterpret_cast<const cx<T>*>(J.otab);
+            const size_t tp_ = (((size_t)t * n_ant + p) * n_chan + cc) * 2;
+            const size_t tq_ = (((size_t)t * n_ant + q) * n_chan + cc) * 2;
+            op0 = ot[tp_]; op1 = ot[tp_ + 1];
+            oq0 = ot[tq_]; oq1 = ot[tq_ + 1];
+          } else {
+            for (int j = 0; j < n_term; ++j) {
+              if (j == act || CH.t[j].n_gdir > 1) continue;
+              const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, 0, nu);
+              const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, 0, nu);
+              op0 = op0 * Jp.a; op1 = op1 * Jp.d;
+              oq0 = oq0 * Jq.a; oq1 = oq1 * Jq.d;
+            }
           }
           m22<T> Bs[NG], Bsc[NG];
           cx<T> gp0[NG], gp1[NG], gq0[NG], gq1[NG];
@@ -802,22 +812,28 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
             Bsc[g] = mzero<T>();
             gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
           }
-          m22<T> Vm = mzero<T>();
-          for (int d = 0; d < n_dir; ++d) {
-            const int gd = TA.d_map[d];
-            cx<T> hp0, hp1, hq0, hq1;            // active gains of p and q
+          // active gains of p and q for gain direction gd
+          auto active_diag = [&](int gd, cx<T>& a0, cx<T>& a1, cx<T>& b0, cx<T>& b1) {
             if constexpr (KIND == KIND_DELAY) {
               const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
-              hp0 = phasor_turns<T>(nu * tp.x);
-              hp1 = phasor_turns<T>(nu * tp.y);
-              hq0 = phasor_turns<T>(nu * tq.x);
-              hq1 = phasor_turns<T>(nu * tq.y);
+              a0 = phasor_turns<T>(nu * tp.x);
+              a1 = phasor_turns<T>(nu * tp.y);
+              b0 = phasor_turns<T>(nu * tq.x);
+              b1 = phasor_turns<T>(nu * tq.y);
             } else {
               const cx<T>* gpp = gc + (p * NG + gd) * 4;
               const cx<T>* gqq = gc + (q * NG + gd) * 4;
-              hp0 = gpp[0]; hp1 = gpp[3];
-              hq0 = gqq[0]; hq1 = gqq[3];
+              a0 = gpp[0]; a1 = gpp[3];
+              b0 = gqq[0]; b1 = gqq[3];
             }
+          };
+          cx<T> hp0, hp1, hq0, hq1;
+          // one gain direction: every model direction maps to it, look up once
+          if constexpr (NG == 1) active_diag(0, hp0, hp1, hq0, hq1);
+          m22<T> Vm = mzero<T>();
+          for (int d = 0; d < n_dir; ++d) {
+            const int gd = NG == 1 ? 0 : TA.d_map[d];
+            if constexpr (NG > 1) active_diag(gd, hp0, hp1, hq0, hq1);
             // direction-dependent part of o
             cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
             for (int j = 0; j < n_term; ++j) {
@@ -884,10 +900,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
             Bsc[g] = mzero<T>();
             gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
           }
-          m22<T> Vm = mzero<T>();
-          for (int d = 0; d < n_dir; ++d) {
-            const int gd = TA.d_map[d];
-            m22<T> Gp, Gq;
+          // active gains of p and q for gain direction gd
+          auto active_jones = [&](int gd, m22<T>& Gp, m22<T>& Gq) {
             if constexpr (KIND == KIND_DELAY) {
               const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
               Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
@@ -901,6 +915,13 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
                 Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
               }
             }
+          };
+          m22<T> Gp, Gq;
+          if constexpr (NG == 1) active_jones(0, Gp, Gq);
+          m22<T> Vm = mzero<T>();
+          for (int d = 0; d < n_dir; ++d) {
+            const int gd = NG == 1 ? 0 : TA.d_map[d];
+            if constexpr (NG > 1) active_jones(gd, Gp, Gq);
             const m22<T> Rp = chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, p, d, nu);
             const m22<T> Rq = chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, q, d, nu);
             const m22<T> Cp = rowscale(ap0, ap1, mmul(Gp, Rp));

@@ -6,8 +6,8 @@
 //   CORRECT : out = C_p^-1 D C_q^-H  for a direction-independent chain; 0 where
 //             C_p or C_q is singular.
 //
-// Consecutive threads take consecutive channels of a row, so every load and
-// store of a wavefront is contiguous.  Arithmetic is in the data precision.
+// Each wavefront takes one row at a time (antennas and time are uniform) and
+// its lanes consecutive channels, so every load and store is contiguous.  Arithmetic is in the data precision.
 
 #include "qc_internal.h"
 
@@ -80,13 +80,16 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
   using T = S;
   const VisArgs& V = L.vis;
   const ChainArgs& CH = L.chain;
-  const size_t n = (size_t)V.n_row * V.n_chan;
   const S* Dp = reinterpret_cast<const S*>(V.data);
   const S* Mp = reinterpret_cast<const S*>(V.model);
   S* Op = reinterpret_cast<S*>(L.out);
-  for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
-    const size_t r = s / V.n_chan;
-    const int c = (int)(s - r * V.n_chan);
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (long long r = (long long)blockIdx.x * nw + wave; r < V.n_row; r += (long long)gridDim.x * nw)
+  for (int c = lane; c < V.n_chan; c += 64) {
+    // one row per wavefront (antennas and time uniform), lanes over channels
+    const size_t s = (size_t)r * V.n_chan + c;
     const int p = V.ant1[r], q = V.ant2[r], t = V.row_time[r];
     if ((unsigned)p >= (unsigned)V.n_ant || (unsigned)q >= (unsigned)V.n_ant) continue;
     const double nu = V.freq[c];
@@ -147,7 +150,7 @@ template <typename S>
 hipError_t launch_s(const OutputLaunch& L, hipStream_t stream) {
   const size_t n = (size_t)L.vis.n_row * L.vis.n_chan;
   if (n == 0) return hipSuccess;
-  size_t blocks = (n + 255) / 256;
+  size_t blocks = ((size_t)L.vis.n_row + 3) / 4;     // 4 wavefronts of one row each
   if (blocks > 256 * 64) blocks = 256 * 64;
   const dim3 g((unsigned)blocks), b(256);
   if (L.diag_chain) {

@@ -65,7 +65,19 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   J.err = L.err;
   J.chisq_ref = L.chisq_ref;
   J.restarted = L.restarted;
+  J.otab = L.otab;
   solve_interval<KIND, S, T, CHM, NG, RPS>(J);
+}
+
+// Workgroups go to the 8 XCDs round-robin by block index.  This maps block
+// indices to logical indices so that each XCD receives one contiguous run of
+// them (a bijection of [0, n)); workgroups sharing an XCD's L2 then work on
+// neighbouring logical items at the same time.
+__device__ __forceinline__ unsigned xcd_order(unsigned bid, unsigned n) {
+  constexpr unsigned X = 8;
+  const unsigned per = n / X, rem = n % X;
+  const unsigned x = bid % X, k = bid / X;
+  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
 // Split schedule for intervals too large for one workgroup: every interval's
@@ -78,8 +90,11 @@ __global__ void __launch_bounds__(512) k_split_pass(SolveLaunch L, int n_part, d
                                                     const uint8_t* done) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
-  const int interval = blockIdx.x / n_part;
-  const int part = blockIdx.x - interval * n_part;
+  const int n_int = TA.n_gt * n_gf;
+  // (part, interval) pairs, interval fastest, in XCD-contiguous runs
+  const unsigned lid = xcd_order(blockIdx.x, gridDim.x);
+  const int part = (int)(lid / (unsigned)n_int);
+  const int interval = (int)(lid - (unsigned)part * n_int);
   if (done[interval]) return;
   const int gt = interval / n_gf;
   const int gf = interval - gt * n_gf;
@@ -109,7 +124,8 @@ __global__ void __launch_bounds__(512) k_split_pass(SolveLaunch L, int n_part, d
   J.err = L.err;
   J.chisq_ref = nullptr;
   J.restarted = nullptr;
-  J.partial = partials + (size_t)blockIdx.x * stride;
+  J.partial = partials + ((size_t)interval * n_part + part) * stride;
+  J.otab = L.otab;
   solve_interval<KIND, S, T, CHM, NG, RPS, true>(J);
 }
 
@@ -147,7 +163,34 @@ __global__ void __launch_bounds__(256) k_split_update(SolveLaunch L, int n_part,
   J.chisq_ref = nullptr;
   J.restarted = nullptr;
   J.partial = nullptr;
+  J.otab = nullptr;
   split_update<KIND, T, NG>(J, partials + (size_t)interval * n_part * stride, n_part, St);
+}
+
+// Fixed direction-independent factors of a diagonal chain: for every time,
+// antenna and channel, the product of the diagonals of the terms with one
+// gain direction other than the active one (diagonal matrices commute, so
+// the position of the active term does not matter).  One workgroup per
+// (time, antenna), lanes over channels.
+template <typename T>
+__global__ void __launch_bounds__(256) k_chain_table(SolveLaunch L, cx<T>* out) {
+  const ChainArgs& CH = L.chain;
+  const int n_ant = L.vis.n_ant, n_chan = L.vis.n_chan;
+  const int t = blockIdx.x / n_ant;
+  const int a = blockIdx.x - t * n_ant;
+  for (int c = threadIdx.x; c < n_chan; c += blockDim.x) {
+    const double nu = L.vis.freq[c];
+    cx<T> h0 = cone<T>(), h1 = cone<T>();
+    for (int j = 0; j < CH.n_term; ++j) {
+      if (j == CH.active || CH.t[j].n_gdir > 1) continue;
+      const m22<T> J = term_jones<T>(CH.t[j], n_ant, t, c, a, 0, nu);
+      h0 = h0 * J.a;
+      h1 = h1 * J.d;
+    }
+    const size_t o = (((size_t)t * n_ant + a) * n_chan + c) * 2;
+    out[o] = h0;
+    out[o + 1] = h1;
+  }
 }
 
 __global__ void k_split_reset(SplitState St, int n_int) {
@@ -255,6 +298,23 @@ hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t s
 }
 
 }  // namespace
+
+size_t chain_table_bytes(const SolveLaunch& L) {
+  const size_t elt = L.prec_mixed ? sizeof(cx<float>) : sizeof(cx<double>);
+  return (size_t)L.vis.n_time * L.vis.n_ant * L.vis.n_chan * 2 * elt;
+}
+
+hipError_t launch_chain_table(const SolveLaunch& L, void* table, hipStream_t stream) {
+  const unsigned grid = (unsigned)((size_t)L.vis.n_time * L.vis.n_ant);
+  if (grid == 0) return hipSuccess;
+  if (L.prec_mixed)
+    hipLaunchKernelGGL(k_chain_table<float>, dim3(grid), dim3(256), 0, stream, L,
+                       reinterpret_cast<cx<float>*>(table));
+  else
+    hipLaunchKernelGGL(k_chain_table<double>, dim3(grid), dim3(256), 0, stream, L,
+                       reinterpret_cast<cx<double>*>(table));
+  return hipGetLastError();
+}
 
 hipError_t launch_solve(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
   const int kind = L.chain.t[L.chain.active].kind;

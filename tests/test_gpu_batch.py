@@ -122,6 +122,8 @@ def test_batch_graph_replays_and_tuning(qc_lib):
     for rep in (1, 2):
         for a, c in zip(outs[0], outs[rep]):
             assert np.array_equal(a, c)
+    for (_, t), g0 in zip(dev, init):
+        t.gains.copy_(g0)
     b.tune(reps=1)
     sched = b.schedule()
     assert all(s["tuned_ms"] > 0 for s in sched if s["items"] > 0)
