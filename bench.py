@@ -34,6 +34,41 @@ BYTES_PER_SAMPLE = 32 + 32 + 16 + 1        # data c64 2x2, model c64 2x2, 4 fp32
 BYTES_PER_ROW = 12                          # ant1, ant2, row_time int32
 
 
+# FP32 arithmetic of the full-Jones solver step per sample and pass, counted in
+# the ISA of the single-term kernel: 200 fused multiply-adds (2 flop) and 40
+# multiplies
+FLOP_PER_SAMPLE_C2X2 = 2 * 200 + 40
+
+
+def interval_samples(vis, term_h):
+    """Samples (rows x channels) of each solution interval of a term, [n_gt][n_gf]."""
+    import numpy as np
+    t_map = np.asarray(term_h.t_map.cpu() if hasattr(term_h.t_map, "cpu") else term_h.t_map)
+    f_map = np.asarray(term_h.f_map.cpu() if hasattr(term_h.f_map, "cpu") else term_h.f_map)
+    rows = np.bincount(t_map[vis.row_time.cpu().numpy()], minlength=int(term_h.n_gt)).astype(np.float64)
+    chans = np.bincount(f_map, minlength=int(term_h.n_gf)).astype(np.float64)
+    return rows[:, None] * chans[None, :]
+
+
+def copy_bandwidth(dev, n_bytes: int = 1 << 32, reps: int = 5) -> float:
+    """Device-to-device copy of n_bytes (read + write counted), best of reps, GB/s:
+    the streaming rate this GPU sustains, beside the nominal HBM peak."""
+    import torch
+    src = torch.empty(n_bytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n_bytes / (best * 1e-3) / 1e9
+
+
 def pass_bytes(vis, term_h):
     """Algorithmic HBM bytes of one solver pass over each solution interval of a
     term, [n_gt][n_gf]: samples x (data + model over every direction + weights +
@@ -381,6 +416,7 @@ def main():
     stream = torch.cuda.current_stream()
     n_int = int(term0.n_gt * term0.n_gf)
     int_bytes = pass_bytes(vis, prob.chain[0])
+    int_samples = interval_samples(vis, prob.chain[0])
 
     def step():
         term0.gains.copy_(init_gains)
@@ -408,6 +444,7 @@ def main():
 
     ms_per_step = 1e3 * t_total / args.steps
     value = n_samples / (t_total / args.steps)
+    copy_gbs = copy_bandwidth(dev)
     k_ms = float(np.mean(kern_ms))
     achieved = float(np.mean(alg_bytes)) / (k_ms * 1e-3) / 1e9
     it = iters_all[-1]
@@ -433,10 +470,15 @@ def main():
                                "channels, complex64, 20 sources, 10% flags, interval 1 time x 64 channels, "
                                "tol 1e-6, plain MIXED solver + residual pass",
                    "samples": n_samples, "intervals": n_int, "mean_iterations": float(it.mean()),
+                   "iterations_histogram": {int(k): int(v) for k, v in zip(*np.unique(it, return_counts=True))},
                    "converged_fraction": conv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_solve_fused",
-                     "kernel_ms": k_ms, "algorithmic_gb_per_launch": float(np.mean(alg_bytes)) / 1e9},
+                     "kernel_ms": k_ms, "algorithmic_gb_per_launch": float(np.mean(alg_bytes)) / 1e9,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "flop_per_sample_pass": FLOP_PER_SAMPLE_C2X2,
+                     "fp32_tflops": FLOP_PER_SAMPLE_C2X2 * float(np.sum(np.maximum(it, 1) * int_samples))
+                                    / (k_ms * 1e-3) / 1e12},
     }
     tr = measured_traffic()
     if tr is not None and args.n_time == 600:

@@ -357,19 +357,27 @@ __device__ __forceinline__ m22<T> load_m22(const S* base, size_t elem) {
 
 template <typename S, typename T>
 __device__ __forceinline__ void load_w(const S* base, size_t s, int n_wcorr, T& w0, T& w1, T& w2, T& w3) {
+  // The one-weight value is spread to the four correlations by selects after
+  // the branch, not by copies inside it: a copy of a load result would make
+  // the wavefront wait for that load at the branch.
+  T a, b = T(0), c = T(0), d = T(0);
   if (n_wcorr == 4) {
     if constexpr (sizeof(S) == 4) {
       const float4 u = reinterpret_cast<const float4*>(base)[s];
-      w0 = (T)u.x; w1 = (T)u.y; w2 = (T)u.z; w3 = (T)u.w;
+      a = (T)u.x; b = (T)u.y; c = (T)u.z; d = (T)u.w;
     } else {
       const double2* p = reinterpret_cast<const double2*>(base) + 2 * s;
-      const double2 a = p[0], b = p[1];
-      w0 = (T)a.x; w1 = (T)a.y; w2 = (T)b.x; w3 = (T)b.y;
+      const double2 x = p[0], y = p[1];
+      a = (T)x.x; b = (T)x.y; c = (T)y.x; d = (T)y.y;
     }
   } else {
-    const T x = (T)base[s];
-    w0 = w1 = w2 = w3 = x;
+    a = (T)base[s];
   }
+  const bool four = n_wcorr == 4;
+  w0 = a;
+  w1 = four ? b : a;
+  w2 = four ? c : a;
+  w3 = four ? d : a;
 }
 
 // Component-wise selects: a conditional between whole structs becomes a
@@ -467,7 +475,9 @@ template <int KIND, typename T, int NG>
 __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool lane_rows = false) {
   const size_t n_slots = (size_t)n_ant * NG;
   const size_t nv = KindInfo<KIND>::NV;
-  size_t b = sizeof(double) * n_slots * nv + sizeof(double2) * n_slots * 4 + sizeof(double) * 48 +
+  // the FP64 block totals are an LDS array only in the split schedule's
+  // update kernel (nw == 0); the streaming kernels sum their wave slots
+  size_t b = (nw == 0 ? sizeof(double) * n_slots * nv : 0) + sizeof(double2) * n_slots * 4 + sizeof(double) * 48 +
              sizeof(cx<T>) * n_slots * 4 + sizeof(int) * (n_slots + 4);
   b = (b + 15) & ~size_t(15);
   return b + sizeof(T) * n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1) +
@@ -475,10 +485,12 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool 
 }
 
 // One FP64 block solve per (antenna, gain direction) of an interval from its
-// accumulated blocks `tot`, the damped update of the LDS gains, and the
+// accumulated blocks, the damped update of the LDS gains, and the
 // convergence test over the interval (uniform over the workgroup).
-template <int KIND, typename T, int NG>
-__device__ __forceinline__ bool update_and_test(const double* tot, double2* gm, cx<T>* gc, int* gfl, double* red,
+// `sum(i)` returns the FP64 total of block value i (slot * NV + k); the
+// block values are read before the first barrier inside.
+template <int KIND, typename T, int NG, typename Sum>
+__device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<T>* gc, int* gfl, double* red,
                                                 int* ctl, int n_ant, int n_gdir, int k_upd, int damping,
                                                 double nu_max, double tol, int* err) {
   constexpr int NV = KindInfo<KIND>::NV;
@@ -490,7 +502,9 @@ const double alpha = step_length(damping, k_upd);
   for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
     const int ant = i / n_gdir, gd = i - ant * n_gdir;
     const int slot = ant * NG + gd;
-    const double* h = tot + (size_t)slot * NV;
+    double h[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) h[k] = sum((size_t)slot * NV + k);
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < NV; ++k) finite = finite && isfinite(h[k]);
@@ -628,7 +642,6 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 
   // ---- LDS carve-up ----
   unsigned char* lp = qc_lds;
-  double* tot = reinterpret_cast<double*>(lp);            lp += sizeof(double) * slot_vals;
   double2* gm = reinterpret_cast<double2*>(lp);           lp += sizeof(double2) * n_slots * 4;
   double* red = reinterpret_cast<double*>(lp);            lp += sizeof(double) * 2 * 16;
   double* chiw = reinterpret_cast<double*>(lp);           lp += sizeof(double) * 16;
@@ -744,13 +757,19 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
         const bool inb = c < c_hi;
         const int cc = inb ? c : c_lo;
         const size_t s = (size_t)r * n_chan + cc;
-        const bool use = inb && row_ok && (V.flag[s] == 0);
-        const double nu = V.freq[cc];
-        const T tpn = (T)(TWO_PI * nu);
+        // Weights first (their load width is a uniform branch on n_wcorr),
+        // then the flag and the data, unconditionally (the indices are in
+        // range): all of them are in flight together.  Bitwise & keeps the
+        // flag load out of a branch.
         T w0, w1, w2, w3;
         load_w<S, T>(Wp, s, V.n_wcorr, w0, w1, w2, w3);
+        const uint8_t fl = V.flag[s];
+        const m22<T> Draw = load_m22<S, T>(Dp, s);
+        const bool use = inb & row_ok & (fl == 0);
+        const double nu = V.freq[cc];
+        const T tpn = (T)(TWO_PI * nu);
         w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
-        const m22<T> D = select_m(use, load_m22<S, T>(Dp, s));
+        const m22<T> D = select_m(use, Draw);
 
         if constexpr (SINGLE) {
           // chain = the active term alone: C_p = G_p, C_q = G_q
@@ -977,19 +996,19 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     }
     __syncthreads();
 
-    // ---- combine the wave slots in a fixed order (FP64) ----
-    for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) {
+    // ---- the wave slots summed in a fixed order (FP64), where needed ----
+    auto slot_sum = [&](size_t i) -> double {
       double sum = 0.0;
       for (int w = 0; w < nw; ++w) {
         sum += (double)acc_s[(size_t)w * slot_vals + i];
         if constexpr (KAHAN) sum -= (double)acc_c[(size_t)w * slot_vals + i];
       }
-      tot[i] = sum;
-    }
+      return sum;
+    };
     double chi_now = 0.0;
     for (int w = 0; w < nw; ++w) chi_now += chiw[w];
     if constexpr (PASS_ONLY) {
-      for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) J.partial[i] = tot[i];
+      for (int i = threadIdx.x; i < slot_vals; i += blockDim.x) J.partial[i] = slot_sum(i);
       if (threadIdx.x == 0) J.partial[slot_vals] = chi_now;
       __syncthreads();
       return;
@@ -1014,8 +1033,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     __syncthreads();
     if (it >= J.max_iter) break;
     const int k_upd = it + 1;
-    const bool conv = update_and_test<KIND, T, NG>(tot, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd, J.damping,
-                                                   nu_max, J.tol, J.err);
+    const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd,
+                                                   J.damping, nu_max, J.tol, J.err);
     iters = k_upd;
     if (conv) {
       converged = 1;
@@ -1120,8 +1139,8 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
     finish = true;
   } else {
     const int k_upd = pass + 1;
-    conv = update_and_test<KIND, T, NG>(tot, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd, J.damping, nu_max, J.tol,
-                                        J.err);
+    conv = update_and_test<KIND, T, NG>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, red, ctl, n_ant,
+                                        n_gdir, k_upd, J.damping, nu_max, J.tol, J.err);
     for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
       const int slot = ant * NG + gd;
