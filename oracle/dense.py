@@ -30,7 +30,7 @@ def _residual_vector(vis, chain, s):
 
 def unknown_index(vis, term):
     """Ordered list of unknowns (antenna, gdir, entry) of one interval."""
-    U = UNKNOWNS[term.kind] if term.kind != "delay" else (0, 1)
+    U = UNKNOWNS[term.kind] if term.kind not in ("delay", "phase", "amplitude") else (0, 1)
     return [(a, g, u) for a in range(vis.n_ant) for g in range(int(term.n_gdir)) for u in U]
 
 

@@ -40,7 +40,9 @@ def term_jones(term, vis, rows, chans, ants, d):
     """Jones matrix of one chain term for antenna `ants` at samples (rows, chans),
     direction d.  The gain is looked up through the term's time/frequency/direction
     maps.  Diagonal terms use only entries XX and YY; a delay term is
-    diag(exp(2 pi i nu tau_X), exp(2 pi i nu tau_Y)) at the channel frequency nu."""
+    diag(exp(2 pi i nu tau_X), exp(2 pi i nu tau_Y)) at the channel frequency nu;
+    a phase-only term diag(exp(i phi_X), exp(i phi_Y)); an amplitude-only term
+    diag(a_X, a_Y) with real a (paper Section 2.4, Scenario 1)."""
     t = np.asarray(vis.row_time)[rows]
     gt = np.asarray(term.t_map)[t]
     gf = np.asarray(term.f_map)[chans]
@@ -52,6 +54,14 @@ def term_jones(term, vis, rows, chans, ants, d):
         nu = np.asarray(vis.chan_freq, dtype=np.float64)[chans]
         J[:, 0, 0] = np.exp(2j * np.pi * nu * tau[:, 0])
         J[:, 1, 1] = np.exp(2j * np.pi * nu * tau[:, 1])
+    elif term.kind == "phase":
+        phi = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]      # [S][2]
+        J[:, 0, 0] = np.exp(1j * phi[:, 0])
+        J[:, 1, 1] = np.exp(1j * phi[:, 1])
+    elif term.kind == "amplitude":
+        amp = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]      # [S][2]
+        J[:, 0, 0] = amp[:, 0]
+        J[:, 1, 1] = amp[:, 1]
     else:
         g = np.asarray(term.gains, dtype=np.complex128)[gt, gf, ants, gd]      # [S][4]
         if term.kind == "diag":

@@ -9,20 +9,25 @@ paper is silent or inconsistent (see the design notes of the repository):
   what is computed here.
 * Blocks.  The kept diagonal blocks are per (interval, antenna, gain
   direction): 4x4 for a complex 2x2 term, 2x2 over (XX, YY) for a diagonal
-  term, real 2x2 over (tau_X, tau_Y) for a delay term.
+  term, real 2x2 over (tau_X, tau_Y) for a delay term, and the same real
+  form over (phi_X, phi_Y) or (a_X, a_Y) for phase- and amplitude-only terms
+  (Section 2.4, Scenario 1: eq. jhj_case1, eq. jhwr_case1).
 * Conjugate baselines are folded in (eq. jhj_entry_simplified): a row (p,q)
   also serves antenna q as the virtual row (q,p) with D^H, M^H and the weights
   permuted by P.
 * Damping (the paper leaves the step length open, noting that the extension to
   Levenberg-Marquardt is trivial): x <- x + alpha_k Delta with alpha = 1
   (full), 1/2 (half), or 1 on odd / 1/2 on even updates (alternate).  The
-  default picks alternate for direction-independent complex/diagonal terms,
-  half for direction-dependent terms and full for delay terms.
+  default picks full for delay and phase-only terms (a common phase or delay
+  leaves the model unchanged, so no scale mode is excited), and otherwise
+  alternate for direction-independent terms and half for direction-dependent
+  ones.
 * Convergence (Algorithm 1's "||Delta g|| > eps"): per interval, the 2-norm
   of the applied step over the unknown entries of unflagged blocks divided by
-  the 2-norm of the updated gains; for delays, the largest band-edge phase
-  change 2 pi nu_max |alpha Delta tau|.  The iteration count is the number of
-  applied updates.
+  the 2-norm of the updated gains (amplitude-only: of the amplitudes); for
+  delays, the largest band-edge phase change 2 pi nu_max |alpha Delta tau|;
+  for phase-only terms, the largest phase change |alpha Delta phi|.  The
+  iteration count is the number of applied updates.
 * A block whose Cholesky pivot falls to 1e-12 of its largest diagonal entry
   (or that has no data) gets Delta = 0 and gain flag 1; flagged blocks are
   left out of the convergence norm.  The flag reflects the last update.
@@ -38,7 +43,9 @@ import numpy as np
 
 from .jones import PERM_IDX, vec, unvec, dagger, term_jones, chain_product
 
-UNKNOWNS = {"diag": (0, 3), "c2x2": (0, 1, 2, 3), "delay": (0, 3)}
+UNKNOWNS = {"diag": (0, 3), "c2x2": (0, 1, 2, 3), "delay": (0, 3), "phase": (0, 3), "amplitude": (0, 3)}
+# real-parameterised diagonal terms: params [..][2] per (antenna, gain direction)
+PARAM_KINDS = ("delay", "phase", "amplitude")
 PIVOT_REL = 1e-12
 
 
@@ -137,7 +144,7 @@ def accumulate(vis, chain, n, s_fwd: Samples):
     U = list(UNKNOWNS[term.kind])
     n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
     nu_ = len(U)
-    if term.kind == "delay":
+    if term.kind in PARAM_KINDS:
         JHJ = np.zeros((n_ant, n_gdir, 2, 2), dtype=np.float64)
         JHr = np.zeros((n_ant, n_gdir, 2), dtype=np.float64)
     else:
@@ -152,10 +159,16 @@ def accumulate(vis, chain, n, s_fwd: Samples):
         if k == 0:
             chisq = float(np.sum(s.w * np.abs(R) ** 2))
         Ku = K[..., U]                                               # [S][gd][4][nu]
-        if term.kind == "delay":
-            nu = np.asarray(vis.chan_freq, dtype=np.float64)[s.chans]
+        if term.kind in PARAM_KINDS:
+            # E = (dv/dg) (dg/du) for the real parameter u of each hand
             gdiag = np.stack([Gn[..., 0, 0], Gn[..., 1, 1]], axis=-1)   # [S][gd][2]
-            dg = 2j * np.pi * nu[:, None, None] * gdiag                 # d g_c / d tau_c
+            if term.kind == "delay":
+                nu = np.asarray(vis.chan_freq, dtype=np.float64)[s.chans]
+                dg = 2j * np.pi * nu[:, None, None] * gdiag             # d g / d tau
+            elif term.kind == "phase":
+                dg = 1j * gdiag                                         # d g / d phi
+            else:
+                dg = np.ones_like(gdiag)                                 # d g / d a
             E = Ku * dg[:, :, None, :]
             H = np.real(np.einsum("sdxu,sx,sdxv->sduv", np.conj(E), s.w, E))
             b = np.real(np.einsum("sdxu,sx->sdu", np.conj(E), s.w * R))
@@ -199,7 +212,7 @@ def block_solve(H, b, rel=PIVOT_REL):
 
 def resolve_damping(mode, term):
     if mode == "auto":
-        if term.kind == "delay":
+        if term.kind in ("delay", "phase"):
             return "full"
         return "half" if term.direction_dependent else "alternate"
     if mode not in ("full", "half", "alternate"):
@@ -264,9 +277,17 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
         alpha = step_length(mode, k)
         step = alpha * delta
         ok = flags == 0
-        if term.kind == "delay":
-            term.params[gt, gf] = term.params[gt, gf] + step
-            ratio = float(np.max(2.0 * np.pi * nu_max * np.abs(step[ok]))) if np.any(ok) else 0.0
+        if term.kind in PARAM_KINDS:
+            u_new = term.params[gt, gf] + step
+            term.params[gt, gf] = u_new
+            if term.kind == "delay":      # band-edge phase change
+                ratio = float(np.max(2.0 * np.pi * nu_max * np.abs(step[ok]))) if np.any(ok) else 0.0
+            elif term.kind == "phase":    # phase change in radians
+                ratio = float(np.max(np.abs(step[ok]))) if np.any(ok) else 0.0
+            else:                         # relative change of the amplitudes
+                num = float(np.sum(step[ok] ** 2))
+                den = float(np.sum(u_new[ok] ** 2))
+                ratio = 0.0 if num == 0.0 else (np.sqrt(num / den) if den > 0.0 else np.inf)
         else:
             x_new = term.gains[gt, gf].copy()
             x_new[..., U] = x_new[..., U] + step

@@ -152,6 +152,12 @@ def truth_jones(term: Term, t_idx: torch.Tensor, ants: torch.Tensor, freq: torch
         z = torch.polar(torch.ones_like(ph), ph)
         J[..., 0, 0] = z[..., 0]
         J[..., 1, 1] = z[..., 1]
+    elif term.kind in ("phase", "amplitude"):
+        par = _as_t(term.params, dev, torch.float64)
+        u = par[gt[:, None], fm[None, :], ants.long()[:, None], gd]            # [R][C][2]
+        z = torch.polar(torch.ones_like(u), u) if term.kind == "phase" else u.to(torch.complex128)
+        J[..., 0, 0] = z[..., 0]
+        J[..., 1, 1] = z[..., 1]
     else:
         gains = _as_t(term.gains, dev, torch.complex128)
         gv = gains[gt[:, None], fm[None, :], ants.long()[:, None], gd]          # [R][C][4]
@@ -209,7 +215,8 @@ def interval_centres(mapping: np.ndarray, n_int: int) -> np.ndarray:
 
 def make_term(kind: str, n_time: int, n_chan: int, n_ant: int, t_int: int, f_int: int,
               n_dir: int = 1, direction_dependent: bool = False, d_map=None, name: str = "") -> Term:
-    """A chain term with unit gains (zero delays) over contiguous solution intervals."""
+    """A chain term with unit gains (zero delays and phases, unit amplitudes) over
+    contiguous solution intervals."""
     t_map = block_map(n_time, t_int)
     f_map = block_map(n_chan, f_int)
     n_gt, n_gf = int(t_map.max()) + 1, int(f_map.max()) + 1
@@ -221,7 +228,11 @@ def make_term(kind: str, n_time: int, n_chan: int, n_ant: int, t_int: int, f_int
     gains = np.zeros(shape + (4,), dtype=np.complex128)
     gains[..., 0] = 1.0
     gains[..., 3] = 1.0
-    params = np.zeros(shape + (2,), dtype=np.float64) if kind == "delay" else None
+    params = None
+    if kind in ("delay", "phase"):
+        params = np.zeros(shape + (2,), dtype=np.float64)
+    elif kind == "amplitude":
+        params = np.ones(shape + (2,), dtype=np.float64)
     return Term(kind=kind, t_map=t_map, f_map=f_map, d_map=d_map, n_gt=n_gt, n_gf=n_gf,
                 n_gdir=n_gdir, gains=gains, params=params,
                 gain_flags=np.zeros(shape, dtype=np.int8),

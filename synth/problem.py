@@ -21,7 +21,9 @@ A chain term (paper eq. joneschain) carries its own solution-interval maps
   t_map [n_time] -> [0, n_gt)     f_map [n_chan] -> [0, n_gf)
   d_map [n_dir]  -> [0, n_gdir)
   gains      [n_gt][n_gf][n_ant][n_gdir][4]  complex128  (diag / c2x2 terms)
-  params     [n_gt][n_gf][n_ant][n_gdir][2]  float64     (delay: tau_X, tau_Y in s)
+  params     [n_gt][n_gf][n_ant][n_gdir][2]  float64     (delay: tau_X, tau_Y in s;
+                                                        phase: phi_X, phi_Y in rad;
+                                                        amplitude: a_X, a_Y)
   gain_flags [n_gt][n_gf][n_ant][n_gdir]     int8
 """
 from __future__ import annotations
@@ -29,7 +31,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field, replace
 from typing import Any, Optional
 
-TERM_KINDS = ("diag", "c2x2", "delay")
+TERM_KINDS = ("diag", "c2x2", "delay", "phase", "amplitude")
+PARAM_KINDS = ("delay", "phase", "amplitude")
 
 
 @dataclass

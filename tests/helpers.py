@@ -15,6 +15,10 @@ def jones_of(term, t, c, a, d, freq):
     if term.kind == "delay":
         tau = term.params[gt, gf, a, gd]
         return np.diag(np.exp(2j * np.pi * freq[c] * tau))
+    if term.kind == "phase":
+        return np.diag(np.exp(1j * term.params[gt, gf, a, gd]))
+    if term.kind == "amplitude":
+        return np.diag(term.params[gt, gf, a, gd].astype(np.complex128))
     g = term.gains[gt, gf, a, gd]
     if term.kind == "diag":
         return np.diag([g[0], g[3]])
@@ -75,6 +79,10 @@ def make_term(rng, kind, n_time, n_chan, n_ant, t_int=None, f_int=None, n_dir=1,
     params = None
     if kind == "delay":
         params = rng.uniform(-1e-9, 1e-9, shape + (2,))
+    elif kind == "phase":
+        params = rng.uniform(-np.pi, np.pi, shape + (2,)) * scale
+    elif kind == "amplitude":
+        params = 1.0 + scale * rng.uniform(-1.0, 1.0, shape + (2,))
     else:
         gains = gains + scale * rand_c(rng, *shape, 4)
         if kind == "diag":
@@ -92,7 +100,7 @@ def unit_like(term):
     g[..., 3] = 1
     t.gains = g
     if term.params is not None:
-        t.params = np.zeros_like(term.params)
+        t.params = np.ones_like(term.params) if term.kind == "amplitude" else np.zeros_like(term.params)
     t.gain_flags = np.zeros_like(term.gain_flags)
     return t
 

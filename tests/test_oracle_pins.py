@@ -142,6 +142,85 @@ def test_delay_blocks_equal_dense_2re_form():
         assert np.max(np.abs(D_JHr[sel] + 2 * JHr[a, 0])) < 1e-6 * scale
 
 
+@pytest.mark.parametrize("kind", ["phase", "amplitude"])
+def test_scenario1_blocks_equal_dense_2re_form(kind):
+    """Phase- and amplitude-only blocks (eq. jhj_case1, eq. jhwr_case1, without
+    their common factor 2) against the real-parameter Jacobian built by central
+    differences (eq. jhj_entry_param: J_o^H W J_o = 2 Re(...))."""
+    rng = np.random.default_rng(7)
+    n_ant = 4
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=4, n_dir=1)
+    chain = [make_term(rng, kind, 2, 4, n_ant), make_term(rng, "diag", 2, 4, n_ant)]
+    vis.data = forward_data(vis, chain) + 0.2 * rand_c(rng, *vis.data.shape)
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(4))
+    JHJ, JHr, _ = solver.accumulate(vis, chain, 0, s)
+    D_JHJ, D_JHr, idx = dense.dense_delay(vis, chain, 0, 0, 0, h=1e-6)
+    scale = np.max(np.abs(D_JHJ))
+    for a in range(n_ant):
+        sel = [j for j, (aa, _, _) in enumerate(idx) if aa == a]
+        assert np.max(np.abs(D_JHJ[np.ix_(sel, sel)] - 2 * JHJ[a, 0])) < 1e-7 * scale
+        assert np.max(np.abs(D_JHr[sel] + 2 * JHr[a, 0])) < 1e-7 * scale
+
+
+def test_recovery_phase_only():
+    rng = np.random.default_rng(41)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=4, n_dir=1, polarised=False)
+    truth = [make_term(rng, "phase", 2, 4, n_ant, t_int=1, f_int=2, scale=0.5)]
+    truth[0].params[:, :, 0] = 0.0
+    vis.data = forward_data(vis, truth)
+    out, st = solver.solve_term(vis, [unit_like(truth[0])], 0, tol=1e-12, max_iter=300)
+    assert st["converged"].all()
+    # only phi_p - phi_q enters the data (per hand): compare referenced to antenna 0
+    got = out[0].params - out[0].params[:, :, :1]
+    d = np.angle(np.exp(1j * (got - truth[0].params)))
+    assert np.max(np.abs(d)) < 1e-10
+
+
+def test_recovery_amplitude_only():
+    rng = np.random.default_rng(43)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=4, n_dir=1, polarised=False)
+    truth = [make_term(rng, "amplitude", 2, 4, n_ant, t_int=1, f_int=2, scale=0.3)]
+    vis.data = forward_data(vis, truth)
+    out, st = solver.solve_term(vis, [unit_like(truth[0])], 0, tol=1e-12, max_iter=300)
+    assert st["converged"].all()
+    assert np.max(np.abs(out[0].params - truth[0].params)) < 1e-10
+
+
+def test_amplitude_one_full_step_exact_for_single_perturbed_antenna():
+    """The model is linear in one antenna's amplitudes with the others fixed, so
+    one undamped step from the truth with only that antenna perturbed lands on
+    it exactly."""
+    rng = np.random.default_rng(47)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=1, n_chan=4, n_dir=1)
+    truth = [make_term(rng, "amplitude", 1, 4, n_ant)]
+    vis.data = forward_data(vis, truth)
+    start = solver.copy_chain(truth)
+    a = 3
+    start[0].params[0, 0, a, 0] += rng.uniform(-0.2, 0.2, 2)
+    out, _ = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=1, damping="full")
+    assert np.max(np.abs(out[0].params[0, 0, a] - truth[0].params[0, 0, a])) < 1e-13
+
+
+def test_phase_and_amplitude_compose_to_the_diagonal_gain():
+    """Corrupting with phase-only then amplitude-only terms equals corrupting
+    with the diagonal gain a exp(i phi) (eq. joneschain of two diagonal terms)."""
+    rng = np.random.default_rng(53)
+    n_ant = 4
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=3, n_dir=1)
+    ph = make_term(rng, "phase", 2, 3, n_ant)
+    am = make_term(rng, "amplitude", 2, 3, n_ant)
+    dg = make_term(rng, "diag", 2, 3, n_ant)
+    z = am.params * np.exp(1j * ph.params)
+    dg.gains[..., 0] = z[..., 0]
+    dg.gains[..., 3] = z[..., 1]
+    a = outputs.corrupt(vis, [ph, am])
+    b = outputs.corrupt(vis, [dg])
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
+
+
 def test_jhj_hermitian_psd():
     rng = np.random.default_rng(3)
     vis = make_vis(rng, n_ant=6, n_time=2, n_chan=3, n_dir=2)
