@@ -367,6 +367,41 @@ def leg_chain(ctx, dev, n_epoch: int = 2):
     return out
 
 
+def leg_params(ctx, dev):
+    """Phase-only and amplitude-only solves (real parameters, one per hand) on the
+    MeerKAT shape: 64 antennas, 600 times x 1024 channels, complex64, interval
+    1 time x 64 channels, truth phases (unit amplitude) or amplitudes (zero
+    phase), MIXED to tol 1e-6."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+    from synth.generate import config_meerkat
+
+    out = {}
+    for kind in ("phase", "amplitude"):
+        p = config_meerkat(device=dev, kind=kind)
+        torch.cuda.synchronize()
+        term = qc.device_term(p.chain[0], dev)
+        init = term.params.clone()
+        ms, st = [], None
+        for rep in range(3):
+            term.params.copy_(init)
+            st = ctx.solve(p.vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+            ms.append(ctx.last_kernel_ms())
+        it = st["iters"].cpu().numpy()
+        gb = float(np.sum(np.maximum(it, 1) * pass_bytes(p.vis, p.chain[0]))) / 1e9
+        k_ms = float(np.mean(ms[1:]))
+        out[kind] = dict(kernel_ms=k_ms, mean_iterations=float(it.mean()), max_iterations=int(it.max()),
+                         converged=float(st["converged"].float().mean().item()), algorithmic_gb=gb,
+                         achieved_gbs=gb / (k_ms * 1e-3), hbm_frac=gb / (k_ms * 1e-3) / HBM_PEAK_GBS)
+        log(f"params: {kind}-only solve {k_ms:.1f} ms, mean iterations {it.mean():.2f} (max {it.max()}), "
+            f"{gb:.1f} GB -> {gb / (k_ms * 1e-3):.0f} GB/s")
+        del p, term, init
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,8 +409,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="batch,warm,chain",
-                    help="comma list of extra legs: batch, warm, chain (or none)")
+    ap.add_argument("--legs", default="batch,warm,chain,params",
+                    help="comma list of extra legs: batch, warm, chain, params (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -506,6 +541,14 @@ def main():
         except Exception as e:   # report, keep the main measurement
             out["legs"]["warm"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"warm leg failed: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if "params" in legs:
+        try:
+            out["legs"]["params"] = leg_params(ctx, dev)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["params"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"params leg failed: {e}")
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     if "chain" in legs:

@@ -67,13 +67,22 @@ typedef enum { QC_PREC_FP64 = 0, QC_PREC_MIXED = 1 } qc_prec;
  *                compensated (Kahan) sums of the per-antenna blocks, FP64
  *                block solve, update and convergence test.  Needs QC_C64.   */
 
-typedef enum { QC_TERM_DIAGONAL = 0, QC_TERM_COMPLEX2X2 = 1, QC_TERM_DELAY = 2 } qc_term_type;
+typedef enum {
+  QC_TERM_DIAGONAL = 0, QC_TERM_COMPLEX2X2 = 1, QC_TERM_DELAY = 2, QC_TERM_PHASE = 3, QC_TERM_AMPLITUDE = 4
+} qc_term_type;
 /* DIAGONAL  : unknowns XX, YY of the gain (XY = YX = 0).
  * COMPLEX2X2: all four entries.
  * DELAY     : real parameters tau_X, tau_Y (seconds); the Jones matrix is
  *             diag(exp(2 pi i nu tau_X), exp(2 pi i nu tau_Y)) at channel
  *             frequency nu (the paper's second parameterisation scenario,
- *             eq. jhj_case2, with a delay as the coarse parameter).       */
+ *             eq. jhj_case2, with a delay as the coarse parameter).
+ * PHASE     : real parameters phi_X, phi_Y (radians), Jones matrix
+ *             diag(exp(i phi_X), exp(i phi_Y)) (phase-only gain; the paper's
+ *             first parameterisation scenario, eq. jhj_case1 / jhwr_case1).
+ * AMPLITUDE : real parameters a_X, a_Y, Jones matrix diag(a_X, a_Y)
+ *             (amplitude-only gain, same scenario).
+ * DELAY, PHASE and AMPLITUDE terms keep their parameters in qc_term.params;
+ * their blocks are real 2x2 (one per hand, decoupled). */
 
 typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3 } qc_damping;
 /* Step length alpha_k of x <- x + alpha_k * Delta (the paper leaves the step
@@ -141,7 +150,8 @@ typedef struct {
   const int32_t* f_map;     /* [n_chan] -> [0, n_gf), non-decreasing          */
   const int32_t* d_map;     /* [n_dir]  -> [0, n_gdir)                        */
   void*   gains;            /* [n_gt][n_gf][n_ant][n_gdir][4] complex128, in/out (DIAGONAL, COMPLEX2X2) */
-  double* params;           /* [n_gt][n_gf][n_ant][n_gdir][2] tau_X, tau_Y in s, in/out (DELAY) */
+  double* params;           /* [n_gt][n_gf][n_ant][n_gdir][2] in/out: tau_X, tau_Y in s (DELAY),
+                               phi_X, phi_Y in rad (PHASE), a_X, a_Y (AMPLITUDE) */
   int8_t* gain_flags;       /* [n_gt][n_gf][n_ant][n_gdir] out (may be NULL for fixed terms) */
 } qc_term;
 

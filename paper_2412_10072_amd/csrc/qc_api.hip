@@ -78,15 +78,16 @@ qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
 }
 
 qc_status check_term(qc_ctx* ctx, const qc_vis* v, const qc_term* t, int j, HostMaps& hm, hipStream_t s) {
-  if (t->type != QC_TERM_DIAGONAL && t->type != QC_TERM_COMPLEX2X2 && t->type != QC_TERM_DELAY)
+  if (t->type < QC_TERM_DIAGONAL || t->type > QC_TERM_AMPLITUDE)
     return fail(ctx, QC_E_ARG, "term %d: bad type %d", j, (int)t->type);
   if (t->n_gt <= 0 || t->n_gf <= 0 || t->n_gdir <= 0)
     return fail(ctx, QC_E_ARG, "term %d: bad gain shape (%d, %d, %d)", j, t->n_gt, t->n_gf, t->n_gdir);
   if (t->n_gdir > QC_MAX_GDIR)
     return fail(ctx, QC_E_UNSUPPORTED, "term %d: n_gdir=%d exceeds %d", j, t->n_gdir, QC_MAX_GDIR);
   if (!t->t_map || !t->f_map || !t->d_map) return fail(ctx, QC_E_ARG, "term %d: a map pointer is NULL", j);
-  if (t->type == QC_TERM_DELAY ? !t->params : !t->gains)
-    return fail(ctx, QC_E_ARG, "term %d: %s is NULL", j, t->type == QC_TERM_DELAY ? "params" : "gains");
+  const bool real_params = t->type >= QC_TERM_DELAY;   // delay, phase, amplitude
+  if (real_params ? !t->params : !t->gains)
+    return fail(ctx, QC_E_ARG, "term %d: %s is NULL", j, real_params ? "params" : "gains");
   hm.t_map.resize(v->n_time);
   hm.f_map.resize(v->n_chan);
   hm.d_map.resize(v->n_dir);
@@ -224,7 +225,9 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
 
 int resolve_damping(qc_damping d, const qc_term& t) {
   if (d == QC_DAMP_AUTO) {
-    if (t.type == QC_TERM_DELAY) return 0;
+    // full steps for delay and phase-only terms: a common phase or delay
+    // leaves the model unchanged, so there is no scale mode to overshoot
+    if (t.type == QC_TERM_DELAY || t.type == QC_TERM_PHASE) return 0;
     return t.direction_dependent ? 1 : 2;
   }
   return (int)d;
@@ -324,7 +327,7 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   if (st != QC_OK) return st;
   for (int j = 0; j < active; ++j) {
     if (chain[j].type == QC_TERM_COMPLEX2X2)
-      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must be diagonal or delay", j);
+      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must be diagonal", j);
     if (!dmap_constant(maps[j]))
       return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must map all directions to one gain", j);
   }

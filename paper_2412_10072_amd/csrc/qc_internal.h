@@ -16,7 +16,10 @@ namespace qc {
 // argument blocks (passed to kernels by value)
 // ---------------------------------------------------------------------------
 
-enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2 };
+enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 4 };
+// KIND_DELAY as a kernel template argument stands for every real-parameterised
+// diagonal term (delay, phase-only, amplitude-only); the term's own kind
+// (TermArgs::kind) selects the Jones form at run time.
 // per-sample chain evaluation of the solver kernels
 enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2 };
 
@@ -163,6 +166,14 @@ __device__ __forceinline__ cx<T> phasor_turns(double turns) {
   }
 }
 
+// Diagonal entry of a real-parameterised term for parameter u at frequency
+// nu: exp(2 pi i nu u) (delay), exp(i u) (phase), u (amplitude).
+template <typename T>
+__device__ __forceinline__ cx<T> param_gain(int kind, double nu, double u) {
+  if (kind == KIND_AMP) return cx<T>{(T)u, T(0)};
+  return phasor_turns<T>(kind == KIND_PHASE ? u * (1.0 / 6.283185307179586476925286766559) : nu * u);
+}
+
 template <typename T>
 __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int t, int c, int x, int d,
                                              double nu) {
@@ -171,11 +182,9 @@ __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int 
   const int gd = tm.d_map[d];
   const size_t blk = (((size_t)gt * tm.n_gf + gf) * n_ant + x) * tm.n_gdir + gd;
   m22<T> J = mzero<T>();
-  if (tm.kind == KIND_DELAY) {
-    const double tx = tm.params[2 * blk + 0];
-    const double ty = tm.params[2 * blk + 1];
-    J.a = phasor_turns<T>(nu * tx);
-    J.d = phasor_turns<T>(nu * ty);
+  if (tm.kind >= KIND_DELAY) {
+    J.a = param_gain<T>(tm.kind, nu, tm.params[2 * blk + 0]);
+    J.d = param_gain<T>(tm.kind, nu, tm.params[2 * blk + 1]);
   } else {
     const double2* g = tm.gains + 4 * blk;
     double2 g0 = g[0], g3 = g[3];

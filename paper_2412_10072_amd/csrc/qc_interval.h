@@ -254,12 +254,14 @@ __device__ __forceinline__ A wave_sum(A x) {
 //     JHr[i,k] = conj(alpha_i) sum_b w_ib R_ib conj(B_kb).
 //   DIAGONAL: h_i = |alpha_i|^2 sum_b w_ib |B_ib|^2, j_i = conj(alpha_i) sum_b w_ib R_ib conj(B_ib).
 //   DELAY (g_i = exp(2 pi i nu tau_i)): h_i = (2 pi nu)^2 |alpha_i g_i|^2 sum_b w_ib |B_ib|^2,
-//     b_i = 2 pi nu Im(conj(g_i) j_i)   (the real parameterised blocks
+//     b_i = 2 pi nu Im(conj(g_i) j_i); PHASE (g_i = exp(i phi_i)): the same
+//     with 1 for 2 pi nu; AMPLITUDE (g_i = a_i, amp set): h_i = |alpha_i|^2
+//     sum_b w_ib |B_ib|^2, b_i = Re(j_i)   (the real parameterised blocks
 //     without their common factor 2, which cancels in the update).
 // ---------------------------------------------------------------------------
 template <int KIND, bool ALPHA1, typename T>
 __device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, const m22<T>& WR, T w0, T w1,
-                                        T w2, T w3, cx<T> g0, cx<T> g1, T tpn, T* acc) {
+                                        T w2, T w3, cx<T> g0, cx<T> g1, T tpn, T* acc, bool amp = false) {
   // acc += the contribution; WR = W o R (elementwise).  Every sum is an FMA
   // chain into the accumulator.
   if constexpr (KIND == KIND_C2X2) {
@@ -313,7 +315,14 @@ __device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, con
       acc[1] = fma(s1, h1, acc[1]);
       acc[2] += j0.re; acc[3] += j0.im;
       acc[4] += j1.re; acc[5] += j1.im;
+    } else if (amp) {
+      // amplitude-only (dg/da = 1): h_i = |alpha_i|^2 sum_b w_ib |B_ib|^2, b_i = Re(j_i)
+      acc[0] = fma(s0, h0, acc[0]);
+      acc[1] = fma(s1, h1, acc[1]);
+      acc[2] += j0.re;
+      acc[3] += j1.re;
     } else {
+      // delay (tpn = 2 pi nu) and phase-only (tpn = 1): dg/du = i tpn g
       const T t2 = tpn * tpn;
       acc[0] = fma(t2 * norm2(g0), s0 * h0, acc[0]);
       acc[1] = fma(t2 * norm2(g1), s1 * h1, acc[1]);
@@ -492,7 +501,10 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool 
 template <int KIND, typename T, int NG, typename Sum>
 __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<T>* gc, int* gfl, double* red,
                                                 int* ctl, int n_ant, int n_gdir, int k_upd, int damping,
-                                                double nu_max, double tol, int* err) {
+                                                double nu_max, double tol, int* err, int pk = KIND_DELAY) {
+  // real-parameter terms: a relative test for amplitudes, the largest phase
+  // change for delays (at the band edge) and phases
+  const bool rel_test = KIND != KIND_DELAY || pk == KIND_AMP;
   constexpr int NV = KindInfo<KIND>::NV;
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -559,7 +571,13 @@ const double alpha = step_length(damping, k_upd);
         const double d1 = alpha * ((h[3] / l1) / l1);
         double2* g = gm + slot * 4;
         g[0] = make_double2(g[0].x + d0, g[0].y + d1);
-        num = fmax(num, TWO_PI * nu_max * fmax(fabs(d0), fabs(d1)));
+        if (pk == KIND_AMP) {
+          num += d0 * d0 + d1 * d1;
+          den += g[0].x * g[0].x + g[0].y * g[0].y;
+        } else {
+          const double scale = pk == KIND_DELAY ? TWO_PI * nu_max : 1.0;
+          num = fmax(num, scale * fmax(fabs(d0), fabs(d1)));
+        }
       }
     }
     gfl[slot] = ok ? 0 : 1;
@@ -567,7 +585,7 @@ const double alpha = step_length(damping, k_upd);
   // ---- convergence over the interval ----
   {
     double a = num, b = den;
-    if constexpr (KIND == KIND_DELAY) {
+    if (!rel_test) {
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
     } else {
@@ -583,12 +601,12 @@ const double alpha = step_length(damping, k_upd);
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
     for (int w = 0; w < nw; ++w) {
-      if constexpr (KIND == KIND_DELAY) a = fmax(a, red[2 * w]);
+      if (!rel_test) a = fmax(a, red[2 * w]);
       else a += red[2 * w];
       b += red[2 * w + 1];
     }
     double ratio;
-    if constexpr (KIND == KIND_DELAY) ratio = a;
+    if (!rel_test) ratio = a;
     else ratio = (a == 0.0) ? 0.0 : (b > 0.0 ? sqrt(a / b) : INFINITY);
     ctl[0] = (ratio <= tol) ? 1 : 0;
   }
@@ -626,6 +644,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 
   const VisArgs& V = *J.V;
   const TermArgs& TA = *J.TA;
+  const int pk = TA.kind;                    // delay / phase / amplitude for KIND_DELAY
+  const bool pk_amp = (KIND == KIND_DELAY) && pk == KIND_AMP;
   const int n_ant = V.n_ant;
   const int n_gdir = SINGLE ? 1 : TA.n_gdir;
   const int gt = J.gt, gf = J.gf, n_gf = J.n_gf;
@@ -767,7 +787,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
         const m22<T> Draw = load_m22<S, T>(Dp, s);
         const bool use = inb & row_ok & (fl == 0);
         const double nu = V.freq[cc];
-        const T tpn = (T)(TWO_PI * nu);
+        const T tpn = (T)(pk == KIND_DELAY ? TWO_PI * nu : 1.0);   // d(phase)/d(parameter)
         w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
         const m22<T> D = select_m(use, Draw);
 
@@ -776,8 +796,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           m22<T> Gp, Gq;
           if constexpr (KIND == KIND_DELAY) {
             const double2 tp = gm[p * 4], tq = gm[q * 4];
-            Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
-            Gq = {phasor_turns<T>(nu * tq.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tq.y)};
+            Gp = {param_gain<T>(pk, nu, tp.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tp.y)};
+            Gq = {param_gain<T>(pk, nu, tq.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tq.y)};
           } else {
             Gp = {gc[p * 4 + 0], gc[p * 4 + 1], gc[p * 4 + 2], gc[p * 4 + 3]};
             Gq = {gc[q * 4 + 0], gc[q * 4 + 1], gc[q * 4 + 2], gc[q * 4 + 3]};
@@ -791,8 +811,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           const m22<T> R = msub_mul(D, Gp, B);   // D - G_p M G_q^H
           const m22<T> WR = wmul(R, w0, w1, w2, w3);
           // conjugate baseline: B' = M^H G_p^H, W' o R' = (W o R)^H
-          contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, Gp.a, Gp.d, tpn, PACC ? pacc : prow);
-          contrib<KIND, true, T>(aq0, aq1, herm(GM), herm(WR), w0, w2, w1, w3, Gq.a, Gq.d, tpn, qacc);
+          contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, Gp.a, Gp.d, tpn, PACC ? pacc : prow, pk_amp);
+          contrib<KIND, true, T>(aq0, aq1, herm(GM), herm(WR), w0, w2, w1, w3, Gq.a, Gq.d, tpn, qacc, pk_amp);
           chi = chisq_acc(WR, R, chi);
         } else if constexpr (DIAGC) {
           // Diagonal chain: C_{a,d} = g_{a,d} o_{a,d} per hand, o the product
@@ -835,10 +855,10 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           auto active_diag = [&](int gd, cx<T>& a0, cx<T>& a1, cx<T>& b0, cx<T>& b1) {
             if constexpr (KIND == KIND_DELAY) {
               const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
-              a0 = phasor_turns<T>(nu * tp.x);
-              a1 = phasor_turns<T>(nu * tp.y);
-              b0 = phasor_turns<T>(nu * tq.x);
-              b1 = phasor_turns<T>(nu * tq.y);
+              a0 = param_gain<T>(pk, nu, tp.x);
+              a1 = param_gain<T>(pk, nu, tp.y);
+              b0 = param_gain<T>(pk, nu, tq.x);
+              b1 = param_gain<T>(pk, nu, tq.y);
             } else {
               const cx<T>* gpp = gc + (p * NG + gd) * 4;
               const cx<T>* gqq = gc + (q * NG + gd) * 4;
@@ -896,8 +916,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
           for (int g = 0; g < NG; ++g) {
             contrib<KIND, false, T>(ap0, ap1, Bs[g], WR, w0, w1, w2, w3, gp0[g], gp1[g], tpn,
-                                    (PACC ? pacc : prow) + g * NV);
-            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV);
+                                    (PACC ? pacc : prow) + g * NV, pk_amp);
+            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV,
+                                    pk_amp);
           }
           chi = chisq_acc(WR, R, chi);
         } else {
@@ -923,8 +944,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           auto active_jones = [&](int gd, m22<T>& Gp, m22<T>& Gq) {
             if constexpr (KIND == KIND_DELAY) {
               const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
-              Gp = {phasor_turns<T>(nu * tp.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tp.y)};
-              Gq = {phasor_turns<T>(nu * tq.x), czero<T>(), czero<T>(), phasor_turns<T>(nu * tq.y)};
+              Gp = {param_gain<T>(pk, nu, tp.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tp.y)};
+              Gq = {param_gain<T>(pk, nu, tq.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tq.y)};
             } else {
               const cx<T>* gpp = gc + (p * NG + gd) * 4;
               const cx<T>* gqq = gc + (q * NG + gd) * 4;
@@ -967,8 +988,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
           for (int g = 0; g < NG; ++g) {
             contrib<KIND, false, T>(ap0, ap1, Bs[g], WR, w0, w1, w2, w3, gp0[g], gp1[g], tpn,
-                                    (PACC ? pacc : prow) + g * NV);
-            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV);
+                                    (PACC ? pacc : prow) + g * NV, pk_amp);
+            contrib<KIND, false, T>(aq0, aq1, Bsc[g], WRc, w0, w2, w1, w3, gq0[g], gq1[g], tpn, qacc + g * NV,
+                                    pk_amp);
           }
           chi = chisq_acc(WR, R, chi);
         }
@@ -1020,7 +1042,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double v = (KIND != KIND_DELAY && (k == 0 || k == 3)) ? 1.0 : 0.0;
-          gm[i * 4 + k] = make_double2(v, 0.0);
+          gm[i * 4 + k] = (pk_amp && k == 0) ? make_double2(1.0, 1.0) : make_double2(v, 0.0);
           gc[i * 4 + k] = cmake<T>((T)v, T(0));
         }
       }
@@ -1034,7 +1056,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     if (it >= J.max_iter) break;
     const int k_upd = it + 1;
     const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd,
-                                                   J.damping, nu_max, J.tol, J.err);
+                                                   J.damping, nu_max, J.tol, J.err, pk);
     iters = k_upd;
     if (conv) {
       converged = 1;
@@ -1140,7 +1162,7 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
   } else {
     const int k_upd = pass + 1;
     conv = update_and_test<KIND, T, NG>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, red, ctl, n_ant,
-                                        n_gdir, k_upd, J.damping, nu_max, J.tol, J.err);
+                                        n_gdir, k_upd, J.damping, nu_max, J.tol, J.err, J.TA->kind);
     for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
       const int slot = ant * NG + gd;

@@ -16,6 +16,9 @@ one (whole-problem oracle runs at these sizes would take hours).
     size-independent property that the MIXED update agrees with the FP64
     GPU path (whose oracle parity the small-size tests establish) to 1e-4,
     and the split K reduction with the unsplit one.
+  * Phase-only and amplitude-only solves on the MeerKAT shape: sampled
+    intervals against the oracle (parameters <= 1e-4, iteration counts
+    within one).
 """
 import sys
 
@@ -178,3 +181,30 @@ def test_chain_full_size_sampled_parity(qc_lib):
     say(f"K: split parts {n_s} vs {n_1}, max |dtau| {np.abs(tau_s - tau_1).max():.3e} s")
     assert n_s > 1 and n_1 == 1
     assert np.abs(tau_s - tau_1).max() <= 1e-4 * max(np.abs(tau_1).max(), 1e-12)
+
+
+@pytest.mark.parametrize("kind", ["phase", "amplitude"])
+def test_parameter_terms_full_size_sampled_parity(qc_lib, kind):
+    """Phase-only / amplitude-only solve on the full MeerKAT shape (MIXED,
+    tol 1e-6, default launch), sampled intervals against the oracle."""
+    from paper_2412_10072_amd import qc
+    say(f"full-size {kind}-only: generating")
+    p = config_meerkat(device=DEV, kind=kind)
+    vis = p.vis
+    nbl = 64 * 63 // 2
+    term = qc.device_term(p.chain[0], DEV)
+    st = qc_lib.solve(vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+    qc_lib.sync()
+    it = st["iters"].cpu().numpy()
+    assert st["converged"].cpu().numpy().all()
+    par = term.params.cpu().numpy()
+    unit = p.chain[0]
+    for gt, gf in [(0, 0), (311, 9), (599, 15)]:
+        r0, r1, c0, c1 = gt * nbl, (gt + 1) * nbl, gf * 64, (gf + 1) * 64
+        vh = host_slice(vis, r0, r1, c0, c1)
+        ref = o_solver.copy_chain([unit.copy(f_map=np.asarray(unit.f_map)[c0:c1])])
+        ri, rc, _, _ = o_solver.solve_interval(vh, ref, 0, gt, gf, 1e-6, 100)
+        d = np.abs(par[gt, gf] - ref[0].params[gt, gf]).max()
+        say(f"{kind} interval ({gt}, {gf}): oracle {ri} updates, gpu {it[gt, gf]}, max |d param| {d:.2e}")
+        assert rc == 1 and abs(int(it[gt, gf]) - ri) <= 1
+        assert d <= 1e-4 * max(1.0, np.abs(ref[0].params[gt, gf]).max())
