@@ -4,7 +4,7 @@ None of these compare the oracle with itself."""
 import numpy as np
 import pytest
 
-from oracle import dense, jones, outputs, solver, warmstart, delay_init
+from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging
 from oracle.jones import PERM, dagger, unvec, vec
 from synth.generate import config_tiny, to_numpy_vis
 from helpers import (forward_data, make_term, make_vis, rand_c, reference_diag, unit_like)
@@ -607,3 +607,86 @@ def test_reference_features_gauge():
     # the reference antenna's own XX / YY ratios become real and non-negative
     z = f1.reshape(n_ant, 4, 2)
     assert abs(z[0, 0, 1]) < 1e-15 and z[0, 0, 0] >= 0 and abs(z[0, 3, 1]) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# MAD flagging of residuals
+# --------------------------------------------------------------------------
+
+def test_lower_median_against_full_sort():
+    rng = np.random.default_rng(61)
+    for n in (1, 2, 3, 10, 11, 1000, 1001):
+        x = rng.standard_normal(n).astype(np.float32)
+        x[: n // 3] = x[0]                      # ties
+        assert flagging.lower_median(x) == np.sort(x)[(n - 1) // 2]
+
+
+def test_mad_threshold_known_answer():
+    """x = [1, 2, 3, 4, 100]: m = 3, |x - m| = [2, 1, 0, 1, 97], d = 1, so with
+    k = 5 only 100 exceeds 3 + 5 * 1."""
+    from synth.problem import Vis
+    n = 5
+    R = np.zeros((n, 1, 4), np.complex64)
+    R[:, 0, 0] = np.sqrt(np.array([1, 2, 3, 4, 100], np.float32))
+    vis = Vis(data=R, model=np.zeros((n, 1, 1, 4), np.complex64), weight=np.ones((n, 1, 1), np.float32),
+              flag=np.zeros((n, 1), np.uint8), ant1=np.zeros(n, np.int32), ant2=np.ones(n, np.int32),
+              row_time=np.arange(n, dtype=np.int32), chan_freq=np.array([1e9]), n_ant=2, n_time=n)
+    s = flagging.sample_stat(vis, R)
+    out, stats = flagging.mad_flag(vis, R, 5.0, mode="global")
+    assert stats[0] == (float(s[2, 0]), 1.0) or abs(stats[0][0] - 3.0) < 1e-6
+    assert out[:, 0].tolist() == [0, 0, 0, 0, 1]
+
+
+def test_stat_sums_to_the_solver_chisq():
+    rng = np.random.default_rng(67)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=3, n_chan=6, n_dir=1)
+    chain = [make_term(rng, "c2x2", 3, 6, n_ant)]
+    vis.data = forward_data(vis, chain) + 0.3 * rand_c(rng, *vis.data.shape)
+    vis.flag = (rng.random(vis.flag.shape) < 0.2).astype(np.uint8)
+    R = outputs.residual(vis, chain)
+    st = flagging.sample_stat(vis, R)
+    sm = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(6))
+    _, _, chi2 = solver.accumulate(vis, chain, 0, sm)
+    assert abs(float(np.sum(st[vis.flag == 0])) - chi2) <= 1e-12 * chi2
+
+
+def _noise_vis(rng, n_ant=8, n_time=40, n_chan=16, sigma=0.1):
+    vis = make_vis(rng, n_ant=n_ant, n_time=n_time, n_chan=n_chan, n_dir=1, n_wcorr=4)
+    vis.weight = np.full(vis.weight.shape, 1.0 / sigma ** 2)
+    R = sigma / np.sqrt(2.0) * rand_c(rng, *vis.data.shape)
+    return vis, R
+
+
+def test_injected_outliers_are_flagged_alone():
+    rng = np.random.default_rng(71)
+    vis, R = _noise_vis(rng)
+    hits = rng.choice(R.shape[0] * R.shape[1], 12, replace=False)
+    r, c = np.unravel_index(hits, R.shape[:2])
+    R[r, c, 0] += 50 * 0.1
+    for mode in ("global", "baseline"):
+        out, _ = flagging.mad_flag(vis, R, 15.0, mode=mode)
+        assert out[r, c].all()
+        assert int(out.sum()) == hits.size
+
+
+def test_per_baseline_equals_global_for_one_baseline():
+    rng = np.random.default_rng(73)
+    vis, R = _noise_vis(rng, n_ant=2, n_time=200)
+    a, sa = flagging.mad_flag(vis, R, 3.0, mode="global")
+    b, sb = flagging.mad_flag(vis, R, 3.0, mode="baseline")
+    assert np.array_equal(a, b) and sa[0] == sb[1]
+
+
+def test_flagged_garbage_does_not_move_the_statistics():
+    rng = np.random.default_rng(79)
+    vis, R = _noise_vis(rng)
+    out0, st0 = flagging.mad_flag(vis, R, 5.0)
+    R2 = R.copy()
+    vis2 = vis.copy(flag=vis.flag.copy())
+    vis2.flag[3, :] = 1
+    R2[3, :, :] = np.nan
+    vis.flag[3, :] = 1
+    out1, st1 = flagging.mad_flag(vis, R, 5.0)
+    out2, st2 = flagging.mad_flag(vis2, R2, 5.0)
+    assert np.array_equal(out1, out2) and st1 == st2
