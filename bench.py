@@ -402,6 +402,56 @@ def leg_params(ctx, dev):
     return out
 
 
+def flag_pass_bytes(vis) -> dict:
+    """Algorithmic HBM bytes per sample of qc_mad_flag's passes: the statistic
+    pass reads the residual (4 complex), the weights and the flag and writes
+    the statistic; each radix-select histogram pass reads the statistic (11-bit
+    digits: 3 passes per selection in FP32, 6 in FP64; two selections, median
+    and MAD); the apply pass reads the statistic and the flag and writes the
+    output flag.  one_pass is the floor of any method: read the residual,
+    weights and flag once, write the flag."""
+    import torch
+    c64 = vis.data.dtype == torch.complex64
+    e = 4 if c64 else 8
+    wcorr = int(vis.weight.shape[-1])
+    stat = 8 * e + wcorr * e + 1 + e
+    hist = 2 * (3 if c64 else 6) * e
+    apply = e + 1 + 1
+    return dict(stat=stat, hist=hist, apply=apply, total=stat + hist + apply,
+                one_pass=8 * e + wcorr * e + 1 + 1)
+
+
+def leg_flag(ctx, vis, resid, k: float = 5.0, reps: int = 3):
+    """MAD outlier flagging of the main solve's residual (MeerKAT shape,
+    1.24e9 samples), over all samples at once and per baseline."""
+    import numpy as np
+    import torch
+    n_samples = int(vis.data.shape[0]) * int(vis.data.shape[1])
+    pb = flag_pass_bytes(vis)
+    out = dict(samples=n_samples, k=k, bytes_per_sample=pb)
+    flags = torch.empty_like(vis.flag)
+    n_in = int((vis.flag != 0).sum().item())
+    for mode in ("global", "baseline"):
+        ms, wall = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, n_new, st = ctx.mad_flag(vis, resid, mode=mode, k=k, flag_out=flags, stats=True)
+            wall.append(1e3 * (time.perf_counter() - t0))
+            ms.append(ctx.last_kernel_ms())
+        k_ms = float(np.mean(ms[1:]))
+        gb = pb["total"] * n_samples / 1e9
+        stn = st.cpu().numpy()
+        out[mode] = dict(kernel_ms=k_ms, wall_ms=float(np.mean(wall[1:])), new_flags=int(n_new),
+                         new_flag_frac=n_new / max(n_samples - n_in, 1), algorithmic_gb=gb,
+                         achieved_gbs=gb / (k_ms * 1e-3), hbm_frac=gb / (k_ms * 1e-3) / HBM_PEAK_GBS,
+                         one_pass_ms_at_peak=pb["one_pass"] * n_samples / 1e9 / HBM_PEAK_GBS * 1e3,
+                         median=float(np.median(stn[:, 0])), mad=float(np.median(stn[:, 1])))
+        log(f"flag {mode}: {k_ms:.1f} ms kernels ({np.mean(wall[1:]):.1f} ms wall), {n_new} new flags "
+            f"({100 * n_new / max(n_samples - n_in, 1):.3f}%), {gb:.1f} GB -> {gb / (k_ms * 1e-3):.0f} GB/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,8 +459,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="batch,warm,chain,params",
-                    help="comma list of extra legs: batch, warm, chain, params (or none)")
+    ap.add_argument("--legs", default="flag,batch,warm,chain,params",
+                    help="comma list of extra legs: flag, batch, warm, chain, params (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -524,6 +574,13 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     if legs:
         out["legs"] = {}
+    if "flag" in legs:
+        try:
+            out["legs"]["flag"] = leg_flag(ctx, vis, resid)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["flag"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"flag leg failed: {e}")
+    if legs:
         del prob, vis, resid, chain, term0, init_gains
         torch.cuda.synchronize()
         torch.cuda.empty_cache()

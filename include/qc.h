@@ -106,7 +106,8 @@ qc_status   qc_ctx_sync(qc_ctx* ctx);
 const char* qc_last_error(const qc_ctx* ctx);
 /* Duration in milliseconds of the last solve kernel launched through ctx,
  * measured with HIP events on the launch stream around that kernel alone
- * (waits for it).  Negative if none. */
+ * (waits for it), or of the last qc_mad_flag's kernels (from its first
+ * launch after the row checks to its last).  Negative if none. */
 double      qc_last_kernel_ms(qc_ctx* ctx);
 
 /* Launch shape of the per-interval solve used by qc_solve_interval,
@@ -238,6 +239,28 @@ qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, i
  * qc_apply_gains. */
 qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                       const uint8_t* dir_mask, void* out, void* stream);
+
+/* Outlier flags from residual visibilities by the median absolute deviation
+ * (paper Section 4.6, "Additional Features": with a near-complete model the
+ * residuals are Gaussian and outliers are taken to be RFI).
+ *   resid    : device [n_row][n_chan][4], same dtype as vis->data (the output
+ *              of qc_residual); vis supplies weights, flags and antennas.
+ * Per unflagged cross-correlation sample s = sum_k w_k |R_k|^2 (in the
+ * residual's precision, one rounding per operation in a fixed order); per
+ * group (QC_MAD_GLOBAL: every such sample; QC_MAD_BASELINE: every unordered
+ * antenna pair) m = lower median of s, d = lower median of |s - m| (the
+ * lower median of N values is the one of rank floor((N - 1) / 2)).  A sample
+ * is flagged when s > m + k d (float64); a group with d = 0 flags nothing;
+ * non-finite s take no part.  flag_out[r][c] (device, may equal vis->flag)
+ * receives the input flag where it is set, else 1 for a new outlier, else 0.
+ * stats (device, may be NULL): [n_groups][2] double (m, d); n_groups = 1 for
+ * QC_MAD_GLOBAL, n_ant (n_ant - 1) / 2 for QC_MAD_BASELINE with the pair
+ * (p, q), p < q, at p n_ant - p (p + 1) / 2 + q - p - 1.  n_flagged (host,
+ * may be NULL) receives the number of new flags (the call then waits).
+ * k must be finite and >= 0.  Scratch memory is owned by ctx. */
+typedef enum { QC_MAD_GLOBAL = 0, QC_MAD_BASELINE = 1 } qc_mad_mode;
+qc_status qc_mad_flag(qc_ctx* ctx, const qc_vis* vis, const void* resid, qc_mad_mode mode, double k,
+                      uint8_t* flag_out, double* stats, int64_t* n_flagged, void* stream);
 
 /*
  * Learned warm start (a two-layer MLP from interval features to initial

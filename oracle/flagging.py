@@ -13,7 +13,8 @@ The paper names the method but not its formulas; the readings taken here:
   one rounding per operation in the fixed order
   s = ((w0 (re0^2 + im0^2) + w1 (re1^2 + im1^2)) + w2 (...)) + w3 (...),
   each square and each product rounded (no fused operations).
-* Samples entering the statistics: unflagged cross-correlations (p != q).
+* Samples entering the statistics: unflagged cross-correlations (p != q)
+  whose statistic is finite.
 * Groups: all of them (global), or one group per unordered antenna pair
   (per baseline).
 * Median: the lower median, the element of rank floor((N - 1) / 2) in
@@ -63,13 +64,16 @@ def lower_median(x):
 
 
 def group_ids(vis, mode):
-    """Group of every row: 0 for all rows (global) or p * n_ant + q with p < q
-    (per baseline)."""
+    """Group of every row: 0 for all rows (global) or, per baseline, the
+    position of the pair (p, q), p < q, in the order (0,1), (0,2), ...,
+    (n_ant-2, n_ant-1)."""
     a1, a2 = np.asarray(vis.ant1), np.asarray(vis.ant2)
     if mode == "global":
         return np.zeros(a1.shape, dtype=np.int64)
-    p, q = np.minimum(a1, a2), np.maximum(a1, a2)
-    return p.astype(np.int64) * int(vis.n_ant) + q
+    p = np.minimum(a1, a2).astype(np.int64)
+    q = np.maximum(a1, a2).astype(np.int64)
+    n = int(vis.n_ant)
+    return p * n - p * (p + 1) // 2 + (q - p - 1)
 
 
 def mad_flag(vis, resid, k, mode="baseline"):
@@ -78,7 +82,8 @@ def mad_flag(vis, resid, k, mode="baseline"):
     flag = np.asarray(vis.flag)
     a1, a2 = np.asarray(vis.ant1), np.asarray(vis.ant2)
     cross = (a1 != a2)
-    use = (flag == 0) & cross[:, None]
+    with np.errstate(invalid="ignore"):
+        use = (flag == 0) & cross[:, None] & np.isfinite(s)
     gid = group_ids(vis, mode)
     out = flag.copy()
     stats = {}

@@ -164,6 +164,23 @@ qc_status read_err(qc_ctx* ctx, hipStream_t s) {
 
 // Validates the rows on the device and (when active >= 0) computes the row
 // and channel ranges of every solution interval of the active term.
+qc_status validate_rows(qc_ctx* ctx, const qc_vis* v, hipStream_t s) {
+  qc_status st = check_vis(ctx, v);
+  if (st != QC_OK) return st;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  VisArgs va;
+  ChainArgs ca;
+  fill_args(v, nullptr, 0, -1, va, ca);
+  HIP_TRY(ctx, grow(ctx->d_rowpos, ctx->rowpos_cap, (size_t)v->n_time + 1));
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, ctx->d_err);
+  if (v->n_row > 0) {
+    const long long nb = (v->n_row + 255) / 256;
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(256), 0, s, va, ctx->d_rowpos, ctx->d_err);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return read_err(ctx, s);
+}
+
 qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
                   std::vector<HostMaps>& maps, hipStream_t s) {
   qc_status st = check_vis(ctx, v);
@@ -278,6 +295,12 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_dh);
   hipFree(ctx->d_partials);
   hipFree(ctx->d_otab);
+  hipFree(ctx->d_fl_stat);
+  hipFree(ctx->d_fl_groups);
+  hipFree(ctx->d_fl_hist);
+  hipFree(ctx->d_fl_count);
+  hipFree(ctx->d_fl_rows);
+  hipFree(ctx->d_fl_new);
   hipFree(ctx->d_passes);
   hipFree(ctx->d_done);
   hipFree(ctx->d_active);

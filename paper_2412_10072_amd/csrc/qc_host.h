@@ -42,6 +42,19 @@ struct qc_ctx {
   size_t partials_cap = 0;
   unsigned char* d_otab = nullptr;    // fixed chain factors of diagonal chains
   size_t otab_cap = 0;
+  // MAD flagging scratch
+  unsigned char* d_fl_stat = nullptr;  // per-sample statistic
+  size_t fl_stat_cap = 0;
+  unsigned char* d_fl_groups = nullptr;
+  size_t fl_groups_cap = 0;
+  unsigned* d_fl_hist = nullptr;
+  size_t fl_hist_cap = 0;
+  int* d_fl_count = nullptr;
+  size_t fl_count_cap = 0;
+  int* d_fl_rows = nullptr;
+  size_t fl_rows_cap = 0;
+  unsigned long long* d_fl_new = nullptr;
+  size_t fl_new_cap = 0;
   int* d_passes = nullptr;
   size_t passes_cap = 0;
   uint8_t* d_done = nullptr;
@@ -99,6 +112,9 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
                   std::vector<HostMaps>& maps, hipStream_t s);
 void fill_args(const qc_vis* v, const qc_term* chain, int n_term, int active, VisArgs& va, ChainArgs& ca);
 qc_status read_err(qc_ctx* ctx, hipStream_t s);
+// check_vis plus the device checks of row order and antenna/time ranges
+// (waits for them); for calls that take no chain
+qc_status validate_rows(qc_ctx* ctx, const qc_vis* v, hipStream_t s);
 int resolve_damping(qc_damping d, const qc_term& t);
 bool dmap_constant(const HostMaps& hm);
 

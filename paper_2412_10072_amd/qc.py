@@ -33,7 +33,8 @@ EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "q
            "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
-           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels")
+           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag")
+MAD_MODES = {"global": 0, "baseline": 1}
 BATCH_BUCKETS = 6
 
 
@@ -102,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                    C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_residual.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32,
                                 C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.qc_mad_flag.argtypes = [C.c_void_p, C.POINTER(QcVis), C.c_void_p, C.c_int32, C.c_double, C.c_void_p,
+                                C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]
     lib.qc_batch_create.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(QcSolveOpts), C.POINTER(C.c_void_p)]
     lib.qc_batch_tune.argtypes = [C.c_void_p, C.c_int32]
     lib.qc_batch_run.argtypes = [C.c_void_p, C.c_void_p]
@@ -452,6 +455,29 @@ class Context:
         self._check(self.lib.qc_residual(self.h, C.byref(cv), cc, len(chain), mp, C.c_void_p(out.data_ptr()),
                                          C.c_void_p(_stream_ptr(stream))))
         return out
+
+    def mad_flag(self, vis, resid, mode: str = "baseline", k: float = 5.0, flag_out=None, stats: bool = False,
+                 stream=None):
+        """qc_mad_flag: outlier flags from the residual by the median absolute
+        deviation.  Returns (flags [n_row][n_chan] uint8, number of new flags,
+        per-group (median, MAD) as a float64 tensor [n_groups][2] or None)."""
+        if mode not in MAD_MODES:
+            raise ValueError(f"unknown MAD mode {mode!r}")
+        if not isinstance(resid, torch.Tensor) or resid.dtype != vis.data.dtype or not resid.is_contiguous() \
+                or tuple(resid.shape) != tuple(vis.data.shape) or resid.device != vis.data.device:
+            raise ValueError("resid must be a contiguous tensor shaped and typed like vis.data")
+        if flag_out is None:
+            flag_out = torch.empty_like(vis.flag)
+        n_ant = int(vis.n_ant)
+        n_groups = 1 if mode == "global" else max(1, n_ant * (n_ant - 1) // 2)
+        st = torch.empty(n_groups, 2, dtype=torch.float64, device=vis.data.device) if stats else None
+        n_new = C.c_int64(0)
+        cv = _c_vis(vis)
+        self._check(self.lib.qc_mad_flag(self.h, C.byref(cv), C.c_void_p(resid.data_ptr()), MAD_MODES[mode],
+                                         float(k), C.c_void_p(_ptr(flag_out, torch.uint8, "flag_out")),
+                                         C.c_void_p(st.data_ptr()) if st is not None else None,
+                                         C.byref(n_new), C.c_void_p(_stream_ptr(stream))))
+        return flag_out, int(n_new.value), st
 
     def apply(self, vis, chain, mode: str = "corrupt", dir_mask=None, out=None, stream=None) -> torch.Tensor:
         """qc_apply_gains: CORRUPT (model through the chain) or CORRECT (C_p^-1 D C_q^-H)."""

@@ -531,3 +531,29 @@ def config_chain(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int =
                       flag_frac, dtype, device, block_rows=time_block * nbl)
     return Problem(vis=vis, chain=[K, B, G, dE], truth=truth,
                    meta=dict(name="chain", sigma=sigma, n_samples=n_row * n_chan, n_dir=n_dir))
+
+
+def noise_residual(n_row: int, n_chan: int, device, dtype="c64", sigma: float = 0.1, n_spikes: int = 1000,
+                   spike_lo: float = 2.0, spike_hi: float = 5.0, seed: int = 0, block_rows: int = 65536):
+    """Residual-shaped input [n_row][n_chan][4]: each correlation CN with real
+    and imaginary parts N(0, sigma^2), plus n_spikes samples (row, channel) where
+    one correlation gets a real offset U(spike_lo, spike_hi) (RFI-like outliers).
+    Generated in row blocks in device memory; returns (resid, spike_rows,
+    spike_chans) with the spike positions on the host."""
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    rdt = torch.float32 if dtype == "c64" else torch.float64
+    g = rng(device, 2412, 90, seed)
+    R = torch.empty(n_row, n_chan, 4, dtype=cdt, device=device)
+    for r0 in range(0, n_row, block_rows):
+        r1 = min(n_row, r0 + block_rows)
+        R[r0:r1] = cnormal(g, (r1 - r0, n_chan, 4), sigma, device, dtype=rdt)
+    hs = np.random.default_rng(seed_of(2412, 91, seed))
+    flat = hs.choice(n_row * n_chan, size=min(n_spikes, n_row * n_chan), replace=False)
+    rows, chans = np.unravel_index(flat, (n_row, n_chan))
+    corr = hs.integers(0, 4, rows.size)
+    amp = hs.uniform(spike_lo, spike_hi, rows.size)
+    ri = torch.as_tensor(rows, device=device)
+    ci = torch.as_tensor(chans, device=device)
+    ki = torch.as_tensor(corr, device=device)
+    R[ri, ci, ki] += torch.as_tensor(amp, device=device, dtype=rdt).to(cdt)
+    return R, rows, chans

@@ -19,6 +19,12 @@ one (whole-problem oracle runs at these sizes would take hours).
   * Phase-only and amplitude-only solves on the MeerKAT shape: sampled
     intervals against the oracle (parameters <= 1e-4, iteration counts
     within one).
+  * MAD flagging of a MeerKAT-shaped residual (1.24e9 samples): per baseline,
+    sampled baselines against the oracle exactly (flags, median and MAD);
+    globally, properties that pin the answer at any size: the returned median
+    and MAD have the lower-median rank among the statistics recomputed
+    elementwise on the device, and every flag equals the threshold rule
+    applied to those statistics.
 """
 import sys
 
@@ -27,9 +33,10 @@ import pytest
 import torch
 
 from oracle import delay_init as o_delay
+from oracle import flagging as o_flag
 from oracle import outputs as o_out
 from oracle import solver as o_solver
-from synth.generate import config_chain, config_meerkat
+from synth.generate import config_chain, config_meerkat, noise_residual
 from synth.problem import Vis
 
 pytestmark = pytest.mark.gpu
@@ -208,3 +215,79 @@ def test_parameter_terms_full_size_sampled_parity(qc_lib, kind):
         say(f"{kind} interval ({gt}, {gf}): oracle {ri} updates, gpu {it[gt, gf]}, max |d param| {d:.2e}")
         assert rc == 1 and abs(int(it[gt, gf]) - ri) <= 1
         assert d <= 1e-4 * max(1.0, np.abs(ref[0].params[gt, gf]).max())
+
+
+def rows_vis(vis, rows):
+    """Host copy of the given rows (all channels) of a device visibility set."""
+    idx = torch.as_tensor(rows, device=vis.data.device)
+
+    def h(x):
+        return x.index_select(0, idx).cpu().numpy()
+    return Vis(data=h(vis.data), model=h(vis.model), weight=h(vis.weight), flag=h(vis.flag),
+               ant1=h(vis.ant1), ant2=h(vis.ant2), row_time=h(vis.row_time),
+               chan_freq=vis.chan_freq.cpu().numpy(), n_ant=int(vis.n_ant), n_time=int(vis.n_time))
+
+
+def test_mad_flag_full_size(qc_lib):
+    say("full-size MAD flagging: generating 600 x 1024 x 2016 baselines and a noise residual")
+    p = config_meerkat(device=DEV)
+    vis = p.vis
+    n_row, n_chan = int(vis.data.shape[0]), int(vis.data.shape[1])
+    R, _, _ = noise_residual(n_row, n_chan, DEV, sigma=0.1, n_spikes=20000, seed=3)
+    k = 5.0
+
+    # per baseline: sampled baselines against the oracle, exactly
+    out_b, n_b, st_b = qc_lib.mad_flag(vis, R, mode="baseline", k=k, stats=True)
+    qc_lib.sync()
+    out_b, st_b = out_b.cpu().numpy(), st_b.cpu().numpy()
+    a1, a2 = vis.ant1.cpu().numpy(), vis.ant2.cpu().numpy()
+    rng = np.random.default_rng(5)
+    pairs = [(0, 1), (5, 40), (62, 63)] + [tuple(sorted(rng.choice(64, 2, replace=False))) for _ in range(2)]
+    for pa, qa in pairs:
+        rows = np.nonzero((a1 == pa) & (a2 == qa))[0]
+        vh = rows_vis(vis, rows)
+        want, stats = o_flag.mad_flag(vh, R.index_select(0, torch.as_tensor(rows, device=DEV)).cpu().numpy(),
+                                      k, mode="global")
+        g = pa * 64 - pa * (pa + 1) // 2 + qa - pa - 1
+        say(f"baseline ({pa}, {qa}) group {g}: {len(rows)} rows, median {stats[0][0]:.6g} MAD {stats[0][1]:.6g}, "
+            f"{int(want.sum() - vh.flag.sum())} new flags")
+        assert np.array_equal(out_b[rows], want)
+        assert st_b[g, 0] == stats[0][0] and st_b[g, 1] == stats[0][1]
+    del out_b
+
+    # global: rank properties of (m, d) and the rule on every sample
+    out_g, n_g, st_g = qc_lib.mad_flag(vis, R, mode="global", k=k, stats=True)
+    qc_lib.sync()
+    m64, d64 = float(st_g[0, 0]), float(st_g[0, 1])
+    m = torch.tensor(m64, dtype=torch.float32, device=DEV)
+    assert float(m) == m64 and float(torch.tensor(d64, dtype=torch.float32)) == d64
+    t = m64 + k * d64
+    n_use = n_lt = n_le = d_lt = d_le = n_hit = bad = 0
+    for r0 in range(0, n_row, 65536):
+        r1 = min(n_row, r0 + 65536)
+        Rc, Wc, Fc = R[r0:r1], vis.weight[r0:r1], vis.flag[r0:r1]
+        s = None
+        for c in range(4):                      # one rounding per operation, fixed order
+            a = Rc[..., c].real * Rc[..., c].real
+            b = Rc[..., c].imag * Rc[..., c].imag
+            term = Wc[..., c] * (a + b)
+            s = term if s is None else s + term
+        cross = (vis.ant1[r0:r1] != vis.ant2[r0:r1])[:, None]
+        use = (Fc == 0) & cross & torch.isfinite(s)
+        dev = (s - m).abs()
+        n_use += int(use.sum())
+        n_lt += int((use & (s < m)).sum())
+        n_le += int((use & (s <= m)).sum())
+        d = torch.tensor(d64, dtype=torch.float32, device=DEV)
+        d_lt += int((use & (dev < d)).sum())
+        d_le += int((use & (dev <= d)).sum())
+        hit = use & (s.double() > t)
+        n_hit += int(hit.sum())
+        want = torch.where(Fc != 0, Fc, hit.to(torch.uint8))
+        bad += int((want != out_g[r0:r1]).sum())
+    rank = (n_use - 1) // 2
+    say(f"global: {n_use} samples, median {m64:.6g} (below {n_lt}, at or below {n_le}), MAD {d64:.6g} "
+        f"(below {d_lt}, at or below {d_le}), rank {rank}; {n_hit} new flags, {bad} mismatches")
+    assert n_lt <= rank < n_le
+    assert d_lt <= rank < d_le
+    assert bad == 0 and n_g == n_hit

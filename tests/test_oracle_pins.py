@@ -675,7 +675,7 @@ def test_per_baseline_equals_global_for_one_baseline():
     vis, R = _noise_vis(rng, n_ant=2, n_time=200)
     a, sa = flagging.mad_flag(vis, R, 3.0, mode="global")
     b, sb = flagging.mad_flag(vis, R, 3.0, mode="baseline")
-    assert np.array_equal(a, b) and sa[0] == sb[1]
+    assert np.array_equal(a, b) and sa[0] == sb[0]
 
 
 def test_flagged_garbage_does_not_move_the_statistics():
