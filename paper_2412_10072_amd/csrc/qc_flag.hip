@@ -32,6 +32,20 @@ constexpr int FL_THREADS = 256;
 constexpr int FL_ROWS = 64;          // rows of the list per workgroup chunk
 constexpr int DIGIT = 11;
 constexpr int NBIN = 1 << DIGIT;
+// LDS histogram copies per workgroup (lane i counts into copy i mod NREP), one
+// bank apart, so that lanes whose keys share a bin do not all hit one address
+constexpr int NREP = 4;
+constexpr int HSTRIDE = NBIN + 1;
+
+// 16 bytes of statistics (4 floats or 2 doubles), one vector load
+template <typename S> struct alignas(16) Vec16 {
+  static constexpr int N = 16 / sizeof(S);
+  S v[N];
+};
+// the matching flags
+template <typename S> struct alignas(16 / sizeof(S)) Flag16 {
+  uint8_t f[16 / sizeof(S)];
+};
 
 struct GroupState {
   unsigned long long prefix;         // selected high bits of the key
@@ -69,6 +83,7 @@ struct FlagArgs {
   unsigned* hist;                    // [n_groups][NBIN]
   int shift, bits;                   // digit of this pass
   int phase;                         // 0: median of s; 1: median of |s - m|
+  bool vec_r, vec_w;                 // residual / weights aligned for whole-sample loads
   double k;
   uint8_t* flag_out;
   unsigned long long* n_new;
@@ -99,17 +114,41 @@ __device__ __forceinline__ long long list_len(const FlagArgs& A) {
 // s of one sample: ((w0 (re0^2 + im0^2) + w1 (...)) + w2 (...)) + w3 (...),
 // every operation rounded on its own (floating-point contraction is off in
 // these functions, so no fused multiply-add is formed).
+template <typename S> struct alignas(8 * sizeof(S)) Resid4 {
+  S v[8];                              // four complex correlations
+};
+template <typename S> struct alignas(4 * sizeof(S)) Weight4 {
+  S v[4];
+};
+
+// vec_r / vec_w: the residual / weights are aligned for whole-sample loads
 template <typename S>
-__device__ __forceinline__ S sample_stat(const S* R, const S* W, int n_wcorr, size_t s) {
+__device__ __forceinline__ S sample_stat(const S* R, const S* W, int n_wcorr, bool vec_r, bool vec_w, size_t s) {
 #pragma clang fp contract(off)
+  Resid4<S> r;
+  if (vec_r) {
+    r = reinterpret_cast<const Resid4<S>*>(R)[s];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r.v[j] = R[8 * s + j];
+  }
+  Weight4<S> w;
+  if (n_wcorr == 4 && vec_w) {
+    w = reinterpret_cast<const Weight4<S>*>(W)[s];
+  } else if (n_wcorr == 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w.v[k] = W[4 * s + k];
+  } else {
+    const S w0 = W[s];
+    w.v[0] = w.v[1] = w.v[2] = w.v[3] = w0;
+  }
   S acc = S(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const S re = R[8 * s + 2 * k], im = R[8 * s + 2 * k + 1];
-    const S w = W[n_wcorr == 4 ? 4 * s + k : s];
+    const S re = r.v[2 * k], im = r.v[2 * k + 1];
     const S a = re * re;
     const S b = im * im;
-    const S t = w * (a + b);
+    const S t = w.v[k] * (a + b);
     acc = k == 0 ? t : acc + t;
   }
   return acc;
@@ -170,7 +209,7 @@ __global__ void k_fl_init(GroupState* gs, int n_groups) {
 // ---- statistic pass: s (or -1) per sample, samples per group ----
 template <typename S>
 __global__ void __launch_bounds__(FL_THREADS) k_fl_stat(FlagArgs A) {
-  __shared__ int s_cnt[FL_THREADS / 64];
+  __shared__ long long s_cnt[FL_THREADS / 64];
   const S* R = reinterpret_cast<const S*>(A.resid);
   const S* W = reinterpret_cast<const S*>(A.vis.weight);
   S* out = reinterpret_cast<S*>(A.stat);
@@ -178,35 +217,55 @@ __global__ void __launch_bounds__(FL_THREADS) k_fl_stat(FlagArgs A) {
   const long long i0 = (long long)blockIdx.x * FL_ROWS;
   const long long i1 = min(list_len(A), i0 + FL_ROWS);
   int cur = -1;
-  long long acc = 0;                 // thread 0: samples of group `cur` so far
-  for (long long i = i0; i < i1; ++i) {
-    const long long r = list_row(A, i);
-    const int g = group_of(A, r);
-    if (g != cur) {
-      if (threadIdx.x == 0 && cur >= 0 && acc > 0) atomicAdd((unsigned long long*)&A.gs[cur].n, (unsigned long long)acc);
-      cur = g;
-      acc = 0;
-    }
-    int mine = 0;
-    for (int c = threadIdx.x; c < n_chan; c += FL_THREADS) {
-      const size_t s = (size_t)r * n_chan + c;
-      bool use = g >= 0 && A.vis.flag[s] == 0;
-      const S v = use ? sample_stat<S>(R, W, A.vis.n_wcorr, s) : S(-1);
-      use = use && isfinite(v);          // non-finite statistics take no part
-      out[s] = use ? v : S(-1);
-      mine += use ? 1 : 0;
-    }
-    // workgroup sum of `mine` (fixed order)
-    int w = mine;
+  int mine = 0;                      // this thread's used samples of group `cur`
+  // workgroup sum of `mine` (fixed order) added to the group's count
+  auto flush = [&]() {
+    long long w = mine;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) w += __shfl_xor(w, o);
     if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = w;
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+      long long acc = 0;
       for (int k = 0; k < FL_THREADS / 64; ++k) acc += s_cnt[k];
+      if (acc > 0) atomicAdd((unsigned long long*)&A.gs[cur].n, (unsigned long long)acc);
+    }
     __syncthreads();
+    mine = 0;
+  };
+  auto one = [&](size_t e, bool live) {
+    const uint8_t f = A.vis.flag[e];
+    const S v = sample_stat<S>(R, W, A.vis.n_wcorr, A.vec_r, A.vec_w, e);
+    const bool use = live && f == 0 && isfinite(v);   // non-finite statistics take no part
+    out[e] = use ? v : S(-1);
+    mine += use ? 1 : 0;
+  };
+  long long i = i0;
+  while (i < i1) {                   // i, r, g: uniform over the workgroup
+    const long long r = list_row(A, i);
+    const int g = group_of(A, r);
+    if (g != cur) {
+      if (cur >= 0) flush();
+      cur = g;
+    }
+    const bool live = g >= 0;
+    if (i + 4 <= i1) {               // four rows of one group in flight
+      const long long r1 = list_row(A, i + 1), r2 = list_row(A, i + 2), r3 = list_row(A, i + 3);
+      if (group_of(A, r1) == g && group_of(A, r2) == g && group_of(A, r3) == g) {
+        for (int c = threadIdx.x; c < n_chan; c += FL_THREADS) {
+          one((size_t)r * n_chan + c, live);
+          one((size_t)r1 * n_chan + c, live);
+          one((size_t)r2 * n_chan + c, live);
+          one((size_t)r3 * n_chan + c, live);
+        }
+        i += 4;
+        continue;
+      }
+    }
+    for (int c = threadIdx.x; c < n_chan; c += FL_THREADS) one((size_t)r * n_chan + c, live);
+    ++i;
   }
-  if (threadIdx.x == 0 && cur >= 0 && acc > 0) atomicAdd((unsigned long long*)&A.gs[cur].n, (unsigned long long)acc);
+  if (cur >= 0) flush();
 }
 
 __global__ void k_fl_rank(GroupState* gs, int n_groups) {
@@ -231,31 +290,52 @@ template <typename S>
 __global__ void __launch_bounds__(FL_THREADS) k_fl_hist(FlagArgs A) {
   using K = KeyT<S>;
   using U = typename K::U;
-  __shared__ unsigned h[NBIN];
+  using V = Vec16<S>;
+  __shared__ unsigned h[NREP * HSTRIDE];
   const S* st = reinterpret_cast<const S*>(A.stat);
   const int n_chan = A.vis.n_chan;
+  const bool vec = n_chan % V::N == 0;
+  const int nv = n_chan / V::N;
   const long long i0 = (long long)blockIdx.x * FL_ROWS;
   const long long i1 = min(list_len(A), i0 + FL_ROWS);
   const U dmask = (U)((1u << A.bits) - 1u);
-  for (int b = threadIdx.x; b < NBIN; b += FL_THREADS) h[b] = 0;
+  for (int b = threadIdx.x; b < NREP * HSTRIDE; b += FL_THREADS) h[b] = 0;
   __syncthreads();
+  unsigned* hm = h + (threadIdx.x & (NREP - 1)) * HSTRIDE;   // this lane's copy
   int cur = -1;
   U prefix = 0, mask = 0;
   S m = S(0);
   bool live = false;
-  for (long long i = i0; i < i1; ++i) {
+  auto count = [&](S s) {
+    if (!(s >= S(0))) return;                        // unused sample
+    const U key = K::of(phase_value<S>(s, A.phase, m));
+    if ((key & mask) != prefix) return;
+    atomicAdd(&hm[(unsigned)((key >> A.shift) & dmask)], 1u);
+  };
+  auto count_vec = [&](const V& v) {
+#pragma unroll
+    for (int j = 0; j < V::N; ++j) count(v.v[j]);
+  };
+  // sum of the copies into the group's histogram; clears the copies
+  auto flush = [&]() {
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBIN; b += FL_THREADS) {
+      unsigned v = 0;
+#pragma unroll
+      for (int q = 0; q < NREP; ++q) {
+        v += h[q * HSTRIDE + b];
+        h[q * HSTRIDE + b] = 0;
+      }
+      if (v) atomicAdd(&A.hist[(size_t)cur * NBIN + b], v);
+    }
+    __syncthreads();
+  };
+  long long i = i0;
+  while (i < i1) {                                   // i, r, g: uniform over the workgroup
     const long long r = list_row(A, i);
     const int g = group_of(A, r);
     if (g != cur) {
-      if (cur >= 0 && live) {
-        __syncthreads();
-        for (int b = threadIdx.x; b < NBIN; b += FL_THREADS) {
-          const unsigned v = h[b];
-          if (v) atomicAdd(&A.hist[(size_t)cur * NBIN + b], v);
-          h[b] = 0;
-        }
-        __syncthreads();
-      }
+      if (cur >= 0 && live) flush();
       cur = g;
       live = g >= 0 && A.gs[g].n > 0;
       if (live) {
@@ -264,22 +344,37 @@ __global__ void __launch_bounds__(FL_THREADS) k_fl_hist(FlagArgs A) {
         m = (S)A.gs[g].m;
       }
     }
-    if (!live) continue;
-    for (int c = threadIdx.x; c < n_chan; c += FL_THREADS) {
-      const S s = st[(size_t)r * n_chan + c];
-      if (!(s >= S(0))) continue;                    // unused sample
-      const U key = K::of(phase_value<S>(s, A.phase, m));
-      if ((key & mask) != prefix) continue;
-      atomicAdd(&h[(unsigned)((key >> A.shift) & dmask)], 1u);
+    if (vec && i + 4 <= i1) {                        // four rows of one group in flight
+      const long long r1 = list_row(A, i + 1), r2 = list_row(A, i + 2), r3 = list_row(A, i + 3);
+      if (group_of(A, r1) == g && group_of(A, r2) == g && group_of(A, r3) == g) {
+        if (live) {
+          const V* p0 = reinterpret_cast<const V*>(st + (size_t)r * n_chan);
+          const V* p1 = reinterpret_cast<const V*>(st + (size_t)r1 * n_chan);
+          const V* p2 = reinterpret_cast<const V*>(st + (size_t)r2 * n_chan);
+          const V* p3 = reinterpret_cast<const V*>(st + (size_t)r3 * n_chan);
+          for (int c = threadIdx.x; c < nv; c += FL_THREADS) {
+            const V v0 = p0[c], v1 = p1[c], v2 = p2[c], v3 = p3[c];
+            count_vec(v0);
+            count_vec(v1);
+            count_vec(v2);
+            count_vec(v3);
+          }
+        }
+        i += 4;
+        continue;
+      }
     }
-  }
-  if (cur >= 0 && live) {
-    __syncthreads();
-    for (int b = threadIdx.x; b < NBIN; b += FL_THREADS) {
-      const unsigned v = h[b];
-      if (v) atomicAdd(&A.hist[(size_t)cur * NBIN + b], v);
+    if (live) {
+      if (vec) {
+        const V* p0 = reinterpret_cast<const V*>(st + (size_t)r * n_chan);
+        for (int c = threadIdx.x; c < nv; c += FL_THREADS) count_vec(p0[c]);
+      } else {
+        for (int c = threadIdx.x; c < n_chan; c += FL_THREADS) count(st[(size_t)r * n_chan + c]);
+      }
     }
+    ++i;
   }
+  if (cur >= 0 && live) flush();
 }
 
 // ---- one wavefront per group: the digit holding the wanted rank ----
@@ -339,29 +434,67 @@ __global__ void __launch_bounds__(64) k_fl_select(FlagArgs A, int last) {
 template <typename S>
 __global__ void __launch_bounds__(FL_THREADS) k_fl_apply(FlagArgs A) {
 #pragma clang fp contract(off)
+  using V = Vec16<S>;
+  using F = Flag16<S>;
   __shared__ unsigned s_cnt[FL_THREADS / 64];
   const S* st = reinterpret_cast<const S*>(A.stat);
   const int n_chan = A.vis.n_chan;
+  const bool vec = n_chan % V::N == 0 && reinterpret_cast<uintptr_t>(A.vis.flag) % V::N == 0 &&
+                   reinterpret_cast<uintptr_t>(A.flag_out) % V::N == 0;
+  const int nv = n_chan / V::N;
   const long long r0 = (long long)blockIdx.x * FL_ROWS;
   const long long r1 = min(A.vis.n_row, r0 + FL_ROWS);
   unsigned mine = 0;
-  for (long long r = r0; r < r1; ++r) {
+  // the rule of row r's group: whether it can flag, and its threshold
+  auto rule = [&](long long r, double& t) -> bool {
     const int g = group_of(A, r);
-    double t = 0.0;
-    bool live = false;
-    if (g >= 0) {
-      const GroupState& G = A.gs[g];
-      live = G.n > 0 && G.d > 0.0;
-      const double kd = A.k * G.d;
-      t = G.m + kd;
+    t = 0.0;
+    if (g < 0) return false;
+    const GroupState& G = A.gs[g];
+    const double kd = A.k * G.d;
+    t = G.m + kd;
+    return G.n > 0 && G.d > 0.0;
+  };
+  auto one = [&](uint8_t fin, S v, bool live, double t) -> uint8_t {
+    const bool hit = live && fin == 0 && v >= S(0) && (double)v > t;
+    mine += hit ? 1u : 0u;
+    return fin ? fin : (hit ? (uint8_t)1 : (uint8_t)0);
+  };
+  long long r = r0;
+  if (vec) {
+    const V* sv = reinterpret_cast<const V*>(st);
+    const F* fv = reinterpret_cast<const F*>(A.vis.flag);
+    F* ov = reinterpret_cast<F*>(A.flag_out);
+    for (; r + 4 <= r1; r += 4) {                    // four rows in flight
+      double t[4];
+      bool lv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lv[j] = rule(r + j, t[j]);
+      for (int c = threadIdx.x; c < nv; c += FL_THREADS) {
+        V v[4];
+        F f[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const size_t e = (size_t)(r + j) * nv + c;
+          v[j] = sv[e];
+          f[j] = fv[e];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          F o;
+#pragma unroll
+          for (int q = 0; q < V::N; ++q) o.f[q] = one(f[j].f[q], v[j].v[q], lv[j], t[j]);
+          ov[(size_t)(r + j) * nv + c] = o;
+        }
+      }
     }
+  }
+  for (; r < r1; ++r) {
+    double t;
+    const bool live = rule(r, t);
     for (int c = threadIdx.x; c < n_chan; c += FL_THREADS) {
-      const size_t s = (size_t)r * n_chan + c;
-      const uint8_t fin = A.vis.flag[s];
-      const S v = st[s];
-      const bool hit = live && fin == 0 && v >= S(0) && (double)v > t;
-      A.flag_out[s] = fin ? fin : (hit ? (uint8_t)1 : (uint8_t)0);
-      mine += hit ? 1u : 0u;
+      const size_t e = (size_t)r * n_chan + c;
+      A.flag_out[e] = one(A.vis.flag[e], st[e], live, t);
     }
   }
   unsigned w = mine;
@@ -454,6 +587,8 @@ qc_status qc_mad_flag(qc_ctx* ctx, const qc_vis* vis, const void* resid, qc_mad_
   ChainArgs ca;
   fill_args(vis, nullptr, 0, -1, A.vis, ca);
   A.resid = resid;
+  A.vec_r = reinterpret_cast<uintptr_t>(resid) % (8 * elt) == 0;
+  A.vec_w = reinterpret_cast<uintptr_t>(vis->weight) % (4 * elt) == 0;
   A.mode = mode == QC_MAD_GLOBAL ? 0 : 1;
   A.n_groups = n_groups;
   A.stat = ctx->d_fl_stat;

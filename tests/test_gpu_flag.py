@@ -84,11 +84,13 @@ def check(vis, R, mode, k, out, n_new, st):
             assert st[g, 0] == 0.0 and st[g, 1] == 0.0
 
 
+@pytest.mark.parametrize("n_chan", [70, 72])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("mode", ["global", "baseline"])
-def test_flags_and_statistics_match_oracle(qc_lib, dtype, mode):
-    say(f"mad flag {dtype} {mode}")
-    vis, R = noise_problem(401, dtype=dtype)
+def test_flags_and_statistics_match_oracle(qc_lib, dtype, mode, n_chan):
+    """70 channels: rows of whole 16-byte vectors in FP64 only; 72: in both."""
+    say(f"mad flag {dtype} {mode} n_chan={n_chan}")
+    vis, R = noise_problem(401, dtype=dtype, n_chan=n_chan)
     for k in (0.0, 3.0, 8.0):
         out, n_new, st = run_gpu(qc_lib, vis, R, mode, k)
         check(vis, R, mode, k, out, n_new, st)
@@ -139,3 +141,34 @@ def test_in_place_flags_and_rejections(qc_lib):
         qc_lib.mad_flag(vd, Rd, mode="baseline", k=-1.0)
     with pytest.raises(ValueError):
         qc_lib.mad_flag(vd, Rd[:-1].contiguous(), mode="baseline", k=1.0)
+
+
+def offset_copy(t, offset):
+    """Contiguous device copy of t starting `offset` elements into a larger buffer."""
+    buf = torch.zeros(t.numel() + offset, dtype=t.dtype, device=t.device)
+    v = buf[offset:].view(t.shape)
+    v.copy_(t)
+    return v
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_unaligned_buffers(qc_lib, dtype):
+    """Residual, weights and output flags at offsets that rule out whole-sample
+    vector loads (the kernels then load element by element) give the oracle's
+    answer."""
+    from paper_2412_10072_amd import qc
+    say(f"mad flag unaligned buffers {dtype}")
+    vis, R = noise_problem(431, dtype=dtype, n_chan=72)
+    want, stats = o_flag.mad_flag(vis, R, 4.0, mode="baseline")
+    vd = qc.device_vis(vis, DEV)
+    vd = vd.copy(weight=offset_copy(vd.weight, 1))
+    Rd = offset_copy(torch.as_tensor(R).to(DEV), 1)
+    buf = torch.full((vis.flag.size + 1,), 7, dtype=torch.uint8, device=DEV)
+    out = buf[1:].view(vis.flag.shape)
+    _, n_new, st = qc_lib.mad_flag(vd, Rd, mode="baseline", k=4.0, flag_out=out, stats=True)
+    qc_lib.sync()
+    assert np.array_equal(out.cpu().numpy(), want)
+    assert int(buf[0]) == 7
+    st = st.cpu().numpy()
+    for g, (m, d) in stats.items():
+        assert st[g, 0] == m and st[g, 1] == d
