@@ -4,7 +4,7 @@ None of these compare the oracle with itself."""
 import numpy as np
 import pytest
 
-from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging
+from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging, predict
 from oracle.jones import PERM, dagger, unvec, vec
 from synth.generate import config_tiny, to_numpy_vis
 from helpers import (forward_data, make_term, make_vis, rand_c, reference_diag, unit_like)
@@ -690,3 +690,129 @@ def test_flagged_garbage_does_not_move_the_statistics():
     out1, st1 = flagging.mad_flag(vis, R, 5.0)
     out2, st2 = flagging.mad_flag(vis2, R2, 5.0)
     assert np.array_equal(out1, out2) and st1 == st2
+
+
+# ---------------------------------------------------------------------------
+# DFT prediction of component models (Section 4.6)
+# ---------------------------------------------------------------------------
+
+def _sky(rng, n_comp, n_dir, radius=0.02, pol=True):
+    lm = rng.uniform(-radius, radius, (n_comp, 2))
+    st = np.zeros((n_comp, 4))
+    st[:, 0] = rng.uniform(0.1, 2.0, n_comp)
+    if pol:
+        st[:, 1:] = rng.uniform(-0.1, 0.1, (n_comp, 3))
+    spi = rng.uniform(-1.0, 0.5, n_comp)
+    nu0 = rng.uniform(0.9e9, 1.5e9, n_comp)
+    d = rng.integers(0, n_dir, n_comp)
+    return lm, st, spi, nu0, d
+
+
+def test_predict_phase_centre_is_the_brightness():
+    """l = m = 0: no delay on any baseline, so every row predicts B(nu)."""
+    rng = np.random.default_rng(101)
+    uvw = rng.normal(0, 3000, (9, 3))
+    nu = np.array([0.9e9, 1.2e9, 1.5e9])
+    st = np.array([[1.5, 0.2, -0.1, 0.05]])
+    M = predict.predict_dft(uvw, nu, [[0.0, 0.0]], st, [-0.7], [1.2e9], [0], 1)
+    spec = (nu / 1.2e9) ** -0.7
+    want = np.array([1.7, -0.1 + 0.05j, -0.1 - 0.05j, 1.3])
+    for r in range(9):
+        assert np.allclose(M[r, :, 0, :], spec[:, None] * want[None, :], rtol=1e-15, atol=0)
+
+
+def test_predict_grid_source_matches_fft():
+    """A unit point source on pixel (jl, jm) of an N x N grid of cell dl, seen
+    at w = 0 on the uv grid point (ku, kv) (u = ku / (N dl) wavelengths), is
+    entry (ku, kv) of numpy's 2-D FFT of the one-pixel image."""
+    N, dl = 16, 1e-3
+    jl, jm = 3, 13                       # l = 3 dl, m = 13 dl (aliased to -3 dl in the FFT)
+    img = np.zeros((N, N))
+    img[jl, jm] = 1.0
+    F = np.fft.fft2(img)
+    nu = np.array([1.0e9, 1.4e9])
+    rows, want = [], []
+    for ku in range(N):
+        for kv in range(N):
+            rows.append((ku, kv))
+            want.append(F[ku, kv])
+    uvw = []
+    for nuk in nu:
+        lam = predict.C_LIGHT / nuk
+        uvw.append([[ku / (N * dl) * lam, kv / (N * dl) * lam, 0.0] for ku, kv in rows])
+    lmx = [[jl * dl, jm * dl]]
+    for k, nuk in enumerate(nu):
+        M = predict.predict_dft(np.array(uvw[k]), [nuk], lmx, [[1.0, 0, 0, 0]], [0.0], [1e9], [0], 1)
+        assert np.allclose(M[:, 0, 0, 0], want, atol=1e-12)
+        assert np.allclose(M[:, 0, 0, 3], want, atol=1e-12)
+        assert np.abs(M[:, 0, 0, 1:3]).max() == 0.0
+
+
+def test_predict_conjugate_baseline_is_hermitian_transpose():
+    """Reversing the baseline (uvw -> -uvw) conjugates the phases; with a
+    Hermitian brightness the prediction becomes M^H (XY <-> conj YX)."""
+    rng = np.random.default_rng(103)
+    lm, st, spi, nu0, d = _sky(rng, 7, 2)
+    uvw = rng.normal(0, 2000, (11, 3))
+    nu = np.linspace(0.9e9, 1.6e9, 5)
+    A = predict.predict_dft(uvw, nu, lm, st, spi, nu0, d, 2)
+    B = predict.predict_dft(-uvw, nu, lm, st, spi, nu0, d, 2)
+    AH = np.conj(A[..., [0, 2, 1, 3]])
+    assert np.allclose(B, AH, rtol=0, atol=1e-12)
+
+
+def test_predict_is_linear_in_components_and_directions_separate():
+    rng = np.random.default_rng(107)
+    lm, st, spi, nu0, d = _sky(rng, 6, 3)
+    uvw = rng.normal(0, 2000, (8, 3))
+    nu = np.linspace(1.0e9, 1.5e9, 4)
+    full = predict.predict_dft(uvw, nu, lm, st, spi, nu0, d, 3)
+    parts = sum(predict.predict_dft(uvw, nu, lm[i:i + 1], st[i:i + 1], spi[i:i + 1], nu0[i:i + 1], d[i:i + 1], 3)
+                for i in range(6))
+    assert np.allclose(full, parts, rtol=0, atol=1e-13)
+    for k in range(3):
+        if not (d == k).any():
+            assert np.abs(full[:, :, k]).max() == 0.0
+        keep = d == k
+        only = predict.predict_dft(uvw, nu, lm[keep], st[keep], spi[keep], nu0[keep], d[keep], 3)
+        assert np.allclose(full[:, :, k], only[:, :, k], rtol=0, atol=1e-13)
+
+
+def test_predict_spectral_law():
+    """(nu / nu0)^alpha on every Stokes parameter: 1 at nu0, 2^alpha at 2 nu0."""
+    st = np.array([[2.0, 0.3, 0.1, -0.2]])
+    for alpha in (-0.8, 0.0, 1.5):
+        M = predict.predict_dft(np.zeros((1, 3)), [1e9, 2e9], [[0.0, 0.0]], st, [alpha], [1e9], [0], 1)
+        assert np.allclose(M[0, 1, 0], (2.0 ** alpha) * M[0, 0, 0], rtol=1e-15)
+        assert np.allclose(M[0, 0, 0], [2.3, 0.1 - 0.2j, 0.1 + 0.2j, 1.7], rtol=1e-15)
+
+
+def test_predict_stokes_structure():
+    """Stokes Q splits XX from YY with opposite signs; U is real and V
+    imaginary on the cross hands, opposite in XY and YX."""
+    z = np.zeros((1, 3))
+    one = lambda s: predict.predict_dft(z, [1e9], [[0.0, 0.0]], [s], [0.0], [1e9], [0], 1)[0, 0, 0]
+    assert np.allclose(one([0, 1, 0, 0]), [1, 0, 0, -1])
+    assert np.allclose(one([0, 0, 1, 0]), [0, 1, 1, 0])
+    assert np.allclose(one([0, 0, 0, 1]), [0, 1j, -1j, 0])
+
+
+def test_predict_matches_the_generator_sum():
+    """Agrees with the synthetic-data generator's own point-source sum (an
+    independent evaluation on the device library) for unpolarised flat
+    spectra."""
+    import torch
+    from synth.generate import point_source_vis
+    rng = np.random.default_rng(109)
+    lm, st, _, _, _ = _sky(rng, 5, 1, pol=False)
+    uvw = rng.normal(0, 3000, (13, 3))
+    nu = np.linspace(0.86e9, 1.71e9, 9)
+    M = predict.predict_dft(uvw, nu, lm, st, np.zeros(5), np.ones(5), np.zeros(5, int), 1)
+    G = point_source_vis(torch.as_tensor(uvw), torch.as_tensor(nu), torch.as_tensor(lm[:, 0]),
+                         torch.as_tensor(lm[:, 1]), torch.as_tensor(st[:, 0])).numpy()
+    # the two sums round the phase argument (up to ~5000 rad here) in
+    # different orders: a few ulps of the largest phase per component
+    ph_max = 2 * np.pi * np.abs(uvw).sum(1).max() * np.abs(lm).max() * nu.max() / predict.C_LIGHT
+    tol = 8 * np.finfo(float).eps * ph_max * st[:, 0].sum()
+    assert np.abs(M[:, :, 0, 0] - G).max() <= tol
+    assert np.abs(M[:, :, 0, 3] - G).max() <= tol
