@@ -421,6 +421,67 @@ def flag_pass_bytes(vis) -> dict:
                 one_pass=8 * e + wcorr * e + 1 + 1)
 
 
+LANE_SLOTS_PER_S = 256 * 64 * 2.4e9       # CUs x lanes issued per cycle x clock
+PREDICT_SLOTS = 16                          # minimal issue slots per component-sample (flat, unpolarised)
+
+
+def leg_predict(ctx, prob, reps: int = 3):
+    """DFT prediction of the main workload's model (MeerKAT shape, 20 point
+    sources) from its component list, then the plain solve from that model;
+    and the same components with full Stokes and spectral indices."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+    vis = prob.vis
+    dev = vis.data.device
+    n_row, n_chan = int(vis.data.shape[0]), int(vis.data.shape[1])
+    l, m, flux = prob.meta["sky"][0]
+    n_comp = int(l.shape[0])
+    uvw = prob.meta["uvw"]
+    lm = torch.stack([l, m], 1).contiguous()
+    st = torch.zeros(n_comp, 4, dtype=torch.float64, device=dev)
+    st[:, 0] = flux
+    spi = torch.zeros(n_comp, dtype=torch.float64, device=dev)
+    nu0 = torch.full((n_comp,), 1.284e9, dtype=torch.float64, device=dev)
+    d = torch.zeros(n_comp, dtype=torch.int32, device=dev)
+    model = torch.empty_like(vis.model)
+    evals = n_row * n_chan * n_comp
+    peak = LANE_SLOTS_PER_S / PREDICT_SLOTS
+    out = dict(samples=n_row * n_chan, components=n_comp, comp_samples=evals, peak_comp_samples_per_s=peak)
+
+    def timed(stk, sp):
+        ms = []
+        for _ in range(reps):
+            ctx.predict(uvw, vis.chan_freq, lm, stk, sp, nu0, d, n_dir=1, dtype="c64", out=model)
+            ms.append(ctx.last_kernel_ms())
+        return float(np.mean(ms[1:]))
+
+    k_ms = timed(st, spi)
+    rate = evals / (k_ms * 1e-3)
+    out["flat_unpolarised"] = dict(kernel_ms=k_ms, comp_samples_per_s=rate, alu_frac=rate / peak,
+                                   write_gbs=32.0 * n_row * n_chan / (k_ms * 1e-3) / 1e9)
+    log(f"predict: {n_comp} components x {n_row * n_chan / 1e9:.3f}e9 samples in {k_ms:.1f} ms -> "
+        f"{rate:.3e} component-samples/s ({100 * rate / peak:.1f}% of the ALU bound)")
+    # the solve from the predicted model (the same iterations as from the generator's model)
+    term = qc.device_term(prob.chain[0], dev)
+    stt = ctx.solve(vis.copy(model=model), [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+    s_ms = ctx.last_kernel_ms()
+    it = stt["iters"].cpu().numpy()
+    out["solve_from_predicted"] = dict(kernel_ms=s_ms, mean_iterations=float(it.mean()),
+                                       converged=float(stt["converged"].float().mean().item()))
+    log(f"predict: solve from the predicted model {s_ms:.1f} ms, mean iterations {it.mean():.2f}")
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    stp = st.clone()
+    stp[:, 1:] = 0.05 * flux[:, None] * (2 * torch.rand(n_comp, 3, generator=g, device=dev, dtype=torch.float64) - 1)
+    spp = -0.7 + 0.2 * torch.rand(n_comp, generator=g, device=dev, dtype=torch.float64)
+    k2 = timed(stp, spp)
+    out["full_stokes_spectral"] = dict(kernel_ms=k2, comp_samples_per_s=evals / (k2 * 1e-3))
+    log(f"predict: full Stokes with spectral indices {k2:.1f} ms")
+    del model
+    return out
+
+
 def leg_flag(ctx, vis, resid, k: float = 5.0, reps: int = 3):
     """MAD outlier flagging of the main solve's residual (MeerKAT shape,
     1.24e9 samples), over all samples at once and per baseline."""
@@ -459,8 +520,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="flag,batch,warm,chain,params",
-                    help="comma list of extra legs: flag, batch, warm, chain, params (or none)")
+    ap.add_argument("--legs", default="flag,predict,batch,warm,chain,params",
+                    help="comma list of extra legs: flag, predict, batch, warm, chain, params (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -580,6 +641,14 @@ def main():
         except Exception as e:   # report, keep the main measurement
             out["legs"]["flag"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"flag leg failed: {e}")
+    if "predict" in legs:
+        try:
+            out["legs"]["predict"] = leg_predict(ctx, prob)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["predict"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"predict leg failed: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     if legs:
         del prob, vis, resid, chain, term0, init_gains
         torch.cuda.synchronize()

@@ -263,6 +263,40 @@ qc_status qc_mad_flag(qc_ctx* ctx, const qc_vis* vis, const void* resid, qc_mad_
                       uint8_t* flag_out, double* stats, int64_t* n_flagged, void* stream);
 
 /*
+ * Model visibilities predicted from a list of point components by a direct
+ * Fourier sum (paper Section 4.6, "Additional Features": component models
+ * predicted on the fly with the DFT; the predicted visibility M of
+ * eq. baselinemodel).  For every row r, channel nu and direction d:
+ *   M[r][nu][d] = sum over the components c with dir[c] = d of
+ *                 B_c (nu / nu0_c)^alpha_c exp(-2 pi i nu (u l + v m + w (n - 1)) / c0)
+ * with (u, v, w) = uvw[r] in metres, n = sqrt(1 - l^2 - m^2), c0 the speed of
+ * light in vacuum, and the linear-feed brightness in the order (XX, XY, YX, YY)
+ *   B = (I + Q, U + iV, U - iV, I - Q)   (no factor 1/2).
+ * A direction without components predicts zero.
+ * Components of one direction are summed in their order in the arrays.
+ */
+typedef struct {
+  int64_t n_comp;
+  const double*  lm;        /* [n_comp][2] direction cosines, l^2 + m^2 < 1        */
+  const double*  stokes;    /* [n_comp][4] I, Q, U, V in Jy at ref_freq            */
+  const double*  spi;       /* [n_comp] spectral index alpha                       */
+  const double*  ref_freq;  /* [n_comp] reference frequency nu0 > 0, Hz            */
+  const int32_t* dir;       /* [n_comp] model direction in [0, n_dir)              */
+} qc_sky;
+/* uvw [n_row][3] double, chan_freq [n_chan] double, every qc_sky array and
+ * model_out [n_row][n_chan][n_dir][4] (complex64 for QC_C64, complex128 for
+ * QC_C128, the layout of qc_vis.model) are device memory; model_out is
+ * overwritten.  QC_C128: FP64 throughout.  QC_C64: the phase in turns is
+ * formed and reduced to [-1/2, 1/2] in FP64, then the phasor, the spectral
+ * factor and the sums are FP32.  The call reads the component directions back
+ * to the host (it waits for `stream` once) to order the sums; QC_E_RANGE for a
+ * direction outside [0, n_dir), QC_E_ARG for l^2 + m^2 >= 1 or nu0 <= 0 (both
+ * found on the device, reported by this call, which then waits again).
+ * Scratch memory is owned by ctx. */
+qc_status qc_predict_dft(qc_ctx* ctx, const double* uvw, int64_t n_row, const double* chan_freq, int32_t n_chan,
+                         const qc_sky* sky, int32_t n_dir, qc_dtype dtype, void* model_out, void* stream);
+
+/*
  * Learned warm start (a two-layer MLP from interval features to initial
  * diagonal gains), all FP32 unless stated.  Parameters are one flat array
  * [W1 (n_hid x n_in) | b1 (n_hid) | W2 (n_out x n_hid) | b2 (n_out)],

@@ -301,6 +301,8 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_fl_count);
   hipFree(ctx->d_fl_rows);
   hipFree(ctx->d_fl_new);
+  hipFree(ctx->d_pc);
+  hipFree(ctx->d_pc_off);
   hipFree(ctx->d_passes);
   hipFree(ctx->d_done);
   hipFree(ctx->d_active);

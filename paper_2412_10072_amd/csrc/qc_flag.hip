@@ -606,6 +606,7 @@ qc_status qc_mad_flag(qc_ctx* ctx, const qc_vis* vis, const void* resid, qc_mad_
                                       : run_flag<double>(A, count, off, cursor, ctx->d_fl_rows, s);
   if (e != hipSuccess) return fail(ctx, QC_E_DEVICE, "MAD flagging: %s", hipGetErrorString(e));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+  ctx->timed = true;
   if (stats) {
     hipLaunchKernelGGL(k_fl_stats_out, dim3((n_groups + 255) / 256), dim3(256), 0, s,
                        reinterpret_cast<const GroupState*>(ctx->d_fl_groups), n_groups, stats);

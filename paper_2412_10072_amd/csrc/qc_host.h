@@ -55,6 +55,10 @@ struct qc_ctx {
   size_t fl_rows_cap = 0;
   unsigned long long* d_fl_new = nullptr;
   size_t fl_new_cap = 0;
+  unsigned char* d_pc = nullptr;       // prepared sky components, direction order
+  size_t pc_cap = 0;
+  int* d_pc_off = nullptr;             // [n_dir + 1] first component of each direction
+  size_t pc_off_cap = 0;
   int* d_passes = nullptr;
   size_t passes_cap = 0;
   uint8_t* d_done = nullptr;

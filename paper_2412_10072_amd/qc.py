@@ -33,7 +33,7 @@ EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "q
            "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
-           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag")
+           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft")
 MAD_MODES = {"global": 0, "baseline": 1}
 BATCH_BUCKETS = 6
 
@@ -72,6 +72,11 @@ class QcProblem(C.Structure):
     _fields_ = [("vis", QcVis), ("term", QcTerm), ("stats", QcSolveStats)]
 
 
+class QcSky(C.Structure):
+    _fields_ = [("n_comp", C.c_int64), ("lm", C.c_void_p), ("stokes", C.c_void_p), ("spi", C.c_void_p),
+                ("ref_freq", C.c_void_p), ("dir", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -105,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                 C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_mad_flag.argtypes = [C.c_void_p, C.POINTER(QcVis), C.c_void_p, C.c_int32, C.c_double, C.c_void_p,
                                 C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]
+    lib.qc_predict_dft.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.POINTER(QcSky),
+                                   C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
     lib.qc_batch_create.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(QcSolveOpts), C.POINTER(C.c_void_p)]
     lib.qc_batch_tune.argtypes = [C.c_void_p, C.c_int32]
     lib.qc_batch_run.argtypes = [C.c_void_p, C.c_void_p]
@@ -478,6 +485,32 @@ class Context:
                                          C.c_void_p(st.data_ptr()) if st is not None else None,
                                          C.byref(n_new), C.c_void_p(_stream_ptr(stream))))
         return flag_out, int(n_new.value), st
+
+    def predict(self, uvw, chan_freq, lm, stokes, spi, ref_freq, comp_dir, n_dir: int = 1, dtype: str = "c64",
+                out=None, stream=None) -> torch.Tensor:
+        """qc_predict_dft: model visibilities [n_row][n_chan][n_dir][4] from point
+        components (device tensors: uvw [n_row][3] float64, chan_freq [n_chan]
+        float64, lm [n_comp][2], stokes [n_comp][4], spi [n_comp], ref_freq
+        [n_comp] float64, comp_dir [n_comp] int32)."""
+        dev = uvw.device
+        n_row, n_chan = int(uvw.shape[0]), int(chan_freq.shape[0])
+        n_comp = int(lm.shape[0])
+        cdt = {"c64": torch.complex64, "c128": torch.complex128}[dtype]
+        if out is None:
+            out = torch.empty(n_row, n_chan, n_dir, 4, dtype=cdt, device=dev)
+        if tuple(out.shape) != (n_row, n_chan, n_dir, 4) or out.dtype != cdt:
+            raise ValueError("out must be [n_row][n_chan][n_dir][4] of the requested dtype")
+        if tuple(lm.shape) != (n_comp, 2) or tuple(stokes.shape) != (n_comp, 4) or spi.numel() != n_comp \
+                or ref_freq.numel() != n_comp or comp_dir.numel() != n_comp or tuple(uvw.shape) != (n_row, 3):
+            raise ValueError("inconsistent component or uvw shapes")
+        sky = QcSky(n_comp=n_comp, lm=_ptr(lm, torch.float64, "lm"), stokes=_ptr(stokes, torch.float64, "stokes"),
+                    spi=_ptr(spi, torch.float64, "spi"), ref_freq=_ptr(ref_freq, torch.float64, "ref_freq"),
+                    dir=_ptr(comp_dir, torch.int32, "comp_dir"))
+        self._check(self.lib.qc_predict_dft(self.h, C.c_void_p(_ptr(uvw, torch.float64, "uvw")), n_row,
+                                            C.c_void_p(_ptr(chan_freq, torch.float64, "chan_freq")), n_chan,
+                                            C.byref(sky), int(n_dir), {"c64": 0, "c128": 1}[dtype],
+                                            C.c_void_p(_ptr(out, cdt, "out")), C.c_void_p(_stream_ptr(stream))))
+        return out
 
     def apply(self, vis, chain, mode: str = "corrupt", dir_mask=None, out=None, stream=None) -> torch.Tensor:
         """qc_apply_gains: CORRUPT (model through the chain) or CORRECT (C_p^-1 D C_q^-H)."""

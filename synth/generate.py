@@ -316,7 +316,9 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
     kind "phase" / "amplitude": the truth keeps only the phases (unit amplitude) or only
     the amplitudes (zero phase) of the diagonal gains, held as the term's parameters.
     gain_mode="random": independent diagonal truth gains per interval, amp U(0.8, 1.2),
-    phase U(-pi, pi), antenna 0 phase 0 (the warm-start training and evaluation data)."""
+    phase U(-pi, pi), antenna 0 phase 0 (the warm-start training and evaluation data).
+    meta["uvw"]: [n_row][3] baseline coordinates (m) of the kept rows; meta["sky"]: per model
+    direction, the (l, m, flux) tensors of its unpolarised flat-spectrum point sources."""
     g0 = rng(device, 2412, cfg_id, 2 * seed_block)
     ant1, ant2, row_time = row_layout(n_time, n_ant)
     nbl = n_ant * (n_ant - 1) // 2
@@ -370,9 +372,11 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
     g1 = rng(device, 2412, cfg_id, 2 * seed_block + 1)
     vis = _finish_vis(model, [truth], ant1, ant2, row_time, freq, n_ant, n_time, sigma, g1,
                       flag_frac, dtype, device, block_rows=time_block * nbl, n_wcorr=n_wcorr)
+    uvw_all = uvw_tracks(enu, ant1, ant2, row_time, n_time)
     if row_drop > 0:
         keep = torch.rand(n_row, generator=g1, device=device) >= row_drop
         idx = torch.nonzero(keep).squeeze(1)
+        uvw_all = uvw_all[idx].contiguous()
         vis = Vis(data=vis.data[idx].contiguous(), model=vis.model[idx].contiguous(),
                   weight=vis.weight[idx].contiguous(), flag=vis.flag[idx].contiguous(),
                   ant1=vis.ant1[idx].contiguous(), ant2=vis.ant2[idx].contiguous(),
@@ -382,7 +386,7 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
     return Problem(vis=vis, chain=[term], truth=[truth],
                    meta=dict(name="meerkat", sigma=sigma, n_samples=n_row * n_chan,
                              n_time=n_time, n_chan=n_chan, n_ant=n_ant, kind=kind, t_int=t_int,
-                             f_int=f_int))
+                             f_int=f_int, uvw=uvw_all, sky=[(l, m, flux)]))
 
 
 def batch_shapes(n_problems: int = 256, cfg_id: int = 4, ant_range=(16, 64), time_range=(20, 200),
@@ -530,7 +534,8 @@ def config_chain(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int =
     vis = _finish_vis(model, truth, ant1, ant2, row_time, freq, n_ant, n_time, sigma, g1,
                       flag_frac, dtype, device, block_rows=time_block * nbl)
     return Problem(vis=vis, chain=[K, B, G, dE], truth=truth,
-                   meta=dict(name="chain", sigma=sigma, n_samples=n_row * n_chan, n_dir=n_dir))
+                   meta=dict(name="chain", sigma=sigma, n_samples=n_row * n_chan, n_dir=n_dir,
+                             uvw=uvw_tracks(enu, ant1, ant2, row_time, n_time), sky=list(clusters)))
 
 
 def noise_residual(n_row: int, n_chan: int, device, dtype="c64", sigma: float = 0.1, n_spikes: int = 1000,
