@@ -4,7 +4,7 @@ None of these compare the oracle with itself."""
 import numpy as np
 import pytest
 
-from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging, predict
+from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging, predict, robust
 from oracle.jones import PERM, dagger, unvec, vec
 from synth.generate import config_tiny, to_numpy_vis
 from helpers import (forward_data, make_term, make_vis, rand_c, reference_diag, unit_like)
@@ -816,3 +816,82 @@ def test_predict_matches_the_generator_sum():
     tol = 8 * np.finfo(float).eps * ph_max * st[:, 0].sum()
     assert np.abs(M[:, :, 0, 0] - G).max() <= tol
     assert np.abs(M[:, :, 0, 3] - G).max() <= tol
+
+
+# ---------------------------------------------------------------------------
+# Robust reweighting and corrected weights (Sections 4.3 and 4.4)
+# ---------------------------------------------------------------------------
+
+def _rw_vis(rng, n_wcorr=4, n_ant=8, n_time=30, n_chan=16, sigma=0.1, flag_frac=0.1):
+    vis = make_vis(rng, n_ant=n_ant, n_time=n_time, n_chan=n_chan, n_dir=1, n_wcorr=n_wcorr)
+    vis.weight = rng.uniform(0.5, 2.0, vis.weight.shape) / sigma ** 2
+    vis.flag = (rng.random(vis.flag.shape) < flag_frac).astype(np.uint8)
+    R = sigma / np.sqrt(2.0) * rand_c(rng, *vis.data.shape)
+    return vis, R
+
+
+def test_robust_weights_limits():
+    """nu -> infinity keeps the prior weights; a zero residual gets
+    w0 (nu + D) / nu."""
+    rng = np.random.default_rng(201)
+    for n_wc, D in ((4, 1), (1, 4)):
+        vis, R = _rw_vis(rng, n_wcorr=n_wc)
+        w, s2 = robust.robust_weights(vis, R, 1e12)
+        assert s2 is not None and np.allclose(w, vis.weight, rtol=1e-9)
+        R[3, 5] = 0.0
+        vis.flag[3, 5] = 0
+        w, _ = robust.robust_weights(vis, R, 2.5)
+        assert np.allclose(w[3, 5], vis.weight[3, 5] * (2.5 + D) / 2.5, rtol=1e-14)
+
+
+def test_robust_weights_scale_invariant_and_flags_untouched():
+    """A common scale of every residual leaves the weights unchanged (s2
+    normalises it); flagged samples keep w0 and their (garbage) residuals
+    do not move the others."""
+    rng = np.random.default_rng(203)
+    vis, R = _rw_vis(rng)
+    w1, _ = robust.robust_weights(vis, R, 3.0)
+    w2, _ = robust.robust_weights(vis, 7.0 * R, 3.0)
+    assert np.allclose(w1, w2, rtol=1e-12)
+    fl = vis.flag == 1
+    assert np.array_equal(w1[fl], vis.weight[fl])
+    R2 = R.copy()
+    R2[fl] = np.nan
+    w3, _ = robust.robust_weights(vis, R2, 3.0)
+    assert np.array_equal(w1, w3)
+
+
+@pytest.mark.parametrize("n_wc,D", [(4, 1), (1, 4)])
+def test_robust_weights_gaussian_mean_matches_the_integral(n_wc, D):
+    """For Gaussian residuals of variance 1 / w0, X = w0 sum |r|^2 / s2 is
+    Gamma(D, 1) (the exponential for D = 1), so the mean of w / w0 is the
+    integral of (nu + D) / (nu + x) against that density."""
+    from scipy import integrate, special
+    rng = np.random.default_rng(205 + D)
+    vis, R = _rw_vis(rng, n_wcorr=n_wc, n_ant=24, n_time=40, n_chan=64, flag_frac=0.0)
+    Wk = vis.weight if n_wc == 4 else np.repeat(vis.weight, 4, axis=-1)
+    R = rand_c(rng, *R.shape) / np.sqrt(2.0 * Wk)       # each correlation CN(0, 1 / w0)
+    nu = 3.0
+    w, _ = robust.robust_weights(vis, R, nu)
+    ratio = (w / vis.weight).ravel()
+    dens = lambda x: x ** (D - 1) * np.exp(-x) / special.gamma(D)
+    want = integrate.quad(lambda x: (nu + D) / (nu + x) * dens(x), 0, np.inf)[0]
+    se = ratio.std() / np.sqrt(ratio.size)
+    assert abs(ratio.mean() - want) <= 5 * se + 1e-3 * want
+
+
+def test_corrected_weights_keep_the_weighted_residual_power():
+    """For a diagonal chain, w' |C_p^-1 R C_q^-H|^2 = w |R|^2 sample by sample,
+    with the correction computed by the oracle's own output routine; unit
+    gains leave the weights unchanged."""
+    rng = np.random.default_rng(209)
+    vis, R = _rw_vis(rng, n_ant=6, n_time=4, n_chan=5)
+    vis.data = R
+    chain = [make_term(rng, "diag", vis.n_time, 5, 6, t_int=2, f_int=2),
+             make_term(rng, "phase", vis.n_time, 5, 6, t_int=1, f_int=5)]
+    chain = [t.copy(direction_dependent=False) for t in chain]
+    w2 = robust.corrected_weights(vis, chain)
+    Rc = outputs.correct(vis, chain)
+    assert np.allclose(w2 * np.abs(Rc) ** 2, vis.weight * np.abs(R) ** 2, rtol=1e-12)
+    unit = [make_term(rng, "diag", vis.n_time, 5, 6, scale=0.0).copy(direction_dependent=False)]
+    assert np.allclose(robust.corrected_weights(vis, unit), vis.weight, rtol=0, atol=0)
