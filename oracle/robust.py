@@ -26,15 +26,23 @@ w |c_p,i|^2 |c_q,j|^2, c the diagonal of the chain's Jones matrix (reading:
 off-diagonal terms of a full 2x2 chain are left out of the weight).  A
 single weight per sample (n_wcorr = 1) takes the mean of its four factors.
 
+Chain driver with reweighting: each epoch solves every term in turn (as the
+plain driver); after every epoch but the last, the residual of the whole
+chain gives new weights from the prior ones (never from the previous
+epoch's robust weights), used by the next epoch.
+
 parity pinned: tests/test_oracle_pins.py (nu -> infinity and zero residual
 closed forms; invariance to a common residual scale; the mean robust weight
 of Gaussian residuals against the integral of the exponential / gamma
 density; flagged samples untouched; corrected weights keep w |r|^2 under the
-oracle's own correction of a residual, unit gains leave them unchanged).
+oracle's own correction of a residual, unit gains leave them unchanged;
+the reweighted chain solve equals the plain one as nu -> infinity and gets
+closer to the truth than the plain one on data with injected RFI).
 """
 import numpy as np
 
 from .jones import chain_product
+from . import outputs, solver
 
 
 def robust_weights(vis, resid, nu):
@@ -82,3 +90,18 @@ def corrected_weights(vis, chain):
     if W.shape[-1] == 4:
         return W * f
     return W * f.mean(axis=-1, keepdims=True)
+
+
+def solve_chain_robust(vis, chain, n_epoch, nu, tol=1e-6, max_iter=100, damping="auto"):
+    """Returns (chain, stats per epoch and term, weights used by the last epoch)."""
+    w_vis = vis
+    stats = []
+    for e in range(n_epoch):
+        for n in range(len(chain)):
+            chain, st = solver.solve_term(w_vis, chain, n, tol, max_iter, damping)
+            stats.append(st)
+        if e < n_epoch - 1:
+            R = outputs.residual(vis, chain)
+            W, _ = robust_weights(vis, R, nu)
+            w_vis = vis.copy(weight=W)
+    return chain, stats, np.asarray(w_vis.weight)

@@ -895,3 +895,38 @@ def test_corrected_weights_keep_the_weighted_residual_power():
     assert np.allclose(w2 * np.abs(Rc) ** 2, vis.weight * np.abs(R) ** 2, rtol=1e-12)
     unit = [make_term(rng, "diag", vis.n_time, 5, 6, scale=0.0).copy(direction_dependent=False)]
     assert np.allclose(robust.corrected_weights(vis, unit), vis.weight, rtol=0, atol=0)
+
+
+def _rfi_problem(seed, n_ant=6, n_time=8, n_chan=12):
+    from synth.generate import config_tiny, to_numpy_vis
+    p = config_tiny(n_ant=n_ant, n_time=n_time, n_chan=n_chan, t_int=4, f_int=6, sigma=0.01)
+    vis = to_numpy_vis(p.vis)
+    rng = np.random.default_rng(seed)
+    hits = rng.choice(vis.data.shape[0] * vis.data.shape[1], 12, replace=False)
+    r, c = np.unravel_index(hits, vis.data.shape[:2])
+    D = np.array(vis.data)
+    D[r, c] += 0.5 * rand_c(rng, 12, 4)                 # RFI: 50 sigma spikes
+    return p, vis.copy(data=D)
+
+
+def test_robust_chain_equals_plain_for_large_nu():
+    p, vis = _rfi_problem(211)
+    plain, _ = solver.solve_chain(vis, p.chain, 2, tol=-1.0, max_iter=4)
+    rob, _, W = robust.solve_chain_robust(vis, p.chain, 2, 1e15, tol=-1.0, max_iter=4)
+    assert np.allclose(W, vis.weight, rtol=1e-12)
+    for a, b in zip(plain, rob):
+        assert np.allclose(a.gains, b.gains, rtol=0, atol=1e-9)
+
+
+def test_robust_chain_resists_rfi():
+    """Down-weighting the spikes brings the model closer to the truth."""
+    p, vis = _rfi_problem(213)
+    plain, _ = solver.solve_chain(vis, p.chain, 3, tol=1e-8, max_iter=50)
+    rob, _, W = robust.solve_chain_robust(vis, p.chain, 3, 2.0, tol=1e-8, max_iter=50)
+    clean = to_numpy_vis(p.vis).copy(data=outputs.corrupt(to_numpy_vis(p.vis), p.truth))
+
+    def model_err(ch):
+        return np.linalg.norm(outputs.corrupt(clean, ch) - clean.data) / np.linalg.norm(clean.data)
+    e_plain, e_rob = model_err(plain), model_err(rob)
+    assert e_rob < 0.5 * e_plain
+    assert W.min() < 0.05 * np.asarray(vis.weight).max()
