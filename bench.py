@@ -482,6 +482,32 @@ def leg_predict(ctx, prob, reps: int = 3):
     return out
 
 
+def leg_robust(ctx, vis, resid, chain, nu: float = 2.0, reps: int = 3):
+    """Robust weights from the main solve's residual and the weights of the
+    corrected data through the solved gains (MeerKAT shape, complex64).
+    Algorithmic bytes per sample: robust weights 2 x (32 residual + 16
+    weights + 1 flag) + 16 written = 114; corrected weights 16 read + 16
+    written = 32 (gains and row metadata are negligible)."""
+    import numpy as np
+    import torch
+    n = int(vis.data.shape[0]) * int(vis.data.shape[1])
+    w = torch.empty_like(vis.weight)
+    out = {}
+    for name, fn, bps in (("robust_weights", lambda: ctx.robust_weights(vis, resid, nu=nu, out=w, want_s2=False), 114),
+                          ("corrected_weights", lambda: ctx.corrected_weights(vis, chain, out=w), 32)):
+        ms = []
+        for _ in range(reps):
+            fn()
+            ms.append(ctx.last_kernel_ms())
+        k_ms = float(np.mean(ms[1:]))
+        gb = bps * n / 1e9
+        out[name] = dict(kernel_ms=k_ms, bytes_per_sample=bps, algorithmic_gb=gb, achieved_gbs=gb / (k_ms * 1e-3),
+                         hbm_frac=gb / (k_ms * 1e-3) / HBM_PEAK_GBS)
+        log(f"robust: {name} {k_ms:.1f} ms, {gb:.1f} GB -> {gb / (k_ms * 1e-3):.0f} GB/s")
+    del w
+    return out
+
+
 def leg_flag(ctx, vis, resid, k: float = 5.0, reps: int = 3):
     """MAD outlier flagging of the main solve's residual (MeerKAT shape,
     1.24e9 samples), over all samples at once and per baseline."""
@@ -520,8 +546,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="flag,predict,batch,warm,chain,params",
-                    help="comma list of extra legs: flag, predict, batch, warm, chain, params (or none)")
+    ap.add_argument("--legs", default="flag,robust,predict,batch,warm,chain,params",
+                    help="comma list of extra legs: flag, robust, predict, batch, warm, chain, params (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -641,6 +667,14 @@ def main():
         except Exception as e:   # report, keep the main measurement
             out["legs"]["flag"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"flag leg failed: {e}")
+    if "robust" in legs:
+        try:
+            out["legs"]["robust"] = leg_robust(ctx, vis, resid, chain)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["robust"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"robust leg failed: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     if "predict" in legs:
         try:
             out["legs"]["predict"] = leg_predict(ctx, prob)

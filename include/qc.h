@@ -104,10 +104,11 @@ qc_status   qc_ctx_destroy(qc_ctx* ctx);
 qc_status   qc_ctx_sync(qc_ctx* ctx);
 /* Message for the last non-OK status of ctx; valid until the next call. */
 const char* qc_last_error(const qc_ctx* ctx);
-/* Duration in milliseconds of the last solve kernel launched through ctx,
- * measured with HIP events on the launch stream around that kernel alone
- * (waits for it), or of the last qc_mad_flag's kernels (from its first
- * launch after the row checks to its last).  Negative if none. */
+/* Duration in milliseconds of the timed kernels of the last call through ctx
+ * that launched any, measured with HIP events on the launch stream (waits for
+ * them): a solve's solve kernel alone; for qc_mad_flag, qc_robust_weights,
+ * qc_predict_dft, qc_apply_gains, qc_residual and qc_corrected_weights their
+ * kernels after the argument checks.  Negative if none. */
 double      qc_last_kernel_ms(qc_ctx* ctx);
 
 /* Launch shape of the per-interval solve used by qc_solve_interval,
@@ -208,6 +209,19 @@ qc_status qc_solve_chain(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t
                          const qc_solve_opts* opts, qc_solve_stats* stats);
 
 /*
+ * Chain / epoch driver with robust reweighting between epochs (Section 4.3,
+ * solver features): as qc_solve_chain, and after every epoch but the last
+ * the residual of the whole chain is formed into resid_work ([n_row][n_chan][4],
+ * the data dtype) and the next epoch's weights into weight_work (the layout
+ * and type of vis->weight) by qc_robust_weights from the prior weights
+ * vis->weight and nu.  The work arrays are device memory owned by the caller
+ * (unused, and may be NULL, when n_epoch <= 1); vis is not modified.
+ */
+qc_status qc_solve_chain_robust(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t n_epoch,
+                                const qc_solve_opts* opts, double nu, void* resid_work, void* weight_work,
+                                qc_solve_stats* stats);
+
+/*
  * Initial delay estimate (Section 4.3, "Initial estimates"): for every
  * interval of the DELAY term k_term and every antenna a != ref_ant, per hand
  * (X: XX, Y: YY), y(nu) = sum over the interval's unflagged samples of the
@@ -239,6 +253,32 @@ qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, i
  * qc_apply_gains. */
 qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                       const uint8_t* dir_mask, void* out, void* stream);
+
+/* Weights of the corrected data C_p^-1 D C_q^-H (paper Section 4.4: corrected
+ * weights as an output): w |c_p,i|^2 |c_q,j|^2 per correlation (i, j) in the
+ * order XX, XY, YX, YY, c the diagonal of the chain's Jones matrix (the
+ * off-diagonal terms of a full 2x2 chain are left out); with one weight per
+ * sample (n_wcorr = 1) the mean of the four factors.  The chain must be
+ * direction independent (QC_E_ARG otherwise).  weight_out: device, the layout
+ * and type of vis->weight (may equal it).  Every (row, channel). */
+qc_status qc_corrected_weights(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
+                               void* weight_out, void* stream);
+
+/* Robust reweighting (paper Section 4.3, solver features: reweighting between
+ * epochs after Sob et al. 2020, against overfitting RFI and unmodelled
+ * emission), the expectation step of a complex Student's t noise model with
+ * nu > 0 degrees of freedom: a weight w0 of vis->weight shared by D complex
+ * correlations (D = 1 for n_wcorr = 4, D = 4 for n_wcorr = 1) with residuals
+ * r_k becomes
+ *   w = w0 (nu + D) / (nu + w0 sum_k |r_k|^2 / s2),
+ * s2 the mean of w0 |r|^2 over every complex residual value of the unflagged
+ * cross-correlation samples with a finite residual; other samples (and all
+ * samples if there is none) keep w0.  FP64 arithmetic, fixed-order sums.
+ * resid: device [n_row][n_chan][4] of the data dtype (qc_residual's output);
+ * weight_out: device, the layout and type of vis->weight (may equal it);
+ * s2_out: host, may be NULL (the call then does not wait), NaN if undefined. */
+qc_status qc_robust_weights(qc_ctx* ctx, const qc_vis* vis, const void* resid, double nu, void* weight_out,
+                            double* s2_out, void* stream);
 
 /* Outlier flags from residual visibilities by the median absolute deviation
  * (paper Section 4.6, "Additional Features": with a near-complete model the

@@ -301,6 +301,7 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_fl_count);
   hipFree(ctx->d_fl_rows);
   hipFree(ctx->d_fl_new);
+  hipFree(ctx->d_rw);
   hipFree(ctx->d_pc);
   hipFree(ctx->d_pc_off);
   hipFree(ctx->d_passes);
@@ -498,6 +499,34 @@ qc_status qc_solve_chain(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t
   return QC_OK;
 }
 
+qc_status qc_solve_chain_robust(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t n_epoch,
+                                const qc_solve_opts* opts, double nu, void* resid_work, void* weight_work,
+                                qc_solve_stats* stats) {
+  if (!ctx) return QC_E_ARG;
+  if (!vis || !opts) return fail(ctx, QC_E_ARG, "vis or opts is NULL");
+  if (n_epoch < 0) return fail(ctx, QC_E_ARG, "n_epoch < 0");
+  if (!(nu > 0.0) || !std::isfinite(nu)) return fail(ctx, QC_E_ARG, "nu must be finite and > 0");
+  if (n_epoch > 1 && vis->n_row > 0 && (!resid_work || !weight_work))
+    return fail(ctx, QC_E_ARG, "resid_work or weight_work is NULL");
+  qc_vis wv = *vis;                            // the weights of the current epoch
+  for (int e = 0; e < n_epoch; ++e) {
+    for (int n = 0; n < n_term; ++n) {
+      qc_solve_stats* st = stats ? &stats[(size_t)e * n_term + n] : nullptr;
+      qc_status s = qc_solve_interval(ctx, &wv, chain, n_term, n, opts, st);
+      if (s != QC_OK) return s;
+    }
+    if (e + 1 < n_epoch) {
+      // the residual of the whole chain, then weights from the prior ones
+      qc_status s = qc_residual(ctx, vis, chain, n_term, nullptr, resid_work, opts->stream);
+      if (s != QC_OK) return s;
+      s = qc_robust_weights(ctx, vis, resid_work, nu, weight_work, nullptr, opts->stream);
+      if (s != QC_OK) return s;
+      wv.weight = weight_work;
+    }
+  }
+  return QC_OK;
+}
+
 qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t ref_ant, void* stream) {
   if (!ctx) return QC_E_ARG;
   if (!k_term) return fail(ctx, QC_E_ARG, "term is NULL");
@@ -651,10 +680,11 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
   std::vector<HostMaps> maps;
   qc_status st = prepare(ctx, vis, chain, n_term, -1, maps, s);
   if (st != QC_OK) return st;
-  if (mode == 1) {
+  if (mode == 1 || mode == 3) {
     for (int j = 0; j < n_term; ++j)
       if (!dmap_constant(maps[j]))
-        return fail(ctx, QC_E_ARG, "CORRECT needs a direction-independent chain (term %d)", j);
+        return fail(ctx, QC_E_ARG, "%s needs a direction-independent chain (term %d)",
+                    mode == 1 ? "CORRECT" : "corrected weights", j);
   }
   OutputLaunch L;
   memset(&L, 0, sizeof L);
@@ -669,7 +699,10 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
     if (!dir_mask || dir_mask[d]) mask |= 1u << d;
   L.dir_mask = mask;
   L.out = out;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   HIP_TRY(ctx, launch_outputs(L, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+  ctx->timed = true;
   return QC_OK;
 }
 
@@ -682,6 +715,11 @@ qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, i
 qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                       const uint8_t* dir_mask, void* out, void* stream) {
   return outputs_common(ctx, vis, chain, n_term, 2, dir_mask, out, stream);
+}
+
+qc_status qc_corrected_weights(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
+                               void* weight_out, void* stream) {
+  return outputs_common(ctx, vis, chain, n_term, 3, nullptr, weight_out, stream);
 }
 
 }  // extern "C"

@@ -55,6 +55,8 @@ struct qc_ctx {
   size_t fl_rows_cap = 0;
   unsigned long long* d_fl_new = nullptr;
   size_t fl_new_cap = 0;
+  double* d_rw = nullptr;              // robust reweighting: partial sums, s2
+  size_t rw_cap = 0;
   unsigned char* d_pc = nullptr;       // prepared sky components, direction order
   size_t pc_cap = 0;
   int* d_pc_off = nullptr;             // [n_dir + 1] first component of each direction

@@ -315,7 +315,7 @@ struct OutputLaunch {
   VisArgs vis;
   ChainArgs chain;
   int vis_is_c128;
-  int mode;                   // 0 corrupt, 1 correct, 2 residual
+  int mode;                   // 0 corrupt, 1 correct, 2 residual, 3 corrected weights
   unsigned dir_mask;          // bit d set = direction d included
   int diag_chain;             // every chain term is diagonal or a delay
   void* out;

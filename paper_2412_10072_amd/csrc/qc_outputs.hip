@@ -5,6 +5,10 @@
 //   RESIDUAL: out = D - CORRUPT                               (eq. baselineresidual)
 //   CORRECT : out = C_p^-1 D C_q^-H  for a direction-independent chain; 0 where
 //             C_p or C_q is singular.
+//   WEIGHTS : out = w |c_p,i|^2 |c_q,j|^2 per correlation (i, j), c the diagonal
+//             of the direction-independent chain (the weights of the corrected
+//             data: its noise is scaled by 1 / (|c_p,i|^2 |c_q,j|^2) for diagonal
+//             chains); one weight per sample takes the mean of the four factors.
 //
 // Each wavefront takes one row at a time (antennas and time are uniform) and
 // its lanes consecutive channels, so every load and store is contiguous.  Arithmetic is in the data precision.
@@ -72,6 +76,21 @@ __device__ __forceinline__ void diag_part(const ChainArgs& CH, int n_ant, int t,
   }
 }
 
+// w |c_p,i|^2 |c_q,j|^2 into the weights of sample s (one weight: the mean factor)
+template <typename S, typename T>
+__device__ __forceinline__ void corrected_weight(const VisArgs& V, size_t s, cx<T> p0, cx<T> p1, cx<T> q0,
+                                                 cx<T> q1, S* out) {
+  const S* W = reinterpret_cast<const S*>(V.weight);
+  const T a0 = norm2(p0), a1 = norm2(p1), b0 = norm2(q0), b1 = norm2(q1);
+  const T f[4] = {a0 * b0, a0 * b1, a1 * b0, a1 * b1};
+  if (V.n_wcorr == 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[4 * s + k] = (S)((T)W[4 * s + k] * f[k]);
+  } else {
+    out[s] = (S)((T)W[s] * ((((f[0] + f[1]) + f[2]) + f[3]) / T(4)));
+  }
+}
+
 // DIAG: every term is diagonal or a delay, so each chain product is a pair
 // of complex numbers and the direction-independent part is formed once per
 // sample.
@@ -97,7 +116,15 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
       cx<T> p0 = cone<T>(), p1 = cone<T>(), q0 = cone<T>(), q1 = cone<T>();
       diag_part<T, false>(CH, V.n_ant, t, c, p, 0, nu, p0, p1);
       diag_part<T, false>(CH, V.n_ant, t, c, q, 0, nu, q0, q1);
-      if constexpr (MODE == 1) {
+      if constexpr (MODE == 1 || MODE == 3) {
+        // a direction-independent chain: terms with several gain directions
+        // map every direction to one, so direction 0 stands for all
+        diag_part<T, true>(CH, V.n_ant, t, c, p, 0, nu, p0, p1);
+        diag_part<T, true>(CH, V.n_ant, t, c, q, 0, nu, q0, q1);
+      }
+      if constexpr (MODE == 3) {
+        corrected_weight<S, T>(V, s, p0, p1, q0, q1, Op);
+      } else if constexpr (MODE == 1) {
         // C_p^-1 D C_q^-H, zero where C_p or C_q is singular
         const bool ok = !(p0.re == T(0) && p0.im == T(0)) && !(p1.re == T(0) && p1.im == T(0)) &&
                         !(q0.re == T(0) && q0.im == T(0)) && !(q1.re == T(0) && q1.im == T(0));
@@ -124,6 +151,10 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
         if constexpr (MODE == 2) Vm = ld<S, T>(Dp, s) - Vm;
         st<S, T>(Op, s, Vm);
       }
+    } else if constexpr (MODE == 3) {
+      const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, 0, nu);
+      const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, 0, nu);
+      corrected_weight<S, T>(V, s, Cp.a, Cp.d, Cq.a, Cq.d, Op);
     } else if constexpr (MODE == 1) {
       const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, 0, nu);
       const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, 0, nu);
@@ -157,12 +188,14 @@ hipError_t launch_s(const OutputLaunch& L, hipStream_t stream) {
     switch (L.mode) {
       case 0: hipLaunchKernelGGL((k_outputs<S, 0, true>), g, b, 0, stream, L); break;
       case 1: hipLaunchKernelGGL((k_outputs<S, 1, true>), g, b, 0, stream, L); break;
+      case 3: hipLaunchKernelGGL((k_outputs<S, 3, true>), g, b, 0, stream, L); break;
       default: hipLaunchKernelGGL((k_outputs<S, 2, true>), g, b, 0, stream, L); break;
     }
   } else {
     switch (L.mode) {
       case 0: hipLaunchKernelGGL((k_outputs<S, 0, false>), g, b, 0, stream, L); break;
       case 1: hipLaunchKernelGGL((k_outputs<S, 1, false>), g, b, 0, stream, L); break;
+      case 3: hipLaunchKernelGGL((k_outputs<S, 3, false>), g, b, 0, stream, L); break;
       default: hipLaunchKernelGGL((k_outputs<S, 2, false>), g, b, 0, stream, L); break;
     }
   }

@@ -33,7 +33,8 @@ EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "q
            "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
-           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft")
+           "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft", "qc_robust_weights",
+           "qc_corrected_weights", "qc_solve_chain_robust")
 MAD_MODES = {"global": 0, "baseline": 1}
 BATCH_BUCKETS = 6
 
@@ -110,6 +111,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                 C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_mad_flag.argtypes = [C.c_void_p, C.POINTER(QcVis), C.c_void_p, C.c_int32, C.c_double, C.c_void_p,
                                 C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]
+    lib.qc_solve_chain_robust.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
+                                          C.POINTER(QcSolveOpts), C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.qc_robust_weights.argtypes = [C.c_void_p, C.POINTER(QcVis), C.c_void_p, C.c_double, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]
+    lib.qc_corrected_weights.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_void_p,
+                                         C.c_void_p]
     lib.qc_predict_dft.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.POINTER(QcSky),
                                    C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
     lib.qc_batch_create.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(QcSolveOpts), C.POINTER(C.c_void_p)]
@@ -363,6 +370,38 @@ class Context:
                                             C.cast(cstats, C.c_void_p)))
         return stats
 
+    def solve_chain_robust(self, vis, chain, n_epoch: int = 2, nu: float = 2.0, tol: float = 1e-6,
+                           max_iter: int = 100, prec: str = "mixed", damping: str = "auto", resid_work=None,
+                           weight_work=None, stream=None):
+        """qc_solve_chain_robust: qc_solve_chain with robust reweighting between
+        epochs; returns ([epoch][term] stats, the weights of the last epoch)."""
+        dev = vis.data.device
+        stats, cstats = [], (QcSolveStats * max(1, n_epoch * len(chain)))()
+        for e in range(n_epoch):
+            row = []
+            for n, term in enumerate(chain):
+                st = _stats_for(term, dev)
+                cstats[e * len(chain) + n] = _c_stats(st)
+                row.append(st)
+            stats.append(row)
+        if resid_work is None:
+            resid_work = torch.empty_like(vis.data)
+        if weight_work is None:
+            weight_work = torch.empty_like(vis.weight)
+        if tuple(resid_work.shape) != tuple(vis.data.shape) or resid_work.dtype != vis.data.dtype \
+                or tuple(weight_work.shape) != tuple(vis.weight.shape) or weight_work.dtype != vis.weight.dtype:
+            raise ValueError("work arrays must be shaped and typed like vis.data and vis.weight")
+        cv = _c_vis(vis)
+        cc = _c_chain(chain)
+        opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
+                           damping=DAMPINGS[damping], stream=_stream_ptr(stream))
+        self._check(self.lib.qc_solve_chain_robust(self.h, C.byref(cv), cc, len(chain), int(n_epoch),
+                                                   C.byref(opts), float(nu),
+                                                   C.c_void_p(_ptr(resid_work, vis.data.dtype, "resid_work")),
+                                                   C.c_void_p(_ptr(weight_work, vis.weight.dtype, "weight_work")),
+                                                   C.cast(cstats, C.c_void_p)))
+        return stats, (weight_work if n_epoch > 1 else vis.weight)
+
     def delay_init(self, vis, term, ref_ant: int = 0, stream=None):
         """qc_delay_init: Fourier-peak delay estimate written into term.params."""
         cv = _c_vis(vis)
@@ -485,6 +524,36 @@ class Context:
                                          C.c_void_p(st.data_ptr()) if st is not None else None,
                                          C.byref(n_new), C.c_void_p(_stream_ptr(stream))))
         return flag_out, int(n_new.value), st
+
+    def robust_weights(self, vis, resid, nu: float = 2.0, out=None, want_s2: bool = True, stream=None):
+        """qc_robust_weights: Student's t weights from the residual; returns
+        (weights like vis.weight, s2 or None when not asked for)."""
+        if not isinstance(resid, torch.Tensor) or resid.dtype != vis.data.dtype or not resid.is_contiguous() \
+                or tuple(resid.shape) != tuple(vis.data.shape) or resid.device != vis.data.device:
+            raise ValueError("resid must be a contiguous tensor shaped and typed like vis.data")
+        if out is None:
+            out = torch.empty_like(vis.weight)
+        if tuple(out.shape) != tuple(vis.weight.shape) or out.dtype != vis.weight.dtype:
+            raise ValueError("out must be shaped and typed like vis.weight")
+        s2 = C.c_double(0.0)
+        cv = _c_vis(vis)
+        self._check(self.lib.qc_robust_weights(self.h, C.byref(cv), C.c_void_p(resid.data_ptr()), float(nu),
+                                               C.c_void_p(_ptr(out, vis.weight.dtype, "out")),
+                                               C.byref(s2) if want_s2 else None, C.c_void_p(_stream_ptr(stream))))
+        return out, (float(s2.value) if want_s2 else None)
+
+    def corrected_weights(self, vis, chain, out=None, stream=None) -> torch.Tensor:
+        """qc_corrected_weights: w |c_p,i|^2 |c_q,j|^2 (weights of the corrected data)."""
+        if out is None:
+            out = torch.empty_like(vis.weight)
+        if tuple(out.shape) != tuple(vis.weight.shape) or out.dtype != vis.weight.dtype:
+            raise ValueError("out must be shaped and typed like vis.weight")
+        cv = _c_vis(vis)
+        cc = _c_chain(chain)
+        self._check(self.lib.qc_corrected_weights(self.h, C.byref(cv), cc, len(chain),
+                                                  C.c_void_p(_ptr(out, vis.weight.dtype, "out")),
+                                                  C.c_void_p(_stream_ptr(stream))))
+        return out
 
     def predict(self, uvw, chan_freq, lm, stokes, spi, ref_freq, comp_dir, n_dir: int = 1, dtype: str = "c64",
                 out=None, stream=None) -> torch.Tensor:
