@@ -4,7 +4,7 @@ None of these compare the oracle with itself."""
 import numpy as np
 import pytest
 
-from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging, predict, robust
+from oracle import dense, jones, outputs, solver, warmstart, delay_init, flagging, predict, robust, interp
 from oracle.jones import PERM, dagger, unvec, vec
 from synth.generate import config_tiny, to_numpy_vis
 from helpers import (forward_data, make_term, make_vis, rand_c, reference_diag, unit_like)
@@ -930,3 +930,85 @@ def test_robust_chain_resists_rfi():
     e_plain, e_rob = model_err(plain), model_err(rob)
     assert e_rob < 0.5 * e_plain
     assert W.min() < 0.05 * np.asarray(vis.weight).max()
+
+
+# ---------------------------------------------------------------------------
+# Gain interpolation onto another grid (Section 4.4)
+# ---------------------------------------------------------------------------
+
+def _bilinear_gains(t, f, n_ant=3, n_dir=2, seed=0):
+    """Gains whose amplitude and phase are bilinear in (t, f), per entry."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-1, 1, (8, n_ant, n_dir, 4))
+    T, Fq = np.meshgrid(t, f, indexing="ij")
+    T = T[..., None, None, None]
+    Fq = Fq[..., None, None, None]
+    A = 1.0 + 0.1 * (c[0] + c[1] * T + c[2] * Fq + c[3] * T * Fq)
+    ph = 2.0 * c[4] + 0.3 * (c[5] * T + c[6] * Fq + c[7] * T * Fq)
+    return A * np.exp(1j * ph)
+
+
+def test_interp_exact_on_the_source_grid():
+    t = np.array([0.0, 8.0, 16.0, 40.0])
+    f = np.linspace(1e9, 1.5e9, 5)
+    G = _bilinear_gains(t / 40.0, (f - 1e9) / 5e8)
+    F = np.zeros(G.shape[:-1], np.int8)
+    out, of = interp.interp_gains(G, F, t, f, t, f)
+    assert np.allclose(out, G, rtol=1e-14, atol=0) and not of.any()
+
+
+def test_interp_reproduces_bilinear_amplitude_and_phase():
+    """Between grid points the bilinear amplitude and phase come back exactly
+    (a common phase rotation of every gain commutes with the interpolation)."""
+    t = np.array([0.0, 1.0, 2.5, 4.0])
+    f = np.array([0.0, 0.5, 1.0])
+    td = np.array([0.3, 1.7, 2.5, 3.9])
+    fd = np.array([0.1, 0.75, 0.99])
+    G = _bilinear_gains(t, f, seed=1)
+    want = _bilinear_gains(td, fd, seed=1)
+    F = np.zeros(G.shape[:-1], np.int8)
+    out, _ = interp.interp_gains(G, F, t, f, td, fd)
+    assert np.allclose(out, want, rtol=1e-12, atol=1e-14)
+    rot = np.exp(1j * 2.2)
+    out2, _ = interp.interp_gains(G * rot, F, t, f, td, fd)
+    assert np.allclose(out2, out * rot, rtol=1e-12, atol=1e-14)
+
+
+def test_interp_holds_end_points_and_takes_the_short_arc():
+    t = np.array([10.0, 20.0])
+    f = np.array([1e9])
+    G = np.zeros((2, 1, 1, 1, 4), complex)
+    G[0, 0, 0, 0, 0] = 2.0 * np.exp(3.0j)
+    G[1, 0, 0, 0, 0] = 2.0 * np.exp(-3.0j)
+    F = np.zeros((2, 1, 1, 1), np.int8)
+    out, _ = interp.interp_gains(G, F, t, f, [0.0, 15.0, 99.0], [0.5e9, 2e9])
+    assert np.allclose(out[0, :, 0, 0, 0], G[0, 0, 0, 0, 0])          # before the first time
+    assert np.allclose(out[2, :, 0, 0, 0], G[1, 0, 0, 0, 0])          # after the last
+    # halfway across the branch cut: the short arc passes through pi
+    assert np.allclose(out[1, :, 0, 0, 0], -2.0, atol=1e-12)
+
+
+def test_interp_flags_come_from_contributing_neighbours():
+    t = np.array([0.0, 1.0, 2.0])
+    f = np.array([0.0, 1.0])
+    G = _bilinear_gains(t, f, n_ant=2, n_dir=1, seed=3)
+    F = np.zeros(G.shape[:-1], np.int8)
+    F[1, 0, 1, 0] = 1                                   # time 1, channel point 0, antenna 1
+    out, of = interp.interp_gains(G, F, t, f, [0.5, 1.0, 2.0], [0.0, 0.5, 1.0])
+    assert of[0, 0, 1, 0] and of[0, 1, 1, 0] and not of[0, 2, 1, 0]      # f weight 0 on the flagged point at f = 1
+    assert of[1, 0, 1, 0] and not of[2, 0, 1, 0]
+    assert not of[..., 0, :].any()                       # the other antenna untouched
+    assert np.allclose(out[0, 0, 1, 0], [1, 0, 0, 1])
+
+
+def test_interp_params_linear():
+    t = np.array([0.0, 2.0, 3.0])
+    f = np.array([0.0, 1.0])
+    T, Fq = np.meshgrid(t, f, indexing="ij")
+    P = np.stack([1e-9 * (T + 2 * Fq), 0.3 * T - Fq], -1)[:, :, None, None, :]
+    F = np.zeros(P.shape[:-1], np.int8)
+    td, fd = np.array([0.5, 2.5]), np.array([0.25, 0.8])
+    out, _ = interp.interp_params(P, F, t, f, td, fd)
+    Td, Fd = np.meshgrid(td, fd, indexing="ij")
+    want = np.stack([1e-9 * (Td + 2 * Fd), 0.3 * Td - Fd], -1)[:, :, None, None, :]
+    assert np.allclose(out, want, rtol=1e-13, atol=1e-22)
