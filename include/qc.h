@@ -254,6 +254,25 @@ qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, i
 qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                       const uint8_t* dir_mask, void* out, void* stream);
 
+/* Gain solutions interpolated onto another time/frequency grid (paper
+ * Section 4.4: gains of a previous run applied up- or downsampled, and
+ * interpolated from one field to another for 1GC / transfer calibration).
+ * src and dst are terms of the same type and n_gdir over n_ant antennas;
+ * t_src [src->n_gt] and f_src [src->n_gf] (device, strictly increasing) are
+ * the times (s) and frequencies (Hz) of src's solution points, t_dst
+ * [dst->n_gt] and f_dst [dst->n_gf] (device) those wanted.  Per axis a
+ * target point between source points i and i + 1 takes u = (x - x_i) /
+ * (x_{i+1} - x_i); outside the source range the nearest end point.
+ * Bilinear: amplitudes of the gain entries linearly, their phases relative to
+ * the lower-left neighbour on the shortest arc linearly (then added to its
+ * phase); DELAY/PHASE/AMPLITUDE terms interpolate their params linearly.
+ * A target point with a flagged contributing neighbour (src->gain_flags, may
+ * be NULL) is flagged in dst->gain_flags (may be NULL) and gets the identity
+ * (zero params).  Writes dst->gains or dst->params.  FP64.  Reads the
+ * coordinates back to check them (waits for `stream` once). */
+qc_status qc_interp_term(qc_ctx* ctx, const qc_term* src, const double* t_src, const double* f_src,
+                         qc_term* dst, const double* t_dst, const double* f_dst, int32_t n_ant, void* stream);
+
 /* Weights of the corrected data C_p^-1 D C_q^-H (paper Section 4.4: corrected
  * weights as an output): w |c_p,i|^2 |c_q,j|^2 per correlation (i, j) in the
  * order XX, XY, YX, YY, c the diagonal of the chain's Jones matrix (the

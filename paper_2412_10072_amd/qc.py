@@ -34,7 +34,7 @@ EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "q
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
            "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft", "qc_robust_weights",
-           "qc_corrected_weights", "qc_solve_chain_robust")
+           "qc_corrected_weights", "qc_solve_chain_robust", "qc_interp_term")
 MAD_MODES = {"global": 0, "baseline": 1}
 BATCH_BUCKETS = 6
 
@@ -111,6 +111,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                 C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_mad_flag.argtypes = [C.c_void_p, C.POINTER(QcVis), C.c_void_p, C.c_int32, C.c_double, C.c_void_p,
                                 C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]
+    lib.qc_interp_term.argtypes = [C.c_void_p, C.POINTER(QcTerm), C.c_void_p, C.c_void_p, C.POINTER(QcTerm),
+                                   C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.qc_solve_chain_robust.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                           C.POINTER(QcSolveOpts), C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.qc_robust_weights.argtypes = [C.c_void_p, C.POINTER(QcVis), C.c_void_p, C.c_double, C.c_void_p,
@@ -524,6 +526,18 @@ class Context:
                                          C.c_void_p(st.data_ptr()) if st is not None else None,
                                          C.byref(n_new), C.c_void_p(_stream_ptr(stream))))
         return flag_out, int(n_new.value), st
+
+    def interp_term(self, src, t_src, f_src, dst, t_dst, f_dst, n_ant: int, stream=None):
+        """qc_interp_term: src's solutions onto dst's grid (dst's gains or params
+        and gain flags written); coordinates are float64 device tensors."""
+        cs = _c_chain([src])
+        cd = _c_chain([dst])
+        self._check(self.lib.qc_interp_term(self.h, cs, C.c_void_p(_ptr(t_src, torch.float64, "t_src")),
+                                            C.c_void_p(_ptr(f_src, torch.float64, "f_src")), cd,
+                                            C.c_void_p(_ptr(t_dst, torch.float64, "t_dst")),
+                                            C.c_void_p(_ptr(f_dst, torch.float64, "f_dst")), int(n_ant),
+                                            C.c_void_p(_stream_ptr(stream))))
+        return dst
 
     def robust_weights(self, vis, resid, nu: float = 2.0, out=None, want_s2: bool = True, stream=None):
         """qc_robust_weights: Student's t weights from the residual; returns
