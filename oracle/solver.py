@@ -31,6 +31,15 @@ paper is silent or inconsistent (see the design notes of the repository):
 * A block whose Cholesky pivot falls to 1e-12 of its largest diagonal entry
   (or that has no data) gets Delta = 0 and gain flag 1; flagged blocks are
   left out of the convergence norm.  The flag reflects the last update.
+* Divergence flagging of gains (Section 4.3, solver features: gains whose
+  updates do not tend to zero are flagged): per block, b_k is the size of its
+  applied step at update k: the 2-norm over its unknowns (complex gains,
+  amplitudes), the band-edge phase change 2 pi nu_max max |alpha Delta tau|
+  (delays) or max |alpha Delta phi| (phases); its run r_k = r_{k-1} + 1 when k > 1, b_k > 1e-5 and
+  b_k >= (1 - 1e-6) b_{k-1} (the step did not shrink), else 0 (also for a
+  singular block).  When the interval stops without meeting tol, a block that
+  is not singular and has r >= 3 gets gain flag 2.  The floor keeps steps at
+  rounding level from counting; the margin keeps exact 2-cycles on one side.
 
 parity pinned: see tests/test_oracle_pins.py (finite-difference and dense
 augmented-Jacobian checks, one-step exactness, StefCal closed form, damping
@@ -63,6 +72,12 @@ class Samples:
     @property
     def size(self):
         return self.rows.size
+
+
+# divergence flagging: step floor, shrink margin, run length
+DIV_FLOOR = 1e-5
+DIV_SHRINK = 1.0 - 1e-6
+DIV_RUN = 3
 
 
 def weights4(vis, rows, chans):
@@ -260,6 +275,8 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
     chisq_first = chisq_last = 0.0
     n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
     n_pass = max_iter if max_iter > 0 else 1      # max_iter = 0: evaluate chi^2 only
+    run = np.zeros((n_ant, n_gdir), dtype=np.int64)    # divergence runs per block
+    prev = np.zeros((n_ant, n_gdir))
     for k in range(1, n_pass + 1):
         JHJ, JHr, chi2 = accumulate(vis, chain, n, s)
         if k == 1:
@@ -296,10 +313,22 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
             term.gains[gt, gf] = x_new
             ratio = 0.0 if num == 0.0 else (np.sqrt(num / den) if den > 0.0 else np.inf)
         term.gain_flags[gt, gf] = flags
+        # per-block step measures and their runs of updates that did not shrink
+        if term.kind in ("delay", "phase"):
+            scale = 2.0 * np.pi * nu_max if term.kind == "delay" else 1.0
+            b = scale * np.max(np.abs(step), axis=-1)
+        else:
+            b = np.sqrt(np.sum(np.abs(step) ** 2, axis=-1))
+        grow_ = (k > 1) & (b > DIV_FLOOR) & (b >= DIV_SHRINK * prev) & ok
+        run = np.where(grow_, run + 1, 0)
+        prev = np.where(ok, b, 0.0)
         iters = k
         if ratio <= tol:
             converged = 1
             break
+    if max_iter > 0 and not converged:
+        f = term.gain_flags[gt, gf]
+        term.gain_flags[gt, gf] = np.where((f == 0) & (run >= DIV_RUN), np.int8(2), f)
     return iters, converged, chisq_first, chisq_last
 
 

@@ -304,6 +304,43 @@ def test_full_step_two_cycle_closed_form():
     assert np.max(np.abs(out2[0].gains[..., [0, 3]] - start[0].gains[..., [0, 3]])) < 1e-13
 
 
+def _two_cycle_problem(seed=4, n_ant=6, c=1.3):
+    rng = np.random.default_rng(seed)
+    vis = make_vis(rng, n_ant=n_ant, n_time=1, n_chan=3, n_dir=1, polarised=False)
+    truth = [make_term(rng, "diag", 1, 3, n_ant)]
+    vis.data = forward_data(vis, truth)
+    start = solver.copy_chain(truth)
+    start[0].gains = truth[0].gains * c
+    return vis, start
+
+
+def test_divergence_flags_the_full_step_two_cycle():
+    """A FULL step turns a global scale into a 2-cycle (closed form above):
+    the updates never shrink, the interval does not converge, every block is
+    flagged 2; the default damping converges and flags nothing."""
+    vis, start = _two_cycle_problem()
+    out, st = solver.solve_term(vis, start, 0, tol=1e-8, max_iter=10, damping="full")
+    assert st["converged"].sum() == 0
+    assert (out[0].gain_flags == 2).all()
+    out, st = solver.solve_term(vis, start, 0, tol=1e-8, max_iter=60)
+    assert st["converged"].all() and not (out[0].gain_flags == 2).any()
+
+
+def test_divergence_ignores_steps_below_the_floor():
+    """The same 2-cycle with a scale of 1 + 1e-7 never shrinks either, but its
+    steps stay below the floor (at the size of rounding in MIXED sums): no
+    block is called diverging; a fixed-iteration run long past convergence
+    flags nothing either."""
+    vis, start = _two_cycle_problem(c=1.0 + 1e-7)
+    out, st = solver.solve_term(vis, start, 0, tol=1e-14, max_iter=10, damping="full")
+    assert st["converged"].sum() == 0
+    assert not (out[0].gain_flags == 2).any()
+    vis, start = _two_cycle_problem(seed=5)
+    out, st = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=40)
+    assert st["converged"].sum() == 0
+    assert not (out[0].gain_flags == 2).any()
+
+
 def test_block_solve_cholesky_textbook():
     rng = np.random.default_rng(2)
     A = rand_c(rng, 4, 4)
