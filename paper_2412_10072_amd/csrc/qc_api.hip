@@ -304,6 +304,7 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_rw);
   hipFree(ctx->d_pc);
   hipFree(ctx->d_pc_off);
+  hipFree(ctx->d_dv);
   hipFree(ctx->d_passes);
   hipFree(ctx->d_done);
   hipFree(ctx->d_active);
@@ -424,6 +425,8 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
     HIP_TRY(ctx, grow(ctx->d_passes, ctx->passes_cap, (size_t)n_int));
     HIP_TRY(ctx, grow(ctx->d_done, ctx->done_cap, (size_t)n_int));
     HIP_TRY(ctx, grow(ctx->d_active, ctx->active_cap, 1));
+    HIP_TRY(ctx, grow(ctx->d_dv, ctx->dv_cap, (size_t)n_int * vis->n_ant * ng * 2));
+    P.state.dv = ctx->d_dv;
     P.n_part = parts;
     P.partials = ctx->d_partials;
     P.state.passes = ctx->d_passes;

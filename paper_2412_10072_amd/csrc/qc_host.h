@@ -61,6 +61,8 @@ struct qc_ctx {
   size_t pc_cap = 0;
   int* d_pc_off = nullptr;             // [n_dir + 1] first component of each direction
   size_t pc_off_cap = 0;
+  double* d_dv = nullptr;              // split schedule: divergence state per block
+  size_t dv_cap = 0;
   int* d_passes = nullptr;
   size_t passes_cap = 0;
   uint8_t* d_done = nullptr;

@@ -258,7 +258,16 @@ struct SplitState {
   int* passes;                // [n_int] passes accumulated so far
   uint8_t* done;              // [n_int]
   int* n_active;              // intervals not done
+  double* dv;                 // [n_int][n_ant * NG][2] divergence state per block
 };
+
+// divergence flagging of gains: a block's run counts consecutive updates whose
+// applied step exceeds DIV_FLOOR and did not shrink (>= DIV_SHRINK times the
+// previous); a block of an interval that stops unconverged with a run of at
+// least DIV_RUN is flagged 2
+constexpr double DIV_FLOOR = 1e-5;
+constexpr double DIV_SHRINK = 1.0 - 1e-6;
+constexpr int DIV_RUN = 3;
 
 struct SplitLaunch {
   int phase;

@@ -486,8 +486,10 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool 
   const size_t nv = KindInfo<KIND>::NV;
   // the FP64 block totals are an LDS array only in the split schedule's
   // update kernel (nw == 0); the streaming kernels sum their wave slots
-  size_t b = (nw == 0 ? sizeof(double) * n_slots * nv : 0) + sizeof(double2) * n_slots * 4 + sizeof(double) * 48 +
-             sizeof(cx<T>) * n_slots * 4 + sizeof(int) * (n_slots + 4);
+  // (the split schedule keeps the divergence state in device memory instead)
+  size_t b = (nw == 0 ? sizeof(double) * n_slots * nv : sizeof(double) * n_slots * 2) +
+             sizeof(double2) * n_slots * 4 + sizeof(double) * 48 + sizeof(cx<T>) * n_slots * 4 +
+             sizeof(int) * (n_slots + 4);
   b = (b + 15) & ~size_t(15);
   return b + sizeof(T) * n_slots * nv * nw * (sizeof(T) == 4 ? 2 : 1) +
          (lane_rows ? sizeof(unsigned) * (size_t)n_ant * nw : 0);
@@ -496,12 +498,16 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool 
 // One FP64 block solve per (antenna, gain direction) of an interval from its
 // accumulated blocks, the damped update of the LDS gains, and the
 // convergence test over the interval (uniform over the workgroup).
+// dv[2 slot], dv[2 slot + 1]: the block's run of updates whose applied step
+// did not shrink (above DIV_FLOOR) and the size of its last step; a block of
+// an interval that stops unconverged with a run >= DIV_RUN is flagged 2.
 // `sum(i)` returns the FP64 total of block value i (slot * NV + k); the
 // block values are read before the first barrier inside.
 template <int KIND, typename T, int NG, typename Sum>
-__device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<T>* gc, int* gfl, double* red,
-                                                int* ctl, int n_ant, int n_gdir, int k_upd, int damping,
-                                                double nu_max, double tol, int* err, int pk = KIND_DELAY) {
+__device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<T>* gc, int* gfl, double* dv,
+                                                double* red, int* ctl, int n_ant, int n_gdir, int k_upd,
+                                                int damping, double nu_max, double tol, int* err,
+                                                int pk = KIND_DELAY) {
   // real-parameter terms: a relative test for amplitudes, the largest phase
   // change for delays (at the band edge) and phases
   const bool rel_test = KIND != KIND_DELAY || pk == KIND_AMP;
@@ -522,6 +528,8 @@ const double alpha = step_length(damping, k_upd);
     for (int k = 0; k < NV; ++k) finite = finite && isfinite(h[k]);
     bool ok = finite;
     if (!finite) atomicOr(err, ERR_NONFINITE);
+    double bsq = 0.0;                 // squared 2-norm of the block's applied step
+    double bmax = 0.0;                // delays and phases: the largest phase change
     if constexpr (KIND == KIND_C2X2) {
       const double dmax = fmax(fmax(h[0], h[1]), fmax(h[4], h[5]));
       c64d x00 = {0, 0}, x01 = {0, 0}, x10 = {0, 0}, x11 = {0, 0};
@@ -539,6 +547,7 @@ const double alpha = step_length(damping, k_upd);
           gc[slot * 4 + k] = cmake<T>((T)xn.x, (T)xn.y);
           num += sr * sr + si * si;
           den += xn.x * xn.x + xn.y * xn.y;
+          bsq += sr * sr + si * si;
         }
       }
     } else if constexpr (KIND == KIND_DIAG) {
@@ -559,6 +568,7 @@ const double alpha = step_length(damping, k_upd);
           gc[slot * 4 + e] = cmake<T>((T)xn.x, (T)xn.y);
           num += sr * sr + si * si;
           den += xn.x * xn.x + xn.y * xn.y;
+          bsq += sr * sr + si * si;
         }
       }
     } else {
@@ -574,13 +584,23 @@ const double alpha = step_length(damping, k_upd);
         if (pk == KIND_AMP) {
           num += d0 * d0 + d1 * d1;
           den += g[0].x * g[0].x + g[0].y * g[0].y;
+          bsq = d0 * d0 + d1 * d1;
         } else {
           const double scale = pk == KIND_DELAY ? TWO_PI * nu_max : 1.0;
-          num = fmax(num, scale * fmax(fabs(d0), fabs(d1)));
+          bmax = scale * fmax(fabs(d0), fabs(d1));
+          num = fmax(num, bmax);
         }
       }
     }
     gfl[slot] = ok ? 0 : 1;
+    {
+      const bool phase_like = KIND == KIND_DELAY && pk != KIND_AMP;
+      const double b = phase_like ? bmax : sqrt(bsq);
+      double run = 0.0;
+      if (ok && k_upd > 1 && b > DIV_FLOOR && b >= DIV_SHRINK * dv[2 * slot + 1]) run = dv[2 * slot] + 1.0;
+      dv[2 * slot] = ok ? run : 0.0;
+      dv[2 * slot + 1] = ok ? b : 0.0;
+    }
   }
   // ---- convergence over the interval ----
   {
@@ -665,6 +685,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   double2* gm = reinterpret_cast<double2*>(lp);           lp += sizeof(double2) * n_slots * 4;
   double* red = reinterpret_cast<double*>(lp);            lp += sizeof(double) * 2 * 16;
   double* chiw = reinterpret_cast<double*>(lp);           lp += sizeof(double) * 16;
+  double* dv = reinterpret_cast<double*>(lp);             lp += sizeof(double) * n_slots * 2;
   cx<T>* gc = reinterpret_cast<cx<T>*>(lp);               lp += sizeof(cx<T>) * n_slots * 4;
   int* gfl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * n_slots;
   int* ctl = reinterpret_cast<int*>(lp);                  lp += sizeof(int) * 4;
@@ -1055,7 +1076,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     __syncthreads();
     if (it >= J.max_iter) break;
     const int k_upd = it + 1;
-    const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, red, ctl, n_ant, n_gdir, k_upd,
+    const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir, k_upd,
                                                    J.damping, nu_max, J.tol, J.err, pk);
     iters = k_upd;
     if (conv) {
@@ -1077,7 +1098,11 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
     }
-    if (J.gflags && J.max_iter > 0) J.gflags[dst] = (int8_t)gfl[slot];
+    if (J.gflags && J.max_iter > 0) {
+      int f = gfl[slot];
+      if (f == 0 && !converged && dv[2 * slot] >= (double)DIV_RUN) f = 2;   // updates did not tend to zero
+      J.gflags[dst] = (int8_t)f;
+    }
   }
   if (threadIdx.x == 0) {
     if (J.iters) J.iters[interval] = iters;
@@ -1161,8 +1186,10 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
     finish = true;
   } else {
     const int k_upd = pass + 1;
-    conv = update_and_test<KIND, T, NG>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, red, ctl, n_ant,
-                                        n_gdir, k_upd, J.damping, nu_max, J.tol, J.err, J.TA->kind);
+    double* dv = St.dv + (size_t)interval * n_slots * 2;
+    conv = update_and_test<KIND, T, NG>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, dv, red, ctl,
+                                        n_ant, n_gdir, k_upd, J.damping, nu_max, J.tol, J.err, J.TA->kind);
+    finish = conv || k_upd >= J.max_iter;
     for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
       const int slot = ant * NG + gd;
@@ -1174,9 +1201,12 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
 #pragma unroll
         for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
       }
-      if (J.gflags) J.gflags[dst] = (int8_t)gfl[slot];
+      if (J.gflags) {
+        int f = gfl[slot];
+        if (f == 0 && finish && !conv && dv[2 * slot] >= (double)DIV_RUN) f = 2;   // updates did not tend to zero
+        J.gflags[dst] = (int8_t)f;
+      }
     }
-    finish = conv || k_upd >= J.max_iter;
   }
   if (threadIdx.x == 0) {
     const int iters = pass >= J.max_iter ? pass : pass + 1;
