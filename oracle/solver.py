@@ -31,6 +31,18 @@ paper is silent or inconsistent (see the design notes of the repository):
 * A block whose Cholesky pivot falls to 1e-12 of its largest diagonal entry
   (or that has no data) gets Delta = 0 and gain flag 1; flagged blocks are
   left out of the convergence norm.  The flag reflects the last update.
+* Levenberg-Marquardt (damping "lm"; Section 2.1 calls the extension from
+  Gauss-Newton trivial and cites Madsen et al. 2004, whose gain-ratio
+  strategy is taken): one damping mu per interval, 1e-3 of the largest
+  diagonal entry of the interval's blocks at the first attempt; each block
+  solves (H + mu I) Delta = b (a block singular for Gauss-Newton stays
+  flagged) and the full step is applied; the predicted decrease of chi^2 is
+  sum over blocks of Re(Delta^H b) + mu |Delta|^2 (the quadratic model of the
+  block-diagonal approximation); at the next pass rho = (chi^2 before -
+  chi^2 after) / predicted: rho > 0 accepts (mu *= max(1/3, 1 - (2 rho -
+  1)^3), nu = 2), else the last accepted gains are restored, mu *= nu, nu *=
+  2 and the next pass recomputes the blocks there.  Every attempt counts as
+  an iteration; convergence is tested on the applied step as above.
 * Divergence flagging of gains (Section 4.3, solver features: gains whose
   updates do not tend to zero are flagged): per block, b_k is the size of its
   applied step at update k: the 2-norm over its unknowns (complex gains,
@@ -73,6 +85,9 @@ class Samples:
     def size(self):
         return self.rows.size
 
+
+# Levenberg-Marquardt: initial damping relative to the largest diagonal entry
+LM_TAU = 1e-3
 
 # divergence flagging: step floor, shrink margin, run length
 DIV_FLOOR = 1e-5
@@ -230,7 +245,7 @@ def resolve_damping(mode, term):
         if term.kind in ("delay", "phase"):
             return "full"
         return "half" if term.direction_dependent else "alternate"
-    if mode not in ("full", "half", "alternate"):
+    if mode not in ("full", "half", "alternate", "lm"):
         raise ValueError(f"unknown damping {mode!r}")
     return mode
 
@@ -262,11 +277,131 @@ def copy_chain(chain):
     return out
 
 
+def _step_ratio(term, step, x_new_u, ok, nu_max):
+    """The interval's convergence measure of an applied step (module notes)."""
+    if term.kind == "delay":
+        return float(np.max(2.0 * np.pi * nu_max * np.abs(step[ok]))) if np.any(ok) else 0.0
+    if term.kind == "phase":
+        return float(np.max(np.abs(step[ok]))) if np.any(ok) else 0.0
+    num = float(np.sum(np.abs(step[ok]) ** 2))
+    den = float(np.sum(np.abs(x_new_u[ok]) ** 2))
+    return 0.0 if num == 0.0 else (np.sqrt(num / den) if den > 0.0 else np.inf)
+
+
+def _block_steps(term, step, nu_max):
+    """Per-block applied step sizes for divergence flagging (module notes)."""
+    if term.kind in ("delay", "phase"):
+        scale = 2.0 * np.pi * nu_max if term.kind == "delay" else 1.0
+        return scale * np.max(np.abs(step), axis=-1)
+    return np.sqrt(np.sum(np.abs(step) ** 2, axis=-1))
+
+
+def solve_interval_lm(vis, chain, n, gt, gf, tol, max_iter):
+    """Levenberg-Marquardt for one interval (reading in the module notes):
+    every step attempt counts as an iteration; a rejected attempt restores the
+    last accepted gains and the next pass recomputes the blocks there."""
+    term = chain[n]
+    U = list(UNKNOWNS[term.kind])
+    param = term.kind in PARAM_KINDS
+    rows, chans = interval_rows_chans(vis, term, gt, gf)
+    s = samples_of(vis, rows, chans)
+    nu_max = float(np.max(np.asarray(vis.chan_freq)[chans])) if chans.size else 0.0
+    n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
+
+    def values():
+        return np.array(term.params[gt, gf] if param else term.gains[gt, gf][..., U], copy=True)
+
+    def set_values(v):
+        if param:
+            term.params[gt, gf] = v
+        else:
+            g = term.gains[gt, gf].copy()
+            g[..., U] = v
+            term.gains[gt, gf] = g
+
+    iters, converged = 0, 0
+    chisq_first = chisq_last = 0.0
+    run = np.zeros((n_ant, n_gdir), dtype=np.int64)
+    prev = np.zeros((n_ant, n_gdir))
+    mu, nu_lm, chi_acc, pred = -1.0, 2.0, 0.0, None
+    x_acc = values()
+    first = True
+    while True:
+        JHJ, JHr, chi2 = accumulate(vis, chain, n, s)
+        if first:
+            chisq_first = chi2
+            first = False
+        chisq_last = chi2
+        if max_iter <= 0:
+            break
+        if pred is not None:                       # judge the last attempt
+            rho = (chi_acc - chi2) / pred if pred > 0.0 else -1.0
+            pred = None
+            if rho > 0.0:
+                chi_acc = chi2
+                mu *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+                nu_lm = 2.0
+                x_acc = values()
+            else:
+                mu *= nu_lm
+                nu_lm *= 2.0
+                set_values(x_acc)
+                if iters >= max_iter:
+                    break
+                continue                           # the blocks again, at the restored gains
+        else:
+            chi_acc = chi2
+            x_acc = values()
+        if iters >= max_iter:
+            break
+        if mu < 0.0:                               # first attempt: 1e-3 of the largest diagonal entry
+            d = np.real(np.diagonal(JHJ, axis1=-2, axis2=-1))
+            d = d[np.isfinite(d)]
+            mu = LM_TAU * float(d.max()) if d.size else 0.0
+        delta = np.zeros_like(JHr)
+        flags = np.zeros((n_ant, n_gdir), dtype=np.int8)
+        pr = 0.0
+        eye = np.eye(JHJ.shape[-1])
+        for a in range(n_ant):
+            for dd in range(n_gdir):
+                _, sing = block_solve(JHJ[a, dd], JHr[a, dd])     # singular as in Gauss-Newton
+                if sing:
+                    flags[a, dd] = 1
+                    continue
+                x, sing2 = block_solve(JHJ[a, dd] + mu * eye, JHr[a, dd])
+                if sing2:
+                    flags[a, dd] = 1
+                    continue
+                delta[a, dd] = x
+                pr += float(np.real(np.vdot(x, JHr[a, dd]))) + mu * float(np.sum(np.abs(x) ** 2))
+        pred = pr
+        ok = flags == 0
+        step = delta
+        x_new = x_acc + step
+        set_values(x_new)
+        ratio = _step_ratio(term, step, x_new, ok, nu_max)
+        term.gain_flags[gt, gf] = flags
+        b = _block_steps(term, step, nu_max)
+        grow_ = (iters > 0) & (b > DIV_FLOOR) & (b >= DIV_SHRINK * prev) & ok
+        run = np.where(grow_, run + 1, 0)
+        prev = np.where(ok, b, 0.0)
+        iters += 1
+        if ratio <= tol:
+            converged = 1
+            break
+    if max_iter > 0 and not converged:
+        f = term.gain_flags[gt, gf]
+        term.gain_flags[gt, gf] = np.where((f == 0) & (run >= DIV_RUN), np.int8(2), f)
+    return iters, converged, chisq_first, chisq_last
+
+
 def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
     """Algorithm 1 for one interval of term n (in place on chain[n]).
     Returns (iters, converged, chisq_first, chisq_last)."""
     term = chain[n]
     mode = resolve_damping(damping, term)
+    if mode == "lm":
+        return solve_interval_lm(vis, chain, n, gt, gf, tol, max_iter)
     U = list(UNKNOWNS[term.kind])
     rows, chans = interval_rows_chans(vis, term, gt, gf)
     s = samples_of(vis, rows, chans)

@@ -341,6 +341,62 @@ def test_divergence_ignores_steps_below_the_floor():
     assert not (out[0].gain_flags == 2).any()
 
 
+def test_lm_one_step_closed_form():
+    """One perturbed antenna of a noise-free diagonal problem (its
+    Gauss-Newton step is exact): its first LM step is that step shrunk by
+    h / (h + mu) per hand, mu = 1e-3 of the largest diagonal block entry."""
+    rng = np.random.default_rng(61)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=4, n_dir=1, polarised=False)
+    truth = [make_term(rng, "diag", 2, 4, n_ant)]
+    vis.data = forward_data(vis, truth)
+    start = solver.copy_chain(truth)
+    start[0].gains[0, 0, 2, 0, 0] *= 1.2 * np.exp(0.3j)
+    start[0].gains[0, 0, 2, 0, 3] *= 0.9 * np.exp(-0.2j)
+    s_ = solver.samples_of(vis, *solver.interval_rows_chans(vis, start[0], 0, 0))
+    JHJ, _, _ = solver.accumulate(vis, start, 0, s_)
+    h = np.real(np.diagonal(JHJ, axis1=-2, axis2=-1))
+    mu = solver.LM_TAU * h.max()
+    out, _ = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=1, damping="lm")
+    for k, e in enumerate((0, 3)):
+        g0 = start[0].gains[0, 0, 2, 0, e]
+        want = g0 + (truth[0].gains[0, 0, 2, 0, e] - g0) * h[2, 0, k] / (h[2, 0, k] + mu)
+        assert abs(out[0].gains[0, 0, 2, 0, e] - want) < 1e-12
+
+
+def test_lm_converges_where_the_full_step_cycles():
+    vis, start = _two_cycle_problem()
+    out, st = solver.solve_term(vis, start, 0, tol=1e-9, max_iter=60, damping="lm")
+    assert st["converged"].all()
+    assert not (out[0].gain_flags != 0).any()
+    model = outputs.corrupt(vis, out)
+    assert np.abs(model - vis.data).max() < 1e-7 * np.abs(vis.data).max()
+
+
+def test_lm_tends_to_gauss_newton_and_rejects_uphill_steps(monkeypatch):
+    """As the initial damping goes to zero LM attempts the FULL Gauss-Newton
+    steps.  Here the first two lower chi^2 and the third raises it (FULL
+    steps excite the scale mode): two LM iterations give the two Gauss-Newton
+    steps, and a third is judged, rejected and undone."""
+    rng = np.random.default_rng(63)
+    vis = make_vis(rng, n_ant=6, n_time=2, n_chan=6, n_dir=1)
+    truth = [make_term(rng, "c2x2", 2, 6, 6, scale=0.1)]
+    vis.data = forward_data(vis, truth) + 0.01 * rand_c(rng, *vis.data.shape)
+    start = [unit_like(truth[0])]
+
+    def chisq(chain):
+        return solver.solve_term(vis, chain, 0, tol=-1.0, max_iter=0)[1]["chisq_first"].item()
+    gn = [solver.solve_term(vis, start, 0, tol=-1.0, max_iter=m, damping="full")[0] for m in (1, 2, 3)]
+    c = [chisq(start)] + [chisq(g) for g in gn]
+    assert c[1] < c[0] and c[2] < c[1] and c[3] > c[2]
+    monkeypatch.setattr(solver, "LM_TAU", 1e-15)
+    lm2, st2 = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=2, damping="lm")
+    lm3, st3 = solver.solve_term(vis, start, 0, tol=-1.0, max_iter=3, damping="lm")
+    assert np.allclose(lm2[0].gains, gn[1][0].gains, rtol=0, atol=1e-10)
+    assert np.allclose(lm3[0].gains, gn[1][0].gains, rtol=0, atol=1e-10)
+    assert st3["iters"].item() == 3 and abs(st3["chisq_last"].item() - c[3]) < 1e-9 * c[3]
+
+
 def test_block_solve_cholesky_textbook():
     rng = np.random.default_rng(2)
     A = rand_c(rng, 4, 4)
