@@ -84,12 +84,25 @@ typedef enum {
  * DELAY, PHASE and AMPLITUDE terms keep their parameters in qc_term.params;
  * their blocks are real 2x2 (one per hand, decoupled). */
 
-typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3 } qc_damping;
+typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3,
+               QC_DAMP_LM = 4 } qc_damping;
 /* Step length alpha_k of x <- x + alpha_k * Delta (the paper leaves the step
  * open, noting that Levenberg-Marquardt is a trivial extension):
  * FULL alpha = 1; HALF alpha = 1/2; ALTERNATE alpha = 1 on odd, 1/2 on even
- * updates; AUTO = FULL for delay terms, HALF for direction-dependent terms,
- * ALTERNATE otherwise.                                                       */
+ * updates; AUTO = FULL for delay and phase terms, HALF for direction-dependent
+ * terms, ALTERNATE otherwise.
+ * LM: Levenberg-Marquardt with the gain-ratio strategy of Madsen et al.
+ * (2004): one damping mu per interval (1e-3 of the largest diagonal block
+ * entry at first), every block solves (H + mu I) Delta = b and the full step
+ * is attempted; the next pass judges it by rho = (chi^2 before - after) /
+ * (sum over blocks of Re(Delta^H b) + mu |Delta|^2): rho > 0 accepts it (mu
+ * *= max(1/3, 1 - (2 rho - 1)^3)), otherwise the last accepted gains return
+ * (mu *= nu, nu doubles, starting at 2) and the blocks are formed again there.
+ * Every attempt counts as an iteration and the last one is judged (one more
+ * pass), so the result is the last accepted gains unless the interval
+ * converged.  Not with the split schedule (QC_E_UNSUPPORTED for parts > 1;
+ * the automatic schedule does not split an LM solve) nor in batched solves
+ * (QC_E_UNSUPPORTED).                                                       */
 
 typedef enum { QC_CORRUPT = 0, QC_CORRECT = 1 } qc_apply_mode;
 

@@ -342,7 +342,7 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
     return fail(ctx, QC_E_ARG, "active=%d outside the chain of %d terms", active, n_term);
   if (opts->prec != QC_PREC_FP64 && opts->prec != QC_PREC_MIXED)
     return fail(ctx, QC_E_ARG, "bad precision %d", (int)opts->prec);
-  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_AUTO)
+  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_LM)
     return fail(ctx, QC_E_ARG, "bad damping %d", (int)opts->damping);
   if (opts->max_iter < 0) return fail(ctx, QC_E_ARG, "max_iter < 0");
   if (vis && opts->prec == QC_PREC_MIXED && vis->dtype != QC_C64)
@@ -396,9 +396,11 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   const int n_int = ta.n_gt * ta.n_gf;
   const double avg_samples = n_int > 0 ? (double)vis->n_row * vis->n_chan / n_int : 0.0;
   int parts = 1;
+  const bool lm = opts->damping == QC_DAMP_LM;
   if (ctx->split_parts > 1) {
+    if (lm) return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take Levenberg-Marquardt damping");
     parts = ctx->split_parts;
-  } else if (ctx->split_parts == 0 && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
+  } else if (ctx->split_parts == 0 && !lm && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
              avg_samples >= (double)(1 << 18)) {
     const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
     parts = (int)std::ceil(4.0 * ctx->n_cu / n_int);

@@ -145,8 +145,10 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
   if (!opts) return fail(ctx, QC_E_ARG, "opts is NULL");
   if (opts->prec != QC_PREC_FP64 && opts->prec != QC_PREC_MIXED)
     return fail(ctx, QC_E_ARG, "bad precision %d", (int)opts->prec);
-  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_AUTO)
+  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_LM)
     return fail(ctx, QC_E_ARG, "bad damping %d", (int)opts->damping);
+  if (opts->damping == QC_DAMP_LM)
+    return fail(ctx, QC_E_UNSUPPORTED, "batched solves do not take Levenberg-Marquardt damping");
   if (opts->max_iter < 0) return fail(ctx, QC_E_ARG, "max_iter < 0");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(opts->stream);

@@ -261,6 +261,12 @@ struct SplitState {
   double* dv;                 // [n_int][n_ant * NG][2] divergence state per block
 };
 
+// Levenberg-Marquardt damping (the damping code after FULL, HALF, ALTERNATE):
+// one damping per interval, LM_TAU times the largest diagonal block entry at
+// the first attempt, adapted by the gain ratio of each attempt
+constexpr int DAMP_LM = 4;
+constexpr double LM_TAU = 1e-3;
+
 // divergence flagging of gains: a block's run counts consecutive updates whose
 // applied step exceeds DIV_FLOOR and did not shrink (>= DIV_SHRINK times the
 // previous); a block of an interval that stops unconverged with a run of at

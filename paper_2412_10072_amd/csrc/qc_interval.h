@@ -443,9 +443,42 @@ __device__ __forceinline__ bool chol_diag(double h, c64d b, double dmax, c64d& x
 }
 
 __device__ __forceinline__ double step_length(int damping, int k) {
-  if (damping == 0) return 1.0;
+  if (damping == 0 || damping == DAMP_LM) return 1.0;
   if (damping == 1) return 0.5;
   return (k & 1) ? 1.0 : 0.5;
+}
+
+// Levenberg-Marquardt: the largest finite diagonal entry of the interval's
+// blocks (the scale of the first damping); uses red[16 .. 16 + nw], red[31]
+template <int KIND, int NG, typename Sum>
+__device__ __forceinline__ double block_diag_max(const Sum& sum, double* red, int n_ant, int n_gdir) {
+  constexpr int NV = KindInfo<KIND>::NV;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+    const int ant = i / n_gdir, gd = i - ant * n_gdir;
+    const size_t base = (size_t)(ant * NG + gd) * NV;
+    const int nd = KIND == KIND_C2X2 ? 4 : 2;
+#pragma unroll
+    for (int k = 0; k < nd; ++k) {
+      const double d = sum(base + (KIND == KIND_C2X2 ? (k < 2 ? k : k + 2) : k));
+      if (isfinite(d)) m = fmax(m, d);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[16 + wave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t = fmax(t, red[16 + w]);
+    red[31] = t;
+  }
+  __syncthreads();
+  const double r = red[31];
+  __syncthreads();
+  return r;
 }
 
 
@@ -501,13 +534,17 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool 
 // dv[2 slot], dv[2 slot + 1]: the block's run of updates whose applied step
 // did not shrink (above DIV_FLOOR) and the size of its last step; a block of
 // an interval that stops unconverged with a run >= DIV_RUN is flagged 2.
+// mu >= 0 (Levenberg-Marquardt): a block singular for Gauss-Newton stays
+// flagged, the others solve (H + mu I) Delta = b, and *pred receives the
+// predicted chi^2 decrease sum Re(Delta^H b) + mu |Delta|^2 (uses red[16 ..]).
 // `sum(i)` returns the FP64 total of block value i (slot * NV + k); the
 // block values are read before the first barrier inside.
 template <int KIND, typename T, int NG, typename Sum>
 __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<T>* gc, int* gfl, double* dv,
                                                 double* red, int* ctl, int n_ant, int n_gdir, int k_upd,
                                                 int damping, double nu_max, double tol, int* err,
-                                                int pk = KIND_DELAY) {
+                                                int pk = KIND_DELAY, double mu = -1.0,
+                                                double* pred = nullptr) {
   // real-parameter terms: a relative test for amplitudes, the largest phase
   // change for delays (at the band edge) and phases
   const bool rel_test = KIND != KIND_DELAY || pk == KIND_AMP;
@@ -515,8 +552,9 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-const double alpha = step_length(damping, k_upd);
-  double num = 0.0, den = 0.0;
+  const double alpha = step_length(damping, k_upd);
+  const bool lm = mu >= 0.0;
+  double num = 0.0, den = 0.0, prd = 0.0;
   for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
     const int ant = i / n_gdir, gd = i - ant * n_gdir;
     const int slot = ant * NG + gd;
@@ -536,6 +574,18 @@ const double alpha = step_length(damping, k_upd);
       ok = ok && isfinite(dmax) && dmax > 0.0;
       ok = ok && chol2(h[0], h[1], h[2], h[3], {h[8], h[9]}, {h[10], h[11]}, dmax, x00, x01);
       ok = ok && chol2(h[4], h[5], h[6], h[7], {h[12], h[13]}, {h[14], h[15]}, dmax, x10, x11);
+      if (ok && lm) {
+        const double dm = dmax + mu;
+        ok = chol2(h[0] + mu, h[1] + mu, h[2], h[3], {h[8], h[9]}, {h[10], h[11]}, dm, x00, x01) &&
+             chol2(h[4] + mu, h[5] + mu, h[6], h[7], {h[12], h[13]}, {h[14], h[15]}, dm, x10, x11);
+        if (ok) {
+          const c64d bb[4] = {{h[8], h[9]}, {h[10], h[11]}, {h[12], h[13]}, {h[14], h[15]}};
+          const c64d xx[4] = {x00, x01, x10, x11};
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            prd += xx[k].re * bb[k].re + xx[k].im * bb[k].im + mu * (xx[k].re * xx[k].re + xx[k].im * xx[k].im);
+        }
+      }
       if (ok) {
         const c64d dx[4] = {x00, x01, x10, x11};
         double2* g = gm + slot * 4;
@@ -556,6 +606,13 @@ const double alpha = step_length(damping, k_upd);
       ok = ok && isfinite(dmax) && dmax > 0.0;
       ok = ok && chol_diag(h[0], {h[2], h[3]}, dmax, x0);
       ok = ok && chol_diag(h[1], {h[4], h[5]}, dmax, x1);
+      if (ok && lm) {
+        const double dm = dmax + mu;
+        ok = chol_diag(h[0] + mu, {h[2], h[3]}, dm, x0) && chol_diag(h[1] + mu, {h[4], h[5]}, dm, x1);
+        if (ok)
+          prd += x0.re * h[2] + x0.im * h[3] + x1.re * h[4] + x1.im * h[5] +
+                 mu * (x0.re * x0.re + x0.im * x0.im + x1.re * x1.re + x1.im * x1.im);
+      }
       if (ok) {
         const c64d dx[2] = {x0, x1};
         double2* g = gm + slot * 4;
@@ -575,10 +632,13 @@ const double alpha = step_length(damping, k_upd);
       const double dmax = fmax(h[0], h[1]);
       ok = ok && isfinite(dmax) && dmax > 0.0;
       ok = ok && (h[0] > PIVOT_REL * dmax) && (h[1] > PIVOT_REL * dmax);
+      const double m = lm ? mu : 0.0;
+      if (ok && lm) ok = (h[0] + m > PIVOT_REL * (dmax + m)) && (h[1] + m > PIVOT_REL * (dmax + m));
       if (ok) {
-        const double l0 = sqrt(h[0]), l1 = sqrt(h[1]);
+        const double l0 = sqrt(h[0] + m), l1 = sqrt(h[1] + m);
         const double d0 = alpha * ((h[2] / l0) / l0);
         const double d1 = alpha * ((h[3] / l1) / l1);
+        if (lm) prd += d0 * h[2] + d1 * h[3] + mu * (d0 * d0 + d1 * d1);
         double2* g = gm + slot * 4;
         g[0] = make_double2(g[0].x + d0, g[0].y + d1);
         if (pk == KIND_AMP) {
@@ -616,6 +676,10 @@ const double alpha = step_length(damping, k_upd);
       red[2 * wave + 0] = a;
       red[2 * wave + 1] = b;
     }
+    if (lm) {
+      const double pw = wave_sum<double>(prd);
+      if (lane == 0) red[16 + wave] = pw;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -629,9 +693,17 @@ const double alpha = step_length(damping, k_upd);
     if (!rel_test) ratio = a;
     else ratio = (a == 0.0) ? 0.0 : (b > 0.0 ? sqrt(a / b) : INFINITY);
     ctl[0] = (ratio <= tol) ? 1 : 0;
+    if (lm) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[16 + w];
+      red[31] = t;
+    }
   }
   __syncthreads();
-  return ctl[0] != 0;
+  if (lm && pred) *pred = red[31];
+  const bool conv = ctl[0] != 0;
+  if (lm) __syncthreads();              // red[31] is read before it is reused
+  return conv;
 }
 
 // CHM:    how the chain is evaluated per sample.
@@ -646,7 +718,9 @@ const double alpha = step_length(damping, k_upd);
 //         every lane busy).
 // PASS_ONLY: one streaming pass over rows [r_lo, r_hi) at the gains in
 //         J.gains; the FP64 blocks and chi^2 go to J.partial (split schedule).
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false>
+// LMT:    Levenberg-Marquardt damping (kernels of their own, so that the
+//         Gauss-Newton kernels carry none of its state).
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false, bool LMT = false>
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
@@ -746,6 +820,49 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 
   double chisq_first = 0.0, chisq_last = 0.0;
   int iters = 0, converged = 0, restarted = 0;
+  // Levenberg-Marquardt state, in LDS (not live in registers across the
+  // streaming pass), written by thread 0 between barriers: red[24] damping,
+  // red[25] its growth factor, red[26] chi^2 at the last accepted gains,
+  // red[27] the predicted decrease of the pending attempt, red[28] pending
+  constexpr bool LM = LMT;               // Levenberg-Marquardt kernels are instantiated apart
+  if (LM && threadIdx.x == 0) {
+    red[24] = -1.0;
+    red[25] = 2.0;
+    red[28] = 0.0;
+  }
+  // the last accepted gains live in the term's output array (each thread its
+  // own blocks, so it reads back what it wrote)
+  auto lm_store = [&]() {
+    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+      const int ant = i / n_gdir, gd = i - ant * n_gdir;
+      const int slot = ant * NG + gd;
+      const size_t dst = (gbase + ant) * n_gdir + gd;
+      if constexpr (KIND == KIND_DELAY) {
+        J.params[2 * dst + 0] = gm[slot * 4].x;
+        J.params[2 * dst + 1] = gm[slot * 4].y;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
+      }
+    }
+  };
+  auto lm_restore = [&]() {
+    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+      const int ant = i / n_gdir, gd = i - ant * n_gdir;
+      const int slot = ant * NG + gd;
+      const size_t src = (gbase + ant) * n_gdir + gd;
+      if constexpr (KIND == KIND_DELAY) {
+        gm[slot * 4] = make_double2(J.params[2 * src + 0], J.params[2 * src + 1]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 g = J.gains[4 * src + k];
+          gm[slot * 4 + k] = g;
+          gc[slot * 4 + k] = cmake<T>((T)g.x, (T)g.y);
+        }
+      }
+    }
+  };
 
   for (int it = 0;; ++it) {
     for (int i = lane; i < slot_vals; i += 64) {
@@ -1074,6 +1191,57 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     if (it == 0) chisq_first = chi_now;
     chisq_last = chi_now;
     __syncthreads();
+    if constexpr (LM) {
+      if (red[28] != 0.0) {                    // judge the last attempt by its gain ratio
+        const double rho = red[27] > 0.0 ? (red[26] - chi_now) / red[27] : -1.0;
+        __syncthreads();                       // every thread has read the state
+        if (rho > 0.0) {
+          if (threadIdx.x == 0) {
+            const double t3 = (2.0 * rho - 1.0) * (2.0 * rho - 1.0) * (2.0 * rho - 1.0);
+            red[24] *= fmax(1.0 / 3.0, 1.0 - t3);
+            red[25] = 2.0;
+            red[26] = chi_now;
+            red[28] = 0.0;
+          }
+          lm_store();
+        } else {
+          if (threadIdx.x == 0) {
+            red[24] *= red[25];
+            red[25] *= 2.0;
+            red[28] = 0.0;
+          }
+          lm_restore();
+          __syncthreads();
+          if (iters >= J.max_iter) break;
+          continue;                            // the blocks again, at the restored gains
+        }
+      } else {
+        if (threadIdx.x == 0) red[26] = chi_now;
+        lm_store();
+      }
+      __syncthreads();
+      if (iters >= J.max_iter) break;
+      if (red[24] < 0.0) {
+        const double mu0 = LM_TAU * block_diag_max<KIND, NG>(slot_sum, red, n_ant, n_gdir);
+        if (threadIdx.x == 0) red[24] = mu0;
+        __syncthreads();
+      }
+      const double mu = red[24];
+      const int k_upd = iters + 1;
+      double pred = 0.0;
+      const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir, k_upd,
+                                                     J.damping, nu_max, J.tol, J.err, pk, mu, &pred);
+      if (threadIdx.x == 0) {
+        red[27] = pred;
+        red[28] = 1.0;
+      }
+      iters = k_upd;
+      if (conv) {
+        converged = 1;
+        break;
+      }
+      continue;
+    }
     if (it >= J.max_iter) break;
     const int k_upd = it + 1;
     const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir, k_upd,

@@ -35,7 +35,7 @@
 namespace qc {
 namespace {
 
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false>
 __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
   J.chisq_ref = L.chisq_ref;
   J.restarted = L.restarted;
   J.otab = L.otab;
-  solve_interval<KIND, S, T, CHM, NG, RPS>(J);
+  solve_interval<KIND, S, T, CHM, NG, RPS, false, LMT>(J);
 }
 
 // Workgroups go to the 8 XCDs round-robin by block index.  This maps block
@@ -235,13 +235,13 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
   return hipGetLastError();
 }
 
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   const int nw = L.waves;
   const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw, RPS == 64);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS>;
+  auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS, LMT>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -263,10 +263,29 @@ inline int rows_per_step(int max_chan, int nvp) {
   return nvp <= 16 ? 4 : (nvp <= 32 ? 2 : 1);
 }
 
+// Levenberg-Marquardt solves (fused schedule only): one row per wavefront
+// step, the chain evaluated as for Gauss-Newton
+template <int KIND, typename S, typename T>
+hipError_t launch_kind_lm(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
+  const ChainArgs& ch = L.chain;
+  const TermArgs& ta = ch.t[ch.active];
+  if (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1)
+    return launch_one<KIND, S, T, CHAIN_SINGLE, 1, 1, true>(L, stream, lds_out);
+  if constexpr (KIND != KIND_C2X2) {
+    if (L.diag_chain) {
+      if (ta.n_gdir == 1) return launch_one<KIND, S, T, CHAIN_DIAG, 1, 1, true>(L, stream, lds_out);
+      return launch_one<KIND, S, T, CHAIN_DIAG, 4, 1, true>(L, stream, lds_out);
+    }
+  }
+  if (ta.n_gdir == 1) return launch_one<KIND, S, T, CHAIN_GENERAL, 1, 1, true>(L, stream, lds_out);
+  return launch_one<KIND, S, T, CHAIN_GENERAL, 4, 1, true>(L, stream, lds_out);
+}
+
 template <int KIND, typename S, typename T>
 hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
+  if (L.damping == DAMP_LM && !P) return launch_kind_lm<KIND, S, T>(L, stream, lds_out);
   const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
 #define QC_LAUNCH(CHM_, NG_, RPS_)                                                          \
   return P ? launch_split_one<KIND, S, T, CHM_, NG_, RPS_>(L, *P, stream, lds_out)        \

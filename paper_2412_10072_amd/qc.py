@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "QC_OK", -1: "QC_E_ARG", -2: "QC_E_RANGE", -3: "QC_E_NONFINIT
                 -5: "QC_E_NOMEM", -6: "QC_E_UNSUPPORTED"}
 TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2, "phase": 3, "amplitude": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3}
+DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3, "lm": 4}
 
 EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms", "qc_ctx_set_tile",
            "qc_ctx_set_split", "qc_ctx_last_split",
