@@ -13,6 +13,7 @@ For each interval of the delay term and each antenna a != ref, per hand c
 The grid is tau_k = k / (N dnu), k = -N/2 .. N/2-1, with dnu the mean channel
 spacing of the interval and N the smallest power of two >= 8 x the number of
 channels (zero padding of at least 8x).  The reference antenna gets tau = 0.
+A delay-and-offset term gets the same delays and zero phase offsets.
 
 parity pinned: tests/test_oracle_pins.py (noise-free recovery of random delays
 to within half a grid step).
@@ -45,8 +46,9 @@ def delay_init(vis, chain, n, ref_ant=0):
     from .solver import copy_chain
     chain = copy_chain(chain)
     term = chain[n]
-    if term.kind != "delay":
+    if term.kind not in ("delay", "delay_offset"):
         raise ValueError("delay_init needs a delay term")
+    offset = term.kind == "delay_offset"        # params (phi0_X, tau_X, phi0_Y, tau_Y)
     data = np.asarray(vis.data).astype(np.complex128)
     model = np.asarray(vis.model).astype(np.complex128).sum(axis=2)
     weight = np.asarray(vis.weight).astype(np.float64)
@@ -76,5 +78,10 @@ def delay_init(vis, chain, n, ref_ant=0):
                         use = flag[r, chans] == 0
                         y += np.where(use, weight[r, chans, corr] * z, 0.0)
                     A = delay_spectrum(y, freqs, taus)
-                    term.params[gt, gf, a, :, hand] = taus[int(np.argmax(A))]
+                    tau = taus[int(np.argmax(A))]
+                    if offset:
+                        term.params[gt, gf, a, :, 2 * hand] = 0.0
+                        term.params[gt, gf, a, :, 2 * hand + 1] = tau
+                    else:
+                        term.params[gt, gf, a, :, hand] = tau
     return chain

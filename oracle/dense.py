@@ -30,7 +30,10 @@ def _residual_vector(vis, chain, s):
 
 def unknown_index(vis, term):
     """Ordered list of unknowns (antenna, gdir, entry) of one interval."""
-    U = UNKNOWNS[term.kind] if term.kind not in ("delay", "phase", "amplitude") else (0, 1)
+    if term.kind == "delay_offset":
+        U = (0, 1, 2, 3)
+    else:
+        U = UNKNOWNS[term.kind] if term.kind not in ("delay", "phase", "amplitude") else (0, 1)
     return [(a, g, u) for a in range(vis.n_ant) for g in range(int(term.n_gdir)) for u in U]
 
 
@@ -71,8 +74,9 @@ def dense_complex(vis, chain, n, gt, gf, h=1e-6):
 
 
 def dense_delay(vis, chain, n, gt, gf, h=1e-15):
-    """Real-parameter Jacobian J_o = d r_aug / d tau by central differences;
-    returns (J_o^H W J_o, J_o^H W r_aug, idx)."""
+    """Real-parameter Jacobian J_o = d r_aug / d u by central differences;
+    returns (J_o^H W J_o, J_o^H W r_aug, idx).  h: one step, or one per
+    parameter slot u (for parameters of different scale)."""
     chain = copy_chain(chain)
     term = chain[n]
     rows, chans = interval_rows_chans(vis, term, gt, gf)
@@ -82,13 +86,14 @@ def dense_delay(vis, chain, n, gt, gf, h=1e-15):
     base = term.params.copy()
     J = np.zeros((2 * r0.size, len(idx)), dtype=np.complex128)
     for j, (a, g, u) in enumerate(idx):
+        hu = h[u] if np.ndim(h) else h
         term.params = base.copy()
-        term.params[gt, gf, a, g, u] += h
+        term.params[gt, gf, a, g, u] += hu
         rp = _residual_vector(vis, chain, s)
         term.params = base.copy()
-        term.params[gt, gf, a, g, u] -= h
+        term.params[gt, gf, a, g, u] -= hu
         rm = _residual_vector(vis, chain, s)
-        d = (rp - rm) / (2 * h)
+        d = (rp - rm) / (2 * hu)
         J[:, j] = np.concatenate([d, np.conj(d)])
     term.params = base
     w = s.w.ravel()

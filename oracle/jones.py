@@ -42,14 +42,21 @@ def term_jones(term, vis, rows, chans, ants, d):
     maps.  Diagonal terms use only entries XX and YY; a delay term is
     diag(exp(2 pi i nu tau_X), exp(2 pi i nu tau_Y)) at the channel frequency nu;
     a phase-only term diag(exp(i phi_X), exp(i phi_Y)); an amplitude-only term
-    diag(a_X, a_Y) with real a (paper Section 2.4, Scenario 1)."""
+    diag(a_X, a_Y) with real a (paper Section 2.4, Scenario 1); a delay and
+    offset term diag(exp(i (phi0_X + 2 pi nu tau_X)), exp(i (phi0_Y + 2 pi nu
+    tau_Y)))."""
     t = np.asarray(vis.row_time)[rows]
     gt = np.asarray(term.t_map)[t]
     gf = np.asarray(term.f_map)[chans]
     gd = int(np.asarray(term.d_map)[d])
     S = rows.size
     J = np.zeros((S, 2, 2), dtype=np.complex128)
-    if term.kind == "delay":
+    if term.kind == "delay_offset":
+        u = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]        # [S][4]
+        nu = np.asarray(vis.chan_freq, dtype=np.float64)[chans]
+        J[:, 0, 0] = np.exp(1j * (u[:, 0] + 2.0 * np.pi * nu * u[:, 1]))
+        J[:, 1, 1] = np.exp(1j * (u[:, 2] + 2.0 * np.pi * nu * u[:, 3]))
+    elif term.kind == "delay":
         tau = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]      # [S][2]
         nu = np.asarray(vis.chan_freq, dtype=np.float64)[chans]
         J[:, 0, 0] = np.exp(2j * np.pi * nu * tau[:, 0])

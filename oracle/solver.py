@@ -22,6 +22,16 @@ paper is silent or inconsistent (see the design notes of the repository):
   leaves the model unchanged, so no scale mode is excited), and otherwise
   alternate for direction-independent terms and half for direction-dependent
   ones.
+* Delay and phase offset ("delay_offset", the paper's K in its experiments:
+  residual delays and phase offsets; Scenario 2): per hand two parameters,
+  g = exp(i (phi0 + 2 pi nu tau)), params (phi0_X, tau_X, phi0_Y, tau_Y); the
+  block per hand is the real 2 x 2 of the columns i g and 2 pi i nu g (the hands
+  decouple); convergence and divergence measure the largest band-edge phase
+  change |alpha Delta phi0| + 2 pi nu_max |alpha Delta tau|; AUTO damping FULL.
+  The diagonal entries differ by (2 pi nu)^2 between phi0 and tau, so the
+  pivot test compares each pivot with its own diagonal entry (the test of the
+  Jacobi-scaled block); Levenberg-Marquardt, one damping for both, is not
+  offered for this term.
 * Convergence (Algorithm 1's "||Delta g|| > eps"): per interval, the 2-norm
   of the applied step over the unknown entries of unflagged blocks divided by
   the 2-norm of the updated gains (amplitude-only: of the amplitudes); for
@@ -64,9 +74,15 @@ import numpy as np
 
 from .jones import PERM_IDX, vec, unvec, dagger, term_jones, chain_product
 
-UNKNOWNS = {"diag": (0, 3), "c2x2": (0, 1, 2, 3), "delay": (0, 3), "phase": (0, 3), "amplitude": (0, 3)}
-# real-parameterised diagonal terms: params [..][2] per (antenna, gain direction)
-PARAM_KINDS = ("delay", "phase", "amplitude")
+UNKNOWNS = {"diag": (0, 3), "c2x2": (0, 1, 2, 3), "delay": (0, 3), "phase": (0, 3), "amplitude": (0, 3),
+            "delay_offset": (0, 3)}
+# real-parameterised diagonal terms: params [..][2] per (antenna, gain direction),
+# [..][4] = (phi0_X, tau_X, phi0_Y, tau_Y) for delay_offset
+PARAM_KINDS = ("delay", "phase", "amplitude", "delay_offset")
+
+
+def n_params(kind):
+    return 4 if kind == "delay_offset" else 2
 PIVOT_REL = 1e-12
 
 
@@ -175,8 +191,9 @@ def accumulate(vis, chain, n, s_fwd: Samples):
     n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
     nu_ = len(U)
     if term.kind in PARAM_KINDS:
-        JHJ = np.zeros((n_ant, n_gdir, 2, 2), dtype=np.float64)
-        JHr = np.zeros((n_ant, n_gdir, 2), dtype=np.float64)
+        npar = n_params(term.kind)
+        JHJ = np.zeros((n_ant, n_gdir, npar, npar), dtype=np.float64)
+        JHr = np.zeros((n_ant, n_gdir, npar), dtype=np.float64)
     else:
         JHJ = np.zeros((n_ant, n_gdir, nu_, nu_), dtype=np.complex128)
         JHr = np.zeros((n_ant, n_gdir, nu_), dtype=np.complex128)
@@ -192,6 +209,19 @@ def accumulate(vis, chain, n, s_fwd: Samples):
         if term.kind in PARAM_KINDS:
             # E = (dv/dg) (dg/du) for the real parameter u of each hand
             gdiag = np.stack([Gn[..., 0, 0], Gn[..., 1, 1]], axis=-1)   # [S][gd][2]
+            if term.kind == "delay_offset":
+                # per hand: d g / d phi0 = i g, d g / d tau = 2 pi i nu g
+                nu = np.asarray(vis.chan_freq, dtype=np.float64)[s.chans][:, None]
+                cols = [Ku[..., 0] * (1j * gdiag[..., 0])[:, :, None],
+                        Ku[..., 0] * (2j * np.pi * nu * gdiag[..., 0])[:, :, None],
+                        Ku[..., 1] * (1j * gdiag[..., 1])[:, :, None],
+                        Ku[..., 1] * (2j * np.pi * nu * gdiag[..., 1])[:, :, None]]
+                E = np.stack(cols, axis=-1)                              # [S][gd][4 corr][4 params]
+                H = np.real(np.einsum("sdxu,sx,sdxv->sduv", np.conj(E), s.w, E))
+                b = np.real(np.einsum("sdxu,sx->sdu", np.conj(E), s.w * R))
+                np.add.at(JHJ, s.p, H)
+                np.add.at(JHr, s.p, b)
+                continue
             if term.kind == "delay":
                 nu = np.asarray(vis.chan_freq, dtype=np.float64)[s.chans]
                 dg = 2j * np.pi * nu[:, None, None] * gdiag             # d g / d tau
@@ -214,10 +244,12 @@ def accumulate(vis, chain, n, s_fwd: Samples):
 # per-block solve (Cholesky, FP64) and damping
 # ----------------------------------------------------------------------------
 
-def block_solve(H, b, rel=PIVOT_REL):
+def block_solve(H, b, rel=PIVOT_REL, scaled=False):
     """Solve H x = b for a small Hermitian positive-definite block by Cholesky
     H = L L^H.  Returns (x, singular): singular when the block is empty or a
-    pivot is <= rel * max diagonal (then x = 0)."""
+    pivot is <= rel * max diagonal (then x = 0).  scaled: each pivot is
+    compared with its own diagonal entry instead (the test of the Jacobi-scaled
+    block, for unknowns of very different scale)."""
     n = b.shape[0]
     diag = np.real(np.diag(H))
     dmax = float(np.max(diag)) if n else 0.0
@@ -226,7 +258,8 @@ def block_solve(H, b, rel=PIVOT_REL):
     L = np.zeros((n, n), dtype=H.dtype)
     for j in range(n):
         s = np.real(H[j, j]) - np.sum(np.abs(L[j, :j]) ** 2)
-        if not (s > rel * dmax):
+        ref = diag[j] if scaled else dmax
+        if not (s > rel * ref):
             return np.zeros_like(b), True
         L[j, j] = np.sqrt(s)
         for i in range(j + 1, n):
@@ -242,7 +275,7 @@ def block_solve(H, b, rel=PIVOT_REL):
 
 def resolve_damping(mode, term):
     if mode == "auto":
-        if term.kind in ("delay", "phase"):
+        if term.kind in ("delay", "phase", "delay_offset"):
             return "full"
         return "half" if term.direction_dependent else "alternate"
     if mode not in ("full", "half", "alternate", "lm"):
@@ -277,8 +310,16 @@ def copy_chain(chain):
     return out
 
 
+def _offset_delay_change(step, nu_max):
+    """Per block: the largest over hands of |alpha Delta phi0| + 2 pi nu_max |alpha Delta tau|."""
+    return np.maximum(np.abs(step[..., 0]) + 2.0 * np.pi * nu_max * np.abs(step[..., 1]),
+                      np.abs(step[..., 2]) + 2.0 * np.pi * nu_max * np.abs(step[..., 3]))
+
+
 def _step_ratio(term, step, x_new_u, ok, nu_max):
     """The interval's convergence measure of an applied step (module notes)."""
+    if term.kind == "delay_offset":
+        return float(np.max(_offset_delay_change(step, nu_max)[ok])) if np.any(ok) else 0.0
     if term.kind == "delay":
         return float(np.max(2.0 * np.pi * nu_max * np.abs(step[ok]))) if np.any(ok) else 0.0
     if term.kind == "phase":
@@ -290,6 +331,8 @@ def _step_ratio(term, step, x_new_u, ok, nu_max):
 
 def _block_steps(term, step, nu_max):
     """Per-block applied step sizes for divergence flagging (module notes)."""
+    if term.kind == "delay_offset":
+        return _offset_delay_change(step, nu_max)
     if term.kind in ("delay", "phase"):
         scale = 2.0 * np.pi * nu_max if term.kind == "delay" else 1.0
         return scale * np.max(np.abs(step), axis=-1)
@@ -401,6 +444,9 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
     term = chain[n]
     mode = resolve_damping(damping, term)
     if mode == "lm":
+        if term.kind == "delay_offset":
+            raise ValueError("Levenberg-Marquardt takes no delay-and-offset term (one damping for unknowns "
+                             "of very different scale)")
         return solve_interval_lm(vis, chain, n, gt, gf, tol, max_iter)
     U = list(UNKNOWNS[term.kind])
     rows, chans = interval_rows_chans(vis, term, gt, gf)
@@ -421,9 +467,10 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
             break
         delta = np.zeros_like(JHr)
         flags = np.zeros((n_ant, n_gdir), dtype=np.int8)
+        scaled = term.kind == "delay_offset"
         for a in range(n_ant):
             for dd in range(n_gdir):
-                x, sing = block_solve(JHJ[a, dd], JHr[a, dd])
+                x, sing = block_solve(JHJ[a, dd], JHr[a, dd], scaled=scaled)
                 delta[a, dd] = x
                 flags[a, dd] = 1 if sing else 0
         alpha = step_length(mode, k)
@@ -432,28 +479,15 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
         if term.kind in PARAM_KINDS:
             u_new = term.params[gt, gf] + step
             term.params[gt, gf] = u_new
-            if term.kind == "delay":      # band-edge phase change
-                ratio = float(np.max(2.0 * np.pi * nu_max * np.abs(step[ok]))) if np.any(ok) else 0.0
-            elif term.kind == "phase":    # phase change in radians
-                ratio = float(np.max(np.abs(step[ok]))) if np.any(ok) else 0.0
-            else:                         # relative change of the amplitudes
-                num = float(np.sum(step[ok] ** 2))
-                den = float(np.sum(u_new[ok] ** 2))
-                ratio = 0.0 if num == 0.0 else (np.sqrt(num / den) if den > 0.0 else np.inf)
+            ratio = _step_ratio(term, step, u_new, ok, nu_max)
         else:
             x_new = term.gains[gt, gf].copy()
             x_new[..., U] = x_new[..., U] + step
-            num = float(np.sum(np.abs(step[ok]) ** 2))
-            den = float(np.sum(np.abs(x_new[..., U][ok]) ** 2))
             term.gains[gt, gf] = x_new
-            ratio = 0.0 if num == 0.0 else (np.sqrt(num / den) if den > 0.0 else np.inf)
+            ratio = _step_ratio(term, step, x_new[..., U], ok, nu_max)
         term.gain_flags[gt, gf] = flags
         # per-block step measures and their runs of updates that did not shrink
-        if term.kind in ("delay", "phase"):
-            scale = 2.0 * np.pi * nu_max if term.kind == "delay" else 1.0
-            b = scale * np.max(np.abs(step), axis=-1)
-        else:
-            b = np.sqrt(np.sum(np.abs(step) ** 2, axis=-1))
+        b = _block_steps(term, step, nu_max)
         grow_ = (k > 1) & (b > DIV_FLOOR) & (b >= DIV_SHRINK * prev) & ok
         run = np.where(grow_, run + 1, 0)
         prev = np.where(ok, b, 0.0)

@@ -152,6 +152,13 @@ def truth_jones(term: Term, t_idx: torch.Tensor, ants: torch.Tensor, freq: torch
         z = torch.polar(torch.ones_like(ph), ph)
         J[..., 0, 0] = z[..., 0]
         J[..., 1, 1] = z[..., 1]
+    elif term.kind == "delay_offset":
+        par = _as_t(term.params, dev, torch.float64)
+        u = par[gt[:, None], fm[None, :], ants.long()[:, None], gd]            # [R][C][4]
+        ph = u[..., [0, 2]] + 2.0 * math.pi * freq[None, :, None] * u[..., [1, 3]]
+        z = torch.polar(torch.ones_like(ph), ph)
+        J[..., 0, 0] = z[..., 0]
+        J[..., 1, 1] = z[..., 1]
     elif term.kind in ("phase", "amplitude"):
         par = _as_t(term.params, dev, torch.float64)
         u = par[gt[:, None], fm[None, :], ants.long()[:, None], gd]            # [R][C][2]
@@ -231,6 +238,8 @@ def make_term(kind: str, n_time: int, n_chan: int, n_ant: int, t_int: int, f_int
     params = None
     if kind in ("delay", "phase"):
         params = np.zeros(shape + (2,), dtype=np.float64)
+    elif kind == "delay_offset":
+        params = np.zeros(shape + (4,), dtype=np.float64)
     elif kind == "amplitude":
         params = np.ones(shape + (2,), dtype=np.float64)
     return Term(kind=kind, t_map=t_map, f_map=f_map, d_map=d_map, n_gt=n_gt, n_gf=n_gf,

@@ -23,7 +23,9 @@ A chain term (paper eq. joneschain) carries its own solution-interval maps
   gains      [n_gt][n_gf][n_ant][n_gdir][4]  complex128  (diag / c2x2 terms)
   params     [n_gt][n_gf][n_ant][n_gdir][2]  float64     (delay: tau_X, tau_Y in s;
                                                         phase: phi_X, phi_Y in rad;
-                                                        amplitude: a_X, a_Y)
+                                                        amplitude: a_X, a_Y;
+                                                        delay_offset: [4] phi0_X,
+                                                        tau_X, phi0_Y, tau_Y)
   gain_flags [n_gt][n_gf][n_ant][n_gdir]     int8
 """
 from __future__ import annotations
@@ -31,8 +33,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field, replace
 from typing import Any, Optional
 
-TERM_KINDS = ("diag", "c2x2", "delay", "phase", "amplitude")
-PARAM_KINDS = ("delay", "phase", "amplitude")
+TERM_KINDS = ("diag", "c2x2", "delay", "phase", "amplitude", "delay_offset")
+PARAM_KINDS = ("delay", "phase", "amplitude", "delay_offset")
 
 
 @dataclass

@@ -15,6 +15,9 @@ def jones_of(term, t, c, a, d, freq):
     if term.kind == "delay":
         tau = term.params[gt, gf, a, gd]
         return np.diag(np.exp(2j * np.pi * freq[c] * tau))
+    if term.kind == "delay_offset":
+        u = term.params[gt, gf, a, gd]
+        return np.diag(np.exp(1j * (u[[0, 2]] + 2 * np.pi * freq[c] * u[[1, 3]])))
     if term.kind == "phase":
         return np.diag(np.exp(1j * term.params[gt, gf, a, gd]))
     if term.kind == "amplitude":
@@ -79,6 +82,10 @@ def make_term(rng, kind, n_time, n_chan, n_ant, t_int=None, f_int=None, n_dir=1,
     params = None
     if kind == "delay":
         params = rng.uniform(-1e-9, 1e-9, shape + (2,))
+    elif kind == "delay_offset":
+        params = np.zeros(shape + (4,))
+        params[..., [0, 2]] = rng.uniform(-np.pi, np.pi, shape + (2,)) * scale
+        params[..., [1, 3]] = rng.uniform(-1e-9, 1e-9, shape + (2,))
     elif kind == "phase":
         params = rng.uniform(-np.pi, np.pi, shape + (2,)) * scale
     elif kind == "amplitude":

@@ -162,6 +162,56 @@ def test_scenario1_blocks_equal_dense_2re_form(kind):
         assert np.max(np.abs(D_JHr[sel] + 2 * JHr[a, 0])) < 1e-7 * scale
 
 
+def test_delay_offset_blocks_equal_dense_2re_form():
+    """Delay-and-offset blocks (per hand the real 2 x 2 of phi0 and tau, the
+    common factor 2 left out) against the real-parameter Jacobian by central
+    differences, steps scaled per parameter (radians, seconds)."""
+    rng = np.random.default_rng(9)
+    n_ant = 4
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=5, n_dir=1, freq0=1.0e9, dfreq=50e6)
+    chain = [make_term(rng, "delay_offset", 2, 5, n_ant), make_term(rng, "diag", 2, 5, n_ant)]
+    vis.data = forward_data(vis, chain) + 0.2 * rand_c(rng, *vis.data.shape)
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(5))
+    JHJ, JHr, _ = solver.accumulate(vis, chain, 0, s)
+    ht = 1e-6 / (2 * np.pi * 1.2e9)
+    D_JHJ, D_JHr, idx = dense.dense_delay(vis, chain, 0, 0, 0, h=(1e-6, ht, 1e-6, ht))
+    for a in range(n_ant):
+        sel = [j for j, (aa, _, _) in enumerate(idx) if aa == a]
+        D = D_JHJ[np.ix_(sel, sel)]
+        sc = np.sqrt(np.outer(np.diag(np.abs(D)), np.diag(np.abs(D))))   # per-entry scale
+        assert np.max(np.abs(D - 2 * JHJ[a, 0]) / sc) < 1e-6
+        rs = np.sqrt(np.diag(np.abs(D))) * np.sqrt(np.abs(np.real(np.sum(s.w))))
+        assert np.max(np.abs(D_JHr[sel] + 2 * JHr[a, 0]) / rs) < 1e-6
+    # the hands decouple: no X-Y entries
+    assert np.max(np.abs(JHJ[:, :, :2, 2:])) == 0.0
+
+
+def test_delay_offset_recovery_and_reduction_to_delay():
+    """Noise-free recovery of offsets and delays (referenced to antenna 0, the
+    gauge the data leave free); with zero offsets the Jones equal the delay
+    term's."""
+    rng = np.random.default_rng(59)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=16, n_dir=1, polarised=False, freq0=1.0e9, dfreq=8e6)
+    truth = [make_term(rng, "delay_offset", 2, 16, n_ant, t_int=1, f_int=16, scale=0.1)]
+    truth[0].params[:, :, 0] = 0.0
+    vis.data = forward_data(vis, truth)
+    out, st = solver.solve_term(vis, [unit_like(truth[0])], 0, tol=1e-12, max_iter=200)
+    assert st["converged"].all()
+    got = out[0].params - out[0].params[:, :, :1]
+    d_phi = np.angle(np.exp(1j * (got[..., [0, 2]] - truth[0].params[..., [0, 2]])))
+    assert np.max(np.abs(d_phi)) < 1e-9
+    assert np.max(np.abs(got[..., [1, 3]] - truth[0].params[..., [1, 3]])) < 1e-18
+    dl = truth[0].copy(kind="delay", params=np.ascontiguousarray(truth[0].params[..., [1, 3]]))
+    do = truth[0].copy(params=truth[0].params.copy())
+    do.params[..., [0, 2]] = 0.0
+    rows = np.arange(vis.data.shape[0])
+    for c in range(16):
+        chans = np.full(rows.size, c)
+        assert np.allclose(jones.term_jones(do, vis, rows, chans, vis.ant1, 0),
+                           jones.term_jones(dl, vis, rows, chans, vis.ant1, 0), rtol=0, atol=1e-15)
+
+
 def test_recovery_phase_only():
     rng = np.random.default_rng(41)
     n_ant = 6
