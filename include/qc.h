@@ -68,7 +68,8 @@ typedef enum { QC_PREC_FP64 = 0, QC_PREC_MIXED = 1 } qc_prec;
  *                block solve, update and convergence test.  Needs QC_C64.   */
 
 typedef enum {
-  QC_TERM_DIAGONAL = 0, QC_TERM_COMPLEX2X2 = 1, QC_TERM_DELAY = 2, QC_TERM_PHASE = 3, QC_TERM_AMPLITUDE = 4
+  QC_TERM_DIAGONAL = 0, QC_TERM_COMPLEX2X2 = 1, QC_TERM_DELAY = 2, QC_TERM_PHASE = 3, QC_TERM_AMPLITUDE = 4,
+  QC_TERM_DELAY_OFFSET = 5
 } qc_term_type;
 /* DIAGONAL  : unknowns XX, YY of the gain (XY = YX = 0).
  * COMPLEX2X2: all four entries.
@@ -81,7 +82,15 @@ typedef enum {
  *             first parameterisation scenario, eq. jhj_case1 / jhwr_case1).
  * AMPLITUDE : real parameters a_X, a_Y, Jones matrix diag(a_X, a_Y)
  *             (amplitude-only gain, same scenario).
- * DELAY, PHASE and AMPLITUDE terms keep their parameters in qc_term.params;
+ * DELAY_OFFSET: real parameters phi0 (radians) and tau (seconds) per hand,
+ *             Jones matrix diag(exp(i (phi0_X + 2 pi nu tau_X)),
+ *             exp(i (phi0_Y + 2 pi nu tau_Y))) (residual delays with phase
+ *             offsets, the K term of the paper's experiments); per hand a real
+ *             2x2 block whose pivots are tested against their own diagonal
+ *             entries (the two unknowns differ in scale by (2 pi nu)^2).  Not
+ *             with QC_DAMP_LM.
+ * DELAY, PHASE, AMPLITUDE and DELAY_OFFSET terms keep their parameters in
+ * qc_term.params;
  * their blocks are real 2x2 (one per hand, decoupled). */
 
 typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3,
@@ -166,7 +175,8 @@ typedef struct {
   const int32_t* d_map;     /* [n_dir]  -> [0, n_gdir)                        */
   void*   gains;            /* [n_gt][n_gf][n_ant][n_gdir][4] complex128, in/out (DIAGONAL, COMPLEX2X2) */
   double* params;           /* [n_gt][n_gf][n_ant][n_gdir][2] in/out: tau_X, tau_Y in s (DELAY),
-                               phi_X, phi_Y in rad (PHASE), a_X, a_Y (AMPLITUDE) */
+                               phi_X, phi_Y in rad (PHASE), a_X, a_Y (AMPLITUDE);
+                               [..][4] phi0_X, tau_X, phi0_Y, tau_Y (DELAY_OFFSET) */
   int8_t* gain_flags;       /* [n_gt][n_gf][n_ant][n_gdir] out (may be NULL for fixed terms) */
 } qc_term;
 

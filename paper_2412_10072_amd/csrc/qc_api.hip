@@ -78,14 +78,14 @@ qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
 }
 
 qc_status check_term(qc_ctx* ctx, const qc_vis* v, const qc_term* t, int j, HostMaps& hm, hipStream_t s) {
-  if (t->type < QC_TERM_DIAGONAL || t->type > QC_TERM_AMPLITUDE)
+  if (t->type < QC_TERM_DIAGONAL || t->type > QC_TERM_DELAY_OFFSET)
     return fail(ctx, QC_E_ARG, "term %d: bad type %d", j, (int)t->type);
   if (t->n_gt <= 0 || t->n_gf <= 0 || t->n_gdir <= 0)
     return fail(ctx, QC_E_ARG, "term %d: bad gain shape (%d, %d, %d)", j, t->n_gt, t->n_gf, t->n_gdir);
   if (t->n_gdir > QC_MAX_GDIR)
     return fail(ctx, QC_E_UNSUPPORTED, "term %d: n_gdir=%d exceeds %d", j, t->n_gdir, QC_MAX_GDIR);
   if (!t->t_map || !t->f_map || !t->d_map) return fail(ctx, QC_E_ARG, "term %d: a map pointer is NULL", j);
-  const bool real_params = t->type >= QC_TERM_DELAY;   // delay, phase, amplitude
+  const bool real_params = t->type >= QC_TERM_DELAY;   // delay, phase, amplitude, delay and offset
   if (real_params ? !t->params : !t->gains)
     return fail(ctx, QC_E_ARG, "term %d: %s is NULL", j, real_params ? "params" : "gains");
   hm.t_map.resize(v->n_time);
@@ -244,7 +244,7 @@ int resolve_damping(qc_damping d, const qc_term& t) {
   if (d == QC_DAMP_AUTO) {
     // full steps for delay and phase-only terms: a common phase or delay
     // leaves the model unchanged, so there is no scale mode to overshoot
-    if (t.type == QC_TERM_DELAY || t.type == QC_TERM_PHASE) return 0;
+    if (t.type == QC_TERM_DELAY || t.type == QC_TERM_PHASE || t.type == QC_TERM_DELAY_OFFSET) return 0;
     return t.direction_dependent ? 1 : 2;
   }
   return (int)d;
@@ -397,6 +397,8 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   const double avg_samples = n_int > 0 ? (double)vis->n_row * vis->n_chan / n_int : 0.0;
   int parts = 1;
   const bool lm = opts->damping == QC_DAMP_LM;
+  if (lm && ta.type == QC_TERM_DELAY_OFFSET)
+    return fail(ctx, QC_E_UNSUPPORTED, "Levenberg-Marquardt takes no delay-and-offset term");
   if (ctx->split_parts > 1) {
     if (lm) return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take Levenberg-Marquardt damping");
     parts = ctx->split_parts;
@@ -420,7 +422,8 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   if (want_tab) HIP_TRY(ctx, grow(ctx->d_otab, ctx->otab_cap, chain_table_bytes(L)));
   SplitLaunch P;
   if (parts > 1) {
-    const int nv = ta.type == QC_TERM_DIAGONAL ? 6 : (ta.type == QC_TERM_COMPLEX2X2 ? 16 : 4);
+    const int nv = ta.type == QC_TERM_DIAGONAL ? 6
+                 : ta.type == QC_TERM_COMPLEX2X2 ? 16 : (ta.type == QC_TERM_DELAY_OFFSET ? 10 : 4);
     const int ng = ta.n_gdir == 1 ? 1 : 4;
     const size_t stride = (size_t)vis->n_ant * ng * nv + 1;
     HIP_TRY(ctx, grow(ctx->d_partials, ctx->partials_cap, stride * (size_t)n_int * parts));
@@ -535,7 +538,8 @@ qc_status qc_solve_chain_robust(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, 
 qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t ref_ant, void* stream) {
   if (!ctx) return QC_E_ARG;
   if (!k_term) return fail(ctx, QC_E_ARG, "term is NULL");
-  if (k_term->type != QC_TERM_DELAY) return fail(ctx, QC_E_ARG, "qc_delay_init needs a DELAY term");
+  if (k_term->type != QC_TERM_DELAY && k_term->type != QC_TERM_DELAY_OFFSET)
+    return fail(ctx, QC_E_ARG, "qc_delay_init needs a DELAY or DELAY_OFFSET term");
   if (!vis) return fail(ctx, QC_E_ARG, "vis is NULL");
   if (ref_ant < 0 || ref_ant >= vis->n_ant) return fail(ctx, QC_E_ARG, "ref_ant=%d outside [0,%d)", ref_ant, vis->n_ant);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -548,6 +552,7 @@ qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t
   ChainArgs ca;
   fill_args(vis, k_term, 1, 0, L.vis, ca);
   L.vis_is_c128 = vis->dtype == QC_C128;
+  L.offset = k_term->type == QC_TERM_DELAY_OFFSET ? 1 : 0;
   L.n_gt = k_term->n_gt;
   L.n_gf = k_term->n_gf;
   L.n_gdir = k_term->n_gdir;

@@ -49,8 +49,9 @@ __global__ void __launch_bounds__(DI_THREADS) k_delay_init(DelayInitLaunch L) {
   const int n_ch = c_hi - c_lo;
   const size_t pbase = ((size_t)gt * n_gf + gf) * n_ant + a;
 
+  const int np = L.offset ? 4 : 2;      // parameters per gain direction
   if (a == L.ref_ant || n_ch <= 0) {   // reference antenna (or no channels): tau = 0
-    if (threadIdx.x < 2 * L.n_gdir) L.params[2 * (pbase * L.n_gdir) + threadIdx.x] = 0.0;
+    if (threadIdx.x < np * L.n_gdir) L.params[np * (pbase * L.n_gdir) + threadIdx.x] = 0.0;
     return;
   }
 
@@ -153,7 +154,14 @@ __global__ void __launch_bounds__(DI_THREADS) k_delay_init(DelayInitLaunch L) {
   if (threadIdx.x < L.n_gdir) {
     for (int h = 0; h < 2; ++h) {
       const int k = red_k[h * DI_THREADS];
-      L.params[2 * (pbase * L.n_gdir + threadIdx.x) + h] = (double)(k - npad / 2) / (npad * dnu);
+      const double tau = (double)(k - npad / 2) / (npad * dnu);
+      const size_t blk = pbase * L.n_gdir + threadIdx.x;
+      if (L.offset) {                  // delays with zero phase offsets
+        L.params[4 * blk + 2 * h] = 0.0;
+        L.params[4 * blk + 2 * h + 1] = tau;
+      } else {
+        L.params[2 * blk + h] = tau;
+      }
     }
   }
 }

@@ -16,7 +16,7 @@ namespace qc {
 // argument blocks (passed to kernels by value)
 // ---------------------------------------------------------------------------
 
-enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 4 };
+enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 4, KIND_DELOFF = 5 };
 // KIND_DELAY as a kernel template argument stands for every real-parameterised
 // diagonal term (delay, phase-only, amplitude-only); the term's own kind
 // (TermArgs::kind) selects the Jones form at run time.
@@ -152,6 +152,8 @@ template <typename T> __device__ __forceinline__ m22<T> rowscale(cx<T> a0, cx<T>
 
 // exp(2 pi i nu tau) with the turn count removed in FP64 so that an FP32
 // sine/cosine sees an argument in [-pi, pi] (nu * tau reaches ~10 turns).
+constexpr double INV_TWO_PI = 0.15915494309189533576888376337251;   // 1 / (2 pi)
+
 template <typename T>
 __device__ __forceinline__ cx<T> phasor_turns(double turns) {
   double fr = turns - rint(turns);
@@ -182,7 +184,12 @@ __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int 
   const int gd = tm.d_map[d];
   const size_t blk = (((size_t)gt * tm.n_gf + gf) * n_ant + x) * tm.n_gdir + gd;
   m22<T> J = mzero<T>();
-  if (tm.kind >= KIND_DELAY) {
+  if (tm.kind == KIND_DELOFF) {
+    // exp(i (phi0 + 2 pi nu tau)) per hand, params (phi0_X, tau_X, phi0_Y, tau_Y)
+    const double* u = tm.params + 4 * blk;
+    J.a = phasor_turns<T>(u[0] * INV_TWO_PI + nu * u[1]);
+    J.d = phasor_turns<T>(u[2] * INV_TWO_PI + nu * u[3]);
+  } else if (tm.kind >= KIND_DELAY) {
     J.a = param_gain<T>(tm.kind, nu, tm.params[2 * blk + 0]);
     J.d = param_gain<T>(tm.kind, nu, tm.params[2 * blk + 1]);
   } else {
@@ -293,7 +300,8 @@ struct DelayInitLaunch {
   const long long* row_hi;
   const int* chan_lo;         // [n_gf]
   const int* chan_hi;
-  double* params;             // [n_gt][n_gf][n_ant][n_gdir][2]
+  double* params;             // [n_gt][n_gf][n_ant][n_gdir][2], or [4] with offsets
+  int offset;                 // delay-and-offset term: (phi0, tau) per hand, phi0 set to 0
 };
 
 size_t delay_init_lds(int max_chan);

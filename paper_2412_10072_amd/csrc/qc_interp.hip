@@ -24,7 +24,7 @@ namespace {
 
 struct InterpArgs {
   const double2* g_src;     // [n_gt][n_gf][n_ant][n_gdir][4] (complex terms)
-  const double* p_src;      // [n_gt][n_gf][n_ant][n_gdir][2] (parameterised terms)
+  const double* p_src;      // [n_gt][n_gf][n_ant][n_gdir][2 or 4] (parameterised terms)
   const int8_t* f_src;      // flags [n_gt][n_gf][n_ant][n_gdir] or null
   const double* t_src;
   const double* nu_src;
@@ -36,7 +36,7 @@ struct InterpArgs {
   const double* nu_dst;
   int nt_d, nf_d;
   int n_ant, n_gdir;
-  int params;               // 1: interpolate parameters, 0: complex gains
+  int params;               // parameters per block to interpolate (2 or 4), 0: complex gains
 };
 
 // bracket of x among increasing xs[0..n): x = (1 - u) xs[i0] + u xs[i1]
@@ -83,15 +83,16 @@ __global__ void k_interp(InterpArgs A) {
     for (int c = 0; c < 4; ++c) bad = bad || (w[c] != 0.0 && A.f_src[src(c)] != 0);
   }
   if (A.params) {
-    double acc0 = 0.0, acc1 = 0.0;
+    const int np = A.params;
+    for (int k = 0; k < np; ++k) {
+      double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (w[c] == 0.0) continue;
-      acc0 += w[c] * A.p_src[2 * src(c)];
-      acc1 += w[c] * A.p_src[2 * src(c) + 1];
+      for (int c = 0; c < 4; ++c) {
+        if (w[c] == 0.0) continue;
+        acc += w[c] * A.p_src[np * src(c) + k];
+      }
+      A.p_dst[np * i + k] = bad ? 0.0 : acc;
     }
-    A.p_dst[2 * i] = bad ? 0.0 : acc0;
-    A.p_dst[2 * i + 1] = bad ? 0.0 : acc1;
   } else {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -138,7 +139,8 @@ qc_status qc_interp_term(qc_ctx* ctx, const qc_term* src, const double* t_src, c
   if (src->n_gdir != dst->n_gdir) return fail(ctx, QC_E_ARG, "source and target terms differ in gain directions");
   if (n_ant <= 0 || src->n_gdir <= 0 || src->n_gt <= 0 || src->n_gf <= 0 || dst->n_gt <= 0 || dst->n_gf <= 0)
     return fail(ctx, QC_E_ARG, "bad sizes");
-  const bool params = src->type == QC_TERM_DELAY || src->type == QC_TERM_PHASE || src->type == QC_TERM_AMPLITUDE;
+  const bool params = src->type == QC_TERM_DELAY || src->type == QC_TERM_PHASE || src->type == QC_TERM_AMPLITUDE ||
+                      src->type == QC_TERM_DELAY_OFFSET;
   if (params ? (!src->params || !dst->params) : (!src->gains || !dst->gains))
     return fail(ctx, QC_E_ARG, "the term's %s array is NULL", params ? "params" : "gains");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -173,7 +175,7 @@ qc_status qc_interp_term(qc_ctx* ctx, const qc_term* src, const double* t_src, c
   A.nf_d = dst->n_gf;
   A.n_ant = n_ant;
   A.n_gdir = src->n_gdir;
-  A.params = params ? 1 : 0;
+  A.params = params ? (src->type == QC_TERM_DELAY_OFFSET ? 4 : 2) : 0;
   const long long n = (long long)dst->n_gt * dst->n_gf * n_ant * dst->n_gdir;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   hipLaunchKernelGGL(k_interp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A);

@@ -16,6 +16,37 @@ template <int KIND> struct KindInfo;
 template <> struct KindInfo<KIND_DIAG>  { static constexpr int NV = 6;  };
 template <> struct KindInfo<KIND_C2X2>  { static constexpr int NV = 16; };
 template <> struct KindInfo<KIND_DELAY> { static constexpr int NV = 4;  };
+// delay and offset: per hand the three entries of the real 2x2 block of
+// (phi0, tau) and its two right-hand sides
+template <> struct KindInfo<KIND_DELOFF> { static constexpr int NV = 10; };
+
+// kinds whose unknowns are real parameters held in the term's params array
+__host__ __device__ constexpr bool is_param(int kind) { return kind == KIND_DELAY || kind == KIND_DELOFF; }
+
+// A parameterised block's parameters in LDS: g[0] = (u_X, u_Y) for delay,
+// phase and amplitude terms (2 per block in params); g[0] = (phi0_X, tau_X),
+// g[1] = (phi0_Y, tau_Y) for delay-and-offset terms (4 per block).
+template <int KIND>
+__device__ __forceinline__ void params_load(const double* P, size_t blk, double2* g) {
+  if constexpr (KIND == KIND_DELOFF) {
+    g[0] = make_double2(P[4 * blk + 0], P[4 * blk + 1]);
+    g[1] = make_double2(P[4 * blk + 2], P[4 * blk + 3]);
+  } else {
+    g[0] = make_double2(P[2 * blk + 0], P[2 * blk + 1]);
+  }
+}
+template <int KIND>
+__device__ __forceinline__ void params_store(double* P, size_t blk, const double2* g) {
+  if constexpr (KIND == KIND_DELOFF) {
+    P[4 * blk + 0] = g[0].x;
+    P[4 * blk + 1] = g[0].y;
+    P[4 * blk + 2] = g[1].x;
+    P[4 * blk + 3] = g[1].y;
+  } else {
+    P[2 * blk + 0] = g[0].x;
+    P[2 * blk + 1] = g[0].y;
+  }
+}
 
 constexpr int pow2ceil(int n) { return n <= 1 ? 1 : 2 * pow2ceil((n + 1) / 2); }
 
@@ -315,6 +346,21 @@ __device__ __forceinline__ void contrib(cx<T> a0, cx<T> a1, const m22<T>& B, con
       acc[1] = fma(s1, h1, acc[1]);
       acc[2] += j0.re; acc[3] += j0.im;
       acc[4] += j1.re; acc[5] += j1.im;
+    } else if constexpr (KIND == KIND_DELOFF) {
+      // delay and offset: per hand the columns i g (phi0) and i tpn g (tau,
+      // tpn = 2 pi nu): H = base [[1, tpn], [tpn, tpn^2]], b = Im(conj(g) j) [1, tpn]
+      const T b0 = norm2(g0) * (s0 * h0), b1 = norm2(g1) * (s1 * h1);
+      const T q0 = cmulc(g0, j0).im, q1 = cmulc(g1, j1).im;
+      acc[0] += b0;
+      acc[1] = fma(tpn, b0, acc[1]);
+      acc[2] = fma(tpn * tpn, b0, acc[2]);
+      acc[3] += q0;
+      acc[4] = fma(tpn, q0, acc[4]);
+      acc[5] += b1;
+      acc[6] = fma(tpn, b1, acc[6]);
+      acc[7] = fma(tpn * tpn, b1, acc[7]);
+      acc[8] += q1;
+      acc[9] = fma(tpn, q1, acc[9]);
     } else if (amp) {
       // amplitude-only (dg/da = 1): h_i = |alpha_i|^2 sum_b w_ib |B_ib|^2, b_i = Re(j_i)
       acc[0] = fma(s0, h0, acc[0]);
@@ -448,6 +494,18 @@ __device__ __forceinline__ double step_length(int damping, int k) {
   return (k & 1) ? 1.0 : 0.5;
 }
 
+// The diagonal gains (XX, YY) of a parameterised block at frequency nu.
+template <int KIND, typename T>
+__device__ __forceinline__ void param_diag(const double2* g, int pk, double nu, cx<T>& a, cx<T>& d) {
+  if constexpr (KIND == KIND_DELOFF) {
+    a = phasor_turns<T>(g[0].x * INV_TWO_PI + nu * g[0].y);
+    d = phasor_turns<T>(g[1].x * INV_TWO_PI + nu * g[1].y);
+  } else {
+    a = param_gain<T>(pk, nu, g[0].x);
+    d = param_gain<T>(pk, nu, g[0].y);
+  }
+}
+
 // Levenberg-Marquardt: the largest finite diagonal entry of the interval's
 // blocks (the scale of the first damping); uses red[16 .. 16 + nw], red[31]
 template <int KIND, int NG, typename Sum>
@@ -547,7 +605,7 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
                                                 double* pred = nullptr) {
   // real-parameter terms: a relative test for amplitudes, the largest phase
   // change for delays (at the band edge) and phases
-  const bool rel_test = KIND != KIND_DELAY || pk == KIND_AMP;
+  const bool rel_test = !is_param(KIND) || pk == KIND_AMP;
   constexpr int NV = KindInfo<KIND>::NV;
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -628,6 +686,37 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
           bsq += sr * sr + si * si;
         }
       }
+    } else if constexpr (KIND == KIND_DELOFF) {
+      // per hand the real 2x2 of (phi0, tau); the two unknowns differ in scale
+      // by (2 pi nu)^2, so each pivot is tested against its own diagonal entry
+      const double dmax = fmax(fmax(h[0], h[2]), fmax(h[5], h[7]));
+      ok = ok && isfinite(dmax) && dmax > 0.0;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int hd = 0; hd < 2; ++hd) {
+        const double* e = h + 5 * hd;             // a = H00, b = H01, c = H11, r0, r1
+        const bool p0 = e[0] > PIVOT_REL * e[0] && e[0] > 0.0;
+        const double l00 = p0 ? sqrt(e[0]) : 1.0;
+        const double l10 = e[1] / l00;
+        const double piv = e[2] - l10 * l10;
+        const bool p1 = piv > PIVOT_REL * e[2];
+        ok = ok && p0 && p1;
+        const double l11 = p1 ? sqrt(piv) : 1.0;
+        const double y0 = e[3] / l00;
+        const double y1 = (e[4] - l10 * y0) / l11;
+        const double x1 = y1 / l11;
+        const double x0 = (y0 - l10 * x1) / l00;
+        d[2 * hd + 0] = alpha * x0;
+        d[2 * hd + 1] = alpha * x1;
+      }
+      if (ok) {
+        double2* g = gm + slot * 4;
+        g[0] = make_double2(g[0].x + d[0], g[0].y + d[1]);
+        g[1] = make_double2(g[1].x + d[2], g[1].y + d[3]);
+        const double scale = TWO_PI * nu_max;
+        bmax = fmax(fabs(d[0]) + scale * fabs(d[1]), fabs(d[2]) + scale * fabs(d[3]));
+        num = fmax(num, bmax);
+      }
     } else {
       const double dmax = fmax(h[0], h[1]);
       ok = ok && isfinite(dmax) && dmax > 0.0;
@@ -654,7 +743,7 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
     }
     gfl[slot] = ok ? 0 : 1;
     {
-      const bool phase_like = KIND == KIND_DELAY && pk != KIND_AMP;
+      const bool phase_like = is_param(KIND) && pk != KIND_AMP;
       const double b = phase_like ? bmax : sqrt(bsq);
       double run = 0.0;
       if (ok && k_upd > 1 && b > DIV_FLOOR && b >= DIV_SHRINK * dv[2 * slot + 1]) run = dv[2 * slot] + 1.0;
@@ -785,8 +874,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     const int ant = i / n_gdir, gd = i - ant * n_gdir;
     const int slot = ant * NG + gd;
     const size_t src = (gbase + ant) * n_gdir + gd;
-    if constexpr (KIND == KIND_DELAY) {
-      gm[slot * 4 + 0] = make_double2(J.params[2 * src + 0], J.params[2 * src + 1]);
+    if constexpr (is_param(KIND)) {
+      params_load<KIND>(J.params, src, gm + slot * 4);
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -798,7 +887,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     gfl[slot] = 0;
   }
   double nu_max = 0.0;
-  if constexpr (KIND == KIND_DELAY) {
+  if constexpr (is_param(KIND)) {
     if (threadIdx.x == 0) {
       double m = 0.0;
       for (int c = c_lo; c < c_hi; ++c) m = fmax(m, V.freq[c]);
@@ -806,7 +895,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     }
   }
   __syncthreads();
-  if constexpr (KIND == KIND_DELAY) nu_max = red[0];
+  if constexpr (is_param(KIND)) nu_max = red[0];
 
   // ---- rows of this wave ----
   const long long n_rows = r_hi - r_lo;
@@ -837,9 +926,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
       const int slot = ant * NG + gd;
       const size_t dst = (gbase + ant) * n_gdir + gd;
-      if constexpr (KIND == KIND_DELAY) {
-        J.params[2 * dst + 0] = gm[slot * 4].x;
-        J.params[2 * dst + 1] = gm[slot * 4].y;
+      if constexpr (is_param(KIND)) {
+        params_store<KIND>(J.params, dst, gm + slot * 4);
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
@@ -851,8 +939,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
       const int slot = ant * NG + gd;
       const size_t src = (gbase + ant) * n_gdir + gd;
-      if constexpr (KIND == KIND_DELAY) {
-        gm[slot * 4] = make_double2(J.params[2 * src + 0], J.params[2 * src + 1]);
+      if constexpr (is_param(KIND)) {
+        params_load<KIND>(J.params, src, gm + slot * 4);
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -925,17 +1013,20 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
         const m22<T> Draw = load_m22<S, T>(Dp, s);
         const bool use = inb & row_ok & (fl == 0);
         const double nu = V.freq[cc];
-        const T tpn = (T)(pk == KIND_DELAY ? TWO_PI * nu : 1.0);   // d(phase)/d(parameter)
+        // d(phase)/d(parameter): 2 pi nu for delays (the tau column of
+        // delay-and-offset terms), 1 for phases
+        const T tpn = (T)((pk == KIND_DELAY || KIND == KIND_DELOFF) ? TWO_PI * nu : 1.0);
         w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
         const m22<T> D = select_m(use, Draw);
 
         if constexpr (SINGLE) {
           // chain = the active term alone: C_p = G_p, C_q = G_q
           m22<T> Gp, Gq;
-          if constexpr (KIND == KIND_DELAY) {
-            const double2 tp = gm[p * 4], tq = gm[q * 4];
-            Gp = {param_gain<T>(pk, nu, tp.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tp.y)};
-            Gq = {param_gain<T>(pk, nu, tq.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tq.y)};
+          if constexpr (is_param(KIND)) {
+            Gp = mzero<T>();
+            Gq = mzero<T>();
+            param_diag<KIND, T>(gm + p * 4, pk, nu, Gp.a, Gp.d);
+            param_diag<KIND, T>(gm + q * 4, pk, nu, Gq.a, Gq.d);
           } else {
             Gp = {gc[p * 4 + 0], gc[p * 4 + 1], gc[p * 4 + 2], gc[p * 4 + 3]};
             Gq = {gc[q * 4 + 0], gc[q * 4 + 1], gc[q * 4 + 2], gc[q * 4 + 3]};
@@ -991,12 +1082,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           }
           // active gains of p and q for gain direction gd
           auto active_diag = [&](int gd, cx<T>& a0, cx<T>& a1, cx<T>& b0, cx<T>& b1) {
-            if constexpr (KIND == KIND_DELAY) {
-              const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
-              a0 = param_gain<T>(pk, nu, tp.x);
-              a1 = param_gain<T>(pk, nu, tp.y);
-              b0 = param_gain<T>(pk, nu, tq.x);
-              b1 = param_gain<T>(pk, nu, tq.y);
+            if constexpr (is_param(KIND)) {
+              param_diag<KIND, T>(gm + (p * NG + gd) * 4, pk, nu, a0, a1);
+              param_diag<KIND, T>(gm + (q * NG + gd) * 4, pk, nu, b0, b1);
             } else {
               const cx<T>* gpp = gc + (p * NG + gd) * 4;
               const cx<T>* gqq = gc + (q * NG + gd) * 4;
@@ -1080,10 +1168,11 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           }
           // active gains of p and q for gain direction gd
           auto active_jones = [&](int gd, m22<T>& Gp, m22<T>& Gq) {
-            if constexpr (KIND == KIND_DELAY) {
-              const double2 tp = gm[(p * NG + gd) * 4], tq = gm[(q * NG + gd) * 4];
-              Gp = {param_gain<T>(pk, nu, tp.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tp.y)};
-              Gq = {param_gain<T>(pk, nu, tq.x), czero<T>(), czero<T>(), param_gain<T>(pk, nu, tq.y)};
+            if constexpr (is_param(KIND)) {
+              Gp = mzero<T>();
+              Gq = mzero<T>();
+              param_diag<KIND, T>(gm + (p * NG + gd) * 4, pk, nu, Gp.a, Gp.d);
+              param_diag<KIND, T>(gm + (q * NG + gd) * 4, pk, nu, Gq.a, Gq.d);
             } else {
               const cx<T>* gpp = gc + (p * NG + gd) * 4;
               const cx<T>* gqq = gc + (q * NG + gd) * 4;
@@ -1179,7 +1268,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const double v = (KIND != KIND_DELAY && (k == 0 || k == 3)) ? 1.0 : 0.0;
+          const double v = (!is_param(KIND) && (k == 0 || k == 3)) ? 1.0 : 0.0;
           gm[i * 4 + k] = (pk_amp && k == 0) ? make_double2(1.0, 1.0) : make_double2(v, 0.0);
           gc[i * 4 + k] = cmake<T>((T)v, T(0));
         }
@@ -1259,9 +1348,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     const int ant = i / n_gdir, gd = i - ant * n_gdir;
     const int slot = ant * NG + gd;
     const size_t dst = (gbase + ant) * n_gdir + gd;
-    if constexpr (KIND == KIND_DELAY) {
-      J.params[2 * dst + 0] = gm[slot * 4].x;
-      J.params[2 * dst + 1] = gm[slot * 4].y;
+    if constexpr (is_param(KIND)) {
+      params_store<KIND>(J.params, dst, gm + slot * 4);
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
@@ -1313,8 +1401,8 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
     const int ant = i / n_gdir, gd = i - ant * n_gdir;
     const int slot = ant * NG + gd;
     const size_t src = (gbase + ant) * n_gdir + gd;
-    if constexpr (KIND == KIND_DELAY) {
-      gm[slot * 4 + 0] = make_double2(J.params[2 * src + 0], J.params[2 * src + 1]);
+    if constexpr (is_param(KIND)) {
+      params_load<KIND>(J.params, src, gm + slot * 4);
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -1336,7 +1424,7 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
     for (int k = 0; k < n_part; ++k) c += partials[k * stride + slot_vals];
     chiw[0] = c;
     double m = 0.0;
-    if (KIND == KIND_DELAY)
+    if (is_param(KIND))
       for (int c2 = J.c_lo; c2 < J.c_hi; ++c2) m = fmax(m, V.freq[c2]);
     red[0] = m;
   }
@@ -1362,9 +1450,8 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
       const int slot = ant * NG + gd;
       const size_t dst = (gbase + ant) * n_gdir + gd;
-      if constexpr (KIND == KIND_DELAY) {
-        J.params[2 * dst + 0] = gm[slot * 4].x;
-        J.params[2 * dst + 1] = gm[slot * 4].y;
+      if constexpr (is_param(KIND)) {
+        params_store<KIND>(J.params, dst, gm + slot * 4);
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];

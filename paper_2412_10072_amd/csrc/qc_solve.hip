@@ -285,7 +285,9 @@ template <int KIND, typename S, typename T>
 hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
-  if (L.damping == DAMP_LM && !P) return launch_kind_lm<KIND, S, T>(L, stream, lds_out);
+  if constexpr (KIND != KIND_DELOFF) {          // (the host offers no LM for delay-and-offset terms)
+    if (L.damping == DAMP_LM && !P) return launch_kind_lm<KIND, S, T>(L, stream, lds_out);
+  }
   const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
 #define QC_LAUNCH(CHM_, NG_, RPS_)                                                          \
   return P ? launch_split_one<KIND, S, T, CHM_, NG_, RPS_>(L, *P, stream, lds_out)        \
@@ -342,6 +344,7 @@ hipError_t launch_solve(const SolveLaunch& L, const SplitLaunch* P, hipStream_t 
     switch (kind) {
       case KIND_DIAG: return launch_kind<KIND_DIAG, float, float>(L, P, stream, lds_out);
       case KIND_C2X2: return launch_kind<KIND_C2X2, float, float>(L, P, stream, lds_out);
+      case KIND_DELOFF: return launch_kind<KIND_DELOFF, float, float>(L, P, stream, lds_out);
       default: return launch_kind<KIND_DELAY, float, float>(L, P, stream, lds_out);
     }
   }
@@ -349,12 +352,14 @@ hipError_t launch_solve(const SolveLaunch& L, const SplitLaunch* P, hipStream_t 
     switch (kind) {
       case KIND_DIAG: return launch_kind<KIND_DIAG, double, double>(L, P, stream, lds_out);
       case KIND_C2X2: return launch_kind<KIND_C2X2, double, double>(L, P, stream, lds_out);
+      case KIND_DELOFF: return launch_kind<KIND_DELOFF, double, double>(L, P, stream, lds_out);
       default: return launch_kind<KIND_DELAY, double, double>(L, P, stream, lds_out);
     }
   }
   switch (kind) {
     case KIND_DIAG: return launch_kind<KIND_DIAG, float, double>(L, P, stream, lds_out);
     case KIND_C2X2: return launch_kind<KIND_C2X2, float, double>(L, P, stream, lds_out);
+    case KIND_DELOFF: return launch_kind<KIND_DELOFF, float, double>(L, P, stream, lds_out);
     default: return launch_kind<KIND_DELAY, float, double>(L, P, stream, lds_out);
   }
 }

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libqc.so")
 QC_OK, QC_E_ARG, QC_E_RANGE, QC_E_NONFINITE, QC_E_DEVICE, QC_E_NOMEM, QC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "QC_OK", -1: "QC_E_ARG", -2: "QC_E_RANGE", -3: "QC_E_NONFINITE", -4: "QC_E_DEVICE",
                 -5: "QC_E_NOMEM", -6: "QC_E_UNSUPPORTED"}
-TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2, "phase": 3, "amplitude": 4}
+TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2, "phase": 3, "amplitude": 4, "delay_offset": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3, "lm": 4}
 

@@ -1,0 +1,153 @@
+"""Delay-and-offset terms (per hand phi0 and tau: the K term of the paper's
+experiments) on the GPU against the CPU oracle: single-term and chain solves
+in FP64 (<= 1e-10) and MIXED (the model to 1e-4), the split schedule, the delay
+initial estimate, outputs, interpolation, and the LM rejection."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import forward_data, make_term, make_vis, rand_c, unit_like
+from oracle import delay_init as o_delay
+from oracle import interp as o_interp
+from oracle import outputs as o_out
+from oracle import solver as o_solver
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def problem(seed, dtype="c128", chain=False, sigma=0.02):
+    rng = np.random.default_rng(seed)
+    vis = make_vis(rng, n_ant=6, n_time=4, n_chan=32, n_dir=1, polarised=False, freq0=1.0e9, dfreq=8e6)
+    truth = [make_term(rng, "delay_offset", 4, 32, 6, t_int=2, f_int=32, scale=0.1)]
+    if chain:
+        truth.append(make_term(rng, "diag", 4, 32, 6, t_int=1, f_int=8, scale=0.1))
+    vis.data = forward_data(vis, truth) + sigma * rand_c(rng, *vis.data.shape)
+    if dtype == "c64":
+        vis = vis.copy(data=vis.data.astype(np.complex64), model=vis.model.astype(np.complex64),
+                       weight=vis.weight.astype(np.float32))
+    return vis, [unit_like(t) for t in truth], truth
+
+
+def to_dev(vis, chain):
+    from paper_2412_10072_amd import qc
+    return qc.device_vis(vis, DEV), [qc.device_term(t, DEV) for t in chain]
+
+
+def host(chain_d):
+    from paper_2412_10072_amd import qc
+    return [qc.host_term(t) for t in chain_d]
+
+
+def param_err(got, want):
+    """Largest error of phases (rad) and of delays relative to their largest size."""
+    g, w = np.asarray(got), np.asarray(want)
+    e_phi = np.abs(np.angle(np.exp(1j * (g[..., [0, 2]] - w[..., [0, 2]])))).max()
+    e_tau = np.abs(g[..., [1, 3]] - w[..., [1, 3]]).max() / max(np.abs(w[..., [1, 3]]).max(), 1e-12)
+    return e_phi, e_tau
+
+
+@pytest.mark.parametrize("mode", ["fixed", "tol"])
+def test_single_term_fp64_matches_oracle(qc_lib, mode):
+    say(f"delay_offset fp64 {mode}")
+    vis, start, _ = problem(801)
+    kw = dict(tol=-1.0, max_iter=6) if mode == "fixed" else dict(tol=1e-8, max_iter=60)
+    ref, rst = o_solver.solve_term(vis, start, 0, **kw)
+    vd, cd = to_dev(vis, start)
+    st = qc_lib.solve(vd, cd, 0, prec="fp64", **kw)
+    qc_lib.sync()
+    got = host(cd)
+    e_phi, e_tau = param_err(got[0].params, ref[0].params)
+    say(f"  iterations {st['iters'].cpu().numpy().ravel()} / {rst['iters'].ravel()}, err phi {e_phi:.2e} tau {e_tau:.2e}")
+    assert np.array_equal(st["iters"].cpu().numpy(), rst["iters"])
+    assert np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    assert e_phi <= 1e-10 and e_tau <= 1e-10
+
+
+def test_single_term_mixed_matches_oracle(qc_lib):
+    say("delay_offset mixed")
+    vis, start, _ = problem(803, dtype="c64")
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=1e-6, max_iter=60)
+    vd, cd = to_dev(vis, start)
+    st = qc_lib.solve(vd, cd, 0, prec="mixed", tol=1e-6, max_iter=60)
+    qc_lib.sync()
+    got = host(cd)
+    assert st["converged"].cpu().numpy().all() and rst["converged"].all()
+    Vg = o_out.corrupt(vis, got)
+    Vr = o_out.corrupt(vis, ref)
+    assert np.abs(Vg - Vr).max() <= 1e-4 * np.abs(Vr).max()
+
+
+def test_chain_two_epochs_fp64_and_split(qc_lib):
+    """K (delay and offset) then a diagonal G, two epochs, fixed iterations;
+    then K alone with its interval cut into 3 parts against 1."""
+    say("delay_offset chain fp64 + split")
+    vis, start, _ = problem(805, chain=True)
+    ref, _ = o_solver.solve_chain(vis, start, n_epoch=2, tol=-1.0, max_iter=4)
+    vd, cd = to_dev(vis, start)
+    qc_lib.solve_chain(vd, cd, n_epoch=2, tol=-1.0, max_iter=4, prec="fp64")
+    qc_lib.sync()
+    got = host(cd)
+    e_phi, e_tau = param_err(got[0].params, ref[0].params)
+    assert e_phi <= 1e-10 and e_tau <= 1e-10
+    d = np.abs(got[1].gains[..., [0, 3]] - ref[1].gains[..., [0, 3]]).max()
+    assert d <= 1e-10 * np.abs(ref[1].gains[..., [0, 3]]).max()
+    out = {}
+    for parts in (1, 3):
+        qc_lib.set_split(parts)
+        try:
+            vd, cd = to_dev(vis, start[:1])
+            qc_lib.solve(vd, cd, 0, tol=-1.0, max_iter=5, prec="fp64")
+            out[parts] = (host(cd)[0].params, qc_lib.last_split_parts())
+        finally:
+            qc_lib.set_split(0)
+    assert out[3][1] == 3 and out[1][1] == 1
+    e_phi, e_tau = param_err(out[3][0], out[1][0])
+    assert e_phi <= 1e-12 and e_tau <= 1e-12
+
+
+def test_delay_init_residual_and_interp(qc_lib):
+    from paper_2412_10072_amd import qc
+    import torch
+    say("delay_offset: delay init, residual, interpolation")
+    vis, start, truth = problem(807, sigma=0.0)
+    # delay initial estimate: the oracle's delays, zero offsets
+    vd, cd = to_dev(vis, start)
+    qc_lib.delay_init(vd, cd[0], ref_ant=0)
+    qc_lib.sync()
+    want = o_delay.delay_init(vis, start, 0, ref_ant=0)[0].params
+    got = cd[0].params.cpu().numpy()
+    assert np.array_equal(got, want)
+    assert (got[..., [0, 2]] == 0.0).all()
+    # residual through the truth chain, sample by sample
+    vd, td = to_dev(vis, truth)
+    R = qc_lib.residual(vd, td).cpu().numpy()
+    Rw = o_out.residual(vis, truth)
+    assert np.abs(R - Rw).max() <= 1e-12 * np.abs(vis.data).max()
+    # interpolation of the parameters onto a finer time grid
+    t_src = np.array([0.0, 16.0])
+    f_src = np.array([1.12e9])
+    t_dst = np.array([-4.0, 4.0, 8.0, 15.0, 30.0])
+    dst = make_term(np.random.default_rng(1), "delay_offset", 5, 1, 6, t_int=1, f_int=1)
+    src_d = qc.device_term(truth[0], DEV)
+    dst_d = qc.device_term(dst, DEV)
+    d64 = lambda x: torch.as_tensor(x, dtype=torch.float64, device=DEV)
+    qc_lib.interp_term(src_d, d64(t_src), d64(f_src), dst_d, d64(t_dst), d64(f_src), 6)
+    qc_lib.sync()
+    want, want_f = o_interp.interp_params(truth[0].params, truth[0].gain_flags, t_src, f_src, t_dst, f_src)
+    assert np.allclose(dst_d.params.cpu().numpy(), want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+
+
+def test_lm_rejected(qc_lib):
+    from paper_2412_10072_amd import qc
+    say("delay_offset: LM rejected")
+    vis, start, _ = problem(809)
+    vd, cd = to_dev(vis, start)
+    with pytest.raises(qc.QcError):
+        qc_lib.solve(vd, cd, 0, prec="fp64", damping="lm", tol=1e-6, max_iter=10)
