@@ -371,7 +371,9 @@ def leg_params(ctx, dev):
     """Phase-only and amplitude-only solves (real parameters, one per hand) on the
     MeerKAT shape: 64 antennas, 600 times x 1024 channels, complex64, interval
     1 time x 64 channels, truth phases (unit amplitude) or amplitudes (zero
-    phase), MIXED to tol 1e-6."""
+    phase), MIXED to tol 1e-6; then a delay-and-offset solve (phase offset and
+    delay per hand) with interval 1 time x 1024 channels from the delay
+    initial estimate."""
     import numpy as np
     import torch
     from paper_2412_10072_amd import qc
@@ -399,6 +401,38 @@ def leg_params(ctx, dev):
         del p, term, init
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    # delay and phase offset per hand (the K term), interval 1 time x the band, from the
+    # Fourier-peak delay start; too few intervals to fill the chip, so split across it
+    p = config_meerkat(device=dev, kind="delay_offset", f_int=1024)
+    torch.cuda.synchronize()
+    term = qc.device_term(p.chain[0], dev)
+    ts = time.perf_counter()
+    ctx.delay_init(p.vis, term, ref_ant=0)
+    ctx.sync()
+    t_init = 1e3 * (time.perf_counter() - ts)
+    init = term.params.clone()
+    ms, st = [], None
+    for rep in range(3):
+        term.params.copy_(init)
+        st = ctx.solve(p.vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+        ms.append(ctx.last_kernel_ms())
+    parts = ctx.last_split_parts()
+    it = st["iters"].cpu().numpy()
+    gb = float(np.sum(np.maximum(it, 1) * pass_bytes(p.vis, p.chain[0]))) / 1e9
+    k_ms = float(np.mean(ms[1:]))
+    host = qc.host_term(term)
+    d_tau = host.params[..., [1, 3]] - p.truth[0].params[..., [1, 3]]
+    out["delay_offset"] = dict(kernel_ms=k_ms, delay_init_ms=t_init, split_parts=int(parts),
+                               mean_iterations=float(it.mean()), max_iterations=int(it.max()),
+                               converged=float(st["converged"].float().mean().item()), algorithmic_gb=gb,
+                               achieved_gbs=gb / (k_ms * 1e-3), hbm_frac=gb / (k_ms * 1e-3) / HBM_PEAK_GBS,
+                               max_delay_error_ps=float(1e12 * np.abs(d_tau).max()))
+    log(f"params: delay_offset solve {k_ms:.1f} ms in {parts} parts (delay init {t_init:.1f} ms), mean "
+        f"iterations {it.mean():.2f} (max {it.max()}), {gb:.1f} GB -> {gb / (k_ms * 1e-3):.0f} GB/s, "
+        f"max delay error {1e12 * np.abs(d_tau).max():.2f} ps")
+    del p, term, init
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     return out
 
 

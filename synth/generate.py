@@ -324,6 +324,8 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
     rows stay time-ordered).
     kind "phase" / "amplitude": the truth keeps only the phases (unit amplitude) or only
     the amplitudes (zero phase) of the diagonal gains, held as the term's parameters.
+    kind "delay_offset": per hand a phase offset 0.3 pi P and a delay 2 ns P (P the smooth
+    polynomials, antenna 0 zero), unit amplitude.
     gain_mode="random": independent diagonal truth gains per interval, amp U(0.8, 1.2),
     phase U(-pi, pi), antenna 0 phase 0 (the warm-start training and evaluation data).
     meta["uvw"]: [n_row][3] baseline coordinates (m) of the kept rows; meta["sky"]: per model
@@ -344,7 +346,8 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
     P = eval_poly(smooth_poly(g0, n_ant * 8, 2, device), xt, xf).reshape(n_ant, 8, term.n_gt, term.n_gf)
     P = P.permute(2, 3, 0, 1)                                    # [gt][gf][ant][8]
     tg = torch.zeros(term.n_gt, term.n_gf, n_ant, 1, 4, dtype=torch.complex128, device=device)
-    tp = torch.zeros(term.n_gt, term.n_gf, n_ant, 1, 2, dtype=torch.float64, device=device)
+    tp = torch.zeros(term.n_gt, term.n_gf, n_ant, 1, 4 if kind == "delay_offset" else 2, dtype=torch.float64,
+                     device=device)
     for k, c in enumerate((0, 3)):
         if gain_mode == "random":
             amp = uniform(g0, (term.n_gt, term.n_gf, n_ant), 0.8, 1.2, device)
@@ -359,13 +362,19 @@ def config_meerkat(device="cpu", n_ant: int = 64, n_time: int = 600, n_chan: int
         elif kind == "amplitude":    # amplitude-only truth: zero phase
             ph = torch.zeros_like(ph)
             tp[:, :, :, 0, k] = amp
+        elif kind == "delay_offset":  # residual delay (+-2 ns) and phase offset, unit amplitude
+            amp = torch.ones_like(amp)
+            tp[:, :, :, 0, 2 * k] = 0.3 * ph
+            tp[:, :, :, 0, 2 * k + 1] = 2e-9 * P[..., 2 * k]
+            tp[:, :, 0, 0, 2 * k:2 * k + 2] = 0.0       # the reference antenna
+            continue
         tg[:, :, :, 0, c] = amp * torch.polar(torch.ones_like(ph), ph)
     if kind == "c2x2":
         z = cnormal(g0, (n_ant, 2), math.sqrt(leakage_var / 2.0), device)
         for k, c in enumerate((1, 2)):
             tg[:, :, :, 0, c] = z[None, None, :, k] * (1.0 + 0.1 * P[..., 4 + k])
     truth = term.copy(gains=tg.cpu().numpy())
-    if kind in ("phase", "amplitude"):
+    if kind in ("phase", "amplitude", "delay_offset"):
         truth = truth.copy(params=tp.cpu().numpy())
     cdt = torch.complex64 if dtype == "c64" else torch.complex128
     model = torch.empty(n_row, n_chan, 1, 4, dtype=cdt, device=device)
