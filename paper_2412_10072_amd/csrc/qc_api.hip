@@ -562,9 +562,11 @@ qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t
   L.chan_lo = ctx->d_chlo;
   L.chan_hi = ctx->d_chhi;
   L.params = k_term->params;
-  if (delay_init_lds(ctx->max_int_chan) > 64 * 1024)
+  L.max_chan = ctx->max_int_chan;
+  L.fft = delay_init_lds(L.max_chan, true) <= 64 * 1024;     // up to 1024 channels per interval
+  if (delay_init_lds(L.max_chan, L.fft != 0) > 64 * 1024)
     return fail(ctx, QC_E_UNSUPPORTED, "delay interval of %d channels exceeds the LDS budget", ctx->max_int_chan);
-  HIP_TRY(ctx, launch_delay_init(L, ctx->max_int_chan, s));
+  HIP_TRY(ctx, launch_delay_init(L, s));
   return QC_OK;
 }
 

@@ -302,10 +302,12 @@ struct DelayInitLaunch {
   const int* chan_hi;
   double* params;             // [n_gt][n_gf][n_ant][n_gdir][2], or [4] with offsets
   int offset;                 // delay-and-offset term: (phi0, tau) per hand, phi0 set to 0
+  int max_chan;               // most channels in one interval (sizes the LDS)
+  int fft;                    // LDS holds the FFT buffers: evenly spaced intervals take the FFT route
 };
 
-size_t delay_init_lds(int max_chan);
-hipError_t launch_delay_init(const DelayInitLaunch& L, int max_chan, hipStream_t stream);
+size_t delay_init_lds(int max_chan, bool fft);
+hipError_t launch_delay_init(const DelayInitLaunch& L, hipStream_t stream);
 
 struct FeatLaunch {
   VisArgs vis;

@@ -53,6 +53,35 @@ def test_delay_init_reference_antenna_and_weights(qc_lib):
     assert (got[:, :, 3] == 0).all()
 
 
+@pytest.mark.parametrize("layout", ["ragged", "decreasing", "irregular", "wide"])
+def test_delay_init_channel_layouts(qc_lib, layout):
+    """Evenly spaced channels take the FFT route (ragged: intervals of 16, 16
+    and 8 channels; decreasing: the band reversed), unevenly spaced ones and
+    intervals too wide for the FFT buffers the direct sum: the same grid
+    argmax as the oracle's direct sum in every case."""
+    from paper_2412_10072_amd import qc
+    from helpers import forward_data, make_term, make_vis, rand_c
+    say(f"delay init layout {layout}")
+    rng = np.random.default_rng(61)
+    n_chan, f_int, n_ant, n_time = {"ragged": (40, 16, 6, 4), "decreasing": (64, 64, 6, 4),
+                                    "irregular": (48, 48, 6, 4), "wide": (1100, 1100, 4, 1)}[layout]
+    vis = make_vis(rng, n_ant=n_ant, n_time=n_time, n_chan=n_chan, polarised=False, freq0=1.0e9, dfreq=1e7)
+    if layout == "decreasing":
+        vis = vis.copy(chan_freq=vis.chan_freq[::-1].copy())
+    elif layout == "irregular":
+        vis = vis.copy(chan_freq=1.0e9 + 1e7 * (np.arange(n_chan) + rng.uniform(-0.3, 0.3, n_chan)))
+    truth = [make_term(rng, "delay", n_time, n_chan, n_ant, t_int=2, f_int=f_int)]
+    truth[0].params = truth[0].params * 10.0      # ~10 ns: many grid steps of the 16-channel intervals
+    vis.data = forward_data(vis, truth) + 0.05 * rand_c(rng, *vis.data.shape)
+    ref = o_delay.delay_init(vis, truth, 0, ref_ant=0)
+    K = qc.device_term(truth[0], DEV)
+    qc_lib.delay_init(qc.device_vis(vis, DEV), K, ref_ant=0)
+    qc_lib.sync()
+    got = K.params.cpu().numpy()
+    assert np.array_equal(got, ref[0].params)
+    assert (got[:, :, 0] == 0).all() and (got[:, :, 1:] != 0).any()
+
+
 def test_chain_two_epochs_fp64(qc_lib):
     from paper_2412_10072_amd import qc
     say("chain K B G dE, 2 epochs, fp64 fixed iterations")
