@@ -32,6 +32,8 @@ def unknown_index(vis, term):
     """Ordered list of unknowns (antenna, gdir, entry) of one interval."""
     if term.kind == "delay_offset":
         U = (0, 1, 2, 3)
+    elif term.kind == "pointing":
+        U = (0, 1)
     else:
         U = UNKNOWNS[term.kind] if term.kind not in ("delay", "phase", "amplitude") else (0, 1)
     return [(a, g, u) for a in range(vis.n_ant) for g in range(int(term.n_gdir)) for u in U]

@@ -36,6 +36,12 @@ def eye2(S):
     return out
 
 
+def beam_beta(term):
+    """4 ln 2 / (fwhm nu_ref)^2 of a pointing term's Gaussian beam."""
+    fwhm, nu_ref = term.beam
+    return 4.0 * np.log(2.0) / (float(fwhm) * float(nu_ref)) ** 2
+
+
 def term_jones(term, vis, rows, chans, ants, d):
     """Jones matrix of one chain term for antenna `ants` at samples (rows, chans),
     direction d.  The gain is looked up through the term's time/frequency/direction
@@ -44,14 +50,25 @@ def term_jones(term, vis, rows, chans, ants, d):
     a phase-only term diag(exp(i phi_X), exp(i phi_Y)); an amplitude-only term
     diag(a_X, a_Y) with real a (paper Section 2.4, Scenario 1); a delay and
     offset term diag(exp(i (phi0_X + 2 pi nu tau_X)), exp(i (phi0_Y + 2 pi nu
-    tau_Y)))."""
+    tau_Y))); a pointing term (Section 2.4, Scenario 3: one parameter pair per
+    antenna, a gain that differs by direction) b I with b the term's Gaussian
+    beam at direction d seen from the antenna's pointing offset (dl, dm),
+    b = exp(-4 ln 2 ((l_d - dl)^2 + (m_d - dm)^2) (nu / (fwhm nu_ref))^2):
+    1/2 at half the full width at nu_ref, the width scaling as 1/nu."""
     t = np.asarray(vis.row_time)[rows]
     gt = np.asarray(term.t_map)[t]
     gf = np.asarray(term.f_map)[chans]
     gd = int(np.asarray(term.d_map)[d])
     S = rows.size
     J = np.zeros((S, 2, 2), dtype=np.complex128)
-    if term.kind == "delay_offset":
+    if term.kind == "pointing":
+        u = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]        # [S][2]
+        nu = np.asarray(vis.chan_freq, dtype=np.float64)[chans]
+        lm = np.asarray(term.dir_lm, dtype=np.float64)[d]
+        b = np.exp(-beam_beta(term) * nu ** 2 * ((lm[0] - u[:, 0]) ** 2 + (lm[1] - u[:, 1]) ** 2))
+        J[:, 0, 0] = b
+        J[:, 1, 1] = b
+    elif term.kind == "delay_offset":
         u = np.asarray(term.params, dtype=np.float64)[gt, gf, ants, gd]        # [S][4]
         nu = np.asarray(vis.chan_freq, dtype=np.float64)[chans]
         J[:, 0, 0] = np.exp(1j * (u[:, 0] + 2.0 * np.pi * nu * u[:, 1]))

@@ -32,6 +32,18 @@ paper is silent or inconsistent (see the design notes of the repository):
   pivot test compares each pivot with its own diagonal entry (the test of the
   Jacobi-scaled block); Levenberg-Marquardt, one damping for both, is not
   offered for this term.
+* Pointing ("pointing"; Section 2.4, Scenario 3: a parameter that does not
+  depend on direction with an effect that does): per antenna the offset
+  u = (dl, dm) of its Gaussian beam, g_{a,d} = b I with
+  b = exp(-beta nu^2 |x_d - u|^2), x_d the direction cosines of model
+  direction d, beta = 4 ln 2 / (fwhm nu_ref)^2 (the full width at half
+  maximum fwhm at nu_ref, scaling as 1/nu), both hands alike.  One real 2 x 2
+  block per (interval, antenna) from E = sum_d V_d d ln b_d / du; convergence
+  and divergence measure the step in beam widths at the top of the band,
+  |alpha Delta u| nu_max / (fwhm nu_ref); AUTO damping ALTERNATE (the beams
+  enter the model as the product b_p b_q, as amplitudes do, and a FULL step
+  excites the mode that moves every antenna's beam together); no
+  Levenberg-Marquardt.
 * Convergence (Algorithm 1's "||Delta g|| > eps"): per interval, the 2-norm
   of the applied step over the unknown entries of unflagged blocks divided by
   the 2-norm of the updated gains (amplitude-only: of the amplitudes); for
@@ -72,13 +84,13 @@ from __future__ import annotations
 import copy
 import numpy as np
 
-from .jones import PERM_IDX, vec, unvec, dagger, term_jones, chain_product
+from .jones import PERM_IDX, vec, unvec, dagger, term_jones, chain_product, beam_beta
 
 UNKNOWNS = {"diag": (0, 3), "c2x2": (0, 1, 2, 3), "delay": (0, 3), "phase": (0, 3), "amplitude": (0, 3),
-            "delay_offset": (0, 3)}
+            "delay_offset": (0, 3), "pointing": (0, 3)}
 # real-parameterised diagonal terms: params [..][2] per (antenna, gain direction),
 # [..][4] = (phi0_X, tau_X, phi0_Y, tau_Y) for delay_offset
-PARAM_KINDS = ("delay", "phase", "amplitude", "delay_offset")
+PARAM_KINDS = ("delay", "phase", "amplitude", "delay_offset", "pointing")
 
 
 def n_params(kind):
@@ -187,6 +199,8 @@ def accumulate(vis, chain, n, s_fwd: Samples):
     eq. jhwr_case2 without their common factor 2, which cancels in the update).
     Also returns chi^2 = sum w |r|^2 over the interval (eq. min)."""
     term = chain[n]
+    if term.kind == "pointing":
+        return _pointing_accumulate(vis, chain, n, s_fwd)
     U = list(UNKNOWNS[term.kind])
     n_ant, n_gdir = vis.n_ant, int(term.n_gdir)
     nu_ = len(U)
@@ -240,6 +254,50 @@ def accumulate(vis, chain, n, s_fwd: Samples):
     return JHJ, JHr, chisq
 
 
+def _pointing_accumulate(vis, chain, n, s_fwd):
+    """Blocks of a pointing term (Section 2.4, Scenario 3: eq. jhj_case3,
+    eq. jhwr_case3 without their common factor 2).  The term is b I, a scalar
+    multiple of the identity, so the model of direction d on baseline (p, q)
+    is b_{p,d} b_{q,d} times the rest of the chain and
+    dv_pq / du_p = sum_d V_pq,d d ln b_{p,d} / du_p, with V_pq,d the corrupted
+    model of direction d and d ln b / du = 2 beta nu^2 (x_d - u) (x_d = (l_d,
+    m_d), u = (dl, dm)).  E sums over directions before the real 2 x 2 block
+    of the antenna is formed; the conjugate orientation serves antenna q."""
+    term = chain[n]
+    N = len(chain)
+    n_ant = vis.n_ant
+    JHJ = np.zeros((n_ant, 1, 2, 2), dtype=np.float64)
+    JHr = np.zeros((n_ant, 1, 2), dtype=np.float64)
+    beta = beam_beta(term)
+    lm = np.asarray(term.dir_lm, dtype=np.float64)
+    t_map, f_map = np.asarray(term.t_map), np.asarray(term.f_map)
+    chisq = 0.0
+    for k, s in enumerate((s_fwd, conjugate_samples(s_fwd))):
+        if s.size == 0:
+            continue
+        nu = np.asarray(vis.chan_freq, dtype=np.float64)[s.chans]
+        gt = t_map[np.asarray(vis.row_time)[s.rows]]
+        gf = f_map[s.chans]
+        u = np.asarray(term.params, dtype=np.float64)[gt, gf, s.p, 0]          # [S][2]
+        V = np.zeros((s.size, 2, 2), dtype=np.complex128)
+        E = np.zeros((s.size, 4, 2), dtype=np.complex128)
+        for d in range(s.M.shape[1]):
+            Cp = chain_product(chain, vis, s.rows, s.chans, s.p, d, 0, N)
+            Cq = chain_product(chain, vis, s.rows, s.chans, s.q, d, 0, N)
+            Vd = Cp @ unvec(s.M[:, d]) @ dagger(Cq)
+            V += Vd
+            dlnb = 2.0 * beta * (nu ** 2)[:, None] * (lm[d][None, :] - u)        # [S][2]
+            E += vec(Vd)[:, :, None] * dlnb[:, None, :]
+        R = s.D - vec(V)
+        if k == 0:
+            chisq = float(np.sum(s.w * np.abs(R) ** 2))
+        H = np.real(np.einsum("sxu,sx,sxv->suv", np.conj(E), s.w, E))
+        b = np.real(np.einsum("sxu,sx->su", np.conj(E), s.w * R))
+        np.add.at(JHJ[:, 0], s.p, H)
+        np.add.at(JHr[:, 0], s.p, b)
+    return JHJ, JHr, chisq
+
+
 # ----------------------------------------------------------------------------
 # per-block solve (Cholesky, FP64) and damping
 # ----------------------------------------------------------------------------
@@ -277,6 +335,8 @@ def resolve_damping(mode, term):
     if mode == "auto":
         if term.kind in ("delay", "phase", "delay_offset"):
             return "full"
+        if term.kind == "pointing":
+            return "alternate"
         return "half" if term.direction_dependent else "alternate"
     if mode not in ("full", "half", "alternate", "lm"):
         raise ValueError(f"unknown damping {mode!r}")
@@ -316,8 +376,17 @@ def _offset_delay_change(step, nu_max):
                       np.abs(step[..., 2]) + 2.0 * np.pi * nu_max * np.abs(step[..., 3]))
 
 
+def _pointing_change(term, step, nu_max):
+    """Per block: the pointing step |alpha Delta u| in beam widths at the top of
+    the band (fwhm nu_ref / nu_max)."""
+    fwhm, nu_ref = term.beam
+    return np.sqrt(np.sum(step ** 2, axis=-1)) * nu_max / (float(fwhm) * float(nu_ref))
+
+
 def _step_ratio(term, step, x_new_u, ok, nu_max):
     """The interval's convergence measure of an applied step (module notes)."""
+    if term.kind == "pointing":
+        return float(np.max(_pointing_change(term, step, nu_max)[ok])) if np.any(ok) else 0.0
     if term.kind == "delay_offset":
         return float(np.max(_offset_delay_change(step, nu_max)[ok])) if np.any(ok) else 0.0
     if term.kind == "delay":
@@ -331,6 +400,8 @@ def _step_ratio(term, step, x_new_u, ok, nu_max):
 
 def _block_steps(term, step, nu_max):
     """Per-block applied step sizes for divergence flagging (module notes)."""
+    if term.kind == "pointing":
+        return _pointing_change(term, step, nu_max)
     if term.kind == "delay_offset":
         return _offset_delay_change(step, nu_max)
     if term.kind in ("delay", "phase"):
@@ -444,6 +515,8 @@ def solve_interval(vis, chain, n, gt, gf, tol, max_iter, damping="auto"):
     term = chain[n]
     mode = resolve_damping(damping, term)
     if mode == "lm":
+        if term.kind == "pointing":
+            raise ValueError("Levenberg-Marquardt is not offered for pointing terms")
         if term.kind == "delay_offset":
             raise ValueError("Levenberg-Marquardt takes no delay-and-offset term (one damping for unknowns "
                              "of very different scale)")

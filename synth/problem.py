@@ -25,16 +25,22 @@ A chain term (paper eq. joneschain) carries its own solution-interval maps
                                                         phase: phi_X, phi_Y in rad;
                                                         amplitude: a_X, a_Y;
                                                         delay_offset: [4] phi0_X,
-                                                        tau_X, phi0_Y, tau_Y)
+                                                        tau_X, phi0_Y, tau_Y;
+                                                        pointing: dl, dm)
   gain_flags [n_gt][n_gf][n_ant][n_gdir]     int8
+
+A pointing term (one parameter pair per antenna whose effect differs by direction)
+also carries dir_lm [n_dir][2] (direction cosines of each model direction) and
+beam = (fwhm, ref_freq): the full width at half maximum (rad) of its Gaussian
+beam at ref_freq (Hz); its d_map is all zeros and n_gdir = 1.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
 from typing import Any, Optional
 
-TERM_KINDS = ("diag", "c2x2", "delay", "phase", "amplitude", "delay_offset")
-PARAM_KINDS = ("delay", "phase", "amplitude", "delay_offset")
+TERM_KINDS = ("diag", "c2x2", "delay", "phase", "amplitude", "delay_offset", "pointing")
+PARAM_KINDS = ("delay", "phase", "amplitude", "delay_offset", "pointing")
 
 
 @dataclass
@@ -84,6 +90,8 @@ class Term:
     gain_flags: Any = None
     direction_dependent: bool = False
     name: str = ""
+    dir_lm: Any = None
+    beam: Any = None
 
     def __post_init__(self):
         if self.kind not in TERM_KINDS:

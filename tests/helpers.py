@@ -18,6 +18,14 @@ def jones_of(term, t, c, a, d, freq):
     if term.kind == "delay_offset":
         u = term.params[gt, gf, a, gd]
         return np.diag(np.exp(1j * (u[[0, 2]] + 2 * np.pi * freq[c] * u[[1, 3]])))
+    if term.kind == "pointing":
+        # Gaussian beam: half power at half the full width at the reference frequency
+        u = term.params[gt, gf, a, gd]
+        fwhm, nu_ref = term.beam
+        l, m = term.dir_lm[d]
+        half_width = 0.5 * fwhm * nu_ref / freq[c]
+        b = 0.5 ** (((l - u[0]) ** 2 + (m - u[1]) ** 2) / half_width ** 2)
+        return np.diag([b, b]).astype(np.complex128)
     if term.kind == "phase":
         return np.diag(np.exp(1j * term.params[gt, gf, a, gd]))
     if term.kind == "amplitude":
@@ -67,8 +75,14 @@ def make_vis(rng, n_ant=5, n_time=3, n_chan=2, n_dir=1, n_wcorr=4, polarised=Tru
                chan_freq=freq0 + dfreq * np.arange(n_chan), n_ant=n_ant, n_time=n_time)
 
 
+POINTING_BEAM = (0.02, 1.4e9)      # 1.15 deg full width at half maximum at 1.4 GHz
+
+
 def make_term(rng, kind, n_time, n_chan, n_ant, t_int=None, f_int=None, n_dir=1, dd=False,
-              scale=0.3, name=""):
+              scale=0.3, name="", dir_lm=None, beam=POINTING_BEAM):
+    """A random term; a pointing term gets offsets of scale / 3 x 0.1 of the beam's
+    full width, model directions within 0.6 of its half width at 1 GHz (dir_lm
+    [n_dir][2] when given) and beam = (fwhm, ref_freq)."""
     t_int = t_int or n_time
     f_int = f_int or n_chan
     t_map = (np.arange(n_time) // t_int).astype(np.int32)
@@ -90,6 +104,10 @@ def make_term(rng, kind, n_time, n_chan, n_ant, t_int=None, f_int=None, n_dir=1,
         params = rng.uniform(-np.pi, np.pi, shape + (2,)) * scale
     elif kind == "amplitude":
         params = 1.0 + scale * rng.uniform(-1.0, 1.0, shape + (2,))
+    elif kind == "pointing":
+        params = (scale / 3.0) * 0.1 * beam[0] * rng.uniform(-1.0, 1.0, shape + (2,))
+        if dir_lm is None:
+            dir_lm = 0.6 * 0.5 * beam[0] * 1.4 * rng.uniform(-1.0, 1.0, (n_dir, 2))
     else:
         gains = gains + scale * rand_c(rng, *shape, 4)
         if kind == "diag":
@@ -97,7 +115,9 @@ def make_term(rng, kind, n_time, n_chan, n_ant, t_int=None, f_int=None, n_dir=1,
             gains[..., 2] = 0
     return Term(kind=kind, t_map=t_map, f_map=f_map, d_map=d_map, n_gt=n_gt, n_gf=n_gf,
                 n_gdir=n_gdir, gains=gains, params=params,
-                gain_flags=np.zeros(shape, np.int8), direction_dependent=dd, name=name)
+                gain_flags=np.zeros(shape, np.int8), direction_dependent=dd, name=name,
+                dir_lm=None if kind != "pointing" else np.asarray(dir_lm, dtype=np.float64),
+                beam=None if kind != "pointing" else tuple(beam))
 
 
 def unit_like(term):

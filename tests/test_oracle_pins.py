@@ -212,6 +212,73 @@ def test_delay_offset_recovery_and_reduction_to_delay():
                            jones.term_jones(dl, vis, rows, chans, vis.ant1, 0), rtol=0, atol=1e-15)
 
 
+def test_pointing_beam_half_power_and_width_scaling():
+    """The pointing term's beam is 1 on axis, 1/2 at half the full width at the
+    reference frequency, and its width scales as 1/nu (half power at a quarter
+    of the full width at twice the frequency); both hands alike, no off-diagonal."""
+    rng = np.random.default_rng(3)
+    fwhm, nu_ref = 0.02, 1.4e9
+    vis = make_vis(rng, n_ant=3, n_time=1, n_chan=2, n_dir=3, freq0=nu_ref, dfreq=nu_ref)
+    term = make_term(rng, "pointing", 1, 2, 3, n_dir=3, beam=(fwhm, nu_ref),
+                     dir_lm=[[0.0, 0.0], [0.5 * fwhm, 0.0], [0.0, 0.25 * fwhm]])
+    term.params[:] = 0.0
+    term.params[0, 0, 1] = [0.3 * fwhm, -0.1 * fwhm]      # antenna 1 pointed away: shifted beam
+    rows = np.arange(vis.data.shape[0])
+    ant = np.zeros(rows.size, np.int64)
+    want = {(0, 0): 1.0, (1, 0): 0.5, (2, 1): 0.5, (1, 1): 0.5 ** 4, (2, 0): 0.5 ** 0.25}
+    for (d, c), b in want.items():
+        J = jones.term_jones(term, vis, rows, np.full(rows.size, c), ant, d)
+        assert np.allclose(J[:, 0, 0], b, rtol=1e-14, atol=0) and np.allclose(J[:, 1, 1], b, rtol=1e-14, atol=0)
+        assert np.all(J[:, 0, 1] == 0) and np.all(J[:, 1, 0] == 0)
+    # a pointing offset moves the beam: antenna 1 at direction 0 sees |x - u| = |u|
+    J = jones.term_jones(term, vis, rows, np.zeros(rows.size, np.int64), np.ones(rows.size, np.int64), 0)
+    rho2 = (0.3 * fwhm) ** 2 + (0.1 * fwhm) ** 2
+    assert np.allclose(J[:, 0, 0], 0.5 ** (rho2 / (0.5 * fwhm) ** 2), rtol=1e-14, atol=0)
+
+
+def test_pointing_blocks_equal_dense_2re_form():
+    """Pointing blocks (Scenario 3: the per-antenna pair (dl, dm), the Jacobian
+    summed over directions before the block is formed, common factor 2 left
+    out) against the real-parameter Jacobian by central differences of the
+    residual over the rows as given, in a chain behind a diagonal term."""
+    rng = np.random.default_rng(17)
+    n_ant = 5
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=4, n_dir=3, freq0=1.0e9, dfreq=80e6)
+    chain = [make_term(rng, "diag", 2, 4, n_ant, n_dir=3), make_term(rng, "pointing", 2, 4, n_ant, n_dir=3, scale=3.0)]
+    vis.data = forward_data(vis, chain) + 0.1 * rand_c(rng, *vis.data.shape)
+    s = solver.samples_of(vis, np.arange(vis.data.shape[0]), np.arange(4))
+    JHJ, JHr, _ = solver.accumulate(vis, chain, 1, s)
+    D_JHJ, D_JHr, idx = dense.dense_delay(vis, chain, 1, 0, 0, h=1e-7)
+    for a in range(n_ant):
+        sel = [j for j, (aa, _, _) in enumerate(idx) if aa == a]
+        D = D_JHJ[np.ix_(sel, sel)]
+        sc = np.max(np.abs(D))
+        assert np.max(np.abs(D - 2 * JHJ[a, 0])) < 1e-6 * sc
+        rs = np.sqrt(sc) * np.sqrt(np.sum(s.w))
+        assert np.max(np.abs(D_JHr[sel] + 2 * JHr[a, 0])) < 1e-6 * rs
+    assert np.all(np.linalg.eigvalsh(JHJ[:, 0]) > 0)
+
+
+def test_pointing_recovery_and_single_direction_singular():
+    """Noise-free recovery of every antenna's pointing offset from zero (no gauge:
+    several directions fix each antenna's beam); with one model direction the
+    beam depends on the offset only through its distance, the block has rank
+    one and every block is flagged singular."""
+    rng = np.random.default_rng(23)
+    n_ant = 6
+    vis = make_vis(rng, n_ant=n_ant, n_time=2, n_chan=8, n_dir=4, polarised=False, freq0=1.0e9, dfreq=40e6)
+    truth = [make_term(rng, "pointing", 2, 8, n_ant, n_dir=4, t_int=1, scale=3.0)]
+    vis.data = forward_data(vis, truth)
+    out, st = solver.solve_term(vis, [unit_like(truth[0])], 0, tol=1e-12, max_iter=100)
+    assert st["converged"].all() and (out[0].gain_flags == 0).all()
+    assert np.max(np.abs(out[0].params - truth[0].params)) < 1e-9 * truth[0].beam[0]
+    vis1 = make_vis(rng, n_ant=4, n_time=1, n_chan=4, n_dir=1, polarised=False, freq0=1.0e9, dfreq=40e6)
+    t1 = [make_term(rng, "pointing", 1, 4, 4, n_dir=1, scale=3.0)]
+    vis1.data = forward_data(vis1, t1)
+    out1, _ = solver.solve_term(vis1, [unit_like(t1[0])], 0, tol=1e-8, max_iter=3)
+    assert (out1[0].gain_flags == 1).all() and np.all(out1[0].params == 0.0)
+
+
 def test_recovery_phase_only():
     rng = np.random.default_rng(41)
     n_ant = 6
