@@ -69,7 +69,7 @@ typedef enum { QC_PREC_FP64 = 0, QC_PREC_MIXED = 1 } qc_prec;
 
 typedef enum {
   QC_TERM_DIAGONAL = 0, QC_TERM_COMPLEX2X2 = 1, QC_TERM_DELAY = 2, QC_TERM_PHASE = 3, QC_TERM_AMPLITUDE = 4,
-  QC_TERM_DELAY_OFFSET = 5
+  QC_TERM_DELAY_OFFSET = 5, QC_TERM_POINTING = 6
 } qc_term_type;
 /* DIAGONAL  : unknowns XX, YY of the gain (XY = YX = 0).
  * COMPLEX2X2: all four entries.
@@ -89,17 +89,34 @@ typedef enum {
  *             2x2 block whose pivots are tested against their own diagonal
  *             entries (the two unknowns differ in scale by (2 pi nu)^2).  Not
  *             with QC_DAMP_LM.
- * DELAY, PHASE, AMPLITUDE and DELAY_OFFSET terms keep their parameters in
- * qc_term.params;
- * their blocks are real 2x2 (one per hand, decoupled). */
+ * POINTING  : the paper's third parameterisation scenario (eq. jhj_case3,
+ *             eq. jhwr_case3): one real parameter pair per antenna, its
+ *             pointing offset (dl, dm) in direction cosines, whose effect
+ *             differs by direction: the Jones matrix at model direction d is
+ *             b I with the Gaussian beam b = exp(-4 ln 2 ((l_d - dl)^2 +
+ *             (m_d - dm)^2) (nu / (beam_fwhm beam_freq))^2), (l_d, m_d) =
+ *             dir_lm[d], both hands alike.  n_gdir = 1 and d_map all zero
+ *             (the parameter is shared by every direction); one real 2x2
+ *             block per (interval, antenna) from the Jacobian summed over
+ *             directions.  Solved by a schedule of its own (interval rows cut
+ *             into parts, FP64 sums per part, one host wait per iteration);
+ *             convergence measures the step in beam widths at the top of the
+ *             interval's band, |alpha Delta| nu_max / (beam_fwhm beam_freq).
+ *             It depends on direction, so it may not sit left of the active
+ *             term of a solve (see qc_solve_interval).  Not with QC_DAMP_LM
+ *             or qc_solve_batch.
+ * DELAY, PHASE, AMPLITUDE, DELAY_OFFSET and POINTING terms keep their
+ * parameters in qc_term.params; the blocks of the first four are real 2x2
+ * (one per hand, decoupled). */
 
 typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3,
                QC_DAMP_LM = 4 } qc_damping;
 /* Step length alpha_k of x <- x + alpha_k * Delta (the paper leaves the step
  * open, noting that Levenberg-Marquardt is a trivial extension):
  * FULL alpha = 1; HALF alpha = 1/2; ALTERNATE alpha = 1 on odd, 1/2 on even
- * updates; AUTO = FULL for delay and phase terms, HALF for direction-dependent
- * terms, ALTERNATE otherwise.
+ * updates; AUTO = FULL for delay, phase and delay-offset terms, ALTERNATE for
+ * pointing terms, HALF for other direction-dependent terms, ALTERNATE
+ * otherwise.
  * LM: Levenberg-Marquardt with the gain-ratio strategy of Madsen et al.
  * (2004): one damping mu per interval (1e-3 of the largest diagonal block
  * entry at first), every block solves (H + mu I) Delta = b and the full step
@@ -176,8 +193,12 @@ typedef struct {
   void*   gains;            /* [n_gt][n_gf][n_ant][n_gdir][4] complex128, in/out (DIAGONAL, COMPLEX2X2) */
   double* params;           /* [n_gt][n_gf][n_ant][n_gdir][2] in/out: tau_X, tau_Y in s (DELAY),
                                phi_X, phi_Y in rad (PHASE), a_X, a_Y (AMPLITUDE);
-                               [..][4] phi0_X, tau_X, phi0_Y, tau_Y (DELAY_OFFSET) */
+                               [..][4] phi0_X, tau_X, phi0_Y, tau_Y (DELAY_OFFSET);
+                               [..][2] dl, dm (POINTING, n_gdir = 1) */
   int8_t* gain_flags;       /* [n_gt][n_gf][n_ant][n_gdir] out (may be NULL for fixed terms) */
+  const double* dir_lm;     /* POINTING: [n_dir][2] (l, m) of each model direction (device); else unused */
+  double beam_fwhm;         /* POINTING: full width at half maximum of the beam (rad) at beam_freq */
+  double beam_freq;         /* POINTING: Hz */
 } qc_term;
 
 typedef struct {
@@ -218,7 +239,8 @@ typedef struct {
  * The active term's gains/params are overwritten in place.
  * Limitation: every term left of the active one must be DIAGONAL or DELAY
  * with all its directions mapped to one gain direction (QC_E_UNSUPPORTED
- * otherwise).
+ * otherwise; a POINTING term never qualifies).  An active POINTING term may
+ * sit anywhere in its chain.
  */
 qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
                             int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats);

@@ -78,8 +78,19 @@ qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
 }
 
 qc_status check_term(qc_ctx* ctx, const qc_vis* v, const qc_term* t, int j, HostMaps& hm, hipStream_t s) {
-  if (t->type < QC_TERM_DIAGONAL || t->type > QC_TERM_DELAY_OFFSET)
+  if (t->type < QC_TERM_DIAGONAL || t->type > QC_TERM_POINTING)
     return fail(ctx, QC_E_ARG, "term %d: bad type %d", j, (int)t->type);
+  if (t->type == QC_TERM_POINTING) {
+    if (t->n_gdir != 1) return fail(ctx, QC_E_ARG, "term %d: a pointing term has n_gdir = 1", j);
+    if (!t->dir_lm) return fail(ctx, QC_E_ARG, "term %d: dir_lm is NULL", j);
+    if (!(std::isfinite(t->beam_fwhm) && t->beam_fwhm > 0.0 && std::isfinite(t->beam_freq) && t->beam_freq > 0.0))
+      return fail(ctx, QC_E_ARG, "term %d: beam_fwhm and beam_freq must be positive", j);
+    std::vector<double> lm(2 * (size_t)v->n_dir);
+    HIP_TRY(ctx, hipMemcpyAsync(lm.data(), t->dir_lm, sizeof(double) * lm.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (double x : lm)
+      if (!std::isfinite(x)) return fail(ctx, QC_E_ARG, "term %d: non-finite dir_lm", j);
+  }
   if (t->n_gt <= 0 || t->n_gf <= 0 || t->n_gdir <= 0)
     return fail(ctx, QC_E_ARG, "term %d: bad gain shape (%d, %d, %d)", j, t->n_gt, t->n_gf, t->n_gdir);
   if (t->n_gdir > QC_MAX_GDIR)
@@ -149,6 +160,13 @@ void fill_args(const qc_vis* v, const qc_term* chain, int n_term, int active, Vi
     ta.d_map = t.d_map;
     ta.gains = reinterpret_cast<const double2*>(t.gains);
     ta.params = t.params;
+    if (t.type == QC_TERM_POINTING) {
+      // one parameter pair per antenna, a gain per model direction: every chain
+      // path treats the term as direction dependent
+      ta.n_gdir = v->n_dir;
+      ta.dir_lm = t.dir_lm;
+      ta.beta = 4.0 * std::log(2.0) / ((t.beam_fwhm * t.beam_freq) * (t.beam_fwhm * t.beam_freq));
+    }
   }
 }
 
@@ -245,6 +263,8 @@ int resolve_damping(qc_damping d, const qc_term& t) {
     // full steps for delay and phase-only terms: a common phase or delay
     // leaves the model unchanged, so there is no scale mode to overshoot
     if (t.type == QC_TERM_DELAY || t.type == QC_TERM_PHASE || t.type == QC_TERM_DELAY_OFFSET) return 0;
+    // pointing: the beams enter the model as the product b_p b_q (as amplitudes do)
+    if (t.type == QC_TERM_POINTING) return 2;
     return t.direction_dependent ? 1 : 2;
   }
   return (int)d;
@@ -308,6 +328,8 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_passes);
   hipFree(ctx->d_done);
   hipFree(ctx->d_active);
+  hipFree(ctx->d_pt_int);
+  hipFree(ctx->d_pt_dbl);
   hipEventDestroy(ctx->ev0);
   hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -352,9 +374,13 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   std::vector<HostMaps> maps;
   qc_status st = prepare(ctx, vis, chain, n_term, active, maps, s);
   if (st != QC_OK) return st;
+  if (chain[active].type == QC_TERM_POINTING)
+    return solve_pointing(ctx, vis, chain, n_term, active, opts, stats, s);
   for (int j = 0; j < active; ++j) {
     if (chain[j].type == QC_TERM_COMPLEX2X2)
       return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must be diagonal", j);
+    if (chain[j].type == QC_TERM_POINTING)
+      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term differs by direction (pointing)", j);
     if (!dmap_constant(maps[j]))
       return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must map all directions to one gain", j);
   }

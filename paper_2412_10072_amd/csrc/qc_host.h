@@ -69,6 +69,10 @@ struct qc_ctx {
   size_t done_cap = 0;
   int* d_active = nullptr;
   size_t active_cap = 0;
+  int* d_pt_int = nullptr;             // pointing solves: iterations, done, divergence runs
+  size_t pt_int_cap = 0;
+  double* d_pt_dbl = nullptr;          // pointing solves: chi^2 first/last, previous steps
+  size_t pt_dbl_cap = 0;
   int last_split_parts = 1;   // parts per interval of the last solve (1 = fused)
 };
 
@@ -124,6 +128,9 @@ qc_status read_err(qc_ctx* ctx, hipStream_t s);
 // (waits for them); for calls that take no chain
 qc_status validate_rows(qc_ctx* ctx, const qc_vis* v, hipStream_t s);
 int resolve_damping(qc_damping d, const qc_term& t);
+// the schedule of an active pointing term (after prepare())
+qc_status solve_pointing(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int n_term, int active,
+                         const qc_solve_opts* opts, qc_solve_stats* stats, hipStream_t s);
 bool dmap_constant(const HostMaps& hm);
 
 }  // namespace qc

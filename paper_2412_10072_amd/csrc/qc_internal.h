@@ -16,7 +16,8 @@ namespace qc {
 // argument blocks (passed to kernels by value)
 // ---------------------------------------------------------------------------
 
-enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 4, KIND_DELOFF = 5 };
+enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 4, KIND_DELOFF = 5,
+       KIND_POINT = 6 };
 // KIND_DELAY as a kernel template argument stands for every real-parameterised
 // diagonal term (delay, phase-only, amplitude-only); the term's own kind
 // (TermArgs::kind) selects the Jones form at run time.
@@ -24,12 +25,14 @@ enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 
 enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2 };
 
 struct TermArgs {
-  int kind, n_gt, n_gf, n_gdir;
+  int kind, n_gt, n_gf, n_gdir;   // pointing terms: n_gdir = the model directions (they differ by direction)
   const int* t_map;
   const int* f_map;
   const int* d_map;
   const double2* gains;   // [n_gt][n_gf][n_ant][n_gdir][4]
-  const double* params;   // [n_gt][n_gf][n_ant][n_gdir][2]
+  const double* params;   // [n_gt][n_gf][n_ant][n_gdir][2]; pointing: [n_gt][n_gf][n_ant][2]
+  const double* dir_lm;   // pointing: [n_dir][2] direction cosines of the model directions
+  double beta;            // pointing: 4 ln 2 / (fwhm nu_ref)^2
 };
 
 struct VisArgs {
@@ -176,14 +179,30 @@ __device__ __forceinline__ cx<T> param_gain(int kind, double nu, double u) {
   return phasor_turns<T>(kind == KIND_PHASE ? u * (1.0 / 6.283185307179586476925286766559) : nu * u);
 }
 
+// Gaussian beam of a pointing term at model direction d for pointing offset
+// (ul, um): exp(-beta nu^2 ((l_d - ul)^2 + (m_d - um)^2)), in FP64 (the
+// exponent reaches tens).
+__device__ __forceinline__ double beam_gain(const double* dir_lm, double beta, int d, double ul, double um,
+                                            double nu) {
+  const double dl = dir_lm[2 * d] - ul, dm = dir_lm[2 * d + 1] - um;
+  return exp(-beta * nu * nu * (dl * dl + dm * dm));
+}
+
 template <typename T>
 __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int t, int c, int x, int d,
                                              double nu) {
   const int gt = tm.t_map[t];
   const int gf = tm.f_map[c];
+  m22<T> J = mzero<T>();
+  if (tm.kind == KIND_POINT) {          // d is the model direction
+    const double* u = tm.params + 2 * (((size_t)gt * tm.n_gf + gf) * n_ant + x);
+    const T b = (T)beam_gain(tm.dir_lm, tm.beta, d, u[0], u[1], nu);
+    J.a = cx<T>{b, T(0)};
+    J.d = cx<T>{b, T(0)};
+    return J;
+  }
   const int gd = tm.d_map[d];
   const size_t blk = (((size_t)gt * tm.n_gf + gf) * n_ant + x) * tm.n_gdir + gd;
-  m22<T> J = mzero<T>();
   if (tm.kind == KIND_DELOFF) {
     // exp(i (phi0 + 2 pi nu tau)) per hand, params (phi0_X, tau_X, phi0_Y, tau_Y)
     const double* u = tm.params + 4 * blk;

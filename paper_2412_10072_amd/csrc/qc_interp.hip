@@ -140,7 +140,7 @@ qc_status qc_interp_term(qc_ctx* ctx, const qc_term* src, const double* t_src, c
   if (n_ant <= 0 || src->n_gdir <= 0 || src->n_gt <= 0 || src->n_gf <= 0 || dst->n_gt <= 0 || dst->n_gf <= 0)
     return fail(ctx, QC_E_ARG, "bad sizes");
   const bool params = src->type == QC_TERM_DELAY || src->type == QC_TERM_PHASE || src->type == QC_TERM_AMPLITUDE ||
-                      src->type == QC_TERM_DELAY_OFFSET;
+                      src->type == QC_TERM_DELAY_OFFSET || src->type == QC_TERM_POINTING;
   if (params ? (!src->params || !dst->params) : (!src->gains || !dst->gains))
     return fail(ctx, QC_E_ARG, "the term's %s array is NULL", params ? "params" : "gains");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libqc.so")
 QC_OK, QC_E_ARG, QC_E_RANGE, QC_E_NONFINITE, QC_E_DEVICE, QC_E_NOMEM, QC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "QC_OK", -1: "QC_E_ARG", -2: "QC_E_RANGE", -3: "QC_E_NONFINITE", -4: "QC_E_DEVICE",
                 -5: "QC_E_NOMEM", -6: "QC_E_UNSUPPORTED"}
-TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2, "phase": 3, "amplitude": 4, "delay_offset": 5}
+TERM_TYPES = {"diag": 0, "c2x2": 1, "delay": 2, "phase": 3, "amplitude": 4, "delay_offset": 5, "pointing": 6}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3, "lm": 4}
 
@@ -56,7 +56,8 @@ class QcTerm(C.Structure):
     _fields_ = [("type", C.c_int32), ("direction_dependent", C.c_int32), ("n_gt", C.c_int32),
                 ("n_gf", C.c_int32), ("n_gdir", C.c_int32),
                 ("t_map", C.c_void_p), ("f_map", C.c_void_p), ("d_map", C.c_void_p),
-                ("gains", C.c_void_p), ("params", C.c_void_p), ("gain_flags", C.c_void_p)]
+                ("gains", C.c_void_p), ("params", C.c_void_p), ("gain_flags", C.c_void_p),
+                ("dir_lm", C.c_void_p), ("beam_fwhm", C.c_double), ("beam_freq", C.c_double)]
 
 
 class QcSolveOpts(C.Structure):
@@ -188,6 +189,8 @@ def device_term(term, device="cuda"):
     t.d_map = to_device(term.d_map, device, torch.int32)
     t.gains = to_device(term.gains, device, torch.complex128) if term.gains is not None else None
     t.params = to_device(term.params, device, torch.float64) if term.params is not None else None
+    if getattr(term, "dir_lm", None) is not None:
+        t.dir_lm = to_device(term.dir_lm, device, torch.float64)
     if term.gain_flags is not None:
         gf = term.gain_flags
     else:
@@ -200,7 +203,7 @@ def device_term(term, device="cuda"):
 def host_term(term):
     """Copy of a chain term with every array as numpy (for comparisons)."""
     t = term.copy()
-    for name in ("t_map", "f_map", "d_map", "gains", "params", "gain_flags"):
+    for name in ("t_map", "f_map", "d_map", "gains", "params", "gain_flags", "dir_lm"):
         v = getattr(term, name)
         if isinstance(v, torch.Tensor):
             setattr(t, name, v.detach().cpu().numpy())
@@ -253,6 +256,11 @@ def _c_chain(chain: Sequence) -> C.Array:
         c.gains = _ptr(t.gains, torch.complex128, "gains") if t.gains is not None else None
         c.params = _ptr(t.params, torch.float64, "params") if t.params is not None else None
         c.gain_flags = _ptr(t.gain_flags, torch.int8, "gain_flags") if t.gain_flags is not None else None
+        if t.kind == "pointing":
+            if t.dir_lm is None or t.beam is None:
+                raise ValueError(f"term {j}: a pointing term needs dir_lm and beam")
+            c.dir_lm = _ptr(t.dir_lm, torch.float64, "dir_lm")
+            c.beam_fwhm, c.beam_freq = float(t.beam[0]), float(t.beam[1])
     return arr
 
 

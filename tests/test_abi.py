@@ -39,11 +39,41 @@ def test_binding_struct_layout_matches_header():
     from paper_2412_10072_amd import qc
     assert C.sizeof(qc.QcVis) == 8 + 6 * 4 + 8 * 8
     assert qc.QcVis.data.offset == 32
-    assert C.sizeof(qc.QcTerm) == 24 + 6 * 8
+    assert C.sizeof(qc.QcTerm) == 24 + 9 * 8
     assert qc.QcTerm.t_map.offset == 24
     assert C.sizeof(qc.QcSolveOpts) == 8 + 3 * 4 + 4 + 8 + 8
     assert C.sizeof(qc.QcSolveStats) == 5 * 8
     assert C.sizeof(qc.QcProblem) == C.sizeof(qc.QcVis) + C.sizeof(qc.QcTerm) + C.sizeof(qc.QcSolveStats)
+
+
+def test_binding_offsets_equal_the_c_compiler_s(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what a C
+    compiler gives for include/qc.h."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2412_10072_amd import qc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"qc_vis": qc.QcVis, "qc_term": qc.QcTerm, "qc_solve_opts": qc.QcSolveOpts,
+               "qc_solve_stats": qc.QcSolveStats, "qc_problem": qc.QcProblem, "qc_sky": qc.QcSky}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, f"{cname}.{fname}"
 
 
 def test_context_without_device_fails_cleanly():

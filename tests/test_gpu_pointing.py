@@ -1,0 +1,189 @@
+"""Pointing terms (one offset pair per antenna whose effect differs by
+direction: Scenario 3 of the paper's parameterisations) on the GPU against the
+CPU oracle: single-term and chain solves in FP64 (parameters <= 1e-10 of the
+beam width, iterations and flags equal), MIXED (the model to 1e-4), parts of
+the interval's rows summed in a fixed order, chi^2 only, outputs through a
+chain holding the term, the single-direction singular case, and rejections."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import forward_data, make_term, make_vis, rand_c, unit_like
+from oracle import interp as o_interp
+from oracle import outputs as o_out
+from oracle import solver as o_solver
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def problem(seed, dtype="c128", chain=False, sigma=0.02, n_dir=3, n_ant=6):
+    rng = np.random.default_rng(seed)
+    vis = make_vis(rng, n_ant=n_ant, n_time=4, n_chan=24, n_dir=n_dir, freq0=1.0e9, dfreq=20e6)
+    truth = []
+    if chain:
+        truth.append(make_term(rng, "diag", 4, 24, n_ant, n_dir=n_dir, t_int=1, f_int=12, scale=0.1))
+    truth.append(make_term(rng, "pointing", 4, 24, n_ant, n_dir=n_dir, t_int=2, f_int=12, scale=3.0))
+    vis.data = forward_data(vis, truth) + sigma * rand_c(rng, *vis.data.shape)
+    if dtype == "c64":
+        vis = vis.copy(data=vis.data.astype(np.complex64), model=vis.model.astype(np.complex64),
+                       weight=vis.weight.astype(np.float32))
+    return vis, [unit_like(t) for t in truth], truth
+
+
+def to_dev(vis, chain):
+    from paper_2412_10072_amd import qc
+    return qc.device_vis(vis, DEV), [qc.device_term(t, DEV) for t in chain]
+
+
+def host(chain_d):
+    from paper_2412_10072_amd import qc
+    return [qc.host_term(t) for t in chain_d]
+
+
+def np_stats(st):
+    return {k: v.cpu().numpy() for k, v in st.items()}
+
+
+def perr(got, want, fwhm):
+    return np.abs(np.asarray(got) - np.asarray(want)).max() / fwhm
+
+
+@pytest.mark.parametrize("parts", [1, 3])
+def test_single_term_fp64_fixed_iterations(qc_lib, parts):
+    say(f"pointing fp64 fixed, parts {parts}")
+    vis, start, truth = problem(901)
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=-1.0, max_iter=6)
+    vd, cd = to_dev(vis, start)
+    qc_lib.set_split(parts)
+    try:
+        st = np_stats(qc_lib.solve(vd, cd, 0, prec="fp64", tol=-1.0, max_iter=6))
+        got_parts = qc_lib.last_split_parts()
+    finally:
+        qc_lib.set_split(0)
+    got = host(cd)
+    assert got_parts == parts
+    e = perr(got[0].params, ref[0].params, truth[0].beam[0])
+    say(f"  param error {e:.2e} of the beam width, iterations {st['iters'].ravel()}")
+    assert np.array_equal(st["iters"], rst["iters"]) and np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    assert e <= 1e-10
+    assert np.allclose(st["chisq_first"], rst["chisq_first"], rtol=1e-11, atol=0)
+    assert np.allclose(st["chisq_last"], rst["chisq_last"], rtol=1e-11, atol=0)
+
+
+def test_single_term_fp64_to_tol_and_recovery(qc_lib):
+    say("pointing fp64 to tol")
+    vis, start, truth = problem(903, sigma=0.0)
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=1e-10, max_iter=100)
+    vd, cd = to_dev(vis, start)
+    st = np_stats(qc_lib.solve(vd, cd, 0, prec="fp64", tol=1e-10, max_iter=100))
+    got = host(cd)
+    assert np.array_equal(st["iters"], rst["iters"]) and st["converged"].all() and rst["converged"].all()
+    assert perr(got[0].params, ref[0].params, truth[0].beam[0]) <= 1e-10
+    assert perr(got[0].params, truth[0].params, truth[0].beam[0]) <= 1e-8     # noise-free: the truth
+
+
+def test_single_term_mixed(qc_lib):
+    say("pointing mixed")
+    vis, start, truth = problem(905, dtype="c64")
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=1e-6, max_iter=100)
+    vd, cd = to_dev(vis, start)
+    st = np_stats(qc_lib.solve(vd, cd, 0, prec="mixed", tol=1e-6, max_iter=100))
+    got = host(cd)
+    assert st["converged"].all() and rst["converged"].all()
+    Vg, Vr = o_out.corrupt(vis, got), o_out.corrupt(vis, ref)
+    assert np.abs(Vg - Vr).max() <= 1e-4 * np.abs(Vr).max()
+    assert perr(got[0].params, ref[0].params, truth[0].beam[0]) <= 1e-3
+
+
+def test_chain_two_epochs_fp64_and_outputs(qc_lib):
+    """A diagonal G then the pointing term, two epochs of fixed iterations; then
+    the residual and the corrupted model through that chain, sample by sample."""
+    say("pointing chain fp64 + outputs")
+    vis, start, truth = problem(907, chain=True)
+    ref, _ = o_solver.solve_chain(vis, start, n_epoch=2, tol=-1.0, max_iter=4)
+    vd, cd = to_dev(vis, start)
+    qc_lib.solve_chain(vd, cd, n_epoch=2, tol=-1.0, max_iter=4, prec="fp64")
+    qc_lib.sync()
+    got = host(cd)
+    fw = truth[1].beam[0]
+    assert perr(got[1].params, ref[1].params, fw) <= 1e-10
+    g = got[0].gains[..., [0, 3]]
+    w = ref[0].gains[..., [0, 3]]
+    assert np.abs(g - w).max() <= 1e-10 * np.abs(w).max()
+    vd, td = to_dev(vis, truth)
+    R = qc_lib.residual(vd, td).cpu().numpy()
+    assert np.abs(R - o_out.residual(vis, truth)).max() <= 1e-12 * np.abs(vis.data).max()
+    Vc = qc_lib.apply(vd, td, mode="corrupt").cpu().numpy()
+    assert np.abs(Vc - o_out.corrupt(vis, truth)).max() <= 1e-12 * np.abs(vis.data).max()
+
+
+def test_full_damping_flags_and_chi2_only(qc_lib):
+    """FULL steps with a fixed number of updates (divergence runs decided as the
+    oracle decides), and max_iter = 0: chi^2 at the start, nothing applied."""
+    say("pointing full damping, chi2 only")
+    vis, start, truth = problem(909)
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=-1.0, max_iter=8, damping="full")
+    vd, cd = to_dev(vis, start)
+    st = np_stats(qc_lib.solve(vd, cd, 0, prec="fp64", tol=-1.0, max_iter=8, damping="full"))
+    got = host(cd)
+    assert np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    assert perr(got[0].params, ref[0].params, truth[0].beam[0]) <= 1e-10
+    ref0, rst0 = o_solver.solve_term(vis, start, 0, tol=1e-6, max_iter=0)
+    vd, cd = to_dev(vis, start)
+    st0 = np_stats(qc_lib.solve(vd, cd, 0, prec="fp64", tol=1e-6, max_iter=0))
+    assert (st0["iters"] == 0).all() and (st0["converged"] == 0).all()
+    assert np.allclose(st0["chisq_first"], rst0["chisq_first"], rtol=1e-12, atol=0)
+    assert np.all(host(cd)[0].params == 0.0)
+
+
+def test_single_direction_blocks_singular(qc_lib):
+    say("pointing single direction")
+    vis, start, _ = problem(911, n_dir=1)
+    ref, _ = o_solver.solve_term(vis, start, 0, tol=1e-8, max_iter=3)
+    vd, cd = to_dev(vis, start)
+    qc_lib.solve(vd, cd, 0, prec="fp64", tol=1e-8, max_iter=3)
+    got = host(cd)
+    assert (ref[0].gain_flags == 1).all() and np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    assert np.all(got[0].params == 0.0)
+
+
+def test_interpolation_of_offsets(qc_lib):
+    import torch
+    from paper_2412_10072_amd import qc
+    say("pointing interpolation")
+    _, _, truth = problem(913)
+    t_src = np.array([0.0, 16.0])
+    f_src = np.array([1.1e9, 1.35e9])
+    t_dst = np.array([-4.0, 4.0, 8.0, 15.0, 30.0])
+    f_dst = np.array([1.0e9, 1.2e9, 1.4e9])
+    dst = make_term(np.random.default_rng(1), "pointing", 5, 3, 6, n_dir=3, t_int=1, f_int=1)
+    src_d, dst_d = qc.device_term(truth[0], DEV), qc.device_term(dst, DEV)
+    d64 = lambda x: torch.as_tensor(x, dtype=torch.float64, device=DEV)
+    qc_lib.interp_term(src_d, d64(t_src), d64(f_src), dst_d, d64(t_dst), d64(f_dst), 6)
+    qc_lib.sync()
+    want, _ = o_interp.interp_params(truth[0].params, truth[0].gain_flags, t_src, f_src, t_dst, f_dst)
+    assert np.allclose(dst_d.params.cpu().numpy(), want, rtol=0, atol=1e-15)
+
+
+def test_rejections(qc_lib):
+    from paper_2412_10072_amd import qc
+    say("pointing rejections")
+    vis, start, _ = problem(915, chain=True)
+    vd, cd = to_dev(vis, start)
+    with pytest.raises(qc.QcError):                          # LM is not offered
+        qc_lib.solve(vd, cd, 1, prec="fp64", damping="lm")
+    swapped = [cd[1], cd[0]]                                 # differs by direction, left of the active term
+    with pytest.raises(qc.QcError) as e:
+        qc_lib.solve(vd, swapped, 1, prec="fp64")
+    assert e.value.status == qc.QC_E_UNSUPPORTED
+    bad = cd[1].copy(beam=(0.0, 1.4e9))
+    with pytest.raises(qc.QcError) as e:
+        qc_lib.solve(vd, [cd[0], bad], 1, prec="fp64")
+    assert e.value.status == qc.QC_E_ARG
