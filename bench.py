@@ -436,6 +436,45 @@ def leg_params(ctx, dev):
     return out
 
 
+def leg_pointing(ctx, dev, reps: int = 3):
+    """Pointing offsets through the primary beam (one parameter pair per antenna whose
+    effect differs by direction): the chain workload's array, band and 4 clustered model
+    directions (64 antennas, 300 times x 512 channels, complex64), one pointing term with
+    intervals of 30 times x the band, MIXED to tol 1e-6 from zero offsets."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+    from synth.generate import config_pointing
+    p = config_pointing(device=dev)
+    torch.cuda.synchronize()
+    term = qc.device_term(p.chain[0], dev)
+    init = term.params.clone()
+    ms, st = [], None
+    for rep in range(reps):
+        term.params.copy_(init)
+        st = ctx.solve(p.vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+        ms.append(ctx.last_kernel_ms())
+    parts = ctx.last_split_parts()
+    it = st["iters"].cpu().numpy()
+    gb = float(np.sum(np.maximum(it, 1) * pass_bytes(p.vis, p.chain[0]))) / 1e9
+    k_ms = float(np.mean(ms[1:]))
+    err = float(np.abs(qc.host_term(term).params - p.truth[0].params).max() / p.meta["fwhm"])
+    n_samples = int(p.vis.data.shape[0]) * int(p.vis.data.shape[1])
+    out = dict(samples=n_samples, directions=int(p.vis.model.shape[2]), intervals=int(it.size), parts=int(parts),
+               solve_ms=k_ms, mean_iterations=float(it.mean()), max_iterations=int(it.max()),
+               converged=float(st["converged"].float().mean().item()), algorithmic_gb=gb,
+               achieved_gbs=gb / (k_ms * 1e-3), hbm_frac=gb / (k_ms * 1e-3) / HBM_PEAK_GBS,
+               sample_passes_per_s=float(np.sum(np.maximum(it, 1)) * n_samples / it.size) / (k_ms * 1e-3),
+               max_offset_error_beamwidths=err)
+    log(f"pointing: {it.size} intervals x {parts} parts, solve {k_ms:.1f} ms, mean iterations {it.mean():.2f} "
+        f"(max {it.max()}), {gb:.1f} GB -> {gb / (k_ms * 1e-3):.0f} GB/s, largest offset error {err:.2e} "
+        f"beam widths")
+    del p, term, init
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def flag_pass_bytes(vis) -> dict:
     """Algorithmic HBM bytes per sample of qc_mad_flag's passes: the statistic
     pass reads the residual (4 complex), the weights and the flag and writes
@@ -610,9 +649,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="flag,robust,interp,predict,batch,warm,chain,params",
-                    help="comma list of extra legs: flag, robust, interp, predict, batch, warm, chain, params "
-                         "(or none)")
+    ap.add_argument("--legs", default="flag,robust,interp,predict,batch,warm,chain,params,pointing",
+                    help="comma list of extra legs: flag, robust, interp, predict, batch, warm, chain, params, "
+                         "pointing (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -780,6 +819,14 @@ def main():
         except Exception as e:   # report, keep the main measurement
             out["legs"]["params"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"params leg failed: {e}")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if "pointing" in legs:
+        try:
+            out["legs"]["pointing"] = leg_pointing(ctx, dev)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["pointing"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"pointing leg failed: {e}")
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     if "chain" in legs:

@@ -180,12 +180,14 @@ __device__ __forceinline__ cx<T> param_gain(int kind, double nu, double u) {
 }
 
 // Gaussian beam of a pointing term at model direction d for pointing offset
-// (ul, um): exp(-beta nu^2 ((l_d - ul)^2 + (m_d - um)^2)), in FP64 (the
-// exponent reaches tens).
-__device__ __forceinline__ double beam_gain(const double* dir_lm, double beta, int d, double ul, double um,
-                                            double nu) {
+// (ul, um): exp(-beta nu^2 ((l_d - ul)^2 + (m_d - um)^2)); the exponent in
+// FP64, the exponential in the arithmetic precision T.
+template <typename T>
+__device__ __forceinline__ T beam_gain(const double* dir_lm, double beta, int d, double ul, double um, double nu) {
   const double dl = dir_lm[2 * d] - ul, dm = dir_lm[2 * d + 1] - um;
-  return exp(-beta * nu * nu * (dl * dl + dm * dm));
+  const double arg = -beta * nu * nu * (dl * dl + dm * dm);
+  if constexpr (sizeof(T) == 4) return expf((float)arg);
+  else return exp(arg);
 }
 
 template <typename T>
@@ -196,7 +198,7 @@ __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int 
   m22<T> J = mzero<T>();
   if (tm.kind == KIND_POINT) {          // d is the model direction
     const double* u = tm.params + 2 * (((size_t)gt * tm.n_gf + gf) * n_ant + x);
-    const T b = (T)beam_gain(tm.dir_lm, tm.beta, d, u[0], u[1], nu);
+    const T b = beam_gain<T>(tm.dir_lm, tm.beta, d, u[0], u[1], nu);
     J.a = cx<T>{b, T(0)};
     J.d = cx<T>{b, T(0)};
     return J;

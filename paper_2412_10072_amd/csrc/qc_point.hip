@@ -36,6 +36,7 @@ constexpr int PT_WAVES = PT_THREADS / 64;
 constexpr int PT_NV = 5;                     // H00, H01, H11, b0, b1 per antenna
 constexpr int PT_MAX_ANT = 256;              // per-wave block sums in LDS
 constexpr double PT_PIVOT_REL = 1e-12;
+constexpr int PT_SOLO_DIRS = 8;              // the term alone in its chain: per-row geometry in registers
 
 struct PointLaunch {
   VisArgs vis;
@@ -107,7 +108,12 @@ __global__ void k_point_init(PointLaunch L) {
   }
 }
 
-template <typename S, typename T>
+// SOLO: the pointing term is the whole chain and there are at most
+// PT_SOLO_DIRS directions.  Then V_pq,d = b_{p,d} b_{q,d} M_d with
+// b_p b_q = exp(-beta nu^2 (|x_d - u_p|^2 + |x_d - u_q|^2)), one exponential
+// per (sample, direction), and E_p = 2 beta nu^2 sum_d V_pq,d (x_d - u_p);
+// the direction geometry of a row is formed once, in FP64, and held in T.
+template <typename S, typename T, bool SOLO>
 __global__ void __launch_bounds__(PT_THREADS) k_point_pass(PointLaunch L) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int interval = blockIdx.x / L.n_part;
@@ -142,6 +148,22 @@ __global__ void __launch_bounds__(PT_THREADS) k_point_pass(PointLaunch L) {
 #pragma unroll
     for (int k = 0; k < 2 * PT_NV + 1; ++k) a[k] = 0.0;
     const double upl = u[2 * p], upm = u[2 * p + 1], uql = u[2 * q], uqm = u[2 * q + 1];
+    // per-row geometry of every direction (SOLO only)
+    T gs[SOLO ? PT_SOLO_DIRS : 1], gpl[SOLO ? PT_SOLO_DIRS : 1], gpm[SOLO ? PT_SOLO_DIRS : 1];
+    T gql[SOLO ? PT_SOLO_DIRS : 1], gqm[SOLO ? PT_SOLO_DIRS : 1];
+    if constexpr (SOLO) {
+#pragma unroll
+      for (int d = 0; d < PT_SOLO_DIRS; ++d) {
+        const int dd = d < n_dir ? d : 0;
+        const double pl = L.dir_lm[2 * dd] - upl, pm = L.dir_lm[2 * dd + 1] - upm;
+        const double ql = L.dir_lm[2 * dd] - uql, qm = L.dir_lm[2 * dd + 1] - uqm;
+        gs[d] = (T)((pl * pl + pm * pm) + (ql * ql + qm * qm));
+        gpl[d] = (T)pl;
+        gpm[d] = (T)pm;
+        gql[d] = (T)ql;
+        gqm[d] = (T)qm;
+      }
+    }
     for (int c = c_lo + lane; c < c_hi; c += 64) {
       const size_t s = (size_t)r * n_chan + c;
       if (V.flag[s] != 0) continue;
@@ -155,7 +177,28 @@ __global__ void __launch_bounds__(PT_THREADS) k_point_pass(PointLaunch L) {
       const double nu = V.freq[c];
       const double g2 = 2.0 * L.beta * nu * nu;
       m22<T> Vm = mzero<T>(), Ep0 = mzero<T>(), Ep1 = mzero<T>(), Eq0 = mzero<T>(), Eq1 = mzero<T>();
-      for (int d = 0; d < n_dir; ++d) {
+      if constexpr (SOLO) {
+        const T bnu = (T)(L.beta * nu * nu);
+#pragma unroll
+        for (int d = 0; d < PT_SOLO_DIRS; ++d) {
+          if (d >= n_dir) break;
+          T bb;
+          if constexpr (sizeof(T) == 4) bb = expf(-bnu * gs[d]);
+          else bb = exp(-bnu * gs[d]);
+          const m22<T> Vd = mscale(load_mat<S, T>(Mp, s * n_dir + d), bb);
+          Vm = Vm + Vd;
+          Ep0 = Ep0 + mscale(Vd, gpl[d]);
+          Ep1 = Ep1 + mscale(Vd, gpm[d]);
+          Eq0 = Eq0 + mscale(Vd, gql[d]);
+          Eq1 = Eq1 + mscale(Vd, gqm[d]);
+        }
+        const T two_bnu = (T)g2;
+        Ep0 = mscale(Ep0, two_bnu);
+        Ep1 = mscale(Ep1, two_bnu);
+        Eq0 = mscale(Eq0, two_bnu);
+        Eq1 = mscale(Eq1, two_bnu);
+      }
+      for (int d = 0; d < (SOLO ? 0 : n_dir); ++d) {
         const m22<T> Cp = chain_range<T>(CH, n_ant, 0, CH.n_term, t, c, p, d, nu);
         const m22<T> Cq = chain_range<T>(CH, n_ant, 0, CH.n_term, t, c, q, d, nu);
         const m22<T> Vd = mmul(Cp, mmul_h(load_mat<S, T>(Mp, s * n_dir + d), Cq));   // C_p M_d C_q^H
@@ -374,18 +417,23 @@ qc_status solve_pointing(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int n_t
   const bool c128 = vis->dtype == QC_C128;
   const bool mixed = opts->prec == QC_PREC_MIXED;
   const unsigned grid_pass = (unsigned)((size_t)n_int * parts);
+  const bool solo = n_term == 1 && vis->n_dir <= PT_SOLO_DIRS;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   hipLaunchKernelGGL(k_point_init, dim3((unsigned)std::min<long long>((n_int + 255) / 256, 65535)), dim3(256), 0, s,
                      L);
   HIP_TRY(ctx, hipGetLastError());
   const int n_it = opts->max_iter > 0 ? opts->max_iter : 1;
   for (int k = 0; k < n_it; ++k) {
-    if (c128)
-      hipLaunchKernelGGL((k_point_pass<double, double>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
-    else if (mixed)
-      hipLaunchKernelGGL((k_point_pass<float, float>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
-    else
-      hipLaunchKernelGGL((k_point_pass<float, double>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+    if (c128) {
+      if (solo) hipLaunchKernelGGL((k_point_pass<double, double, true>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+      else hipLaunchKernelGGL((k_point_pass<double, double, false>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+    } else if (mixed) {
+      if (solo) hipLaunchKernelGGL((k_point_pass<float, float, true>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+      else hipLaunchKernelGGL((k_point_pass<float, float, false>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+    } else {
+      if (solo) hipLaunchKernelGGL((k_point_pass<float, double, true>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+      else hipLaunchKernelGGL((k_point_pass<float, double, false>), dim3(grid_pass), dim3(PT_THREADS), lds, s, L);
+    }
     HIP_TRY(ctx, hipGetLastError());
     hipLaunchKernelGGL(k_point_update, dim3((unsigned)n_int), dim3(PT_THREADS), 0, s, L,
                        opts->max_iter > 0 ? 0 : 1);

@@ -159,6 +159,16 @@ def truth_jones(term: Term, t_idx: torch.Tensor, ants: torch.Tensor, freq: torch
         z = torch.polar(torch.ones_like(ph), ph)
         J[..., 0, 0] = z[..., 0]
         J[..., 1, 1] = z[..., 1]
+    elif term.kind == "pointing":
+        # Gaussian beam with half power at half its full width (which scales as 1/nu)
+        par = _as_t(term.params, dev, torch.float64)
+        u = par[gt[:, None], fm[None, :], ants.long()[:, None], 0]              # [R][C][2]
+        lm = _as_t(term.dir_lm, dev, torch.float64)[d]
+        half = 0.5 * float(term.beam[0]) * float(term.beam[1]) / freq           # [C]
+        rho2 = (lm[0] - u[..., 0]) ** 2 + (lm[1] - u[..., 1]) ** 2
+        b = torch.pow(torch.full_like(rho2, 0.5), rho2 / half[None, :] ** 2)
+        J[..., 0, 0] = b
+        J[..., 1, 1] = b
     elif term.kind in ("phase", "amplitude"):
         par = _as_t(term.params, dev, torch.float64)
         u = par[gt[:, None], fm[None, :], ants.long()[:, None], gd]            # [R][C][2]
@@ -236,7 +246,7 @@ def make_term(kind: str, n_time: int, n_chan: int, n_ant: int, t_int: int, f_int
     gains[..., 0] = 1.0
     gains[..., 3] = 1.0
     params = None
-    if kind in ("delay", "phase"):
+    if kind in ("delay", "phase", "pointing"):
         params = np.zeros(shape + (2,), dtype=np.float64)
     elif kind == "delay_offset":
         params = np.zeros(shape + (4,), dtype=np.float64)
@@ -554,6 +564,49 @@ def config_chain(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int =
     return Problem(vis=vis, chain=[K, B, G, dE], truth=truth,
                    meta=dict(name="chain", sigma=sigma, n_samples=n_row * n_chan, n_dir=n_dir,
                              uvw=uvw_tracks(enu, ant1, ant2, row_time, n_time), sky=list(clusters)))
+
+
+def config_pointing(device="cpu", n_ant: int = 64, n_time: int = 300, n_chan: int = 512, n_clusters: int = 4,
+                    per_cluster: int = 5, sigma: float = 0.05, flag_frac: float = 0.10, t_int: int = 30,
+                    fwhm_deg: float = 2.5, ref_freq: float = 1.28e9, offset_frac: float = 0.05,
+                    time_block: int = 4, dtype="c64", cfg_id: int = 6) -> Problem:
+    """Pointing errors seen through the primary beam: the chain workload's array, band and
+    clustered sky (n_clusters model directions at the cluster centroids), corrupted by one
+    pointing term alone: per antenna and interval of t_int times x the band an offset
+    U(-offset_frac, offset_frac) x fwhm in l and in m of a Gaussian beam of full width
+    fwhm_deg at ref_freq (scaling as 1/nu).  The chain returned for solving has zero offsets."""
+    g0 = rng(device, 2412, cfg_id, 0)
+    ant1, ant2, row_time = row_layout(n_time, n_ant)
+    nbl = n_ant * (n_ant - 1) // 2
+    n_row = ant1.size
+    freq = torch.linspace(856e6, 1712e6, n_chan, dtype=torch.float64, device=device)
+    enu = antenna_positions(g0, n_ant, 4000.0, device)
+    clusters = clustered_sources(g0, n_clusters, per_cluster, 1.0, 0.1, device)
+    n_dir = n_clusters
+    fwhm = math.radians(fwhm_deg)
+    dir_lm = np.array([[float(l.mean()), float(m.mean())] for l, m, _ in clusters], dtype=np.float64)
+    E = make_term("pointing", n_time, n_chan, n_ant, t_int, n_chan, n_dir=n_dir, name="P")
+    E = E.copy(dir_lm=dir_lm, beam=(fwhm, ref_freq))
+    off = uniform(g0, E.params.shape, -offset_frac * fwhm, offset_frac * fwhm, device).cpu().numpy()
+    truth = [E.copy(params=off)]
+    cdt = torch.complex64 if dtype == "c64" else torch.complex128
+    model = torch.empty(n_row, n_chan, n_dir, 4, dtype=cdt, device=device)
+    for t0 in range(0, n_time, time_block):
+        t1 = min(n_time, t0 + time_block)
+        r0, r1 = t0 * nbl, t1 * nbl
+        uvw = uvw_tracks(enu, ant1[r0:r1], ant2[r0:r1], row_time[r0:r1], n_time)
+        for d, (l, m, flux) in enumerate(clusters):
+            M = point_source_vis(uvw, freq, l, m, flux)
+            model[r0:r1, :, d, 0] = M.to(cdt)
+            model[r0:r1, :, d, 1] = 0
+            model[r0:r1, :, d, 2] = 0
+            model[r0:r1, :, d, 3] = M.to(cdt)
+    g1 = rng(device, 2412, cfg_id, 1)
+    vis = _finish_vis(model, truth, ant1, ant2, row_time, freq, n_ant, n_time, sigma, g1,
+                      flag_frac, dtype, device, block_rows=time_block * nbl)
+    return Problem(vis=vis, chain=[E], truth=truth,
+                   meta=dict(name="pointing", sigma=sigma, n_samples=n_row * n_chan, n_dir=n_dir,
+                             fwhm=fwhm, ref_freq=ref_freq))
 
 
 def noise_residual(n_row: int, n_chan: int, device, dtype="c64", sigma: float = 0.1, n_spikes: int = 1000,
