@@ -421,7 +421,8 @@ def leg_params(ctx, dev):
     gb = float(np.sum(np.maximum(it, 1) * pass_bytes(p.vis, p.chain[0]))) / 1e9
     k_ms = float(np.mean(ms[1:]))
     host = qc.host_term(term)
-    d_tau = host.params[..., [1, 3]] - p.truth[0].params[..., [1, 3]]
+    rel = host.params - host.params[:, :, :1]          # referenced to antenna 0: the data fix differences
+    d_tau = rel[..., [1, 3]] - p.truth[0].params[..., [1, 3]]
     out["delay_offset"] = dict(kernel_ms=k_ms, delay_init_ms=t_init, split_parts=int(parts),
                                mean_iterations=float(it.mean()), max_iterations=int(it.max()),
                                converged=float(st["converged"].float().mean().item()), algorithmic_gb=gb,

@@ -19,6 +19,15 @@ one (whole-problem oracle runs at these sizes would take hours).
   * Phase-only and amplitude-only solves on the MeerKAT shape: sampled
     intervals against the oracle (parameters <= 1e-4, iteration counts
     within one).
+  * Delay-and-offset solve on the MeerKAT shape (600 intervals of 1 time x
+    1024 channels, from the delay start, split schedule) and pointing solve
+    on the chain workload's shape (4 directions, 10 intervals of 30 times x
+    512 channels, 103 parts), MIXED to tol 1e-6 as the benchmark runs them:
+    for sampled (interval, antenna) the FP64 oracle forms the antenna's block
+    from every one of its baselines at the GPU's result, and the
+    Gauss-Newton step it gives is below 1e-6 (rad at the band edge, beam
+    widths: the result is stationary for the oracle's arithmetic); the result
+    matches the truth within the noise.
   * MAD flagging of a MeerKAT-shaped residual (1.24e9 samples): per baseline,
     sampled baselines against the oracle exactly (flags, median and MAD);
     globally, properties that pin the answer at any size: the returned median
@@ -36,7 +45,7 @@ from oracle import delay_init as o_delay
 from oracle import flagging as o_flag
 from oracle import outputs as o_out
 from oracle import solver as o_solver
-from synth.generate import config_chain, config_meerkat, noise_residual
+from synth.generate import config_chain, config_meerkat, config_pointing, noise_residual
 from synth.problem import Vis
 
 pytestmark = pytest.mark.gpu
@@ -215,6 +224,80 @@ def test_parameter_terms_full_size_sampled_parity(qc_lib, kind):
         say(f"{kind} interval ({gt}, {gf}): oracle {ri} updates, gpu {it[gt, gf]}, max |d param| {d:.2e}")
         assert rc == 1 and abs(int(it[gt, gf]) - ri) <= 1
         assert d <= 1e-4 * max(1.0, np.abs(ref[0].params[gt, gf]).max())
+
+
+def oracle_step(vis_h, term_h, a, scaled=False):
+    """The FP64 oracle's Gauss-Newton step for antenna a from a host visibility
+    set holding every row of its interval that includes a (the block of a is
+    then complete)."""
+    s = o_solver.samples_of(vis_h, np.arange(vis_h.data.shape[0]), np.arange(vis_h.data.shape[1]))
+    JHJ, JHr, _ = o_solver.accumulate(vis_h, [term_h], 0, s)
+    x, sing = o_solver.block_solve(JHJ[a, 0], JHr[a, 0], scaled=scaled)
+    assert not sing
+    return x
+
+
+def test_delay_offset_full_size_stationary(qc_lib):
+    from paper_2412_10072_amd import qc
+    say("full-size delay and offset: generating")
+    p = config_meerkat(device=DEV, kind="delay_offset", f_int=1024)
+    vis = p.vis
+    nbl = 64 * 63 // 2
+    term = qc.device_term(p.chain[0], DEV)
+    qc_lib.delay_init(vis, term, ref_ant=0)
+    st = qc_lib.solve(vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+    qc_lib.sync()
+    parts = qc_lib.last_split_parts()
+    assert st["converged"].cpu().numpy().all() and parts > 1
+    h = qc.host_term(term)
+    par = h.params
+    truth = p.truth[0].params
+    rel = par - par[:, :, :1]                         # referenced to antenna 0 (the data fix differences)
+    d_tau = np.abs(rel[..., [1, 3]] - truth[..., [1, 3]]).max()
+    d_phi = np.abs(np.angle(np.exp(1j * (rel[..., [0, 2]] - truth[..., [0, 2]])))).max()
+    say(f"delay and offset: {parts} parts, mean updates {st['iters'].float().mean().item():.2f}, "
+        f"max |d tau| {d_tau * 1e12:.1f} ps, max |d phi0| {d_phi:.3f} rad against the truth")
+    assert d_tau <= 10e-12 and d_phi <= 0.02
+    nu_max = float(vis.chan_freq.max())
+    for gt in (0, 299, 599):
+        for a in (1, 40, 63):
+            a1 = vis.ant1[gt * nbl:(gt + 1) * nbl].cpu().numpy()
+            a2 = vis.ant2[gt * nbl:(gt + 1) * nbl].cpu().numpy()
+            rows = gt * nbl + np.nonzero((a1 == a) | (a2 == a))[0]
+            x = oracle_step(rows_vis(vis, rows), h, a, scaled=True)
+            step = max(abs(x[0]) + 2 * np.pi * nu_max * abs(x[1]), abs(x[2]) + 2 * np.pi * nu_max * abs(x[3]))
+            say(f"  interval {gt}, antenna {a}: oracle step at the GPU result {step:.2e} rad")
+            assert step <= 1e-6
+
+
+def test_pointing_full_size_stationary(qc_lib):
+    from paper_2412_10072_amd import qc
+    say("full-size pointing: generating")
+    p = config_pointing(device=DEV)
+    vis = p.vis
+    nbl = 64 * 63 // 2
+    term = qc.device_term(p.chain[0], DEV)
+    st = qc_lib.solve(vis, [term], 0, tol=1e-6, max_iter=100, prec="mixed")
+    qc_lib.sync()
+    parts = qc_lib.last_split_parts()
+    assert st["converged"].cpu().numpy().all() and parts > 1
+    h = qc.host_term(term)
+    width = p.meta["fwhm"] * p.meta["ref_freq"] / float(vis.chan_freq.max())
+    err = np.abs(h.params - p.truth[0].params).max() / p.meta["fwhm"]
+    say(f"pointing: {parts} parts, mean updates {st['iters'].float().mean().item():.2f}, "
+        f"max offset error {err:.2e} beam widths")
+    assert err <= 2e-3
+    t_int = 30
+    for gt in (0, 9):
+        for a in (0, 41):
+            r0, r1 = gt * t_int * nbl, (gt + 1) * t_int * nbl
+            a1 = vis.ant1[r0:r1].cpu().numpy()
+            a2 = vis.ant2[r0:r1].cpu().numpy()
+            rows = r0 + np.nonzero((a1 == a) | (a2 == a))[0]
+            x = oracle_step(rows_vis(vis, rows), h, a)
+            step = float(np.hypot(x[0], x[1])) / width
+            say(f"  interval {gt}, antenna {a}: oracle step at the GPU result {step:.2e} beam widths")
+            assert step <= 1e-6
 
 
 def rows_vis(vis, rows):
