@@ -737,6 +737,8 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
     if (!dir_mask || dir_mask[d]) mask |= 1u << d;
   L.dir_mask = mask;
   L.out = out;
+  L.w_vec = mode == 3 && vis->n_wcorr == 4 && reinterpret_cast<uintptr_t>(vis->weight) % 16 == 0 &&
+            reinterpret_cast<uintptr_t>(out) % 16 == 0;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   HIP_TRY(ctx, launch_outputs(L, s));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));

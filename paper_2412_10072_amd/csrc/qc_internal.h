@@ -364,6 +364,7 @@ struct OutputLaunch {
   int mode;                   // 0 corrupt, 1 correct, 2 residual, 3 corrected weights
   unsigned dir_mask;          // bit d set = direction d included
   int diag_chain;             // every chain term is diagonal or a delay
+  int w_vec;                  // corrected weights: 4 per sample, weights and out 16-byte aligned
   void* out;
 };
 

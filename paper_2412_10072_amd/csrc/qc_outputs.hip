@@ -77,13 +77,26 @@ __device__ __forceinline__ void diag_part(const ChainArgs& CH, int n_ant, int t,
 }
 
 // w |c_p,i|^2 |c_q,j|^2 into the weights of sample s (one weight: the mean factor)
+// (vec: four weights per sample, both arrays 16-byte aligned: one vector load
+// and store per sample, the same products)
 template <typename S, typename T>
 __device__ __forceinline__ void corrected_weight(const VisArgs& V, size_t s, cx<T> p0, cx<T> p1, cx<T> q0,
-                                                 cx<T> q1, S* out) {
+                                                 cx<T> q1, S* out, bool vec) {
   const S* W = reinterpret_cast<const S*>(V.weight);
   const T a0 = norm2(p0), a1 = norm2(p1), b0 = norm2(q0), b1 = norm2(q1);
   const T f[4] = {a0 * b0, a0 * b1, a1 * b0, a1 * b1};
-  if (V.n_wcorr == 4) {
+  if (V.n_wcorr == 4 && vec) {
+    if constexpr (sizeof(S) == 4) {
+      const float4 w = reinterpret_cast<const float4*>(W)[s];
+      reinterpret_cast<float4*>(out)[s] = make_float4(w.x * f[0], w.y * f[1], w.z * f[2], w.w * f[3]);
+    } else {
+      const double2* wp = reinterpret_cast<const double2*>(W) + 2 * s;
+      const double2 w01 = wp[0], w23 = wp[1];
+      double2* op = reinterpret_cast<double2*>(out) + 2 * s;
+      op[0] = make_double2(w01.x * f[0], w01.y * f[1]);
+      op[1] = make_double2(w23.x * f[2], w23.y * f[3]);
+    }
+  } else if (V.n_wcorr == 4) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[4 * s + k] = (S)((T)W[4 * s + k] * f[k]);
   } else {
@@ -123,7 +136,7 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
         diag_part<T, true>(CH, V.n_ant, t, c, q, 0, nu, q0, q1);
       }
       if constexpr (MODE == 3) {
-        corrected_weight<S, T>(V, s, p0, p1, q0, q1, Op);
+        corrected_weight<S, T>(V, s, p0, p1, q0, q1, Op, L.w_vec != 0);
       } else if constexpr (MODE == 1) {
         // C_p^-1 D C_q^-H, zero where C_p or C_q is singular
         const bool ok = !(p0.re == T(0) && p0.im == T(0)) && !(p1.re == T(0) && p1.im == T(0)) &&
@@ -154,7 +167,7 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
     } else if constexpr (MODE == 3) {
       const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, 0, nu);
       const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, 0, nu);
-      corrected_weight<S, T>(V, s, Cp.a, Cp.d, Cq.a, Cq.d, Op);
+      corrected_weight<S, T>(V, s, Cp.a, Cp.d, Cq.a, Cq.d, Op, L.w_vec != 0);
     } else if constexpr (MODE == 1) {
       const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, 0, nu);
       const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, 0, nu);

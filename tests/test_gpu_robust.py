@@ -110,6 +110,31 @@ def test_corrected_weights_match_oracle(qc_lib, dtype, n_wcorr, chain_kind):
     assert np.allclose(got, want, rtol=rtol, atol=0)
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_corrected_weights_unaligned_out_equals_aligned(qc_lib, dtype):
+    """An output buffer one element off 16-byte alignment takes the element
+    route; the aligned call takes vector loads and stores: equal bitwise."""
+    import torch
+    from paper_2412_10072_amd import qc
+    say(f"corrected weights unaligned out {dtype}")
+    rng, vis, _ = problem(641, dtype=dtype, n_wcorr=4, autos=False)
+    n_time, n_chan, n_ant = int(vis.n_time), vis.data.shape[1], int(vis.n_ant)
+    chain = [make_term(rng, "diag", n_time, n_chan, n_ant, t_int=4, f_int=16),
+             make_term(rng, "c2x2", n_time, n_chan, n_ant, t_int=2, f_int=8)]
+    vd = qc.device_vis(vis, DEV)
+    cd = [qc.device_term(t, DEV) for t in chain]
+    aligned = qc_lib.corrected_weights(vd, cd)
+    store = torch.zeros(vd.weight.numel() + 1, dtype=vd.weight.dtype, device=DEV)
+    off = store[1:].view(vd.weight.shape)
+    assert off.data_ptr() % 16 != 0
+    qc_lib.corrected_weights(vd, cd, out=off)
+    qc_lib.sync()
+    assert torch.equal(off, aligned)
+    want = o_rob.corrected_weights(vis, chain)
+    rtol = 1e-12 if dtype == "c128" else 2e-5
+    assert np.allclose(aligned.cpu().numpy(), want, rtol=rtol, atol=0)
+
+
 def test_corrected_weights_reject_direction_dependent_chains(qc_lib):
     from paper_2412_10072_amd import qc
     say("corrected weights rejection")
