@@ -93,16 +93,17 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 }
 
 __global__ void k_point_init(PointLaunch L) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
   const int n_ant = L.vis.n_ant;
-  if (i < L.n_int) {
-    L.iters[i] = 0;
-    L.done[i] = 0;
-    L.chi[2 * i] = 0.0;
-    L.chi[2 * i + 1] = 0.0;
+  for (long long k = i; k < L.n_int; k += stride) {
+    L.iters[k] = 0;
+    L.done[k] = 0;
+    L.chi[2 * k] = 0.0;
+    L.chi[2 * k + 1] = 0.0;
   }
   if (i == 0) L.n_active[0] = L.n_int;
-  for (long long k = i; k < (long long)L.n_int * n_ant; k += (long long)gridDim.x * blockDim.x) {
+  for (long long k = i; k < (long long)L.n_int * n_ant; k += stride) {
     L.run[k] = 0;
     L.prev[k] = 0.0;
   }
