@@ -105,6 +105,89 @@ def measured_traffic():
         return None
 
 
+def _one_blas_thread():
+    """Pool worker start-up: one BLAS thread per process (the pool supplies the parallelism)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _noop(_):
+    return 0
+
+
+def _oracle_interval(task):
+    """Pool worker: one interval solved to tol 1e-6 by the oracle; returns its samples."""
+    from oracle import solver as o_solver
+    vis_k, term_k = task
+    o_solver.solve_term(vis_k, [term_k], 0, tol=1e-6, max_iter=100)
+    return int(vis_k.data.shape[0]) * int(vis_k.data.shape[1])
+
+
+def cpu_baseline_pool(prob, n_times: int = 4, workers: int = 0):
+    """The oracle over a pool of host processes (one interval per task, one BLAS
+    thread each): the intervals of the first n_times times, timed from the
+    first task to the last result, the workers started beforehand."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    from synth.generate import slice_times, to_numpy_vis
+    workers = workers or min(16, os.cpu_count() or 1)
+    term = prob.chain[0]
+    f_map = np.asarray(term.f_map)
+    tasks = []
+    for t in range(n_times):
+        vis_h = to_numpy_vis(slice_times(prob.vis, t, t + 1))
+        for gf in range(int(term.n_gf)):
+            ch = np.nonzero(f_map == gf)[0]
+            vis_k = vis_h.copy(data=np.ascontiguousarray(vis_h.data[:, ch]),
+                               model=np.ascontiguousarray(vis_h.model[:, ch]),
+                               weight=np.ascontiguousarray(vis_h.weight[:, ch]),
+                               flag=np.ascontiguousarray(vis_h.flag[:, ch]), chan_freq=vis_h.chan_freq[ch])
+            term_k = term.copy(t_map=np.zeros(1, np.int32), f_map=np.zeros(ch.size, np.int32), n_gt=1, n_gf=1,
+                               gains=term.gains[:1, :1].copy(), gain_flags=term.gain_flags[:1, :1].copy())
+            tasks.append((vis_k, term_k))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                             initializer=_one_blas_thread) as ex:
+        list(ex.map(_noop, range(4 * workers)))
+        t0 = time.perf_counter()
+        samples = sum(ex.map(_oracle_interval, tasks))
+        dt = time.perf_counter() - t0
+    return dict(value=samples / dt, unit="vis/s", cores=workers,
+                sample=f"{len(tasks)} intervals (the first {n_times} times x {int(term.n_gf)} channel intervals) "
+                       f"solved to tol 1e-6 by the oracle in {workers} processes in {dt:.1f} s")
+
+
+def leg_fp64(ctx, vis, term0, init_gains, int_bytes, stream, reps: int = 2):
+    """The main workload's solve in FP64 (complex64 data widened on load, FP64
+    products and sums), and the MIXED solution's difference from it: the
+    largest over intervals of ||g_mixed - g_fp64||_2 / ||g_fp64||_2."""
+    import numpy as np
+    import torch
+    mixed = term0.gains.clone()
+    ms, st = [], None
+    for _ in range(reps):
+        term0.gains.copy_(init_gains)
+        st = ctx.solve(vis, [term0], 0, tol=1e-6, max_iter=100, prec="fp64", stream=stream)
+        ms.append(ctx.last_kernel_ms())
+    it = st["iters"].cpu().numpy()
+    g64 = term0.gains
+    num = torch.linalg.vector_norm((mixed - g64).reshape(g64.shape[0], g64.shape[1], -1), dim=-1)
+    den = torch.linalg.vector_norm(g64.reshape(g64.shape[0], g64.shape[1], -1), dim=-1)
+    rel = float((num / den).max().item())
+    term0.gains.copy_(mixed)
+    gb = float(np.sum(np.maximum(it, 1) * int_bytes)) / 1e9
+    k_ms = float(ms[-1])
+    log(f"fp64: solve {k_ms:.1f} ms, mean iterations {it.mean():.2f} (max {it.max()}), {gb:.1f} GB -> "
+        f"{gb / (k_ms * 1e-3):.0f} GB/s; MIXED against FP64: {rel:.2e}")
+    return dict(kernel_ms=k_ms, mean_iterations=float(it.mean()), max_iterations=int(it.max()),
+                converged=float(st["converged"].float().mean().item()), algorithmic_gb=gb,
+                achieved_gbs=gb / (k_ms * 1e-3), hbm_frac=gb / (k_ms * 1e-3) / HBM_PEAK_GBS,
+                rel_err_mixed_vs_fp64=rel)
+
+
 def cpu_baseline(prob, budget_s: float = 20.0):
     """The oracle as it stands, timed on host cores on a bounded sample of the
     same workload: whole intervals solved to tol 1e-6 until ~budget_s."""
@@ -650,9 +733,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="flag,robust,interp,predict,batch,warm,chain,params,pointing",
-                    help="comma list of extra legs: flag, robust, interp, predict, batch, warm, chain, params, "
-                         "pointing (or none)")
+    ap.add_argument("--legs", default="fp64,flag,robust,interp,predict,batch,warm,chain,params,pointing",
+                    help="comma list of extra legs: fp64, flag, robust, interp, predict, batch, warm, chain, "
+                         "params, pointing (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
     args = ap.parse_args()
@@ -763,9 +846,23 @@ def main():
         out["roofline"]["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+        try:
+            out["cpu_baseline"]["all_cores"] = cpu_baseline_pool(prob)
+            log(f"cpu baseline: 1 core {out['cpu_baseline']['value']:.3g} vis/s, "
+                f"{out['cpu_baseline']['all_cores']['cores']} processes "
+                f"{out['cpu_baseline']['all_cores']['value']:.3g} vis/s")
+        except Exception as e:   # report, keep the main measurement
+            out["cpu_baseline"]["all_cores"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"all-core oracle baseline failed: {e}")
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     if legs:
         out["legs"] = {}
+    if "fp64" in legs:
+        try:
+            out["legs"]["fp64"] = leg_fp64(ctx, vis, term0, init_gains, int_bytes, stream)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["fp64"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"fp64 leg failed: {e}")
     if "flag" in legs:
         try:
             out["legs"]["flag"] = leg_flag(ctx, vis, resid)
