@@ -268,15 +268,19 @@ qc_status qc_solve_chain_robust(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, 
 
 /*
  * Initial delay estimate (Section 4.3, "Initial estimates"): for every
- * interval of the DELAY term k_term and every antenna a != ref_ant, per hand
+ * interval of the DELAY (or DELAY_OFFSET) term k_term and every antenna a != ref_ant, per hand
  * (X: XX, Y: YY), y(nu) = sum over the interval's unflagged samples of the
  * baselines (ref, a) and (a, ref) of w D conj(M) (oriented so y ~
  * exp(2 pi i nu (tau_a - tau_ref)), M summed over directions); tau_a is the
  * first maximum of |sum_nu y(nu) exp(-2 pi i nu tau)|^2 on the grid
  * tau_k = k / (N dnu), k = -N/2..N/2-1, dnu the mean channel spacing of the
  * interval, N the smallest power of two >= 8 x its channels.  FP64.
- * Writes k_term->params for every gain direction; ref_ant gets 0.
- * QC_E_UNSUPPORTED if an interval has more than ~1900 channels.
+ * Evenly spaced channels (to 1e-9 of their spacing, increasing or
+ * decreasing) in intervals of at most 1024 channels take eight length-N/8
+ * FFTs per hand; others the direct sum over channels (both give the grid
+ * values to rounding).  Writes k_term->params for every gain direction
+ * (DELAY_OFFSET terms: tau, with phi0 = 0); ref_ant gets 0.
+ * QC_E_UNSUPPORTED if an interval has more than 1823 channels.
  */
 qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t ref_ant, void* stream);
 
