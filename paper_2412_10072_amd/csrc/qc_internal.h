@@ -154,16 +154,18 @@ template <typename T> __device__ __forceinline__ m22<T> rowscale(cx<T> a0, cx<T>
 // ---------------------------------------------------------------------------
 
 // exp(2 pi i nu tau) with the turn count removed in FP64 so that an FP32
-// sine/cosine sees an argument in [-pi, pi] (nu * tau reaches ~10 turns).
+// sine/cosine sees an argument in [-1/2, 1/2] turns (nu * tau reaches ~10
+// turns).  FP32: the hardware sine and cosine, which take their argument in
+// revolutions (within 2e-7 of FP64 on [-1/2, 1/2], measured on the device:
+// the accuracy of the library's sincospif, at two transcendental operations).
 constexpr double INV_TWO_PI = 0.15915494309189533576888376337251;   // 1 / (2 pi)
 
 template <typename T>
 __device__ __forceinline__ cx<T> phasor_turns(double turns) {
   double fr = turns - rint(turns);
   if constexpr (sizeof(T) == 4) {
-    float s, c;
-    sincospif(2.0f * (float)fr, &s, &c);
-    return cx<T>{c, s};
+    const float f = (float)fr;
+    return cx<T>{__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
   } else {
     double s, c;
     sincospi(2.0 * fr, &s, &c);
