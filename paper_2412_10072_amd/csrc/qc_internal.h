@@ -192,6 +192,50 @@ __device__ __forceinline__ T beam_gain(const double* dir_lm, double beta, int d,
   else return exp(arg);
 }
 
+// Element i of a term's gains or parameters (as doubles); UNI: i is the
+// same in every lane, read through the scalar cache (constant address space).
+template <bool UNI>
+__device__ __forceinline__ double ld_term(const double* base, size_t i) {
+  if constexpr (UNI) {
+    using CP = const __attribute__((address_space(4))) double*;
+    return ((CP)base)[i];
+  } else {
+    return base[i];
+  }
+}
+
+template <bool UNI>
+__device__ __forceinline__ double2 ld_gain(const double2* base, size_t i) {
+  const double* b = reinterpret_cast<const double*>(base);
+  return make_double2(ld_term<UNI>(b, 2 * i), ld_term<UNI>(b, 2 * i + 1));
+}
+
+// The Jones matrix of one gain block of a (non-pointing) term at frequency nu.
+template <typename T, bool UNI>
+__device__ __forceinline__ m22<T> term_block(const TermArgs& tm, size_t blk, double nu) {
+  m22<T> J = mzero<T>();
+  if (tm.kind == KIND_DELOFF) {
+    // exp(i (phi0 + 2 pi nu tau)) per hand, params (phi0_X, tau_X, phi0_Y, tau_Y)
+    const double u0 = ld_term<UNI>(tm.params, 4 * blk), u1 = ld_term<UNI>(tm.params, 4 * blk + 1);
+    const double u2 = ld_term<UNI>(tm.params, 4 * blk + 2), u3 = ld_term<UNI>(tm.params, 4 * blk + 3);
+    J.a = phasor_turns<T>(u0 * INV_TWO_PI + nu * u1);
+    J.d = phasor_turns<T>(u2 * INV_TWO_PI + nu * u3);
+  } else if (tm.kind >= KIND_DELAY) {
+    J.a = param_gain<T>(tm.kind, nu, ld_term<UNI>(tm.params, 2 * blk + 0));
+    J.d = param_gain<T>(tm.kind, nu, ld_term<UNI>(tm.params, 2 * blk + 1));
+  } else {
+    const double2 g0 = ld_gain<UNI>(tm.gains, 4 * blk), g3 = ld_gain<UNI>(tm.gains, 4 * blk + 3);
+    J.a = cmake<T>((T)g0.x, (T)g0.y);
+    J.d = cmake<T>((T)g3.x, (T)g3.y);
+    if (tm.kind == KIND_C2X2) {
+      const double2 g1 = ld_gain<UNI>(tm.gains, 4 * blk + 1), g2 = ld_gain<UNI>(tm.gains, 4 * blk + 2);
+      J.b = cmake<T>((T)g1.x, (T)g1.y);
+      J.c = cmake<T>((T)g2.x, (T)g2.y);
+    }
+  }
+  return J;
+}
+
 template <typename T>
 __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int t, int c, int x, int d,
                                              double nu) {
@@ -207,26 +251,14 @@ __device__ __forceinline__ m22<T> term_jones(const TermArgs& tm, int n_ant, int 
   }
   const int gd = tm.d_map[d];
   const size_t blk = (((size_t)gt * tm.n_gf + gf) * n_ant + x) * tm.n_gdir + gd;
-  if (tm.kind == KIND_DELOFF) {
-    // exp(i (phi0 + 2 pi nu tau)) per hand, params (phi0_X, tau_X, phi0_Y, tau_Y)
-    const double* u = tm.params + 4 * blk;
-    J.a = phasor_turns<T>(u[0] * INV_TWO_PI + nu * u[1]);
-    J.d = phasor_turns<T>(u[2] * INV_TWO_PI + nu * u[3]);
-  } else if (tm.kind >= KIND_DELAY) {
-    J.a = param_gain<T>(tm.kind, nu, tm.params[2 * blk + 0]);
-    J.d = param_gain<T>(tm.kind, nu, tm.params[2 * blk + 1]);
-  } else {
-    const double2* g = tm.gains + 4 * blk;
-    double2 g0 = g[0], g3 = g[3];
-    J.a = cmake<T>((T)g0.x, (T)g0.y);
-    J.d = cmake<T>((T)g3.x, (T)g3.y);
-    if (tm.kind == KIND_C2X2) {
-      double2 g1 = g[1], g2 = g[2];
-      J.b = cmake<T>((T)g1.x, (T)g1.y);
-      J.c = cmake<T>((T)g2.x, (T)g2.y);
-    }
-  }
-  return J;
+  // Usually every lane of the wavefront needs the same block (one row, the
+  // channels of one interval): then it is read once, through the scalar
+  // cache (the gains and parameters of a term are not written while it is
+  // evaluated), instead of by every lane.
+  const unsigned lo = (unsigned)blk, hi = (unsigned)(blk >> 32);
+  const unsigned lo0 = __builtin_amdgcn_readfirstlane(lo), hi0 = __builtin_amdgcn_readfirstlane(hi);
+  if (__all(lo == lo0 && hi == hi0)) return term_block<T, true>(tm, ((size_t)hi0 << 32) | lo0, nu);
+  return term_block<T, false>(tm, blk, nu);
 }
 
 // Product of terms [j0, j1) for antenna x; identity if empty.
