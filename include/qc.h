@@ -157,7 +157,7 @@ double      qc_last_kernel_ms(qc_ctx* ctx);
 qc_status   qc_ctx_set_tile(qc_ctx* ctx, int32_t waves, int32_t rows_per_step);
 /* Schedule of qc_solve_interval: parts = 0 chooses automatically (a term with
  * fewer intervals than four times the compute units, of >= 2^18 samples on
- * average, is split into about 4 workgroups per compute unit; not with a
+ * average, is split into about 32 workgroups per compute unit; not with a
  * chisq_ref), 1 never splits (one workgroup runs each interval to the end),
  * > 1 cuts every interval's rows into that many parts streamed by separate
  * workgroups whose FP64 blocks are summed in a fixed order before each update

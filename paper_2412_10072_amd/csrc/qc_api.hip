@@ -418,7 +418,7 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   // schedule: fused (one workgroup per interval) unless the term has too few
   // intervals to give every CU several workgroups and they are large enough
   // (>= 2^18 samples on average) to amortise a host wait per iteration; those
-  // are cut into parts streamed by separate workgroups (about 4 per CU)
+  // are cut into parts streamed by separate workgroups (about SPLIT_WG_PER_CU per CU)
   const int n_int = ta.n_gt * ta.n_gf;
   const double avg_samples = n_int > 0 ? (double)vis->n_row * vis->n_chan / n_int : 0.0;
   int parts = 1;
@@ -431,7 +431,7 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   } else if (ctx->split_parts == 0 && !lm && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
              avg_samples >= (double)(1 << 18)) {
     const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
-    parts = (int)std::ceil(4.0 * ctx->n_cu / n_int);
+    parts = (int)std::ceil((double)SPLIT_WG_PER_CU * ctx->n_cu / n_int);
     parts = std::max(2, std::min(parts, (int)std::max(1.0, rows_per_int / 64.0)));
   }
   if (parts > 1 && opts->chisq_ref)

@@ -372,11 +372,11 @@ qc_status solve_pointing(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int n_t
   const int n_int = ta.n_gt * ta.n_gf;
   L.n_gf = ta.n_gf;
   L.n_int = n_int;
-  // parts: about four workgroups per compute unit, at least 16 rows per part
+  // parts: about SPLIT_WG_PER_CU workgroups per compute unit, at least 16 rows per part
   int parts = ctx->split_parts > 0 ? ctx->split_parts : 1;
   if (ctx->split_parts == 0 && n_int > 0) {
     const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
-    parts = (int)std::ceil(4.0 * ctx->n_cu / n_int);
+    parts = (int)std::ceil((double)SPLIT_WG_PER_CU * ctx->n_cu / n_int);
     parts = std::max(1, std::min(parts, (int)(rows_per_int / 16.0)));
   }
   L.n_part = parts;
