@@ -741,7 +741,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver shards by solution intervals with no communication, "
-              "and this build runs on a single MI355X; --gpus above 1 is not supported.", file=sys.stderr)
+              "and this implementation runs on a single MI355X; --gpus above 1 is not supported.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
