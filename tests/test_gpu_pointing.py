@@ -77,6 +77,21 @@ def test_single_term_fp64_fixed_iterations(qc_lib, parts):
     assert np.allclose(st["chisq_last"], rst["chisq_last"], rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("n_dir", [6, 8])
+def test_single_term_more_directions(qc_lib, n_dir):
+    """The single-term pass with 5 to 8 directions (the library's limit): the
+    per-row geometry is held for 8, the loop ending early below that."""
+    say(f"pointing fp64, {n_dir} directions")
+    vis, start, truth = problem(917 + n_dir, n_dir=n_dir, n_ant=5)
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=-1.0, max_iter=4)
+    vd, cd = to_dev(vis, start)
+    st = np_stats(qc_lib.solve(vd, cd, 0, prec="fp64", tol=-1.0, max_iter=4))
+    got = host(cd)
+    assert np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    assert perr(got[0].params, ref[0].params, truth[0].beam[0]) <= 1e-10
+    assert np.allclose(st["chisq_last"], rst["chisq_last"], rtol=1e-11, atol=0)
+
+
 def test_single_term_fp64_to_tol_and_recovery(qc_lib):
     say("pointing fp64 to tol")
     vis, start, truth = problem(903, sigma=0.0)
