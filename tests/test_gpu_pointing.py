@@ -158,6 +158,29 @@ def test_full_damping_flags_and_chi2_only(qc_lib):
     assert np.all(host(cd)[0].params == 0.0)
 
 
+def test_fully_flagged_interval(qc_lib):
+    """Every sample of the first time interval flagged (garbage under the
+    flags): its blocks are empty and flagged, the step is zero and the
+    interval stops after one update, as in the oracle; the others solve."""
+    say("pointing fully flagged interval")
+    vis, start, truth = problem(913)
+    flag = vis.flag.copy()
+    first = vis.row_time < 2
+    flag[first] = 1
+    data = vis.data.copy()
+    data[first] = np.nan
+    vis = vis.copy(flag=flag, data=data)
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=1e-8, max_iter=20)
+    vd, cd = to_dev(vis, start)
+    st = np_stats(qc_lib.solve(vd, cd, 0, prec="fp64", tol=1e-8, max_iter=20))
+    got = host(cd)
+    assert (ref[0].gain_flags[0] == 1).all() and (rst["iters"][0] == 1).all()
+    assert np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    assert np.array_equal(st["iters"], rst["iters"]) and np.array_equal(st["converged"], rst["converged"])
+    assert np.all(got[0].params[0] == 0.0)
+    assert perr(got[0].params, ref[0].params, truth[0].beam[0]) <= 1e-10
+
+
 def test_single_direction_blocks_singular(qc_lib):
     say("pointing single direction")
     vis, start, _ = problem(911, n_dir=1)
