@@ -1096,44 +1096,62 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           // one gain direction: every model direction maps to it, look up once
           if constexpr (NG == 1) active_diag(0, hp0, hp1, hq0, hq1);
           m22<T> Vm = mzero<T>();
-          for (int d = 0; d < n_dir; ++d) {
-            const int gd = NG == 1 ? 0 : TA.d_map[d];
-            if constexpr (NG > 1) active_diag(gd, hp0, hp1, hq0, hq1);
-            // direction-dependent part of o
-            cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
-            for (int j = 0; j < n_term; ++j) {
-              if (j == act || CH.t[j].n_gdir <= 1) continue;
-              const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, d, nu);
-              const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, d, nu);
-              rp0 = rp0 * Jp.a; rp1 = rp1 * Jp.d;
-              rq0 = rq0 * Jq.a; rq1 = rq1 * Jq.d;
-            }
-            const cx<T> cp0 = hp0 * rp0, cp1 = hp1 * rp1;
-            const cx<T> cq0 = hq0 * rq0, cq1 = hq1 * rq1;
-            const m22<T> M = select_m(use, load_m22<S, T>(Mp, s * n_dir + d));
-            m22<T> B, Bc;
-            B.a = mulc(rp0 * M.a, cq0);
-            B.b = mulc(rp0 * M.b, cq1);
-            B.c = mulc(rp1 * M.c, cq0);
-            B.d = mulc(rp1 * M.d, cq1);
-            Bc.a = mulc(rq0, M.a * cp0);
-            Bc.b = mulc(rq0, M.c * cp1);
-            Bc.c = mulc(rq1, M.b * cp0);
-            Bc.d = mulc(rq1, M.d * cp1);
-            Vm.a = cfma(hp0, B.a, Vm.a);
-            Vm.b = cfma(hp0, B.b, Vm.b);
-            Vm.c = cfma(hp1, B.c, Vm.c);
-            Vm.d = cfma(hp1, B.d, Vm.d);
+          // One sample's model holds its directions side by side (four complex64
+          // directions fill one 128-byte line): read four directions at a time, so
+          // the line is used while it is cached rather than a quarter per direction
+          // iteration, with the chain evaluation between the quarters. The index is
+          // clamped, not branched on, so the loads are issued together. FP64
+          // products have no registers to spare for it, and with one row per
+          // lane two directions at a time keep a third wavefront per SIMD.
+          constexpr int MCH = sizeof(T) != 4 ? 1 : LANE_ROWS ? 2 : 4;
+          for (int d0 = 0; d0 < n_dir; d0 += MCH) {
+            m22<T> Mc[MCH];
 #pragma unroll
-            for (int g = 0; g < NG; ++g) {
-              const bool hit = (g == gd);
-              const bool h = (NG == 1) || hit;    // one gain direction: every d maps to 0
-              Bs[g] = msel(h, Bs[g] + B, Bs[g]);
-              Bsc[g] = msel(h, Bsc[g] + Bc, Bsc[g]);
-              gp0[g] = csel(h, hp0, gp0[g]);
-              gp1[g] = csel(h, hp1, gp1[g]);
-              gq0[g] = csel(h, hq0, gq0[g]);
-              gq1[g] = csel(h, hq1, gq1[g]);
+            for (int k = 0; k < MCH; ++k)
+              Mc[k] = load_m22<S, T>(Mp, s * n_dir + min(d0 + k, n_dir - 1));
+            for (int k = 0; k < MCH && d0 + k < n_dir; ++k) {
+              const int d = d0 + k;
+              const int gd = NG == 1 ? 0 : TA.d_map[d];
+              if constexpr (NG > 1) active_diag(gd, hp0, hp1, hq0, hq1);
+              // direction-dependent part of o
+              cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
+              for (int j = 0; j < n_term; ++j) {
+                if (j == act || CH.t[j].n_gdir <= 1) continue;
+                const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, d, nu);
+                const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, d, nu);
+                rp0 = rp0 * Jp.a; rp1 = rp1 * Jp.d;
+                rq0 = rq0 * Jq.a; rq1 = rq1 * Jq.d;
+              }
+              const cx<T> cp0 = hp0 * rp0, cp1 = hp1 * rp1;
+              const cx<T> cq0 = hq0 * rq0, cq1 = hq1 * rq1;
+              m22<T> Mk = Mc[0];
+#pragma unroll
+              for (int u = 1; u < MCH; ++u) Mk = msel(k == u, Mc[u], Mk);
+              const m22<T> M = select_m(use, Mk);
+              m22<T> B, Bc;
+              B.a = mulc(rp0 * M.a, cq0);
+              B.b = mulc(rp0 * M.b, cq1);
+              B.c = mulc(rp1 * M.c, cq0);
+              B.d = mulc(rp1 * M.d, cq1);
+              Bc.a = mulc(rq0, M.a * cp0);
+              Bc.b = mulc(rq0, M.c * cp1);
+              Bc.c = mulc(rq1, M.b * cp0);
+              Bc.d = mulc(rq1, M.d * cp1);
+              Vm.a = cfma(hp0, B.a, Vm.a);
+              Vm.b = cfma(hp0, B.b, Vm.b);
+              Vm.c = cfma(hp1, B.c, Vm.c);
+              Vm.d = cfma(hp1, B.d, Vm.d);
+#pragma unroll
+              for (int g = 0; g < NG; ++g) {
+                const bool hit = (g == gd);
+                const bool h = (NG == 1) || hit;    // one gain direction: every d maps to 0
+                Bs[g] = msel(h, Bs[g] + B, Bs[g]);
+                Bsc[g] = msel(h, Bsc[g] + Bc, Bsc[g]);
+                gp0[g] = csel(h, hp0, gp0[g]);
+                gp1[g] = csel(h, hp1, gp1[g]);
+                gq0[g] = csel(h, hq0, gq0[g]);
+                gq1[g] = csel(h, hq1, gq1[g]);
+              }
             }
           }
           const m22<T> R = D - Vm;
