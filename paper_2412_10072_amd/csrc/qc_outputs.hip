@@ -150,16 +150,28 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
         st<S, T>(Op, s, o);
       } else {
         m22<T> Vm = mzero<T>();
-        for (int d = 0; d < V.n_dir; ++d) {
-          if (!((L.dir_mask >> d) & 1u)) continue;
-          cx<T> cp0 = p0, cp1 = p1, cq0 = q0, cq1 = q1;
-          diag_part<T, true>(CH, V.n_ant, t, c, p, d, nu, cp0, cp1);
-          diag_part<T, true>(CH, V.n_ant, t, c, q, d, nu, cq0, cq1);
-          const m22<T> M = ld<S, T>(Mp, s * V.n_dir + d);
-          Vm.a = Vm.a + mulc(cp0 * M.a, cq0);
-          Vm.b = Vm.b + mulc(cp0 * M.b, cq1);
-          Vm.c = Vm.c + mulc(cp1 * M.c, cq0);
-          Vm.d = Vm.d + mulc(cp1 * M.d, cq1);
+        // A sample's model directions sit side by side (four complex64
+        // directions in one 128-byte line): read four at a time (clamped
+        // index, no branch) so that the line is not evicted and fetched again
+        // between the per-direction chain evaluations. One at a time in FP64.
+        constexpr int MCH = sizeof(T) == 4 ? 4 : 1;
+        for (int d0 = 0; d0 < V.n_dir; d0 += MCH) {
+          m22<T> Mc[MCH];
+#pragma unroll
+          for (int k = 0; k < MCH; ++k) Mc[k] = ld<S, T>(Mp, s * V.n_dir + min(d0 + k, V.n_dir - 1));
+#pragma unroll
+          for (int k = 0; k < MCH; ++k) {
+            const int d = d0 + k;
+            if (d >= V.n_dir || !((L.dir_mask >> d) & 1u)) continue;
+            cx<T> cp0 = p0, cp1 = p1, cq0 = q0, cq1 = q1;
+            diag_part<T, true>(CH, V.n_ant, t, c, p, d, nu, cp0, cp1);
+            diag_part<T, true>(CH, V.n_ant, t, c, q, d, nu, cq0, cq1);
+            const m22<T>& M = Mc[k];
+            Vm.a = Vm.a + mulc(cp0 * M.a, cq0);
+            Vm.b = Vm.b + mulc(cp0 * M.b, cq1);
+            Vm.c = Vm.c + mulc(cp1 * M.c, cq0);
+            Vm.d = Vm.d + mulc(cp1 * M.d, cq1);
+          }
         }
         if constexpr (MODE == 2) Vm = ld<S, T>(Dp, s) - Vm;
         st<S, T>(Op, s, Vm);
