@@ -1101,9 +1101,13 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           // the line is used while it is cached rather than a quarter per direction
           // iteration, with the chain evaluation between the quarters. The index is
           // clamped, not branched on, so the loads are issued together. FP64
-          // products have no registers to spare for it, and with one row per
-          // lane two directions at a time keep a third wavefront per SIMD.
-          constexpr int MCH = sizeof(T) != 4 ? 1 : LANE_ROWS ? 2 : 4;
+          // products have no registers to spare for it. With one row per lane
+          // two directions at a time keep a third wavefront per SIMD, except in
+          // the diagonal split pass, whose kernel is built for three wavefronts
+          // per SIMD with four.
+          constexpr int MCH = sizeof(T) != 4                                   ? 1
+                              : LANE_ROWS && !(PASS_ONLY && KIND == KIND_DIAG) ? 2
+                                                                               : 4;
           for (int d0 = 0; d0 < n_dir; d0 += MCH) {
             m22<T> Mc[MCH];
 #pragma unroll

@@ -85,8 +85,12 @@ __device__ __forceinline__ unsigned xcd_order(unsigned bid, unsigned n) {
 // the current gains and writes FP64 blocks; one workgroup per interval then
 // sums the parts in a fixed order and updates (split_update).  The host
 // repeats pass + update until no interval is active.
+// The diagonal-chain pass with one row per lane reads four model directions
+// at once; held to three wavefronts per SIMD it fits without spilling.
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
-__global__ void __launch_bounds__(512) k_split_pass(SolveLaunch L, int n_part, double* partials,
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(KIND == KIND_DIAG && CHM == 2 && RPS == 64 && sizeof(T) == 4 ? 3 : 1)))
+k_split_pass(SolveLaunch L, int n_part, double* partials,
                                                     const uint8_t* done) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
