@@ -102,12 +102,12 @@ typedef enum {
  *             into parts, FP64 sums per part, one host wait per iteration);
  *             convergence measures the step in beam widths at the top of the
  *             interval's band, |alpha Delta| nu_max / (beam_fwhm beam_freq).
- *             It depends on direction, so it may not sit left of the active
- *             term of a solve (see qc_solve_interval).  Not with QC_DAMP_LM
- *             or qc_solve_batch.
+ *             Not with QC_DAMP_LM or qc_solve_batch; it differs by direction,
+ *             so CORRECT and corrected weights refuse a chain holding it.
  * DELAY, PHASE, AMPLITUDE, DELAY_OFFSET and POINTING terms keep their
  * parameters in qc_term.params; the blocks of the first four are real 2x2
- * (one per hand, decoupled). */
+ * (one per hand, decoupled) unless the chain left of them needs full blocks
+ * (see qc_solve_interval). */
 
 typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAMP_AUTO = 3,
                QC_DAMP_LM = 4 } qc_damping;
@@ -237,10 +237,16 @@ typedef struct {
  * A block whose Cholesky pivot is <= 1e-12 of its largest diagonal entry (or
  * that has no data) gets Delta = 0 and gain_flags = 1.
  * The active term's gains/params are overwritten in place.
- * Limitation: every term left of the active one must be DIAGONAL or DELAY
- * with all its directions mapped to one gain direction (QC_E_UNSUPPORTED
- * otherwise; a POINTING term never qualifies).  An active POINTING term may
- * sit anywhere in its chain.
+ * Any term may sit left of the active one (eq. jonesfactor): the Jacobian
+ * block of antenna p is K = sum_d C<_{p,d} (x) (C>_{p,d} M_d C_{q,d}^H)^T over
+ * the directions sharing the gain (eq. g_derivative_dd / _di).  When that left
+ * product is diagonal and shared by every direction, or every term of the
+ * chain is diagonal (diagonal Jones matrices commute), the block splits by gain
+ * row (two 2x2 blocks for COMPLEX2X2, decoupled hands otherwise); else the
+ * solver forms the full block over all unknowns of the antenna (4x4 Hermitian
+ * for COMPLEX2X2, 2x2 for DIAGONAL, real 2x2 for DELAY / PHASE / AMPLITUDE,
+ * real 4x4 for DELAY_OFFSET, whose pivots are then each tested against their
+ * own diagonal entry), one row per wavefront step.
  */
 qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
                             int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats);
@@ -289,7 +295,8 @@ qc_status qc_delay_init(qc_ctx* ctx, const qc_vis* vis, qc_term* k_term, int32_t
  * samples and autocorrelations included:
  *   CORRUPT: out = sum_{d in mask} C_{p,d} M_d C_{q,d}^H
  *   CORRECT: out = C_p^-1 D C_q^-H  (direction 0 of a chain whose every term
- *            maps all directions to one gain; 0 where C_p or C_q is singular)
+ *            maps all directions to one gain and that holds no POINTING term,
+ *            QC_E_ARG otherwise; 0 where C_p or C_q is singular)
  * dir_mask: [n_dir] uint8 host array, NULL = all directions.
  * out: [n_row][n_chan][4] device array of the data dtype.  Arithmetic is in
  * the data precision (complex64 -> FP32, complex128 -> FP64).
@@ -327,7 +334,7 @@ qc_status qc_interp_term(qc_ctx* ctx, const qc_term* src, const double* t_src, c
  * order XX, XY, YX, YY, c the diagonal of the chain's Jones matrix (the
  * off-diagonal terms of a full 2x2 chain are left out); with one weight per
  * sample (n_wcorr = 1) the mean of the four factors.  The chain must be
- * direction independent (QC_E_ARG otherwise).  weight_out: device, the layout
+ * direction independent, without a POINTING term (QC_E_ARG otherwise).  weight_out: device, the layout
  * and type of vis->weight (may equal it).  Every (row, channel). */
 qc_status qc_corrected_weights(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                                void* weight_out, void* stream);
@@ -349,7 +356,7 @@ qc_status qc_robust_weights(qc_ctx* ctx, const qc_vis* vis, const void* resid, d
                             double* s2_out, void* stream);
 
 /* Outlier flags from residual visibilities by the median absolute deviation
- * (paper Section 4.6, "Additional Features": with a near-complete model the
+ * (paper Section 4.7, "Additional Features": with a near-complete model the
  * residuals are Gaussian and outliers are taken to be RFI).
  *   resid    : device [n_row][n_chan][4], same dtype as vis->data (the output
  *              of qc_residual); vis supplies weights, flags and antennas.
@@ -372,7 +379,7 @@ qc_status qc_mad_flag(qc_ctx* ctx, const qc_vis* vis, const void* resid, qc_mad_
 
 /*
  * Model visibilities predicted from a list of point components by a direct
- * Fourier sum (paper Section 4.6, "Additional Features": component models
+ * Fourier sum (paper Section 4.7, "Additional Features": component models
  * predicted on the fly with the DFT; the predicted visibility M of
  * eq. baselinemodel).  For every row r, channel nu and direction d:
  *   M[r][nu][d] = sum over the components c with dir[c] = d of

@@ -1,5 +1,5 @@
 """Outlier flagging of residual visibilities by the median absolute deviation
-(paper Section 4.6, "Additional Features": residuals of well-calibrated data
+(paper Section 4.7, "Additional Features": residuals of well-calibrated data
 with a near-complete model should be Gaussian, so outliers are taken to be
 RFI; the statistics are formed globally or per baseline).
 

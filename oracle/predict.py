@@ -1,5 +1,5 @@
 """Model visibilities predicted from a list of point components by a direct
-Fourier sum (paper Section 4.6, "Additional Features": component models
+Fourier sum (paper Section 4.7, "Additional Features": component models
 predicted on the fly with the DFT; the predicted visibility M_pq,s,d of
 eq. baselinemodel).
 

@@ -43,7 +43,7 @@ def build(verbose: bool = True) -> str:
     """Compile every kernel source and link libqc.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = min(len(srcs), max(1, (os.cpu_count() or 2) // 2), 8)
+    jobs = min(len(srcs), max(1, os.cpu_count() or 2), 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

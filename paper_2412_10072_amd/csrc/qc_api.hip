@@ -376,14 +376,6 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   if (st != QC_OK) return st;
   if (chain[active].type == QC_TERM_POINTING)
     return solve_pointing(ctx, vis, chain, n_term, active, opts, stats, s);
-  for (int j = 0; j < active; ++j) {
-    if (chain[j].type == QC_TERM_COMPLEX2X2)
-      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must be diagonal", j);
-    if (chain[j].type == QC_TERM_POINTING)
-      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term differs by direction (pointing)", j);
-    if (!dmap_constant(maps[j]))
-      return fail(ctx, QC_E_UNSUPPORTED, "term %d left of the active term must map all directions to one gain", j);
-  }
   SolveLaunch L;
   memset(&L, 0, sizeof L);
   fill_args(vis, chain, n_term, active, L.vis, L.chain);
@@ -392,6 +384,15 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   L.diag_chain = 1;
   for (int j = 0; j < n_term; ++j)
     if (chain[j].type == QC_TERM_COMPLEX2X2) L.diag_chain = 0;
+  // A chain of diagonal terms commutes, so its diagonal-chain evaluation takes
+  // any left factor (direction-dependent ones and pointing beams included).
+  // Otherwise a left factor that is not diagonal, or differs by direction,
+  // needs the full per-antenna blocks (eq. jonesfactor, eq. g_derivative_dd).
+  L.left_general = 0;
+  if (!L.diag_chain)
+    for (int j = 0; j < active; ++j)
+      if (chain[j].type == QC_TERM_COMPLEX2X2 || chain[j].type == QC_TERM_POINTING || !dmap_constant(maps[j]))
+        L.left_general = 1;
   qc_term& ta = chain[active];
   L.gains = reinterpret_cast<double2*>(ta.gains);
   L.params = ta.params;
@@ -448,8 +449,11 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   if (want_tab) HIP_TRY(ctx, grow(ctx->d_otab, ctx->otab_cap, chain_table_bytes(L)));
   SplitLaunch P;
   if (parts > 1) {
-    const int nv = ta.type == QC_TERM_DIAGONAL ? 6
-                 : ta.type == QC_TERM_COMPLEX2X2 ? 16 : (ta.type == QC_TERM_DELAY_OFFSET ? 10 : 4);
+    // values per block (qc_interval.h: KindInfo NV, or NV_FB for full blocks)
+    const int nv = L.left_general ? (ta.type == QC_TERM_DIAGONAL ? 8
+                                     : ta.type == QC_TERM_COMPLEX2X2 ? 24 : (ta.type == QC_TERM_DELAY_OFFSET ? 14 : 5))
+                                  : (ta.type == QC_TERM_DIAGONAL ? 6
+                                     : ta.type == QC_TERM_COMPLEX2X2 ? 16 : (ta.type == QC_TERM_DELAY_OFFSET ? 10 : 4));
     const int ng = ta.n_gdir == 1 ? 1 : 4;
     const size_t stride = (size_t)vis->n_ant * ng * nv + 1;
     HIP_TRY(ctx, grow(ctx->d_partials, ctx->partials_cap, stride * (size_t)n_int * parts));
@@ -720,7 +724,7 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
   if (st != QC_OK) return st;
   if (mode == 1 || mode == 3) {
     for (int j = 0; j < n_term; ++j)
-      if (!dmap_constant(maps[j]))
+      if (!dmap_constant(maps[j]) || chain[j].type == QC_TERM_POINTING)
         return fail(ctx, QC_E_ARG, "%s needs a direction-independent chain (term %d)",
                     mode == 1 ? "CORRECT" : "corrected weights", j);
   }

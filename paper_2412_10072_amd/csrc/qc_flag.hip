@@ -1,5 +1,5 @@
 // Outlier flagging of residual visibilities by the median absolute deviation
-// (paper Section 4.6, "Additional Features"), globally or per baseline.
+// (paper Section 4.7, "Additional Features"), globally or per baseline.
 //
 // Per unflagged cross-correlation sample the statistic is its chi^2
 // contribution s = sum_k w_k |R_k|^2, in the precision of the residual and

@@ -21,8 +21,9 @@ enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 
 // KIND_DELAY as a kernel template argument stands for every real-parameterised
 // diagonal term (delay, phase-only, amplitude-only); the term's own kind
 // (TermArgs::kind) selects the Jones form at run time.
-// per-sample chain evaluation of the solver kernels
-enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2 };
+// per-sample chain evaluation of the solver kernels (CHAIN_LEFT: any chain,
+// with the full per-antenna blocks that a general left factor needs)
+enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2, CHAIN_LEFT = 3 };
 
 struct TermArgs {
   int kind, n_gt, n_gf, n_gdir;   // pointing terms: n_gdir = the model directions (they differ by direction)
@@ -280,6 +281,7 @@ struct SolveLaunch {
   int vis_is_c128;            // storage precision of data/model/weight
   int prec_mixed;             // compute precision
   int diag_chain;             // every chain term is diagonal or a delay
+  int left_general;           // the chain left of the active term is not diagonal or differs by direction
   // active term, in/out
   double2* gains;
   double* params;

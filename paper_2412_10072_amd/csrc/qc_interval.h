@@ -12,13 +12,24 @@
 namespace qc {
 
 
+// Values per block.  NV: the block form used when the chain left of the
+// active term is diagonal and shared by every direction, so that the block
+// splits by gain row (diagonal: two real entries; full-Jones: two 2x2
+// Hermitian blocks; parameters: decoupled hands).  NV_FB: the full block over
+// every unknown of the antenna, for any left factor (upper triangle of the
+// Hermitian / symmetric matrix, row by row after its diagonal, then the
+// right-hand sides).
 template <int KIND> struct KindInfo;
-template <> struct KindInfo<KIND_DIAG>  { static constexpr int NV = 6;  };
-template <> struct KindInfo<KIND_C2X2>  { static constexpr int NV = 16; };
-template <> struct KindInfo<KIND_DELAY> { static constexpr int NV = 4;  };
+template <> struct KindInfo<KIND_DIAG>  { static constexpr int NV = 6;  static constexpr int NV_FB = 8;  };
+template <> struct KindInfo<KIND_C2X2>  { static constexpr int NV = 16; static constexpr int NV_FB = 24; };
+template <> struct KindInfo<KIND_DELAY> { static constexpr int NV = 4;  static constexpr int NV_FB = 5;  };
 // delay and offset: per hand the three entries of the real 2x2 block of
-// (phi0, tau) and its two right-hand sides
-template <> struct KindInfo<KIND_DELOFF> { static constexpr int NV = 10; };
+// (phi0, tau) and its two right-hand sides; full block: the real 4x4 over
+// (phi0_X, tau_X, phi0_Y, tau_Y)
+template <> struct KindInfo<KIND_DELOFF> { static constexpr int NV = 10; static constexpr int NV_FB = 14; };
+
+template <int KIND, bool FB>
+__host__ __device__ constexpr int nv_of() { return FB ? KindInfo<KIND>::NV_FB : KindInfo<KIND>::NV; }
 
 // kinds whose unknowns are real parameters held in the term's params array
 __host__ __device__ constexpr bool is_param(int kind) { return kind == KIND_DELAY || kind == KIND_DELOFF; }
@@ -393,6 +404,129 @@ __device__ __forceinline__ T chisq_acc(const m22<T>& WR, const m22<T>& R, T acc)
 }
 
 // ---------------------------------------------------------------------------
+// per-sample full-block contributions for one antenna orientation, for any
+// chain left of the active term (eq. jonesfactor with eq. g_derivative_dd /
+// _di: the left factor need not be diagonal nor shared by the directions).
+//
+// E[2a + i] (a 2x2 indexed [k][b]) holds sum_d A_d[a,i] B_d[k,b] over the
+// directions d that share the gain, A_d the product of the terms left of the
+// active one and B_d the right factor C>_p M_d C_q^H, so that the derivative
+// block is K[(a,b),(i,k)] = E[2a+i][k][b].  Rows r = 2a + b of K carry the
+// weight w_r and WR_r = w_r R_r.  The unknown columns:
+//   COMPLEX2X2: u = 2i + k (all four gain entries); DIAGONAL: (0,0), (1,1);
+//   DELAY / PHASE / AMPLITUDE: the two diagonal columns times dg/du
+//     (i tpn g, tpn = 2 pi nu for delays and 1 for phases; 1 for amplitudes);
+//   DELAY_OFFSET: column (0,0) times i g_0 and i tpn g_0, then (1,1) times
+//     i g_1 and i tpn g_1 (the order phi0_X, tau_X, phi0_Y, tau_Y).
+// acc receives the upper triangle of H = sum_r w_r conj(K_r.)^T K_r. (its
+// diagonal, then the entries u < u' row by row, as (re, im) for the complex
+// kinds) and the right-hand sides sum_r conj(K_ru) WR_r; the real-parameter
+// kinds keep real parts only (their common factor 2 cancels in the update).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ cx<T> kelem(const m22<T>* E, int r, int i, int k) {
+  const m22<T>& m = E[2 * (r >> 1) + i];
+  const int b = r & 1;
+  return k == 0 ? (b == 0 ? m.a : m.b) : (b == 0 ? m.c : m.d);
+}
+
+template <int KIND>
+__host__ __device__ constexpr int fb_unknowns() { return (KIND == KIND_C2X2 || KIND == KIND_DELOFF) ? 4 : 2; }
+template <int KIND>
+__host__ __device__ constexpr bool fb_complex() { return KIND == KIND_C2X2 || KIND == KIND_DIAG; }
+
+template <int KIND, typename T>
+__device__ __forceinline__ void contrib_fb(const m22<T>* E, const m22<T>& WR, T w0, T w1, T w2, T w3, cx<T> g0,
+                                           cx<T> g1, T tpn, T* acc, bool amp) {
+  constexpr int NU = fb_unknowns<KIND>();
+  constexpr bool CPLX = fb_complex<KIND>();
+  const T w[4] = {w0, w1, w2, w3};
+  const cx<T> wr[4] = {WR.a, WR.b, WR.c, WR.d};
+  const cx<T> ig0 = cmake<T>(-g0.im, g0.re), ig1 = cmake<T>(-g1.im, g1.re);
+  cx<T> col[NU][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if constexpr (KIND == KIND_C2X2) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) col[u][r] = kelem(E, r, u >> 1, u & 1);
+    } else {
+      const cx<T> c0 = kelem(E, r, 0, 0), c1 = kelem(E, r, 1, 1);
+      if constexpr (KIND == KIND_DIAG) {
+        col[0][r] = c0;
+        col[1][r] = c1;
+      } else if constexpr (KIND == KIND_DELOFF) {
+        col[0][r] = c0 * ig0;
+        col[1][r] = scale(col[0][r], tpn);
+        col[2][r] = c1 * ig1;
+        col[3][r] = scale(col[2][r], tpn);
+      } else {
+        col[0][r] = amp ? c0 : scale(c0 * ig0, tpn);
+        col[1][r] = amp ? c1 : scale(c1 * ig1, tpn);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    T h = acc[u];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h = fma(w[r], norm2(col[u][r]), h);
+    acc[u] = h;
+  }
+  int o = NU;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+#pragma unroll
+    for (int v = u + 1; v < NU; ++v) {
+      if constexpr (CPLX) {
+        cx<T> x = cmake<T>(acc[o], acc[o + 1]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x = cfma_jc(col[u][r], scale(col[v][r], w[r]), x);
+        acc[o] = x.re;
+        acc[o + 1] = x.im;
+        o += 2;
+      } else {
+        T x = acc[o];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          x = fma(w[r], fma(col[u][r].re, col[v][r].re, col[u][r].im * col[v][r].im), x);
+        acc[o] = x;
+        o += 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    if constexpr (CPLX) {
+      cx<T> x = cmake<T>(acc[o], acc[o + 1]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x = cfma_jc(col[u][r], wr[r], x);
+      acc[o] = x.re;
+      acc[o + 1] = x.im;
+      o += 2;
+    } else {
+      T x = acc[o];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x = fma(col[u][r].re, wr[r].re, fma(col[u][r].im, wr[r].im, x));
+      acc[o] = x;
+      o += 1;
+    }
+  }
+}
+
+// E[2a + i] += A[a,i] B (one direction's share of the full-block factors)
+template <typename T>
+__device__ __forceinline__ void efactor_add(m22<T>* E, const m22<T>& A, const m22<T>& B) {
+  const cx<T> a[4] = {A.a, A.b, A.c, A.d};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    E[j].a = cfma(a[j], B.a, E[j].a);
+    E[j].b = cfma(a[j], B.b, E[j].b);
+    E[j].c = cfma(a[j], B.c, E[j].c);
+    E[j].d = cfma(a[j], B.d, E[j].d);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // sample loads
 // ---------------------------------------------------------------------------
 template <typename S, typename T>
@@ -488,6 +622,93 @@ __device__ __forceinline__ bool chol_diag(double h, c64d b, double dmax, c64d& x
   return true;
 }
 
+// Full-block solve (H + mu I) x = b by Cholesky H = L L^H, the block given as
+// contrib_fb stores it (N unknowns; complex or real).  Singular when the
+// block's largest diagonal entry is not positive and finite, or a pivot is
+// <= PIVOT_REL times that entry (scaled: times the pivot's own diagonal
+// entry).  b receives the right-hand sides.
+template <int N, bool CPLX>
+__device__ __forceinline__ bool chol_fb(const double* h, double mu, bool scaled, c64d* x, c64d* b) {
+  c64d H[N][N];
+  int o = N;
+  double dmax = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    H[i][i] = {h[i] + mu, 0.0};
+    dmax = i == 0 ? H[0][0].re : fmax(dmax, H[i][i].re);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = i + 1; j < N; ++j) {
+      if constexpr (CPLX) {
+        H[i][j] = {h[o], h[o + 1]};
+        o += 2;
+      } else {
+        H[i][j] = {h[o], 0.0};
+        o += 1;
+      }
+      H[j][i] = {H[i][j].re, -H[i][j].im};
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if constexpr (CPLX) {
+      b[i] = {h[o], h[o + 1]};
+      o += 2;
+    } else {
+      b[i] = {h[o], 0.0};
+      o += 1;
+    }
+  }
+  if (!(isfinite(dmax) && dmax > 0.0)) return false;
+  c64d L[N][N];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double sj = H[j][j].re;
+#pragma unroll
+    for (int m = 0; m < j; ++m) sj -= L[j][m].re * L[j][m].re + L[j][m].im * L[j][m].im;
+    const double ref = scaled ? H[j][j].re : dmax;
+    ok = ok && (sj > PIVOT_REL * ref);
+    const double ljj = ok ? sqrt(sj) : 1.0;
+    L[j][j] = {ljj, 0.0};
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      c64d z = H[i][j];
+#pragma unroll
+      for (int m = 0; m < j; ++m) {   // z -= L[i][m] conj(L[j][m])
+        z.re -= L[i][m].re * L[j][m].re + L[i][m].im * L[j][m].im;
+        z.im -= L[i][m].im * L[j][m].re - L[i][m].re * L[j][m].im;
+      }
+      L[i][j] = {z.re / ljj, z.im / ljj};
+    }
+  }
+  if (!ok) return false;
+  c64d y[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    c64d z = b[i];
+#pragma unroll
+    for (int m = 0; m < i; ++m) {     // z -= L[i][m] y[m]
+      z.re -= L[i][m].re * y[m].re - L[i][m].im * y[m].im;
+      z.im -= L[i][m].re * y[m].im + L[i][m].im * y[m].re;
+    }
+    y[i] = {z.re / L[i][i].re, z.im / L[i][i].re};
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    c64d z = y[i];
+#pragma unroll
+    for (int m = i + 1; m < N; ++m) {  // z -= conj(L[m][i]) x[m]
+      z.re -= L[m][i].re * x[m].re + L[m][i].im * x[m].im;
+      z.im -= L[m][i].re * x[m].im - L[m][i].im * x[m].re;
+    }
+    x[i] = {z.re / L[i][i].re, z.im / L[i][i].re};
+  }
+  return true;
+}
+
 __device__ __forceinline__ double step_length(int damping, int k) {
   if (damping == 0 || damping == DAMP_LM) return 1.0;
   if (damping == 1) return 0.5;
@@ -508,9 +729,9 @@ __device__ __forceinline__ void param_diag(const double2* g, int pk, double nu, 
 
 // Levenberg-Marquardt: the largest finite diagonal entry of the interval's
 // blocks (the scale of the first damping); uses red[16 .. 16 + nw], red[31]
-template <int KIND, int NG, typename Sum>
+template <int KIND, int NG, bool FB = false, typename Sum>
 __device__ __forceinline__ double block_diag_max(const Sum& sum, double* red, int n_ant, int n_gdir) {
-  constexpr int NV = KindInfo<KIND>::NV;
+  constexpr int NV = nv_of<KIND, FB>();
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double m = 0.0;
@@ -520,7 +741,8 @@ __device__ __forceinline__ double block_diag_max(const Sum& sum, double* red, in
     const int nd = KIND == KIND_C2X2 ? 4 : 2;
 #pragma unroll
     for (int k = 0; k < nd; ++k) {
-      const double d = sum(base + (KIND == KIND_C2X2 ? (k < 2 ? k : k + 2) : k));
+      // full blocks keep their diagonal first
+      const double d = sum(base + ((KIND == KIND_C2X2 && !FB) ? (k < 2 ? k : k + 2) : k));
       if (isfinite(d)) m = fmax(m, d);
     }
   }
@@ -571,10 +793,10 @@ struct Job {
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
 // lane_rows: steps of one row per lane, which add a claim word per antenna
 // and wave.
-template <int KIND, typename T, int NG>
+template <int KIND, typename T, int NG, bool FB = false>
 __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool lane_rows = false) {
   const size_t n_slots = (size_t)n_ant * NG;
-  const size_t nv = KindInfo<KIND>::NV;
+  const size_t nv = nv_of<KIND, FB>();
   // the FP64 block totals are an LDS array only in the split schedule's
   // update kernel (nw == 0); the streaming kernels sum their wave slots
   // (the split schedule keeps the divergence state in device memory instead)
@@ -597,7 +819,8 @@ __host__ __device__ constexpr size_t interval_lds_bytes(int n_ant, int nw, bool 
 // predicted chi^2 decrease sum Re(Delta^H b) + mu |Delta|^2 (uses red[16 ..]).
 // `sum(i)` returns the FP64 total of block value i (slot * NV + k); the
 // block values are read before the first barrier inside.
-template <int KIND, typename T, int NG, typename Sum>
+// FB: the blocks are full blocks (contrib_fb), solved by chol_fb.
+template <int KIND, typename T, int NG, bool FB = false, typename Sum>
 __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<T>* gc, int* gfl, double* dv,
                                                 double* red, int* ctl, int n_ant, int n_gdir, int k_upd,
                                                 int damping, double nu_max, double tol, int* err,
@@ -606,7 +829,7 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
   // real-parameter terms: a relative test for amplitudes, the largest phase
   // change for delays (at the band edge) and phases
   const bool rel_test = !is_param(KIND) || pk == KIND_AMP;
-  constexpr int NV = KindInfo<KIND>::NV;
+  constexpr int NV = nv_of<KIND, FB>();
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -626,7 +849,56 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
     if (!finite) atomicOr(err, ERR_NONFINITE);
     double bsq = 0.0;                 // squared 2-norm of the block's applied step
     double bmax = 0.0;                // delays and phases: the largest phase change
-    if constexpr (KIND == KIND_C2X2) {
+    if constexpr (FB) {
+      constexpr int NU = fb_unknowns<KIND>();
+      constexpr bool CPLX = fb_complex<KIND>();
+      constexpr bool SCALED = KIND == KIND_DELOFF;
+      c64d dx[NU], bb[NU];
+      ok = ok && chol_fb<NU, CPLX>(h, 0.0, SCALED, dx, bb);
+      if (ok && lm) {
+        ok = chol_fb<NU, CPLX>(h, mu, SCALED, dx, bb);
+        if (ok) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u)
+            prd += dx[u].re * bb[u].re + dx[u].im * bb[u].im + mu * (dx[u].re * dx[u].re + dx[u].im * dx[u].im);
+        }
+      }
+      if (ok) {
+        double2* g = gm + slot * 4;
+        if constexpr (KIND == KIND_C2X2 || KIND == KIND_DIAG) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const int e = KIND == KIND_C2X2 ? u : (u ? 3 : 0);
+            const double sr = alpha * dx[u].re, si = alpha * dx[u].im;
+            const double2 xn = make_double2(g[e].x + sr, g[e].y + si);
+            g[e] = xn;
+            gc[slot * 4 + e] = cmake<T>((T)xn.x, (T)xn.y);
+            num += sr * sr + si * si;
+            den += xn.x * xn.x + xn.y * xn.y;
+            bsq += sr * sr + si * si;
+          }
+        } else if constexpr (KIND == KIND_DELOFF) {
+          const double d0 = alpha * dx[0].re, d1 = alpha * dx[1].re, d2 = alpha * dx[2].re, d3 = alpha * dx[3].re;
+          g[0] = make_double2(g[0].x + d0, g[0].y + d1);
+          g[1] = make_double2(g[1].x + d2, g[1].y + d3);
+          const double scale = TWO_PI * nu_max;
+          bmax = fmax(fabs(d0) + scale * fabs(d1), fabs(d2) + scale * fabs(d3));
+          num = fmax(num, bmax);
+        } else {
+          const double d0 = alpha * dx[0].re, d1 = alpha * dx[1].re;
+          g[0] = make_double2(g[0].x + d0, g[0].y + d1);
+          if (pk == KIND_AMP) {
+            num += d0 * d0 + d1 * d1;
+            den += g[0].x * g[0].x + g[0].y * g[0].y;
+            bsq = d0 * d0 + d1 * d1;
+          } else {
+            const double scale = pk == KIND_DELAY ? TWO_PI * nu_max : 1.0;
+            bmax = scale * fmax(fabs(d0), fabs(d1));
+            num = fmax(num, bmax);
+          }
+        }
+      }
+    } else if constexpr (KIND == KIND_C2X2) {
       const double dmax = fmax(fmax(h[0], h[1]), fmax(h[4], h[5]));
       c64d x00 = {0, 0}, x01 = {0, 0}, x10 = {0, 0}, x11 = {0, 0};
       ok = ok && isfinite(dmax) && dmax > 0.0;
@@ -814,11 +1086,16 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
   constexpr bool DIAGC = (CHM == CHAIN_DIAG);
+  constexpr bool FB = (CHM == CHAIN_LEFT);   // full blocks (any left factor)
   static_assert(!DIAGC || KIND != KIND_C2X2, "a diagonal chain has no full-Jones term");
+  static_assert(!FB || RPS == 1, "the full-block kernel takes one row per wavefront step");
   constexpr bool KAHAN = (sizeof(T) == 4);
-  constexpr int NV = KindInfo<KIND>::NV;
+  constexpr int NV = nv_of<KIND, FB>();
   constexpr int NVG = NV * NG;
-  constexpr int NVP = pow2ceil(NVG);
+  // full blocks with several gain directions are flushed per gain direction
+  // as they are formed, so the register sums hold one direction's values
+  constexpr bool FB_PER_G = FB && NG > 1;
+  constexpr int NVP = pow2ceil(FB_PER_G ? NV : NVG);
   constexpr int LPR = 64 / RPS;              // lanes per row
   constexpr bool LANE_ROWS = (LPR == 1);     // one row per lane: flush by lane_flush
   constexpr bool PACC = (NG == 1) && !LANE_ROWS;  // keep antenna-p sums in registers over a p-run
@@ -1169,6 +1446,72 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
                                     pk_amp);
           }
           chi = chisq_acc(WR, R, chi);
+        } else if constexpr (FB) {
+          // Any chain, with the full blocks a general left factor needs: a
+          // first sweep over the directions forms the model and the residual;
+          // then per gain direction and orientation a sweep sums
+          // E[2a+i] = sum_d A_d[a,i] B_d over the directions mapped to it
+          // (A_d the left factor, B_d the right factor of the orientation),
+          // whose block contrib_fb adds.  Each sweep evaluates the chain again.
+          const ChainArgs& CH = *J.CH;
+          const int act = CH.active;
+          const int n_term = CH.n_term;
+          auto act_jones = [&](int x, int gd) -> m22<T> {
+            m22<T> G;
+            if constexpr (is_param(KIND)) {
+              G = mzero<T>();
+              param_diag<KIND, T>(gm + (x * NG + gd) * 4, pk, nu, G.a, G.d);
+            } else {
+              const cx<T>* gx = gc + (x * NG + gd) * 4;
+              G = {gx[0], gx[1], gx[2], gx[3]};
+              if constexpr (KIND == KIND_DIAG) G.b = G.c = czero<T>();
+            }
+            return G;
+          };
+          auto left = [&](int x, int d) { return chain_range<T>(CH, n_ant, 0, act, t, cc, x, d, nu); };
+          auto right = [&](int x, int d) { return chain_range<T>(CH, n_ant, act + 1, n_term, t, cc, x, d, nu); };
+          auto full = [&](int x, int d, int gd) { return mmul(mmul(left(x, d), act_jones(x, gd)), right(x, d)); };
+          m22<T> Vm = mzero<T>();
+          for (int d = 0; d < n_dir; ++d) {
+            const int gd = NG == 1 ? 0 : TA.d_map[d];
+            const m22<T> M = select_m(use, load_m22<S, T>(Mp, s * n_dir + d));
+            Vm = Vm + mmul_h(mmul(full(p, d, gd), M), full(q, d, gd));
+          }
+          const m22<T> R = D - Vm;
+          const m22<T> WR = wmul(R, w0, w1, w2, w3);
+          chi = chisq_acc(WR, R, chi);
+          for (int g = 0; g < n_gdir; ++g) {
+            // one orientation: antenna p (Q false) or, through the conjugate
+            // baseline, antenna q (D^H, M^H, weights permuted by P)
+            auto side = [&](auto QT) {
+              constexpr bool Q = decltype(QT)::value;
+              const int x = Q ? q : p, y = Q ? p : q;
+              m22<T> E[4] = {mzero<T>(), mzero<T>(), mzero<T>(), mzero<T>()};
+              for (int d = 0; d < n_dir; ++d) {
+                const int gd = NG == 1 ? 0 : TA.d_map[d];
+                if (gd != g) continue;
+                const m22<T> M = select_m(use, load_m22<S, T>(Mp, s * n_dir + d));
+                const m22<T> Bd = mmul_h(mmul(right(x, d), Q ? herm(M) : M), full(y, d, gd));
+                efactor_add(E, left(x, d), Bd);
+              }
+              const m22<T> Gx = act_jones(x, g);
+              if constexpr (FB_PER_G) {
+                A tmp[NVP];
+#pragma unroll
+                for (int k = 0; k < NVP; ++k) tmp[k] = A(0);
+                contrib_fb<KIND, T>(E, Q ? herm(WR) : WR, w0, Q ? w2 : w1, Q ? w1 : w2, w3, Gx.a, Gx.d, tpn, tmp,
+                                    pk_amp);
+                const unsigned off = (unsigned)(sizeof(A) * (size_t)(x * NG + g) * NV);
+                wave_flush<NVP, NV, KAHAN, LPR>(tmp, lane, my_s_off + off, my_c_off + off, row_ok);
+              } else if constexpr (Q) {
+                contrib_fb<KIND, T>(E, herm(WR), w0, w2, w1, w3, Gx.a, Gx.d, tpn, qacc, pk_amp);
+              } else {
+                contrib_fb<KIND, T>(E, WR, w0, w1, w2, w3, Gx.a, Gx.d, tpn, PACC ? pacc : prow, pk_amp);
+              }
+            };
+            side(std::false_type{});
+            side(std::true_type{});
+          }
         } else {
           const ChainArgs& CH = *J.CH;
           const int act = CH.active;
@@ -1244,7 +1587,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           chi = chisq_acc(WR, R, chi);
         }
       }
-      if constexpr (LANE_ROWS) {
+      if constexpr (FB_PER_G) {
+        // flushed per gain direction above
+      } else if constexpr (LANE_ROWS) {
         lane_flush<NVG, KAHAN, false>(qacc, lane, q, my_s_off, my_c_off, ANT_BYTES, claim, row_ok);
         lane_flush<NVG, KAHAN, true>(prow, lane, p, my_s_off, my_c_off, ANT_BYTES, claim, row_ok);
       } else {
@@ -1333,15 +1678,15 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       __syncthreads();
       if (iters >= J.max_iter) break;
       if (red[24] < 0.0) {
-        const double mu0 = LM_TAU * block_diag_max<KIND, NG>(slot_sum, red, n_ant, n_gdir);
+        const double mu0 = LM_TAU * block_diag_max<KIND, NG, FB>(slot_sum, red, n_ant, n_gdir);
         if (threadIdx.x == 0) red[24] = mu0;
         __syncthreads();
       }
       const double mu = red[24];
       const int k_upd = iters + 1;
       double pred = 0.0;
-      const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir, k_upd,
-                                                     J.damping, nu_max, J.tol, J.err, pk, mu, &pred);
+      const bool conv = update_and_test<KIND, T, NG, FB>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir,
+                                                         k_upd, J.damping, nu_max, J.tol, J.err, pk, mu, &pred);
       if (threadIdx.x == 0) {
         red[27] = pred;
         red[28] = 1.0;
@@ -1355,8 +1700,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
     }
     if (it >= J.max_iter) break;
     const int k_upd = it + 1;
-    const bool conv = update_and_test<KIND, T, NG>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir, k_upd,
-                                                   J.damping, nu_max, J.tol, J.err, pk);
+    const bool conv = update_and_test<KIND, T, NG, FB>(slot_sum, gm, gc, gfl, dv, red, ctl, n_ant, n_gdir, k_upd,
+                                                       J.damping, nu_max, J.tol, J.err, pk);
     iters = k_upd;
     if (conv) {
       converged = 1;
@@ -1399,9 +1744,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 // Sums the interval's n_part partial blocks in a fixed order, then does what
 // the fused loop does after a pass: chi^2 bookkeeping, the FP64 block solves,
 // the damped update of the gains in device memory, the convergence test.
-template <int KIND, typename T, int NG>
+template <int KIND, typename T, int NG, bool FB = false>
 __device__ __forceinline__ void split_update(const Job& J, const double* partials, int n_part, const SplitState& St) {
-  constexpr int NV = KindInfo<KIND>::NV;
+  constexpr int NV = nv_of<KIND, FB>();
   const VisArgs& V = *J.V;
   const TermArgs& TA = *J.TA;
   const int n_ant = V.n_ant;
@@ -1465,8 +1810,8 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
   } else {
     const int k_upd = pass + 1;
     double* dv = St.dv + (size_t)interval * n_slots * 2;
-    conv = update_and_test<KIND, T, NG>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, dv, red, ctl,
-                                        n_ant, n_gdir, k_upd, J.damping, nu_max, J.tol, J.err, J.TA->kind);
+    conv = update_and_test<KIND, T, NG, FB>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, dv, red,
+                                            ctl, n_ant, n_gdir, k_upd, J.damping, nu_max, J.tol, J.err, J.TA->kind);
     finish = conv || k_upd >= J.max_iter;
     for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
       const int ant = i / n_gdir, gd = i - ant * n_gdir;
@@ -1490,6 +1835,7 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
     St.passes[interval] = pass + 1;
     if (J.iters) J.iters[interval] = iters;
     if (J.converged) J.converged[interval] = conv ? 1 : 0;
+    if (J.restarted) J.restarted[interval] = 0;
     if (finish) {
       St.done[interval] = 1;
       atomicSub(St.n_active, 1);

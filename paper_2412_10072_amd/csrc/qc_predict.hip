@@ -1,5 +1,5 @@
 // Model visibilities predicted from point components by a direct Fourier sum
-// (paper Section 4.6, "Additional Features": component models predicted on
+// (paper Section 4.7, "Additional Features": component models predicted on
 // the fly with the DFT; the predicted visibility M of eq. baselinemodel).
 //
 // M[r][nu][d] = sum_{c in d} B_c (nu / nu0_c)^alpha_c

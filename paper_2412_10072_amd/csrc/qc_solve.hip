@@ -1,175 +1,15 @@
-// Fused per-interval AllJones Gauss-Newton solver for gfx950: one workgroup
-// per solution interval of the active chain term (grid = intervals).
-//
-// Each workgroup runs the paper's Algorithm 1 on its interval to convergence
-// without returning to the host (the loop itself is solve_interval in
-// qc_interval.h):
-//
-//   repeat
-//     stream every (row, channel) sample of the interval from HBM once,
-//     form the corrupted model and residual in registers (eq. baselinemodel,
-//     eq. baselineresidual), form the per-antenna JHJ / JHr contributions of
-//     the sample for antenna p and, through the conjugate baseline
-//     v_qp = P conj(v_pq), for antenna q (eq. jhj_entry_simplified,
-//     eq. jhr_entry_simplified; delay terms: eq. jhj_case2, eq. jhwr_case2),
-//     and reduce them into per-wave LDS slots;
-//     combine the wave slots in a fixed order, solve every per-antenna block
-//     in FP64 (eq. update), apply the damped step, test convergence
-//   until converged or max_iter updates.
-//
-// Lanes map to consecutive channels of a row (the innermost, contiguous
-// dimension), so every load of a wavefront is a contiguous segment.  Rows are
-// time-major and p-major within a time, so the antenna-p contributions stay
-// in registers for the length of a p-run; the antenna-q contributions are
-// reduced across the wavefront every row with a reduce-scatter (each lane
-// ends holding one summed value) and added to the wave's private LDS slot
-// with a compensated (Kahan) sum.  No atomics are used, so the result is
-// bitwise reproducible.
-//
-// Precision: T = float (MIXED: complex64 products and residuals, FP32 sums
-// with compensation) or double (FP64 everywhere).  The block solve, the
-// update and the convergence test are FP64 in both.
+// The solve launch of libqc: the fixed-factor table of diagonal chains and
+// the dispatch of a solve to the kernels of its term kind and precision
+// (qc_solve_kernels.h, instantiated in the qc_solve_k*.hip units).
 
 #include "qc_interval.h"
 
 namespace qc {
+
+template <int KIND, typename S, typename T>
+hipError_t launch_solve_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out);
+
 namespace {
-
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false>
-__global__ void __launch_bounds__(512) k_solve_fused(SolveLaunch L) {
-  const TermArgs& TA = L.chain.t[L.chain.active];
-  const int n_gf = TA.n_gf;
-  const int gt = blockIdx.x / n_gf;
-  const int gf = blockIdx.x - gt * n_gf;
-  Job J;
-  J.V = &L.vis;
-  J.CH = &L.chain;
-  J.TA = &TA;
-  J.gains = L.gains;
-  J.params = L.params;
-  J.gflags = L.gflags;
-  J.iters = L.iters;
-  J.converged = L.converged;
-  J.chisq_first = L.chisq_first;
-  J.chisq_last = L.chisq_last;
-  J.gt = gt;
-  J.gf = gf;
-  J.n_gf = n_gf;
-  J.r_lo = L.row_lo[gt];
-  J.r_hi = L.row_hi[gt];
-  J.c_lo = L.chan_lo[gf];
-  J.c_hi = L.chan_hi[gf];
-  J.tol = L.tol;
-  J.max_iter = L.max_iter;
-  J.damping = L.damping;
-  J.err = L.err;
-  J.chisq_ref = L.chisq_ref;
-  J.restarted = L.restarted;
-  J.otab = L.otab;
-  solve_interval<KIND, S, T, CHM, NG, RPS, false, LMT>(J);
-}
-
-// Workgroups go to the 8 XCDs round-robin by block index.  This maps block
-// indices to logical indices so that each XCD receives one contiguous run of
-// them (a bijection of [0, n)); workgroups sharing an XCD's L2 then work on
-// neighbouring logical items at the same time.
-__device__ __forceinline__ unsigned xcd_order(unsigned bid, unsigned n) {
-  constexpr unsigned X = 8;
-  const unsigned per = n / X, rem = n % X;
-  const unsigned x = bid % X, k = bid / X;
-  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
-}
-
-// Split schedule for intervals too large for one workgroup: every interval's
-// rows are cut into n_part parts; one workgroup per part streams its rows at
-// the current gains and writes FP64 blocks; one workgroup per interval then
-// sums the parts in a fixed order and updates (split_update).  The host
-// repeats pass + update until no interval is active.
-// The diagonal-chain pass with one row per lane reads four model directions
-// at once; held to three wavefronts per SIMD it fits without spilling.
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
-__global__ void __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu(KIND == KIND_DIAG && CHM == 2 && RPS == 64 && sizeof(T) == 4 ? 3 : 1)))
-k_split_pass(SolveLaunch L, int n_part, double* partials,
-                                                    const uint8_t* done) {
-  const TermArgs& TA = L.chain.t[L.chain.active];
-  const int n_gf = TA.n_gf;
-  const int n_int = TA.n_gt * n_gf;
-  // (part, interval) pairs, interval fastest, in XCD-contiguous runs
-  const unsigned lid = xcd_order(blockIdx.x, gridDim.x);
-  const int part = (int)(lid / (unsigned)n_int);
-  const int interval = (int)(lid - (unsigned)part * n_int);
-  if (done[interval]) return;
-  const int gt = interval / n_gf;
-  const int gf = interval - gt * n_gf;
-  const long long lo = L.row_lo[gt], n = L.row_hi[gt] - lo;
-  const size_t stride = (size_t)L.vis.n_ant * NG * KindInfo<KIND>::NV + 1;
-  Job J;
-  J.V = &L.vis;
-  J.CH = &L.chain;
-  J.TA = &TA;
-  J.gains = L.gains;
-  J.params = L.params;
-  J.gflags = nullptr;
-  J.iters = nullptr;
-  J.converged = nullptr;
-  J.chisq_first = nullptr;
-  J.chisq_last = nullptr;
-  J.gt = gt;
-  J.gf = gf;
-  J.n_gf = n_gf;
-  J.r_lo = lo + (n * part) / n_part;
-  J.r_hi = lo + (n * (part + 1)) / n_part;
-  J.c_lo = L.chan_lo[gf];
-  J.c_hi = L.chan_hi[gf];
-  J.tol = L.tol;
-  J.max_iter = 1;
-  J.damping = L.damping;
-  J.err = L.err;
-  J.chisq_ref = nullptr;
-  J.restarted = nullptr;
-  J.partial = partials + ((size_t)interval * n_part + part) * stride;
-  J.otab = L.otab;
-  solve_interval<KIND, S, T, CHM, NG, RPS, true>(J);
-}
-
-template <int KIND, typename T, int NG>
-__global__ void __launch_bounds__(256) k_split_update(SolveLaunch L, int n_part, const double* partials,
-                                                      SplitState St) {
-  const TermArgs& TA = L.chain.t[L.chain.active];
-  const int n_gf = TA.n_gf;
-  const int interval = blockIdx.x;
-  const int gt = interval / n_gf;
-  const int gf = interval - gt * n_gf;
-  const size_t stride = (size_t)L.vis.n_ant * NG * KindInfo<KIND>::NV + 1;
-  Job J;
-  J.V = &L.vis;
-  J.CH = &L.chain;
-  J.TA = &TA;
-  J.gains = L.gains;
-  J.params = L.params;
-  J.gflags = L.gflags;
-  J.iters = L.iters;
-  J.converged = L.converged;
-  J.chisq_first = L.chisq_first;
-  J.chisq_last = L.chisq_last;
-  J.gt = gt;
-  J.gf = gf;
-  J.n_gf = n_gf;
-  J.r_lo = L.row_lo[gt];
-  J.r_hi = L.row_hi[gt];
-  J.c_lo = L.chan_lo[gf];
-  J.c_hi = L.chan_hi[gf];
-  J.tol = L.tol;
-  J.max_iter = L.max_iter;
-  J.damping = L.damping;
-  J.err = L.err;
-  J.chisq_ref = nullptr;
-  J.restarted = nullptr;
-  J.partial = nullptr;
-  J.otab = nullptr;
-  split_update<KIND, T, NG>(J, partials + (size_t)interval * n_part * stride, n_part, St);
-}
 
 // Fixed direction-independent factors of a diagonal chain: for every time,
 // antenna and channel, the product of the diagonals of the terms with one
@@ -197,131 +37,6 @@ __global__ void __launch_bounds__(256) k_chain_table(SolveLaunch L, cx<T>* out) 
   }
 }
 
-__global__ void k_split_reset(SplitState St, int n_int) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_int) {
-    St.passes[i] = 0;
-    St.done[i] = 0;
-  }
-  if (i == 0) St.n_active[0] = n_int;
-}
-
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
-hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
-  const int nw = L.waves;
-  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw, RPS == 64);
-  const size_t lds_u = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, 0);
-  if (lds_out) *lds_out = lds;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kp = k_split_pass<KIND, S, T, CHM, NG, RPS>;
-  auto ku = k_split_update<KIND, T, NG>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kp),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  if (lds_u > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ku),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_u);
-    if (e != hipSuccess) return e;
-  }
-  const TermArgs& ta = L.chain.t[L.chain.active];
-  const int n_int = ta.n_gt * ta.n_gf;
-  if (n_int == 0) return hipSuccess;
-  if (P.phase == 0) {
-    hipLaunchKernelGGL(k_split_reset, dim3((n_int + 255) / 256), dim3(256), 0, stream, P.state, n_int);
-  } else {
-    hipLaunchKernelGGL(kp, dim3((unsigned)(n_int * P.n_part)), dim3(64 * nw), lds, stream, L, P.n_part, P.partials,
-                       (const uint8_t*)P.state.done);
-    hipLaunchKernelGGL(ku, dim3((unsigned)n_int), dim3(256), lds_u, stream, L, P.n_part,
-                       (const double*)P.partials, P.state);
-  }
-  return hipGetLastError();
-}
-
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false>
-hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
-  const int nw = L.waves;
-  const size_t lds = interval_lds_bytes<KIND, T, NG>(L.vis.n_ant, nw, RPS == 64);
-  if (lds_out) *lds_out = lds;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS, LMT>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  const TermArgs& ta = L.chain.t[L.chain.active];
-  const unsigned grid = (unsigned)(ta.n_gt * ta.n_gf);
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * nw), lds, stream, L);
-  return hipGetLastError();
-}
-
-// Rows per wavefront step of the single-term kernel: 4 rows of 16 lanes.
-// Narrow intervals keep every lane busy, and on wide intervals one segmented
-// flush serves 4 rows instead of one (measured on the MeerKAT-shaped
-// full-Jones solve: 155.9 ms against 175.1 ms for 1 row of 64 lanes).
-inline int rows_per_step(int max_chan, int nvp) {
-  (void)max_chan;
-  return nvp <= 16 ? 4 : (nvp <= 32 ? 2 : 1);
-}
-
-// Levenberg-Marquardt solves (fused schedule only): one row per wavefront
-// step, the chain evaluated as for Gauss-Newton
-template <int KIND, typename S, typename T>
-hipError_t launch_kind_lm(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
-  const ChainArgs& ch = L.chain;
-  const TermArgs& ta = ch.t[ch.active];
-  if (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1)
-    return launch_one<KIND, S, T, CHAIN_SINGLE, 1, 1, true>(L, stream, lds_out);
-  if constexpr (KIND != KIND_C2X2) {
-    if (L.diag_chain) {
-      if (ta.n_gdir == 1) return launch_one<KIND, S, T, CHAIN_DIAG, 1, 1, true>(L, stream, lds_out);
-      return launch_one<KIND, S, T, CHAIN_DIAG, 4, 1, true>(L, stream, lds_out);
-    }
-  }
-  if (ta.n_gdir == 1) return launch_one<KIND, S, T, CHAIN_GENERAL, 1, 1, true>(L, stream, lds_out);
-  return launch_one<KIND, S, T, CHAIN_GENERAL, 4, 1, true>(L, stream, lds_out);
-}
-
-template <int KIND, typename S, typename T>
-hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
-  const ChainArgs& ch = L.chain;
-  const TermArgs& ta = ch.t[ch.active];
-  if constexpr (KIND != KIND_DELOFF) {          // (the host offers no LM for delay-and-offset terms)
-    if (L.damping == DAMP_LM && !P) return launch_kind_lm<KIND, S, T>(L, stream, lds_out);
-  }
-  const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
-#define QC_LAUNCH(CHM_, NG_, RPS_)                                                          \
-  return P ? launch_split_one<KIND, S, T, CHM_, NG_, RPS_>(L, *P, stream, lds_out)        \
-           : launch_one<KIND, S, T, CHM_, NG_, RPS_>(L, stream, lds_out)
-  if (single) {
-    constexpr int NVP = pow2ceil(KindInfo<KIND>::NV);
-    const int rps = L.rows_per_step > 0 ? L.rows_per_step : rows_per_step(L.max_int_chan, NVP);
-    if (rps == 4) { QC_LAUNCH(CHAIN_SINGLE, 1, 4); }
-    if (rps == 2) { QC_LAUNCH(CHAIN_SINGLE, 1, 2); }
-    QC_LAUNCH(CHAIN_SINGLE, 1, 1);
-  }
-  // chains: intervals of a few channels (a bandpass per channel) take one row
-  // per lane so that every lane works
-  if constexpr (KIND != KIND_C2X2) {
-    if (L.diag_chain) {
-      if (ta.n_gdir == 1) {
-        if (L.max_int_chan <= 4) { QC_LAUNCH(CHAIN_DIAG, 1, 64); }
-        QC_LAUNCH(CHAIN_DIAG, 1, 1);
-      }
-      QC_LAUNCH(CHAIN_DIAG, 4, 1);
-    }
-  }
-  if (ta.n_gdir == 1) {
-    if (L.max_int_chan <= 4) { QC_LAUNCH(CHAIN_GENERAL, 1, 64); }
-    QC_LAUNCH(CHAIN_GENERAL, 1, 1);
-  }
-  QC_LAUNCH(CHAIN_GENERAL, 4, 1);
-#undef QC_LAUNCH
-}
-
 }  // namespace
 
 size_t chain_table_bytes(const SolveLaunch& L) {
@@ -346,25 +61,25 @@ hipError_t launch_solve(const SolveLaunch& L, const SplitLaunch* P, hipStream_t 
   if (L.prec_mixed) {
     if (L.vis_is_c128) return hipErrorInvalidValue;
     switch (kind) {
-      case KIND_DIAG: return launch_kind<KIND_DIAG, float, float>(L, P, stream, lds_out);
-      case KIND_C2X2: return launch_kind<KIND_C2X2, float, float>(L, P, stream, lds_out);
-      case KIND_DELOFF: return launch_kind<KIND_DELOFF, float, float>(L, P, stream, lds_out);
-      default: return launch_kind<KIND_DELAY, float, float>(L, P, stream, lds_out);
+      case KIND_DIAG: return launch_solve_kind<KIND_DIAG, float, float>(L, P, stream, lds_out);
+      case KIND_C2X2: return launch_solve_kind<KIND_C2X2, float, float>(L, P, stream, lds_out);
+      case KIND_DELOFF: return launch_solve_kind<KIND_DELOFF, float, float>(L, P, stream, lds_out);
+      default: return launch_solve_kind<KIND_DELAY, float, float>(L, P, stream, lds_out);
     }
   }
   if (L.vis_is_c128) {
     switch (kind) {
-      case KIND_DIAG: return launch_kind<KIND_DIAG, double, double>(L, P, stream, lds_out);
-      case KIND_C2X2: return launch_kind<KIND_C2X2, double, double>(L, P, stream, lds_out);
-      case KIND_DELOFF: return launch_kind<KIND_DELOFF, double, double>(L, P, stream, lds_out);
-      default: return launch_kind<KIND_DELAY, double, double>(L, P, stream, lds_out);
+      case KIND_DIAG: return launch_solve_kind<KIND_DIAG, double, double>(L, P, stream, lds_out);
+      case KIND_C2X2: return launch_solve_kind<KIND_C2X2, double, double>(L, P, stream, lds_out);
+      case KIND_DELOFF: return launch_solve_kind<KIND_DELOFF, double, double>(L, P, stream, lds_out);
+      default: return launch_solve_kind<KIND_DELAY, double, double>(L, P, stream, lds_out);
     }
   }
   switch (kind) {
-    case KIND_DIAG: return launch_kind<KIND_DIAG, float, double>(L, P, stream, lds_out);
-    case KIND_C2X2: return launch_kind<KIND_C2X2, float, double>(L, P, stream, lds_out);
-    case KIND_DELOFF: return launch_kind<KIND_DELOFF, float, double>(L, P, stream, lds_out);
-    default: return launch_kind<KIND_DELAY, float, double>(L, P, stream, lds_out);
+    case KIND_DIAG: return launch_solve_kind<KIND_DIAG, float, double>(L, P, stream, lds_out);
+    case KIND_C2X2: return launch_solve_kind<KIND_C2X2, float, double>(L, P, stream, lds_out);
+    case KIND_DELOFF: return launch_solve_kind<KIND_DELOFF, float, double>(L, P, stream, lds_out);
+    default: return launch_solve_kind<KIND_DELAY, float, double>(L, P, stream, lds_out);
   }
 }
 

@@ -217,11 +217,29 @@ def test_rejections(qc_lib):
     vd, cd = to_dev(vis, start)
     with pytest.raises(qc.QcError):                          # LM is not offered
         qc_lib.solve(vd, cd, 1, prec="fp64", damping="lm")
-    swapped = [cd[1], cd[0]]                                 # differs by direction, left of the active term
-    with pytest.raises(qc.QcError) as e:
-        qc_lib.solve(vd, swapped, 1, prec="fp64")
-    assert e.value.status == qc.QC_E_UNSUPPORTED
+    with pytest.raises(qc.QcError) as e:                     # CORRECT needs a direction-independent chain
+        qc_lib.apply(vd, cd, "correct")
+    assert e.value.status == qc.QC_E_ARG
+    with pytest.raises(qc.QcError) as e:                     # so do corrected weights
+        qc_lib.corrected_weights(vd, cd)
+    assert e.value.status == qc.QC_E_ARG
     bad = cd[1].copy(beam=(0.0, 1.4e9))
     with pytest.raises(qc.QcError) as e:
         qc_lib.solve(vd, [cd[0], bad], 1, prec="fp64")
     assert e.value.status == qc.QC_E_ARG
+
+
+def test_pointing_left_of_the_active_term(qc_lib):
+    """The beam (direction dependent) left of a diagonal gain being solved:
+    the chain commutes, so the gain's blocks take the beam of every direction."""
+    say("pointing left of the active term")
+    vis, start, truth = problem(917, chain=True)
+    swapped = [truth[1], start[0]]
+    ref, rst = o_solver.solve_term(vis, swapped, 1, tol=-1.0, max_iter=4)
+    vd, cd = to_dev(vis, swapped)
+    st = np_stats(qc_lib.solve(vd, cd, 1, prec="fp64", tol=-1.0, max_iter=4))
+    qc_lib.sync()
+    got = host(cd)
+    assert (st["iters"] == 4).all()
+    g, w = got[1].gains[..., [0, 3]], ref[1].gains[..., [0, 3]]
+    assert np.abs(g - w).max() <= 1e-10 * np.abs(w).max()

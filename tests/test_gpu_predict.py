@@ -1,5 +1,5 @@
 """DFT prediction of component models on the GPU against the CPU oracle
-(Section 4.6: component models predicted on the fly).
+(Section 4.7: component models predicted on the fly).
 
 Tolerances (per sample and correlation, absolute), from the arithmetic:
   * FP64 (complex128 output): both sides round a phase of up to ph_max

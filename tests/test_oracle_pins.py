@@ -903,7 +903,7 @@ def test_flagged_garbage_does_not_move_the_statistics():
 
 
 # ---------------------------------------------------------------------------
-# DFT prediction of component models (Section 4.6)
+# DFT prediction of component models (Section 4.7)
 # ---------------------------------------------------------------------------
 
 def _sky(rng, n_comp, n_dir, radius=0.02, pol=True):
