@@ -252,6 +252,27 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
                             int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as qc_solve_interval, with the same arguments, results and errors,
+ * that calls no hipMalloc, hipFree or allocating library routine.  Its device
+ * scratch (row positions of every time, the row and channel ranges of the
+ * active term's intervals) lives in a fixed array of QC_STATIC_SCRATCH_BYTES
+ * per device, held until the process ends; a solve needing more, i.e.
+ * 256-byte-aligned blocks of 8 (n_time + 1), 16 n_gt, 8 n_gt and 8 n_gf bytes
+ * summing past it, returns QC_E_UNSUPPORTED before any work is enqueued.
+ * Always the fused schedule (one workgroup runs each interval to the end,
+ * whatever qc_ctx_set_split says), without the fixed-factor table of diagonal
+ * chains (those factors are formed per sample); an active POINTING term is
+ * QC_E_UNSUPPORTED.  Every call on a device shares that device's array and
+ * overwrites what it needs before reading it: calls that overlap on one device
+ * (other streams, other host threads, other contexts) race and must not.
+ */
+#define QC_STATIC_SCRATCH_BYTES (4 * 1024 * 1024)
+qc_status qc_solve_interval_static(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
+                                   int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats);
+
+/*
  * Chain / epoch driver (Section 4.3): for n_epoch passes over the chain, solve
  * every term in array order with qc_solve_interval, the others fixed.
  * stats: NULL or an array of n_epoch * n_term entries ([epoch][term]).

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -200,7 +201,7 @@ qc_status validate_rows(qc_ctx* ctx, const qc_vis* v, hipStream_t s) {
 }
 
 qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
-                  std::vector<HostMaps>& maps, hipStream_t s) {
+                  std::vector<HostMaps>& maps, hipStream_t s, const PrepScratch* fixed) {
   qc_status st = check_vis(ctx, v);
   if (st != QC_OK) return st;
   if (!chain || n_term <= 0) return fail(ctx, QC_E_ARG, "empty chain");
@@ -214,13 +215,20 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
   VisArgs va;
   ChainArgs ca;
   fill_args(v, chain, n_term, active, va, ca);
-  HIP_TRY(ctx, grow(ctx->d_rowpos, ctx->rowpos_cap, (size_t)v->n_time + 1));
+  // device scratch: the context's (grown as needed) or the caller's fixed block
+  PrepScratch sc;
+  if (fixed) {
+    sc = *fixed;
+  } else {
+    HIP_TRY(ctx, grow(ctx->d_rowpos, ctx->rowpos_cap, (size_t)v->n_time + 1));
+    sc.rowpos = ctx->d_rowpos;
+  }
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, s, ctx->d_err);
   if (v->n_row > 0) {
     const long long nb = (v->n_row + 255) / 256;
-    hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(256), 0, s, va, ctx->d_rowpos, ctx->d_err);
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(256), 0, s, va, sc.rowpos, ctx->d_err);
   } else {
-    hipLaunchKernelGGL(k_rowpos_empty, dim3((v->n_time + 256) / 256), dim3(256), 0, s, ctx->d_rowpos, v->n_time);
+    hipLaunchKernelGGL(k_rowpos_empty, dim3((v->n_time + 256) / 256), dim3(256), 0, s, sc.rowpos, v->n_time);
   }
   HIP_TRY(ctx, hipGetLastError());
   if (active >= 0) {
@@ -241,18 +249,25 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
       chi[g] = (int)(hi - hm.f_map.begin());
       ctx->max_int_chan = std::max(ctx->max_int_chan, chi[g] - clo[g]);
     }
-    HIP_TRY(ctx, grow(ctx->d_rowlo, ctx->rowlo_cap, (size_t)ta.n_gt));
-    HIP_TRY(ctx, grow(ctx->d_rowhi, ctx->rowhi_cap, (size_t)ta.n_gt));
-    HIP_TRY(ctx, grow(ctx->d_tt, ctx->tt_cap, 2 * (size_t)ta.n_gt));
-    HIP_TRY(ctx, grow(ctx->d_chlo, ctx->chlo_cap, (size_t)ta.n_gf));
-    HIP_TRY(ctx, grow(ctx->d_chhi, ctx->chhi_cap, (size_t)ta.n_gf));
+    if (!fixed) {
+      HIP_TRY(ctx, grow(ctx->d_rowlo, ctx->rowlo_cap, (size_t)ta.n_gt));
+      HIP_TRY(ctx, grow(ctx->d_rowhi, ctx->rowhi_cap, (size_t)ta.n_gt));
+      HIP_TRY(ctx, grow(ctx->d_tt, ctx->tt_cap, 2 * (size_t)ta.n_gt));
+      HIP_TRY(ctx, grow(ctx->d_chlo, ctx->chlo_cap, (size_t)ta.n_gf));
+      HIP_TRY(ctx, grow(ctx->d_chhi, ctx->chhi_cap, (size_t)ta.n_gf));
+      sc.rowlo = ctx->d_rowlo;
+      sc.rowhi = ctx->d_rowhi;
+      sc.tt = ctx->d_tt;
+      sc.chlo = ctx->d_chlo;
+      sc.chhi = ctx->d_chhi;
+    }
     ctx->h_clo = clo;
     ctx->h_chi = chi;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tt, tt.data(), sizeof(int) * tt.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_chlo, clo.data(), sizeof(int) * clo.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_chhi, chi.data(), sizeof(int) * chi.size(), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_ranges, dim3((ta.n_gt + 255) / 256), dim3(256), 0, s, ctx->d_rowpos, ctx->d_tt,
-                       ta.n_gt, ctx->d_rowlo, ctx->d_rowhi);
+    HIP_TRY(ctx, hipMemcpyAsync(sc.tt, tt.data(), sizeof(int) * tt.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(sc.chlo, clo.data(), sizeof(int) * clo.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(sc.chhi, chi.data(), sizeof(int) * chi.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ranges, dim3((ta.n_gt + 255) / 256), dim3(256), 0, s, sc.rowpos, sc.tt, ta.n_gt,
+                       sc.rowlo, sc.rowhi);
     HIP_TRY(ctx, hipGetLastError());
   }
   return read_err(ctx, s);
@@ -271,6 +286,59 @@ int resolve_damping(qc_damping d, const qc_term& t) {
 }
 
 }  // namespace qc
+
+// ---------------------------------------------------------------------------
+// allocation-free scratch (qc_solve_interval_static)
+// ---------------------------------------------------------------------------
+
+// A fixed device array for the scratch of qc_solve_interval_static: each
+// device that loads the library holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is a stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[QC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The address of this device's scratch array, looked up once per device
+// with the device current.
+qc_status static_scratch_ptr(int device, unsigned char** out) {
+  if (device < 0 || device >= MAX_DEVICES) return QC_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return QC_E_DEVICE;
+    g_scratch_ptr[device] = reinterpret_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return QC_OK;
+}
+
+// Carves the prepare scratch of a solve out of the static array; returns the
+// bytes it needs (those beyond QC_STATIC_SCRATCH_BYTES are not carved).
+size_t carve_static(unsigned char* base, const qc_vis* v, const qc_term& ta, PrepScratch& sc) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  const size_t n_time = v ? (size_t)std::max(v->n_time, 0) : 0;
+  const size_t n_gt = (size_t)std::max(ta.n_gt, 0), n_gf = (size_t)std::max(ta.n_gf, 0);
+  sc.rowpos = reinterpret_cast<long long*>(take(sizeof(long long) * (n_time + 1)));
+  sc.rowlo = reinterpret_cast<long long*>(take(sizeof(long long) * n_gt));
+  sc.rowhi = reinterpret_cast<long long*>(take(sizeof(long long) * n_gt));
+  sc.tt = reinterpret_cast<int*>(take(sizeof(int) * 2 * n_gt));
+  sc.chlo = reinterpret_cast<int*>(take(sizeof(int) * n_gf));
+  sc.chhi = reinterpret_cast<int*>(take(sizeof(int) * n_gf));
+  return off;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // public API
@@ -292,6 +360,11 @@ qc_status qc_ctx_create(int32_t device, qc_ctx** out) {
   }
   hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device);
   if (c->n_cu <= 0) c->n_cu = 256;
+  if (static_scratch_ptr(device, &c->static_scratch) != QC_OK) {
+    hipFree(c->d_err);
+    delete c;
+    return QC_E_DEVICE;
+  }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     hipFree(c->d_err);
     delete c;
@@ -356,8 +429,13 @@ double qc_last_kernel_ms(qc_ctx* ctx) {
   return (double)ms;
 }
 
-qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t active,
-                            const qc_solve_opts* opts, qc_solve_stats* stats) {
+}  // extern "C"
+
+// qc_solve_interval; fixed != NULL: the allocation-free form (prepare scratch
+// in `fixed`, always the fused schedule, no fixed-factor table, no pointing)
+static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
+                                     int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats,
+                                     const PrepScratch* fixed) {
   if (!ctx) return QC_E_ARG;
   if (!opts) return fail(ctx, QC_E_ARG, "opts is NULL");
   if (!chain || n_term <= 0 || active < 0 || active >= n_term)
@@ -371,8 +449,10 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
     return fail(ctx, QC_E_ARG, "MIXED precision needs complex64 data");
   hipStream_t s = reinterpret_cast<hipStream_t>(opts->stream);
   ctx->last_stream = s;
+  if (fixed && chain[active].type == QC_TERM_POINTING)
+    return fail(ctx, QC_E_UNSUPPORTED, "the allocation-free solve takes no active POINTING term");
   std::vector<HostMaps> maps;
-  qc_status st = prepare(ctx, vis, chain, n_term, active, maps, s);
+  qc_status st = prepare(ctx, vis, chain, n_term, active, maps, s, fixed);
   if (st != QC_OK) return st;
   if (chain[active].type == QC_TERM_POINTING)
     return solve_pointing(ctx, vis, chain, n_term, active, opts, stats, s);
@@ -397,10 +477,10 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   L.gains = reinterpret_cast<double2*>(ta.gains);
   L.params = ta.params;
   L.gflags = ta.gain_flags;
-  L.row_lo = ctx->d_rowlo;
-  L.row_hi = ctx->d_rowhi;
-  L.chan_lo = ctx->d_chlo;
-  L.chan_hi = ctx->d_chhi;
+  L.row_lo = fixed ? fixed->rowlo : ctx->d_rowlo;
+  L.row_hi = fixed ? fixed->rowhi : ctx->d_rowhi;
+  L.chan_lo = fixed ? fixed->chlo : ctx->d_chlo;
+  L.chan_hi = fixed ? fixed->chhi : ctx->d_chhi;
   if (stats) {
     L.iters = stats->iters;
     L.converged = stats->converged;
@@ -426,7 +506,9 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   const bool lm = opts->damping == QC_DAMP_LM;
   if (lm && ta.type == QC_TERM_DELAY_OFFSET)
     return fail(ctx, QC_E_UNSUPPORTED, "Levenberg-Marquardt takes no delay-and-offset term");
-  if (ctx->split_parts > 1) {
+  if (fixed) {
+    parts = 1;                                 // the split schedule's state is context memory
+  } else if (ctx->split_parts > 1) {
     if (lm) return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take Levenberg-Marquardt damping");
     parts = ctx->split_parts;
   } else if (ctx->split_parts == 0 && !lm && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
@@ -444,7 +526,7 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   bool other_di = false;
   for (int j = 0; j < n_term; ++j)
     if (j != active && chain[j].n_gdir == 1) other_di = true;
-  const bool want_tab = L.diag_chain && !single_chain && other_di;
+  const bool want_tab = !fixed && L.diag_chain && !single_chain && other_di;
   L.otab = nullptr;
   if (want_tab) HIP_TRY(ctx, grow(ctx->d_otab, ctx->otab_cap, chain_table_bytes(L)));
   SplitLaunch P;
@@ -501,6 +583,27 @@ qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int3
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
   ctx->timed = true;
   return QC_OK;
+}
+
+extern "C" {
+
+qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t active,
+                            const qc_solve_opts* opts, qc_solve_stats* stats) {
+  return solve_interval_impl(ctx, vis, chain, n_term, active, opts, stats, nullptr);
+}
+
+qc_status qc_solve_interval_static(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
+                                   int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats) {
+  if (!ctx) return QC_E_ARG;
+  if (!chain || n_term <= 0 || active < 0 || active >= n_term)
+    return fail(ctx, QC_E_ARG, "active=%d outside the chain of %d terms", active, n_term);
+  if (!ctx->static_scratch) return fail(ctx, QC_E_DEVICE, "no scratch array on device %d", ctx->device);
+  PrepScratch sc;
+  const size_t need = carve_static(ctx->static_scratch, vis, chain[active], sc);
+  if (need > QC_STATIC_SCRATCH_BYTES)
+    return fail(ctx, QC_E_UNSUPPORTED, "the allocation-free solve needs %zu B of scratch, more than its %d B",
+                need, (int)QC_STATIC_SCRATCH_BYTES);
+  return solve_interval_impl(ctx, vis, chain, n_term, active, opts, stats, &sc);
 }
 
 int32_t qc_ctx_last_split(const qc_ctx* ctx) { return ctx ? ctx->last_split_parts : -1; }

@@ -80,6 +80,7 @@ struct qc_ctx {
   double* d_pt_dbl = nullptr;          // pointing solves: chi^2 first/last, previous steps
   size_t pt_dbl_cap = 0;
   int last_split_parts = 1;   // parts per interval of the last solve (1 = fused)
+  unsigned char* static_scratch = nullptr;   // this device's allocation-free scratch array (qc_api.hip)
 };
 
 namespace qc {
@@ -126,8 +127,25 @@ struct HostMaps {
   std::vector<int> t_map, f_map, d_map;
 };
 
+// Device scratch of the argument checks and interval ranges: the row position
+// of every time [n_time + 1], the row range [n_gt] x 2 and time range [2][n_gt]
+// of every gain time and the channel range [n_gf] x 2 of every gain frequency
+// of the active term.
+struct PrepScratch {
+  long long* rowpos = nullptr;
+  long long* rowlo = nullptr;
+  long long* rowhi = nullptr;
+  int* tt = nullptr;
+  int* chlo = nullptr;
+  int* chhi = nullptr;
+};
+
+// Checks the visibilities and the chain, validates the rows on the device and
+// (active >= 0) computes the interval ranges of the active term, into `fixed`
+// when given, else into the context's scratch (grown as needed); waits for
+// the device checks.
 qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
-                  std::vector<HostMaps>& maps, hipStream_t s);
+                  std::vector<HostMaps>& maps, hipStream_t s, const PrepScratch* fixed = nullptr);
 void fill_args(const qc_vis* v, const qc_term* chain, int n_term, int active, VisArgs& va, ChainArgs& ca);
 qc_status read_err(qc_ctx* ctx, hipStream_t s);
 // check_vis plus the device checks of row order and antenna/time ranges

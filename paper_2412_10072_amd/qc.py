@@ -30,7 +30,7 @@ DAMPINGS = {"full": 0, "half": 1, "alternate": 2, "auto": 3, "lm": 4}
 
 EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "qc_last_kernel_ms", "qc_ctx_set_tile",
            "qc_ctx_set_split", "qc_ctx_last_split",
-           "qc_solve_interval", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
+           "qc_solve_interval", "qc_solve_interval_static", "qc_solve_chain", "qc_delay_init", "qc_apply_gains", "qc_residual",
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
            "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft", "qc_robust_weights",
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_last_kernel_ms.restype = C.c_double
     lib.qc_solve_interval.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                       C.POINTER(QcSolveOpts), C.POINTER(QcSolveStats)]
+    lib.qc_solve_interval_static.argtypes = lib.qc_solve_interval.argtypes
     lib.qc_ctx_set_tile.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.qc_ctx_set_split.argtypes = [C.c_void_p, C.c_int32]
     lib.qc_ctx_last_split.argtypes = [C.c_void_p]
@@ -341,10 +342,12 @@ class Context:
 
     def solve(self, vis, chain, active: int = 0, tol: float = 1e-6, max_iter: int = 100,
               prec: str = "mixed", damping: str = "auto", stream=None, stats: Optional[dict] = None,
-              chisq_ref: Optional[torch.Tensor] = None):
+              chisq_ref: Optional[torch.Tensor] = None, static: bool = False):
         """qc_solve_interval: solve chain[active] in place; returns the per-interval stats tensors.
         chisq_ref (per interval, float64): restart an interval from unit gains when chi^2 at its
-        starting gains exceeds the entry (warm-start fallback)."""
+        starting gains exceeds the entry (warm-start fallback).  static: call
+        qc_solve_interval_static (no device allocation inside the library; pass `stats`
+        to allocate nothing here either)."""
         dev = vis.data.device
         # an out-of-range `active` is passed on: the library rejects it with QC_E_ARG
         term = chain[active] if 0 <= active < len(chain) else None
@@ -356,8 +359,8 @@ class Context:
                            damping=DAMPINGS[damping], stream=_stream_ptr(stream),
                            chisq_ref=_ptr(chisq_ref, torch.float64, "chisq_ref"))
         cs = _c_stats(stats)
-        self._check(self.lib.qc_solve_interval(self.h, C.byref(cv), cc, len(chain), int(active),
-                                               C.byref(opts), C.byref(cs)))
+        fn = self.lib.qc_solve_interval_static if static else self.lib.qc_solve_interval
+        self._check(fn(self.h, C.byref(cv), cc, len(chain), int(active), C.byref(opts), C.byref(cs)))
         return stats
 
     def solve_chain(self, vis, chain, n_epoch: int = 1, tol: float = 1e-6, max_iter: int = 100,
