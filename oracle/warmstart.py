@@ -16,9 +16,11 @@ MLP: y = W2 relu(W1 x + b1) + b2 with flat parameters [W1 (H x I) | b1 (H) |
 W2 (O x H) | b2 (O)], all row-major.  Loss: mean squared error over the batch
 and outputs.  Adam (Kingma & Ba 2015) with bias correction.
 
-parity pinned: tests/test_oracle_pins.py (central finite-difference gradient
-check of the backward pass; Adam reduces to sign-SGD on its first step;
-features equal the true gain product on noise-free single-baseline data).
+parity pinned: tests/test_oracle_pins.py (a forward pass worked by hand;
+central finite-difference gradient check of the backward pass; Adam reduces
+to sign-SGD on its first step and, for a constant gradient with eps = 0, on
+every step; features equal the true gain product on noise-free
+single-baseline data).
 """
 import numpy as np
 

@@ -761,6 +761,36 @@ def test_mlp_backward_matches_finite_differences():
         assert abs((Lp - Lm) / (2 * h) - g[j]) < 1e-7
 
 
+def test_mlp_forward_hand_computed():
+    """A 2-input, 3-hidden, 2-output network with small integer weights,
+    worked by hand: pre = W1 x + b1 = (2, -3, 5) for x = (3, 1), relu ->
+    (2, 0, 5), y = W2 h + b2 = (2 + 10 + 0.5, -2 + 0 + 5 - 1) = (12.5, 2);
+    the second input row (-1, 2) gives pre (-3, 1, -3) -> (0, 1, 0),
+    y = (0 + 0 + 0 + 0.5, 0 + 1 + 0 - 1) = (0.5, 0)."""
+    W1 = np.array([[1.0, -1.0], [-1.0, 0.0], [2.0, 0.0]])
+    b1 = np.array([0.0, 0.0, -1.0])
+    W2 = np.array([[1.0, 0.0, 2.0], [-1.0, 1.0, 1.0]])
+    b2 = np.array([0.5, -1.0])
+    params = np.concatenate([W1.ravel(), b1, W2.ravel(), b2])
+    x = np.array([[3.0, 1.0], [-1.0, 2.0]])
+    y, pre = warmstart.forward(params, x, 2, 3, 2)
+    np.testing.assert_array_equal(pre, [[2.0, -3.0, 5.0], [-3.0, 1.0, -3.0]])
+    np.testing.assert_array_equal(y, [[12.5, 2.0], [0.5, 0.0]])
+
+
+def test_adam_constant_gradient_stream_steps_by_lr_sign():
+    """With a gradient that never changes, the bias-corrected moments are
+    exactly g and g^2 at every step, so with eps = 0 each step moves every
+    parameter by lr sign(g): after k steps p = p0 - k lr sign(g)."""
+    g = np.array([0.3, -2.0, 1e-3, -7.5e4])
+    p0 = np.array([1.0, -0.5, 0.25, 3.0])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    lr = 0.01
+    for k in range(1, 41):
+        p, m, v = warmstart.adam(p, g, m, v, lr, 0.9, 0.999, 0.0, k)
+        np.testing.assert_allclose(p, p0 - k * lr * np.sign(g), rtol=0, atol=1e-13)
+
+
 def test_adam_first_step_is_sign_step():
     g = np.array([0.3, -2.0, 1e-3])
     p, m, v = warmstart.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 0.01, 0.9, 0.999, 1e-12, 1)
