@@ -368,6 +368,7 @@ def leg_warm(ctx, dev, n_sets: int = 5, n_time_train: int = 625, epochs: int = 3
         res[mode] = dict(ms=1e3 * (time.perf_counter() - ts), iters=float(st["iters"].float().mean().item()),
                          restarted=float(st["restarted"].float().mean().item()),
                          converged=float(st["converged"].float().mean().item()), gains=t.gains)
+    lb = learned_batched(ctx, net, dev)
     # agreement of the two solutions (model-level, gauge free): max |g_p conj(g_q)| difference
     gu, gw = res["unit"]["gains"], res["warm"]["gains"]
     pu = gu[:, :, :, 0, 0, None] * gu[:, :, None, :, 0, 0].conj()
@@ -381,11 +382,103 @@ def leg_warm(ctx, dev, n_sets: int = 5, n_time_train: int = 625, epochs: int = 3
                unit_ms=res["unit"]["ms"], warm_ms=res["warm"]["ms"],
                time_saved_frac=1.0 - res["warm"]["ms"] / res["unit"]["ms"],
                restarted_frac=res["warm"]["restarted"], converged_frac=res["warm"]["converged"],
-               model_agreement=agree, params=net.n_params)
+               model_agreement=agree, params=net.n_params, learned_batched=lb)
     log(f"warm start: {n_train} training intervals ({gen_s:.1f} s to make), training {train_s:.1f} s, "
         f"loss {hist[0]:.4f} -> {hist[-1]:.4f}; held-out iterations unit {out['unit_iters']:.2f} "
         f"warm {out['warm_iters']:.2f}; time unit {out['unit_ms']:.1f} ms warm {out['warm_ms']:.1f} ms")
     return out
+
+
+def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
+    """Learned + batched against plain, at tol 1e-6 (MIXED): n_problems held-out problems of
+    uneven size (64 antennas, times U{8..40}, 256 / 512 / 1024 channels, whole rows dropped at a
+    fraction U(0, 0.3), 10% sample flags, random diagonal gains, intervals 1 time x 64 channels)
+    solved four ways, each timed on the wall clock from the first launch to the last result:
+    plain (one qc_solve_interval per problem from unit gains), batched (one graph launch from
+    unit gains), learned (per problem: feature pass, MLP, gain write, solve with the unit-gain
+    fallback) and learned + batched (the warm starts of every problem, then one graph launch
+    with per-problem fallback references)."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc, warmstart
+    from synth.generate import config_meerkat
+
+    g = np.random.default_rng(np.random.SeedSequence([2412, 51]))
+    probs = []
+    t0 = time.perf_counter()
+    for i in range(n_problems):
+        n_time = int(g.integers(8, 41))
+        n_chan = int(g.choice([256, 512, 1024]))
+        drop = float(g.uniform(0.0, 0.3))
+        p = config_meerkat(device=dev, n_time=n_time, n_chan=n_chan, f_int=64, kind="diag", gain_mode="random",
+                           cfg_id=51, seed_block=i, row_drop=drop)
+        t = qc.device_term(p.chain[0], dev)
+        ref = torch.empty(int(t.n_gt) * int(t.n_gf), dtype=torch.float64, device=dev)
+        probs.append((p.vis, t, ref, t.gains.clone()))
+    torch.cuda.synchronize()
+    n_samples = int(sum(int(v.data.shape[0]) * int(v.data.shape[1]) for v, _, _, _ in probs))
+    n_int = int(sum(int(t.n_gt) * int(t.n_gf) for _, t, _, _ in probs))
+    log(f"learned+batched: {n_problems} problems, {n_int} intervals, {n_samples / 1e9:.3f}e9 samples "
+        f"({time.perf_counter() - t0:.1f} s to make)")
+    stream = torch.cuda.current_stream()
+
+    def reset():
+        for _, t, _, g0 in probs:
+            t.gains.copy_(g0)
+
+    b_unit = qc.Batch(ctx, [(v, t) for v, t, _, _ in probs], tol=1e-6, max_iter=100, prec="mixed", stream=stream)
+    b_warm = qc.Batch(ctx, [(v, t, r) for v, t, r, _ in probs], tol=1e-6, max_iter=100, prec="mixed",
+                      stream=stream)
+
+    def run(mode):
+        stats = None
+        if mode == "plain":
+            stats = [ctx.solve(v, [t], 0, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
+                     for v, t, _, _ in probs]
+        elif mode == "batched":
+            b_unit.run(stream)
+            stats = b_unit.stats
+        elif mode == "learned":
+            stats = []
+            for v, t, r, _ in probs:
+                net.init_gains(v, t, stream=stream, chisq_out=r)
+                stats.append(ctx.solve(v, [t], 0, tol=1e-6, max_iter=100, prec="mixed", stream=stream,
+                                       chisq_ref=r.reshape(int(t.n_gt), int(t.n_gf))))
+        else:
+            for v, t, r, _ in probs:
+                net.init_gains(v, t, stream=stream, chisq_out=r)
+            b_warm.run(stream)
+            stats = b_warm.stats
+        return stats
+
+    out = {}
+    for mode in ("plain", "batched", "learned", "learned_batched"):
+        best = None
+        for _ in range(reps):
+            reset()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            stats = run(mode)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - ts)
+            best = ms if best is None else min(best, ms)
+        it = np.concatenate([s["iters"].cpu().numpy().ravel() for s in stats])
+        rs = np.concatenate([s["restarted"].cpu().numpy().ravel() for s in stats])
+        cv = np.concatenate([s["converged"].cpu().numpy().ravel() for s in stats])
+        out[mode] = dict(ms=best, vis_per_s=n_samples / (best * 1e-3), mean_iterations=float(it.mean()),
+                         restarted_frac=float(rs.mean()), converged_frac=float(cv.mean()))
+    b_unit.close()
+    b_warm.close()
+    res = dict(problems=n_problems, intervals=n_int, samples=n_samples, **out,
+               speedup_learned_batched_vs_plain=out["plain"]["ms"] / out["learned_batched"]["ms"],
+               speedup_batched_vs_plain=out["plain"]["ms"] / out["batched"]["ms"],
+               speedup_learned_vs_plain=out["plain"]["ms"] / out["learned"]["ms"])
+    log("learned+batched: " + ", ".join(f"{m} {out[m]['ms']:.1f} ms ({out[m]['mean_iterations']:.2f} updates)"
+                                       for m in out) +
+        f"; learned+batched vs plain {res['speedup_learned_batched_vs_plain']:.2f}x")
+    del probs
+    torch.cuda.empty_cache()
+    return res
 
 
 def leg_chain(ctx, dev, n_epoch: int = 2):

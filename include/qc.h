@@ -485,6 +485,9 @@ typedef struct {
   qc_vis vis;
   qc_term term;             /* the solved term (its gains/gain_flags are in/out) */
   qc_solve_stats stats;     /* per interval of the term; pointers may be NULL */
+  const double* chisq_ref;  /* NULL, or per interval of the term [n_gt][n_gf]: the
+                               warm-start fallback of qc_solve_opts.chisq_ref for
+                               this problem (opts.chisq_ref itself is ignored here) */
 } qc_problem;
 
 #define QC_BATCH_BUCKETS 6  /* channel width (<=16, <=32, wider) x size (< 65536 samples, larger) */

@@ -15,6 +15,8 @@ struct BatchProb {
   uint8_t* converged;
   double* chisq_first;
   double* chisq_last;
+  const double* chisq_ref;     // warm-start fallback reference per interval, or null
+  uint8_t* restarted;          // per interval, or null
   int damping;
   int pad;
 };

@@ -58,8 +58,8 @@ __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
     J.max_iter = B.max_iter;
     J.damping = P.damping;
     J.err = B.err;
-    J.chisq_ref = nullptr;
-    J.restarted = nullptr;
+    J.chisq_ref = P.chisq_ref;
+    J.restarted = P.restarted;
     J.partial = nullptr;
     J.otab = nullptr;
     if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, true, 1, RPS>(J);

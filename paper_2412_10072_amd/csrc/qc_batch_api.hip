@@ -197,6 +197,8 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
     bp.converged = P.stats.converged;
     bp.chisq_first = P.stats.chisq_first;
     bp.chisq_last = P.stats.chisq_last;
+    bp.chisq_ref = P.chisq_ref;
+    bp.restarted = P.stats.restarted;
     bp.damping = resolve_damping(opts->damping, P.term);
     b->probs.push_back(bp);
     b->max_ant = std::max(b->max_ant, P.vis.n_ant);

@@ -71,7 +71,7 @@ class QcSolveStats(C.Structure):
 
 
 class QcProblem(C.Structure):
-    _fields_ = [("vis", QcVis), ("term", QcTerm), ("stats", QcSolveStats)]
+    _fields_ = [("vis", QcVis), ("term", QcTerm), ("stats", QcSolveStats), ("chisq_ref", C.c_void_p)]
 
 
 class QcSky(C.Structure):
@@ -622,9 +622,10 @@ class Batch:
     """A qc_batch plan: many independent single-term problems solved by one
     graph launch (qc_batch_create / qc_batch_tune / qc_batch_run).
 
-    problems: list of (vis, term) pairs with device tensors; each term's
-    gains are solved in place on every run.  The plan keeps references to
-    every tensor it was given."""
+    problems: list of (vis, term) pairs, or (vis, term, chisq_ref) triples
+    (chisq_ref: float64 per interval of the term, the warm-start fallback
+    reference), with device tensors; each term's gains are solved in place on
+    every run.  The plan keeps references to every tensor it was given."""
 
     def __init__(self, ctx: "Context", problems, tol: float = 1e-6, max_iter: int = 100,
                  prec: str = "mixed", damping: str = "auto", stream=None):
@@ -633,12 +634,19 @@ class Batch:
         self.problems = list(problems)
         self.stats = []
         arr = (QcProblem * len(self.problems))()
-        for i, (vis, term) in enumerate(self.problems):
+        for i, prob in enumerate(self.problems):
+            vis, term = prob[0], prob[1]
+            ref = prob[2] if len(prob) > 2 else None
             st = _stats_for(term, vis.data.device)
             self.stats.append(st)
             arr[i].vis = _c_vis(vis)
             arr[i].term = _c_chain([term])[0]
             arr[i].stats = _c_stats(st)
+            if ref is not None:
+                n_int = int(term.n_gt) * int(term.n_gf)
+                if ref.numel() != n_int:
+                    raise ValueError(f"problem {i}: chisq_ref needs {n_int} entries, got {ref.numel()}")
+            arr[i].chisq_ref = _ptr(ref, torch.float64, "chisq_ref")
         self._arr = arr
         opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
                            damping=DAMPINGS[damping], stream=_stream_ptr(stream))

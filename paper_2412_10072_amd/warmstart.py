@@ -94,12 +94,13 @@ class WarmStartNet:
                 log(f"warm start: epoch {ep + 1}/{epochs} loss {hist[-1]:.5f}")
         return hist
 
-    def init_gains(self, vis, term, stream=None) -> torch.Tensor:
+    def init_gains(self, vis, term, stream=None, chisq_out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Write warm-start gains into term.gains (diagonal term, one gain
         direction); returns chi^2 at unit gains per interval, the reference of
-        the solver's fallback."""
+        the solver's fallback (written into chisq_out when given)."""
         n_int = int(term.n_gt) * int(term.n_gf)
-        chisq_unit = torch.empty(n_int, dtype=torch.float64, device=vis.data.device)
+        chisq_unit = chisq_out if chisq_out is not None else torch.empty(n_int, dtype=torch.float64,
+                                                                         device=vis.data.device)
         feat = self.ctx.ws_features(vis, term, chisq_unit=chisq_unit, ref_ant=0, stream=stream)
         y = self.predict(feat, stream=stream)
         self.ctx.ws_gains(y, self.n_ant, term.gains, stream=stream)

@@ -43,7 +43,7 @@ def test_binding_struct_layout_matches_header():
     assert qc.QcTerm.t_map.offset == 24
     assert C.sizeof(qc.QcSolveOpts) == 8 + 3 * 4 + 4 + 8 + 8
     assert C.sizeof(qc.QcSolveStats) == 5 * 8
-    assert C.sizeof(qc.QcProblem) == C.sizeof(qc.QcVis) + C.sizeof(qc.QcTerm) + C.sizeof(qc.QcSolveStats)
+    assert C.sizeof(qc.QcProblem) == C.sizeof(qc.QcVis) + C.sizeof(qc.QcTerm) + C.sizeof(qc.QcSolveStats) + 8
 
 
 def test_binding_offsets_equal_the_c_compiler_s(tmp_path):

@@ -149,3 +149,46 @@ def test_batch_rejects_unsupported(qc_lib):
     with pytest.raises(qc.QcError) as e:
         qc.Batch(qc_lib, [(bad_vis, dev[0][1])] + dev[1:], prec="fp64")
     assert e.value.status == qc.QC_E_RANGE
+
+
+def test_batch_warm_start_fallback_matches_oracle(qc_lib):
+    """Per-problem warm-start references in the batch (qc_problem.chisq_ref):
+    intervals whose chi^2 at the starting gains exceeds chi^2 at unit gains
+    restart from unit gains in the same launch.  Starts alternate between
+    the truth (kept) and a scaled, disturbed truth (restarted); the result is
+    the oracle's solve from the start each interval should take."""
+    from paper_2412_10072_amd import qc
+    say("batch warm-start fallback")
+    dev_p, host_p, expect = [], [], []
+    for i, sh in enumerate(SHAPES):
+        p = config_batch_problem(sh, i, dtype="c128")
+        vis_h = to_numpy_vis(p.vis)
+        unit = p.chain[0]
+        truth = p.truth[0]
+        rng = np.random.default_rng(500 + i)
+        warm = truth.copy(gains=truth.gains.copy())
+        bad = np.zeros(warm.gains.shape[:2], bool)
+        bad[1::2] = True                                   # every other gain time
+        noise = 0.3 * (rng.standard_normal(warm.gains.shape) + 1j * rng.standard_normal(warm.gains.shape))
+        if truth.kind == "diag":
+            noise[..., 1] = 0
+            noise[..., 2] = 0
+        warm.gains[bad] = 3.0 * warm.gains[bad] + noise[bad]
+        _, st_u = o_solver.solve_term(vis_h, [unit], 0, tol=-1.0, max_iter=0)
+        _, st_w = o_solver.solve_term(vis_h, [warm], 0, tol=-1.0, max_iter=0)
+        restart = st_w["chisq_first"] > st_u["chisq_first"]
+        start = warm.copy(gains=np.where(restart[:, :, None, None, None], unit.gains, warm.gains))
+        ref, _ = o_solver.solve_term(vis_h, [start], 0, tol=-1.0, max_iter=4)
+        expect.append((restart, ref[0].gains, truth.kind))
+        ref_d = torch.as_tensor(st_u["chisq_first"], dtype=torch.float64).to(DEV).contiguous()
+        dev_p.append((qc.device_vis(vis_h, DEV), qc.device_term(warm, DEV), ref_d))
+    n_restart = sum(int(r.sum()) for r, _, _ in expect)
+    n_keep = sum(int((~r).sum()) for r, _, _ in expect)
+    assert n_restart > 0 and n_keep > 0
+    b = qc.Batch(qc_lib, dev_p, tol=-1.0, max_iter=4, prec="fp64")
+    b.run()
+    torch.cuda.synchronize()
+    for (vis_d, t, _), st, (restart, want, kind) in zip(dev_p, b.stats, expect):
+        np.testing.assert_array_equal(st["restarted"].cpu().numpy().astype(bool), restart)
+        assert rel_err(t.gains.cpu().numpy(), want, kind) <= 1e-10
+    b.close()
