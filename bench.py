@@ -506,6 +506,7 @@ def leg_chain(ctx, dev, n_epoch: int = 2):
     ctx.delay_init(vis, chain[0], ref_ant=0, stream=stream)
     torch.cuda.synchronize()
     t_delay = time.perf_counter() - ts
+    k_start = chain[0].params.clone()
     log(f"chain: delay initial estimate {1e3 * t_delay:.1f} ms")
     terms = []
     for e in range(n_epoch):
@@ -536,10 +537,73 @@ def leg_chain(ctx, dev, n_epoch: int = 2):
     sigma = float(p.meta["sigma"])
     out = dict(samples=n_samples, directions=int(vis.model.shape[2]), delay_init_ms=1e3 * t_delay,
                terms=terms, residual_ms=1e3 * (t_end - t2), total_s=t_total,
-               vis_per_s=n_samples / t_total, residual_rms=rms, noise_rms=sigma * math.sqrt(2))
+               vis_per_s=n_samples / t_total, residual_rms=rms, noise_rms=sigma * math.sqrt(2),
+               bytes_per_sample_pass=float(np.mean(pass_bytes(vis, p.chain[0]))) / max(
+                   float(np.mean(interval_samples(vis, p.chain[0]))), 1.0))
     log(f"chain: delay init {1e3 * t_delay:.1f} ms; " + "; ".join(
         f"{d['term']}{d['epoch']} {d['ms']:.0f} ms it {d['mean_iterations']:.1f} parts {d['split_parts']}"
         for d in terms) + f"; total {t_total:.2f} s; residual rms {rms:.4f} (noise {sigma * math.sqrt(2):.4f})")
+    del resid
+    out["predicted_model"] = chain_predicted(ctx, p, k_start, n_epoch, stream)
+    return out
+
+
+def chain_predicted(ctx, p, k_start, n_epoch, stream):
+    """The same chain solve with the model predicted inside every pass from the 20 point
+    components (qc_solve_interval_sky / qc_residual_sky) instead of read: per sample and
+    pass 32 B data + 16 B weights + 1 B flag (+ 24 B of baseline coordinates per row) against
+    the 177 B with the stored 4-direction model; from the same delay start."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+
+    vis = p.vis
+    dev = vis.data.device
+    lm, fl, dr = [], [], []
+    for d, (l, m, flux) in enumerate(p.meta["sky"]):
+        lm.append(torch.stack([torch.as_tensor(l, dtype=torch.float64, device=dev).reshape(-1),
+                               torch.as_tensor(m, dtype=torch.float64, device=dev).reshape(-1)], -1))
+        fl.append(torch.as_tensor(flux, dtype=torch.float64, device=dev).reshape(-1))
+        dr.append(torch.full((fl[-1].numel(),), d, dtype=torch.int32, device=dev))
+    lm, fl, dr = torch.cat(lm).contiguous(), torch.cat(fl), torch.cat(dr).contiguous()
+    n_comp = int(fl.numel())
+    stokes = torch.zeros(n_comp, 4, dtype=torch.float64, device=dev)
+    stokes[:, 0] = fl
+    sky = qc.Sky(lm=lm, stokes=stokes, spi=torch.zeros(n_comp, dtype=torch.float64, device=dev),
+                 ref_freq=torch.full((n_comp,), 1.4e9, dtype=torch.float64, device=dev), comp_dir=dr,
+                 uvw=p.meta["uvw"].to(torch.float64).contiguous(), n_dir=len(p.meta["sky"]))
+    vis_s = vis.copy(model=None)
+    chain = [qc.device_term(t, dev) for t in p.chain]
+    chain[0].params.copy_(k_start)
+    n_samples = int(vis.data.shape[0]) * int(vis.data.shape[1])
+    n_rows = int(vis.data.shape[0])
+    per_sample = 32 + 4 * int(vis.weight.shape[2]) + 1
+    terms = []
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for e in range(n_epoch):
+        for n, t in enumerate(chain):
+            t1 = time.perf_counter()
+            st = ctx.solve_sky(vis_s, sky, chain, n, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t1)
+            it = st["iters"].cpu().numpy()
+            n_int = int(t.n_gt * t.n_gf)
+            gb = float(np.maximum(it, 1).mean()) * (n_samples * per_sample + n_rows * 24 * int(t.n_gf)) / 1e9
+            terms.append(dict(epoch=e, term=t.name, split_parts=int(ctx.last_split_parts()), ms=ms,
+                              mean_iterations=float(it.mean()),
+                              converged=float(st["converged"].float().mean().item()), algorithmic_gb=gb))
+    t2 = time.perf_counter()
+    resid = ctx.residual_sky(vis_s, sky, chain, stream=stream)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    use = (vis.flag == 0)
+    rms = float(torch.sqrt((resid.abs() ** 2).sum(-1)[use].mean() / 4).item())
+    out = dict(components=n_comp, bytes_per_sample_pass=per_sample, terms=terms, residual_ms=1e3 * (t_end - t2),
+               total_s=t_end - ts, vis_per_s=n_samples / (t_end - ts), residual_rms=rms)
+    log("chain, predicted model: " + "; ".join(
+        f"{d['term']}{d['epoch']} {d['ms']:.0f} ms it {d['mean_iterations']:.1f}" for d in terms) +
+        f"; residual {1e3 * (t_end - t2):.1f} ms; total {t_end - ts:.2f} s; residual rms {rms:.4f}")
     return out
 
 

@@ -433,6 +433,33 @@ qc_status qc_predict_dft(qc_ctx* ctx, const double* uvw, int64_t n_row, const do
                          const qc_sky* sky, int32_t n_dir, qc_dtype dtype, void* model_out, void* stream);
 
 /*
+ * The solve and outputs with the model predicted inside their passes (paper
+ * Section 4.7, "Additional Features": component models predicted with the
+ * DFT, here on the fly): every pass evaluates, per sample and model direction,
+ * the direct Fourier sum of qc_predict_dft from the sky's components instead
+ * of reading vis->model, which is not read and may be NULL (vis->n_dir gives
+ * the directions; component directions must lie in [0, n_dir)).  uvw
+ * [n_row][3] double (device, metres) are the rows' baseline coordinates.
+ * The phase in turns is formed and reduced to [-1/2, 1/2] in FP64; the
+ * phasor and the sums are in the solve's arithmetic (FP32 in MIXED, as
+ * qc_predict_dft's complex64 output; FP64 otherwise).  Otherwise the calls
+ * take the arguments and give the results of qc_solve_interval and
+ * qc_residual / qc_apply_gains(CORRUPT).  The solve takes a single term with
+ * one direction, or a chain whose terms are all DIAGONAL / DELAY / PHASE /
+ * AMPLITUDE / DELAY_OFFSET / POINTING, with an active term that is not
+ * POINTING and damping other than LM (QC_E_UNSUPPORTED otherwise); the
+ * outputs take any chain.  The sky is checked and ordered as in
+ * qc_predict_dft (the call waits for `stream` once to read it).
+ */
+qc_status qc_solve_interval_sky(qc_ctx* ctx, const qc_vis* vis, const qc_sky* sky, const double* uvw,
+                                qc_term* chain, int32_t n_term, int32_t active, const qc_solve_opts* opts,
+                                qc_solve_stats* stats);
+qc_status qc_residual_sky(qc_ctx* ctx, const qc_vis* vis, const qc_sky* sky, const double* uvw,
+                          const qc_term* chain, int32_t n_term, const uint8_t* dir_mask, void* out, void* stream);
+qc_status qc_corrupt_sky(qc_ctx* ctx, const qc_vis* vis, const qc_sky* sky, const double* uvw,
+                         const qc_term* chain, int32_t n_term, const uint8_t* dir_mask, void* out, void* stream);
+
+/*
  * Learned warm start (a two-layer MLP from interval features to initial
  * diagonal gains), all FP32 unless stated.  Parameters are one flat array
  * [W1 (n_hid x n_in) | b1 (n_hid) | W2 (n_out x n_hid) | b2 (n_out)],

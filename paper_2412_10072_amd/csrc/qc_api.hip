@@ -63,7 +63,7 @@ __global__ void k_ranges(const long long* rowpos, const int* tt, int n_gt, long 
 // host checks
 // ---------------------------------------------------------------------------
 
-qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
+qc_status check_vis(qc_ctx* ctx, const qc_vis* v, bool need_model) {
   if (!v) return fail(ctx, QC_E_ARG, "vis is NULL");
   if (v->n_row < 0 || v->n_chan <= 0 || v->n_dir <= 0 || v->n_ant <= 0 || v->n_time <= 0)
     return fail(ctx, QC_E_ARG, "bad sizes: n_row=%lld n_chan=%d n_dir=%d n_ant=%d n_time=%d",
@@ -72,7 +72,8 @@ qc_status check_vis(qc_ctx* ctx, const qc_vis* v) {
   if (v->n_ant > QC_MAX_ANT) return fail(ctx, QC_E_UNSUPPORTED, "n_ant=%d exceeds %d", v->n_ant, QC_MAX_ANT);
   if (v->n_wcorr != 1 && v->n_wcorr != 4) return fail(ctx, QC_E_ARG, "n_wcorr must be 1 or 4, got %d", v->n_wcorr);
   if (v->dtype != QC_C64 && v->dtype != QC_C128) return fail(ctx, QC_E_ARG, "bad dtype %d", (int)v->dtype);
-  if (v->n_row > 0 && (!v->data || !v->model || !v->weight || !v->flag || !v->ant1 || !v->ant2 || !v->row_time))
+  if (v->n_row > 0 && (!v->data || (need_model && !v->model) || !v->weight || !v->flag || !v->ant1 || !v->ant2 ||
+                       !v->row_time))
     return fail(ctx, QC_E_ARG, "a visibility array pointer is NULL");
   if (!v->chan_freq) return fail(ctx, QC_E_ARG, "chan_freq is NULL");
   return QC_OK;
@@ -184,7 +185,7 @@ qc_status read_err(qc_ctx* ctx, hipStream_t s) {
 // Validates the rows on the device and (when active >= 0) computes the row
 // and channel ranges of every solution interval of the active term.
 qc_status validate_rows(qc_ctx* ctx, const qc_vis* v, hipStream_t s) {
-  qc_status st = check_vis(ctx, v);
+  qc_status st = check_vis(ctx, v, true);
   if (st != QC_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   VisArgs va;
@@ -201,8 +202,8 @@ qc_status validate_rows(qc_ctx* ctx, const qc_vis* v, hipStream_t s) {
 }
 
 qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
-                  std::vector<HostMaps>& maps, hipStream_t s, const PrepScratch* fixed) {
-  qc_status st = check_vis(ctx, v);
+                  std::vector<HostMaps>& maps, hipStream_t s, const PrepScratch* fixed, bool need_model) {
+  qc_status st = check_vis(ctx, v, need_model);
   if (st != QC_OK) return st;
   if (!chain || n_term <= 0) return fail(ctx, QC_E_ARG, "empty chain");
   if (n_term > QC_MAX_TERMS) return fail(ctx, QC_E_UNSUPPORTED, "n_term=%d exceeds %d", n_term, QC_MAX_TERMS);
@@ -432,10 +433,12 @@ double qc_last_kernel_ms(qc_ctx* ctx) {
 }  // extern "C"
 
 // qc_solve_interval; fixed != NULL: the allocation-free form (prepare scratch
-// in `fixed`, always the fused schedule, no fixed-factor table, no pointing)
+// in `fixed`, always the fused schedule, no fixed-factor table, no pointing);
+// sky != NULL: the model predicted from point components in the passes
 static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
                                      int32_t active, const qc_solve_opts* opts, qc_solve_stats* stats,
-                                     const PrepScratch* fixed) {
+                                     const PrepScratch* fixed, const qc_sky* sky = nullptr,
+                                     const double* uvw = nullptr) {
   if (!ctx) return QC_E_ARG;
   if (!opts) return fail(ctx, QC_E_ARG, "opts is NULL");
   if (!chain || n_term <= 0 || active < 0 || active >= n_term)
@@ -451,9 +454,28 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
   ctx->last_stream = s;
   if (fixed && chain[active].type == QC_TERM_POINTING)
     return fail(ctx, QC_E_UNSUPPORTED, "the allocation-free solve takes no active POINTING term");
+  if (sky) {
+    if (!uvw && vis && vis->n_row > 0) return fail(ctx, QC_E_ARG, "uvw is NULL");
+    bool diag = true;
+    for (int j = 0; j < n_term; ++j)
+      if (chain[j].type == QC_TERM_COMPLEX2X2) diag = false;
+    const bool single = vis && n_term == 1 && vis->n_dir == 1 && chain[active].n_gdir == 1;
+    if (!single && !diag)
+      return fail(ctx, QC_E_UNSUPPORTED, "the predicted model takes a single term or a chain of diagonal terms");
+    if (chain[active].type == QC_TERM_POINTING)
+      return fail(ctx, QC_E_UNSUPPORTED, "the predicted model takes no active POINTING term");
+    if (opts->damping == QC_DAMP_LM)
+      return fail(ctx, QC_E_UNSUPPORTED, "the predicted model takes no Levenberg-Marquardt damping");
+  }
   std::vector<HostMaps> maps;
-  qc_status st = prepare(ctx, vis, chain, n_term, active, maps, s, fixed);
+  qc_status st = prepare(ctx, vis, chain, n_term, active, maps, s, fixed, sky == nullptr);
   if (st != QC_OK) return st;
+  SkyArgs sk;
+  memset(&sk, 0, sizeof sk);
+  if (sky) {
+    st = prepare_sky(ctx, sky, vis->n_dir, uvw, s, sk);
+    if (st != QC_OK) return st;
+  }
   if (chain[active].type == QC_TERM_POINTING)
     return solve_pointing(ctx, vis, chain, n_term, active, opts, stats, s);
   SolveLaunch L;
@@ -489,6 +511,7 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
     L.restarted = stats->restarted;
   }
   L.chisq_ref = opts->chisq_ref;
+  L.sky = sk;
   L.tol = opts->tol;
   L.max_iter = opts->max_iter;
   L.damping = resolve_damping(opts->damping, ta);
@@ -590,6 +613,14 @@ extern "C" {
 qc_status qc_solve_interval(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term, int32_t active,
                             const qc_solve_opts* opts, qc_solve_stats* stats) {
   return solve_interval_impl(ctx, vis, chain, n_term, active, opts, stats, nullptr);
+}
+
+qc_status qc_solve_interval_sky(qc_ctx* ctx, const qc_vis* vis, const qc_sky* sky, const double* uvw,
+                                qc_term* chain, int32_t n_term, int32_t active, const qc_solve_opts* opts,
+                                qc_solve_stats* stats) {
+  if (!ctx) return QC_E_ARG;
+  if (!sky) return fail(ctx, QC_E_ARG, "sky is NULL");
+  return solve_interval_impl(ctx, vis, chain, n_term, active, opts, stats, nullptr, sky, uvw);
 }
 
 qc_status qc_solve_interval_static(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int32_t n_term,
@@ -817,14 +848,22 @@ qc_status qc_ws_labels(qc_ctx* ctx, const void* gains, int32_t n_int, int32_t n_
 }
 
 static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term, int mode,
-                                const uint8_t* dir_mask, void* out, void* stream) {
+                                const uint8_t* dir_mask, void* out, void* stream, const qc_sky* sky = nullptr,
+                                const double* uvw = nullptr) {
   if (!ctx) return QC_E_ARG;
   if (!out) return fail(ctx, QC_E_ARG, "out is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   ctx->last_stream = s;
+  if (sky && !uvw && vis && vis->n_row > 0) return fail(ctx, QC_E_ARG, "uvw is NULL");
   std::vector<HostMaps> maps;
-  qc_status st = prepare(ctx, vis, chain, n_term, -1, maps, s);
+  qc_status st = prepare(ctx, vis, chain, n_term, -1, maps, s, nullptr, sky == nullptr);
   if (st != QC_OK) return st;
+  SkyArgs sk;
+  memset(&sk, 0, sizeof sk);
+  if (sky) {
+    st = prepare_sky(ctx, sky, vis->n_dir, uvw, s, sk);
+    if (st != QC_OK) return st;
+  }
   if (mode == 1 || mode == 3) {
     for (int j = 0; j < n_term; ++j)
       if (!dmap_constant(maps[j]) || chain[j].type == QC_TERM_POINTING)
@@ -846,6 +885,7 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
   L.out = out;
   L.w_vec = mode == 3 && vis->n_wcorr == 4 && reinterpret_cast<uintptr_t>(vis->weight) % 16 == 0 &&
             reinterpret_cast<uintptr_t>(out) % 16 == 0;
+  L.sky = sk;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   HIP_TRY(ctx, launch_outputs(L, s));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
@@ -867,6 +907,20 @@ qc_status qc_residual(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int3
 qc_status qc_corrected_weights(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                                void* weight_out, void* stream) {
   return outputs_common(ctx, vis, chain, n_term, 3, nullptr, weight_out, stream);
+}
+
+qc_status qc_residual_sky(qc_ctx* ctx, const qc_vis* vis, const qc_sky* sky, const double* uvw,
+                          const qc_term* chain, int32_t n_term, const uint8_t* dir_mask, void* out, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!sky) return fail(ctx, QC_E_ARG, "sky is NULL");
+  return outputs_common(ctx, vis, chain, n_term, 2, dir_mask, out, stream, sky, uvw);
+}
+
+qc_status qc_corrupt_sky(qc_ctx* ctx, const qc_vis* vis, const qc_sky* sky, const double* uvw,
+                         const qc_term* chain, int32_t n_term, const uint8_t* dir_mask, void* out, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (!sky) return fail(ctx, QC_E_ARG, "sky is NULL");
+  return outputs_common(ctx, vis, chain, n_term, 0, dir_mask, out, stream, sky, uvw);
 }
 
 }  // extern "C"

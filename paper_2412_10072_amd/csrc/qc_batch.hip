@@ -62,6 +62,7 @@ __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
     J.restarted = P.restarted;
     J.partial = nullptr;
     J.otab = nullptr;
+    J.sky = nullptr;
     if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, true, 1, RPS>(J);
     else solve_interval<KIND_C2X2, S, T, true, 1, RPS>(J);
   }

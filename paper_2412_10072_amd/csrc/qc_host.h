@@ -144,8 +144,10 @@ struct PrepScratch {
 // (active >= 0) computes the interval ranges of the active term, into `fixed`
 // when given, else into the context's scratch (grown as needed); waits for
 // the device checks.
+// need_model false: vis->model may be NULL (a model predicted from a sky).
 qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term, int active,
-                  std::vector<HostMaps>& maps, hipStream_t s, const PrepScratch* fixed = nullptr);
+                  std::vector<HostMaps>& maps, hipStream_t s, const PrepScratch* fixed = nullptr,
+                  bool need_model = true);
 void fill_args(const qc_vis* v, const qc_term* chain, int n_term, int active, VisArgs& va, ChainArgs& ca);
 qc_status read_err(qc_ctx* ctx, hipStream_t s);
 // check_vis plus the device checks of row order and antenna/time ranges
@@ -156,5 +158,9 @@ int resolve_damping(qc_damping d, const qc_term& t);
 qc_status solve_pointing(qc_ctx* ctx, const qc_vis* vis, qc_term* chain, int n_term, int active,
                          const qc_solve_opts* opts, qc_solve_stats* stats, hipStream_t s);
 bool dmap_constant(const HostMaps& hm);
+// Checks a point-component sky and prepares its table (direction order, the
+// context's memory) for n_dir model directions; uvw [n_row][3] (device) is
+// carried along.  Waits for `s`.
+qc_status prepare_sky(qc_ctx* ctx, const qc_sky* sky, int n_dir, const double* uvw, hipStream_t s, SkyArgs& out);
 
 }  // namespace qc

@@ -272,6 +272,79 @@ __device__ __forceinline__ m22<T> chain_range(const ChainArgs& ch, int n_ant, in
 }
 
 // ---------------------------------------------------------------------------
+// point-component sky (DFT prediction of the model, eq. baselinemodel's M)
+// ---------------------------------------------------------------------------
+
+// One prepared point component, in direction order.
+struct PComp {
+  double l, m, nm1;        // direction cosines and n - 1
+  double lc, mc, nc;       // l, m, n - 1 divided by the speed of light (s/m)
+  double lnu0;             // log2 of the reference frequency
+  double alpha;            // spectral index
+  double bxx, byy, bu, bv; // I + Q, I - Q, U, V
+  float fxx, fyy, fu, fv;  // the same in FP32
+  int pol;                 // any of Q, U, V nonzero (cross hands predicted)
+  int pad;
+};
+
+// A sky for the solver and output passes: comp == null means the model is
+// read from the visibility set instead.
+struct SkyArgs {
+  const PComp* comp;       // direction order
+  const int* off;          // [n_dir + 1] first component of each direction
+  const double* uvw;       // [n_row][3] baseline coordinates (m)
+  int spectral;            // any spectral index nonzero
+  int polarised;           // any component with Q, U or V
+};
+
+// Model of direction d at one sample, sum over the direction's components of
+// B_c (nu / nu0_c)^alpha_c exp(-2 pi i nu (u l + v m + w (n - 1)) / c0), with
+// (un, vn, wn) = nu (u, v, w) the baseline in wavelengths and lnu = log2(nu)
+// (read only for a spectral sky).  The phase in turns is formed and reduced in
+// FP64; the phasor and the sums are in T.  d, and so every component read, is
+// uniform over the wavefront: the table is read through the scalar cache.
+template <typename T>
+__device__ __forceinline__ m22<T> sky_model(const SkyArgs& K, double un, double vn, double wn, double lnu, int d) {
+  using CP = const __attribute__((address_space(4))) PComp*;
+  using IP = const __attribute__((address_space(4))) int*;
+  const CP tab = (CP)K.comp;
+  const int k0 = ((IP)K.off)[d], k1 = ((IP)K.off)[d + 1];
+  T xr = T(0), xi = T(0), pr = T(0), pi = T(0), qr = T(0), qi = T(0), yr = T(0), yi = T(0);
+  for (int k = k0; k < k1; ++k) {
+    const double x = fma(un, tab[k].lc, fma(vn, tab[k].mc, wn * tab[k].nc));   // turns
+    const cx<T> e = phasor_turns<T>(-x);                                        // exp(-2 pi i x)
+    T kr = e.re, ki = e.im;
+    if (K.spectral) {
+      const double a = tab[k].alpha;
+      if (a != 0.0) {
+        T sp;
+        if constexpr (sizeof(T) == 4) sp = exp2f((float)(a * (lnu - tab[k].lnu0)));
+        else sp = exp2(a * (lnu - tab[k].lnu0));
+        kr *= sp;
+        ki *= sp;
+      }
+    }
+    T bxx, byy;
+    if constexpr (sizeof(T) == 4) { bxx = tab[k].fxx; byy = tab[k].fyy; }
+    else { bxx = tab[k].bxx; byy = tab[k].byy; }
+    xr = fma(bxx, kr, xr);
+    xi = fma(bxx, ki, xi);
+    yr = fma(byy, kr, yr);
+    yi = fma(byy, ki, yi);
+    if (K.polarised && tab[k].pol) {
+      T bu, bv;
+      if constexpr (sizeof(T) == 4) { bu = tab[k].fu; bv = tab[k].fv; }
+      else { bu = tab[k].bu; bv = tab[k].bv; }
+      pr += bu * kr - bv * ki;          // (U + iV) K
+      pi += bu * ki + bv * kr;
+      qr += bu * kr + bv * ki;          // (U - iV) K
+      qi += bu * ki - bv * kr;
+    }
+  }
+  return {cmake<T>(xr, xi), cmake<T>(pr, pi), cmake<T>(qr, qi), cmake<T>(yr, yi)};
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers implemented in the kernel translation units
 // ---------------------------------------------------------------------------
 
@@ -305,6 +378,7 @@ struct SolveLaunch {
   int rows_per_step;          // 0: the kernel default
   const double* chisq_ref;    // may be null
   uint8_t* restarted;         // may be null
+  SkyArgs sky;                // sky.comp non-null: the model is predicted from it per sample
   // diagonal chains: product of the direction-independent terms other than
   // the active one, [n_time][n_ant][n_chan][2 hands] complex of the compute
   // precision, or null (then formed per sample)
@@ -402,6 +476,7 @@ struct OutputLaunch {
   int diag_chain;             // every chain term is diagonal or a delay
   int w_vec;                  // corrected weights: 4 per sample, weights and out 16-byte aligned
   void* out;
+  SkyArgs sky;                // sky.comp non-null: the model is predicted from it per sample
 };
 
 hipError_t launch_outputs(const OutputLaunch& L, hipStream_t stream);

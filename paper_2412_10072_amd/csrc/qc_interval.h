@@ -788,6 +788,7 @@ struct Job {
   uint8_t* restarted;        // per interval: 1 if that restart happened
   double* partial;           // pass-only mode: [slot values + 1] FP64 blocks and chi^2 of these rows
   const void* otab;          // diagonal chains: fixed direction-independent factors, or null
+  const SkyArgs* sky;        // the model's components (kernels built to predict it), else unused
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
@@ -1081,7 +1082,11 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
 //         J.gains; the FP64 blocks and chi^2 go to J.partial (split schedule).
 // LMT:    Levenberg-Marquardt damping (kernels of their own, so that the
 //         Gauss-Newton kernels carry none of its state).
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false, bool LMT = false>
+// SKY:    the model of each sample is predicted from J.sky's point components
+//         (a direct Fourier sum per direction) instead of read from the
+//         visibility set: single-term and diagonal-chain evaluation.
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false, bool LMT = false,
+          bool SKY = false>
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
@@ -1089,6 +1094,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   constexpr bool FB = (CHM == CHAIN_LEFT);   // full blocks (any left factor)
   static_assert(!DIAGC || KIND != KIND_C2X2, "a diagonal chain has no full-Jones term");
   static_assert(!FB || RPS == 1, "the full-block kernel takes one row per wavefront step");
+  static_assert(!SKY || SINGLE || DIAGC, "the predicted model is built into the single and diagonal chains");
   constexpr bool KAHAN = (sizeof(T) == 4);
   constexpr int NV = nv_of<KIND, FB>();
   constexpr int NVG = NV * NG;
@@ -1248,6 +1254,13 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       int q = V.ant2[r];
       const int t = V.row_time[r];
       const bool row_ok = r_in && p != q && (unsigned)p < (unsigned)n_ant && (unsigned)q < (unsigned)n_ant;
+      // baseline coordinates of the row (predicted model)
+      double ru = 0.0, rv = 0.0, rw = 0.0;
+      if constexpr (SKY) {
+        ru = J.sky->uvw[3 * r];
+        rv = J.sky->uvw[3 * r + 1];
+        rw = J.sky->uvw[3 * r + 2];
+      }
       if constexpr (RPS == 1) {
         if (!row_ok) continue;               // uniform over the wave
       } else {
@@ -1295,6 +1308,17 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
         const T tpn = (T)((pk == KIND_DELAY || KIND == KIND_DELOFF) ? TWO_PI * nu : 1.0);
         w0 = use ? w0 : T(0); w1 = use ? w1 : T(0); w2 = use ? w2 : T(0); w3 = use ? w3 : T(0);
         const m22<T> D = select_m(use, Draw);
+        // the model of direction d at this sample: read, or predicted from the
+        // components with the baseline in wavelengths
+        const double un = ru * nu, vn = rv * nu, wn = rw * nu;
+        double lnu = 0.0;
+        if constexpr (SKY) {
+          if (J.sky->spectral) lnu = log2(nu);
+        }
+        auto model_at = [&](int d) -> m22<T> {
+          if constexpr (SKY) return sky_model<T>(*J.sky, un, vn, wn, lnu, d);
+          else return load_m22<S, T>(Mp, s * n_dir + d);
+        };
 
         if constexpr (SINGLE) {
           // chain = the active term alone: C_p = G_p, C_q = G_q
@@ -1311,7 +1335,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
               Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
             }
           }
-          const m22<T> M = select_m(use, load_m22<S, T>(Mp, s));
+          const m22<T> M = select_m(use, model_at(0));
           const m22<T> B = mmul_h(M, Gq);        // M G_q^H
           const m22<T> GM = mmul(Gp, M);         // G_p M
           const m22<T> R = msub_mul(D, Gp, B);   // D - G_p M G_q^H
@@ -1382,14 +1406,14 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           // two directions at a time keep a third wavefront per SIMD, except in
           // the diagonal split pass, whose kernel is built for three wavefronts
           // per SIMD with four.
-          constexpr int MCH = sizeof(T) != 4                                   ? 1
+          // (A predicted model has no line to keep: one direction at a time.)
+          constexpr int MCH = (SKY || sizeof(T) != 4)                          ? 1
                               : LANE_ROWS && !(PASS_ONLY && KIND == KIND_DIAG) ? 2
                                                                                : 4;
           for (int d0 = 0; d0 < n_dir; d0 += MCH) {
             m22<T> Mc[MCH];
 #pragma unroll
-            for (int k = 0; k < MCH; ++k)
-              Mc[k] = load_m22<S, T>(Mp, s * n_dir + min(d0 + k, n_dir - 1));
+            for (int k = 0; k < MCH; ++k) Mc[k] = model_at(min(d0 + k, n_dir - 1));
             for (int k = 0; k < MCH && d0 + k < n_dir; ++k) {
               const int d = d0 + k;
               const int gd = NG == 1 ? 0 : TA.d_map[d];

@@ -106,8 +106,9 @@ __device__ __forceinline__ void corrected_weight(const VisArgs& V, size_t s, cx<
 
 // DIAG: every term is diagonal or a delay, so each chain product is a pair
 // of complex numbers and the direction-independent part is formed once per
-// sample.
-template <typename S, int MODE, bool DIAG>
+// sample.  SKY (CORRUPT and RESIDUAL): the model is predicted per sample from
+// L.sky's point components instead of read.
+template <typename S, int MODE, bool DIAG, bool SKY = false>
 __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
   using T = S;
   const VisArgs& V = L.vis;
@@ -125,6 +126,18 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
     const int p = V.ant1[r], q = V.ant2[r], t = V.row_time[r];
     if ((unsigned)p >= (unsigned)V.n_ant || (unsigned)q >= (unsigned)V.n_ant) continue;
     const double nu = V.freq[c];
+    // the model of direction d: read, or predicted with the baseline in wavelengths
+    double un = 0.0, vn = 0.0, wn = 0.0, lnu = 0.0;
+    if constexpr (SKY) {
+      un = L.sky.uvw[3 * r] * nu;
+      vn = L.sky.uvw[3 * r + 1] * nu;
+      wn = L.sky.uvw[3 * r + 2] * nu;
+      if (L.sky.spectral) lnu = log2(nu);
+    }
+    auto model_at = [&](int d) -> m22<T> {
+      if constexpr (SKY) return sky_model<T>(L.sky, un, vn, wn, lnu, d);
+      else return ld<S, T>(Mp, s * V.n_dir + d);
+    };
     if constexpr (DIAG) {
       cx<T> p0 = cone<T>(), p1 = cone<T>(), q0 = cone<T>(), q1 = cone<T>();
       diag_part<T, false>(CH, V.n_ant, t, c, p, 0, nu, p0, p1);
@@ -154,11 +167,12 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
         // directions in one 128-byte line): read four at a time (clamped
         // index, no branch) so that the line is not evicted and fetched again
         // between the per-direction chain evaluations. One at a time in FP64.
-        constexpr int MCH = sizeof(T) == 4 ? 4 : 1;
+        // A predicted model is formed per direction as it is used.
+        constexpr int MCH = (sizeof(T) == 4 && !SKY) ? 4 : 1;
         for (int d0 = 0; d0 < V.n_dir; d0 += MCH) {
           m22<T> Mc[MCH];
 #pragma unroll
-          for (int k = 0; k < MCH; ++k) Mc[k] = ld<S, T>(Mp, s * V.n_dir + min(d0 + k, V.n_dir - 1));
+          for (int k = 0; k < MCH; ++k) Mc[k] = model_at(min(d0 + k, V.n_dir - 1));
 #pragma unroll
           for (int k = 0; k < MCH; ++k) {
             const int d = d0 + k;
@@ -194,7 +208,7 @@ __global__ void __launch_bounds__(256) k_outputs(OutputLaunch L) {
         if (!((L.dir_mask >> d) & 1u)) continue;
         const m22<T> Cp = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, p, d, nu);
         const m22<T> Cq = chain_range<T>(CH, V.n_ant, 0, CH.n_term, t, c, q, d, nu);
-        Vm = Vm + mmul_h(mmul(Cp, ld<S, T>(Mp, s * V.n_dir + d)), Cq);
+        Vm = Vm + mmul_h(mmul(Cp, model_at(d)), Cq);
       }
       if constexpr (MODE == 2) Vm = ld<S, T>(Dp, s) - Vm;
       st<S, T>(Op, s, Vm);
@@ -209,6 +223,17 @@ hipError_t launch_s(const OutputLaunch& L, hipStream_t stream) {
   size_t blocks = ((size_t)L.vis.n_row + 3) / 4;     // 4 wavefronts of one row each
   if (blocks > 256 * 64) blocks = 256 * 64;
   const dim3 g((unsigned)blocks), b(256);
+  if (L.sky.comp) {
+    if (L.mode != 0 && L.mode != 2) return hipErrorNotSupported;
+    if (L.diag_chain) {
+      if (L.mode == 0) hipLaunchKernelGGL((k_outputs<S, 0, true, true>), g, b, 0, stream, L);
+      else hipLaunchKernelGGL((k_outputs<S, 2, true, true>), g, b, 0, stream, L);
+    } else {
+      if (L.mode == 0) hipLaunchKernelGGL((k_outputs<S, 0, false, true>), g, b, 0, stream, L);
+      else hipLaunchKernelGGL((k_outputs<S, 2, false, true>), g, b, 0, stream, L);
+    }
+    return hipGetLastError();
+  }
   if (L.diag_chain) {
     switch (L.mode) {
       case 0: hipLaunchKernelGGL((k_outputs<S, 0, true>), g, b, 0, stream, L); break;

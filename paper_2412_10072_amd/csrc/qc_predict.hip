@@ -33,16 +33,6 @@ namespace {
 
 constexpr double INV_C0 = 1.0 / 299792458.0;   // s/m
 
-struct PComp {
-  double l, m, nm1;        // direction cosines and n - 1
-  double lnu0;             // log2 of the reference frequency
-  double alpha;            // spectral index
-  double bxx, byy, bu, bv; // I + Q, I - Q, U, V
-  float fxx, fyy, fu, fv;  // the same in FP32
-  int pol;                 // any of Q, U, V nonzero (cross hands predicted)
-  int pad;
-};
-
 struct PredictArgs {
   const double* uvw;
   long long n_row;
@@ -63,6 +53,9 @@ __global__ void k_sky_prep(const double* lm, const double* stokes, const double*
   p.l = l;
   p.m = m;
   p.nm1 = -r2 / (1.0 + n);
+  p.lc = l * INV_C0;
+  p.mc = m * INV_C0;
+  p.nc = p.nm1 * INV_C0;
   p.lnu0 = log2(ref_freq[c]);
   p.alpha = spi[c];
   const double I = stokes[4 * c], Q = stokes[4 * c + 1], U = stokes[4 * c + 2], V = stokes[4 * c + 3];
@@ -179,41 +172,32 @@ __global__ void __launch_bounds__(256) k_predict(PredictArgs P, const PComp* __r
 }
 
 }  // namespace
-}  // namespace qc
 
-using namespace qc;
-
-extern "C" {
-
-qc_status qc_predict_dft(qc_ctx* ctx, const double* uvw, int64_t n_row, const double* chan_freq, int32_t n_chan,
-                         const qc_sky* sky, int32_t n_dir, qc_dtype dtype, void* model_out, void* stream) {
-  if (!ctx) return QC_E_ARG;
+qc_status prepare_sky(qc_ctx* ctx, const qc_sky* sky, int n_dir, const double* uvw, hipStream_t s, SkyArgs& out) {
   if (!sky) return fail(ctx, QC_E_ARG, "sky is NULL");
-  if (n_row < 0 || n_chan < 0 || n_dir < 1 || sky->n_comp < 0)
-    return fail(ctx, QC_E_ARG, "bad sizes: n_row=%lld n_chan=%d n_dir=%d n_comp=%lld", (long long)n_row, n_chan,
-                n_dir, (long long)sky->n_comp);
-  if (dtype != QC_C64 && dtype != QC_C128) return fail(ctx, QC_E_ARG, "bad dtype %d", (int)dtype);
-  const bool work = n_row > 0 && n_chan > 0;
-  if (work && (!uvw || !chan_freq || !model_out)) return fail(ctx, QC_E_ARG, "uvw, chan_freq or model_out is NULL");
+  if (sky->n_comp < 0) return fail(ctx, QC_E_ARG, "bad n_comp=%lld", (long long)sky->n_comp);
   const long long n_comp = sky->n_comp;
   if (n_comp > 0 && (!sky->lm || !sky->stokes || !sky->spi || !sky->ref_freq || !sky->dir))
     return fail(ctx, QC_E_ARG, "a sky array is NULL");
   if (n_comp > (long long)INT32_MAX) return fail(ctx, QC_E_ARG, "n_comp=%lld too large", n_comp);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  ctx->last_stream = s;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
 
   // Component checks and the direction order (stable: array order within a
   // direction), on the host from copies of the small per-component arrays.
   std::vector<int> dir((size_t)n_comp);
-  std::vector<double> lm((size_t)n_comp * 2), nu0((size_t)n_comp);
+  std::vector<double> lm((size_t)n_comp * 2), nu0((size_t)n_comp), stokes((size_t)n_comp * 4),
+      spi((size_t)n_comp);
   if (n_comp > 0) {
     HIP_TRY(ctx, hipMemcpyAsync(dir.data(), sky->dir, dir.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(lm.data(), sky->lm, lm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(nu0.data(), sky->ref_freq, nu0.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(stokes.data(), sky->stokes, stokes.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                s));
+    HIP_TRY(ctx, hipMemcpyAsync(spi.data(), sky->spi, spi.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
   }
   std::vector<int> off((size_t)n_dir + 1, 0);
+  int spectral = 0, polarised = 0;
   for (long long c = 0; c < n_comp; ++c) {
     if (dir[c] < 0 || dir[c] >= n_dir)
       return fail(ctx, QC_E_RANGE, "component %lld: direction %d outside [0, %d)", c, dir[c], n_dir);
@@ -222,6 +206,8 @@ qc_status qc_predict_dft(qc_ctx* ctx, const double* uvw, int64_t n_row, const do
     if (!(nu0[c] > 0.0) || !std::isfinite(nu0[c]))
       return fail(ctx, QC_E_ARG, "component %lld: reference frequency must be > 0", c);
     ++off[dir[c] + 1];
+    if (spi[c] != 0.0) spectral = 1;
+    if (stokes[4 * c + 1] != 0.0 || stokes[4 * c + 2] != 0.0 || stokes[4 * c + 3] != 0.0) polarised = 1;
   }
   for (int d = 0; d < n_dir; ++d) off[d + 1] += off[d];
   std::vector<int> perm((size_t)std::max<long long>(n_comp, 1));
@@ -243,7 +229,36 @@ qc_status qc_predict_dft(qc_ctx* ctx, const double* uvw, int64_t n_row, const do
   }
   // the host vectors above are the copies' sources: wait before they go
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  out.comp = pc;
+  out.off = d_off;
+  out.uvw = uvw;
+  out.spectral = spectral;
+  out.polarised = polarised;
+  return QC_OK;
+}
+
+}  // namespace qc
+
+using namespace qc;
+
+extern "C" {
+
+qc_status qc_predict_dft(qc_ctx* ctx, const double* uvw, int64_t n_row, const double* chan_freq, int32_t n_chan,
+                         const qc_sky* sky, int32_t n_dir, qc_dtype dtype, void* model_out, void* stream) {
+  if (!ctx) return QC_E_ARG;
+  if (n_row < 0 || n_chan < 0 || n_dir < 1)
+    return fail(ctx, QC_E_ARG, "bad sizes: n_row=%lld n_chan=%d n_dir=%d", (long long)n_row, n_chan, n_dir);
+  if (dtype != QC_C64 && dtype != QC_C128) return fail(ctx, QC_E_ARG, "bad dtype %d", (int)dtype);
+  const bool work = n_row > 0 && n_chan > 0;
+  if (work && (!uvw || !chan_freq || !model_out)) return fail(ctx, QC_E_ARG, "uvw, chan_freq or model_out is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  SkyArgs K;
+  qc_status st = prepare_sky(ctx, sky, n_dir, uvw, s, K);
+  if (st != QC_OK) return st;
   if (!work) return QC_OK;
+  const PComp* pc = K.comp;
+  const int* d_off = K.off;
 
   PredictArgs P;
   P.uvw = uvw;

@@ -48,7 +48,7 @@ namespace {
 template <int CHM, typename T>
 constexpr bool wide_state() { return CHM == CHAIN_LEFT || (CHM == CHAIN_GENERAL && sizeof(T) == 8); }
 
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false, bool SKY = false>
 __global__ void __launch_bounds__((wide_state<CHM, T>() ? 256 : 512)) k_solve_fused(SolveLaunch L) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
@@ -79,7 +79,8 @@ __global__ void __launch_bounds__((wide_state<CHM, T>() ? 256 : 512)) k_solve_fu
   J.chisq_ref = L.chisq_ref;
   J.restarted = L.restarted;
   J.otab = L.otab;
-  solve_interval<KIND, S, T, CHM, NG, RPS, false, LMT>(J);
+  J.sky = &L.sky;
+  solve_interval<KIND, S, T, CHM, NG, RPS, false, LMT, SKY>(J);
 }
 
 // Workgroups go to the 8 XCDs round-robin by block index.  This maps block
@@ -100,11 +101,10 @@ __device__ __forceinline__ unsigned xcd_order(unsigned bid, unsigned n) {
 // repeats pass + update until no interval is active.
 // The diagonal-chain pass with one row per lane reads four model directions
 // at once; held to three wavefronts per SIMD it fits without spilling.
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool SKY = false>
 __global__ void __launch_bounds__((wide_state<CHM, T>() ? 256 : 512))
 __attribute__((amdgpu_waves_per_eu(KIND == KIND_DIAG && CHM == 2 && RPS == 64 && sizeof(T) == 4 ? 3 : 1)))
-k_split_pass(SolveLaunch L, int n_part, double* partials,
-                                                    const uint8_t* done) {
+k_split_pass(SolveLaunch L, int n_part, double* partials, const uint8_t* done) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
   const int n_int = TA.n_gt * n_gf;
@@ -143,7 +143,8 @@ k_split_pass(SolveLaunch L, int n_part, double* partials,
   J.restarted = nullptr;
   J.partial = partials + ((size_t)interval * n_part + part) * stride;
   J.otab = L.otab;
-  solve_interval<KIND, S, T, CHM, NG, RPS, true>(J);
+  J.sky = &L.sky;
+  solve_interval<KIND, S, T, CHM, NG, RPS, true, false, SKY>(J);
 }
 
 template <int KIND, typename T, int NG, bool FB>
@@ -181,6 +182,7 @@ __global__ void __launch_bounds__(256) k_split_update(SolveLaunch L, int n_part,
   J.restarted = L.restarted;       // the split schedule never restarts: written 0
   J.partial = nullptr;
   J.otab = nullptr;
+  J.sky = nullptr;
   split_update<KIND, T, NG, FB>(J, partials + (size_t)interval * n_part * stride, n_part, St);
 }
 
@@ -206,7 +208,7 @@ int fit_waves(int n_ant, int nw, bool lane_rows) {
   return nw;
 }
 
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool SKY = false>
 hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
   constexpr bool FB = CHM == CHAIN_LEFT;
   const int nw = fit_waves<KIND, T, NG, CHM>(L.vis.n_ant, L.waves, RPS == 64);
@@ -214,7 +216,7 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
   const size_t lds_u = interval_lds_bytes<KIND, T, NG, FB>(L.vis.n_ant, 0);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kp = k_split_pass<KIND, S, T, CHM, NG, RPS>;
+  auto kp = k_split_pass<KIND, S, T, CHM, NG, RPS, SKY>;
   auto ku = k_split_update<KIND, T, NG, FB>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kp),
@@ -240,14 +242,14 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
   return hipGetLastError();
 }
 
-template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false>
+template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false, bool SKY = false>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   constexpr bool FB = CHM == CHAIN_LEFT;
   const int nw = fit_waves<KIND, T, NG, CHM>(L.vis.n_ant, L.waves, RPS == 64);
   const size_t lds = interval_lds_bytes<KIND, T, NG, FB>(L.vis.n_ant, nw, RPS == 64);
   if (lds_out) *lds_out = lds;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS, LMT>;
+  auto kern = k_solve_fused<KIND, S, T, CHM, NG, RPS, LMT, SKY>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -291,10 +293,41 @@ hipError_t launch_kind_lm(const SolveLaunch& L, hipStream_t stream, size_t* lds_
   return launch_one<KIND, S, T, CHAIN_GENERAL, 4, 1, true>(L, stream, lds_out);
 }
 
+// The model predicted from a sky (the host admits single-term and diagonal
+// chains, Gauss-Newton damping): the same schedules with the prediction built in.
+template <int KIND, typename S, typename T>
+hipError_t launch_kind_sky(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
+  const ChainArgs& ch = L.chain;
+  const TermArgs& ta = ch.t[ch.active];
+  const bool single = (ch.n_term == 1 && L.vis.n_dir == 1 && ta.n_gdir == 1);
+#define QC_LAUNCH(CHM_, NG_, RPS_)                                                                  \
+  return P ? launch_split_one<KIND, S, T, CHM_, NG_, RPS_, true>(L, *P, stream, lds_out)          \
+           : launch_one<KIND, S, T, CHM_, NG_, RPS_, false, true>(L, stream, lds_out)
+  if (single) {
+    constexpr int NVP = pow2ceil(KindInfo<KIND>::NV);
+    const int rps = L.rows_per_step > 0 ? L.rows_per_step : rows_per_step(L.max_int_chan, NVP);
+    if (rps == 4) { QC_LAUNCH(CHAIN_SINGLE, 1, 4); }
+    if (rps == 2) { QC_LAUNCH(CHAIN_SINGLE, 1, 2); }
+    QC_LAUNCH(CHAIN_SINGLE, 1, 1);
+  }
+  if constexpr (KIND != KIND_C2X2) {
+    if (L.diag_chain) {
+      if (ta.n_gdir == 1) {
+        if (L.max_int_chan <= 4) { QC_LAUNCH(CHAIN_DIAG, 1, 64); }
+        QC_LAUNCH(CHAIN_DIAG, 1, 1);
+      }
+      QC_LAUNCH(CHAIN_DIAG, 4, 1);
+    }
+  }
+#undef QC_LAUNCH
+  return hipErrorNotSupported;
+}
+
 template <int KIND, typename S, typename T>
 hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t stream, size_t* lds_out) {
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
+  if (L.sky.comp) return launch_kind_sky<KIND, S, T>(L, P, stream, lds_out);
   if constexpr (KIND != KIND_DELOFF) {          // (the host offers no LM for delay-and-offset terms)
     if (L.damping == DAMP_LM && !P) return launch_kind_lm<KIND, S, T>(L, stream, lds_out);
   }

@@ -12,6 +12,7 @@ of ``synth.problem`` (Vis, Term) holding such tensors.
 from __future__ import annotations
 
 import ctypes as C
+from dataclasses import dataclass
 import os
 from typing import Optional, Sequence
 
@@ -34,7 +35,8 @@ EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "q
            "qc_batch_create", "qc_batch_tune", "qc_batch_run", "qc_batch_last_ms", "qc_batch_schedule",
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
            "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft", "qc_robust_weights",
-           "qc_corrected_weights", "qc_solve_chain_robust", "qc_interp_term")
+           "qc_corrected_weights", "qc_solve_chain_robust", "qc_interp_term", "qc_solve_interval_sky",
+           "qc_residual_sky", "qc_corrupt_sky")
 MAD_MODES = {"global": 0, "baseline": 1}
 BATCH_BUCKETS = 6
 
@@ -100,6 +102,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_solve_interval.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcTerm), C.c_int32, C.c_int32,
                                       C.POINTER(QcSolveOpts), C.POINTER(QcSolveStats)]
     lib.qc_solve_interval_static.argtypes = lib.qc_solve_interval.argtypes
+    lib.qc_solve_interval_sky.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcSky), C.c_void_p,
+                                          C.POINTER(QcTerm), C.c_int32, C.c_int32, C.POINTER(QcSolveOpts),
+                                          C.POINTER(QcSolveStats)]
+    lib.qc_residual_sky.argtypes = [C.c_void_p, C.POINTER(QcVis), C.POINTER(QcSky), C.c_void_p, C.POINTER(QcTerm),
+                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.qc_corrupt_sky.argtypes = lib.qc_residual_sky.argtypes
     lib.qc_ctx_set_tile.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.qc_ctx_set_split.argtypes = [C.c_void_p, C.c_int32]
     lib.qc_ctx_last_split.argtypes = [C.c_void_p]
@@ -211,7 +219,8 @@ def host_term(term):
     return t
 
 
-def _c_vis(vis) -> QcVis:
+def _c_vis(vis, n_dir: Optional[int] = None) -> QcVis:
+    """vis.model may be None when n_dir is given (a model predicted from a sky)."""
     data = vis.data
     if data.dtype == torch.complex64:
         dtype, wdt = 0, torch.float32
@@ -222,7 +231,10 @@ def _c_vis(vis) -> QcVis:
     n_row, n_chan = int(data.shape[0]), int(data.shape[1])
     if tuple(data.shape) != (n_row, n_chan, 4):
         raise ValueError(f"data must be [n_row][n_chan][4], got {tuple(data.shape)}")
-    if vis.model.dim() != 4 or tuple(vis.model.shape[:2]) != (n_row, n_chan) or vis.model.shape[3] != 4:
+    if vis.model is None:
+        if n_dir is None:
+            raise ValueError("vis.model is None: give the number of model directions")
+    elif vis.model.dim() != 4 or tuple(vis.model.shape[:2]) != (n_row, n_chan) or vis.model.shape[3] != 4:
         raise ValueError(f"model must be [n_row][n_chan][n_dir][4], got {tuple(vis.model.shape)}")
     if vis.weight.dim() != 3 or tuple(vis.weight.shape[:2]) != (n_row, n_chan):
         raise ValueError(f"weight must be [n_row][n_chan][n_wcorr], got {tuple(vis.weight.shape)}")
@@ -233,7 +245,10 @@ def _c_vis(vis) -> QcVis:
             raise ValueError(f"{name} must be [n_row]")
     if tuple(vis.chan_freq.shape) != (n_chan,):
         raise ValueError("chan_freq must be [n_chan]")
-    return QcVis(n_row=n_row, n_chan=n_chan, n_dir=int(vis.model.shape[2]), n_ant=int(vis.n_ant),
+    nd = int(n_dir) if vis.model is None else int(vis.model.shape[2])
+    if n_dir is not None and int(n_dir) != nd:
+        raise ValueError(f"n_dir={n_dir} differs from the model's {nd} directions")
+    return QcVis(n_row=n_row, n_chan=n_chan, n_dir=nd, n_ant=int(vis.n_ant),
                  n_time=int(vis.n_time), n_wcorr=int(vis.weight.shape[2]), dtype=dtype,
                  data=_ptr(data, name="data"), model=_ptr(vis.model, data.dtype, "model"),
                  weight=_ptr(vis.weight, wdt, "weight"), flag=_ptr(vis.flag, torch.uint8, "flag"),
@@ -263,6 +278,31 @@ def _c_chain(chain: Sequence) -> C.Array:
             c.dir_lm = _ptr(t.dir_lm, torch.float64, "dir_lm")
             c.beam_fwhm, c.beam_freq = float(t.beam[0]), float(t.beam[1])
     return arr
+
+
+@dataclass
+class Sky:
+    """Point components on the device: lm [n_comp][2], stokes [n_comp][4] (I, Q, U,
+    V), spi [n_comp], ref_freq [n_comp] float64, comp_dir [n_comp] int32, with the
+    rows' baseline coordinates uvw [n_row][3] float64 and the number of model
+    directions n_dir."""
+    lm: torch.Tensor
+    stokes: torch.Tensor
+    spi: torch.Tensor
+    ref_freq: torch.Tensor
+    comp_dir: torch.Tensor
+    uvw: torch.Tensor
+    n_dir: int
+
+    def c(self) -> "QcSky":
+        n = int(self.lm.shape[0])
+        if tuple(self.lm.shape) != (n, 2) or tuple(self.stokes.shape) != (n, 4) or self.spi.numel() != n \
+                or self.ref_freq.numel() != n or self.comp_dir.numel() != n or self.uvw.dim() != 2 \
+                or self.uvw.shape[1] != 3:
+            raise ValueError("inconsistent component or uvw shapes")
+        return QcSky(n_comp=n, lm=_ptr(self.lm, torch.float64, "lm"), stokes=_ptr(self.stokes, torch.float64, "stokes"),
+                     spi=_ptr(self.spi, torch.float64, "spi"), ref_freq=_ptr(self.ref_freq, torch.float64, "ref_freq"),
+                     dir=_ptr(self.comp_dir, torch.int32, "comp_dir"))
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -362,6 +402,46 @@ class Context:
         fn = self.lib.qc_solve_interval_static if static else self.lib.qc_solve_interval
         self._check(fn(self.h, C.byref(cv), cc, len(chain), int(active), C.byref(opts), C.byref(cs)))
         return stats
+
+    def solve_sky(self, vis, sky: "Sky", chain, active: int = 0, tol: float = 1e-6, max_iter: int = 100,
+                  prec: str = "mixed", damping: str = "auto", stream=None, stats: Optional[dict] = None):
+        """qc_solve_interval_sky: as solve, with the model predicted from `sky` inside the
+        solver's passes (vis.model is not read and may be None)."""
+        dev = vis.data.device
+        term = chain[active] if 0 <= active < len(chain) else None
+        if stats is None:
+            stats = _stats_for(term, dev) if term is not None else _stats_for(_Shape1(), dev)
+        cv = _c_vis(vis, sky.n_dir)
+        cc = _c_chain(chain)
+        opts = QcSolveOpts(tol=float(tol), max_iter=int(max_iter), prec=PRECISIONS[prec],
+                           damping=DAMPINGS[damping], stream=_stream_ptr(stream))
+        cs = _c_stats(stats)
+        csky = sky.c()
+        self._check(self.lib.qc_solve_interval_sky(self.h, C.byref(cv), C.byref(csky),
+                                                   C.c_void_p(_ptr(sky.uvw, torch.float64, "uvw")), cc, len(chain),
+                                                   int(active), C.byref(opts), C.byref(cs)))
+        return stats
+
+    def residual_sky(self, vis, sky: "Sky", chain, dir_mask=None, out=None, stream=None, corrupt: bool = False):
+        """qc_residual_sky (or qc_corrupt_sky): the residual (corrupted model) with the model
+        predicted from `sky`."""
+        if out is None:
+            out = torch.empty_like(vis.data)
+        if tuple(out.shape) != tuple(vis.data.shape) or out.dtype != vis.data.dtype:
+            raise ValueError("out must be shaped and typed like vis.data")
+        mp = None
+        if dir_mask is not None:
+            keep = np.ascontiguousarray(np.asarray(dir_mask, dtype=np.uint8))
+            if keep.size != sky.n_dir:
+                raise ValueError("dir_mask needs one entry per direction")
+            mp = keep.ctypes.data_as(C.c_void_p)
+        cv = _c_vis(vis, sky.n_dir)
+        cc = _c_chain(chain)
+        csky = sky.c()
+        fn = self.lib.qc_corrupt_sky if corrupt else self.lib.qc_residual_sky
+        self._check(fn(self.h, C.byref(cv), C.byref(csky), C.c_void_p(_ptr(sky.uvw, torch.float64, "uvw")), cc,
+                       len(chain), mp, C.c_void_p(out.data_ptr()), C.c_void_p(_stream_ptr(stream))))
+        return out
 
     def solve_chain(self, vis, chain, n_epoch: int = 1, tol: float = 1e-6, max_iter: int = 100,
                     prec: str = "mixed", damping: str = "auto", stream=None):
