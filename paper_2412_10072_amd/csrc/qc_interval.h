@@ -1245,14 +1245,37 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
     for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
     int p_cur = -1;                          // antenna of the sums in pacc (uniform per segment)
+    // One row per lane: the row indices of the next step are loaded one step
+    // ahead, so that the loads that depend on them (fixed factors, gains of
+    // the row's antennas and time) leave with the sample loads.
+    int p_nx = 0, q_nx = 0, t_nx = 0;
+    if constexpr (LANE_ROWS) {
+      if (rw_lo < rw_hi) {
+        const long long r0 = min(rw_lo + seg, rw_hi - 1);
+        p_nx = V.ant1[r0];
+        q_nx = V.ant2[r0];
+        t_nx = V.row_time[r0];
+      }
+    }
 
     for (long long rb = rw_lo; rb < rw_hi; rb += RPS) {
       const long long r_mine = rb + seg;
       const bool r_in = r_mine < rw_hi;
       const long long r = r_in ? r_mine : rb;
-      int p = V.ant1[r];
-      int q = V.ant2[r];
-      const int t = V.row_time[r];
+      int p, q, t;
+      if constexpr (LANE_ROWS) {
+        p = p_nx;
+        q = q_nx;
+        t = t_nx;
+        const long long rn = min(rb + RPS + seg, rw_hi - 1);
+        p_nx = V.ant1[rn];
+        q_nx = V.ant2[rn];
+        t_nx = V.row_time[rn];
+      } else {
+        p = V.ant1[r];
+        q = V.ant2[r];
+        t = V.row_time[r];
+      }
       const bool row_ok = r_in && p != q && (unsigned)p < (unsigned)n_ant && (unsigned)q < (unsigned)n_ant;
       // baseline coordinates of the row (predicted model)
       double ru = 0.0, rv = 0.0, rw = 0.0;

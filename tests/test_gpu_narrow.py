@@ -128,3 +128,42 @@ def test_chain_outputs_match_oracle(qc_lib, other_kind):
     V = qc_lib.apply(vis_d, chain_d, "corrupt", dir_mask=mask).cpu().numpy()
     assert np.abs(V - o_out.corrupt(vis, chain, mask)).max() <= 1e-12 * scale
     qc_lib.sync()
+
+
+@pytest.mark.parametrize("kind", ["diag", "phase", "amplitude"])
+def test_narrow_split_channel_groups_to_tol(qc_lib, kind):
+    """One-channel intervals on the split schedule (one row per lane), 13
+    channels, diagonal, phase and amplitude terms, solved to tol 1e-6 in FP64 so
+    that intervals finish at different updates (done intervals are skipped by
+    later passes): iteration counts equal to the oracle's, gains <= 1e-10."""
+    say(f"narrow split channel groups {kind}")
+    rng = np.random.default_rng(233)
+    n_ant, n_time, n_chan, n_dir = 6, 12, 13, 2
+    vis = make_vis(rng, n_ant=n_ant, n_time=n_time, n_chan=n_chan, n_dir=n_dir, freq0=1.0e9, dfreq=20e6)
+    truth = [make_term(rng, kind, n_time, n_chan, n_ant, t_int=n_time, f_int=1, n_dir=n_dir, scale=0.2),
+             make_term(rng, "diag", n_time, n_chan, n_ant, t_int=3, f_int=13, n_dir=n_dir, dd=True, scale=0.2)]
+    vis.data = forward_data(vis, truth) + 0.02 * rand_c(rng, *vis.data.shape)
+    vis.flag = (rng.random(vis.flag.shape) < 0.1).astype(np.uint8)
+    start = [t.copy() for t in truth]
+    if truth[0].params is not None:
+        start[0] = truth[0].copy(params=truth[0].params + 0.05 * rng.standard_normal(truth[0].params.shape))
+    else:
+        g = truth[0].gains + 0.1 * rand_c(rng, *truth[0].gains.shape)
+        g[..., 1] = 0
+        g[..., 2] = 0
+        start[0] = truth[0].copy(gains=g)
+    ref, rst = o_solver.solve_term(vis, start, 0, tol=1e-6, max_iter=60)
+    qc_lib.set_split(3)
+    try:
+        got, st = gpu_solve(qc_lib, vis, start, 0, tol=1e-6, max_iter=60, prec="fp64")
+        assert qc_lib.last_split_parts() == 3
+    finally:
+        qc_lib.set_split(0)
+    assert len(np.unique(rst["iters"])) > 1            # intervals finish at different updates
+    np.testing.assert_array_equal(st["iters"], rst["iters"])
+    np.testing.assert_array_equal(st["converged"], rst["converged"])
+    if kind == "diag":
+        assert rel_err(got[0].gains, ref[0].gains, "diag") <= 1e-10
+    else:
+        e = np.abs(got[0].params - ref[0].params).max() / np.abs(ref[0].params).max()
+        assert e <= 1e-10
