@@ -77,30 +77,8 @@ constexpr double TWO_PI = 6.283185307179586476925286766559;
 // lane L holds the total of value `idx` in v[0], identical in every lane of
 // its group of 64/CNT consecutive lanes.
 // ---------------------------------------------------------------------------
-template <int CNT, int OFF, typename A>
-struct ReduceScatter {
-  static __device__ __forceinline__ void run(A* v, int lane, int& idx) {
-    if constexpr (OFF >= 1) {
-      if constexpr (CNT > 1) {
-        constexpr int H = CNT / 2;
-        const bool up = (lane & OFF) != 0;
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-          const A send = up ? v[j] : v[j + H];
-          const A keep = up ? v[j + H] : v[j];
-          v[j] = keep + __shfl_xor(send, OFF);
-        }
-        idx = 2 * idx + (up ? 1 : 0);
-        ReduceScatter<H, OFF / 2, A>::run(v, lane, idx);
-      } else {
-        v[0] += __shfl_xor(v[0], OFF);
-        ReduceScatter<1, OFF / 2, A>::run(v, lane, idx);
-      }
-    }
-  }
-};
 
-// FP32 variant of the reduce-scatter built from cross-lane VALU operations
+// Built from cross-lane VALU operations
 // (no LDS traffic): the offset-32 and offset-16 steps use gfx950's
 // v_permlane32_swap / v_permlane16_swap, which exchange the upper half of
 // one register with the lower half of another, so a pair (x, y) becomes
@@ -174,6 +152,82 @@ struct ReduceScatterF32 {
   }
 };
 
+// FP64 variant: the same cross-lane operations on each 32-bit half of a
+// value (the exchanges move registers, not numbers), so FP64 sums leave the
+// LDS crossbar free as the FP32 ones do.
+__device__ __forceinline__ unsigned lo32(double x) { return (unsigned)__builtin_bit_cast(unsigned long long, x); }
+__device__ __forceinline__ unsigned hi32(double x) {
+  return (unsigned)(__builtin_bit_cast(unsigned long long, x) >> 32);
+}
+__device__ __forceinline__ double dfrom(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int OFF>
+__device__ __forceinline__ double partner(double x) {
+  return dfrom((unsigned)__builtin_amdgcn_mov_dpp((int)lo32(x), DppCtrl<OFF>::v, 0xF, 0xF, true),
+               (unsigned)__builtin_amdgcn_mov_dpp((int)hi32(x), DppCtrl<OFF>::v, 0xF, 0xF, true));
+}
+
+// (x', y') after v_permlane32_swap / v_permlane16_swap of (x, y), halves apart
+template <int OFF>
+__device__ __forceinline__ void swap_halves(double x, double y, double& xs, double& ys) {
+  if constexpr (OFF == 32) {
+    auto a = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(y), false, false);
+    auto b = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(y), false, false);
+    xs = dfrom(a[0], b[0]);
+    ys = dfrom(a[1], b[1]);
+  } else {
+    auto a = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(y), false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(y), false, false);
+    xs = dfrom(a[0], b[0]);
+    ys = dfrom(a[1], b[1]);
+  }
+}
+
+template <int OFF>
+__device__ __forceinline__ double pair_step(double x, double y, bool up) {
+  if constexpr (OFF == 32 || OFF == 16) {
+    double xs, ys;
+    swap_halves<OFF>(x, y, xs, ys);
+    return xs + ys;
+  } else {
+    const double send = up ? x : y;
+    const double keep = up ? y : x;
+    return keep + partner<OFF>(send);
+  }
+}
+
+template <int OFF>
+__device__ __forceinline__ double full_step(double x) {
+  if constexpr (OFF == 32 || OFF == 16) {
+    double xs, ys;
+    swap_halves<OFF>(x, x, xs, ys);
+    return xs + ys;
+  } else {
+    return x + partner<OFF>(x);
+  }
+}
+
+template <int CNT, int OFF>
+struct ReduceScatterF64 {
+  static __device__ __forceinline__ void run(double* v, int lane, int& idx) {
+    if constexpr (OFF >= 1) {
+      if constexpr (CNT > 1) {
+        constexpr int H = CNT / 2;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) v[j] = pair_step<OFF>(v[j], v[j + H], up);
+        idx = 2 * idx + (up ? 1 : 0);
+        ReduceScatterF64<H, OFF / 2>::run(v, lane, idx);
+      } else {
+        v[0] = full_step<OFF>(v[0]);
+        ReduceScatterF64<1, OFF / 2>::run(v, lane, idx);
+      }
+    }
+  }
+};
+
 // Reduce NVP values across each segment of LPR lanes (one row of the step)
 // and add value k (< NVAL) into that segment's LDS slot at byte offset s_off
 // (and its compensation slot at c_off when KAHAN).  When NVP > LPR every lane
@@ -185,7 +239,7 @@ __device__ __forceinline__ void wave_flush(A* v, int lane, unsigned s_off, unsig
   int idx = 0;
   if constexpr (LPR > 1) {
     if constexpr (sizeof(A) == 4) ReduceScatterF32<NVP, LPR / 2>::run(v, lane, idx);
-    else ReduceScatter<NVP, LPR / 2, A>::run(v, lane, idx);
+    else ReduceScatterF64<NVP, LPR / 2>::run(v, lane, idx);
   }
   constexpr int PER = NVP > LPR ? NVP / LPR : 1;       // values held per lane
   constexpr int GROUP = NVP < LPR ? LPR / NVP : 1;     // lanes holding the same values
