@@ -545,6 +545,45 @@ def leg_chain(ctx, dev, n_epoch: int = 2):
         for d in terms) + f"; total {t_total:.2f} s; residual rms {rms:.4f} (noise {sigma * math.sqrt(2):.4f})")
     del resid
     out["predicted_model"] = chain_predicted(ctx, p, k_start, n_epoch, stream)
+    out["de_levenberg_marquardt"] = chain_de_lm(ctx, p, k_start, n_epoch, stream)
+    return out
+
+
+def chain_de_lm(ctx, p, k_start, n_epoch, stream):
+    """The same chain solve with the direction-dependent term dE under Levenberg-Marquardt
+    damping instead of the half steps its default (AUTO) takes, from the same delay start:
+    dE's updates and time per epoch, and the residual."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+
+    vis = p.vis
+    dev = vis.data.device
+    chain = [qc.device_term(t, dev) for t in p.chain]
+    chain[0].params.copy_(k_start)
+    terms = []
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for e in range(n_epoch):
+        for n, t in enumerate(chain):
+            damping = "lm" if t.name == "dE" else "auto"
+            t1 = time.perf_counter()
+            st = ctx.solve(vis, chain, n, tol=1e-6, max_iter=100, prec="mixed", damping=damping, stream=stream)
+            torch.cuda.synchronize()
+            it = st["iters"].cpu().numpy()
+            terms.append(dict(epoch=e, term=t.name, damping=damping, ms=1e3 * (time.perf_counter() - t1),
+                              mean_iterations=float(it.mean()), max_iterations=int(it.max()),
+                              converged=float(st["converged"].float().mean().item()),
+                              split_parts=int(ctx.last_split_parts())))
+    resid = ctx.residual(vis, chain, stream=stream)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    use = (vis.flag == 0)
+    rms = float(torch.sqrt((resid.abs() ** 2).sum(-1)[use].mean() / 4).item())
+    out = dict(terms=terms, total_s=t_end - ts, residual_rms=rms)
+    log("chain, dE under LM: " + "; ".join(
+        f"{d['term']}{d['epoch']} {d['ms']:.0f} ms it {d['mean_iterations']:.1f}" for d in terms) +
+        f"; total {t_end - ts:.2f} s; residual rms {rms:.4f}")
     return out
 
 

@@ -126,9 +126,9 @@ typedef enum { QC_DAMP_FULL = 0, QC_DAMP_HALF = 1, QC_DAMP_ALTERNATE = 2, QC_DAM
  * (mu *= nu, nu doubles, starting at 2) and the blocks are formed again there.
  * Every attempt counts as an iteration and the last one is judged (one more
  * pass), so the result is the last accepted gains unless the interval
- * converged.  Not with the split schedule (QC_E_UNSUPPORTED for parts > 1;
- * the automatic schedule does not split an LM solve) nor in batched solves
- * (QC_E_UNSUPPORTED).                                                       */
+ * converged.  On the split schedule the interval's damping state and last
+ * accepted gains live in context memory and a rejected attempt costs one more
+ * pass; batched solves run it in every problem.                             */
 
 typedef enum { QC_CORRUPT = 0, QC_CORRECT = 1 } qc_apply_mode;
 

@@ -404,6 +404,8 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_active);
   hipFree(ctx->d_pt_int);
   hipFree(ctx->d_pt_dbl);
+  hipFree(ctx->d_lm);
+  hipFree(ctx->d_acc);
   hipEventDestroy(ctx->ev0);
   hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -532,9 +534,8 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
   if (fixed) {
     parts = 1;                                 // the split schedule's state is context memory
   } else if (ctx->split_parts > 1) {
-    if (lm) return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take Levenberg-Marquardt damping");
     parts = ctx->split_parts;
-  } else if (ctx->split_parts == 0 && !lm && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
+  } else if (ctx->split_parts == 0 && !opts->chisq_ref && n_int > 0 && n_int < 4 * ctx->n_cu &&
              avg_samples >= (double)(1 << 18)) {
     const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
     parts = (int)std::ceil((double)SPLIT_WG_PER_CU * ctx->n_cu / n_int);
@@ -572,6 +573,14 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
     P.state.passes = ctx->d_passes;
     P.state.done = ctx->d_done;
     P.state.n_active = ctx->d_active;
+    P.state.lm = nullptr;
+    P.state.acc = nullptr;
+    if (lm) {
+      HIP_TRY(ctx, grow(ctx->d_lm, ctx->lm_cap, (size_t)n_int * LM_STATE));
+      HIP_TRY(ctx, grow(ctx->d_acc, ctx->acc_cap, (size_t)n_int * vis->n_ant * ng * 4));
+      P.state.lm = ctx->d_lm;
+      P.state.acc = ctx->d_acc;
+    }
   }
   size_t lds = 0;
   hipError_t e = hipSuccess;
@@ -588,7 +597,9 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
     P.phase = 0;
     e = launch_solve(L, &P, s, &lds);
     P.phase = 1;
-    for (int k = 0; k <= opts->max_iter && e == hipSuccess; ++k) {
+    // a pass per update; with LM a rejected attempt takes one more pass
+    const int max_rounds = lm ? 2 * opts->max_iter + 2 : opts->max_iter + 1;
+    for (int k = 0; k < max_rounds && e == hipSuccess; ++k) {
       e = launch_solve(L, &P, s, &lds);
       if (e != hipSuccess) break;
       int n_active = 0;

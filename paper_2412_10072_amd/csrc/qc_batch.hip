@@ -25,7 +25,9 @@
 namespace qc {
 namespace {
 
-template <typename S, typename T, int RPS>
+// LM: Levenberg-Marquardt damping for every problem of the batch (kernels of
+// their own, as for the single-problem path)
+template <typename S, typename T, int RPS, bool LM>
 __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
   __shared__ int s_next;
   for (;;) {
@@ -63,8 +65,8 @@ __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
     J.partial = nullptr;
     J.otab = nullptr;
     J.sky = nullptr;
-    if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, true, 1, RPS>(J);
-    else solve_interval<KIND_C2X2, S, T, true, 1, RPS>(J);
+    if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, CHAIN_SINGLE, 1, RPS, false, LM>(J);
+    else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM>(J);
   }
 }
 
@@ -73,19 +75,24 @@ __global__ void k_zero_ints(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-template <typename S, typename T>
+template <typename S, typename T, bool LM>
 void* batch_kernel(int rps) {
-  if (rps == 4) return reinterpret_cast<void*>(k_solve_batch<S, T, 4>);
-  if (rps == 2) return reinterpret_cast<void*>(k_solve_batch<S, T, 2>);
-  return reinterpret_cast<void*>(k_solve_batch<S, T, 1>);
+  if (rps == 4) return reinterpret_cast<void*>(k_solve_batch<S, T, 4, LM>);
+  if (rps == 2) return reinterpret_cast<void*>(k_solve_batch<S, T, 2, LM>);
+  return reinterpret_cast<void*>(k_solve_batch<S, T, 1, LM>);
+}
+
+template <bool LM>
+void* batch_kernel_prec(int prec_mixed, int vis_c128, int rps) {
+  if (prec_mixed) return batch_kernel<float, float, LM>(rps);
+  if (vis_c128) return batch_kernel<double, double, LM>(rps);
+  return batch_kernel<float, double, LM>(rps);
 }
 
 }  // namespace
 
-void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps) {
-  if (prec_mixed) return batch_kernel<float, float>(rps);
-  if (vis_c128) return batch_kernel<double, double>(rps);
-  return batch_kernel<float, double>(rps);
+void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps, int lm) {
+  return lm ? batch_kernel_prec<true>(prec_mixed, vis_c128, rps) : batch_kernel_prec<false>(prec_mixed, vis_c128, rps);
 }
 
 size_t batch_lds_bytes(int prec_mixed, int max_ant, int waves) {

@@ -34,6 +34,7 @@ struct qc_batch {
   qc_ctx* ctx = nullptr;
   int n_prob = 0, n_items = 0;
   int prec_mixed = 0, vis_c128 = 0, max_ant = 1;
+  int lm = 0;                             // Levenberg-Marquardt damping for every problem
   double tol = 1e-6;
   int max_iter = 100;
   std::vector<BatchProb> probs;
@@ -59,7 +60,7 @@ qc_status bucket_config(qc_batch* b, Bucket& k, int waves, int rps) {
   k.rps = rps;
   k.lds = batch_lds_bytes(b->prec_mixed, b->max_ant, waves);
   if (k.lds > 160 * 1024) return fail(ctx, QC_E_UNSUPPORTED, "batch needs %zu B of LDS", k.lds);
-  void* kern = batch_kernel_ptr(b->prec_mixed, b->vis_c128, rps);
+  void* kern = batch_kernel_ptr(b->prec_mixed, b->vis_c128, rps, b->lm);
   if (k.lds > 64 * 1024)
     HIP_TRY(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds));
   int per_cu = 0;
@@ -86,7 +87,7 @@ qc_status launch_bucket(qc_batch* b, int i, hipStream_t s) {
   const Bucket& k = b->bucket[i];
   if (k.count == 0) return QC_OK;
   BatchArgs a = bucket_args(b, i);
-  HIP_TRY(b->ctx, launch_batch_bucket(a, batch_kernel_ptr(b->prec_mixed, b->vis_c128, k.rps), k.waves, k.lds,
+  HIP_TRY(b->ctx, launch_batch_bucket(a, batch_kernel_ptr(b->prec_mixed, b->vis_c128, k.rps, b->lm), k.waves, k.lds,
                                       k.grid, s));
   return QC_OK;
 }
@@ -147,8 +148,6 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
     return fail(ctx, QC_E_ARG, "bad precision %d", (int)opts->prec);
   if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_LM)
     return fail(ctx, QC_E_ARG, "bad damping %d", (int)opts->damping);
-  if (opts->damping == QC_DAMP_LM)
-    return fail(ctx, QC_E_UNSUPPORTED, "batched solves do not take Levenberg-Marquardt damping");
   if (opts->max_iter < 0) return fail(ctx, QC_E_ARG, "max_iter < 0");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(opts->stream);
@@ -156,6 +155,7 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
   b->ctx = ctx;
   b->n_prob = n_problem;
   b->prec_mixed = opts->prec == QC_PREC_MIXED;
+  b->lm = opts->damping == QC_DAMP_LM;
   b->vis_c128 = problems[0].vis.dtype == QC_C128;
   b->tol = opts->tol;
   b->max_iter = opts->max_iter;

@@ -79,6 +79,10 @@ struct qc_ctx {
   size_t pt_int_cap = 0;
   double* d_pt_dbl = nullptr;          // pointing solves: chi^2 first/last, previous steps
   size_t pt_dbl_cap = 0;
+  double* d_lm = nullptr;              // split schedule, Levenberg-Marquardt: state per interval
+  size_t lm_cap = 0;
+  double2* d_acc = nullptr;            // split schedule, Levenberg-Marquardt: last accepted gains
+  size_t acc_cap = 0;
   int last_split_parts = 1;   // parts per interval of the last solve (1 = fused)
   unsigned char* static_scratch = nullptr;   // this device's allocation-free scratch array (qc_api.hip)
 };

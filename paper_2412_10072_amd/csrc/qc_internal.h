@@ -397,7 +397,14 @@ struct SplitState {
   uint8_t* done;              // [n_int]
   int* n_active;              // intervals not done
   double* dv;                 // [n_int][n_ant * NG][2] divergence state per block
+  // Levenberg-Marquardt only (else null): per interval the damping, its
+  // growth factor, chi^2 at the last accepted gains, the predicted decrease
+  // of the pending attempt, whether one is pending and the attempts so far,
+  // and the last accepted gains / parameters of every block
+  double* lm;                 // [n_int][LM_STATE]
+  double2* acc;               // [n_int][n_ant * NG][4]
 };
+constexpr int LM_STATE = 6;
 
 // Levenberg-Marquardt damping (the damping code after FULL, HALF, ALTERNATE):
 // one damping per interval, LM_TAU times the largest diagonal block entry at

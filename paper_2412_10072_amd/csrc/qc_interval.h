@@ -1842,6 +1842,115 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 // split schedule: the update half of one iteration of one interval
 // ---------------------------------------------------------------------------
 
+// Levenberg-Marquardt on the split schedule: what the fused loop's LM branch
+// does after a pass, with the interval's state (damping, growth factor, chi^2
+// at the last accepted gains, the pending attempt's predicted decrease, the
+// attempts) and its last accepted gains in device memory.  A pass after an
+// attempt judges it by the gain ratio: accepted, the gains become the
+// accepted ones and the next attempt follows; rejected, the accepted gains
+// return and the next pass forms the blocks there.  The attempt that reaches
+// max_iter is judged by one more pass, so the result is the last accepted
+// gains unless the interval converged.
+template <int KIND, typename T, int NG, bool FB>
+__device__ __forceinline__ void split_update_lm(const Job& J, const double* tot, double2* gm, cx<T>* gc, int* gfl,
+                                                double* red, int* ctl, double chi_now, double nu_max, int pass,
+                                                const SplitState& St) {
+  const VisArgs& V = *J.V;
+  const int n_ant = V.n_ant;
+  const int n_gdir = J.TA->n_gdir;
+  const int interval = J.gt * J.n_gf + J.gf;
+  const int n_slots = n_ant * NG;
+  const size_t gbase = ((size_t)J.gt * J.n_gf + J.gf) * n_ant;
+  double* ls = St.lm + (size_t)interval * LM_STATE;
+  double2* acc = St.acc + (size_t)interval * n_slots * 4;
+  double* dv = St.dv + (size_t)interval * n_slots * 2;
+  double mu = ls[0], grow = ls[1], chi_acc = ls[2];
+  const double pred = ls[3];
+  const bool pending = ls[4] != 0.0;
+  int att = (int)ls[5];
+  auto each_block = [&](auto&& f) {
+    for (int i = threadIdx.x; i < n_ant * n_gdir; i += blockDim.x) {
+      const int ant = i / n_gdir, gd = i - ant * n_gdir;
+      f(ant * NG + gd, (gbase + ant) * n_gdir + gd);
+    }
+  };
+  bool finish = false, conv = false, attempt = true;
+  if (J.max_iter <= 0) {
+    finish = true;
+    attempt = false;
+  } else if (pending) {
+    const double rho = pred > 0.0 ? (chi_acc - chi_now) / pred : -1.0;
+    if (rho > 0.0) {
+      const double t3 = (2.0 * rho - 1.0) * (2.0 * rho - 1.0) * (2.0 * rho - 1.0);
+      mu *= fmax(1.0 / 3.0, 1.0 - t3);
+      grow = 2.0;
+      chi_acc = chi_now;
+      each_block([&](int slot, size_t) {
+        for (int k = 0; k < 4; ++k) acc[slot * 4 + k] = gm[slot * 4 + k];
+      });
+    } else {
+      mu *= grow;
+      grow *= 2.0;
+      attempt = false;
+      each_block([&](int slot, size_t) {
+        for (int k = 0; k < 4; ++k) {
+          const double2 g = acc[slot * 4 + k];
+          gm[slot * 4 + k] = g;
+          gc[slot * 4 + k] = cmake<T>((T)g.x, (T)g.y);
+        }
+      });
+    }
+    if (att >= J.max_iter) {
+      finish = true;
+      attempt = false;
+    }
+  } else {
+    chi_acc = chi_now;
+    each_block([&](int slot, size_t) {
+      for (int k = 0; k < 4; ++k) acc[slot * 4 + k] = gm[slot * 4 + k];
+    });
+  }
+  __syncthreads();
+  double new_pred = 0.0;
+  if (attempt) {
+    if (mu < 0.0)
+      mu = LM_TAU * block_diag_max<KIND, NG, FB>([&](size_t i) -> double { return tot[i]; }, red, n_ant, n_gdir);
+    conv = update_and_test<KIND, T, NG, FB>([&](size_t i) -> double { return tot[i]; }, gm, gc, gfl, dv, red, ctl,
+                                            n_ant, n_gdir, att + 1, J.damping, nu_max, J.tol, J.err, J.TA->kind, mu,
+                                            &new_pred);
+    att += 1;
+    finish = conv;
+  }
+  each_block([&](int slot, size_t dst) {
+    if constexpr (is_param(KIND)) {
+      params_store<KIND>(J.params, dst, gm + slot * 4);
+    } else {
+      for (int k = 0; k < 4; ++k) J.gains[4 * dst + k] = gm[slot * 4 + k];
+    }
+    if (J.gflags) {
+      int f = attempt ? gfl[slot] : (int)J.gflags[dst];
+      if (f == 0 && finish && !conv && dv[2 * slot] >= (double)DIV_RUN) f = 2;   // updates did not tend to zero
+      J.gflags[dst] = (int8_t)f;
+    }
+  });
+  if (threadIdx.x == 0) {
+    ls[0] = mu;
+    ls[1] = grow;
+    ls[2] = chi_acc;
+    ls[3] = attempt ? new_pred : 0.0;
+    ls[4] = attempt ? 1.0 : 0.0;
+    ls[5] = (double)att;
+    St.passes[interval] = pass + 1;
+    if (J.iters) J.iters[interval] = att;
+    if (J.converged) J.converged[interval] = conv ? 1 : 0;
+    if (J.restarted) J.restarted[interval] = 0;
+    if (finish) {
+      St.done[interval] = 1;
+      atomicSub(St.n_active, 1);
+    }
+  }
+}
+
 // Sums the interval's n_part partial blocks in a fixed order, then does what
 // the fused loop does after a pass: chi^2 bookkeeping, the FP64 block solves,
 // the damped update of the gains in device memory, the convergence test.
@@ -1905,6 +2014,10 @@ __device__ __forceinline__ void split_update(const Job& J, const double* partial
     if (J.chisq_last) J.chisq_last[interval] = chi_now;
   }
   __syncthreads();
+  if (J.damping == DAMP_LM) {
+    split_update_lm<KIND, T, NG, FB>(J, tot, gm, gc, gfl, red, ctl, chi_now, nu_max, pass, St);
+    return;
+  }
   bool finish = false, conv = false;
   if (pass >= J.max_iter) {
     finish = true;

@@ -191,6 +191,15 @@ __global__ void k_split_reset(SplitState St, int n_int) {
   if (i < n_int) {
     St.passes[i] = 0;
     St.done[i] = 0;
+    if (St.lm) {
+      double* ls = St.lm + (size_t)i * LM_STATE;
+      ls[0] = -1.0;      // damping: not yet set
+      ls[1] = 2.0;       // its growth factor
+      ls[2] = 0.0;       // chi^2 at the last accepted gains
+      ls[3] = 0.0;       // predicted decrease of the pending attempt
+      ls[4] = 0.0;       // an attempt is pending
+      ls[5] = 0.0;       // attempts so far
+    }
   }
   if (i == 0) St.n_active[0] = n_int;
 }

@@ -88,16 +88,79 @@ def test_lm_converges_from_the_full_step_two_cycle(qc_lib):
         assert st["converged"].all() and not got[0].gain_flags.any()
 
 
-def test_lm_rejected_by_split_and_batch(qc_lib):
-    from paper_2412_10072_amd import qc
-    say("lm: split and batch rejections")
-    vis, start, _ = problem("c2x2", 63, 0.1, dtype="c64")
-    qc_lib.set_split(2)
+@pytest.mark.parametrize("kind,seed,scale", CASES)
+@pytest.mark.parametrize("mode", ["tol", "fixed"])
+def test_lm_split_schedule_fp64_matches_oracle(qc_lib, kind, seed, scale, mode):
+    """The split schedule (rows in 3 parts, state and accepted gains in device
+    memory, a host wait per pass) takes the same decisions as the oracle."""
+    say(f"lm split fp64 {kind} {seed} {mode}")
+    vis, start, _ = problem(kind, seed, scale)
+    kw = dict(tol=1e-6, max_iter=40) if mode == "tol" else dict(tol=-1.0, max_iter=4)
+    ref, rst = o_solver.solve_term(vis, start, 0, damping="lm", **kw)
+    qc_lib.set_split(3)
     try:
-        with pytest.raises(qc.QcError):
-            gpu(qc_lib, vis, start, tol=1e-6, max_iter=10, prec="mixed", damping="lm")
+        got, st = gpu(qc_lib, vis, start, prec="fp64", damping="lm", **kw)
+        assert qc_lib.last_split_parts() == 3
     finally:
         qc_lib.set_split(0)
+    assert np.array_equal(st["iters"], rst["iters"])
+    assert np.array_equal(st["converged"], rst["converged"])
+    assert np.array_equal(got[0].gain_flags, ref[0].gain_flags)
+    r, g = values(ref[0]), values(got[0])
+    assert np.abs(g - r).max() / np.abs(r).max() <= 1e-10
+    np.testing.assert_allclose(st["chisq_last"], rst["chisq_last"], rtol=1e-10)
+
+
+def test_lm_split_chain_term_fp64(qc_lib):
+    """A direction-dependent term in a chain (diagonal-chain passes, four gain
+    directions) on the split schedule with LM."""
+    say("lm split chain term")
+    rng = np.random.default_rng(75)
+    vis = make_vis(rng, n_ant=6, n_time=4, n_chan=16, n_dir=3)
+    truth = [make_term(rng, "diag", 4, 16, 6, t_int=1, f_int=16, n_dir=3, scale=0.3),
+             make_term(rng, "diag", 4, 16, 6, t_int=2, f_int=8, n_dir=3, dd=True, scale=0.4)]
+    vis.data = forward_data(vis, truth) + 0.02 * rand_c(rng, *vis.data.shape)
+    start = [truth[0], unit_like(truth[1])]
+    ref, rst = o_solver.solve_term(vis, start, 1, damping="lm", tol=-1.0, max_iter=5)
+    from paper_2412_10072_amd import qc
     vd = qc.device_vis(vis, DEV)
-    with pytest.raises(qc.QcError):
-        qc.Batch(qc_lib, [(vd, qc.device_term(start[0], DEV))], damping="lm")
+    cd = [qc.device_term(t, DEV) for t in start]
+    qc_lib.set_split(4)
+    try:
+        st = qc_lib.solve(vd, cd, 1, prec="fp64", damping="lm", tol=-1.0, max_iter=5)
+        qc_lib.sync()
+    finally:
+        qc_lib.set_split(0)
+    got = qc.host_term(cd[1])
+    assert np.array_equal(st["iters"].cpu().numpy(), rst["iters"])
+    g, r = got.gains[..., [0, 3]], ref[1].gains[..., [0, 3]]
+    assert np.abs(g - r).max() / np.abs(r).max() <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lm_batched_matches_oracle(qc_lib, prec):
+    """Batched problems (one graph launch) with LM for every problem."""
+    from paper_2412_10072_amd import qc
+    say(f"lm batched {prec}")
+    dtype = "c128" if prec == "fp64" else "c64"
+    cases = [c for c in CASES if c[0] in ("c2x2", "diag")]
+    probs, refs = [], []
+    kw = dict(tol=1e-6, max_iter=40)
+    for kind, seed, scale in cases:
+        vis, start, _ = problem(kind, seed, scale, dtype=dtype)
+        ref, rst = o_solver.solve_term(vis, start, 0, damping="lm", **kw)
+        refs.append((ref[0], rst))
+        probs.append((qc.device_vis(vis, DEV), qc.device_term(start[0], DEV)))
+    b = qc.Batch(qc_lib, probs, prec=prec, damping="lm", **kw)
+    b.run()
+    qc_lib.sync()
+    for (vd, t), st, (ref, rst) in zip(probs, b.stats, refs):
+        r, g = values(ref), t.gains.cpu().numpy()
+        err = np.abs(g - r).max() / np.abs(r).max()
+        if prec == "fp64":
+            assert np.array_equal(st["iters"].cpu().numpy(), rst["iters"])
+            assert err <= 1e-10
+        else:
+            assert st["converged"].cpu().numpy().all()
+            assert err <= 1e-4
+    b.close()
