@@ -212,6 +212,103 @@ def cpu_baseline(prob, budget_s: float = 20.0):
                        f"baselines solved to tol 1e-6 by the FP64 NumPy oracle in {dt:.1f} s")
 
 
+def leg_tiny(ctx, dev, reps: int = 5):
+    """The tiny configuration (7 antennas, 60 times x 16 channels, complex128, 24 intervals of
+    10 times x 4 channels, sigma 0.01): the FP64 solve to tol 1e-6 on the GPU (median of reps,
+    launch-latency bound) and the oracle on the whole problem on one core, with their
+    largest per-interval relative difference."""
+    import numpy as np
+    import torch
+    from paper_2412_10072_amd import qc
+    from oracle import solver as o_solver
+    from synth.generate import config_tiny, to_numpy_vis
+
+    prob = config_tiny(sigma=0.01)
+    vis_h = to_numpy_vis(prob.vis)
+    vis_d = qc.device_vis(vis_h, dev)
+    t0 = qc.device_term(prob.chain[0], dev)
+    g0 = t0.gains.clone()
+    stream = torch.cuda.current_stream()
+    wall, kern = [], []
+    for _ in range(reps + 1):
+        t0.gains.copy_(g0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st = ctx.solve(vis_d, [t0], 0, tol=1e-6, max_iter=100, prec="fp64", stream=stream)
+        torch.cuda.synchronize()
+        wall.append(1e3 * (time.perf_counter() - ts))
+        kern.append(ctx.last_kernel_ms())
+    got = t0.gains.cpu().numpy()
+    ts = time.perf_counter()
+    ref, rst = o_solver.solve_term(vis_h, prob.chain, 0, tol=1e-6, max_iter=100)
+    oracle_s = time.perf_counter() - ts
+    w = ref[0].gains[..., [0, 3]]
+    d = np.linalg.norm((got[..., [0, 3]] - w).reshape(w.shape[0], w.shape[1], -1), axis=-1)
+    n = np.linalg.norm(w.reshape(w.shape[0], w.shape[1], -1), axis=-1)
+    n_samples = int(vis_h.data.shape[0] * vis_h.data.shape[1])
+    out = dict(samples=n_samples, intervals=int(t0.n_gt * t0.n_gf), gpu_wall_ms=float(np.median(wall[1:])),
+               gpu_kernel_ms=float(np.median(kern[1:])), oracle_s=oracle_s, oracle_cores=1,
+               vis_per_s_gpu=n_samples / (np.median(wall[1:]) * 1e-3), vis_per_s_oracle=n_samples / oracle_s,
+               mean_iterations=float(st["iters"].float().mean().item()),
+               iterations_equal=bool(np.array_equal(st["iters"].cpu().numpy(), rst["iters"])),
+               rel_err_vs_oracle=float(np.max(d / n)))
+    log(f"tiny: GPU {out['gpu_wall_ms']:.2f} ms (kernel {out['gpu_kernel_ms']:.3f} ms), oracle {oracle_s:.2f} s, "
+        f"rel err {out['rel_err_vs_oracle']:.1e}")
+    return out
+
+
+def _oracle_fixed(task):
+    """Oracle solve of one batch problem in fixed-iteration mode (pool worker)."""
+    from oracle import solver as o_solver
+    vis, term, k = task
+    ref, _ = o_solver.solve_term(vis, [term], 0, tol=-1.0, max_iter=k)
+    return ref[0].gains
+
+
+def batch_oracle_stratified(probs, fp64_gains, dev, per_bucket: int = 6, n_pick: int = 32, k: int = 3,
+                            workers: int = 0):
+    """The oracle in fixed-iteration mode (k updates) on n_pick problems of the batch, stratified
+    by the six size buckets of the batched launch (channel width <= 16 / <= 32 / wider x fewer or
+    more than 65,536 samples per interval; the smallest problems of each bucket, for a bounded
+    CPU time), in a pool of host processes, against the FP64 batched solve with the same k."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    from synth.generate import to_numpy_vis
+    workers = workers or min(16, os.cpu_count() or 1)
+    keyed = []
+    for i, (vis, _, th) in enumerate(probs):
+        n_ch = int(np.sum(np.asarray(th.f_map) == 0))
+        rows = int(vis.data.shape[0]) // max(int(th.n_gt), 1)
+        w = 0 if n_ch <= 16 else (1 if n_ch <= 32 else 2)
+        z = 0 if rows * n_ch < (1 << 16) else 1
+        keyed.append((w * 2 + z, int(vis.data.shape[0]) * int(vis.data.shape[1]), i))
+    picked = []
+    for b in range(6):
+        cands = sorted(x for x in keyed if x[0] == b)
+        picked += [x[2] for x in cands[:per_bucket]]
+    rest = sorted((x for x in keyed if x[2] not in picked), key=lambda x: x[1])
+    picked += [x[2] for x in rest[:max(0, n_pick - len(picked))]]
+    picked = picked[:n_pick]
+    tasks = [(to_numpy_vis(probs[i][0]), probs[i][2], k) for i in picked]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                             initializer=_one_blas_thread) as ex:
+        refs = list(ex.map(_oracle_fixed, tasks))
+    dt = time.perf_counter() - t0
+    errs = []
+    for i, ref in zip(picked, refs):
+        g = fp64_gains[i].cpu().numpy()
+        sel = [0, 3] if probs[i][2].kind == "diag" else [0, 1, 2, 3]
+        a, w = g[..., sel], ref[..., sel]
+        d = np.linalg.norm((a - w).reshape(w.shape[0], w.shape[1], -1), axis=-1)
+        n = np.linalg.norm(w.reshape(w.shape[0], w.shape[1], -1), axis=-1)
+        errs.append(float(np.max(d / np.maximum(n, 1e-300))))
+    samples = int(sum(t[0].data.shape[0] * t[0].data.shape[1] for t in tasks))
+    return dict(problems=picked, buckets=sorted(set(x[0] for x in keyed if x[2] in picked)), updates=k,
+                samples=samples, oracle_s=dt, cores=workers, max_rel_err_fp64_vs_oracle=max(errs))
+
+
 def leg_batch(ctx, dev, n_problems: int = 256, steps: int = 3):
     """Uneven batch: n_problems independent problems (antennas U{16..64}, times U{20..200},
     channels U{16..256}, dropped rows, diag / c2x2 50/50) solved to tol 1e-6 (MIXED) by
@@ -284,6 +381,17 @@ def leg_batch(ctx, dev, n_problems: int = 256, steps: int = 3):
     fp64_ms = bf.last_ms()
     fp64 = [t.gains.clone() for _, t, _ in probs]
     bf.close()
+    # FP64 in fixed-iteration mode against the oracle on 32 problems stratified by bucket
+    bk = qc.Batch(ctx, pairs, tol=-1.0, max_iter=3, prec="fp64", stream=stream)
+    reset()
+    bk.run(stream)
+    torch.cuda.synchronize()
+    fixed = [t.gains.clone() for _, t, _ in probs]
+    bk.close()
+    strat = batch_oracle_stratified(probs, fixed, dev)
+    log(f"batch: oracle on {len(strat['problems'])} stratified problems ({strat['samples'] / 1e6:.1f}M samples, "
+        f"{strat['updates']} updates) in {strat['oracle_s']:.1f} s on {strat['cores']} processes; FP64 batched "
+        f"within {strat['max_rel_err_fp64_vs_oracle']:.1e}")
 
     def rel(a, w, kind):
         a, w = a.cpu().numpy(), np.asarray(w)
@@ -322,7 +430,7 @@ def leg_batch(ctx, dev, n_problems: int = 256, steps: int = 3):
                hbm_frac_batched=alg_bytes / (np.mean(tuned_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS,
                max_abs_diff_batched_vs_plain=d_plain,
                rel_err_mixed_vs_fp64_gpu=e_mf, rel_err_mixed_vs_oracle=e_mo, rel_err_fp64_vs_oracle=e_fo,
-               oracle_problems=picked)
+               oracle_problems=picked, oracle_stratified_fixed_iterations=strat)
     log(f"batch: plain {plain_ms:.1f} ms (kernels {kern:.1f}), graph default {np.mean(default_ms):.1f} ms, "
         f"tuned {np.mean(tuned_ms):.1f} ms (tuning {tune_s:.1f} s), fp64 {fp64_ms:.1f} ms; "
         f"mixed vs fp64 {e_mf:.2e}, vs oracle {e_mo:.2e}")
@@ -369,6 +477,7 @@ def leg_warm(ctx, dev, n_sets: int = 5, n_time_train: int = 625, epochs: int = 3
                          restarted=float(st["restarted"].float().mean().item()),
                          converged=float(st["converged"].float().mean().item()), gains=t.gains)
     lb = learned_batched(ctx, net, dev)
+    om = oracle_mlp_step(net)
     # agreement of the two solutions (model-level, gauge free): max |g_p conj(g_q)| difference
     gu, gw = res["unit"]["gains"], res["warm"]["gains"]
     pu = gu[:, :, :, 0, 0, None] * gu[:, :, None, :, 0, 0].conj()
@@ -382,11 +491,35 @@ def leg_warm(ctx, dev, n_sets: int = 5, n_time_train: int = 625, epochs: int = 3
                unit_ms=res["unit"]["ms"], warm_ms=res["warm"]["ms"],
                time_saved_frac=1.0 - res["warm"]["ms"] / res["unit"]["ms"],
                restarted_frac=res["warm"]["restarted"], converged_frac=res["warm"]["converged"],
-               model_agreement=agree, params=net.n_params, learned_batched=lb)
+               model_agreement=agree, params=net.n_params, learned_batched=lb,
+               gpu_train_step_ms=1e3 * train_s / max(1, epochs * (n_train // 256)), oracle_mlp_step=om)
     log(f"warm start: {n_train} training intervals ({gen_s:.1f} s to make), training {train_s:.1f} s, "
         f"loss {hist[0]:.4f} -> {hist[-1]:.4f}; held-out iterations unit {out['unit_iters']:.2f} "
         f"warm {out['warm_iters']:.2f}; time unit {out['unit_ms']:.1f} ms warm {out['warm_ms']:.1f} ms")
     return out
+
+
+def oracle_mlp_step(net, batch: int = 256, reps: int = 5):
+    """The oracle's FP64 training step of the same network (forward, MSE gradient, backward,
+    Adam) on one host core, batch 256, from the trained parameters: the median of reps."""
+    import numpy as np
+    from oracle import warmstart as o_ws
+    rng = np.random.default_rng(7)
+    params = net.params.double().cpu().numpy()
+    I, H, O = net.n_in, net.n_hid, net.n_out
+    x = rng.standard_normal((batch, I))
+    tgt = rng.standard_normal((batch, O))
+    m = np.zeros_like(params)
+    v = np.zeros_like(params)
+    times = []
+    for k in range(reps):
+        t0 = time.perf_counter()
+        y, pre = o_ws.forward(params, x, I, H, O)
+        _, dy = o_ws.mse(y, tgt)
+        g = o_ws.backward(params, x, pre, dy, I, H, O)
+        params, m, v = o_ws.adam(params, g, m, v, 1e-3, 0.9, 0.999, 1e-8, k + 1)
+        times.append(time.perf_counter() - t0)
+    return dict(ms=1e3 * float(np.median(times)), batch=batch, cores=1)
 
 
 def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
@@ -544,9 +677,43 @@ def leg_chain(ctx, dev, n_epoch: int = 2):
         f"{d['term']}{d['epoch']} {d['ms']:.0f} ms it {d['mean_iterations']:.1f} parts {d['split_parts']}"
         for d in terms) + f"; total {t_total:.2f} s; residual rms {rms:.4f} (noise {sigma * math.sqrt(2):.4f})")
     del resid
+    try:
+        out["oracle_k_pass"] = oracle_k_pass(p, chain)
+    except Exception as e:   # report, keep the leg
+        out["oracle_k_pass"] = {"error": f"{type(e).__name__}: {e}"}
     out["predicted_model"] = chain_predicted(ctx, p, k_start, n_epoch, stream)
     out["de_levenberg_marquardt"] = chain_de_lm(ctx, p, k_start, n_epoch, stream)
     return out
+
+
+def oracle_k_pass(p, chain_d, n_times: int = 60, n_chan: int = 4):
+    """The oracle's rate on the delay term's blocks (one accumulation pass of K, chain at the
+    solved gains, 4 directions) over a slice of one K interval: its first 60 times x the first
+    4 channels, on one host core (the full interval of 60 times x 512 channels would need tens
+    of GB of host memory for the oracle's per-sample 4x4 blocks)."""
+    import numpy as np
+    from paper_2412_10072_amd import qc
+    from oracle import solver as o_solver
+    from synth.generate import slice_times, to_numpy_vis
+
+    vis_h = to_numpy_vis(slice_times(p.vis, 0, n_times))
+    vis_k = vis_h.copy(data=np.ascontiguousarray(vis_h.data[:, :n_chan]),
+                       model=np.ascontiguousarray(vis_h.model[:, :n_chan]),
+                       weight=np.ascontiguousarray(vis_h.weight[:, :n_chan]),
+                       flag=np.ascontiguousarray(vis_h.flag[:, :n_chan]), chan_freq=vis_h.chan_freq[:n_chan])
+    chain_h = []
+    for t in chain_d:
+        h = qc.host_term(t)
+        chain_h.append(h.copy(t_map=np.asarray(h.t_map)[:n_times], f_map=np.asarray(h.f_map)[:n_chan]))
+    rows = np.arange(vis_k.data.shape[0])
+    s = o_solver.samples_of(vis_k, rows, np.arange(n_chan))
+    t0 = time.perf_counter()
+    o_solver.accumulate(vis_k, chain_h, 0, s)
+    dt = time.perf_counter() - t0
+    n = int(rows.size * n_chan)
+    log(f"chain: oracle K pass over {n / 1e6:.2f}M samples in {dt:.1f} s ({n / dt:.3g} samples/s, 1 core)")
+    return dict(samples=n, seconds=dt, samples_per_s=n / dt, cores=1,
+                sample=f"first {n_times} times x first {n_chan} channels of one K interval, one pass")
 
 
 def chain_de_lm(ctx, p, k_start, n_epoch, stream):
@@ -929,8 +1096,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-time", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp64,flag,robust,interp,predict,batch,warm,chain,params,pointing",
-                    help="comma list of extra legs: fp64, flag, robust, interp, predict, batch, warm, chain, "
+    ap.add_argument("--legs", default="tiny,fp64,flag,robust,interp,predict,batch,warm,chain,params,pointing",
+                    help="comma list of extra legs: tiny, fp64, flag, robust, interp, predict, batch, warm, chain, "
                          "params, pointing (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
@@ -1043,7 +1210,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
         try:
-            out["cpu_baseline"]["all_cores"] = cpu_baseline_pool(prob)
+            out["cpu_baseline"]["all_cores"] = cpu_baseline_pool(prob, n_times=16)
             log(f"cpu baseline: 1 core {out['cpu_baseline']['value']:.3g} vis/s, "
                 f"{out['cpu_baseline']['all_cores']['cores']} processes "
                 f"{out['cpu_baseline']['all_cores']['value']:.3g} vis/s")
@@ -1053,6 +1220,12 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     if legs:
         out["legs"] = {}
+    if "tiny" in legs:
+        try:
+            out["legs"]["tiny"] = leg_tiny(ctx, dev)
+        except Exception as e:   # report, keep the main measurement
+            out["legs"]["tiny"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"tiny leg failed: {e}")
     if "fp64" in legs:
         try:
             out["legs"]["fp64"] = leg_fp64(ctx, vis, term0, init_gains, int_bytes, stream)

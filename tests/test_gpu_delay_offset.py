@@ -108,8 +108,14 @@ def test_chain_two_epochs_fp64_and_split(qc_lib):
         finally:
             qc_lib.set_split(0)
     assert out[3][1] == 3 and out[1][1] == 1
+    # both schedules against the oracle at the FP64 bar (their sums differ in
+    # order, so they agree with each other to rounding, ~1e-12 here)
+    ref1, _ = o_solver.solve_term(vis, start[:1], 0, tol=-1.0, max_iter=5)
+    for parts in (1, 3):
+        e_phi, e_tau = param_err(out[parts][0], ref1[0].params)
+        assert e_phi <= 1e-10 and e_tau <= 1e-10
     e_phi, e_tau = param_err(out[3][0], out[1][0])
-    assert e_phi <= 1e-12 and e_tau <= 1e-12
+    assert e_phi <= 1e-10 and e_tau <= 1e-10
 
 
 def test_delay_init_residual_and_interp(qc_lib):
