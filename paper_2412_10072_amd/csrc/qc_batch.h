@@ -38,7 +38,7 @@ struct BatchArgs {
   int* err;
 };
 
-void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps, int lm);
+void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps, int lm, int warm);
 size_t batch_lds_bytes(int prec_mixed, int max_ant, int waves);
 hipError_t launch_batch_bucket(const BatchArgs& B, void* kern, int waves, size_t lds, int grid, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);

@@ -35,6 +35,7 @@ struct qc_batch {
   int n_prob = 0, n_items = 0;
   int prec_mixed = 0, vis_c128 = 0, max_ant = 1;
   int lm = 0;                             // Levenberg-Marquardt damping for every problem
+  int warm = 0;                           // some problem has a warm-start fallback reference
   double tol = 1e-6;
   int max_iter = 100;
   std::vector<BatchProb> probs;
@@ -60,7 +61,7 @@ qc_status bucket_config(qc_batch* b, Bucket& k, int waves, int rps) {
   k.rps = rps;
   k.lds = batch_lds_bytes(b->prec_mixed, b->max_ant, waves);
   if (k.lds > 160 * 1024) return fail(ctx, QC_E_UNSUPPORTED, "batch needs %zu B of LDS", k.lds);
-  void* kern = batch_kernel_ptr(b->prec_mixed, b->vis_c128, rps, b->lm);
+  void* kern = batch_kernel_ptr(b->prec_mixed, b->vis_c128, rps, b->lm, b->warm);
   if (k.lds > 64 * 1024)
     HIP_TRY(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds));
   int per_cu = 0;
@@ -87,7 +88,7 @@ qc_status launch_bucket(qc_batch* b, int i, hipStream_t s) {
   const Bucket& k = b->bucket[i];
   if (k.count == 0) return QC_OK;
   BatchArgs a = bucket_args(b, i);
-  HIP_TRY(b->ctx, launch_batch_bucket(a, batch_kernel_ptr(b->prec_mixed, b->vis_c128, k.rps, b->lm), k.waves, k.lds,
+  HIP_TRY(b->ctx, launch_batch_bucket(a, batch_kernel_ptr(b->prec_mixed, b->vis_c128, k.rps, b->lm, b->warm), k.waves, k.lds,
                                       k.grid, s));
   return QC_OK;
 }
@@ -198,6 +199,7 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
     bp.chisq_first = P.stats.chisq_first;
     bp.chisq_last = P.stats.chisq_last;
     bp.chisq_ref = P.chisq_ref;
+    if (P.chisq_ref) b->warm = 1;
     bp.restarted = P.stats.restarted;
     bp.damping = resolve_damping(opts->damping, P.term);
     b->probs.push_back(bp);
