@@ -406,6 +406,8 @@ qc_status qc_ctx_destroy(qc_ctx* ctx) {
   hipFree(ctx->d_pt_dbl);
   hipFree(ctx->d_lm);
   hipFree(ctx->d_acc);
+  hipFree(ctx->d_band);
+  hipFree(ctx->d_ddtab);
   hipEventDestroy(ctx->ev0);
   hipEventDestroy(ctx->ev1);
   delete ctx;
@@ -543,6 +545,27 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
   }
   if (parts > 1 && opts->chisq_ref)
     return fail(ctx, QC_E_UNSUPPORTED, "the split schedule does not take chisq_ref");
+  // intervals of one channel each, in channel order, on a diagonal chain with
+  // one gain direction: the split pass over 16 channels per wavefront
+  bool band = parts > 1 && !sky && L.diag_chain && !L.left_general && ta.type == QC_TERM_DIAGONAL &&
+              ta.n_gdir == 1 && ctx->max_int_chan == 1 && ta.n_gf == vis->n_chan && vis->n_row < (1LL << 31) &&
+              band_lds_bytes_for(vis->n_ant, L.prec_mixed != 0) <= 64 * 1024;
+  for (int g = 0; band && g < ta.n_gf; ++g)
+    if (ctx->h_clo[g] != g) band = false;
+  // its direction-dependent fixed terms: diagonal gains, at most BAND_MAX_DD
+  L.n_dd = 0;
+  for (int j = 0; band && j < n_term; ++j) {
+    if (j == active || chain[j].n_gdir <= 1) continue;
+    if (chain[j].type != QC_TERM_DIAGONAL || L.n_dd == BAND_MAX_DD) band = false;
+    else L.dd_term[L.n_dd++] = j;
+  }
+  if (!band) L.n_dd = 0;
+  if (band && ctx->split_parts == 0) {
+    const long long units = (long long)((vis->n_chan + 15) / 16) * ta.n_gt;
+    const double rows_per_int = (double)vis->n_row / std::max(ta.n_gt, 1);
+    parts = (int)std::ceil((double)BAND_WAVES_PER_CU * ctx->n_cu / (double)units);
+    parts = std::max(2, std::min(parts, (int)std::max(1.0, rows_per_int / 64.0)));
+  }
   ctx->last_split_parts = parts;
   // diagonal chains: the direction-independent terms other than the active
   // one are fixed during the solve; tabulate their product once
@@ -582,12 +605,30 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
       P.state.acc = ctx->d_acc;
     }
   }
+  size_t dd_off[BAND_MAX_DD] = {0, 0};
+  if (band) {
+    HIP_TRY(ctx, grow(ctx->d_band, ctx->band_cap, (size_t)std::max<long long>(vis->n_row, 1)));
+    size_t dd_bytes = 0;
+    for (int j = 0; j < L.n_dd; ++j) {
+      dd_off[j] = dd_bytes;
+      dd_bytes += (dd_table_bytes(L, L.dd_term[j]) + 255) / 256 * 256;
+    }
+    if (L.n_dd > 0) HIP_TRY(ctx, grow(ctx->d_ddtab, ctx->ddtab_cap, dd_bytes));
+  }
   size_t lds = 0;
   hipError_t e = hipSuccess;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   if (want_tab) {
     e = launch_chain_table(L, ctx->d_otab, s);
     L.otab = ctx->d_otab;
+  }
+  if (band && e == hipSuccess) {
+    e = launch_band_steps(L, parts, ctx->d_band, s);
+    L.band_steps = ctx->d_band;
+    for (int j = 0; j < L.n_dd && e == hipSuccess; ++j) {
+      L.dd_tab[j] = ctx->d_ddtab + dd_off[j];
+      e = launch_dd_table(L, L.dd_term[j], ctx->d_ddtab + dd_off[j], s);
+    }
   }
   if (e != hipSuccess) {
     // reported below

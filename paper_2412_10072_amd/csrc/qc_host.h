@@ -16,6 +16,10 @@
 // bandpass, gain, direction-dependent) and the pointing and delay-offset
 // solves ran 10-30% faster at about 32 than at 4 (measured; flat beyond).
 constexpr int SPLIT_WG_PER_CU = 32;
+// Wavefronts per compute unit that the split over one-channel intervals aims
+// at (each holds 16 intervals and 24 KiB of LDS at 64 antennas, so about six
+// are resident per CU: four rounds of them)
+constexpr int BAND_WAVES_PER_CU = 24;
 
 struct qc_ctx {
   int device = 0;
@@ -83,6 +87,10 @@ struct qc_ctx {
   size_t lm_cap = 0;
   double2* d_acc = nullptr;            // split schedule, Levenberg-Marquardt: last accepted gains
   size_t acc_cap = 0;
+  qc::BandStep* d_band = nullptr;        // split schedule over one-channel intervals: steps per row
+  size_t band_cap = 0;
+  unsigned char* d_ddtab = nullptr;    // that split: tables of the direction-dependent fixed terms
+  size_t ddtab_cap = 0;
   int last_split_parts = 1;   // parts per interval of the last solve (1 = fused)
   unsigned char* static_scratch = nullptr;   // this device's allocation-free scratch array (qc_api.hip)
 };

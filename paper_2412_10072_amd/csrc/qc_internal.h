@@ -348,6 +348,19 @@ __device__ __forceinline__ m22<T> sky_model(const SkyArgs& K, double un, double 
 // host-side launchers implemented in the kernel translation units
 // ---------------------------------------------------------------------------
 
+// One step of the single-channel-interval split pass (qc_band.h), stored at
+// the index of its first row: up to four consecutive rows of one time that
+// share antenna p.
+constexpr int BAND_MAX_DD = 2;   // direction-dependent fixed terms the pass takes
+
+struct BandStep {
+  int k;        // rows in the step; 0: no step starts at this row
+  int t;        // time of the rows
+  int p;        // antenna p of the rows
+  int dup;      // two rows share antenna q: their q sums are added one row after the other
+  int q[4];     // antenna q of each row, -1 past k or for a row that adds nothing (p == q)
+};
+
 struct SolveLaunch {
   VisArgs vis;
   ChainArgs chain;
@@ -383,7 +396,25 @@ struct SolveLaunch {
   // the active one, [n_time][n_ant][n_chan][2 hands] complex of the compute
   // precision, or null (then formed per sample)
   const void* otab;
+  // intervals of one channel each, the split schedule's pass over 16 channels
+  // per wavefront (qc_band.h) with these steps [n_row]; else null
+  const BandStep* band_steps;
+  // that pass: the direction-dependent fixed terms (diagonal gains), each as a
+  // table [n_gt][n_gf][n_ant][n_dir][2 hands] complex of the compute precision
+  int n_dd;
+  int dd_term[BAND_MAX_DD];
+  const void* dd_tab[BAND_MAX_DD];
 };
+
+// Fills the steps of the single-channel-interval split pass for n_part parts
+// per gain time (L.row_lo / row_hi) on `stream`.
+hipError_t launch_band_steps(const SolveLaunch& L, int n_part, BandStep* steps, hipStream_t stream);
+// LDS bytes of that pass for n_ant antennas (FP32 or FP64 sums)
+size_t band_lds_bytes_for(int n_ant, bool fp32);
+// Table of direction-dependent fixed term j (diagonal gains) for that pass:
+// bytes needed, and the fill on `stream`.
+size_t dd_table_bytes(const SolveLaunch& L, int j);
+hipError_t launch_dd_table(const SolveLaunch& L, int j, void* table, hipStream_t stream);
 
 // Fills L.otab (see above) on `stream`; `bytes` of table memory are needed.
 size_t chain_table_bytes(const SolveLaunch& L);

@@ -1450,14 +1450,6 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
               oq0 = oq0 * Jq.a; oq1 = oq1 * Jq.d;
             }
           }
-          m22<T> Bs[NG], Bsc[NG];
-          cx<T> gp0[NG], gp1[NG], gq0[NG], gq1[NG];
-#pragma unroll
-          for (int g = 0; g < NG; ++g) {
-            Bs[g] = mzero<T>();
-            Bsc[g] = mzero<T>();
-            gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
-          }
           // active gains of p and q for gain direction gd
           auto active_diag = [&](int gd, cx<T>& a0, cx<T>& a1, cx<T>& b0, cx<T>& b1) {
             if constexpr (is_param(KIND)) {
@@ -1470,40 +1462,96 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
               b0 = gqq[0]; b1 = gqq[3];
             }
           };
-          cx<T> hp0, hp1, hq0, hq1;
-          // one gain direction: every model direction maps to it, look up once
-          if constexpr (NG == 1) active_diag(0, hp0, hp1, hq0, hq1);
-          m22<T> Vm = mzero<T>();
-          // One sample's model holds its directions side by side (four complex64
-          // directions fill one 128-byte line): read four directions at a time, so
-          // the line is used while it is cached rather than a quarter per direction
-          // iteration, with the chain evaluation between the quarters. The index is
-          // clamped, not branched on, so the loads are issued together. FP64
-          // products have no registers to spare for it. With one row per lane
-          // two directions at a time keep a third wavefront per SIMD, except in
-          // the diagonal split pass, whose kernel is built for three wavefronts
-          // per SIMD with four.
-          // (A predicted model has no line to keep: one direction at a time.)
+          // Model directions read in groups: one sample's model holds its
+          // directions side by side (four complex64 directions fill one
+          // 128-byte line), so four at a time use the line while it is
+          // cached rather than a quarter per direction iteration.  The index
+          // is clamped, not branched on, so the loads are issued together.
+          // FP64 products have no registers to spare for it; with one row per
+          // lane two directions at a time keep a third wavefront per SIMD,
+          // except in the diagonal split pass, whose kernel is built for
+          // three wavefronts per SIMD with four.  (A predicted model has no
+          // line to keep: one direction at a time.)
           constexpr int MCH = (SKY || sizeof(T) != 4)                          ? 1
                               : LANE_ROWS && !(PASS_ONLY && KIND == KIND_DIAG) ? 2
                                                                                : 4;
+          // direction-dependent part of o for antennas p and q at direction d (one
+          // loop, so that the lookups of both antennas are in flight together)
+          auto dd_factor = [&](int xp, int xq, int d, cx<T>& p0, cx<T>& p1, cx<T>& q0, cx<T>& q1) {
+            for (int j = 0; j < n_term; ++j) {
+              if (j == act || CH.t[j].n_gdir <= 1) continue;
+              const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, xp, d, nu);
+              const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, xq, d, nu);
+              p0 = p0 * Jp.a;
+              p1 = p1 * Jp.d;
+              q0 = q0 * Jq.a;
+              q1 = q1 * Jq.d;
+            }
+          };
+          if constexpr (NG == 1) {
+            // One gain direction: the active gains h do not depend on the
+            // direction, so with E_ij = sum_d o_{p,d,i} M_d,ij conj(o_{q,d,j})
+            //   V_ij = h_{p,i} E_ij conj(h_{q,j}),  B_ij = E_ij conj(h_{q,j}),
+            //   Bc_ij = conj(E_ji) conj(h_{p,j}):
+            // the directions are summed once, into E, at four complex
+            // products and four multiply-adds per direction.
+            cx<T> hp0, hp1, hq0, hq1;
+            active_diag(0, hp0, hp1, hq0, hq1);
+            m22<T> E = mzero<T>();
+            for (int d0 = 0; d0 < n_dir; d0 += MCH) {
+              m22<T> Mc[MCH];
+#pragma unroll
+              for (int k = 0; k < MCH; ++k) Mc[k] = model_at(min(d0 + k, n_dir - 1));
+              for (int k = 0; k < MCH && d0 + k < n_dir; ++k) {
+                const int d = d0 + k;
+                cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
+                dd_factor(p, q, d, rp0, rp1, rq0, rq1);
+                m22<T> Mk = Mc[0];
+#pragma unroll
+                for (int u = 1; u < MCH; ++u) Mk = msel(k == u, Mc[u], Mk);
+                E.a = cfma(mulc(rp0, rq0), Mk.a, E.a);
+                E.b = cfma(mulc(rp0, rq1), Mk.b, E.b);
+                E.c = cfma(mulc(rp1, rq0), Mk.c, E.c);
+                E.d = cfma(mulc(rp1, rq1), Mk.d, E.d);
+              }
+            }
+            E = select_m(use, E);
+            m22<T> B, Bc;
+            B.a = mulc(E.a, hq0);
+            B.b = mulc(E.b, hq1);
+            B.c = mulc(E.c, hq0);
+            B.d = mulc(E.d, hq1);
+            Bc.a = conj(E.a * hp0);
+            Bc.b = conj(E.c * hp1);
+            Bc.c = conj(E.b * hp0);
+            Bc.d = conj(E.d * hp1);
+            const m22<T> Vm = rowscale(hp0, hp1, B);
+            const m22<T> R = D - Vm;
+            const m22<T> WR = wmul(R, w0, w1, w2, w3);
+            contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, hp0, hp1, tpn, PACC ? pacc : prow, pk_amp);
+            contrib<KIND, true, T>(aq0, aq1, Bc, herm(WR), w0, w2, w1, w3, hq0, hq1, tpn, qacc, pk_amp);
+            chi = chisq_acc(WR, R, chi);
+          } else {
+          m22<T> Bs[NG], Bsc[NG];
+          cx<T> gp0[NG], gp1[NG], gq0[NG], gq1[NG];
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            Bs[g] = mzero<T>();
+            Bsc[g] = mzero<T>();
+            gp0[g] = gp1[g] = gq0[g] = gq1[g] = cone<T>();
+          }
+          cx<T> hp0, hp1, hq0, hq1;
+          m22<T> Vm = mzero<T>();
           for (int d0 = 0; d0 < n_dir; d0 += MCH) {
             m22<T> Mc[MCH];
 #pragma unroll
             for (int k = 0; k < MCH; ++k) Mc[k] = model_at(min(d0 + k, n_dir - 1));
             for (int k = 0; k < MCH && d0 + k < n_dir; ++k) {
               const int d = d0 + k;
-              const int gd = NG == 1 ? 0 : TA.d_map[d];
-              if constexpr (NG > 1) active_diag(gd, hp0, hp1, hq0, hq1);
-              // direction-dependent part of o
+              const int gd = TA.d_map[d];
+              active_diag(gd, hp0, hp1, hq0, hq1);
               cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
-              for (int j = 0; j < n_term; ++j) {
-                if (j == act || CH.t[j].n_gdir <= 1) continue;
-                const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, p, d, nu);
-                const m22<T> Jq = term_jones<T>(CH.t[j], n_ant, t, cc, q, d, nu);
-                rp0 = rp0 * Jp.a; rp1 = rp1 * Jp.d;
-                rq0 = rq0 * Jq.a; rq1 = rq1 * Jq.d;
-              }
+              dd_factor(p, q, d, rp0, rp1, rq0, rq1);
               const cx<T> cp0 = hp0 * rp0, cp1 = hp1 * rp1;
               const cx<T> cq0 = hq0 * rq0, cq1 = hq1 * rq1;
               m22<T> Mk = Mc[0];
@@ -1547,6 +1595,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
                                     pk_amp);
           }
           chi = chisq_acc(WR, R, chi);
+          }
         } else if constexpr (FB) {
           // Any chain, with the full blocks a general left factor needs: a
           // first sweep over the directions forms the model and the residual;

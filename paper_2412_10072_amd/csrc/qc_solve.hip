@@ -37,7 +37,106 @@ __global__ void __launch_bounds__(256) k_chain_table(SolveLaunch L, cx<T>* out) 
   }
 }
 
+// Steps of every part: a wavefront per 64-row window of a part (windows start
+// at the part's first row, so every window starts a run); within a window a
+// run of equal (time, p) is cut into steps of four rows from its first row.
+__global__ void __launch_bounds__(64) k_band_steps(VisArgs V, const long long* row_lo, const long long* row_hi,
+                                                   int n_part, int windows, BandStep* steps) {
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x % windows;
+  const int rest = blockIdx.x / windows;
+  const int part = rest % n_part;
+  const int gt = rest / n_part;
+  const long long lo = row_lo[gt], n = row_hi[gt] - lo;
+  const long long r_lo = lo + (n * part) / n_part, r_hi = lo + (n * (part + 1)) / n_part;
+  const long long r = r_lo + (long long)w * 64 + lane;
+  const bool in = r < r_hi;
+  const int t = in ? V.row_time[r] : -1;
+  const int p = in ? V.ant1[r] : -1;
+  const int q = in ? V.ant2[r] : -1;
+  const int t_up = __shfl_up(t, 1), p_up = __shfl_up(p, 1);
+  const int q1 = __shfl_down(q, 1), q2 = __shfl_down(q, 2), q3 = __shfl_down(q, 3);
+  const bool head = in && (lane == 0 || t_up != t || p_up != p);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long ins = __ballot(in);
+  if (!in) return;
+  // first row of this lane's run, and the row after it
+  const unsigned long long upto = (2ull << lane) - 1;     // lanes 0..lane (all 64 for lane 63)
+  const int run0 = 63 - __clzll(heads & upto);
+  const unsigned long long above = heads & ~upto;
+  const int n_in = __popcll(ins);
+  const int run1 = above ? __ffsll(above) - 1 : n_in;
+  if ((lane - run0) % 4 != 0) return;
+  BandStep s;
+  s.k = min(4, run1 - lane);
+  s.t = t;
+  s.p = p;
+  const int qs[4] = {q, q1, q2, q3};   // (rows past the run are not read: g < k)
+  int dup = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    s.q[g] = (g < s.k && qs[g] != p) ? qs[g] : -1;
+#pragma unroll
+    for (int h = 0; h < g; ++h)
+      if (s.q[g] >= 0 && s.q[g] == s.q[h]) dup = 1;
+  }
+  s.dup = dup;
+  steps[r] = s;
+}
+
+// Direction-dependent fixed term j (diagonal gains) by model direction: entry
+// ((g * n_ant + a) * n_dir + d) * 2 + hand, g = gain time * n_gf + gain
+// frequency.  One workgroup per (gain block, antenna), lanes over directions.
+template <typename T>
+__global__ void __launch_bounds__(64) k_dd_table(TermArgs tm, int n_ant, int n_dir, cx<T>* out) {
+  const int a = blockIdx.x % n_ant;
+  const size_t gb = blockIdx.x / n_ant;
+  for (int d = threadIdx.x; d < n_dir; d += blockDim.x) {
+    const size_t blk = (gb * n_ant + a) * tm.n_gdir + tm.d_map[d];
+    const double2 g0 = tm.gains[4 * blk], g3 = tm.gains[4 * blk + 3];
+    const size_t o = ((gb * n_ant + a) * n_dir + d) * 2;
+    out[o] = cmake<T>((T)g0.x, (T)g0.y);
+    out[o + 1] = cmake<T>((T)g3.x, (T)g3.y);
+  }
+}
+
 }  // namespace
+
+size_t dd_table_bytes(const SolveLaunch& L, int j) {
+  const TermArgs& tm = L.chain.t[j];
+  const size_t elt = L.prec_mixed ? sizeof(cx<float>) : sizeof(cx<double>);
+  return (size_t)tm.n_gt * tm.n_gf * L.vis.n_ant * L.vis.n_dir * 2 * elt;
+}
+
+hipError_t launch_dd_table(const SolveLaunch& L, int j, void* table, hipStream_t stream) {
+  const TermArgs& tm = L.chain.t[j];
+  const long long grid = (long long)tm.n_gt * tm.n_gf * L.vis.n_ant;
+  if (grid == 0) return hipSuccess;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (L.prec_mixed)
+    hipLaunchKernelGGL(k_dd_table<float>, dim3((unsigned)grid), dim3(64), 0, stream, tm, L.vis.n_ant, L.vis.n_dir,
+                       reinterpret_cast<cx<float>*>(table));
+  else
+    hipLaunchKernelGGL(k_dd_table<double>, dim3((unsigned)grid), dim3(64), 0, stream, tm, L.vis.n_ant, L.vis.n_dir,
+                       reinterpret_cast<cx<double>*>(table));
+  return hipGetLastError();
+}
+
+size_t band_lds_bytes_for(int n_ant, bool fp32) {
+  return (fp32 ? sizeof(float) : sizeof(double)) * (size_t)n_ant * KindInfo<KIND_DIAG>::NV * 16;
+}
+
+hipError_t launch_band_steps(const SolveLaunch& L, int n_part, BandStep* steps, hipStream_t stream) {
+  const TermArgs& ta = L.chain.t[L.chain.active];
+  const long long rows_max = (L.vis.n_row + n_part - 1) / n_part + 1;   // rows of the largest part
+  const int windows = (int)((rows_max + 63) / 64);
+  const long long grid = (long long)ta.n_gt * n_part * windows;
+  if (grid == 0) return hipSuccess;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_band_steps, dim3((unsigned)grid), dim3(64), 0, stream, L.vis, L.row_lo, L.row_hi, n_part,
+                     windows, steps);
+  return hipGetLastError();
+}
 
 size_t chain_table_bytes(const SolveLaunch& L) {
   const size_t elt = L.prec_mixed ? sizeof(cx<float>) : sizeof(cx<double>);

@@ -38,6 +38,7 @@
 #include <algorithm>
 
 #include "qc_interval.h"
+#include "qc_band.h"
 
 namespace qc {
 namespace {
@@ -251,6 +252,44 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
   return hipGetLastError();
 }
 
+// Split schedule over intervals of one channel each (qc_band.h): the band
+// pass, then the same update as for the other split passes.
+template <typename S, typename T>
+hipError_t launch_band(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
+  const size_t lds = band_lds_bytes_for(L.vis.n_ant, sizeof(T) == 4);
+  const size_t lds_u = interval_lds_bytes<KIND_DIAG, T, 1, false>(L.vis.n_ant, 0);
+  if (lds_out) *lds_out = lds;
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  auto ku = k_split_update<KIND_DIAG, T, 1, false>;
+  if (lds_u > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(ku),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_u);
+    if (e != hipSuccess) return e;
+  }
+  const TermArgs& ta = L.chain.t[L.chain.active];
+  const int n_int = ta.n_gt * ta.n_gf;
+  if (n_int == 0) return hipSuccess;
+  if (P.phase == 0) {
+    hipLaunchKernelGGL(k_split_reset, dim3((n_int + 255) / 256), dim3(256), 0, stream, P.state, n_int);
+  } else {
+    const long long grid = (long long)((L.vis.n_chan + 15) / 16) * ta.n_gt * P.n_part;
+    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    const uint8_t* done = P.state.done;
+    if (L.n_dd == 0)
+      hipLaunchKernelGGL((k_band_pass<S, T, 0>), dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part,
+                         P.partials, done);
+    else if (L.n_dd == 1)
+      hipLaunchKernelGGL((k_band_pass<S, T, 1>), dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part,
+                         P.partials, done);
+    else
+      hipLaunchKernelGGL((k_band_pass<S, T, 2>), dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part,
+                         P.partials, done);
+    hipLaunchKernelGGL(ku, dim3((unsigned)n_int), dim3(256), lds_u, stream, L, P.n_part,
+                       (const double*)P.partials, P.state);
+  }
+  return hipGetLastError();
+}
+
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool LMT = false, bool SKY = false>
 hipError_t launch_one(const SolveLaunch& L, hipStream_t stream, size_t* lds_out) {
   constexpr bool FB = CHM == CHAIN_LEFT;
@@ -337,6 +376,9 @@ hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t s
   const ChainArgs& ch = L.chain;
   const TermArgs& ta = ch.t[ch.active];
   if (L.sky.comp) return launch_kind_sky<KIND, S, T>(L, P, stream, lds_out);
+  if constexpr (KIND == KIND_DIAG) {
+    if (P && L.band_steps) return launch_band<S, T>(L, *P, stream, lds_out);
+  }
   if constexpr (KIND != KIND_DELOFF) {          // (the host offers no LM for delay-and-offset terms)
     if (L.damping == DAMP_LM && !P) return launch_kind_lm<KIND, S, T>(L, stream, lds_out);
   }
