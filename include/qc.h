@@ -153,7 +153,11 @@ double      qc_last_kernel_ms(qc_ctx* ctx);
 /* Launch shape of the per-interval solve used by qc_solve_interval,
  * qc_solve_chain: waves per workgroup (1, 2, 4, 8; 0 = 4) and rows per
  * wavefront step (1, 2, 4; 0 = 4 rows of 16 lanes).
- * Multi-row steps apply to single-term, single-direction chains only. */
+ * Multi-row steps apply to single-term, single-direction chains only.
+ * rows_per_step 8 sets the split schedule of one-channel intervals (a
+ * bandpass per channel on a diagonal chain) to steps of 8 rows x 8 channels
+ * instead of 4 rows x 16 channels, and leaves the other kernels at their
+ * default. */
 qc_status   qc_ctx_set_tile(qc_ctx* ctx, int32_t waves, int32_t rows_per_step);
 /* Schedule of qc_solve_interval: parts = 0 chooses automatically (a term with
  * fewer intervals than four times the compute units, of >= 2^18 samples on

@@ -7,14 +7,16 @@
 // row, so a wavefront that took one interval would read one sample per row
 // at the row stride.  Here a wavefront takes 16 neighbouring channels -- 16
 // intervals -- and steps through a part of their rows four rows at a time,
-// lane (g, c) = (row g of the step, channel c).  Every sample load is then a
-// contiguous segment of 16 channels, and the intervals need no reduction
-// across lanes: each lane's channel is its own interval.
+// lane (g, c) = (row g of the step, channel c) (or 8 channels and 8 rows,
+// whose LDS slots are half as large: for arrays whose 16-channel slots do not
+// fit).  Every sample load is then a contiguous segment of channels, and the
+// intervals need no reduction across lanes: each lane's channel is its own
+// interval.
 //
-// A step holds up to four consecutive rows of one time that share antenna p
-// and differ in antenna q (a p-run of the row order).  The antenna-p sums stay
-// in registers over the run and are summed over the four rows of the step
-// when p changes; the antenna-q sums go straight to the wavefront's LDS slots
+// A step holds up to four (eight) consecutive rows of one time that share
+// antenna p and differ in antenna q (a p-run of the row order).  The
+// antenna-p sums stay in registers over the run and are summed over the rows
+// of the step when p changes; the antenna-q sums go straight to the wavefront's LDS slots
 // [antenna][value][channel], which the lanes of one step address without
 // collision (distinct q per row, distinct channel per lane), so LDS atomics
 // add them in program order and the result does not depend on timing.  At
@@ -28,10 +30,11 @@
 namespace qc {
 namespace {
 
-constexpr int BAND_CW = 16;        // channels per wavefront
 constexpr int BAND_NV = KindInfo<KIND_DIAG>::NV;
 
-// A step read through the scalar cache (its index is the same in every lane).
+// A step read through the scalar cache (its index is the same in every lane);
+// R rows.
+template <int R>
 __device__ __forceinline__ BandStep band_step_at(const BandStep* steps, long long r) {
   using CP = const __attribute__((address_space(4))) int*;
   const CP b = (CP)(steps + r);
@@ -40,17 +43,44 @@ __device__ __forceinline__ BandStep band_step_at(const BandStep* steps, long lon
   s.t = b[1];
   s.p = b[2];
   s.dup = b[3];
-  s.q[0] = b[4];
-  s.q[1] = b[5];
-  s.q[2] = b[6];
-  s.q[3] = b[7];
+#pragma unroll
+  for (int g = 0; g < BAND_MAX_ROWS; ++g) s.q[g] = g < R ? b[4 + g] : -1;
   return s;
 }
 
-// LDS slot of (antenna, value, channel)
-template <typename A>
+// LDS slot of (antenna, value, channel) for CW channels per wavefront
+template <typename A, int CW>
 __device__ __forceinline__ A* band_slot(int ant, int k, int cl) {
-  return lds_at<A>(0) + ((size_t)ant * BAND_NV + k) * BAND_CW + cl;
+  return lds_at<A>(0) + ((size_t)ant * BAND_NV + k) * CW + cl;
+}
+
+// x of the lane 8 apart in the same 16-lane row (DPP row rotate by 8)
+constexpr int DPP_ROW_ROR8 = 0x128;
+__device__ __forceinline__ float ror8(float x) {
+  return ffrom((unsigned)__builtin_amdgcn_mov_dpp((int)fbits(x), DPP_ROW_ROR8, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double ror8(double x) {
+  return dfrom((unsigned)__builtin_amdgcn_mov_dpp((int)lo32(x), DPP_ROW_ROR8, 0xF, 0xF, true),
+               (unsigned)__builtin_amdgcn_mov_dpp((int)hi32(x), DPP_ROW_ROR8, 0xF, 0xF, true));
+}
+
+// Pair sums across the lanes OFF apart, OFF in {32, 16, 8}: lanes with bit
+// OFF clear keep x summed over the pair, the others y; the lane's channel
+// (its low bits) is kept.
+template <int OFF, typename A>
+__device__ __forceinline__ A band_pair(A x, A y, bool up) {
+  if constexpr (OFF == 8) {
+    const A send = up ? x : y;
+    const A keep = up ? y : x;
+    return keep + ror8(send);
+  } else {
+    return pair_step<OFF>(x, y, up);
+  }
+}
+template <int OFF, typename A>
+__device__ __forceinline__ A band_full(A x) {
+  if constexpr (OFF == 8) return x + ror8(x);
+  else return full_step<OFF>(x);
 }
 
 template <typename A>
@@ -64,13 +94,14 @@ __device__ __forceinline__ int ld_uniform(const int* base, long long i) {
   return ((CP)base)[i];
 }
 
-// grid: (16-channel slice, gain time, part), slice fastest; one wavefront each.
+// grid: (CW-channel slice, gain time, part), slice fastest; one wavefront
+// each, lanes (row g < 64 / CW of the step, channel c < CW).
 // ND: direction-dependent fixed terms, read from their tables (L.dd_tab).
-template <typename S, typename T, int ND>
+template <typename S, typename T, int ND, int CW>
 __global__ void __launch_bounds__(64) k_band_pass(SolveLaunch L, int n_part, double* partials, const uint8_t* done) {
   using A = T;
   constexpr int NV = BAND_NV;
-  constexpr int CW = BAND_CW;
+  constexpr int NR = 64 / CW;           // rows per step
   const VisArgs& V = L.vis;
   const ChainArgs& CH = L.chain;
   const int act = CH.active;
@@ -128,19 +159,20 @@ __global__ void __launch_bounds__(64) k_band_pass(SolveLaunch L, int n_part, dou
   for (int k = 0; k < 8; ++k) pacc[k] = A(0);
   int p_cur = -1, t_cur = -1;
 
-  // the run's antenna-p sums, summed over the four rows of the step, into LDS
+  // the run's antenna-p sums, summed over the NR rows of the step, into LDS
   auto flush_p = [&]() {
     if (p_cur < 0) return;
-    const bool up32 = (lane & 32) != 0, up16 = (lane & 16) != 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) pacc[j] = pair_step<32>(pacc[j], pacc[j + 4], up32);
+    for (int j = 0; j < 4; ++j) pacc[j] = band_pair<32>(pacc[j], pacc[j + 4], (lane & 32) != 0);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) pacc[j] = pair_step<16>(pacc[j], pacc[j + 2], up16);
-    // lane (g, c) holds values 2g and 2g + 1 of its channel
+    for (int j = 0; j < 2; ++j) pacc[j] = band_pair<16>(pacc[j], pacc[j + 2], (lane & 16) != 0);
+    if constexpr (CW == 8) pacc[0] = band_pair<8>(pacc[0], pacc[1], (lane & 8) != 0);
+    // lane (g, c) holds values PER g .. PER g + PER - 1 of its channel
+    constexpr int PER = 8 / NR;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int k = 2 * g + j;
-      if (k < NV && cin) lds_add(band_slot<A>(p_cur, k, cl), pacc[j]);
+    for (int j = 0; j < PER; ++j) {
+      const int k = PER * g + j;
+      if (k < NV && cin) lds_add(band_slot<A, CW>(p_cur, k, cl), pacc[j]);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) pacc[k] = A(0);
@@ -165,11 +197,11 @@ __global__ void __launch_bounds__(64) k_band_pass(SolveLaunch L, int n_part, dou
 
   long long r = r_lo;
   BandStep st;
-  if (r < r_hi) st = band_step_at(L.band_steps, r);
+  if (r < r_hi) st = band_step_at<NR>(L.band_steps, r);
   while (r < r_hi) {
     const long long r_next = r + max(st.k, 1);
     BandStep nx;
-    if (r_next < r_hi) nx = band_step_at(L.band_steps, r_next);
+    if (r_next < r_hi) nx = band_step_at<NR>(L.band_steps, r_next);
     const int t = st.t, p = st.p;
     if (t != t_cur) {
       flush_p();
@@ -181,7 +213,9 @@ __global__ void __launch_bounds__(64) k_band_pass(SolveLaunch L, int n_part, dou
       flush_p();
       p_cur = p;
     }
-    const int q = g == 0 ? st.q[0] : g == 1 ? st.q[1] : g == 2 ? st.q[2] : st.q[3];
+    int q = st.q[0];
+#pragma unroll
+    for (int h = 1; h < NR; ++h) q = g == h ? st.q[h] : q;
     const bool row_ok = q >= 0;
     const int qq = row_ok ? q : p;
     const size_t s = (size_t)(r + (row_ok ? g : 0)) * n_chan + cc;
@@ -282,14 +316,14 @@ __global__ void __launch_bounds__(64) k_band_pass(SolveLaunch L, int n_part, dou
     if (!st.dup) {
       if (add) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) lds_add(band_slot<A>(q, k, cl), qv[k]);
+        for (int k = 0; k < NV; ++k) lds_add(band_slot<A, CW>(q, k, cl), qv[k]);
       }
     } else {
       // two rows of the step share antenna q: one row at a time
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < NR; ++h) {
         if (add && g == h) {
 #pragma unroll
-          for (int k = 0; k < NV; ++k) lds_add(band_slot<A>(q, k, cl), qv[k]);
+          for (int k = 0; k < NV; ++k) lds_add(band_slot<A, CW>(q, k, cl), qv[k]);
         }
       }
     }
@@ -298,10 +332,11 @@ __global__ void __launch_bounds__(64) k_band_pass(SolveLaunch L, int n_part, dou
   }
   flush_p();
   flush_lds();
-  // chi^2 of the channel: the four rows' sums
+  // chi^2 of the channel: the sums of the step's rows
   double cs = chi64;
-  cs = full_step<32>(cs);
-  cs = full_step<16>(cs);
+  cs = band_full<32>(cs);
+  cs = band_full<16>(cs);
+  if constexpr (CW == 8) cs = band_full<8>(cs);
   if (g == 0 && cin) Pc[stride - 1] = cs;
 }
 

@@ -18,8 +18,8 @@
 constexpr int SPLIT_WG_PER_CU = 32;
 // Wavefronts per compute unit that the split over one-channel intervals aims
 // at (each holds 16 intervals and 24 KiB of LDS at 64 antennas, so about six
-// are resident per CU: four rounds of them)
-constexpr int BAND_WAVES_PER_CU = 24;
+// are resident per CU: two rounds of them; 6 to 48 measured within 6%)
+constexpr int BAND_WAVES_PER_CU = 12;
 
 struct qc_ctx {
   int device = 0;

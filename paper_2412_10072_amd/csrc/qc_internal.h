@@ -352,13 +352,14 @@ __device__ __forceinline__ m22<T> sky_model(const SkyArgs& K, double un, double 
 // the index of its first row: up to four consecutive rows of one time that
 // share antenna p.
 constexpr int BAND_MAX_DD = 2;   // direction-dependent fixed terms the pass takes
+constexpr int BAND_MAX_ROWS = 8; // rows per step (64 lanes over 16 channels x 4 rows or 8 x 8)
 
 struct BandStep {
   int k;        // rows in the step; 0: no step starts at this row
   int t;        // time of the rows
   int p;        // antenna p of the rows
   int dup;      // two rows share antenna q: their q sums are added one row after the other
-  int q[4];     // antenna q of each row, -1 past k or for a row that adds nothing (p == q)
+  int q[BAND_MAX_ROWS];   // antenna q of each row, -1 past k or for a row that adds nothing (p == q)
 };
 
 struct SolveLaunch {
@@ -399,6 +400,7 @@ struct SolveLaunch {
   // intervals of one channel each, the split schedule's pass over 16 channels
   // per wavefront (qc_band.h) with these steps [n_row]; else null
   const BandStep* band_steps;
+  int band_rows;              // rows per step of that pass: 4 or 8
   // that pass: the direction-dependent fixed terms (diagonal gains), each as a
   // table [n_gt][n_gf][n_ant][n_dir][2 hands] complex of the compute precision
   int n_dd;
@@ -406,11 +408,12 @@ struct SolveLaunch {
   const void* dd_tab[BAND_MAX_DD];
 };
 
-// Fills the steps of the single-channel-interval split pass for n_part parts
-// per gain time (L.row_lo / row_hi) on `stream`.
-hipError_t launch_band_steps(const SolveLaunch& L, int n_part, BandStep* steps, hipStream_t stream);
-// LDS bytes of that pass for n_ant antennas (FP32 or FP64 sums)
-size_t band_lds_bytes_for(int n_ant, bool fp32);
+// Fills the steps (of `rows` rows at most) of the single-channel-interval
+// split pass for n_part parts per gain time (L.row_lo / row_hi) on `stream`.
+hipError_t launch_band_steps(const SolveLaunch& L, int n_part, int rows, BandStep* steps, hipStream_t stream);
+// LDS bytes of that pass for n_ant antennas (FP32 or FP64 sums) and `rows`
+// rows per step (64 / rows channels per wavefront)
+size_t band_lds_bytes_for(int n_ant, bool fp32, int rows);
 // Table of direction-dependent fixed term j (diagonal gains) for that pass:
 // bytes needed, and the fill on `stream`.
 size_t dd_table_bytes(const SolveLaunch& L, int j);

@@ -39,9 +39,9 @@ __global__ void __launch_bounds__(256) k_chain_table(SolveLaunch L, cx<T>* out) 
 
 // Steps of every part: a wavefront per 64-row window of a part (windows start
 // at the part's first row, so every window starts a run); within a window a
-// run of equal (time, p) is cut into steps of four rows from its first row.
+// run of equal (time, p) is cut into steps of `rows` rows from its first row.
 __global__ void __launch_bounds__(64) k_band_steps(VisArgs V, const long long* row_lo, const long long* row_hi,
-                                                   int n_part, int windows, BandStep* steps) {
+                                                   int n_part, int windows, int rows, BandStep* steps) {
   const int lane = threadIdx.x;
   const int w = blockIdx.x % windows;
   const int rest = blockIdx.x / windows;
@@ -55,7 +55,10 @@ __global__ void __launch_bounds__(64) k_band_steps(VisArgs V, const long long* r
   const int p = in ? V.ant1[r] : -1;
   const int q = in ? V.ant2[r] : -1;
   const int t_up = __shfl_up(t, 1), p_up = __shfl_up(p, 1);
-  const int q1 = __shfl_down(q, 1), q2 = __shfl_down(q, 2), q3 = __shfl_down(q, 3);
+  int qs[BAND_MAX_ROWS];     // q of the next rows (those past the run are not read: g < k)
+  qs[0] = q;
+#pragma unroll
+  for (int g = 1; g < BAND_MAX_ROWS; ++g) qs[g] = __shfl_down(q, g);
   const bool head = in && (lane == 0 || t_up != t || p_up != p);
   const unsigned long long heads = __ballot(head);
   const unsigned long long ins = __ballot(in);
@@ -66,15 +69,14 @@ __global__ void __launch_bounds__(64) k_band_steps(VisArgs V, const long long* r
   const unsigned long long above = heads & ~upto;
   const int n_in = __popcll(ins);
   const int run1 = above ? __ffsll(above) - 1 : n_in;
-  if ((lane - run0) % 4 != 0) return;
+  if ((lane - run0) % rows != 0) return;
   BandStep s;
-  s.k = min(4, run1 - lane);
+  s.k = min(rows, run1 - lane);
   s.t = t;
   s.p = p;
-  const int qs[4] = {q, q1, q2, q3};   // (rows past the run are not read: g < k)
   int dup = 0;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int g = 0; g < BAND_MAX_ROWS; ++g) {
     s.q[g] = (g < s.k && qs[g] != p) ? qs[g] : -1;
 #pragma unroll
     for (int h = 0; h < g; ++h)
@@ -122,11 +124,12 @@ hipError_t launch_dd_table(const SolveLaunch& L, int j, void* table, hipStream_t
   return hipGetLastError();
 }
 
-size_t band_lds_bytes_for(int n_ant, bool fp32) {
-  return (fp32 ? sizeof(float) : sizeof(double)) * (size_t)n_ant * KindInfo<KIND_DIAG>::NV * 16;
+size_t band_lds_bytes_for(int n_ant, bool fp32, int rows) {
+  return (fp32 ? sizeof(float) : sizeof(double)) * (size_t)n_ant * KindInfo<KIND_DIAG>::NV * (64 / rows);
 }
 
-hipError_t launch_band_steps(const SolveLaunch& L, int n_part, BandStep* steps, hipStream_t stream) {
+hipError_t launch_band_steps(const SolveLaunch& L, int n_part, int rows, BandStep* steps, hipStream_t stream) {
+  if (rows != 4 && rows != 8) return hipErrorInvalidValue;
   const TermArgs& ta = L.chain.t[L.chain.active];
   const long long rows_max = (L.vis.n_row + n_part - 1) / n_part + 1;   // rows of the largest part
   const int windows = (int)((rows_max + 63) / 64);
@@ -134,7 +137,7 @@ hipError_t launch_band_steps(const SolveLaunch& L, int n_part, BandStep* steps, 
   if (grid == 0) return hipSuccess;
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_band_steps, dim3((unsigned)grid), dim3(64), 0, stream, L.vis, L.row_lo, L.row_hi, n_part,
-                     windows, steps);
+                     windows, rows, steps);
   return hipGetLastError();
 }
 

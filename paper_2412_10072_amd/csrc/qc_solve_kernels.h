@@ -256,7 +256,7 @@ hipError_t launch_split_one(const SolveLaunch& L, const SplitLaunch& P, hipStrea
 // pass, then the same update as for the other split passes.
 template <typename S, typename T>
 hipError_t launch_band(const SolveLaunch& L, const SplitLaunch& P, hipStream_t stream, size_t* lds_out) {
-  const size_t lds = band_lds_bytes_for(L.vis.n_ant, sizeof(T) == 4);
+  const size_t lds = band_lds_bytes_for(L.vis.n_ant, sizeof(T) == 4, L.band_rows);
   const size_t lds_u = interval_lds_bytes<KIND_DIAG, T, 1, false>(L.vis.n_ant, 0);
   if (lds_out) *lds_out = lds;
   if (lds > 64 * 1024) return hipErrorInvalidValue;
@@ -272,18 +272,17 @@ hipError_t launch_band(const SolveLaunch& L, const SplitLaunch& P, hipStream_t s
   if (P.phase == 0) {
     hipLaunchKernelGGL(k_split_reset, dim3((n_int + 255) / 256), dim3(256), 0, stream, P.state, n_int);
   } else {
-    const long long grid = (long long)((L.vis.n_chan + 15) / 16) * ta.n_gt * P.n_part;
+    const int cw = 64 / L.band_rows;
+    const long long grid = (long long)((L.vis.n_chan + cw - 1) / cw) * ta.n_gt * P.n_part;
     if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
     const uint8_t* done = P.state.done;
-    if (L.n_dd == 0)
-      hipLaunchKernelGGL((k_band_pass<S, T, 0>), dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part,
-                         P.partials, done);
-    else if (L.n_dd == 1)
-      hipLaunchKernelGGL((k_band_pass<S, T, 1>), dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part,
-                         P.partials, done);
-    else
-      hipLaunchKernelGGL((k_band_pass<S, T, 2>), dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part,
-                         P.partials, done);
+    void (*kern)(SolveLaunch, int, double*, const uint8_t*) = nullptr;
+    if (L.band_rows == 8) {
+      kern = L.n_dd == 0 ? k_band_pass<S, T, 0, 8> : L.n_dd == 1 ? k_band_pass<S, T, 1, 8> : k_band_pass<S, T, 2, 8>;
+    } else {
+      kern = L.n_dd == 0 ? k_band_pass<S, T, 0, 16> : L.n_dd == 1 ? k_band_pass<S, T, 1, 16> : k_band_pass<S, T, 2, 16>;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), lds, stream, L, P.n_part, P.partials, done);
     hipLaunchKernelGGL(ku, dim3((unsigned)n_int), dim3(256), lds_u, stream, L, P.n_part,
                        (const double*)P.partials, P.state);
   }

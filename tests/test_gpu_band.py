@@ -29,6 +29,7 @@ def say(msg):
 def split_ctx(qc_lib):
     yield qc_lib
     qc_lib.set_split(0)
+    qc_lib.set_tile(0, 0)
 
 
 def band_chain(seed, n_ant=7, n_time=12, n_chan=21, n_dir=3, sigma=0.02, flag_frac=0.1):
@@ -47,12 +48,14 @@ def band_chain(seed, n_ant=7, n_time=12, n_chan=21, n_dir=3, sigma=0.02, flag_fr
     return vis, [K, unit_like(B), dE]
 
 
+@pytest.mark.parametrize("rows", [4, 8])
 @pytest.mark.parametrize("parts", [2, 5, 9])
-def test_band_chain_fp64_fixed_iterations(split_ctx, parts):
-    say(f"band chain parts={parts}")
+def test_band_chain_fp64_fixed_iterations(split_ctx, parts, rows):
+    say(f"band chain parts={parts} rows per step={rows}")
     vis, chain = band_chain(311)
     ref, rst = o_solver.solve_term(vis, chain, 1, tol=-1.0, max_iter=4)
     split_ctx.set_split(parts)
+    split_ctx.set_tile(0, rows)
     got, st = gpu_solve(split_ctx, vis, chain, 1, tol=-1.0, max_iter=4, prec="fp64")
     assert split_ctx.last_split_parts() == parts
     assert (st["iters"] == 4).all()
@@ -81,19 +84,27 @@ def test_band_chain_mixed_at_tol(split_ctx):
     again, st2 = gpu_solve(split_ctx, vis, chain, 1, tol=1e-6, max_iter=50, prec="mixed")
     assert np.array_equal(again[1].gains, got[1].gains)
     assert np.array_equal(st2["chisq_last"], st["chisq_last"])
+    # steps of 8 rows x 8 channels
+    split_ctx.set_tile(0, 8)
+    got8, st8 = gpu_solve(split_ctx, vis, chain, 1, tol=1e-6, max_iter=50, prec="mixed")
+    assert np.abs(st8["iters"].astype(int) - rst["iters"].astype(int)).max() <= 2
+    e8 = rel_err(got8[1].gains, ref[1].gains, "diag")
+    say(f"  8 rows per step: largest relative difference {e8:.2e}")
+    assert e8 <= 1e-4
 
 
+@pytest.mark.parametrize("rows", [4, 8])
 @pytest.mark.parametrize("parts", [3, 7])
-def test_band_single_term_irregular_rows(split_ctx, parts):
+def test_band_single_term_irregular_rows(split_ctx, parts, rows):
     """One diagonal term, one model direction: autocorrelation rows, baselines
     shuffled within each time, and one baseline of every time given twice in
     neighbouring rows."""
-    say(f"band single term, irregular rows, parts={parts}")
+    say(f"band single term, irregular rows, parts={parts} rows per step={rows}")
     rng = np.random.default_rng(317)
     n_ant, n_time, n_chan = 6, 8, 19
     vis = make_vis(rng, n_ant=n_ant, n_time=n_time, n_chan=n_chan, n_dir=1)
     # add autocorrelations and a repeated baseline per time, then shuffle within each time
-    rows = []
+    row_list = []
     for t in range(n_time):
         idx = np.flatnonzero(vis.row_time == t)
         extra_auto = [(a, a) for a in range(0, n_ant, 2)]
@@ -103,11 +114,11 @@ def test_band_single_term_irregular_rows(split_ctx, parts):
         rng.shuffle(pairs)
         k = pairs.index(rep)
         pairs.insert(k + 1, rep)
-        rows += [(t, p, q) for p, q in pairs]
-    n_row = len(rows)
-    vis.row_time = np.array([r[0] for r in rows], np.int32)
-    vis.ant1 = np.array([r[1] for r in rows], np.int32)
-    vis.ant2 = np.array([r[2] for r in rows], np.int32)
+        row_list += [(t, p, q) for p, q in pairs]
+    n_row = len(row_list)
+    vis.row_time = np.array([r[0] for r in row_list], np.int32)
+    vis.ant1 = np.array([r[1] for r in row_list], np.int32)
+    vis.ant2 = np.array([r[2] for r in row_list], np.int32)
     vis.model = rand_c(rng, n_row, n_chan, 1, 4)
     vis.weight = rng.uniform(0.5, 2.0, (n_row, n_chan, 4))
     vis.data = np.zeros((n_row, n_chan, 4), np.complex128)
@@ -117,6 +128,7 @@ def test_band_single_term_irregular_rows(split_ctx, parts):
     chain = [unit_like(truth[0])]
     ref, rst = o_solver.solve_term(vis, chain, 0, tol=-1.0, max_iter=3)
     split_ctx.set_split(parts)
+    split_ctx.set_tile(0, rows)
     got, st = gpu_solve(split_ctx, vis, chain, 0, tol=-1.0, max_iter=3, prec="fp64")
     assert split_ctx.last_split_parts() == parts
     np.testing.assert_array_equal(got[0].gain_flags, ref[0].gain_flags)
