@@ -255,10 +255,13 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// dy = 2 (y - t) / n; loss = sum (y - t)^2 / n (one workgroup, fixed order)
-__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t,
-                                             float* __restrict__ dy, float* __restrict__ loss, int n) {
-  __shared__ double red[256];
+// dy = 2 (y - t) / n; loss = sum (y - t)^2 / n (one workgroup of 1024
+// threads, fixed order: 4x the 256 it had, the kernel measured at 75 us for a
+// 256 x 256 batch being the longest step of training)
+constexpr int MSE_THREADS = 1024;
+__global__ void __launch_bounds__(MSE_THREADS) k_mse(const float* __restrict__ y, const float* __restrict__ t,
+                                                     float* __restrict__ dy, float* __restrict__ loss, int n) {
+  __shared__ double red[MSE_THREADS];
   double s = 0.0;
   const float inv = 1.f / (float)n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const 
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = MSE_THREADS / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
@@ -364,7 +367,7 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, floa
 }
 
 hipError_t launch_mse(const float* y, const float* t, float* dy, float* loss, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, s, y, t, dy, loss, n);
+  hipLaunchKernelGGL(k_mse, dim3(1), dim3(MSE_THREADS), 0, s, y, t, dy, loss, n);
   return hipGetLastError();
 }
 
