@@ -1,8 +1,9 @@
 """Build libqc.so (HIP, gfx950) in-tree with hipcc.
 
 Every .hip source under csrc/ is compiled to an object with hipcc for gfx950
-(packed FP32 instructions disabled) and linked into one shared library next to
-this file.  Run as ``python -m paper_2412_10072_amd.build``.
+(packed FP32 instructions disabled), every .cpp source (host-only code) with
+the host C++ compiler, and all are linked into one shared library next to this
+file.  Run as ``python -m paper_2412_10072_amd.build``.
 """
 from __future__ import annotations
 
@@ -19,6 +20,7 @@ LIB = os.path.join(HERE, "libqc.so")
 ARCH = os.environ.get("QC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+CXX = shutil.which("g++") or "c++"
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -27,15 +29,18 @@ COMMON = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [CXX, "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")
+        raise RuntimeError(f"compile failed for {src}:\n{res.stdout}\n{res.stderr}")
     return obj
 
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "qc_host.h"
+#include "qc_hostcheck.h"
 
 using namespace qc;
 
@@ -64,43 +65,20 @@ __global__ void k_ranges(const long long* rowpos, const int* tt, int n_gt, long 
 // ---------------------------------------------------------------------------
 
 qc_status check_vis(qc_ctx* ctx, const qc_vis* v, bool need_model) {
-  if (!v) return fail(ctx, QC_E_ARG, "vis is NULL");
-  if (v->n_row < 0 || v->n_chan <= 0 || v->n_dir <= 0 || v->n_ant <= 0 || v->n_time <= 0)
-    return fail(ctx, QC_E_ARG, "bad sizes: n_row=%lld n_chan=%d n_dir=%d n_ant=%d n_time=%d",
-                (long long)v->n_row, v->n_chan, v->n_dir, v->n_ant, v->n_time);
-  if (v->n_dir > QC_MAX_DIR) return fail(ctx, QC_E_UNSUPPORTED, "n_dir=%d exceeds %d", v->n_dir, QC_MAX_DIR);
-  if (v->n_ant > QC_MAX_ANT) return fail(ctx, QC_E_UNSUPPORTED, "n_ant=%d exceeds %d", v->n_ant, QC_MAX_ANT);
-  if (v->n_wcorr != 1 && v->n_wcorr != 4) return fail(ctx, QC_E_ARG, "n_wcorr must be 1 or 4, got %d", v->n_wcorr);
-  if (v->dtype != QC_C64 && v->dtype != QC_C128) return fail(ctx, QC_E_ARG, "bad dtype %d", (int)v->dtype);
-  if (v->n_row > 0 && (!v->data || (need_model && !v->model) || !v->weight || !v->flag || !v->ant1 || !v->ant2 ||
-                       !v->row_time))
-    return fail(ctx, QC_E_ARG, "a visibility array pointer is NULL");
-  if (!v->chan_freq) return fail(ctx, QC_E_ARG, "chan_freq is NULL");
-  return QC_OK;
+  const Check c = check_vis_fields(v, need_model);
+  return c.st == QC_OK ? QC_OK : fail(ctx, c.st, "%s", c.msg.c_str());
 }
 
 qc_status check_term(qc_ctx* ctx, const qc_vis* v, const qc_term* t, int j, HostMaps& hm, hipStream_t s) {
-  if (t->type < QC_TERM_DIAGONAL || t->type > QC_TERM_POINTING)
-    return fail(ctx, QC_E_ARG, "term %d: bad type %d", j, (int)t->type);
+  Check c = check_term_fields(t, j);
+  if (c.st != QC_OK) return fail(ctx, c.st, "%s", c.msg.c_str());
   if (t->type == QC_TERM_POINTING) {
-    if (t->n_gdir != 1) return fail(ctx, QC_E_ARG, "term %d: a pointing term has n_gdir = 1", j);
-    if (!t->dir_lm) return fail(ctx, QC_E_ARG, "term %d: dir_lm is NULL", j);
-    if (!(std::isfinite(t->beam_fwhm) && t->beam_fwhm > 0.0 && std::isfinite(t->beam_freq) && t->beam_freq > 0.0))
-      return fail(ctx, QC_E_ARG, "term %d: beam_fwhm and beam_freq must be positive", j);
     std::vector<double> lm(2 * (size_t)v->n_dir);
     HIP_TRY(ctx, hipMemcpyAsync(lm.data(), t->dir_lm, sizeof(double) * lm.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    for (double x : lm)
-      if (!std::isfinite(x)) return fail(ctx, QC_E_ARG, "term %d: non-finite dir_lm", j);
+    c = check_dir_lm(lm.data(), v->n_dir, j);
+    if (c.st != QC_OK) return fail(ctx, c.st, "%s", c.msg.c_str());
   }
-  if (t->n_gt <= 0 || t->n_gf <= 0 || t->n_gdir <= 0)
-    return fail(ctx, QC_E_ARG, "term %d: bad gain shape (%d, %d, %d)", j, t->n_gt, t->n_gf, t->n_gdir);
-  if (t->n_gdir > QC_MAX_GDIR)
-    return fail(ctx, QC_E_UNSUPPORTED, "term %d: n_gdir=%d exceeds %d", j, t->n_gdir, QC_MAX_GDIR);
-  if (!t->t_map || !t->f_map || !t->d_map) return fail(ctx, QC_E_ARG, "term %d: a map pointer is NULL", j);
-  const bool real_params = t->type >= QC_TERM_DELAY;   // delay, phase, amplitude, delay and offset
-  if (real_params ? !t->params : !t->gains)
-    return fail(ctx, QC_E_ARG, "term %d: %s is NULL", j, real_params ? "params" : "gains");
   hm.t_map.resize(v->n_time);
   hm.f_map.resize(v->n_chan);
   hm.d_map.resize(v->n_dir);
@@ -108,22 +86,8 @@ qc_status check_term(qc_ctx* ctx, const qc_vis* v, const qc_term* t, int j, Host
   HIP_TRY(ctx, hipMemcpyAsync(hm.f_map.data(), t->f_map, sizeof(int) * v->n_chan, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipMemcpyAsync(hm.d_map.data(), t->d_map, sizeof(int) * v->n_dir, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  for (int i = 0; i < v->n_time; ++i) {
-    if (hm.t_map[i] < 0 || hm.t_map[i] >= t->n_gt)
-      return fail(ctx, QC_E_RANGE, "term %d: t_map[%d]=%d outside [0,%d)", j, i, hm.t_map[i], t->n_gt);
-    if (i > 0 && hm.t_map[i] < hm.t_map[i - 1])
-      return fail(ctx, QC_E_ARG, "term %d: t_map is not non-decreasing at %d", j, i);
-  }
-  for (int i = 0; i < v->n_chan; ++i) {
-    if (hm.f_map[i] < 0 || hm.f_map[i] >= t->n_gf)
-      return fail(ctx, QC_E_RANGE, "term %d: f_map[%d]=%d outside [0,%d)", j, i, hm.f_map[i], t->n_gf);
-    if (i > 0 && hm.f_map[i] < hm.f_map[i - 1])
-      return fail(ctx, QC_E_ARG, "term %d: f_map is not non-decreasing at %d", j, i);
-  }
-  for (int i = 0; i < v->n_dir; ++i)
-    if (hm.d_map[i] < 0 || hm.d_map[i] >= t->n_gdir)
-      return fail(ctx, QC_E_RANGE, "term %d: d_map[%d]=%d outside [0,%d)", j, i, hm.d_map[i], t->n_gdir);
-  return QC_OK;
+  c = check_term_maps(t, j, hm.t_map.data(), v->n_time, hm.f_map.data(), v->n_chan, hm.d_map.data(), v->n_dir);
+  return c.st == QC_OK ? QC_OK : fail(ctx, c.st, "%s", c.msg.c_str());
 }
 
 bool dmap_constant(const HostMaps& hm) {
@@ -235,21 +199,8 @@ qc_status prepare(qc_ctx* ctx, const qc_vis* v, const qc_term* chain, int n_term
   if (active >= 0) {
     const qc_term& ta = chain[active];
     const HostMaps& hm = maps[active];
-    std::vector<int> tt(2 * (size_t)ta.n_gt, 0), clo(ta.n_gf, 0), chi(ta.n_gf, 0);
-    ctx->max_int_chan = 0;
-    for (int g = 0; g < ta.n_gt; ++g) {
-      auto lo = std::lower_bound(hm.t_map.begin(), hm.t_map.end(), g);
-      auto hi = std::upper_bound(hm.t_map.begin(), hm.t_map.end(), g);
-      tt[g] = (int)(lo - hm.t_map.begin());
-      tt[ta.n_gt + g] = (int)(hi - hm.t_map.begin());
-    }
-    for (int g = 0; g < ta.n_gf; ++g) {
-      auto lo = std::lower_bound(hm.f_map.begin(), hm.f_map.end(), g);
-      auto hi = std::upper_bound(hm.f_map.begin(), hm.f_map.end(), g);
-      clo[g] = (int)(lo - hm.f_map.begin());
-      chi[g] = (int)(hi - hm.f_map.begin());
-      ctx->max_int_chan = std::max(ctx->max_int_chan, chi[g] - clo[g]);
-    }
+    std::vector<int> tt, clo, chi;
+    ctx->max_int_chan = interval_extents(hm.t_map, hm.f_map, ta.n_gt, ta.n_gf, tt, clo, chi);
     if (!fixed) {
       HIP_TRY(ctx, grow(ctx->d_rowlo, ctx->rowlo_cap, (size_t)ta.n_gt));
       HIP_TRY(ctx, grow(ctx->d_rowhi, ctx->rowhi_cap, (size_t)ta.n_gt));
@@ -447,28 +398,27 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
   if (!opts) return fail(ctx, QC_E_ARG, "opts is NULL");
   if (!chain || n_term <= 0 || active < 0 || active >= n_term)
     return fail(ctx, QC_E_ARG, "active=%d outside the chain of %d terms", active, n_term);
-  if (opts->prec != QC_PREC_FP64 && opts->prec != QC_PREC_MIXED)
-    return fail(ctx, QC_E_ARG, "bad precision %d", (int)opts->prec);
-  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_LM)
-    return fail(ctx, QC_E_ARG, "bad damping %d", (int)opts->damping);
+  const int prec_v = enum_value(opts->prec), damp_v = enum_value(opts->damping);
+  if (prec_v != QC_PREC_FP64 && prec_v != QC_PREC_MIXED) return fail(ctx, QC_E_ARG, "bad precision %d", prec_v);
+  if (damp_v < QC_DAMP_FULL || damp_v > QC_DAMP_LM) return fail(ctx, QC_E_ARG, "bad damping %d", damp_v);
   if (opts->max_iter < 0) return fail(ctx, QC_E_ARG, "max_iter < 0");
-  if (vis && opts->prec == QC_PREC_MIXED && vis->dtype != QC_C64)
+  if (vis && prec_v == QC_PREC_MIXED && enum_value(vis->dtype) != QC_C64)
     return fail(ctx, QC_E_ARG, "MIXED precision needs complex64 data");
   hipStream_t s = reinterpret_cast<hipStream_t>(opts->stream);
   ctx->last_stream = s;
-  if (fixed && chain[active].type == QC_TERM_POINTING)
+  if (fixed && enum_value(chain[active].type) == QC_TERM_POINTING)
     return fail(ctx, QC_E_UNSUPPORTED, "the allocation-free solve takes no active POINTING term");
   if (sky) {
     if (!uvw && vis && vis->n_row > 0) return fail(ctx, QC_E_ARG, "uvw is NULL");
     bool diag = true;
     for (int j = 0; j < n_term; ++j)
-      if (chain[j].type == QC_TERM_COMPLEX2X2) diag = false;
+      if (enum_value(chain[j].type) == QC_TERM_COMPLEX2X2) diag = false;
     const bool single = vis && n_term == 1 && vis->n_dir == 1 && chain[active].n_gdir == 1;
     if (!single && !diag)
       return fail(ctx, QC_E_UNSUPPORTED, "the predicted model takes a single term or a chain of diagonal terms");
-    if (chain[active].type == QC_TERM_POINTING)
+    if (enum_value(chain[active].type) == QC_TERM_POINTING)
       return fail(ctx, QC_E_UNSUPPORTED, "the predicted model takes no active POINTING term");
-    if (opts->damping == QC_DAMP_LM)
+    if (damp_v == QC_DAMP_LM)
       return fail(ctx, QC_E_UNSUPPORTED, "the predicted model takes no Levenberg-Marquardt damping");
   }
   std::vector<HostMaps> maps;
@@ -951,7 +901,8 @@ static qc_status outputs_common(qc_ctx* ctx, const qc_vis* vis, const qc_term* c
 
 qc_status qc_apply_gains(qc_ctx* ctx, const qc_vis* vis, const qc_term* chain, int32_t n_term,
                          qc_apply_mode mode, const uint8_t* dir_mask, void* out, void* stream) {
-  if (mode != QC_CORRUPT && mode != QC_CORRECT) return fail(ctx, QC_E_ARG, "bad apply mode %d", (int)mode);
+  const int mode_v = enum_value(mode);
+  if (mode_v != QC_CORRUPT && mode_v != QC_CORRECT) return fail(ctx, QC_E_ARG, "bad apply mode %d", mode_v);
   return outputs_common(ctx, vis, chain, n_term, mode == QC_CORRECT ? 1 : 0, dir_mask, out, stream);
 }
 

@@ -7,6 +7,7 @@
 
 #include "qc_batch.h"
 #include "qc_host.h"
+#include "qc_hostcheck.h"
 
 using namespace qc;
 
@@ -145,10 +146,9 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
   *out = nullptr;
   if (!problems || n_problem <= 0) return fail(ctx, QC_E_ARG, "no problems");
   if (!opts) return fail(ctx, QC_E_ARG, "opts is NULL");
-  if (opts->prec != QC_PREC_FP64 && opts->prec != QC_PREC_MIXED)
-    return fail(ctx, QC_E_ARG, "bad precision %d", (int)opts->prec);
-  if (opts->damping < QC_DAMP_FULL || opts->damping > QC_DAMP_LM)
-    return fail(ctx, QC_E_ARG, "bad damping %d", (int)opts->damping);
+  const int prec_v = enum_value(opts->prec), damp_v = enum_value(opts->damping);
+  if (prec_v != QC_PREC_FP64 && prec_v != QC_PREC_MIXED) return fail(ctx, QC_E_ARG, "bad precision %d", prec_v);
+  if (damp_v < QC_DAMP_FULL || damp_v > QC_DAMP_LM) return fail(ctx, QC_E_ARG, "bad damping %d", damp_v);
   if (opts->max_iter < 0) return fail(ctx, QC_E_ARG, "max_iter < 0");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(opts->stream);
@@ -157,7 +157,7 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
   b->n_prob = n_problem;
   b->prec_mixed = opts->prec == QC_PREC_MIXED;
   b->lm = opts->damping == QC_DAMP_LM;
-  b->vis_c128 = problems[0].vis.dtype == QC_C128;
+  b->vis_c128 = enum_value(problems[0].vis.dtype) == QC_C128;
   b->tol = opts->tol;
   b->max_iter = opts->max_iter;
   b->problems.assign(problems, problems + n_problem);
@@ -169,11 +169,11 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
   };
   for (int i = 0; i < n_problem; ++i) {
     const qc_problem& P = problems[i];
-    if ((P.vis.dtype == QC_C128) != (b->vis_c128 != 0))
+    if ((enum_value(P.vis.dtype) == QC_C128) != (b->vis_c128 != 0))
       return bail(fail(ctx, QC_E_ARG, "problem %d: every problem must have the same data dtype", i));
-    if (b->prec_mixed && P.vis.dtype != QC_C64)
+    if (b->prec_mixed && enum_value(P.vis.dtype) != QC_C64)
       return bail(fail(ctx, QC_E_ARG, "MIXED precision needs complex64 data"));
-    if (P.term.type != QC_TERM_DIAGONAL && P.term.type != QC_TERM_COMPLEX2X2)
+    if (enum_value(P.term.type) != QC_TERM_DIAGONAL && enum_value(P.term.type) != QC_TERM_COMPLEX2X2)
       return bail(fail(ctx, QC_E_UNSUPPORTED, "problem %d: batched terms must be DIAGONAL or COMPLEX2X2", i));
     if (P.vis.n_dir != 1 || P.term.n_gdir != 1)
       return bail(fail(ctx, QC_E_UNSUPPORTED, "problem %d: batched problems have one direction", i));

@@ -24,6 +24,7 @@
 #include <cstring>
 
 #include "qc_host.h"
+#include "qc_hostcheck.h"
 
 namespace qc {
 namespace {
@@ -565,7 +566,8 @@ extern "C" {
 qc_status qc_mad_flag(qc_ctx* ctx, const qc_vis* vis, const void* resid, qc_mad_mode mode, double k,
                       uint8_t* flag_out, double* stats, int64_t* n_flagged, void* stream) {
   if (!ctx) return QC_E_ARG;
-  if (mode != QC_MAD_GLOBAL && mode != QC_MAD_BASELINE) return fail(ctx, QC_E_ARG, "bad MAD mode %d", (int)mode);
+  const int mode_v = enum_value(mode);
+  if (mode_v != QC_MAD_GLOBAL && mode_v != QC_MAD_BASELINE) return fail(ctx, QC_E_ARG, "bad MAD mode %d", mode_v);
   if (!(k >= 0.0) || !std::isfinite(k)) return fail(ctx, QC_E_ARG, "k must be finite and >= 0");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   ctx->last_stream = s;
