@@ -472,6 +472,9 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
   L.err = ctx->d_err;
   L.waves = ctx->waves;
   L.max_int_chan = ctx->max_int_chan;
+  L.dir_ident = ta.n_gdir > 1 && ta.n_gdir == vis->n_dir && ta.n_gdir <= 4;
+  for (int d = 0; L.dir_ident && d < vis->n_dir; ++d)
+    if (maps[active].d_map[d] != d) L.dir_ident = 0;
   L.rows_per_step = ctx->rows_per_step == 8 ? 0 : ctx->rows_per_step;   // 8: the one-channel split only
   // schedule: fused (one workgroup per interval) unless the term has too few
   // intervals to give every CU several workgroups and they are large enough

@@ -22,8 +22,10 @@ enum { KIND_DIAG = 0, KIND_C2X2 = 1, KIND_DELAY = 2, KIND_PHASE = 3, KIND_AMP = 
 // diagonal term (delay, phase-only, amplitude-only); the term's own kind
 // (TermArgs::kind) selects the Jones form at run time.
 // per-sample chain evaluation of the solver kernels (CHAIN_LEFT: any chain,
-// with the full per-antenna blocks that a general left factor needs)
-enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2, CHAIN_LEFT = 3 };
+// with the full per-antenna blocks that a general left factor needs;
+// CHAIN_DIAG_ID: a diagonal chain whose active term has gain direction d for
+// model direction d)
+enum { CHAIN_GENERAL = 0, CHAIN_SINGLE = 1, CHAIN_DIAG = 2, CHAIN_LEFT = 3, CHAIN_DIAG_ID = 4 };
 
 struct TermArgs {
   int kind, n_gt, n_gf, n_gdir;   // pointing terms: n_gdir = the model directions (they differ by direction)
@@ -399,6 +401,10 @@ struct SolveLaunch {
   const void* otab;
   // intervals of one channel each, the split schedule's pass over 16 channels
   // per wavefront (qc_band.h) with these steps [n_row]; else null
+  // diagonal chains with several gain directions: model direction d has
+  // gain direction d of the active term (n_gdir = n_dir <= 4): the kernels of
+  // the CHAIN_DIAG_ID mode
+  int dir_ident;
   const BandStep* band_steps;
   int band_rows;              // rows per step of that pass: 4 or 8
   // that pass: the direction-dependent fixed terms (diagonal gains), each as a

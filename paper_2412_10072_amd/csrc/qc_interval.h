@@ -1144,7 +1144,8 @@ template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
-  constexpr bool DIAGC = (CHM == CHAIN_DIAG);
+  constexpr bool DIAGC = (CHM == CHAIN_DIAG || CHM == CHAIN_DIAG_ID);
+  constexpr bool DIR_ID = (CHM == CHAIN_DIAG_ID);   // model direction d has gain direction d
   constexpr bool FB = (CHM == CHAIN_LEFT);   // full blocks (any left factor)
   static_assert(!DIAGC || KIND != KIND_C2X2, "a diagonal chain has no full-Jones term");
   static_assert(!FB || RPS == 1, "the full-block kernel takes one row per wavefront step");
@@ -1542,6 +1543,67 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           }
           cx<T> hp0, hp1, hq0, hq1;
           m22<T> Vm = mzero<T>();
+          if constexpr (DIR_ID) {
+            // Model direction d has gain direction d (n_dir = n_gdir <= NG):
+            // the directions are unrolled, and the per-direction factors are
+            // formed twice -- once for the model, once for the blocks after
+            // the residual -- rather than kept for all directions (which
+            // would hold 2 x NG matrices in registers).  With e = o times the
+            // direction-dependent fixed factors,
+            //   E_ij = e_{p,d,i} M_d,ij conj(e_{q,d,j}),
+            //   B_ij = E_ij conj(h_{q,j}), Bc_ij = conj(E_ji h_{p,j}).
+            m22<T> Mc[NG];
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+              for (int g = 0; g < NG; ++g) Mc[g] = model_at(min(g, n_dir - 1));
+            }
+            auto factors = [&](int g, m22<T>& E) {
+              active_diag(g, hp0, hp1, hq0, hq1);
+              cx<T> rp0 = op0, rp1 = op1, rq0 = oq0, rq1 = oq1;
+              dd_factor(p, q, g, rp0, rp1, rq0, rq1);
+              m22<T> Mg;
+              if constexpr (sizeof(T) == 4) Mg = Mc[g];
+              else Mg = model_at(g);
+              const m22<T> M = select_m(use, Mg);
+              E.a = mulc(rp0, rq0) * M.a;
+              E.b = mulc(rp0, rq1) * M.b;
+              E.c = mulc(rp1, rq0) * M.c;
+              E.d = mulc(rp1, rq1) * M.d;
+            };
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+              if (g < n_dir) {
+                m22<T> E;
+                factors(g, E);
+                Vm.a = cfma(hp0, mulc(E.a, hq0), Vm.a);
+                Vm.b = cfma(hp0, mulc(E.b, hq1), Vm.b);
+                Vm.c = cfma(hp1, mulc(E.c, hq0), Vm.c);
+                Vm.d = cfma(hp1, mulc(E.d, hq1), Vm.d);
+              }
+            }
+            const m22<T> R = D - Vm;
+            const m22<T> WR = wmul(R, w0, w1, w2, w3);
+            const m22<T> WRc = herm(WR);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+              if (g < n_dir) {
+                m22<T> E, B, Bc;
+                factors(g, E);
+                B.a = mulc(E.a, hq0);
+                B.b = mulc(E.b, hq1);
+                B.c = mulc(E.c, hq0);
+                B.d = mulc(E.d, hq1);
+                Bc.a = conj(E.a * hp0);
+                Bc.b = conj(E.c * hp1);
+                Bc.c = conj(E.b * hp0);
+                Bc.d = conj(E.d * hp1);
+                contrib<KIND, true, T>(ap0, ap1, B, WR, w0, w1, w2, w3, hp0, hp1, tpn,
+                                       (PACC ? pacc : prow) + g * NV, pk_amp);
+                contrib<KIND, true, T>(aq0, aq1, Bc, WRc, w0, w2, w1, w3, hq0, hq1, tpn, qacc + g * NV, pk_amp);
+              }
+            }
+            chi = chisq_acc(WR, R, chi);
+          } else {
           for (int d0 = 0; d0 < n_dir; d0 += MCH) {
             m22<T> Mc[MCH];
 #pragma unroll
@@ -1595,6 +1657,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
                                     pk_amp);
           }
           chi = chisq_acc(WR, R, chi);
+          }
           }
         } else if constexpr (FB) {
           // Any chain, with the full blocks a general left factor needs: a

@@ -104,7 +104,7 @@ __device__ __forceinline__ unsigned xcd_order(unsigned bid, unsigned n) {
 // at once; held to three wavefronts per SIMD it fits without spilling.
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool SKY = false>
 __global__ void __launch_bounds__((wide_state<CHM, T>() ? 256 : 512))
-__attribute__((amdgpu_waves_per_eu(KIND == KIND_DIAG && CHM == 2 && RPS == 64 && sizeof(T) == 4 ? 3 : 1)))
+__attribute__((amdgpu_waves_per_eu(KIND == KIND_DIAG && CHM == CHAIN_DIAG && RPS == 64 && sizeof(T) == 4 ? 3 : 1)))
 k_split_pass(SolveLaunch L, int n_part, double* partials, const uint8_t* done) {
   const TermArgs& TA = L.chain.t[L.chain.active];
   const int n_gf = TA.n_gf;
@@ -406,6 +406,7 @@ hipError_t launch_kind(const SolveLaunch& L, const SplitLaunch* P, hipStream_t s
         if (L.max_int_chan <= 4) { QC_LAUNCH(CHAIN_DIAG, 1, 64); }
         QC_LAUNCH(CHAIN_DIAG, 1, 1);
       }
+      if (L.dir_ident) { QC_LAUNCH(CHAIN_DIAG_ID, 4, 1); }
       QC_LAUNCH(CHAIN_DIAG, 4, 1);
     }
   }
