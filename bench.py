@@ -87,12 +87,75 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sources the main line's solve kernel is built from: the traffic record holds
+# their hash, and a change to any of them retires the record.
+TRAFFIC_SOURCES = [
+    "include/qc.h",
+    "paper_2412_10072_amd/csrc/qc_internal.h",
+    "paper_2412_10072_amd/csrc/qc_interval.h",
+    "paper_2412_10072_amd/csrc/qc_band.h",
+    "paper_2412_10072_amd/csrc/qc_solve_kernels.h",
+    "paper_2412_10072_amd/csrc/qc_solve_kc2x2_mixed.hip",
+]
+TRAFFIC_RECORD = os.path.join("profiles", "k_solve_fused_meerkat_fulljones_traffic.json")
+
+
+def write_traffic_record(fetch_dir: str, write_dir: str, algorithmic_bytes: float):
+    """The traffic record from two rocprofv3 --pmc runs of `bench.py --legs none --steps 1 --warmup 0
+    --no-cpu-baseline --calib-copy` (FETCH_SIZE in fetch_dir, WRITE_SIZE in write_dir, csv output):
+    the main line's solve dispatch, scaled by what the same counters read for the 4 GiB
+    calibration copy (its largest copy dispatch)."""
+    import csv
+    import glob
+    import hashlib
+
+    def per_dispatch(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (r["Kernel_Name"], r["Dispatch_Id"])
+                vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+        return vals
+
+    def pick(vals, pattern):
+        hits = [v for (k, _), v in vals.items() if pattern in k]
+        return hits
+
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = per_dispatch(write_dir, "WRITE_SIZE")
+    kern = "k_solve_fused<1, float, float, 1, 1, 4, false, false>"
+    f_solve, w_solve = pick(fetch, kern), pick(write, kern)
+    f_copy, w_copy = max(pick(fetch, "copyBuffer")), max(pick(write, "copyBuffer"))
+    if len(f_solve) != 1 or len(w_solve) != 1:
+        raise SystemExit(f"expected one solve dispatch per run, found {len(f_solve)} and {len(w_solve)}")
+    copy_bytes = 1 << 32
+    fetch_scale = copy_bytes / (f_copy * 1024.0)
+    write_scale = copy_bytes / (w_copy * 1024.0)
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    fb = f_solve[0] * 1024.0 * fetch_scale
+    wb = w_solve[0] * 1024.0 * write_scale
+    rec = {"kernel": kern, "workload": "MeerKAT-shaped full-Jones solve, 64 ants, 600 x 1024, tol 1e-6",
+           "sources": TRAFFIC_SOURCES, "sources_sha256": h.hexdigest(),
+           "fetch_size_kib": f_solve[0], "write_size_kib": w_solve[0], "calib_copy_bytes": copy_bytes,
+           "calib_fetch_kib": f_copy, "calib_write_kib": w_copy, "fetch_scale": fetch_scale,
+           "write_scale": write_scale, "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb,
+           "algorithmic_bytes": algorithmic_bytes}
+    with open(os.path.join(ROOT, TRAFFIC_RECORD), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"traffic record: {fb / 1e9:.1f} GB fetched + {wb / 1e9:.3f} GB written = "
+          f"{(fb + wb) / algorithmic_bytes:.3f} x the algorithmic bytes")
+
+
 def measured_traffic():
     """HBM bytes per launch of the solve kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (calibrated on a copy of known size), or None
     when the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_solve_fused_meerkat_fulljones_traffic.json")
+    path = os.path.join(ROOT, TRAFFIC_RECORD)
     try:
         rec = json.load(open(path))
         h = hashlib.sha256()
@@ -1101,7 +1164,12 @@ def main():
                          "params, pointing (or none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 4 GiB device buffer once (a kernel of known traffic for HBM counters)")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "ALG_BYTES"),
+                    help="write the solve kernel's traffic record from two rocprofv3 csv runs and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(args.traffic_record[0], args.traffic_record[1], float(args.traffic_record[2]))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver shards by solution intervals with no communication, "
               "and this implementation runs on a single MI355X; --gpus above 1 is not supported.", file=sys.stderr)
