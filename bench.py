@@ -592,15 +592,16 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
     solved four ways, each timed on the wall clock from the first launch to the last result:
     plain (one qc_solve_interval per problem from unit gains), batched (one graph launch from
     unit gains), learned (per problem: feature pass, MLP, gain write, solve with the unit-gain
-    fallback) and learned + batched (the warm starts of every problem, then one graph launch
-    with per-problem fallback references)."""
+    fallback) and learned + batched (the batch's feature pass over every interval, the MLP
+    over all of them, the batch's gain write, then one graph launch with per-problem fallback
+    references)."""
     import numpy as np
     import torch
     from paper_2412_10072_amd import qc, warmstart
     from synth.generate import config_meerkat
 
     g = np.random.default_rng(np.random.SeedSequence([2412, 51]))
-    probs = []
+    made = []
     t0 = time.perf_counter()
     for i in range(n_problems):
         n_time = int(g.integers(8, 41))
@@ -608,9 +609,15 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
         drop = float(g.uniform(0.0, 0.3))
         p = config_meerkat(device=dev, n_time=n_time, n_chan=n_chan, f_int=64, kind="diag", gain_mode="random",
                            cfg_id=51, seed_block=i, row_drop=drop)
-        t = qc.device_term(p.chain[0], dev)
-        ref = torch.empty(int(t.n_gt) * int(t.n_gf), dtype=torch.float64, device=dev)
-        probs.append((p.vis, t, ref, t.gains.clone()))
+        made.append((p.vis, qc.device_term(p.chain[0], dev)))
+    # chi^2 at unit gains of every interval in one array, problem after problem
+    # (the batch's row order), each problem's fallback reference a slice of it
+    ref_all = torch.empty(sum(int(t.n_gt) * int(t.n_gf) for _, t in made), dtype=torch.float64, device=dev)
+    probs, o = [], 0
+    for v, t in made:
+        n_i = int(t.n_gt) * int(t.n_gf)
+        probs.append((v, t, ref_all[o:o + n_i], t.gains.clone()))
+        o += n_i
     torch.cuda.synchronize()
     n_samples = int(sum(int(v.data.shape[0]) * int(v.data.shape[1]) for v, _, _, _ in probs))
     n_int = int(sum(int(t.n_gt) * int(t.n_gf) for _, t, _, _ in probs))
@@ -641,8 +648,7 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
                 stats.append(ctx.solve(v, [t], 0, tol=1e-6, max_iter=100, prec="mixed", stream=stream,
                                        chisq_ref=r.reshape(int(t.n_gt), int(t.n_gf))))
         else:
-            for v, t, r, _ in probs:
-                net.init_gains(v, t, stream=stream, chisq_out=r)
+            net.init_gains_batch(b_warm, ref_all, stream=stream)
             b_warm.run(stream)
             stats = b_warm.stats
         return stats

@@ -543,6 +543,28 @@ double    qc_batch_last_ms(qc_batch* batch);
 qc_status qc_batch_schedule(const qc_batch* batch, int32_t* items, int32_t* waves, int32_t* rows_per_step,
                             float* tuned_ms, int32_t n);
 qc_status qc_batch_destroy(qc_batch* batch);
+/* Learned warm start over a batch (the growth direction of the warm start;
+ * no paper passage): the feature pass of qc_ws_features and the gain write
+ * of qc_ws_gains for every interval of every problem, one launch each, on the
+ * intervals the batch has already validated (no host wait).  Per-interval
+ * arrays over the whole batch take the problems in order, the intervals of a
+ * problem in its [n_gt][n_gf] order: interval (gt, gf) of problem i is row
+ * n_0 + ... + n_{i-1} + gt * n_gf + gf, n_j = problem j's n_gt * n_gf;
+ * qc_batch_n_intervals gives the total (-1 for a NULL batch).
+ * qc_batch_ws_features: feat [rows][feat_stride] float (feat_stride >= 8 x
+ * the largest antenna count; a problem with fewer antennas fills its first
+ * 8 n_ant values), chisq_unit NULL or [rows] double (chi^2 at unit gains:
+ * pass its row n_0 + ... + n_{i-1} as problem i's qc_problem.chisq_ref at
+ * qc_batch_create for the unit-gain fallback), ref_ant as in qc_ws_features
+ * (QC_E_ARG if outside a problem's antennas).
+ * qc_batch_ws_gains: y [rows][y_stride] float, [antenna][hand][re, im] as
+ * qc_ws_gains (y_stride >= 4 x the largest antenna count), written into every
+ * problem's gains; every term must be DIAGONAL (QC_E_UNSUPPORTED otherwise).
+ * All arrays are device memory; both are asynchronous on `stream`. */
+int32_t   qc_batch_n_intervals(const qc_batch* batch);
+qc_status qc_batch_ws_features(qc_batch* batch, float* feat, int32_t feat_stride, double* chisq_unit,
+                               int32_t ref_ant, void* stream);
+qc_status qc_batch_ws_gains(qc_batch* batch, const float* y, int32_t y_stride, void* stream);
 /* create + run + wait + destroy */
 qc_status qc_solve_batch(qc_ctx* ctx, const qc_problem* problems, int32_t n_problem, const qc_solve_opts* opts);
 

@@ -18,7 +18,7 @@ struct BatchProb {
   const double* chisq_ref;     // warm-start fallback reference per interval, or null
   uint8_t* restarted;          // per interval, or null
   int damping;
-  int pad;
+  int int_base;                // the problem's first row in per-interval arrays over the whole batch
 };
 
 // One work item: one solution interval of one problem.
@@ -39,6 +39,12 @@ struct BatchArgs {
 };
 
 void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps, int lm, int warm);
+// learned warm start over a batch (qc_ws.hip)
+hipError_t launch_batch_features(const BatchProb* probs, const BatchItem* items, int n_items, int max_ant, int vis_c128,
+                                 float* feat, int feat_stride, double* chisq_unit, int ref_ant, hipStream_t s);
+hipError_t launch_batch_ws_gains(const BatchProb* probs, const BatchItem* items, int n_items, int max_ant,
+                                 const float* y, int y_stride, hipStream_t s);
+size_t ws_features_lds(int n_ant, int waves);
 size_t batch_lds_bytes(int prec_mixed, int max_ant, int waves);
 hipError_t launch_batch_bucket(const BatchArgs& B, void* kern, int waves, size_t lds, int grid, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);

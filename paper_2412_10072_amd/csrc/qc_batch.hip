@@ -27,11 +27,17 @@ namespace {
 
 // LM: Levenberg-Marquardt damping for every problem of the batch (kernels of
 // their own, as for the single-problem path).  WARM: some problem carries a
-// warm-start fallback reference; the kernels without it hold 22 fewer VGPRs
-// (three wavefronts per SIMD instead of two).
+// warm-start fallback reference.  Then an interval whose warm start fits
+// worse than unit gains returns from its first pass, and this kernel writes
+// unit gains and solves it again without the reference.  The reference check
+// costs about 22 VGPRs (184 against 162), one wavefront per SIMD; the MIXED
+// kernels are held to three wavefronts per SIMD, spilling 48-60 bytes per
+// lane: measured on the learned + batched solve, 144 ms against 167 ms at two.
 template <typename S, typename T, int RPS, bool LM, bool WARM>
-__global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WARM && !LM && sizeof(T) == 4 ? 3 : 1)))
+k_solve_batch(BatchArgs B) {
   __shared__ int s_next;
+  __shared__ int s_restart;
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(B.queue, 1);
     __syncthreads();
@@ -67,8 +73,32 @@ __global__ void __launch_bounds__(512) k_solve_batch(BatchArgs B) {
     J.partial = nullptr;
     J.otab = nullptr;
     J.sky = nullptr;
-    if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, CHAIN_SINGLE, 1, RPS, false, LM>(J);
-    else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM>(J);
+    J.restart_flag = &s_restart;
+    constexpr int RST = WARM ? 1 : 0;
+    for (int attempt = 0;; ++attempt) {
+      if constexpr (WARM) {
+        if (threadIdx.x == 0) s_restart = 0;
+        __syncthreads();
+      }
+      if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST>(J);
+      else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST>(J);
+      if constexpr (!WARM) break;
+      const bool again = s_restart != 0;        // uniform: set before a barrier in the solve
+      __syncthreads();                          // read by every thread before it is reset
+      if (!again) {
+        if (attempt > 0 && threadIdx.x == 0 && P.restarted)
+          P.restarted[I.gt * P.term.n_gf + I.gf] = 1;
+        break;
+      }
+      // unit gains for this interval, then the solve again without the reference
+      double2* g = P.gains + ((size_t)I.gt * P.term.n_gf + I.gf) * P.vis.n_ant * 4;   // one gain direction
+      for (int i = threadIdx.x; i < P.vis.n_ant * 4; i += blockDim.x) {
+        const int k = i & 3;
+        g[i] = make_double2((k == 0 || k == 3) ? 1.0 : 0.0, 0.0);
+      }
+      __syncthreads();
+      J.chisq_ref = nullptr;
+    }
   }
 }
 

@@ -36,6 +36,8 @@ struct qc_batch {
   int n_prob = 0, n_items = 0;
   int prec_mixed = 0, vis_c128 = 0, max_ant = 1;
   int lm = 0;                             // Levenberg-Marquardt damping for every problem
+  int n_int = 0;                          // intervals over every problem
+  int all_diag = 1;                       // every problem's term is DIAGONAL
   int warm = 0;                           // some problem has a warm-start fallback reference
   double tol = 1e-6;
   int max_iter = 100;
@@ -202,6 +204,9 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
     if (P.chisq_ref) b->warm = 1;
     bp.restarted = P.stats.restarted;
     bp.damping = resolve_damping(opts->damping, P.term);
+    bp.int_base = b->n_int;
+    b->n_int += P.term.n_gt * P.term.n_gf;
+    if (P.term.type != QC_TERM_DIAGONAL) b->all_diag = 0;
     b->probs.push_back(bp);
     b->max_ant = std::max(b->max_ant, P.vis.n_ant);
     for (int gt = 0; gt < P.term.n_gt; ++gt)
@@ -268,6 +273,40 @@ qc_status qc_batch_create(qc_ctx* ctx, const qc_problem* problems, int32_t n_pro
   qc_status st = build_graph(b);
   if (st != QC_OK) return bail(st);
   *out = b;
+  return QC_OK;
+}
+
+int32_t qc_batch_n_intervals(const qc_batch* b) { return b ? b->n_int : -1; }
+
+qc_status qc_batch_ws_features(qc_batch* b, float* feat, int32_t feat_stride, double* chisq_unit, int32_t ref_ant,
+                               void* stream) {
+  if (!b) return QC_E_ARG;
+  qc_ctx* ctx = b->ctx;
+  if (!feat) return fail(ctx, QC_E_ARG, "feat is NULL");
+  if (feat_stride < b->max_ant * 8)
+    return fail(ctx, QC_E_ARG, "feat_stride %d is below 8 x the largest antenna count (%d)", feat_stride, b->max_ant);
+  for (int i = 0; i < b->n_prob; ++i)
+    if (ref_ant >= b->probs[i].vis.n_ant)
+      return fail(ctx, QC_E_ARG, "ref_ant %d outside problem %d's %d antennas", ref_ant, i, b->probs[i].vis.n_ant);
+  if (ws_features_lds(b->max_ant, 4) > 64 * 1024)
+    return fail(ctx, QC_E_UNSUPPORTED, "features of %d antennas exceed the LDS budget", b->max_ant);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, launch_batch_features(b->d_probs, b->d_items, b->n_items, b->max_ant, b->vis_c128, feat, feat_stride,
+                                     chisq_unit, ref_ant, s));
+  return QC_OK;
+}
+
+qc_status qc_batch_ws_gains(qc_batch* b, const float* y, int32_t y_stride, void* stream) {
+  if (!b) return QC_E_ARG;
+  qc_ctx* ctx = b->ctx;
+  if (!y) return fail(ctx, QC_E_ARG, "y is NULL");
+  if (!b->all_diag) return fail(ctx, QC_E_UNSUPPORTED, "warm-start gains need DIAGONAL terms in every problem");
+  if (y_stride < b->max_ant * 4)
+    return fail(ctx, QC_E_ARG, "y_stride %d is below 4 x the largest antenna count (%d)", y_stride, b->max_ant);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ctx->last_stream = s;
+  HIP_TRY(ctx, launch_batch_ws_gains(b->d_probs, b->d_items, b->n_items, b->max_ant, y, y_stride, s));
   return QC_OK;
 }
 

@@ -843,6 +843,7 @@ struct Job {
   double* partial;           // pass-only mode: [slot values + 1] FP64 blocks and chi^2 of these rows
   const void* otab;          // diagonal chains: fixed direction-independent factors, or null
   const SkyArgs* sky;        // the model's components (kernels built to predict it), else unused
+  int* restart_flag;         // RST = 1 kernels: set (LDS) when the warm start is worse than unit gains
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
@@ -1140,7 +1141,7 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
 //         (a direct Fourier sum per direction) instead of read from the
 //         visibility set: single-term and diagonal-chain evaluation.
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false, bool LMT = false,
-          bool SKY = false>
+          bool SKY = false, int RST = 0>
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
@@ -1843,6 +1844,13 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       return;
     }
     if (it == 0 && J.chisq_ref && !restarted && chi_now > J.chisq_ref[interval]) {
+      if constexpr (RST == 1) {
+        // the caller starts the interval again from unit gains: no second
+        // way into the iteration loop, which would keep more of its state live
+        if (threadIdx.x == 0) *J.restart_flag = 1;
+        __syncthreads();
+        return;
+      }
       // the starting gains fit worse than unit gains: start again from those
       restarted = 1;
       for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {

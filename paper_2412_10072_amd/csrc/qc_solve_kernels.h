@@ -81,6 +81,7 @@ __global__ void __launch_bounds__((wide_state<CHM, T>() ? 256 : 512)) k_solve_fu
   J.restarted = L.restarted;
   J.otab = L.otab;
   J.sky = &L.sky;
+  J.restart_flag = nullptr;
   solve_interval<KIND, S, T, CHM, NG, RPS, false, LMT, SKY>(J);
 }
 
@@ -145,6 +146,7 @@ k_split_pass(SolveLaunch L, int n_part, double* partials, const uint8_t* done) {
   J.partial = partials + ((size_t)interval * n_part + part) * stride;
   J.otab = L.otab;
   J.sky = &L.sky;
+  J.restart_flag = nullptr;
   solve_interval<KIND, S, T, CHM, NG, RPS, true, false, SKY>(J);
 }
 
@@ -184,6 +186,7 @@ __global__ void __launch_bounds__(256) k_split_update(SolveLaunch L, int n_part,
   J.partial = nullptr;
   J.otab = nullptr;
   J.sky = nullptr;
+  J.restart_flag = nullptr;
   split_update<KIND, T, NG, FB>(J, partials + (size_t)interval * n_part * stride, n_part, St);
 }
 

@@ -12,6 +12,7 @@
 // chi^2 at unit gains, sum w |D - M|^2, which the solver's fallback compares
 // with chi^2 at the warm start.
 
+#include "qc_batch.h"
 #include "qc_interval.h"
 
 namespace qc {
@@ -23,15 +24,13 @@ constexpr int WS_RPS = 4;
 constexpr int WS_LPR = 64 / WS_RPS;
 constexpr double FEAT_EPS = 1e-12;
 
+// The features of one interval (rows [r_lo, r_hi) x channels [c_lo, c_hi))
+// into feat (n_ant x 8 floats), chi^2 at unit gains into *chisq_out (if not
+// null); one workgroup.
 template <typename S>
-__global__ void __launch_bounds__(256) k_ws_features(FeatLaunch L) {
-  const VisArgs& V = L.vis;
+__device__ void features_interval(const VisArgs& V, long long r_lo, long long r_hi, int c_lo, int c_hi,
+                                  float* feat, double* chisq_out, int ref_ant) {
   const int n_ant = V.n_ant;
-  const int n_gf = L.n_gf;
-  const int interval = blockIdx.x;
-  const int gt = interval / n_gf, gf = interval - gt * n_gf;
-  const long long r_lo = L.row_lo[gt], r_hi = L.row_hi[gt];
-  const int c_lo = L.chan_lo[gf], c_hi = L.chan_hi[gf];
   const int nw = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -140,23 +139,63 @@ __global__ void __launch_bounds__(256) k_ws_features(FeatLaunch L) {
   for (int i = threadIdx.x; i < n_ant * 4; i += blockDim.x) {
     const int a = i >> 2, k = i & 3;
     double2 z = rho[i];
-    if (L.ref_ant >= 0) {
-      const double2 r = rho[L.ref_ant * 4 + k];
+    if (ref_ant >= 0) {
+      const double2 r = rho[ref_ant * 4 + k];
       const double m = sqrt(r.x * r.x + r.y * r.y);
       if (m > 0.0) {
         const double cr = r.x / m, ci = -r.y / m;
         z = make_double2(z.x * cr - z.y * ci, z.x * ci + z.y * cr);
       }
     }
-    float* f = L.feat + (size_t)interval * L.feat_stride + (size_t)a * 8 + 2 * k;
+    float* f = feat + (size_t)a * 8 + 2 * k;
     f[0] = (float)z.x;
     f[1] = (float)z.y;
   }
-  if (threadIdx.x == 0 && L.chisq_unit) {
+  if (threadIdx.x == 0 && chisq_out) {
     double c2 = 0.0;
     for (int w = 0; w < nw; ++w) c2 += chiw[w];
-    L.chisq_unit[interval] = c2;
+    *chisq_out = c2;
   }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_ws_features(FeatLaunch L) {
+  const int n_gf = L.n_gf;
+  const int interval = blockIdx.x;
+  const int gt = interval / n_gf, gf = interval - gt * n_gf;
+  features_interval<S>(L.vis, L.row_lo[gt], L.row_hi[gt], L.chan_lo[gf], L.chan_hi[gf],
+                       L.feat + (size_t)interval * L.feat_stride, L.chisq_unit ? L.chisq_unit + interval : nullptr,
+                       L.ref_ant);
+}
+
+// The same over every interval of a batch (one workgroup per work item); row
+// int_base + gt * n_gf + gf of feat / chisq_unit for interval (gt, gf) of a
+// problem.
+template <typename S>
+__global__ void __launch_bounds__(256) k_batch_features(const BatchProb* probs, const BatchItem* items, float* feat,
+                                                        int feat_stride, double* chisq_unit, int ref_ant) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProb& P = probs[it.prob];
+  const size_t row = (size_t)P.int_base + (size_t)it.gt * P.term.n_gf + it.gf;
+  features_interval<S>(P.vis, it.r_lo, it.r_hi, it.c_lo, it.c_hi, feat + row * feat_stride,
+                       chisq_unit ? chisq_unit + row : nullptr, ref_ant);
+}
+
+// Diagonal gains of every interval of a batch from y (rows as above):
+// grid (work item, antenna blocks of 64).
+__global__ void k_batch_ws_gains(const BatchProb* probs, const BatchItem* items, const float* __restrict__ y,
+                                 int y_stride) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProb& P = probs[it.prob];
+  const int a = blockIdx.y * blockDim.x + threadIdx.x;
+  if (a >= P.vis.n_ant) return;
+  const size_t interval = (size_t)it.gt * P.term.n_gf + it.gf;
+  const float* yy = y + ((size_t)P.int_base + interval) * y_stride + (size_t)a * 4;
+  double2* g = P.gains + (interval * P.vis.n_ant + a) * 4;      // one gain direction
+  g[0] = make_double2(yy[0], yy[1]);
+  g[1] = make_double2(0.0, 0.0);
+  g[2] = make_double2(0.0, 0.0);
+  g[3] = make_double2(yy[2], yy[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,9 +364,35 @@ hipError_t launch_ws_labels(const double2* gains, int n_int, int n_ant, int ref,
   return hipGetLastError();
 }
 
+size_t ws_features_lds(int n_ant, int waves) {
+  return sizeof(double) * 16 + sizeof(float) * (size_t)n_ant * WS_NV * waves * 2 + sizeof(double2) * (size_t)n_ant * 4 +
+         16;
+}
+
+hipError_t launch_batch_features(const BatchProb* probs, const BatchItem* items, int n_items, int max_ant, int vis_c128,
+                                 float* feat, int feat_stride, double* chisq_unit, int ref_ant, hipStream_t s) {
+  constexpr int waves = 4;
+  const size_t lds = ws_features_lds(max_ant, waves);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  if (n_items == 0) return hipSuccess;
+  if (vis_c128)
+    hipLaunchKernelGGL(k_batch_features<double>, dim3(n_items), dim3(64 * waves), lds, s, probs, items, feat,
+                       feat_stride, chisq_unit, ref_ant);
+  else
+    hipLaunchKernelGGL(k_batch_features<float>, dim3(n_items), dim3(64 * waves), lds, s, probs, items, feat,
+                       feat_stride, chisq_unit, ref_ant);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_ws_gains(const BatchProb* probs, const BatchItem* items, int n_items, int max_ant,
+                                 const float* y, int y_stride, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_ws_gains, dim3(n_items, (max_ant + 63) / 64), dim3(64), 0, s, probs, items, y, y_stride);
+  return hipGetLastError();
+}
+
 hipError_t launch_ws_features(const FeatLaunch& L, int waves, hipStream_t stream) {
-  const size_t lds = sizeof(double) * 16 + sizeof(float) * (size_t)L.vis.n_ant * WS_NV * waves * 2 +
-                     sizeof(double2) * (size_t)L.vis.n_ant * 4 + 16;
+  const size_t lds = ws_features_lds(L.vis.n_ant, waves);
   if (lds > 64 * 1024) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(L.n_gt * L.n_gf);
   if (grid == 0) return hipSuccess;

@@ -36,7 +36,7 @@ EXPORTS = ("qc_ctx_create", "qc_ctx_destroy", "qc_ctx_sync", "qc_last_error", "q
            "qc_batch_destroy", "qc_solve_batch", "qc_ws_features", "qc_mlp_forward", "qc_mlp_backward",
            "qc_adam_step", "qc_mse_grad", "qc_ws_gains", "qc_ws_labels", "qc_mad_flag", "qc_predict_dft", "qc_robust_weights",
            "qc_corrected_weights", "qc_solve_chain_robust", "qc_interp_term", "qc_solve_interval_sky",
-           "qc_residual_sky", "qc_corrupt_sky")
+           "qc_residual_sky", "qc_corrupt_sky", "qc_batch_n_intervals", "qc_batch_ws_features", "qc_batch_ws_gains")
 MAD_MODES = {"global": 0, "baseline": 1}
 BATCH_BUCKETS = 6
 
@@ -147,6 +147,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qc_mse_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     lib.qc_ws_gains.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.qc_ws_labels.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+    lib.qc_batch_n_intervals.argtypes = [vp]
+    lib.qc_batch_ws_features.argtypes = [vp, vp, i32, vp, i32, vp]
+    lib.qc_batch_ws_gains.argtypes = [vp, vp, i32, vp]
     for name in EXPORTS:
         if name not in ("qc_last_error", "qc_last_kernel_ms", "qc_batch_last_ms", "qc_ctx_last_split"):
             getattr(lib, name).restype = C.c_int32
@@ -743,6 +746,29 @@ class Batch:
 
     def last_ms(self) -> float:
         return float(self.lib.qc_batch_last_ms(self.h))
+
+    def n_intervals(self) -> int:
+        """Solution intervals over every problem (rows of the per-interval arrays)."""
+        return int(self.lib.qc_batch_n_intervals(self.h))
+
+    def ws_features(self, feat: torch.Tensor, chisq_unit: Optional[torch.Tensor] = None, ref_ant: int = 0,
+                    stream=None):
+        """qc_batch_ws_features: feat [n_intervals][stride] float32, chisq_unit [n_intervals]
+        float64 or None, rows in problem order."""
+        if feat.dim() != 2 or feat.shape[0] != self.n_intervals():
+            raise ValueError(f"feat must be [{self.n_intervals()}][stride], got {tuple(feat.shape)}")
+        if chisq_unit is not None and chisq_unit.numel() != self.n_intervals():
+            raise ValueError(f"chisq_unit needs {self.n_intervals()} entries")
+        self.ctx._check(self.lib.qc_batch_ws_features(self.h, _ptr(feat, torch.float32, "feat"), int(feat.shape[1]),
+                                                      _ptr(chisq_unit, torch.float64, "chisq_unit"), int(ref_ant),
+                                                      _stream_ptr(stream)))
+
+    def ws_gains(self, y: torch.Tensor, stream=None):
+        """qc_batch_ws_gains: every problem's diagonal gains from y [n_intervals][stride] float32."""
+        if y.dim() != 2 or y.shape[0] != self.n_intervals():
+            raise ValueError(f"y must be [{self.n_intervals()}][stride], got {tuple(y.shape)}")
+        self.ctx._check(self.lib.qc_batch_ws_gains(self.h, _ptr(y, torch.float32, "y"), int(y.shape[1]),
+                                                   _stream_ptr(stream)))
 
     def schedule(self):
         n = BATCH_BUCKETS

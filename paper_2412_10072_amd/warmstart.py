@@ -106,6 +106,17 @@ class WarmStartNet:
         self.ctx.ws_gains(y, self.n_ant, term.gains, stream=stream)
         return chisq_unit.reshape(int(term.n_gt), int(term.n_gf))
 
+    def init_gains_batch(self, batch, chisq_out: torch.Tensor, stream=None) -> None:
+        """Warm starts of every interval of a batch of diagonal problems (qc.Batch) in three
+        launches: the batch's feature pass, the MLP over all intervals, the gain write.
+        chisq_out [batch.n_intervals()] float64 receives chi^2 at unit gains; give each
+        problem its slice of it as the fallback reference when the batch is created."""
+        n = batch.n_intervals()
+        feat = torch.empty(n, self.n_in, dtype=torch.float32, device=chisq_out.device)
+        batch.ws_features(feat, chisq_unit=chisq_out, ref_ant=0, stream=stream)
+        y = self.predict(feat, stream=stream)
+        batch.ws_gains(y, stream=stream)
+
     def state(self) -> dict:
         return dict(params=self.params.detach().cpu().numpy(), n_ant=self.n_ant, n_hid=self.n_hid,
                     step=self.step)

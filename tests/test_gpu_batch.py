@@ -192,3 +192,49 @@ def test_batch_warm_start_fallback_matches_oracle(qc_lib):
         np.testing.assert_array_equal(st["restarted"].cpu().numpy().astype(bool), restart)
         assert rel_err(t.gains.cpu().numpy(), want, kind) <= 1e-10
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_warm_start_kernels_equal_per_problem(qc_lib, dtype):
+    """The batch's warm-start launches (qc_batch_ws_features, qc_batch_ws_gains)
+    over the diagonal problems of uneven antenna counts, against the
+    per-problem qc_ws_features / qc_ws_gains: features, chi^2 at unit gains
+    and written gains bitwise equal, rows in problem order, shorter rows
+    padded; a full-Jones problem refuses the gain write."""
+    from paper_2412_10072_amd import qc
+    say(f"batch warm-start kernels {dtype}")
+    _, dev = make_problems(dtype)
+    diag = [(v, t) for (v, t), sh in zip(dev, SHAPES) if sh["kind"] == "diag"]
+    b = qc.Batch(qc_lib, diag, tol=1e-6, max_iter=10, prec="mixed" if dtype == "c64" else "fp64")
+    n = b.n_intervals()
+    assert n == sum(int(t.n_gt) * int(t.n_gf) for _, t in diag)
+    max_ant = max(int(v.n_ant) for v, _ in diag)
+    feat = torch.full((n, max_ant * 8), 7.0, dtype=torch.float32, device=DEV)
+    chisq = torch.zeros(n, dtype=torch.float64, device=DEV)
+    b.ws_features(feat, chisq_unit=chisq, ref_ant=0)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(11)
+    y = (torch.rand(n, max_ant * 4, generator=g) * 2 - 1).to(DEV)
+    b.ws_gains(y)
+    torch.cuda.synchronize()
+    base = 0
+    for v, t in diag:
+        n_i, n_ant = int(t.n_gt) * int(t.n_gf), int(v.n_ant)
+        c_i = torch.zeros(n_i, dtype=torch.float64, device=DEV)
+        f_i = qc_lib.ws_features(v, t, chisq_unit=c_i, ref_ant=0)
+        torch.cuda.synchronize()
+        assert torch.equal(feat[base:base + n_i, :n_ant * 8], f_i)
+        assert bool((feat[base:base + n_i, n_ant * 8:] == 7.0).all())      # untouched padding
+        assert torch.equal(chisq[base:base + n_i], c_i)
+        want = torch.zeros_like(t.gains)
+        qc_lib.ws_gains(y[base:base + n_i, :n_ant * 4].contiguous(), n_ant, want)
+        torch.cuda.synchronize()
+        assert torch.equal(t.gains, want)
+        base += n_i
+    b.close()
+    b2 = qc.Batch(qc_lib, dev, tol=1e-6, max_iter=10, prec="mixed" if dtype == "c64" else "fp64")
+    with pytest.raises(qc.QcError):
+        b2.ws_gains(torch.zeros(b2.n_intervals(), 64 * 4, dtype=torch.float32, device=DEV))
+    with pytest.raises(qc.QcError):
+        b2.ws_features(torch.zeros(b2.n_intervals(), 8, dtype=torch.float32, device=DEV))
+    b2.close()
