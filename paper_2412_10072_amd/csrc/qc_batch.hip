@@ -80,8 +80,8 @@ k_solve_batch(BatchArgs B) {
         if (threadIdx.x == 0) s_restart = 0;
         __syncthreads();
       }
-      if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST>(J);
-      else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST>(J);
+      if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST, false>(J);
+      else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST, false>(J);
       if constexpr (!WARM) break;
       const bool again = s_restart != 0;        // uniform: set before a barrier in the solve
       __syncthreads();                          // read by every thread before it is reset

@@ -623,6 +623,80 @@ __device__ __forceinline__ void load_w(const S* base, size_t s, int n_wcorr, T& 
   w3 = four ? d : a;
 }
 
+// One sample's stored values (data, model of its one direction, weights,
+// flag) as loaded, before any conversion: the FP64 single-term pass issues
+// the loads of its next chunk into one of these before it computes the
+// current chunk, so that the loads are in flight during that work.
+template <typename S> struct RawSample;
+template <> struct RawSample<float> {
+  float4 d0, d1, m0, m1;
+  float wa, wb, wc, wd;
+  unsigned f;
+};
+template <> struct RawSample<double> {
+  double2 d0, d1, d2, d3, m0, m1, m2, m3;
+  double wa, wb, wc, wd;
+  unsigned f;
+};
+
+template <typename S>
+__device__ __forceinline__ void raw_load(RawSample<S>& x, const S* D, const S* M, const S* W, const uint8_t* F,
+                                         size_t s, int n_wcorr) {
+  // the weights as in load_w: the four-weight case loads all four, the
+  // one-weight case the first, spread to the others when converted
+  x.wb = x.wc = x.wd = S(0);
+  if (n_wcorr == 4) {
+    if constexpr (sizeof(S) == 4) {
+      const float4 u = reinterpret_cast<const float4*>(W)[s];
+      x.wa = u.x; x.wb = u.y; x.wc = u.z; x.wd = u.w;
+    } else {
+      const double2* p = reinterpret_cast<const double2*>(W) + 2 * s;
+      const double2 a = p[0], b = p[1];
+      x.wa = a.x; x.wb = a.y; x.wc = b.x; x.wd = b.y;
+    }
+  } else {
+    x.wa = W[s];
+  }
+  x.f = F[s];
+  if constexpr (sizeof(S) == 4) {
+    const float4* d = reinterpret_cast<const float4*>(D) + 2 * s;
+    const float4* m = reinterpret_cast<const float4*>(M) + 2 * s;
+    x.d0 = d[0]; x.d1 = d[1];
+    x.m0 = m[0]; x.m1 = m[1];
+  } else {
+    const double2* d = reinterpret_cast<const double2*>(D) + 4 * s;
+    const double2* m = reinterpret_cast<const double2*>(M) + 4 * s;
+    x.d0 = d[0]; x.d1 = d[1]; x.d2 = d[2]; x.d3 = d[3];
+    x.m0 = m[0]; x.m1 = m[1]; x.m2 = m[2]; x.m3 = m[3];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ m22<T> raw_m22(float4 u, float4 v) {
+  return {cmake<T>((T)u.x, (T)u.y), cmake<T>((T)u.z, (T)u.w), cmake<T>((T)v.x, (T)v.y), cmake<T>((T)v.z, (T)v.w)};
+}
+template <typename T>
+__device__ __forceinline__ m22<T> raw_m22(double2 a, double2 b, double2 c, double2 d) {
+  return {cmake<T>((T)a.x, (T)a.y), cmake<T>((T)b.x, (T)b.y), cmake<T>((T)c.x, (T)c.y), cmake<T>((T)d.x, (T)d.y)};
+}
+template <typename T>
+__device__ __forceinline__ m22<T> raw_data(const RawSample<float>& x) { return raw_m22<T>(x.d0, x.d1); }
+template <typename T>
+__device__ __forceinline__ m22<T> raw_data(const RawSample<double>& x) { return raw_m22<T>(x.d0, x.d1, x.d2, x.d3); }
+template <typename T>
+__device__ __forceinline__ m22<T> raw_model(const RawSample<float>& x) { return raw_m22<T>(x.m0, x.m1); }
+template <typename T>
+__device__ __forceinline__ m22<T> raw_model(const RawSample<double>& x) { return raw_m22<T>(x.m0, x.m1, x.m2, x.m3); }
+
+template <typename S, typename T>
+__device__ __forceinline__ void raw_weights(const RawSample<S>& x, int n_wcorr, T& w0, T& w1, T& w2, T& w3) {
+  const bool four = n_wcorr == 4;
+  w0 = (T)x.wa;
+  w1 = (T)(four ? x.wb : x.wa);
+  w2 = (T)(four ? x.wc : x.wa);
+  w3 = (T)(four ? x.wd : x.wa);
+}
+
 // Component-wise selects: a conditional between whole structs becomes a
 // select of their addresses, which forces them into scratch memory.
 template <typename T>
@@ -1141,7 +1215,7 @@ __device__ __forceinline__ bool update_and_test(const Sum& sum, double2* gm, cx<
 //         (a direct Fourier sum per direction) instead of read from the
 //         visibility set: single-term and diagonal-chain evaluation.
 template <int KIND, typename S, typename T, int CHM, int NG, int RPS, bool PASS_ONLY = false, bool LMT = false,
-          bool SKY = false, int RST = 0>
+          bool SKY = false, int RST = 0, bool PREFETCH = true>
 __device__ __forceinline__ void solve_interval(const Job& J) {
   using A = T;
   constexpr bool SINGLE = (CHM == CHAIN_SINGLE);
@@ -1161,6 +1235,19 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   constexpr int LPR = 64 / RPS;              // lanes per row
   constexpr bool LANE_ROWS = (LPR == 1);     // one row per lane: flush by lane_flush
   constexpr bool PACC = (NG == 1) && !LANE_ROWS;  // keep antenna-p sums in registers over a p-run
+  // FP64 single-term passes over complex64 data with full-Jones or
+  // real-parameter terms: the loads of the next chunk (and the row indices of
+  // the next step) are issued before the current chunk is computed.  These
+  // kernels hold two wavefronts per SIMD whatever is added below 256 VGPRs,
+  // so the latency of a chunk's loads is hidden behind the work of the one
+  // before instead of by other wavefronts (the full-Jones solve: 223.5 ->
+  // 180.8 ms).  The diagonal kernels would drop from three wavefronts per
+  // SIMD to two, and complex128 data would spill: neither takes it.
+  // (PREFETCH false: the batch kernel, which holds both term kinds and its
+  // queue, would spill with it.)
+  constexpr bool PF = PREFETCH && SINGLE && sizeof(T) == 8 && sizeof(S) == 4 && KIND != KIND_DIAG && !LANE_ROWS &&
+                      !SKY && !LMT;
+  constexpr bool ROWS_AHEAD = LANE_ROWS || PF;
   static_assert(NVP <= 64, "too many values per antenna");
   static_assert(SINGLE || RPS == 1 || NG == 1, "multi-row steps of the general kernel take one gain direction");
 
@@ -1301,16 +1388,26 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
 #pragma unroll
     for (int k = 0; k < NVP; ++k) pacc[k] = A(0);
     int p_cur = -1;                          // antenna of the sums in pacc (uniform per segment)
-    // One row per lane: the row indices of the next step are loaded one step
-    // ahead, so that the loads that depend on them (fixed factors, gains of
-    // the row's antennas and time) leave with the sample loads.
+    // One row per lane (and the prefetching passes): the row indices of the
+    // next step are loaded one step ahead, so that the loads that depend on
+    // them (fixed factors, gains of the row's antennas and time) leave with
+    // the sample loads.
     int p_nx = 0, q_nx = 0, t_nx = 0;
-    if constexpr (LANE_ROWS) {
+    if constexpr (ROWS_AHEAD) {
       if (rw_lo < rw_hi) {
         const long long r0 = min(rw_lo + seg, rw_hi - 1);
         p_nx = V.ant1[r0];
         q_nx = V.ant2[r0];
         t_nx = V.row_time[r0];
+      }
+    }
+    // the stored values of this lane's sample in the next chunk (PF)
+    RawSample<S> nxt = {};
+    if constexpr (PF) {
+      if (rw_lo < rw_hi) {
+        const long long r0 = min(rw_lo + seg, rw_hi - 1);
+        const int c = c_lo + sl;
+        raw_load<S>(nxt, Dp, Mp, Wp, V.flag, (size_t)r0 * n_chan + (c < c_hi ? c : c_lo), V.n_wcorr);
       }
     }
 
@@ -1319,7 +1416,7 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
       const bool r_in = r_mine < rw_hi;
       const long long r = r_in ? r_mine : rb;
       int p, q, t;
-      if constexpr (LANE_ROWS) {
+      if constexpr (ROWS_AHEAD) {
         p = p_nx;
         q = q_nx;
         t = t_nx;
@@ -1340,9 +1437,9 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
         rv = J.sky->uvw[3 * r + 1];
         rw = J.sky->uvw[3 * r + 2];
       }
-      if constexpr (RPS == 1) {
+      if constexpr (RPS == 1 && !PF) {
         if (!row_ok) continue;               // uniform over the wave
-      } else {
+      } else {                               // (a prefetching pass consumes every step's loads)
         p = row_ok ? p : 0;                  // keep LDS indices in range; the row adds nothing
         q = row_ok ? q : 0;
       }
@@ -1377,9 +1474,28 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
         // range): all of them are in flight together.  Bitwise & keeps the
         // flag load out of a branch.
         T w0, w1, w2, w3;
-        load_w<S, T>(Wp, s, V.n_wcorr, w0, w1, w2, w3);
-        const uint8_t fl = V.flag[s];
-        const m22<T> Draw = load_m22<S, T>(Dp, s);
+        uint8_t fl;
+        m22<T> Draw, Mpf;
+        if constexpr (PF) {
+          // this chunk's values were loaded during the last one; the loads of
+          // the next chunk of this step (else the first chunk of the next
+          // step) leave now.  Every index is clamped into the wave's rows and
+          // the interval's channels; what a clamped lane loads is not used.
+          const RawSample<S> cur = nxt;
+          const bool more = c0 + LPR < c_hi;
+          const long long rn = more ? r : min(rb + RPS + seg, rw_hi - 1);
+          const int cn0 = (more ? c0 + LPR : c_lo) + sl;
+          const int cn = cn0 < c_hi ? cn0 : c_lo;
+          raw_load<S>(nxt, Dp, Mp, Wp, V.flag, (size_t)rn * n_chan + cn, V.n_wcorr);
+          raw_weights<S, T>(cur, V.n_wcorr, w0, w1, w2, w3);
+          fl = (uint8_t)cur.f;
+          Draw = raw_data<T>(cur);
+          Mpf = raw_model<T>(cur);
+        } else {
+          load_w<S, T>(Wp, s, V.n_wcorr, w0, w1, w2, w3);
+          fl = V.flag[s];
+          Draw = load_m22<S, T>(Dp, s);
+        }
         const bool use = inb & row_ok & (fl == 0);
         const double nu = V.freq[cc];
         // d(phase)/d(parameter): 2 pi nu for delays (the tau column of
@@ -1414,7 +1530,10 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
               Gp.b = Gp.c = Gq.b = Gq.c = czero<T>();
             }
           }
-          const m22<T> M = select_m(use, model_at(0));
+          m22<T> M0;
+          if constexpr (PF) M0 = Mpf;
+          else M0 = model_at(0);
+          const m22<T> M = select_m(use, M0);
           const m22<T> B = mmul_h(M, Gq);        // M G_q^H
           const m22<T> GM = mmul(Gp, M);         // G_p M
           const m22<T> R = msub_mul(D, Gp, B);   // D - G_p M G_q^H
