@@ -1665,13 +1665,15 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           m22<T> Vm = mzero<T>();
           if constexpr (DIR_ID) {
             // Model direction d has gain direction d (n_dir = n_gdir <= NG):
-            // the directions are unrolled, and the per-direction factors are
-            // formed twice -- once for the model, once for the blocks after
-            // the residual -- rather than kept for all directions (which
-            // would hold 2 x NG matrices in registers).  With e = o times the
+            // the directions are unrolled.  MIXED keeps each direction's
+            // factor E from the model sweep for the blocks after the residual
+            // (+16 VGPRs, still two wavefronts per SIMD; the dE passes of the
+            // four-direction chain 283 -> 251 ms); FP64, where they would take
+            // twice the registers, forms them again.  With e = o times the
             // direction-dependent fixed factors,
             //   E_ij = e_{p,d,i} M_d,ij conj(e_{q,d,j}),
             //   B_ij = E_ij conj(h_{q,j}), Bc_ij = conj(E_ji h_{p,j}).
+            constexpr bool KEEP_E = sizeof(T) == 4;
             m22<T> Mc[NG];
             if constexpr (sizeof(T) == 4) {
 #pragma unroll
@@ -1690,11 +1692,13 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
               E.c = mulc(rp1, rq0) * M.c;
               E.d = mulc(rp1, rq1) * M.d;
             };
+            m22<T> Ek[KEEP_E ? NG : 1];
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
               if (g < n_dir) {
                 m22<T> E;
                 factors(g, E);
+                if constexpr (KEEP_E) Ek[g] = E;
                 Vm.a = cfma(hp0, mulc(E.a, hq0), Vm.a);
                 Vm.b = cfma(hp0, mulc(E.b, hq1), Vm.b);
                 Vm.c = cfma(hp1, mulc(E.c, hq0), Vm.c);
@@ -1708,7 +1712,12 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
             for (int g = 0; g < NG; ++g) {
               if (g < n_dir) {
                 m22<T> E, B, Bc;
-                factors(g, E);
+                if constexpr (KEEP_E) {
+                  E = Ek[g];
+                  active_diag(g, hp0, hp1, hq0, hq1);
+                } else {
+                  factors(g, E);
+                }
                 B.a = mulc(E.a, hq0);
                 B.b = mulc(E.b, hq1);
                 B.c = mulc(E.c, hq0);
