@@ -505,14 +505,20 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
               band_lds_bytes_for(vis->n_ant, L.prec_mixed != 0, 8) <= 64 * 1024;
   for (int g = 0; band && g < ta.n_gf; ++g)
     if (ctx->h_clo[g] != g) band = false;
-  // its direction-dependent fixed terms: diagonal gains, at most BAND_MAX_DD
+  // diagonal chains: the direction-dependent fixed terms, when all are
+  // diagonal gains and at most BAND_MAX_DD, tabulated once per solve for every
+  // pass (the band pass takes no other kind).  A pointing term differs by
+  // direction through its beam although it has one gain direction.
   L.n_dd = 0;
-  for (int j = 0; band && j < n_term; ++j) {
-    if (j == active || chain[j].n_gdir <= 1) continue;
-    if (chain[j].type != QC_TERM_DIAGONAL || L.n_dd == BAND_MAX_DD) band = false;
+  L.dd_tabled = !fixed && L.diag_chain && !L.left_general;
+  for (int j = 0; L.dd_tabled && j < n_term; ++j) {
+    const bool dd = chain[j].n_gdir > 1 || enum_value(chain[j].type) == QC_TERM_POINTING;
+    if (j == active || !dd) continue;
+    if (chain[j].type != QC_TERM_DIAGONAL || L.n_dd == BAND_MAX_DD) L.dd_tabled = 0;
     else L.dd_term[L.n_dd++] = j;
   }
-  if (!band) L.n_dd = 0;
+  if (!L.dd_tabled) L.n_dd = 0;
+  if (!L.dd_tabled) band = false;
   // 4 rows x 16 channels per step (measured faster than 8 x 8 on the 64-antenna
   // bandpass: 11.1 against 12.9 ms per pass), unless asked otherwise or its LDS
   // slots do not fit
@@ -563,14 +569,14 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
     }
   }
   size_t dd_off[BAND_MAX_DD] = {0, 0};
-  if (band) {
-    HIP_TRY(ctx, grow(ctx->d_band, ctx->band_cap, (size_t)std::max<long long>(vis->n_row, 1)));
+  if (band) HIP_TRY(ctx, grow(ctx->d_band, ctx->band_cap, (size_t)std::max<long long>(vis->n_row, 1)));
+  if (L.n_dd > 0) {
     size_t dd_bytes = 0;
     for (int j = 0; j < L.n_dd; ++j) {
       dd_off[j] = dd_bytes;
       dd_bytes += (dd_table_bytes(L, L.dd_term[j]) + 255) / 256 * 256;
     }
-    if (L.n_dd > 0) HIP_TRY(ctx, grow(ctx->d_ddtab, ctx->ddtab_cap, dd_bytes));
+    HIP_TRY(ctx, grow(ctx->d_ddtab, ctx->ddtab_cap, dd_bytes));
   }
   size_t lds = 0;
   hipError_t e = hipSuccess;
@@ -582,10 +588,10 @@ static qc_status solve_interval_impl(qc_ctx* ctx, const qc_vis* vis, qc_term* ch
   if (band && e == hipSuccess) {
     e = launch_band_steps(L, parts, L.band_rows, ctx->d_band, s);
     L.band_steps = ctx->d_band;
-    for (int j = 0; j < L.n_dd && e == hipSuccess; ++j) {
-      L.dd_tab[j] = ctx->d_ddtab + dd_off[j];
-      e = launch_dd_table(L, L.dd_term[j], ctx->d_ddtab + dd_off[j], s);
-    }
+  }
+  for (int j = 0; j < L.n_dd && e == hipSuccess; ++j) {
+    L.dd_tab[j] = ctx->d_ddtab + dd_off[j];
+    e = launch_dd_table(L, L.dd_term[j], ctx->d_ddtab + dd_off[j], s);
   }
   if (e != hipSuccess) {
     // reported below

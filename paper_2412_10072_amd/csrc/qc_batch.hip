@@ -74,6 +74,7 @@ k_solve_batch(BatchArgs B) {
     J.otab = nullptr;
     J.sky = nullptr;
     J.restart_flag = &s_restart;
+    J.n_dd = -1;
     constexpr int RST = WARM ? 1 : 0;
     for (int attempt = 0;; ++attempt) {
       if constexpr (WARM) {

@@ -407,8 +407,13 @@ struct SolveLaunch {
   int dir_ident;
   const BandStep* band_steps;
   int band_rows;              // rows per step of that pass: 4 or 8
-  // that pass: the direction-dependent fixed terms (diagonal gains), each as a
-  // table [n_gt][n_gf][n_ant][n_dir][2 hands] complex of the compute precision
+  // diagonal chains (every pass, the band pass included) whose
+  // direction-dependent fixed terms are all diagonal, at most BAND_MAX_DD of
+  // them: dd_tabled, and those terms (chain indices) each as a table
+  // [n_gt][n_gf][n_ant][n_dir][2 hands] complex of the compute precision,
+  // built once per solve (k_dd_table); else dd_tabled = 0 and each pass
+  // evaluates them per sample
+  int dd_tabled;
   int n_dd;
   int dd_term[BAND_MAX_DD];
   const void* dd_tab[BAND_MAX_DD];

@@ -918,6 +918,12 @@ struct Job {
   const void* otab;          // diagonal chains: fixed direction-independent factors, or null
   const SkyArgs* sky;        // the model's components (kernels built to predict it), else unused
   int* restart_flag;         // RST = 1 kernels: set (LDS) when the warm start is worse than unit gains
+  // diagonal chains: the direction-dependent fixed terms' tables (n_dd >= 0:
+  // terms dd_term[0 .. n_dd), tables dd_tab, layout of SolveLaunch::dd_tab),
+  // or n_dd = -1 (evaluated per sample)
+  int n_dd;
+  int dd_term[BAND_MAX_DD];
+  const void* dd_tab[BAND_MAX_DD];
 };
 
 // LDS bytes the interval solve needs for n_ant antennas and nw waves.
@@ -1596,9 +1602,43 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
           constexpr int MCH = (SKY || sizeof(T) != 4)                          ? 1
                               : LANE_ROWS && !(PASS_ONLY && KIND == KIND_DIAG) ? 2
                                                                                : 4;
-          // direction-dependent part of o for antennas p and q at direction d (one
-          // loop, so that the lookups of both antennas are in flight together)
+          // direction-dependent fixed factors of antennas p and q: with tables,
+          // the rows of (gain block at this sample, antenna) of each term, one
+          // entry pair per model direction.  (Not in the one-row-per-lane
+          // pass, whose per-lane table rows would spill; one-channel
+          // intervals take the band pass, which has its own.)
+          const int n_dd = LANE_ROWS ? -1 : J.n_dd;
+          const cx<T>* ddp[BAND_MAX_DD];
+          const cx<T>* ddq[BAND_MAX_DD];
+#pragma unroll
+          for (int k = 0; k < BAND_MAX_DD; ++k) {
+            ddp[k] = ddq[k] = nullptr;
+            if (k < n_dd) {
+              const TermArgs& tj = CH.t[J.dd_term[k]];
+              const size_t g = (size_t)tj.t_map[t] * tj.n_gf + tj.f_map[cc];
+              const cx<T>* base = reinterpret_cast<const cx<T>*>(J.dd_tab[k]) + g * n_ant * n_dir * 2;
+              ddp[k] = base + (size_t)p * n_dir * 2;
+              ddq[k] = base + (size_t)q * n_dir * 2;
+            }
+          }
+          // direction-dependent part of o for antennas p and q at direction d:
+          // from the tables, else per term (one loop, so that the lookups of
+          // both antennas are in flight together)
           auto dd_factor = [&](int xp, int xq, int d, cx<T>& p0, cx<T>& p1, cx<T>& q0, cx<T>& q1) {
+            if (n_dd >= 0) {                   // xp = p, xq = q at every call
+#pragma unroll
+              for (int k = 0; k < BAND_MAX_DD; ++k) {
+                if (k < n_dd) {
+                  const cx<T>* a = ddp[k] + 2 * d;
+                  const cx<T>* b = ddq[k] + 2 * d;
+                  p0 = p0 * a[0];
+                  p1 = p1 * a[1];
+                  q0 = q0 * b[0];
+                  q1 = q1 * b[1];
+                }
+              }
+              return;
+            }
             for (int j = 0; j < n_term; ++j) {
               if (j == act || CH.t[j].n_gdir <= 1) continue;
               const m22<T> Jp = term_jones<T>(CH.t[j], n_ant, t, cc, xp, d, nu);

@@ -82,6 +82,12 @@ __global__ void __launch_bounds__((wide_state<CHM, T>() ? 256 : 512)) k_solve_fu
   J.otab = L.otab;
   J.sky = &L.sky;
   J.restart_flag = nullptr;
+  J.n_dd = L.dd_tabled ? L.n_dd : -1;
+#pragma unroll
+  for (int k = 0; k < BAND_MAX_DD; ++k) {
+    J.dd_term[k] = L.dd_term[k];
+    J.dd_tab[k] = L.dd_tab[k];
+  }
   solve_interval<KIND, S, T, CHM, NG, RPS, false, LMT, SKY>(J);
 }
 
@@ -147,6 +153,12 @@ k_split_pass(SolveLaunch L, int n_part, double* partials, const uint8_t* done) {
   J.otab = L.otab;
   J.sky = &L.sky;
   J.restart_flag = nullptr;
+  J.n_dd = L.dd_tabled ? L.n_dd : -1;
+#pragma unroll
+  for (int k = 0; k < BAND_MAX_DD; ++k) {
+    J.dd_term[k] = L.dd_term[k];
+    J.dd_tab[k] = L.dd_tab[k];
+  }
   solve_interval<KIND, S, T, CHM, NG, RPS, true, false, SKY>(J);
 }
 
@@ -187,6 +199,7 @@ __global__ void __launch_bounds__(256) k_split_update(SolveLaunch L, int n_part,
   J.otab = nullptr;
   J.sky = nullptr;
   J.restart_flag = nullptr;
+  J.n_dd = -1;
   split_update<KIND, T, NG, FB>(J, partials + (size_t)interval * n_part * stride, n_part, St);
 }
 

@@ -136,3 +136,29 @@ def test_band_single_term_irregular_rows(split_ctx, parts, rows):
     e = rel_err(got[0].gains, ref[0].gains, "diag")
     say(f"  largest relative difference {e:.2e}")
     assert e <= 1e-10
+
+
+@pytest.mark.parametrize("parts", [2, 5])
+def test_one_channel_intervals_with_a_pointing_term(split_ctx, parts):
+    """B (one channel per interval) right of a pointing term: the beam makes
+    the chain differ by direction although the pointing term has one gain
+    direction, so its factors are evaluated per direction (the band pass,
+    which takes only tabulated diagonal terms, is not used)."""
+    say(f"one-channel intervals with a pointing term, parts={parts}")
+    rng = np.random.default_rng(331)
+    n_ant, n_time, n_chan, n_dir = 6, 8, 13, 3
+    vis = make_vis(rng, n_ant=n_ant, n_time=n_time, n_chan=n_chan, n_dir=n_dir, freq0=1.0e9, dfreq=16e6)
+    Pt = make_term(rng, "pointing", n_time, n_chan, n_ant, t_int=4, f_int=n_chan, n_dir=n_dir, name="Pt")
+    B = make_term(rng, "diag", n_time, n_chan, n_ant, t_int=n_time, f_int=1, n_dir=n_dir, scale=0.3, name="B")
+    truth = [Pt, B]
+    vis.data = forward_data(vis, truth) + 0.02 * rand_c(rng, *vis.data.shape)
+    vis.flag = (rng.random(vis.flag.shape) < 0.1).astype(np.uint8)
+    chain = [Pt, unit_like(B)]
+    ref, rst = o_solver.solve_term(vis, chain, 1, tol=-1.0, max_iter=3)
+    split_ctx.set_split(parts)
+    got, st = gpu_solve(split_ctx, vis, chain, 1, tol=-1.0, max_iter=3, prec="fp64")
+    assert split_ctx.last_split_parts() == parts
+    np.testing.assert_allclose(st["chisq_first"], rst["chisq_first"], rtol=1e-11)
+    e = rel_err(got[1].gains, ref[1].gains, "diag")
+    say(f"  largest relative difference {e:.2e}")
+    assert e <= 1e-10
