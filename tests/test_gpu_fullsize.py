@@ -7,7 +7,9 @@ one (whole-problem oracle runs at these sizes would take hours).
     the default tile, then the residual pass: sampled intervals against the
     oracle (gains <= 1e-4, iteration counts within one), every interval's
     statistics checked for validity, the residual on the sampled intervals
-    against the oracle's residual through the same gains.
+    against the oracle's residual through the same gains; then the same
+    workload in FP64 for three updates, sampled intervals against the
+    oracle's three updates (<= 1e-10).
   * K.B.G.dE chain with 4 directions (300 times x 512 channels): the delay
     initial estimate on every K interval and antenna (a grid argmax taken in
     FP64 on both sides: identical), one MIXED update of a G interval and of a
@@ -125,6 +127,26 @@ def test_meerkat_full_size_sampled_parity(qc_lib):
         keep = vh.flag == 0
         scale = np.abs(vh.data[keep]).max()
         assert np.abs(got_r[keep] - want_r[keep]).max() <= 2e-6 * scale
+    # The same workload with FP64 products and sums (the paper's gain
+    # precision) in the launch configuration of the benchmark's FP64 solve
+    # (default tile: 4 rows of 16 channels per step, whose loop loads the
+    # next chunk while it computes the current one), three updates from unit
+    # gains: sampled intervals against the oracle's three updates <= 1e-10.
+    del resid
+    term64 = qc.device_term(unit, DEV)
+    st64 = qc_lib.solve(vis, [term64], 0, tol=-1.0, max_iter=3, prec="fp64")
+    qc_lib.sync()
+    assert (st64["iters"].cpu().numpy() == 3).all()
+    g64 = term64.gains.cpu().numpy()
+    assert np.isfinite(g64).all()
+    for gt, gf in samples[:4]:
+        r0, r1, ch0, ch1 = gt * nbl, (gt + 1) * nbl, gf * 64, (gf + 1) * 64
+        vh = host_slice(vis, r0, r1, ch0, ch1)
+        ref = o_solver.copy_chain([unit.copy(f_map=np.asarray(unit.f_map)[ch0:ch1])])
+        o_solver.solve_interval(vh, ref, 0, gt, gf, -1.0, 3)
+        e = rel_err(g64[gt, gf], ref[0].gains[gt, gf], [0, 1, 2, 3])
+        say(f"FP64 interval ({gt}, {gf}), 3 updates: rel err {e:.2e}")
+        assert e <= 1e-10
 
 
 def test_chain_full_size_sampled_parity(qc_lib):
