@@ -594,7 +594,9 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
     unit gains), learned (per problem: feature pass, MLP, gain write, solve with the unit-gain
     fallback) and learned + batched (the batch's feature pass over every interval, the MLP
     over all of them, the batch's gain write, then one graph launch with per-problem fallback
-    references)."""
+    references).  The two batched paths run on their autotuned schedules, as the batch leg's
+    tuned graph (the tuning itself is not timed; the warm batch is tuned from its learned
+    start); their default schedules are timed too."""
     import numpy as np
     import torch
     from paper_2412_10072_amd import qc, warmstart
@@ -635,10 +637,17 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
 
     def run(mode):
         stats = None
+        if mode == "tune":
+            reset()
+            b_unit.tune()
+            reset()
+            net.init_gains_batch(b_warm, ref_all, stream=stream)
+            b_warm.tune()
+            return None
         if mode == "plain":
             stats = [ctx.solve(v, [t], 0, tol=1e-6, max_iter=100, prec="mixed", stream=stream)
                      for v, t, _, _ in probs]
-        elif mode == "batched":
+        elif mode.startswith("batched"):
             b_unit.run(stream)
             stats = b_unit.stats
         elif mode == "learned":
@@ -654,7 +663,15 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
         return stats
 
     out = {}
-    for mode in ("plain", "batched", "learned", "learned_batched"):
+    t_tune = 0.0
+    for mode in ("plain", "batched_default", "learned_batched_default", "tune", "batched", "learned",
+                 "learned_batched"):
+        if mode == "tune":
+            ts = time.perf_counter()
+            run(mode)
+            torch.cuda.synchronize()
+            t_tune = time.perf_counter() - ts
+            continue
         best = None
         for _ in range(reps):
             reset()
@@ -671,10 +688,11 @@ def learned_batched(ctx, net, dev, n_problems: int = 32, reps: int = 2):
                          restarted_frac=float(rs.mean()), converged_frac=float(cv.mean()))
     b_unit.close()
     b_warm.close()
-    res = dict(problems=n_problems, intervals=n_int, samples=n_samples, **out,
+    res = dict(problems=n_problems, intervals=n_int, samples=n_samples, **out, tune_s=t_tune,
                speedup_learned_batched_vs_plain=out["plain"]["ms"] / out["learned_batched"]["ms"],
                speedup_batched_vs_plain=out["plain"]["ms"] / out["batched"]["ms"],
-               speedup_learned_vs_plain=out["plain"]["ms"] / out["learned"]["ms"])
+               speedup_learned_vs_plain=out["plain"]["ms"] / out["learned"]["ms"],
+               speedup_learned_batched_default_vs_plain=out["plain"]["ms"] / out["learned_batched_default"]["ms"])
     log("learned+batched: " + ", ".join(f"{m} {out[m]['ms']:.1f} ms ({out[m]['mean_iterations']:.2f} updates)"
                                        for m in out) +
         f"; learned+batched vs plain {res['speedup_learned_batched_vs_plain']:.2f}x")
