@@ -25,14 +25,31 @@
 namespace qc {
 namespace {
 
+// A wave-uniform copy of *src: every 32-bit word read and broadcast from the
+// first lane, so that the problem's pointers and sizes can live in scalar
+// registers for the whole solve (the item index comes from LDS, which the
+// compiler cannot prove uniform).
+template <typename X>
+__device__ __forceinline__ X uniform_copy(const X* src) {
+  static_assert(sizeof(X) % 4 == 0, "whole words");
+  X out;
+  const unsigned* s = reinterpret_cast<const unsigned*>(src);
+  unsigned* d = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(X) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+  return out;
+}
+
 // LM: Levenberg-Marquardt damping for every problem of the batch (kernels of
 // their own, as for the single-problem path).  WARM: some problem carries a
 // warm-start fallback reference.  Then an interval whose warm start fits
 // worse than unit gains returns from its first pass, and this kernel writes
-// unit gains and solves it again without the reference.  The reference check
-// costs about 22 VGPRs (184 against 162), one wavefront per SIMD; the MIXED
-// kernels are held to three wavefronts per SIMD, spilling 48-60 bytes per
-// lane: measured on the learned + batched solve, 144 ms against 167 ms at two.
+// unit gains and solves it again without the reference.  The item and its
+// problem are read as wave-uniform copies: with the problem's pointers and
+// sizes in vector registers the MIXED kernel took 160 VGPRs (the warm one
+// 168 with spills, LM 239) against 132 (148, 156), and the batch graph at
+// six updates 282 against 228 ms.  The MIXED warm kernels stay held to three
+// wavefronts per SIMD.
 template <typename S, typename T, int RPS, bool LM, bool WARM>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WARM && !LM && sizeof(T) == 4 ? 3 : 1)))
 k_solve_batch(BatchArgs B) {
@@ -44,8 +61,8 @@ k_solve_batch(BatchArgs B) {
     const int k = s_next;
     __syncthreads();
     if (k >= B.n_items) break;
-    const BatchItem I = B.items[B.item_begin + k];
-    const BatchProb& P = B.probs[I.prob];
+    const BatchItem I = uniform_copy(B.items + B.item_begin + k);
+    const BatchProb P = uniform_copy(B.probs + I.prob);
     Job J;
     J.V = &P.vis;
     J.CH = nullptr;
