@@ -38,6 +38,22 @@ struct BatchArgs {
   int* err;
 };
 
+// A wave-uniform copy of *src (the same in every lane): every 32-bit word
+// read and broadcast from the first lane, so that a problem's pointers and
+// sizes can live in scalar registers (a struct read from device memory at an
+// index the compiler cannot prove uniform -- from LDS, or through another
+// such read -- would otherwise hold them in vector registers).
+template <typename X>
+__device__ __forceinline__ X uniform_copy(const X* src) {
+  static_assert(sizeof(X) % 4 == 0, "whole words");
+  X out;
+  const unsigned* s = reinterpret_cast<const unsigned*>(src);
+  unsigned* d = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(X) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+  return out;
+}
+
 void* batch_kernel_ptr(int prec_mixed, int vis_c128, int rps, int lm, int warm);
 // learned warm start over a batch (qc_ws.hip)
 hipError_t launch_batch_features(const BatchProb* probs, const BatchItem* items, int n_items, int max_ant, int vis_c128,

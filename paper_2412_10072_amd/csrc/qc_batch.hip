@@ -25,21 +25,6 @@
 namespace qc {
 namespace {
 
-// A wave-uniform copy of *src: every 32-bit word read and broadcast from the
-// first lane, so that the problem's pointers and sizes can live in scalar
-// registers for the whole solve (the item index comes from LDS, which the
-// compiler cannot prove uniform).
-template <typename X>
-__device__ __forceinline__ X uniform_copy(const X* src) {
-  static_assert(sizeof(X) % 4 == 0, "whole words");
-  X out;
-  const unsigned* s = reinterpret_cast<const unsigned*>(src);
-  unsigned* d = reinterpret_cast<unsigned*>(&out);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(X) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
-  return out;
-}
-
 // LM: Levenberg-Marquardt damping for every problem of the batch (kernels of
 // their own, as for the single-problem path).  WARM: some problem carries a
 // warm-start fallback reference.  Then an interval whose warm start fits

@@ -174,8 +174,8 @@ __global__ void __launch_bounds__(256) k_ws_features(FeatLaunch L) {
 template <typename S>
 __global__ void __launch_bounds__(256) k_batch_features(const BatchProb* probs, const BatchItem* items, float* feat,
                                                         int feat_stride, double* chisq_unit, int ref_ant) {
-  const BatchItem it = items[blockIdx.x];
-  const BatchProb& P = probs[it.prob];
+  const BatchItem it = uniform_copy(items + blockIdx.x);
+  const BatchProb P = uniform_copy(probs + it.prob);
   const size_t row = (size_t)P.int_base + (size_t)it.gt * P.term.n_gf + it.gf;
   features_interval<S>(P.vis, it.r_lo, it.r_hi, it.c_lo, it.c_hi, feat + row * feat_stride,
                        chisq_unit ? chisq_unit + row : nullptr, ref_ant);
@@ -185,8 +185,8 @@ __global__ void __launch_bounds__(256) k_batch_features(const BatchProb* probs, 
 // grid (work item, antenna blocks of 64).
 __global__ void k_batch_ws_gains(const BatchProb* probs, const BatchItem* items, const float* __restrict__ y,
                                  int y_stride) {
-  const BatchItem it = items[blockIdx.x];
-  const BatchProb& P = probs[it.prob];
+  const BatchItem it = uniform_copy(items + blockIdx.x);
+  const BatchProb P = uniform_copy(probs + it.prob);
   const int a = blockIdx.y * blockDim.x + threadIdx.x;
   if (a >= P.vis.n_ant) return;
   const size_t interval = (size_t)it.gt * P.term.n_gf + it.gf;
