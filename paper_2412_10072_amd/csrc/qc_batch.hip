@@ -83,8 +83,11 @@ k_solve_batch(BatchArgs B) {
         if (threadIdx.x == 0) s_restart = 0;
         __syncthreads();
       }
+      // FP64 full-Jones intervals load their next chunk during the current
+      // one's work, except in the warm kernel, which would spill with it
+      // (FP64 batch graph about 620 -> 540 ms)
       if (P.term.kind == KIND_DIAG) solve_interval<KIND_DIAG, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST, false>(J);
-      else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST, false>(J);
+      else solve_interval<KIND_C2X2, S, T, CHAIN_SINGLE, 1, RPS, false, LM, false, RST, !WARM>(J);
       if constexpr (!WARM) break;
       const bool again = s_restart != 0;        // uniform: set before a barrier in the solve
       __syncthreads();                          // read by every thread before it is reset

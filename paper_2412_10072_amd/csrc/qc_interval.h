@@ -1249,8 +1249,8 @@ __device__ __forceinline__ void solve_interval(const Job& J) {
   // before instead of by other wavefronts (the full-Jones solve: 223.5 ->
   // 180.8 ms).  The diagonal kernels would drop from three wavefronts per
   // SIMD to two, and complex128 data would spill: neither takes it.
-  // (PREFETCH false: the batch kernel, which holds both term kinds and its
-  // queue, would spill with it.)
+  // (PREFETCH false: the batch kernel's warm variant, which would spill with
+  // it.)
   constexpr bool PF = PREFETCH && SINGLE && sizeof(T) == 8 && sizeof(S) == 4 && KIND != KIND_DIAG && !LANE_ROWS &&
                       !SKY && !LMT;
   constexpr bool ROWS_AHEAD = LANE_ROWS || PF;
